@@ -1,0 +1,149 @@
+/*
+ * libqds — quasi-cylindrical direction-splitting (QDS) field advance with the
+ * Klein-Gordon axion solver and the axion-regenerated fields, for MI355X (gfx950).
+ *
+ * Method: "X-dispersionless solver for electromagnetic and axion fields in a
+ * cylindrical particle-in-cell code" (arXiv 2609.03550).  Every retained
+ * azimuthal mode m of the fields (Eq. fourier_decomp) lives on a staggered
+ * (x, r) grid; the transverse transport variables T_r^+- = E_r +- B_theta,
+ * T_theta^+- = E_theta +- B_r (Eq. Tdefs) move exactly one cell per step
+ * (c dt = dx, Eqs. Trp_update..Ttm_update), E_x and B_x leapfrog (Eq.
+ * Ex_update), the axion transport variables T_a^+- and phi follow Eqs.
+ * Ta_plus_update, Ta_minus_update, phi_update, and a duplicate set of fields
+ * is driven by the axion current j_a (Eqs. jax_mode, jar_mode, jat_mode).
+ *
+ * Units: c = eps0 = mu0 = 1.  The axion and regenerated fields are carried
+ * scaled (phi/g, E1/g^2) when s_phi = s_j = 1, so the coupling never appears.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are HIP device memory owned by the caller unless stated.
+ *  - Work is enqueued on ``stream`` (a hipStream_t; NULL = the null stream) and
+ *    is asynchronous; argument errors are returned synchronously before
+ *    anything is enqueued.  A launch failure is returned as QDS_EHIP.
+ *  - A handle must not be used from two host threads at once.
+ *  - On any error, qds_last_error(handle) holds a message (never NULL).
+ */
+#ifndef QDS_H
+#define QDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QDS_OK = 0,
+    QDS_EINVAL = 1,        /* bad argument (sizes, flags, null pointers) */
+    QDS_ECFL = 2,          /* c dt != dx, or the radial stability bound fails */
+    QDS_ENOMEM = 3,        /* library-owned allocation failed */
+    QDS_EHIP = 4,          /* a HIP call or kernel launch failed */
+    QDS_EUNSUPPORTED = 5,  /* combination not built (e.g. more than 8 modes) */
+    QDS_ESTATE = 6         /* state descriptor inconsistent with the handle */
+} qds_status;
+
+enum { QDS_F64 = 0, QDS_F32 = 1 };
+enum { QDS_X_OPEN = 0, QDS_X_PERIODIC = 1, QDS_X_WINDOW = 2 };
+enum { QDS_R_OPEN = 0, QDS_R_PEC = 1 };
+enum { QDS_HAS_PLASMA = 1, QDS_HAS_AXION = 2, QDS_HAS_AREM = 4 };
+enum { QDS_J_NONE = 0, QDS_J_RING = 1 };
+
+/* Planes of the state (each [modes][nr+1][ld] complex, x contiguous). */
+enum {
+    QDS_P_TRP = 0,   /* T_r^+ at (x_i, r_{j+1/2}, t^n); row nr holds the exterior ghost B_theta(r_{nr+1/2}) */
+    QDS_P_TRM = 1,   /* T_r^- at (x_i, r_{j+1/2}, t^n); row nr unused */
+    QDS_P_TTP = 2,   /* T_theta^+ at (x_i, r_j, t^n), rows 0..nr */
+    QDS_P_TTM = 3,   /* T_theta^- at (x_i, r_j, t^n) */
+    QDS_P_EX = 4,    /* E_x at (x_{i+1/2}, r_j, t^{n-1/2}) */
+    QDS_P_BX = 5,    /* B_x at (x_{i+1/2}, r_{j+1/2}, t^{n-1/2}); row nr = exterior ghost */
+    QDS_P_JX = 6,    /* plasma j_x at (x_{i+1/2}, r_j, t^{n-1}) */
+    QDS_P_JR = 7,    /* plasma j_r at (x_i, r_{j+1/2}, t^{n-1/2}) */
+    QDS_P_JT = 8,    /* plasma j_theta at (x_i, r_j, t^{n-1/2}) */
+    /* 9..17: the same nine planes for the regenerated set (QDS_P_SET1 + k) */
+    QDS_P_SET1 = 9,
+    QDS_P_PHI = 18,  /* phi at (x_{i+1/2}, r_{j+1/2}, t^n); row nr = exterior ghost phi */
+    QDS_P_TAP = 19,  /* T_a^+ at (x_i, r_{j+1/2}, t^{n-1/2}) */
+    QDS_P_TAM = 20,  /* T_a^- at (x_i, r_{j+1/2}, t^{n-1/2}) */
+    QDS_NPLANES = 21
+};
+
+/* Grid and field content.  x columns i = 0..nx-1 (x_i = i dx); half-x columns
+ * hold x_{i+1/2}, the last one (i = nx-1) outside the domain and zero unless
+ * x is periodic.  Radial rows r_j = j dr (j = 0..nr) and r_{j+1/2}. */
+typedef struct {
+    int32_t nx;        /* >= 8 */
+    int32_t nr;        /* >= 4 */
+    int32_t dtype;     /* QDS_F64 | QDS_F32 (complex interleaved re, im) */
+    int32_t x_bc;      /* QDS_X_OPEN | QDS_X_PERIODIC | QDS_X_WINDOW (one cell per step) */
+    int32_t r_bc;      /* QDS_R_OPEN (outflow, Sec. 3.2) | QDS_R_PEC (conducting wall, tests) */
+    int32_t content;   /* QDS_HAS_* bits: which planes the state holds */
+    double dr;
+} qds_grid;
+
+/* Current model: cold-plasma response d_t j = wp2 E on every set, plus an
+ * optional prescribed j_x^(0) drive standing in for deposition:
+ *   j_x = amp exp(-(x - x0 - v t)^2 / 2 sx^2) exp(-(r - r0)^2 / 2 sr^2) (1 + noise xi),
+ * xi a SplitMix64 + Box-Muller normal per (step, lab column, row) from seed. */
+typedef struct {
+    double wp2;
+    int32_t kind;      /* QDS_J_NONE | QDS_J_RING */
+    int32_t pad_;
+    double amp, x0, v, sx, r0, sr, noise;
+    uint64_t seed;
+} qds_current;
+
+/* Axion parameters (ignored unless the grid content has QDS_HAS_AXION). */
+typedef struct {
+    double ma2;        /* (m_a c^2 / hbar)^2 in code units */
+    double s_phi;      /* scale of the KG source E.B (1 in scaled units) */
+    double s_j;        /* scale of j_a (1 in scaled units) */
+    double bext[6];    /* uniform external B added to the background in S_a and j_a:
+                          re/im of B_x^(0), B_r^(1), B_theta^(1) */
+} qds_axion;
+
+/* State: two caller-owned device buffers of qds_state_bytes() bytes each.
+ * ``cur`` names the one holding the current state; qds_step advances it,
+ * the step counter and the moving-window offset. */
+typedef struct {
+    void* buf[2];
+    int32_t cur;
+    int32_t pad_;
+    int64_t step;      /* n: the state is at t^n = n dt */
+    int64_t window;    /* cells the moving window has advanced */
+} qds_state;
+
+typedef struct qds_ctx* qds_handle;
+
+/* Create a handle.  ``modes`` retained azimuthal modes m = 0..modes-1 (1..8).
+ * Fails with QDS_ECFL unless |dt - dx| <= 4 ulp(dx) (exact one-cell shift,
+ * Sec. 2.1) and dt^2 mu_max <= 4 for a Gershgorin bound mu_max of the radial
+ * operators (the factorised dispersion relation of the scheme).  Allocates
+ * the library's own scratch (axion-current planes) in device memory. */
+qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out);
+
+/* Bytes of one state buffer, the row pitch in elements, and the byte offset
+ * of a plane within a buffer (-1 if the content does not include it). */
+size_t qds_state_bytes(qds_handle h);
+int32_t qds_row_pitch(qds_handle h);
+int64_t qds_plane_offset(qds_handle h, int32_t plane);
+
+/* Add a forward pulse of polarisation pol ('y','z': linear in mode 1; 'r','t':
+ * radial / azimuthal in mode 0) to set 0 of buffer buf[cur].  f_K, f_J, f_G
+ * are the real polarised field sampled at (x_i, r_{j+1/2}) [nr x nx],
+ * (x_i, r_j) [(nr+1) x nx] and (x_i, r_{nr+1/2}) [nx], in device memory, float64. */
+qds_status qds_add_pulse(qds_handle h, qds_state* st, int32_t pol, const double* f_K,
+                         const double* f_J, const double* f_G, void* stream);
+
+/* Advance n_steps steps (background set, axion, regenerated set). */
+qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const qds_axion* axion,
+                    int64_t n_steps, void* stream);
+
+qds_status qds_destroy(qds_handle h);
+const char* qds_last_error(qds_handle h);
+const char* qds_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

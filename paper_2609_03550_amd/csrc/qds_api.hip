@@ -1,0 +1,239 @@
+// C ABI of libqds (declared in include/qds.h): validation, handle, plane
+// layout and the per-step launch sequence.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/qds.h"
+#include "qds_kernels.hpp"
+
+struct qds_ctx {
+    qds_grid g;
+    int M;
+    double h;
+    int ld;
+    size_t plane_elems;      // complex elements per plane
+    size_t elem_bytes;       // 16 (F64) or 8 (F32)
+    int slot[QDS_NPLANES];   // plane -> position in the buffer, -1 if absent
+    int nplanes;
+    void* scratch;           // axion-current planes (3), library owned
+    char err[256];
+};
+
+namespace {
+
+thread_local char g_err[256] = "";
+
+qds_status fail(qds_ctx* c, qds_status s, const char* fmt, const char* detail = "") {
+    char* buf = c ? c->err : g_err;
+    snprintf(buf, 256, fmt, detail);
+    return s;
+}
+
+bool has(const qds_ctx* c, int plane) { return c->slot[plane] >= 0; }
+
+template <typename T>
+void plane_table(const qds_ctx* c, void* base, qds::cx<T>** out) {
+    for (int p = 0; p < QDS_NPLANES; ++p) {
+        out[p] = c->slot[p] < 0 ? nullptr
+                                : reinterpret_cast<qds::cx<T>*>(static_cast<char*>(base) +
+                                                                size_t(c->slot[p]) * c->plane_elems * c->elem_bytes);
+    }
+}
+
+qds::Geo geo(const qds_ctx* c) {
+    qds::Geo g;
+    g.nx = c->g.nx;
+    g.nr = c->g.nr;
+    g.M = c->M;
+    g.ld = c->ld;
+    g.h = c->h;
+    g.dr = c->g.dr;
+    g.per = c->g.x_bc == QDS_X_PERIODIC;
+    g.open_r = c->g.r_bc == QDS_R_OPEN;
+    return g;
+}
+
+template <typename T>
+qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
+                     hipStream_t s) {
+    qds::StepPlan<T> p;
+    p.g = geo(c);
+    p.plasma = has(c, QDS_P_JX);
+    p.axion = has(c, QDS_P_PHI);
+    p.arem = has(c, QDS_P_SET1);
+    p.wp2 = J ? J->wp2 : 0.0;
+    if (!p.plasma) p.wp2 = 0.0;
+    p.ma2 = ax ? ax->ma2 : 0.0;
+    p.s_phi = ax ? ax->s_phi : 1.0;
+    p.s_j = ax ? ax->s_j : 1.0;
+    p.bx0 = ax ? qds::cx<T>{T(ax->bext[0]), T(ax->bext[1])} : qds::cx<T>{T(0), T(0)};
+    p.br1 = ax ? qds::cx<T>{T(ax->bext[2]), T(ax->bext[3])} : qds::cx<T>{T(0), T(0)};
+    p.bt1 = ax ? qds::cx<T>{T(ax->bext[4]), T(ax->bext[5])} : qds::cx<T>{T(0), T(0)};
+    p.drive.on = (J && J->kind == QDS_J_RING) ? 1 : 0;
+    if (p.drive.on) {
+        p.drive.amp = J->amp; p.drive.x0 = J->x0; p.drive.v = J->v; p.drive.sx = J->sx;
+        p.drive.r0 = J->r0; p.drive.sr = J->sr; p.drive.noise = J->noise; p.drive.seed = J->seed;
+    }
+    qds::cx<T>* scr[3] = {nullptr, nullptr, nullptr};
+    if (c->scratch) {
+        for (int k = 0; k < 3; ++k)
+            scr[k] = reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) + size_t(k) * c->plane_elems * c->elem_bytes);
+    }
+    for (int k = 0; k < 3; ++k) p.ja[k] = scr[k];
+    const bool window = c->g.x_bc == QDS_X_WINDOW;
+    for (int64_t it = 0; it < n_steps; ++it) {
+        int a = st->cur, b = 1 - st->cur;
+        plane_table<T>(c, st->buf[a], p.A);
+        plane_table<T>(c, st->buf[b], p.B);
+        p.n = st->step;
+        p.w = st->window;
+        hipError_t e = qds::staged_step<T>(p, s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (window) {
+            // the new state (in b) moves one cell left into a
+            e = qds::window_shift<T>(reinterpret_cast<const qds::cx<T>*>(st->buf[b]),
+                                     reinterpret_cast<qds::cx<T>*>(st->buf[a]), p.g, c->nplanes, s);
+            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            st->window += 1;
+        } else {
+            st->cur = b;
+        }
+        st->step += 1;
+    }
+    return QDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qds_version(void) { return "qds-mi355x 0.1"; }
+
+const char* qds_last_error(qds_handle h) { return h ? h->err : g_err; }
+
+qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out) {
+    if (!grid || !out) return fail(nullptr, QDS_EINVAL, "null argument%s");
+    *out = nullptr;
+    const qds_grid& g = *grid;
+    if (g.nx < 8 || g.nr < 4) return fail(nullptr, QDS_EINVAL, "grid too small (nx >= 8, nr >= 4)%s");
+    if (g.nx >= (1 << 20) || g.nr >= 4096) return fail(nullptr, QDS_EINVAL, "grid too large%s");
+    if (modes < 1 || modes > QDS_MAX_MODES) return fail(nullptr, QDS_EUNSUPPORTED, "modes must be 1..8%s");
+    if (g.dtype != QDS_F64 && g.dtype != QDS_F32) return fail(nullptr, QDS_EINVAL, "bad dtype%s");
+    if (g.x_bc < 0 || g.x_bc > 2 || g.r_bc < 0 || g.r_bc > 1) return fail(nullptr, QDS_EINVAL, "bad boundary%s");
+    if ((g.content & QDS_HAS_AREM) && !(g.content & QDS_HAS_AXION))
+        return fail(nullptr, QDS_EINVAL, "regenerated fields need the axion%s");
+    if (!(dx > 0) || !(g.dr > 0)) return fail(nullptr, QDS_EINVAL, "dx and dr must be positive%s");
+    // exact one-cell transport needs c dt = dx (Sec. 2.1)
+    if (fabs(dt - dx) > 4.0 * (nextafter(dx, 2 * dx) - dx))
+        return fail(nullptr, QDS_ECFL, "c dt must equal dx%s");
+    // radial stability: dt^2 mu_max <= 4 with mu_max bounded by row sums of the
+    // radial operators (|Laplacian| <= 4/dr^2 plus the coupling terms, and
+    // m^2/r^2 <= 4 m^2/dr^2 on the first half row)
+    const double mmax = modes - 1;
+    const double mu_bound = (8.0 + 4.0 * mmax * mmax) / (g.dr * g.dr);
+    if (dt * dt * mu_bound > 4.0) return fail(nullptr, QDS_ECFL, "radial stability bound dt^2 mu_max <= 4 fails%s");
+
+    qds_ctx* c = new (std::nothrow) qds_ctx;
+    if (!c) return fail(nullptr, QDS_ENOMEM, "out of host memory%s");
+    memset(c, 0, sizeof(*c));
+    c->g = g;
+    c->M = modes;
+    c->h = dx;
+    c->ld = (g.nx + 31) / 32 * 32;
+    c->plane_elems = size_t(modes) * size_t(g.nr + 1) * size_t(c->ld);
+    c->elem_bytes = g.dtype == QDS_F64 ? 16 : 8;
+    for (int p = 0; p < QDS_NPLANES; ++p) c->slot[p] = -1;
+    int n = 0;
+    auto add_set = [&](int base, bool plasma) {
+        for (int k = 0; k < 6; ++k) c->slot[base + k] = n++;
+        if (plasma)
+            for (int k = 6; k < 9; ++k) c->slot[base + k] = n++;
+    };
+    const bool plasma = g.content & QDS_HAS_PLASMA;
+    add_set(0, plasma);
+    if (g.content & QDS_HAS_AREM) add_set(QDS_P_SET1, plasma);
+    if (g.content & QDS_HAS_AXION)
+        for (int k = QDS_P_PHI; k <= QDS_P_TAM; ++k) c->slot[k] = n++;
+    c->nplanes = n;
+    if (g.content & QDS_HAS_AREM) {
+        hipError_t e = hipMalloc(&c->scratch, 3 * c->plane_elems * c->elem_bytes);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, QDS_ENOMEM, "hipMalloc of the axion-current scratch failed: %s", hipGetErrorString(e));
+        }
+        hipMemset(c->scratch, 0, 3 * c->plane_elems * c->elem_bytes);
+    }
+    *out = c;
+    return QDS_OK;
+}
+
+size_t qds_state_bytes(qds_handle h) { return h ? size_t(h->nplanes) * h->plane_elems * h->elem_bytes : 0; }
+
+int32_t qds_row_pitch(qds_handle h) { return h ? h->ld : 0; }
+
+int64_t qds_plane_offset(qds_handle h, int32_t plane) {
+    if (!h || plane < 0 || plane >= QDS_NPLANES || h->slot[plane] < 0) return -1;
+    return int64_t(h->slot[plane]) * int64_t(h->plane_elems * h->elem_bytes);
+}
+
+static qds_status check_state(qds_ctx* c, const qds_state* st) {
+    if (!st) return fail(c, QDS_EINVAL, "null state%s");
+    if (!st->buf[0] || !st->buf[1] || st->buf[0] == st->buf[1])
+        return fail(c, QDS_ESTATE, "state needs two distinct device buffers%s");
+    if (st->cur != 0 && st->cur != 1) return fail(c, QDS_ESTATE, "state.cur must be 0 or 1%s");
+    if (st->step < 0 || st->window < 0) return fail(c, QDS_ESTATE, "negative step or window%s");
+    if (st->step >= (int64_t(1) << 31)) return fail(c, QDS_ESTATE, "step counter out of range%s");
+    return QDS_OK;
+}
+
+qds_status qds_add_pulse(qds_handle h, qds_state* st, int32_t pol, const double* f_K, const double* f_J,
+                         const double* f_G, void* stream) {
+    if (!h) return fail(nullptr, QDS_EINVAL, "null handle%s");
+    qds_status s = check_state(h, st);
+    if (s != QDS_OK) return s;
+    if (!f_K || !f_J || !f_G) return fail(h, QDS_EINVAL, "null field sample%s");
+    if (pol != 'y' && pol != 'z' && pol != 'r' && pol != 't') return fail(h, QDS_EINVAL, "pol must be y, z, r or t%s");
+    if ((pol == 'y' || pol == 'z') && h->M < 2) return fail(h, QDS_EINVAL, "a linear polarisation needs mode 1%s");
+    hipError_t e;
+    qds::Geo g = geo(h);
+    if (h->g.dtype == QDS_F64) {
+        qds::cx<double>* P[QDS_NPLANES];
+        plane_table<double>(h, st->buf[st->cur], P);
+        e = qds::add_pulse<double>(qds::SetPtr<double>{P[0], P[1], P[2], P[3], P[4], P[5], P[6], P[7], P[8]}, g, pol,
+                                   f_K, f_J, f_G, hipStream_t(stream));
+    } else {
+        qds::cx<float>* P[QDS_NPLANES];
+        plane_table<float>(h, st->buf[st->cur], P);
+        e = qds::add_pulse<float>(qds::SetPtr<float>{P[0], P[1], P[2], P[3], P[4], P[5], P[6], P[7], P[8]}, g, pol,
+                                  f_K, f_J, f_G, hipStream_t(stream));
+    }
+    if (e != hipSuccess) return fail(h, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    return QDS_OK;
+}
+
+qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const qds_axion* axion, int64_t n_steps,
+                    void* stream) {
+    if (!h) return fail(nullptr, QDS_EINVAL, "null handle%s");
+    qds_status s = check_state(h, fields);
+    if (s != QDS_OK) return s;
+    if (n_steps < 0) return fail(h, QDS_EINVAL, "negative step count%s");
+    if (J && J->kind != QDS_J_NONE && J->kind != QDS_J_RING) return fail(h, QDS_EINVAL, "bad current kind%s");
+    if (J && J->kind == QDS_J_RING && (!(J->sx > 0) || !(J->sr > 0)))
+        return fail(h, QDS_EINVAL, "drive widths must be positive%s");
+    if (J && J->wp2 != 0.0 && !has(h, QDS_P_JX)) return fail(h, QDS_EINVAL, "plasma response needs the plasma planes%s");
+    if (fields->step + n_steps >= (int64_t(1) << 31)) return fail(h, QDS_ESTATE, "step counter would overflow%s");
+    if (h->g.dtype == QDS_F64) return run_steps<double>(h, fields, J, axion, n_steps, hipStream_t(stream));
+    return run_steps<float>(h, fields, J, axion, n_steps, hipStream_t(stream));
+}
+
+qds_status qds_destroy(qds_handle h) {
+    if (!h) return QDS_OK;
+    if (h->scratch) hipFree(h->scratch);
+    delete h;
+    return QDS_OK;
+}
+
+}  // extern "C"

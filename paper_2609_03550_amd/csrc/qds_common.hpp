@@ -1,0 +1,99 @@
+// Device-side building blocks shared by the QDS kernels: complex arithmetic,
+// plane addressing, the mode convolution C_m and the counter-based noise.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define QDS_MAX_MODES 8
+
+namespace qds {
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> zero() { return cx<T>{T(0), T(0)}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+// i * s * a  (multiplication by an imaginary number i s)
+template <typename T> __device__ __forceinline__ cx<T> imul(T s, cx<T> a) { return {-s * a.im, s * a.re}; }
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> mulc(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+// Vector load/store of one complex element (16 B for double, 8 B for float).
+__device__ __forceinline__ cx<double> ld(const cx<double>* p) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ld(const cx<float>* p) {
+    float2 v = *reinterpret_cast<const float2*>(p);
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st(cx<double>* p, cx<double> a) {
+    *reinterpret_cast<double2*>(p) = make_double2(a.re, a.im);
+}
+__device__ __forceinline__ void st(cx<float>* p, cx<float> a) {
+    *reinterpret_cast<float2*>(p) = make_float2(a.re, a.im);
+}
+
+// Mode convolution C_m{A, B} (the azimuthal projection of a product of two
+// real fields, Eqs. source_mode_zero / source_mode_m): with a_k = A^(k) for
+// k = 0 and A^(k)/2, conj(A^(k))/2 for +-k, the mode-m coefficient of AB is
+// P^(0) = sum_k a_k b_-k and P^(m) = 2 sum_{k+l=m} a_k b_l.  Written out:
+//   m = 0: A0 B0 + 1/2 sum_{k>0} Re(A_k conj(B_k))
+//   m > 0: 1/2 [ sum_{k+l=m} A_k B_l + sum_{k-l=m} A_k conj(B_l) + sum_{l-k=m} conj(A_k) B_l ]
+template <typename T, int M>
+__device__ __forceinline__ void conv_acc(const cx<T>* A, const cx<T>* B, T sign, cx<T>* out) {
+    {
+        cx<T> s = A[0] * B[0];
+        T re = T(0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) re += A[k].re * B[k].re + A[k].im * B[k].im;
+        s.re += T(0.5) * re;
+        out[0] = out[0] + sign * s;
+    }
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+        cx<T> acc = zero<T>();
+#pragma unroll
+        for (int k = 0; k <= m; ++k) acc = acc + A[k] * B[m - k];
+#pragma unroll
+        for (int l = 0; l + m < M; ++l) acc = acc + mulc(A[l + m], B[l]);
+#pragma unroll
+        for (int k = 0; k + m < M; ++k) acc = acc + cmul(A[k], B[k + m]);
+        out[m] = out[m] + (sign * T(0.5)) * acc;
+    }
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k >= 1 of the stream seeded
+// with ``seed`` is mix(seed + k * 0x9E3779B97F4A7C15).  Box-Muller normal from
+// outputs 2c+1, 2c+2 of counter c = (step << 32) | (lab column << 12) | row.
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double normal_ctr(uint64_t seed, uint64_t c) {
+    const uint64_t g = 0x9E3779B97F4A7C15ull;
+    uint64_t z1 = sm64_mix(seed + (2 * c + 1) * g);
+    uint64_t z2 = sm64_mix(seed + (2 * c + 2) * g);
+    double u1 = (double((z1 >> 11)) + 1.0) * 0x1.0p-53;
+    double u2 = double(z2 >> 11) * 0x1.0p-53;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+}  // namespace qds

@@ -1,0 +1,122 @@
+// Kernel argument blocks and host-side entry points of the QDS step.
+#pragma once
+#include "qds_common.hpp"
+
+namespace qds {
+
+// Grid geometry and plane addressing: element (mode m, row, column c) of a
+// plane is at (m * (nr + 1) + row) * ld + c.
+struct Geo {
+    int nx, nr, M, ld;
+    double h, dr;
+    int per;      // periodic x
+    int open_r;   // outflow at r = R_max (else conducting wall)
+    __host__ __device__ __forceinline__ size_t at(int m, int row, int c) const {
+        return (size_t(m) * size_t(nr + 1) + size_t(row)) * size_t(ld) + size_t(c);
+    }
+};
+
+struct Drive {
+    int on;
+    double amp, x0, v, sx, r0, sr, noise;
+    uint64_t seed;
+};
+
+template <typename T>
+struct SetPtr {
+    cx<T>* trp;
+    cx<T>* trm;
+    cx<T>* ttp;
+    cx<T>* ttm;
+    cx<T>* ex;
+    cx<T>* bx;
+    cx<T>* jx;   // plasma planes (null without plasma)
+    cx<T>* jr;
+    cx<T>* jt;
+};
+
+template <typename T>
+struct StageArgs {
+    Geo g;
+    SetPtr<T> A, B;             // old / new state of this set
+    const cx<T>* jx_add;        // extra currents at the source points (or null)
+    const cx<T>* jr_add;
+    const cx<T>* jt_add;
+    int plasma;
+    double wp2;
+    Drive drive;                // prescribed j_x^(0) (background set only)
+    int64_t n, w;               // step and window offset
+};
+
+template <typename T>
+struct AxionArgs {
+    Geo g;
+    SetPtr<T> A0, B0;           // background set, old / new
+    const cx<T>* phiA;
+    const cx<T>* tapA;
+    const cx<T>* tamA;
+    cx<T>* phiB;
+    cx<T>* tapB;
+    cx<T>* tamB;
+    cx<T>* jax;                 // scratch: axion current at the source points
+    cx<T>* jar;
+    cx<T>* jat;
+    double ma2, s_phi, s_j;
+    cx<T> bx0, br1, bt1;        // uniform external field (B_x^(0), B_r^(1), B_theta^(1))
+};
+
+// Everything one step needs: two state buffers (old A, new B) as plane
+// pointer tables, the physics and the step counters.
+template <typename T>
+struct StepPlan {
+    Geo g;
+    cx<T>* A[21];
+    cx<T>* B[21];
+    cx<T>* ja[3];
+    int plasma, axion, arem;
+    double wp2, ma2, s_phi, s_j;
+    cx<T> bx0, br1, bt1;
+    Drive drive;
+    int64_t n, w;
+
+    SetPtr<T> set(cx<T>* const* P, int s) const {
+        const int b = 9 * s;
+        return SetPtr<T>{P[b + 0], P[b + 1], P[b + 2], P[b + 3], P[b + 4], P[b + 5], P[b + 6], P[b + 7], P[b + 8]};
+    }
+    StageArgs<T> set_args(int s) const {
+        StageArgs<T> a;
+        a.g = g;
+        a.A = set(A, s);
+        a.B = set(B, s);
+        a.jx_add = s ? ja[0] : nullptr;
+        a.jr_add = s ? ja[1] : nullptr;
+        a.jt_add = s ? ja[2] : nullptr;
+        a.plasma = plasma;
+        a.wp2 = wp2;
+        a.drive = drive;
+        if (s) a.drive.on = 0;
+        a.n = n;
+        a.w = w;
+        return a;
+    }
+    AxionArgs<T> axion_args() const {
+        AxionArgs<T> x;
+        x.g = g;
+        x.A0 = set(A, 0);
+        x.B0 = set(B, 0);
+        x.phiA = A[18]; x.tapA = A[19]; x.tamA = A[20];
+        x.phiB = B[18]; x.tapB = B[19]; x.tamB = B[20];
+        x.jax = ja[0]; x.jar = ja[1]; x.jat = ja[2];
+        x.ma2 = ma2; x.s_phi = s_phi; x.s_j = s_j;
+        x.bx0 = bx0; x.br1 = br1; x.bt1 = bt1;
+        return x;
+    }
+};
+
+template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
+template <typename T> hipError_t window_shift(const cx<T>* src, cx<T>* dst, const Geo& g, int nplanes, hipStream_t s);
+template <typename T>
+hipError_t add_pulse(SetPtr<T> s0, const Geo& g, int pol, const double* fK, const double* fJ, const double* fG,
+                     hipStream_t s);
+
+}  // namespace qds

@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libqds (include/qds.h).
+
+Argument marshalling only: every step of the field advance runs in the HIP
+library.  PyTorch supplies the device memory (two state buffers) and the
+stream.  Importing this module loads libqds.so and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqds.so")
+
+QDS_OK, QDS_EINVAL, QDS_ECFL, QDS_ENOMEM, QDS_EHIP, QDS_EUNSUPPORTED, QDS_ESTATE = range(7)
+F64, F32 = 0, 1
+X_BC = {"open": 0, "periodic": 1, "window": 2}
+R_BC = {"open": 0, "pec": 1}
+HAS_PLASMA, HAS_AXION, HAS_AREM = 1, 2, 4
+J_NONE, J_RING = 0, 1
+P_TRP, P_TRM, P_TTP, P_TTM, P_EX, P_BX, P_JX, P_JR, P_JT = range(9)
+P_SET1, P_PHI, P_TAP, P_TAM = 9, 18, 19, 20
+
+EXPORTS = ("qds_init", "qds_state_bytes", "qds_row_pitch", "qds_plane_offset", "qds_add_pulse",
+           "qds_step", "qds_destroy", "qds_last_error", "qds_version")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nr", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("x_bc", ctypes.c_int32), ("r_bc", ctypes.c_int32), ("content", ctypes.c_int32),
+                ("dr", ctypes.c_double)]
+
+
+class Current(ctypes.Structure):
+    _fields_ = [("wp2", ctypes.c_double), ("kind", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("amp", ctypes.c_double), ("x0", ctypes.c_double), ("v", ctypes.c_double),
+                ("sx", ctypes.c_double), ("r0", ctypes.c_double), ("sr", ctypes.c_double),
+                ("noise", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class Axion(ctypes.Structure):
+    _fields_ = [("ma2", ctypes.c_double), ("s_phi", ctypes.c_double), ("s_j", ctypes.c_double),
+                ("bext", ctypes.c_double * 6)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("buf", ctypes.c_void_p * 2), ("cur", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("window", ctypes.c_int64)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.qds_init.argtypes = [ctypes.POINTER(Grid), i32, dbl, dbl, ctypes.POINTER(vp)]
+    lib.qds_init.restype = i32
+    lib.qds_state_bytes.argtypes = [vp]
+    lib.qds_state_bytes.restype = ctypes.c_size_t
+    lib.qds_row_pitch.argtypes = [vp]
+    lib.qds_row_pitch.restype = i32
+    lib.qds_plane_offset.argtypes = [vp, i32]
+    lib.qds_plane_offset.restype = i64
+    lib.qds_add_pulse.argtypes = [vp, ctypes.POINTER(State), i32, vp, vp, vp, vp]
+    lib.qds_add_pulse.restype = i32
+    lib.qds_step.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion), i64, vp]
+    lib.qds_step.restype = i32
+    lib.qds_destroy.argtypes = [vp]
+    lib.qds_destroy.restype = i32
+    lib.qds_last_error.argtypes = [vp]
+    lib.qds_last_error.restype = ctypes.c_char_p
+    lib.qds_version.argtypes = []
+    lib.qds_version.restype = ctypes.c_char_p
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class QDSError(RuntimeError):
+    pass
+
+
+def _check(status: int, handle) -> None:
+    if status != QDS_OK:
+        msg = lib().qds_last_error(handle).decode()
+        raise QDSError(f"libqds status {status}: {msg}")
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Solver:
+    """One QDS field advance on one GPU: a libqds handle plus its two state
+    buffers (torch uint8 tensors on the device)."""
+
+    def __init__(self, wl: I.Workload, dtype: str = "f64", device: str = "cuda:0"):
+        self.wl = wl
+        self.device = torch.device(device)
+        self.dtype = dtype
+        content = 0
+        if wl.wp2 != 0.0:
+            content |= HAS_PLASMA
+        if wl.axion:
+            content |= HAS_AXION
+        if wl.arem:
+            content |= HAS_AREM
+        g = Grid(wl.nx, wl.nr, F64 if dtype == "f64" else F32, X_BC[wl.x_bc], R_BC[wl.r_bc], content, wl.dr)
+        h = ctypes.c_void_p()
+        _check(lib().qds_init(ctypes.byref(g), wl.nmodes, wl.h, wl.h, ctypes.byref(h)), None)
+        self.h = h
+        self.nbytes = int(lib().qds_state_bytes(h))
+        self.ld = int(lib().qds_row_pitch(h))
+        self.bufs = [torch.zeros(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.state = State()
+        self.state.buf[0] = self.bufs[0].data_ptr()
+        self.state.buf[1] = self.bufs[1].data_ptr()
+        self.state.cur = 0
+        self.state.step = 0
+        self.state.window = 0
+        self.cur = self._current()
+        self.ax = self._axion()
+
+    # -- parameters ---------------------------------------------------------
+    def _current(self) -> Current:
+        c = Current()
+        c.wp2 = self.wl.wp2
+        d = self.wl.drive
+        if d is None:
+            c.kind = J_NONE
+        else:
+            c.kind = J_RING
+            c.amp, c.x0, c.v, c.sx, c.r0, c.sr, c.noise = d.amp, d.x0, d.v, d.sx, d.r0, d.sr, d.noise
+            c.seed = d.seed
+        return c
+
+    def _axion(self) -> Axion:
+        a = Axion()
+        a.ma2, a.s_phi, a.s_j = self.wl.ma2, self.wl.s_phi, self.wl.s_j
+        for k, z in enumerate(self.wl.bext):
+            a.bext[2 * k] = complex(z).real
+            a.bext[2 * k + 1] = complex(z).imag
+        return a
+
+    # -- state --------------------------------------------------------------
+    def load_pulses(self, pulses=None, basis=None) -> None:
+        """Add the workload's pulses (sampled at the staggered points) to set 0.
+        ``basis`` = (pulse index, coefficient index) loads the derivative of the
+        pulse with respect to that envelope coefficient instead."""
+        wl = self.wl
+        xI = np.arange(wl.nx) * wl.h
+        rK = (np.arange(wl.nr) + 0.5) * wl.dr
+        rJ = np.arange(wl.nr + 1) * wl.dr
+        rG = np.array([(wl.nr + 0.5) * wl.dr])
+        plist = [(None, p) for p in (pulses if pulses is not None else wl.pulses)]
+        if basis is not None:
+            plist = [(basis[1], wl.pulses[basis[0]])]
+        for q, p in plist:
+            f = p.field if q is None else (lambda x, r, p=p, q=q: p.field_basis(x, r, q))
+            fK = torch.from_numpy(np.ascontiguousarray(f(xI[None, :], rK[:, None]))).to(self.device)
+            fJ = torch.from_numpy(np.ascontiguousarray(f(xI[None, :], rJ[:, None]))).to(self.device)
+            fG = torch.from_numpy(np.ascontiguousarray(f(xI[None, :], rG[:, None])[0])).to(self.device)
+            _check(lib().qds_add_pulse(self.h, ctypes.byref(self.state), ord(p.pol), fK.data_ptr(),
+                                       fJ.data_ptr(), fG.data_ptr(), _stream_ptr()), self.h)
+            torch.cuda.current_stream().synchronize()
+
+    def step(self, n: int = 1, stream=None) -> None:
+        _check(lib().qds_step(self.h, ctypes.byref(self.state), ctypes.byref(self.cur),
+                              ctypes.byref(self.ax), int(n), _stream_ptr(stream)), self.h)
+
+    @property
+    def n(self) -> int:
+        return int(self.state.step)
+
+    @property
+    def window(self) -> int:
+        return int(self.state.window)
+
+    def plane(self, plane: int, which: Optional[int] = None) -> Optional[torch.Tensor]:
+        """View of one plane of a state buffer as a complex tensor [M, nr+1, nx]."""
+        off = int(lib().qds_plane_offset(self.h, plane))
+        if off < 0:
+            return None
+        b = self.bufs[self.state.cur if which is None else which]
+        ebytes = 16 if self.dtype == "f64" else 8
+        cdt = torch.complex128 if self.dtype == "f64" else torch.complex64
+        M, nr, ld = self.wl.nmodes, self.wl.nr, self.ld
+        n = M * (nr + 1) * ld
+        v = b[off:off + n * ebytes].view(cdt).view(M, nr + 1, ld)
+        return v[..., : self.wl.nx]
+
+    def fields(self) -> Dict[str, torch.Tensor]:
+        """Current state as named complex128 CPU tensors (names of the
+        state dictionary the oracle uses)."""
+        nr = self.wl.nr
+        out = {}
+        sets = [0, 1] if self.wl.arem else [0]
+        for s in sets:
+            b = 9 * s
+            trp = self.plane(b + P_TRP)
+            out[f"Trp{s}"] = trp[:, :nr]
+            out[f"Bg{s}"] = trp[:, nr]
+            out[f"Trm{s}"] = self.plane(b + P_TRM)[:, :nr]
+            out[f"Ttp{s}"] = self.plane(b + P_TTP)
+            out[f"Ttm{s}"] = self.plane(b + P_TTM)
+            out[f"Ex{s}"] = self.plane(b + P_EX)
+            out[f"Bx{s}"] = self.plane(b + P_BX)
+            if self.wl.wp2 != 0.0:
+                out[f"jx{s}"] = self.plane(b + P_JX)
+                out[f"jr{s}"] = self.plane(b + P_JR)[:, :nr]
+                out[f"jt{s}"] = self.plane(b + P_JT)
+        if self.wl.axion:
+            phi = self.plane(P_PHI)
+            out["phi"] = phi[:, :nr]
+            out["phig"] = phi[:, nr]
+            out["Tap"] = self.plane(P_TAP)[:, :nr]
+            out["Tam"] = self.plane(P_TAM)[:, :nr]
+        return {k: v.to("cpu", torch.complex128) for k, v in out.items()}
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().qds_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

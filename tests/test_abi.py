@@ -1,0 +1,75 @@
+"""The C-ABI library: loads on a CPU-only host, exports every declared symbol,
+and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qds.h")
+LIB = os.path.join(ROOT, "paper_2609_03550_amd", "libqds.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(qds_\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libqds.so not built (run __graft_entry__.build())")
+    from paper_2609_03550_amd import qds
+    return qds.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("qds_init", "qds_step", "qds_destroy", "qds_last_error", "qds_state_bytes",
+              "qds_plane_offset", "qds_add_pulse"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_init_rejects_bad_arguments(lib):
+    from paper_2609_03550_amd import qds
+    h = ctypes.c_void_p()
+    g = qds.Grid(64, 16, qds.F64, 0, 0, 0, 1.0)
+    # c dt != dx
+    assert lib.qds_init(ctypes.byref(g), 2, 0.25, 0.3, ctypes.byref(h)) == qds.QDS_ECFL
+    assert b"dt" in lib.qds_last_error(None)
+    # radial stability bound (dr far too small for the step)
+    g2 = qds.Grid(64, 16, qds.F64, 0, 0, 0, 0.05)
+    assert lib.qds_init(ctypes.byref(g2), 3, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_ECFL
+    # too many modes, tiny grid, regenerated fields without the axion
+    assert lib.qds_init(ctypes.byref(g), 9, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_EUNSUPPORTED
+    g3 = qds.Grid(4, 16, qds.F64, 0, 0, 0, 1.0)
+    assert lib.qds_init(ctypes.byref(g3), 2, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_EINVAL
+    g4 = qds.Grid(64, 16, qds.F64, 0, 0, qds.HAS_AREM, 1.0)
+    assert lib.qds_init(ctypes.byref(g4), 2, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_EINVAL
+
+
+def test_layout_queries_on_cpu(lib):
+    """Handles without the regenerated set allocate nothing on the device, so
+    the layout can be queried on a CPU-only host."""
+    from paper_2609_03550_amd import qds
+    h = ctypes.c_void_p()
+    g = qds.Grid(100, 16, qds.F64, 0, 0, qds.HAS_PLASMA | qds.HAS_AXION, 1.0)
+    assert lib.qds_init(ctypes.byref(g), 3, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_OK
+    ld = lib.qds_row_pitch(h)
+    assert ld % 32 == 0 and ld >= 100
+    plane = 3 * 17 * ld * 16
+    assert lib.qds_state_bytes(h) == 12 * plane
+    assert lib.qds_plane_offset(h, qds.P_TRP) == 0
+    assert lib.qds_plane_offset(h, qds.P_JT) == 8 * plane
+    assert lib.qds_plane_offset(h, qds.P_SET1) == -1
+    assert lib.qds_plane_offset(h, qds.P_PHI) == 9 * plane
+    assert lib.qds_step(h, None, None, None, 1, None) == qds.QDS_EINVAL
+    st = qds.State()
+    assert lib.qds_step(h, ctypes.byref(st), None, None, 1, None) == qds.QDS_ESTATE
+    assert lib.qds_destroy(h) == qds.QDS_OK

@@ -1,0 +1,91 @@
+"""GPU parity: the HIP step (through the C ABI) against the CPU oracle, element
+by element on the same seeded inputs.  FP64: relative L2 per field and mode
+<= 1e-12; FP32: <= 1e-5 per field and mode relative to the norm of the field
+set (background EM, regenerated EM, plasma currents, axion) it belongs to."""
+import os
+
+import pytest
+import torch
+
+from paper_2609_03550_amd import inputs as I
+import parity_tools as P
+
+pytestmark = pytest.mark.gpu
+H, DR = I.H, I.DR
+TOL = {"f64": (1e-12, 1e-13), "f32": (1e-5, 1e-6)}
+
+
+def _solver(wl, dtype):
+    from paper_2609_03550_amd import qds
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_pulses()
+    return s
+
+
+def _check(wl, nsteps, dtype, chunks=1):
+    s = _solver(wl, dtype)
+    for _ in range(chunks):
+        s.step(nsteps // chunks)
+    torch.cuda.synchronize()
+    ora = P.oracle_run(wl, nsteps)
+    tol, floor = TOL[dtype]
+    P.compare_states(s.fields(), ora, tol, floor, by_group=(dtype == "f32"))
+    assert s.n == nsteps
+    return s
+
+
+def _vac(nx, nr, M, **kw):
+    p = I.Pulse("y", 0.05, 1.0, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+    return I.Workload("vac", nx, nr, M, 0, pulses=(p,)).with_(**kw)
+
+
+def _full(nx, nr, M, **kw):
+    p1 = I.Pulse("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+    p2 = I.Pulse("z", 0.5, 0.8, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+    if M == 1:
+        p1 = I.Pulse("r", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+        p2 = I.Pulse("t", 0.5, 0.8, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+    wl = I.Workload("full", nx, nr, M, 0, wp2=0.01, axion=True, arem=True, ma2=0.02, pulses=(p1, p2))
+    return wl.with_(**kw)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("x_bc,r_bc", [("open", "open"), ("periodic", "pec"), ("open", "pec"), ("periodic", "open")])
+def test_vacuum_em(dtype, x_bc, r_bc):
+    _check(_vac(130, 14, 3, x_bc=x_bc, r_bc=r_bc), 25, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_config1_vacuum_pulse_full_length(dtype):
+    """512 x 64 x 2 modes, 200 steps: the small EM workload in full."""
+    _check(I.vacuum_em(), 200, dtype, chunks=4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_driven_moving_window(dtype):
+    wl = I.driven_window(nx=200, nr=20, steps=0)
+    d = wl.drive
+    wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed),
+                  pulses=(wl.pulses[0].__class__("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 140 * H),))
+    _check(wl, 30, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
+def test_full_physics_modes(dtype, M):
+    _check(_full(97, 13, M), 14, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64"])
+@pytest.mark.parametrize("x_bc,r_bc", [("periodic", "pec"), ("periodic", "open"), ("open", "pec")])
+def test_full_physics_boundaries(dtype, x_bc, r_bc):
+    _check(_full(96, 12, 3, x_bc=x_bc, r_bc=r_bc), 14, dtype)
+
+
+def test_full_physics_external_field_and_scales():
+    wl = _full(100, 12, 3, bext=(0.3 + 0j, 0.7 - 0.2j, -0.2 - 0.7j), s_phi=0.5, s_j=2.0)
+    _check(wl, 10, "f64")
+
+
+def test_full_physics_longer_run():
+    _check(_full(160, 24, 3), 120, "f64", chunks=3)
