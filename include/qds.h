@@ -139,6 +139,25 @@ qds_status qds_add_pulse(qds_handle h, qds_state* st, int32_t pol, const double*
 qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const qds_axion* axion,
                     int64_t n_steps, void* stream);
 
+/* Options (synchronous, host only):
+ *  QDS_OPT_PATH   QDS_PATH_AUTO (fused single-pass kernels when modes <= 4),
+ *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
+ *  QDS_OPT_ROWS   radial rows per workgroup chunk of the fused kernels (1..4096)
+ *  QDS_OPT_TIMING 1: qds_step brackets each kernel with HIP events on the
+ *                 caller's stream and synchronises on them (for measurement);
+ *                 resets the accumulated times */
+enum { QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3 };
+enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
+qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
+
+/* Accumulated kernel time (ms) and launch counts since timing was enabled:
+ * index 0 = the background-set kernel (kernel A; the whole step on the staged
+ * path), index 1 = the regenerated-set kernel (kernel B).  ms[2], launches[2]. */
+qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches);
+
+/* 1 if qds_step runs the fused kernels for this handle. */
+int32_t qds_uses_fused(qds_handle h);
+
 qds_status qds_destroy(qds_handle h);
 const char* qds_last_error(qds_handle h);
 const char* qds_version(void);

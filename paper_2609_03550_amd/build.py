@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqds.so")
-SOURCES = ["qds_api.hip", "qds_stages.hip"]
+SOURCES = ["qds_api.hip", "qds_stages.hip", "qds_fused.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -17,6 +17,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-result",
 ]
+if os.environ.get("QDS_RESOURCE_USAGE"):
+    FLAGS.append("-Rpass-analysis=kernel-resource-usage")
 
 
 def build(verbose: bool = False) -> str:

@@ -19,6 +19,12 @@ struct qds_ctx {
     int slot[QDS_NPLANES];   // plane -> position in the buffer, -1 if absent
     int nplanes;
     void* scratch;           // axion-current planes (3), library owned
+    int path;                // QDS_PATH_*
+    int rows;                // radial rows per workgroup of the fused kernels
+    int timing;              // record per-kernel HIP events in qds_step
+    hipEvent_t ev[3];
+    double t_ms[2];          // accumulated kernel time: [0] kernel A / set 0, [1] kernel B
+    int64_t t_n[2];
     char err[256];
 };
 
@@ -56,6 +62,74 @@ qds::Geo geo(const qds_ctx* c) {
     return g;
 }
 
+bool use_fused(const qds_ctx* c) {
+    if (c->path == QDS_PATH_STAGED) return false;
+    return c->M <= 4;
+}
+
+template <typename T>
+qds::SetP<T> fused_set(qds::cx<T>* const* A, qds::cx<T>* const* B, int s) {
+    const int b = 9 * s;
+    qds::SetP<T> p;
+    p.trp = A[b + 0]; p.trm = A[b + 1]; p.ttp = A[b + 2]; p.ttm = A[b + 3];
+    p.ex = A[b + 4]; p.bx = A[b + 5]; p.jx = A[b + 6]; p.jr = A[b + 7]; p.jt = A[b + 8];
+    p.otrp = B[b + 0]; p.otrm = B[b + 1]; p.ottp = B[b + 2]; p.ottm = B[b + 3];
+    p.oex = B[b + 4]; p.obx = B[b + 5]; p.ojx = B[b + 6]; p.ojr = B[b + 7]; p.ojt = B[b + 8];
+    p.jxa = p.jra = p.jta = nullptr;
+    return p;
+}
+
+template <typename T>
+qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s) {
+    qds::FusedArgs<T> a;
+    a.g = p0.g;
+    a.plasma = p0.plasma;
+    a.axion = p0.axion;
+    a.wp2 = p0.wp2; a.ma2 = p0.ma2; a.s_phi = p0.s_phi; a.s_j = p0.s_j;
+    a.bx0 = p0.bx0; a.br1 = p0.br1; a.bt1 = p0.bt1;
+    a.drive = p0.drive;
+    a.window = c->g.x_bc == QDS_X_WINDOW;
+    a.rows = c->rows;
+    a.jax = p0.ja[0]; a.jar = p0.ja[1]; a.jat = p0.ja[2];
+    for (int64_t it = 0; it < n_steps; ++it) {
+        const int ia = st->cur, ib = 1 - st->cur;
+        qds::cx<T>* A[QDS_NPLANES];
+        qds::cx<T>* B[QDS_NPLANES];
+        plane_table<T>(c, st->buf[ia], A);
+        plane_table<T>(c, st->buf[ib], B);
+        a.s0 = fused_set<T>(A, B, 0);
+        a.s1 = fused_set<T>(A, B, 1);
+        a.s1.jxa = a.jax; a.s1.jra = a.jar; a.s1.jta = a.jat;
+        a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
+        a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
+        a.n = st->step;
+        a.w = st->window;
+        if (c->timing) hipEventRecord(c->ev[0], s);
+        hipError_t e = qds::fused_step<T>(a, s, 0);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (c->timing) hipEventRecord(c->ev[1], s);
+        if (p0.arem) {
+            e = qds::fused_step<T>(a, s, 1);
+            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            if (c->timing) hipEventRecord(c->ev[2], s);
+        }
+        if (c->timing) {
+            float ms = 0.f;
+            hipEventSynchronize(p0.arem ? c->ev[2] : c->ev[1]);
+            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+            c->t_ms[0] += ms; c->t_n[0] += 1;
+            if (p0.arem) {
+                hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+                c->t_ms[1] += ms; c->t_n[1] += 1;
+            }
+        }
+        st->cur = ib;
+        if (a.window) st->window += 1;
+        st->step += 1;
+    }
+    return QDS_OK;
+}
+
 template <typename T>
 qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
                      hipStream_t s) {
@@ -83,6 +157,7 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
             scr[k] = reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) + size_t(k) * c->plane_elems * c->elem_bytes);
     }
     for (int k = 0; k < 3; ++k) p.ja[k] = scr[k];
+    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
         int a = st->cur, b = 1 - st->cur;
@@ -90,8 +165,16 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
         plane_table<T>(c, st->buf[b], p.B);
         p.n = st->step;
         p.w = st->window;
+        if (c->timing) hipEventRecord(c->ev[0], s);
         hipError_t e = qds::staged_step<T>(p, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (c->timing) {
+            float ms = 0.f;
+            hipEventRecord(c->ev[1], s);
+            hipEventSynchronize(c->ev[1]);
+            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+            c->t_ms[0] += ms; c->t_n[0] += 1;
+        }
         if (window) {
             // the new state (in b) moves one cell left into a
             e = qds::window_shift<T>(reinterpret_cast<const qds::cx<T>*>(st->buf[b]),
@@ -158,6 +241,8 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     if (g.content & QDS_HAS_AXION)
         for (int k = QDS_P_PHI; k <= QDS_P_TAM; ++k) c->slot[k] = n++;
     c->nplanes = n;
+    c->path = QDS_PATH_AUTO;
+    c->rows = 16;
     if (g.content & QDS_HAS_AREM) {
         hipError_t e = hipMalloc(&c->scratch, 3 * c->plane_elems * c->elem_bytes);
         if (e != hipSuccess) {
@@ -229,8 +314,49 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
     return run_steps<float>(h, fields, J, axion, n_steps, hipStream_t(stream));
 }
 
+qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
+    if (!h) return fail(nullptr, QDS_EINVAL, "null handle%s");
+    switch (key) {
+        case QDS_OPT_PATH:
+            if (value < QDS_PATH_AUTO || value > QDS_PATH_FUSED) return fail(h, QDS_EINVAL, "bad path%s");
+            if (value == QDS_PATH_FUSED && h->M > 4) return fail(h, QDS_EUNSUPPORTED, "fused path needs <= 4 modes%s");
+            h->path = int(value);
+            return QDS_OK;
+        case QDS_OPT_ROWS:
+            if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");
+            h->rows = int(value);
+            return QDS_OK;
+        case QDS_OPT_TIMING:
+            if (value && !h->timing) {
+                for (int k = 0; k < 3; ++k)
+                    if (hipEventCreate(&h->ev[k]) != hipSuccess) return fail(h, QDS_EHIP, "hipEventCreate failed%s");
+            }
+            if (!value && h->timing)
+                for (int k = 0; k < 3; ++k) hipEventDestroy(h->ev[k]);
+            h->timing = value ? 1 : 0;
+            h->t_ms[0] = h->t_ms[1] = 0.0;
+            h->t_n[0] = h->t_n[1] = 0;
+            return QDS_OK;
+        default:
+            return fail(h, QDS_EINVAL, "unknown option%s");
+    }
+}
+
+qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches) {
+    if (!h || !ms || !launches) return fail(h, QDS_EINVAL, "null argument%s");
+    for (int k = 0; k < 2; ++k) {
+        ms[k] = h->t_ms[k];
+        launches[k] = h->t_n[k];
+    }
+    return QDS_OK;
+}
+
+int32_t qds_uses_fused(qds_handle h) { return h && use_fused(h) ? 1 : 0; }
+
 qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
+    if (h->timing)
+        for (int k = 0; k < 3; ++k) hipEventDestroy(h->ev[k]);
     if (h->scratch) hipFree(h->scratch);
     delete h;
     return QDS_OK;

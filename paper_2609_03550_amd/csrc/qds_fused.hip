@@ -1,0 +1,826 @@
+// Fused single-pass QDS step for gfx950.
+//
+// Layout of the work: a workgroup is NW = number of modes wavefronts; wave w
+// advances mode m = w of one strip of 64 half-x cells (lanes; 62 owned, one
+// halo lane on each side) over one chunk of radial rows.  Each lane marches
+// the rows in increasing r keeping a sliding window of rows in registers, so
+// every state plane is read once and written once per step; the neighbouring
+// cells' new transport values come from lane shuffles.  The azimuthal mode
+// convolutions (axion source and axion current) exchange their per-mode
+// factors through LDS between the waves of the workgroup.
+//
+// Kernel A advances the background set, the axion and produces the axion
+// current at the source points; kernel B advances the regenerated set with it.
+// Both compute exactly the quantities of the staged kernels (qds_stages.hip).
+#include "qds_kernels.hpp"
+
+namespace qds {
+namespace fused {
+
+constexpr int WAVE = 64;
+constexpr int OWN = 62;   // owned cells per wave (halo lane at each end)
+
+template <typename T>
+struct XAcc {
+    // column helpers for one lane: H cell i, integer columns i and i+1
+    int nr1, ld;     // rows per mode and row pitch of a plane
+    int i;
+    int i1;          // column of x_{i+1} (wrapped if periodic, -1 outside)
+    int ir;          // destination column of right movers (i+1), -1 outside
+    __device__ __forceinline__ size_t at(int m, int row, int c) const {
+        return (size_t(m) * size_t(nr1) + size_t(row)) * size_t(ld) + size_t(c);
+    }
+    __device__ __forceinline__ cx<T> L(const cx<T>* p, int m, int row) const { return ld_(p + at(m, row, i)); }
+    __device__ __forceinline__ cx<T> R(const cx<T>* p, int m, int row) const {
+        return i1 >= 0 ? ld_(p + at(m, row, i1)) : zero<T>();
+    }
+    static __device__ __forceinline__ cx<T> ld_(const cx<T>* p) { return qds::ld(p); }
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_up1(cx<T> v) {
+    return cx<T>{__shfl_up(v.re, 1, WAVE), __shfl_up(v.im, 1, WAVE)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_dn1(cx<T> v) {
+    return cx<T>{__shfl_down(v.re, 1, WAVE), __shfl_down(v.im, 1, WAVE)};
+}
+
+// prescribed j_x^(0) at (x_{i+1/2}, r_j, t^n), lab column i + w
+__device__ __forceinline__ double drive_jx_f(const Drive& d, const Geo& g, int i, int j, int64_t n, int64_t w) {
+    const double x = (double(i) + 0.5 + double(w)) * g.h;
+    const double t = double(n) * g.h;
+    const double r = double(j) * g.dr;
+    const double ax = x - d.x0 - d.v * t;
+    const double ar = r - d.r0;
+    const double gx = exp(-ax * ax / (2.0 * d.sx * d.sx));
+    const double gr = exp(-ar * ar / (2.0 * d.sr * d.sr));
+    const uint64_t c = (uint64_t(n) << 32) | (uint64_t(int64_t(i) + w) << 12) | uint64_t(j);
+    return d.amp * gr * gx * (1.0 + d.noise * normal_ctr(d.seed, c));
+}
+
+// Output addressing: with the moving window every write lands one column to
+// the left and the last column is zero-filled by the owner of the last cell.
+struct Out {
+    int shift;
+    int nx;
+    __device__ __forceinline__ int col(int c) const { return c - shift; }
+};
+
+// ---------------------------------------------------------------------------
+// the electromagnetic part of a set, marched in r
+// ---------------------------------------------------------------------------
+template <typename T>
+struct EmWin {
+    // T_r^+- at K rows j (slot 0) and j+1 (slot 1), columns i (a) and i+1 (b)
+    cx<T> rpa[2], rpb[2], rma[2], rmb[2];
+    // T_theta^+- at J rows j (slot 0) and j+1 (slot 1)
+    cx<T> tpa[2], tpb[2], tma[2], tmb[2];
+    cx<T> ex0[2];      // E_x^{n-1/2} at J = j, j+1
+    cx<T> ex1[3];      // E_x^{n+1/2} at J = j-1, j, j+1
+    cx<T> bx0[2];      // B_x^{n-1/2} at K = j, j+1
+    cx<T> bx1[2];      // B_x^{n+1/2} at K = j-1, j
+    cx<T> bx1g;        // exterior ghost B_x^{n+1/2}
+    cx<T> jx_n1;       // total j_x at (x_{i+1/2}, r_{j+1}, t^n) (used for E_x(J=j+1))
+    cx<T> jx_nr;       // total j_x at row nr (for the ghost B_theta)
+    // new transverse values after the transport of this step (both columns)
+    cx<T> n_rpa, n_rpb, n_rma, n_rmb;   // T_r^{n+1} at K = j
+    cx<T> n_tpa, n_tpb, n_tma, n_tmb;   // T_theta^{n+1} at J = j
+};
+
+
+template <typename T>
+struct Ctx {
+    Geo g;
+    int m;           // mode of this wave
+    int lane;
+    int i;           // H cell
+    bool live;       // H cell inside the domain
+    bool owner;      // lane owns cell i
+    XAcc<T> x;
+    Out o;
+    T h, dr;
+    T wp2h;
+    int plasma;
+    Drive drive;
+    int64_t n, w;
+};
+
+// load the row j+1 of the window (T_r on K = j+1 or the ghost B_theta, T_theta
+// on J = j+1, E_x^{n-1/2} on J = j+1, B_x^{n-1/2} on K = j+1)
+template <typename T>
+__device__ __forceinline__ void em_load_next(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j) {
+    const int m = c.m;
+    const int k = j + 1;
+    if (k < c.g.nr) {
+        W.rpa[1] = c.x.L(s.trp, m, k); W.rpb[1] = c.x.R(s.trp, m, k);
+        W.rma[1] = c.x.L(s.trm, m, k); W.rmb[1] = c.x.R(s.trm, m, k);
+    } else if (k == c.g.nr) {
+        // exterior ghost row: B_theta stored in the T_r^+ plane; expressed as
+        // T_r^+ = B_theta, T_r^- = -B_theta so that (T+ - T-)/2 = B_theta
+        cx<T> a = c.x.L(s.trp, m, k), b = c.x.R(s.trp, m, k);
+        W.rpa[1] = a; W.rpb[1] = b; W.rma[1] = -a; W.rmb[1] = -b;
+    }
+    if (k <= c.g.nr) {
+        W.tpa[1] = c.x.L(s.ttp, m, k); W.tpb[1] = c.x.R(s.ttp, m, k);
+        W.tma[1] = c.x.L(s.ttm, m, k); W.tmb[1] = c.x.R(s.ttm, m, k);
+        W.ex0[1] = c.x.L(s.ex, m, k);
+        W.bx0[1] = c.x.L(s.bx, m, k);
+    }
+}
+
+// total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra + drive
+template <typename T>
+__device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write) {
+    cx<T> v = zero<T>();
+    if (!c.live) {
+        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0) st(s.ojx + c.g.at(c.m, row, c.o.col(c.i)), v);
+        return v;
+    }
+    if (c.plasma) {
+        cx<T> jn = c.x.L(s.jx, c.m, row) + c.wp2h * ex0;
+        if (write && c.owner && c.o.col(c.i) >= 0) st(s.ojx + c.g.at(c.m, row, c.o.col(c.i)), jn);
+        v = jn;
+    }
+    if (s.jxa) v = v + c.x.L(s.jxa, c.m, row);
+    if (c.drive.on && c.m == 0) v.re += T(drive_jx_f(c.drive, c.g, c.i, row, c.n, c.w));
+    return v;
+}
+
+// E_x^{n+1/2} at J = j+1 from the window (Eqs. Ex_update, Gammax_explicit, axis_Ex)
+template <typename T>
+__device__ __forceinline__ cx<T> em_ex_new(const Ctx<T>& c, const EmWin<T>& W, int jj, cx<T> jx) {
+    const T h = c.h, dr = c.dr;
+    const int m = c.m;
+    if (!c.live || (!c.g.open_r && jj == c.g.nr)) return zero<T>();
+    if (jj == 0) {
+        if (m != 0) return zero<T>();
+        cx<T> b = T(0.25) * ((W.rpa[1] - W.rma[1]) + (W.rpb[1] - W.rmb[1]));
+        return W.ex0[1] + h * ((T(4) / dr) * b - jx);
+    }
+    const T rj = T(jj) * dr;
+    cx<T> lo0 = T(0.5) * (W.rpa[0] - W.rma[0]), lo1 = T(0.5) * (W.rpb[0] - W.rmb[0]);
+    cx<T> hi0 = T(0.5) * (W.rpa[1] - W.rma[1]), hi1 = T(0.5) * (W.rpb[1] - W.rmb[1]);
+    cx<T> bavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
+    cx<T> db = (T(1) / (T(2) * dr)) * ((hi0 + hi1) - (lo0 + lo1));
+    cx<T> bravg = T(0.25) * ((W.tpa[1] - W.tma[1]) + (W.tpb[1] - W.tmb[1]));
+    cx<T> gx = (T(1) / rj) * bavg + db + imul(T(m) / rj, bravg) - jx;
+    return W.ex0[1] + h * gx;
+}
+
+// B_x^{n+1/2} at K = j (Eqs. Ex_update, Phix_explicit)
+template <typename T>
+__device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, int k) {
+    if (!c.live) return zero<T>();
+    const T h = c.h, dr = c.dr;
+    const T rk = (T(k) + T(0.5)) * dr;
+    cx<T> lo0 = T(0.5) * (W.tpa[0] + W.tma[0]), lo1 = T(0.5) * (W.tpb[0] + W.tmb[0]);
+    cx<T> hi0 = T(0.5) * (W.tpa[1] + W.tma[1]), hi1 = T(0.5) * (W.tpb[1] + W.tmb[1]);
+    cx<T> eavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
+    cx<T> de = (T(1) / (T(2) * dr)) * ((hi0 + hi1) - (lo0 + lo1));
+    cx<T> eravg = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
+    cx<T> fx = -((T(1) / rk) * eavg + de) - imul(T(c.m) / rk, eravg);
+    return W.bx0[0] + h * fx;
+}
+
+// plasma j_theta at (x_{i+1/2}, r_j, t^{n+1/2}) from the window slot s, writing
+// the new plasma j_theta at the integer column i
+template <typename T>
+__device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, int row, int slot,
+                                           bool write) {
+    cx<T> ja = c.x.L(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
+    cx<T> jb = c.x.R(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpb[slot] + W.tmb[slot]));
+    if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
+    if (write && c.owner && c.o.col(c.i) >= 0) st(s.ojt + c.g.at(c.m, row, c.o.col(c.i)), ja);
+    if (c.x.i1 < 0) jb = zero<T>();
+    return T(0.5) * (ja + jb);
+}
+
+// one march step of the electromagnetic set: outputs E_x(J=j+1), B_x(K=j)
+// (and the exterior ghost at j = nr-1), T_r(K=j), T_theta(J=j)
+template <typename T>
+__device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j, int r0, int r1) {
+    const Geo& g = c.g;
+    const int m = c.m;
+    const T h = c.h, dr = c.dr;
+    const int ocI = c.o.col(c.i);     // output column of integer column i
+    const bool wI = c.owner && ocI >= 0;
+    // ---- E_x^{n+1/2} at J = j+1
+    if (j + 1 <= g.nr) {
+        W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1);
+        W.ex1[2] = em_ex_new(c, W, j + 1, W.jx_n1);
+        if (j + 1 >= r0 && j + 1 < r1 && wI) st(s.oex + g.at(m, j + 1, ocI), W.ex1[2]);
+        if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
+    }
+    if (j < 0) return;
+    const bool own_row = j >= r0 && j < r1;
+    // ---- B_x^{n+1/2} at K = j
+    if (j < g.nr) {
+        W.bx1[1] = em_bx_new(c, W, j);
+        if (own_row && wI) st(s.obx + g.at(m, j, ocI), W.bx1[1]);
+    }
+    // ---- exterior ghost B_x^{n+1/2} at r_{nr+1/2} (Eq. em_r_open_bx)
+    if (j == g.nr - 1) {
+        cx<T> gh = zero<T>();
+        if (g.open_r && c.live) {
+            const int N = g.nr;
+            const T rN = T(N) * dr;
+            const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+            cx<T> br_a = T(0.5) * (W.tpa[1] - W.tma[1]), br_b = T(0.5) * (W.tpb[1] - W.tmb[1]);
+            cx<T> rx = (T(0.5) / h) * (br_b - br_a);
+            cx<T> ea = T(0.25) * ((W.tpa[1] + W.tma[1]) + (W.tpb[1] + W.tmb[1]));
+            cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
+            rx = rx - (T(1) / (T(2) * rN)) * (ea + imul(T(m), ra));
+            cx<T> jt = zero<T>();
+            if (c.plasma) jt = em_jt_avg(c, s, W, N, 1, false);
+            if (s.jta) jt = jt + c.x.L(s.jta, m, N);
+            rx = rx - T(0.5) * jt;
+            gh = W.bx0[0] + kap * (W.bx0[1] - W.bx1[1]) + cR * rx;
+        }
+        W.bx1g = gh;
+        if (r1 == g.nr + 1 && wI) st(s.obx + g.at(m, g.nr, ocI), gh);
+    }
+    // ---- T_r transport on K = j
+    if (j < g.nr) {
+        cx<T> sp = zero<T>(), sm = zero<T>();
+        cx<T> jra = zero<T>();
+        if (c.plasma) {
+            jra = c.x.L(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
+            if (own_row && wI) st(s.ojr + g.at(m, j, ocI), jra);
+        }
+        if (c.live) {
+            const T rk = (T(j) + T(0.5)) * dr;
+            cx<T> jr = zero<T>();
+            if (c.plasma) {
+                cx<T> jrb = c.x.R(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpb[0] + W.rmb[0]));
+                if (c.x.i1 < 0) jrb = zero<T>();
+                jr = T(0.5) * (jra + jrb);
+            }
+            if (s.jra) jr = jr + c.x.L(s.jra, m, j);
+            cx<T> gr = -imul(T(m) / rk, W.bx1[1]) - jr;
+            cx<T> pr = (T(1) / dr) * (W.ex1[2] - W.ex1[1]);
+            sp = h * (gr + pr);
+            sm = h * (gr - pr);
+        }
+        W.n_rpb = (c.x.i1 >= 0) ? W.rpa[0] + sp : zero<T>();       // T_r^+ at column i+1
+        W.n_rma = W.rmb[0] + sm;                                     // T_r^- at column i
+        cx<T> from_left = shfl_up1(W.n_rpb);
+        cx<T> from_right = shfl_dn1(W.n_rma);
+        W.n_rpa = (c.i == 0 && !g.per) ? zero<T>() : from_left;
+        W.n_rmb = (c.x.i1 >= 0) ? from_right : zero<T>();
+        if (own_row) {
+            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(s.otrp + g.at(m, j, c.o.col(c.x.ir)), W.n_rpb);
+            if (wI) st(s.otrm + g.at(m, j, ocI), W.n_rma);
+            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(s.otrp + g.at(m, j, c.o.col(0)), zero<T>());
+        }
+    }
+    // ---- T_theta transport on J = j (exterior ghost B_x used at j = nr)
+    {
+        const bool zrow = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
+        cx<T> jt = zero<T>();
+        if (c.plasma) jt = em_jt_avg(c, s, W, j, 0, own_row);
+        if (s.jta && c.live) jt = jt + c.x.L(s.jta, m, j);
+        cx<T> sp = zero<T>(), sm = zero<T>();
+        if (c.live && !zrow) {
+            cx<T> gt, pt;
+            if (j == 0) {
+                gt = -(T(2) / dr) * W.bx1[1] - jt;
+                pt = imul(T(1) / dr, W.ex1[2]);
+            } else {
+                const T rj = T(j) * dr;
+                cx<T> bhi = (j == g.nr) ? W.bx1g : W.bx1[1];
+                gt = -(T(1) / dr) * (bhi - W.bx1[0]) - jt;
+                pt = imul(T(m) / rj, W.ex1[1]);
+            }
+            sp = h * (gt + pt);
+            sm = h * (gt - pt);
+        }
+        if (zrow) {
+            W.n_tpa = zero<T>();
+            W.n_tmb = zero<T>();
+        } else {
+            W.n_tpa = W.tpb[0] + sp;                                      // T_theta^+ at column i
+            W.n_tmb = (c.x.i1 >= 0) ? W.tma[0] + sm : zero<T>();          // T_theta^- at column i+1
+        }
+        cx<T> from_right = shfl_dn1(W.n_tpa);
+        cx<T> from_left = shfl_up1(W.n_tmb);
+        W.n_tpb = (c.x.i1 >= 0) ? from_right : zero<T>();
+        W.n_tma = (c.i == 0 && !g.per) ? zero<T>() : from_left;
+        if (own_row) {
+            if (wI) st(s.ottp + g.at(m, j, ocI), W.n_tpa);
+            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(s.ottm + g.at(m, j, c.o.col(c.x.ir)), W.n_tmb);
+            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(s.ottm + g.at(m, j, c.o.col(0)), zero<T>());
+        }
+    }
+}
+
+// exterior ghost B_theta at r_{nr+1/2} (Eq. em_r_open_bt), at j = nr - 1 after em_step
+template <typename T>
+__device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, int r1) {
+    const Geo& g = c.g;
+    const int m = c.m, N = g.nr;
+    const T h = c.h, dr = c.dr;
+    cx<T> er_a = T(0.5) * (W.rpa[0] + W.rma[0]);
+    cx<T> er_b = T(0.5) * (W.rpb[0] + W.rmb[0]);
+    cx<T> er_l = shfl_up1(er_a);                        // E_r at column i-1
+    cx<T> jx_l = shfl_up1(W.jx_nr);                     // j_x at (x_{i-1/2}, r_nr)
+    if (c.i == 0 && !g.per) er_l = jx_l = zero<T>();
+    cx<T> out = zero<T>();
+    if (g.open_r) {
+        const T rN = T(N) * dr;
+        const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+        cx<T> I0 = T(0.5) * (W.rpa[0] - W.rma[0]);
+        cx<T> I1 = T(0.5) * (W.n_rpa - W.n_rma);
+        cx<T> G0 = T(0.5) * (W.rpa[1] - W.rma[1]);          // stored ghost (see em_load_next)
+        cx<T> br = T(0.5) * (W.tpa[1] - W.tma[1]);          // B_r at (x_i, r_nr)
+        cx<T> dxer = (T(1) / (T(2) * h)) * (er_b - er_l);
+        cx<T> jxi = T(0.5) * (W.jx_nr + jx_l);
+        cx<T> rt = -T(0.5) * dxer - (T(1) / (T(2) * rN)) * (T(0.5) * (I0 + G0) + imul(T(m), br)) + T(0.5) * jxi;
+        out = I0 + kap * (G0 - I1) + cR * rt;
+    }
+    const int oc = c.o.col(c.i);
+    if (c.owner && oc >= 0 && r1 == g.nr + 1) {
+        st(s.otrp + g.at(m, N, oc), out);
+        st(s.otrm + g.at(m, N, oc), zero<T>());
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void em_rotate(EmWin<T>& W) {
+    W.rpa[0] = W.rpa[1]; W.rpb[0] = W.rpb[1]; W.rma[0] = W.rma[1]; W.rmb[0] = W.rmb[1];
+    W.tpa[0] = W.tpa[1]; W.tpb[0] = W.tpb[1]; W.tma[0] = W.tma[1]; W.tmb[0] = W.tmb[1];
+    W.ex0[0] = W.ex0[1];
+    W.ex1[0] = W.ex1[1]; W.ex1[1] = W.ex1[2];
+    W.bx0[0] = W.bx0[1];
+    W.bx1[0] = W.bx1[1];
+}
+
+// ---------------------------------------------------------------------------
+// axion window
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AxWin {
+    cx<T> phi[3];         // phi^n at K = j-1, j, j+1
+    cx<T> phi1[2];        // phi^{n+1} at K = j-1, j
+    cx<T> ta_o[2][2];     // [K j-1, j][col a/b] d_t phi at t^{n-1/2}
+    cx<T> tapa[2], tama[2], tapb[2], tamb[2];   // T_a^{n+1/2} at K = j-1, j, columns a/b
+    cx<T> bxn[2];         // B_x at t^n (mean of n -+ 1/2) at K = j-1, j
+    cx<T> er0[2][2];      // E_r^n at K = j-1, j, columns a/b
+    cx<T> erh[2][2];      // E_r^{n+1/2}
+    cx<T> bth[2][2];      // B_theta^{n+1/2}
+    cx<T> brh[2][2];      // B_r^{n+1/2} at J = j-1, j
+    cx<T> eth[2][2];      // E_theta^{n+1/2} at J = j-1, j
+    cx<T> ax_brh, ax_eth; // J = 0 values (m = 1 axis reflection), columns a/b averaged later
+    cx<T> ax_brh_b, ax_eth_b;
+};
+
+template <typename T>
+__device__ __forceinline__ T par(int m) { return m == 0 ? T(1) : T(-1); }
+
+// LDS exchange slots per lane: 6 source factors, 18 current factors
+constexpr int NS = 6;
+constexpr int NJ = 18;
+
+template <typename T, int M>
+__device__ __forceinline__ void conv_one(const cx<T>* A, const cx<T>* B, int m, cx<T>& out, T sign) {
+    // C_m{A, B} for the single output mode m (see conv_acc)
+    if (m == 0) {
+        cx<T> s = A[0] * B[0];
+        T re = T(0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) re += A[k].re * B[k].re + A[k].im * B[k].im;
+        s.re += T(0.5) * re;
+        out = out + sign * s;
+        return;
+    }
+    cx<T> acc = zero<T>();
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        if (k <= m) acc = acc + A[k] * B[m - k];
+        if (k + m < M) acc = acc + mulc(A[k + m], B[k]) + cmul(A[k], B[k + m]);
+    }
+    out = out + (sign * T(0.5)) * acc;
+}
+
+// ---------------------------------------------------------------------------
+// kernel A: background set + axion + axion current
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
+    const Geo g = a.g;
+    const int wave = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int strip = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int r0 = chunk * a.rows;
+    const int r1 = min(g.nr + 1, r0 + a.rows);
+    const int ncell = g.nx;                       // H cells 0..nx-1 (the last is dead unless periodic)
+    Ctx<T> c;
+    c.g = g;
+    c.m = wave;
+    c.lane = lane;
+    const int raw = strip * OWN - 1 + lane;
+    const bool inrange = raw >= 0 && raw < ncell;
+    // halo lanes wrap with periodic x; otherwise they are clamped (their
+    // results only reach owned lanes through terms the x boundary zeroes)
+    c.i = g.per ? ((raw % ncell) + ncell) % ncell : (raw < 0 ? 0 : (raw >= ncell ? ncell - 1 : raw));
+    c.owner = inrange && lane >= 1 && lane <= OWN;
+    c.live = g.per || c.i < g.nx - 1;
+    c.x.nr1 = g.nr + 1;
+    c.x.ld = g.ld;
+    c.x.i = c.i;
+    c.x.i1 = (c.i + 1 < g.nx) ? c.i + 1 : (g.per ? 0 : -1);
+    c.x.ir = c.x.i1;
+    c.o.shift = a.window;
+    c.o.nx = g.nx;
+    c.h = T(g.h);
+    c.dr = T(g.dr);
+    c.wp2h = T(a.wp2 * g.h);
+    c.plasma = a.plasma;
+    c.drive = a.drive;
+    c.n = a.n;
+    c.w = a.w;
+
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* sm = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* smS = sm;                                 // [NS][M][WAVE]
+    cx<T>* smJ = sm + NS * M * WAVE;                 // [NJ][M][WAVE]
+    auto put = [&](cx<T>* base, int f, cx<T> v) { base[(f * M + wave) * WAVE + lane] = v; };
+    auto get = [&](const cx<T>* base, int f, int k) { return base[(f * M + k) * WAVE + lane]; };
+
+    const SetP<T>& s = a.s0;
+    EmWin<T> W;
+    AxWin<T> X;
+    const int m = wave;
+    const T h = c.h, dr = c.dr;
+    const T kap = (dr - h) / (dr + h);
+    const int ocI = c.o.col(c.i);
+    const bool wI = c.owner && ocI >= 0;
+    const int jstart = max(r0 - 2, -1);
+    // prime slot 1 with row jstart (so that the first em_load_next fills j+1)
+    for (int q = 0; q < 2; ++q) {
+        W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
+        W.tpa[q] = W.tpb[q] = W.tma[q] = W.tmb[q] = zero<T>();
+        W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
+        X.phi1[q] = X.bxn[q] = zero<T>();
+        X.tapa[q] = X.tama[q] = X.tapb[q] = X.tamb[q] = zero<T>();
+        for (int e = 0; e < 2; ++e) X.ta_o[q][e] = X.er0[q][e] = X.erh[q][e] = X.bth[q][e] = X.brh[q][e] = X.eth[q][e] = zero<T>();
+    }
+    W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
+    W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
+    X.phi[0] = X.phi[1] = X.phi[2] = zero<T>();
+    X.ax_brh = X.ax_eth = X.ax_brh_b = X.ax_eth_b = zero<T>();
+    if (jstart >= 0) {
+        em_load_next(c, s, W, jstart - 1);           // row jstart into slot 1
+        X.phi[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
+        if (jstart - 1 >= 0) X.phi[1] = c.x.L(a.phi, m, jstart - 1);
+    }
+
+    const int jend = min(r1, g.nr);
+    for (int j = jstart; j <= jend; ++j) {
+        // ---------------- shift the window and load row j+1
+        em_rotate(W);
+        X.phi[0] = X.phi[1]; X.phi[1] = X.phi[2];
+        if (j + 1 < g.nr) X.phi[2] = c.x.L(a.phi, m, j + 1);
+        else if (j + 1 == g.nr) X.phi[2] = g.open_r ? c.x.L(a.phi, m, g.nr) : zero<T>();
+        else X.phi[2] = zero<T>();
+        em_load_next(c, s, W, j);
+        if (j >= 0) {
+            // B_x at K = j-1 and E_x at J = j (old values) enter the sources below
+        }
+        const cx<T> ex1_j = W.ex1[1];
+        em_step(c, s, W, j, r0, r1);
+        if (j < 0) continue;
+        const bool own_row = j >= r0 && j < r1;
+        if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
+
+        // ---------------- axion source S_a at K = j (Eqs. source_mode_zero/_m)
+        cx<T> Sa = zero<T>();
+        cx<T> ga = zero<T>();
+        if (j < g.nr) {
+            cx<T> bx_n = T(0.5) * (W.bx0[0] + W.bx1[1]);
+            cx<T> exn0 = T(0.5) * (W.ex0[0] + ex1_j);
+            cx<T> exn1 = T(0.5) * (W.ex0[1] + W.ex1[2]);
+            cx<T> fEx = T(0.5) * (exn0 + exn1);
+            cx<T> fBx = bx_n;
+            cx<T> fEr = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
+            cx<T> fBt = T(0.25) * ((W.rpa[0] - W.rma[0]) + (W.rpb[0] - W.rmb[0]));
+            cx<T> fEt = T(0.125) * ((W.tpa[0] + W.tma[0]) + (W.tpa[1] + W.tma[1]) + (W.tpb[0] + W.tmb[0]) +
+                                    (W.tpb[1] + W.tmb[1]));
+            cx<T> fBr = T(0.125) * ((W.tpa[0] - W.tma[0]) + (W.tpa[1] - W.tma[1]) + (W.tpb[0] - W.tmb[0]) +
+                                    (W.tpb[1] - W.tmb[1]));
+            if (m == 0) fBx = fBx + a.bx0;
+            if (m == 1) { fBr = fBr + a.br1; fBt = fBt + a.bt1; }
+            put(smS, 0, fEx); put(smS, 1, fBx); put(smS, 2, fEr); put(smS, 3, fBr); put(smS, 4, fEt); put(smS, 5, fBt);
+            X.bxn[1] = bx_n;
+        }
+        __syncthreads();
+        if (j < g.nr) {
+            cx<T> A[M], B[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = get(smS, 0, k); B[k] = get(smS, 1, k); }
+            conv_one<T, M>(A, B, m, Sa, T(1));
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = get(smS, 2, k); B[k] = get(smS, 3, k); }
+            conv_one<T, M>(A, B, m, Sa, T(1));
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = get(smS, 4, k); B[k] = get(smS, 5, k); }
+            conv_one<T, M>(A, B, m, Sa, T(1));
+            if (!c.live) Sa = zero<T>();
+            // ---------------- Gamma_a, T_a transport, phi (Eqs. Ta_plus/minus_update, phi_update)
+            const T rk = (T(j) + T(0.5)) * dr;
+            cx<T> p = X.phi[1];
+            cx<T> up = X.phi[2];
+            cx<T> dn = (j > 0) ? X.phi[0] : zero<T>();
+            if (c.live)
+                ga = (T(1) / (dr * dr)) * (up - T(2) * p + dn) + (T(1) / (T(2) * dr * rk)) * (up - dn)
+                     - (T(m * m) / (rk * rk) + T(a.ma2)) * p + T(a.s_phi) * Sa;
+            cx<T> tap_a = c.x.L(a.tap, m, j), tap_b = c.x.R(a.tap, m, j);
+            cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.R(a.tam, m, j);
+            X.ta_o[1][0] = T(0.5) * (tap_a + tam_a);
+            X.ta_o[1][1] = T(0.5) * (tap_b + tam_b);
+            cx<T> nap_b = (c.x.i1 >= 0) ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
+            cx<T> nam_a = tam_b + h * ga;                                  // T_a^- at column i
+            cx<T> l = shfl_up1(nap_b), r = shfl_dn1(nam_a);
+            cx<T> nap_a = (c.i == 0 && !g.per) ? zero<T>() : l;
+            cx<T> nam_b = (c.x.i1 >= 0) ? r : zero<T>();
+            X.tapa[1] = nap_a; X.tapb[1] = nap_b; X.tama[1] = nam_a; X.tamb[1] = nam_b;
+            cx<T> p1 = zero<T>();
+            if (c.live) p1 = p + (h / T(4)) * (nap_a + nap_b + nam_a + nam_b);
+            X.phi1[1] = p1;
+            if (own_row) {
+                if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(a.otap + g.at(m, j, c.o.col(c.x.ir)), nap_b);
+                if (wI) {
+                    st(a.otam + g.at(m, j, ocI), nam_a);
+                    st(a.ophi + g.at(m, j, ocI), p1);
+                }
+                if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(a.otap + g.at(m, j, c.o.col(0)), zero<T>());
+            }
+            if (j == g.nr - 1 && wI && r1 == g.nr + 1) {
+                // exterior ghost phi at r_{nr+1/2}: outgoing-wave condition, two-level centring
+                cx<T> G = X.phi[2];
+                cx<T> Gn = G;
+                if (g.open_r) Gn = c.live ? (p + kap * (G - p1)) : zero<T>();
+                st(a.ophi + g.at(m, g.nr, ocI), Gn);
+            }
+            // time-centred transverse fields at K = j (columns a, b)
+            X.er0[1][0] = T(0.5) * (W.rpa[0] + W.rma[0]);
+            X.er0[1][1] = T(0.5) * (W.rpb[0] + W.rmb[0]);
+            X.erh[1][0] = T(0.5) * (X.er0[1][0] + T(0.5) * (W.n_rpa + W.n_rma));
+            X.erh[1][1] = T(0.5) * (X.er0[1][1] + T(0.5) * (W.n_rpb + W.n_rmb));
+            X.bth[1][0] = T(0.5) * (T(0.5) * (W.rpa[0] - W.rma[0]) + T(0.5) * (W.n_rpa - W.n_rma));
+            X.bth[1][1] = T(0.5) * (T(0.5) * (W.rpb[0] - W.rmb[0]) + T(0.5) * (W.n_rpb - W.n_rmb));
+        }
+        // time-centred transverse fields at J = j
+        X.brh[1][0] = T(0.5) * (T(0.5) * (W.tpa[0] - W.tma[0]) + T(0.5) * (W.n_tpa - W.n_tma));
+        X.brh[1][1] = T(0.5) * (T(0.5) * (W.tpb[0] - W.tmb[0]) + T(0.5) * (W.n_tpb - W.n_tmb));
+        X.eth[1][0] = T(0.5) * (T(0.5) * (W.tpa[0] + W.tma[0]) + T(0.5) * (W.n_tpa + W.n_tma));
+        X.eth[1][1] = T(0.5) * (T(0.5) * (W.tpb[0] + W.tmb[0]) + T(0.5) * (W.n_tpb + W.n_tmb));
+        if (j == 0) {
+            X.ax_brh = X.brh[1][0]; X.ax_brh_b = X.brh[1][1];
+            X.ax_eth = X.eth[1][0]; X.ax_eth_b = X.eth[1][1];
+        }
+
+        // ---------------- axion current factors (Eqs. jax_mode, jar_mode, jat_mode)
+        const bool ax = (j == 0);
+        const T pr = par<T>(m);
+        if (j < g.nr) {
+            // j_a,x at (x_{i+1/2}, r_j, t^n)
+            const T rj = T(j) * dr;
+            cx<T> dtn_a = T(0.5) * (X.ta_o[1][0] + T(0.5) * (X.tapa[1] + X.tama[1]));
+            cx<T> dtn_b = T(0.5) * (X.ta_o[1][1] + T(0.5) * (X.tapb[1] + X.tamb[1]));
+            cx<T> dtl_a = ax ? pr * dtn_a : T(0.5) * (X.ta_o[0][0] + T(0.5) * (X.tapa[0] + X.tama[0]));
+            cx<T> dtl_b = ax ? pr * dtn_b : T(0.5) * (X.ta_o[0][1] + T(0.5) * (X.tapb[0] + X.tamb[0]));
+            cx<T> bl = ax ? pr * X.bxn[1] : X.bxn[0];
+            cx<T> A1 = T(0.5) * (bl + X.bxn[1]);
+            if (m == 0) A1 = A1 + a.bx0;
+            cx<T> A2 = T(0.5) * (T(0.5) * (dtl_a + dtn_a) + T(0.5) * (dtl_b + dtn_b));
+            cx<T> ga_ = X.er0[1][0], gb_ = X.er0[1][1];
+            cx<T> la, lb;
+            if (ax) {
+                if (m == 1) {
+                    la = imul(T(2), T(0.5) * (W.tpa[0] + W.tma[0])) - ga_;
+                    lb = imul(T(2), T(0.5) * (W.tpb[0] + W.tmb[0])) - gb_;
+                } else {
+                    la = -ga_; lb = -gb_;
+                }
+            } else {
+                la = X.er0[0][0]; lb = X.er0[0][1];
+            }
+            cx<T> B1 = T(0.5) * (T(0.5) * (la + ga_) + T(0.5) * (lb + gb_));
+            cx<T> phl = ax ? pr * X.phi[1] : X.phi[0];
+            cx<T> B2;
+            if (ax) B2 = (m == 1) ? imul(-T(2) / dr, X.phi[1]) : zero<T>();
+            else B2 = imul(-T(m) / rj, T(0.5) * (phl + X.phi[1]));
+            cx<T> C1 = T(0.25) * ((W.tpa[0] + W.tma[0]) + (W.tpb[0] + W.tmb[0]));
+            cx<T> C2 = (T(1) / dr) * (X.phi[1] - phl);
+            put(smJ, 0, A1); put(smJ, 1, A2); put(smJ, 2, B1); put(smJ, 3, B2); put(smJ, 4, C1); put(smJ, 5, C2);
+            // j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2})
+            cx<T> b0 = X.bth[1][0], b1 = X.bth[1][1];
+            cx<T> e0 = X.erh[1][0], e1 = X.erh[1][1];
+            cx<T> gb0, gb1, ge0, ge1;
+            if (ax) {
+                if (m == 1) {
+                    gb0 = imul(-T(2), X.ax_brh) - b0;
+                    gb1 = imul(-T(2), X.ax_brh_b) - b1;
+                    ge0 = imul(T(2), X.ax_eth) - e0;
+                    ge1 = imul(T(2), X.ax_eth_b) - e1;
+                } else {
+                    gb0 = -b0; gb1 = -b1; ge0 = -e0; ge1 = -e1;
+                }
+            } else {
+                gb0 = X.bth[0][0]; gb1 = X.bth[0][1]; ge0 = X.erh[0][0]; ge1 = X.erh[0][1];
+            }
+            cx<T> tA1 = T(0.5) * (T(0.5) * (gb0 + b0) + T(0.5) * (gb1 + b1));
+            if (m == 1) tA1 = tA1 + a.bt1;
+            cx<T> tC1 = T(0.5) * (T(0.5) * (ge0 + e0) + T(0.5) * (ge1 + e1));
+            cx<T> t0 = T(0.5) * (X.tapa[1] + X.tama[1]), t1 = T(0.5) * (X.tapb[1] + X.tamb[1]);
+            cx<T> x0 = T(0.5) * (X.tama[1] - X.tapa[1]), x1 = T(0.5) * (X.tamb[1] - X.tapb[1]);
+            cx<T> tl0 = ax ? pr * t0 : T(0.5) * (X.tapa[0] + X.tama[0]);
+            cx<T> tl1 = ax ? pr * t1 : T(0.5) * (X.tapb[0] + X.tamb[0]);
+            cx<T> xl0 = ax ? pr * x0 : T(0.5) * (X.tama[0] - X.tapa[0]);
+            cx<T> xl1 = ax ? pr * x1 : T(0.5) * (X.tamb[0] - X.tapb[0]);
+            cx<T> tA2 = T(0.5) * (T(0.5) * (tl0 + t0) + T(0.5) * (tl1 + t1));
+            cx<T> tC2 = T(0.5) * (T(0.5) * (xl0 + x0) + T(0.5) * (xl1 + x1));
+            cx<T> phh = T(0.5) * (X.phi[1] + X.phi1[1]);
+            cx<T> phl2 = ax ? pr * phh : T(0.5) * (X.phi[0] + X.phi1[0]);
+            cx<T> tB2 = (T(1) / dr) * (phh - phl2);
+            put(smJ, 6, tA1); put(smJ, 7, tA2); put(smJ, 8, ex1_j); put(smJ, 9, tB2); put(smJ, 10, tC1); put(smJ, 11, tC2);
+        }
+        if (j >= 1) {
+            // j_a,r at (x_{i+1/2}, r_{j-1/2}, t^{n+1/2})
+            const int k = j - 1;
+            const T rk = (T(k) + T(0.5)) * dr;
+            cx<T> rA1 = T(0.25) * (X.brh[0][0] + X.brh[0][1] + X.brh[1][0] + X.brh[1][1]);
+            if (m == 1) rA1 = rA1 + a.br1;
+            cx<T> rA2 = T(0.25) * ((X.tapa[0] + X.tama[0]) + (X.tapb[0] + X.tamb[0]));
+            cx<T> rB1 = T(0.25) * (X.eth[0][0] + X.eth[0][1] + X.eth[1][0] + X.eth[1][1]);
+            cx<T> rB2 = T(0.25) * ((X.tama[0] - X.tapa[0]) + (X.tamb[0] - X.tapb[0]));
+            cx<T> rC1 = T(0.5) * (W.ex1[0] + ex1_j);
+            cx<T> rC2 = imul(-T(m) / rk, T(0.5) * (X.phi[0] + X.phi1[0]));
+            put(smJ, 12, rA1); put(smJ, 13, rA2); put(smJ, 14, rB1); put(smJ, 15, rB2); put(smJ, 16, rC1); put(smJ, 17, rC2);
+        }
+        __syncthreads();
+        const T sj = T(a.s_j);
+        if (j < g.nr) {
+            cx<T> A[M], B[M];
+            cx<T> jx = zero<T>(), jt = zero<T>();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 2 * q, k); B[k] = get(smJ, 2 * q + 1, k); }
+                conv_one<T, M>(A, B, m, jx, q == 1 ? T(-1) : T(1));
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 6 + 2 * q, k); B[k] = get(smJ, 7 + 2 * q, k); }
+                conv_one<T, M>(A, B, m, jt, q == 1 ? T(-1) : T(1));
+            }
+            if (!c.live) jx = jt = zero<T>();
+            if (own_row && c.owner) {
+                st(a.jax + g.at(m, j, c.i), sj * jx);
+                st(a.jat + g.at(m, j, c.i), sj * jt);
+            }
+        } else if (j == g.nr && own_row && c.owner) {
+            st(a.jax + g.at(m, j, c.i), zero<T>());
+            st(a.jat + g.at(m, j, c.i), zero<T>());
+        }
+        if (j >= 1 && j - 1 < g.nr && j - 1 >= r0 && j - 1 < r1 && c.owner) {
+            cx<T> A[M], B[M];
+            cx<T> jr = zero<T>();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 12 + 2 * q, k); B[k] = get(smJ, 13 + 2 * q, k); }
+                conv_one<T, M>(A, B, m, jr, q == 1 ? T(-1) : T(1));
+            }
+            if (!c.live) jr = zero<T>();
+            st(a.jar + g.at(m, j - 1, c.i), sj * jr);
+        }
+        // ---------------- rotate the axion window
+        X.phi1[0] = X.phi1[1];
+        X.bxn[0] = X.bxn[1];
+        X.tapa[0] = X.tapa[1]; X.tama[0] = X.tama[1]; X.tapb[0] = X.tapb[1]; X.tamb[0] = X.tamb[1];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            X.ta_o[0][e] = X.ta_o[1][e];
+            X.er0[0][e] = X.er0[1][e];
+            X.erh[0][e] = X.erh[1][e];
+            X.bth[0][e] = X.bth[1][e];
+            X.brh[0][e] = X.brh[1][e];
+            X.eth[0][e] = X.eth[1][e];
+        }
+    }
+    // moving window: the owner of the last cell zero-fills the last column
+    if (a.window && c.owner && c.i == g.nx - 1) {
+        for (int row = r0; row < r1; ++row) {
+            const size_t e = g.at(m, row, g.nx - 1);
+            st(s.otrp + e, zero<T>()); st(s.otrm + e, zero<T>()); st(s.ottp + e, zero<T>()); st(s.ottm + e, zero<T>());
+            st(s.oex + e, zero<T>()); st(s.obx + e, zero<T>());
+            if (c.plasma) { st(s.ojx + e, zero<T>()); st(s.ojr + e, zero<T>()); st(s.ojt + e, zero<T>()); }
+            st(a.ophi + e, zero<T>()); st(a.otap + e, zero<T>()); st(a.otam + e, zero<T>());
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel B (and the electromagnetic-only step): one set, marched in r
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
+    const Geo g = a.g;
+    const int lane = threadIdx.x;
+    const int strip = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int m = blockIdx.z;
+    const int r0 = chunk * a.rows;
+    const int r1 = min(g.nr + 1, r0 + a.rows);
+    Ctx<T> c;
+    c.g = g;
+    c.m = m;
+    c.lane = lane;
+    const int raw = strip * OWN - 1 + lane;
+    const bool inrange = raw >= 0 && raw < g.nx;
+    c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
+    c.owner = inrange && lane >= 1 && lane <= OWN;
+    c.live = g.per || c.i < g.nx - 1;
+    c.x.nr1 = g.nr + 1;
+    c.x.ld = g.ld;
+    c.x.i = c.i;
+    c.x.i1 = (c.i + 1 < g.nx) ? c.i + 1 : (g.per ? 0 : -1);
+    c.x.ir = c.x.i1;
+    c.o.shift = a.window;
+    c.o.nx = g.nx;
+    c.h = T(g.h);
+    c.dr = T(g.dr);
+    c.wp2h = T(a.wp2 * g.h);
+    c.plasma = a.plasma;
+    c.drive = a.drive;
+    if (which) c.drive.on = 0;
+    c.n = a.n;
+    c.w = a.w;
+    const SetP<T>& s = which ? a.s1 : a.s0;
+    EmWin<T> W;
+    for (int q = 0; q < 2; ++q) {
+        W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
+        W.tpa[q] = W.tpb[q] = W.tma[q] = W.tmb[q] = zero<T>();
+        W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
+    }
+    W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
+    W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
+    const int jstart = max(r0 - 2, -1);
+    if (jstart >= 0) em_load_next(c, s, W, jstart - 1);
+    const int jend = min(r1, g.nr);
+    for (int j = jstart; j <= jend; ++j) {
+        em_rotate(W);
+        em_load_next(c, s, W, j);
+        em_step(c, s, W, j, r0, r1);
+        if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
+    }
+    if (a.window && c.owner && c.i == g.nx - 1) {
+        for (int row = r0; row < r1; ++row) {
+            const size_t e = g.at(m, row, g.nx - 1);
+            st(s.otrp + e, zero<T>()); st(s.otrm + e, zero<T>()); st(s.ottp + e, zero<T>()); st(s.ottm + e, zero<T>());
+            st(s.oex + e, zero<T>()); st(s.obx + e, zero<T>());
+            if (c.plasma) { st(s.ojx + e, zero<T>()); st(s.ojr + e, zero<T>()); st(s.ojt + e, zero<T>()); }
+        }
+    }
+}
+
+}  // namespace fused
+
+template <typename T, int M>
+static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
+    const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
+    const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
+    const size_t lds = size_t(fused::NS + fused::NJ) * M * fused::WAVE * sizeof(cx<T>);
+    hipLaunchKernelGGL((fused::k_fused_a<T, M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
+    const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
+    const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
+    if (stage == 0) {
+        if (!a.axion) {
+            hipLaunchKernelGGL(fused::k_fused_em<T>, dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a, 0);
+            return hipGetLastError();
+        }
+        switch (a.g.M) {
+            case 1: return launch_a<T, 1>(a, s);
+            case 2: return launch_a<T, 2>(a, s);
+            case 3: return launch_a<T, 3>(a, s);
+            case 4: return launch_a<T, 4>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    hipLaunchKernelGGL(fused::k_fused_em<T>, dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a, 1);
+    return hipGetLastError();
+}
+
+template hipError_t fused_step<double>(const FusedArgs<double>&, hipStream_t, int);
+template hipError_t fused_step<float>(const FusedArgs<float>&, hipStream_t, int);
+
+}  // namespace qds

@@ -113,7 +113,35 @@ struct StepPlan {
     }
 };
 
+// One electromagnetic set for the fused kernels: old planes, new planes and
+// the extra currents at the source points (regenerated set only).
+template <typename T>
+struct SetP {
+    const cx<T>* trp; const cx<T>* trm; const cx<T>* ttp; const cx<T>* ttm;
+    const cx<T>* ex; const cx<T>* bx; const cx<T>* jx; const cx<T>* jr; const cx<T>* jt;
+    cx<T>* otrp; cx<T>* otrm; cx<T>* ottp; cx<T>* ottm;
+    cx<T>* oex; cx<T>* obx; cx<T>* ojx; cx<T>* ojr; cx<T>* ojt;
+    const cx<T>* jxa; const cx<T>* jra; const cx<T>* jta;
+};
+
+template <typename T>
+struct FusedArgs {
+    Geo g;
+    SetP<T> s0, s1;
+    const cx<T>* phi; const cx<T>* tap; const cx<T>* tam;
+    cx<T>* ophi; cx<T>* otap; cx<T>* otam;
+    cx<T>* jax; cx<T>* jar; cx<T>* jat;   // axion current scratch
+    int plasma, axion;
+    double wp2, ma2, s_phi, s_j;
+    cx<T> bx0, br1, bt1;
+    Drive drive;
+    int64_t n, w;
+    int window;       // 1: moving window (outputs one column to the left)
+    int rows;         // radial rows per workgroup chunk
+};
+
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
+template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
 template <typename T> hipError_t window_shift(const cx<T>* src, cx<T>* dst, const Geo& g, int nplanes, hipStream_t s);
 template <typename T>
 hipError_t add_pulse(SetPtr<T> s0, const Geo& g, int pol, const double* fK, const double* fJ, const double* fG,

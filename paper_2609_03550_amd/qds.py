@@ -28,8 +28,8 @@ J_NONE, J_RING = 0, 1
 P_TRP, P_TRM, P_TTP, P_TTM, P_EX, P_BX, P_JX, P_JR, P_JT = range(9)
 P_SET1, P_PHI, P_TAP, P_TAM = 9, 18, 19, 20
 
-EXPORTS = ("qds_init", "qds_state_bytes", "qds_row_pitch", "qds_plane_offset", "qds_add_pulse",
-           "qds_step", "qds_destroy", "qds_last_error", "qds_version")
+OPT_PATH, OPT_ROWS, OPT_TIMING = 1, 2, 3
+PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 
 
 class Grid(ctypes.Structure):
@@ -78,6 +78,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_last_error.restype = ctypes.c_char_p
     lib.qds_version.argtypes = []
     lib.qds_version.restype = ctypes.c_char_p
+    lib.qds_set_option.argtypes = [vp, i32, i64]
+    lib.qds_set_option.restype = i32
+    lib.qds_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.qds_get_timing.restype = i32
+    lib.qds_uses_fused.argtypes = [vp]
+    lib.qds_uses_fused.restype = i32
     return lib
 
 
@@ -110,7 +116,8 @@ class Solver:
     """One QDS field advance on one GPU: a libqds handle plus its two state
     buffers (torch uint8 tensors on the device)."""
 
-    def __init__(self, wl: I.Workload, dtype: str = "f64", device: str = "cuda:0"):
+    def __init__(self, wl: I.Workload, dtype: str = "f64", device: str = "cuda:0", path: int = PATH_AUTO,
+                 rows: Optional[int] = None):
         self.wl = wl
         self.device = torch.device(device)
         self.dtype = dtype
@@ -136,6 +143,24 @@ class Solver:
         self.state.window = 0
         self.cur = self._current()
         self.ax = self._axion()
+        self.set_option(OPT_PATH, path)
+        if rows is not None:
+            self.set_option(OPT_ROWS, rows)
+
+    def set_option(self, key: int, value: int) -> None:
+        _check(lib().qds_set_option(self.h, key, int(value)), self.h)
+
+    @property
+    def fused(self) -> bool:
+        return bool(lib().qds_uses_fused(self.h))
+
+    def timing(self):
+        """(ms per kernel, launches per kernel) accumulated since timing was enabled;
+        index 0 = background-set kernel, 1 = regenerated-set kernel."""
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int64 * 2)()
+        _check(lib().qds_get_timing(self.h, ms, n), self.h)
+        return [ms[0], ms[1]], [n[0], n[1]]
 
     # -- parameters ---------------------------------------------------------
     def _current(self) -> Current:

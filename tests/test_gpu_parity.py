@@ -15,15 +15,15 @@ H, DR = I.H, I.DR
 TOL = {"f64": (1e-12, 1e-13), "f32": (1e-5, 1e-6)}
 
 
-def _solver(wl, dtype):
+def _solver(wl, dtype, path=0, rows=None):
     from paper_2609_03550_amd import qds
-    s = qds.Solver(wl, dtype=dtype)
+    s = qds.Solver(wl, dtype=dtype, path=path, rows=rows)
     s.load_pulses()
     return s
 
 
-def _check(wl, nsteps, dtype, chunks=1):
-    s = _solver(wl, dtype)
+def _check(wl, nsteps, dtype, chunks=1, path=0, rows=None):
+    s = _solver(wl, dtype, path, rows)
     for _ in range(chunks):
         s.step(nsteps // chunks)
     torch.cuda.synchronize()
@@ -89,3 +89,50 @@ def test_full_physics_external_field_and_scales():
 
 def test_full_physics_longer_run():
     _check(_full(160, 24, 3), 120, "f64", chunks=3)
+
+
+# ---- both paths: the staged kernels and the fused single-pass kernels
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("rows", [1, 3, 7, 16, 64])
+def test_fused_and_staged_chunk_seams(path, rows):
+    """Every radial chunk size (seams between workgroups at every row) gives
+    the oracle's result; path 1 = staged kernels, 2 = fused kernels."""
+    if path == 1 and rows != 16:
+        pytest.skip("the chunk size only affects the fused kernels")
+    s = _check(_full(131, 15, 3), 12, "f64", path=path, rows=rows)
+    assert s.fused == (path == 2)
+
+
+@pytest.mark.parametrize("M", [1, 2, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_modes(M, dtype):
+    s = _check(_full(70, 9, M), 10, dtype, path=2, rows=4)
+    assert s.fused
+
+
+@pytest.mark.parametrize("x_bc,r_bc", [("periodic", "pec"), ("periodic", "open"), ("open", "pec"), ("window", "open")])
+def test_fused_boundaries(x_bc, r_bc):
+    _check(_full(128, 12, 3, x_bc=x_bc, r_bc=r_bc), 12, "f64", path=2, rows=5)
+
+
+@pytest.mark.parametrize("rows", [2, 9])
+def test_fused_em_only_window_drive(rows):
+    wl = I.driven_window(nx=200, nr=20, steps=0)
+    d = wl.drive
+    wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed),
+                  pulses=(wl.pulses[0].__class__("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 140 * H),))
+    _check(wl, 30, "f64", path=2, rows=rows)
+
+
+def test_fused_matches_staged_on_a_long_run():
+    """The two paths agree with each other to rounding after many steps."""
+    from paper_2609_03550_amd import qds
+    wl = _full(250, 30, 3, bext=(0.1 + 0j, 0.2 + 0.1j, -0.1 + 0.2j))
+    a = _solver(wl, "f64", path=1)
+    b = _solver(wl, "f64", path=2, rows=8)
+    a.step(300)
+    b.step(300)
+    torch.cuda.synchronize()
+    P.compare_states(b.fields(), a.fields(), 1e-11, 1e-12)
