@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the QDS + Klein-Gordon field advance on one MI355X.
+
+One step = one full pass of the hot path (background set with cold-plasma
+response, Klein-Gordon axion with its source, axion current, regenerated set)
+over the 8192 x 256 x 3-mode two-colour axion workload, FP64 complex, inputs
+resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--workload axion|window|vacuum]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-mode updates/s + % HBM peak (QDS+KG); fwd+adjoint vs fwd time"
+HBM_PEAK_GBPS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_kernel_a_axion_8192x256x3_f64.json")
+
+
+def plane_accesses(wl, kernel):
+    """Complex planes read + written per cell-mode by one launch of each fused
+    kernel (their algorithmic bytes):
+      kernel 0 (A): reads and writes the background set (T_r^+-, T_theta^+-,
+        E_x, B_x and, with plasma, j_x, j_r, j_theta) and the axion (phi, T_a^+-);
+      kernel 1 (B): reads and writes the regenerated set, reads the axion current;
+      kernel 2 (axion current): reads T^n and T^{n+1} of the background set
+        (4 + 4), B_x at t^{n-1/2} and t^{n+1/2}, E_x at t^{n+1/2}, T_a at
+        t^{n-1/2} and t^{n+1/2} (2 + 2), phi^n and phi^{n+1}; writes 3.
+    Electromagnetic-only: kernel 0 reads and writes the 6 (or 9) planes."""
+    em = 6 + (3 if wl.wp2 else 0)
+    if not wl.axion:
+        return 2 * em if kernel == 0 else 0
+    if kernel == 0:
+        return 2 * (em + 3)
+    if kernel == 1:
+        return (2 * em + 3) if wl.arem else 0
+    return 20 if wl.arem else 0
+
+
+KERNEL_NAMES = {0: "kernel A (background set + axion)", 1: "kernel B (regenerated set)",
+                2: "axion-current kernel"}
+
+
+def workload(name):
+    from paper_2609_03550_amd import inputs as I
+    if name == "axion":
+        return I.axion_two_colour(8192, 256, 6000, 3)
+    if name == "window":
+        return I.driven_window(4096, 256, 4000)
+    if name == "vacuum":
+        return I.vacuum_em()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("qds_fused.hip", "qds_kernels.hpp", "qds_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(wl, dtype, launches_cells):
+    """HBM bytes per launch of kernel A from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    with open(PROFILE_TRAFFIC) as f:
+        d = json.load(f)
+    if d.get("source_digest") != source_digest() or d.get("workload") != wl.name or d.get("dtype") != dtype:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, seconds_target=15.0):
+    """The FP64 oracle on this host: whole-grid steps of the same workload
+    until about ``seconds_target`` of CPU work, extrapolated per update."""
+    import torch
+    from oracle import qds as Q
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    st = Q.step(st, g, ph)                  # first step outside the timing
+    n, t0 = 0, time.perf_counter()
+    while True:
+        st = Q.step(st, g, ph)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or n >= 20:
+            break
+    return {"value": wl.cell_modes * n / el, "unit": "cell-mode updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} whole-grid steps of {wl.name} (FP64 oracle, after 1 untimed step), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--workload", default="axion", choices=["axion", "window", "vacuum"])
+    ap.add_argument("--path", type=int, default=0, help="0 auto (fused), 1 staged, 2 fused")
+    ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for the HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (every box has one MI355X); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_03550_amd import qds
+
+    wl = workload(args.workload)
+    dev = torch.device("cuda:0")
+    s = qds.Solver(wl, dtype=args.dtype, device="cuda:0", path=args.path, rows=args.rows)
+    s.load_pulses()
+    stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    s.set_option(qds.OPT_TIMING, 1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kms, kn = s.timing()
+    s.set_option(qds.OPT_TIMING, 0)
+
+    ms_per_step = total_ms / args.steps
+    cells = wl.cell_modes
+    value = cells * args.steps / (total_ms / 1e3)
+    eb = 16 if args.dtype == "f64" else 8
+    # dominant kernel: the one with the largest summed time
+    k = max(range(3), key=lambda q: kms[q])
+    kname = KERNEL_NAMES[k] if wl.axion else "electromagnetic set"
+    if not s.fused:
+        kname = "staged step (all stage kernels)"
+    avg_ms = kms[k] / max(kn[k], 1)
+    alg_bytes = plane_accesses(wl, k) * eb * cells
+    if not s.fused:
+        alg_bytes = sum(plane_accesses(wl, q) for q in range(3)) * eb * cells
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    traffic = measured_traffic(wl, args.dtype, cells) if (s.fused and k == 0) else None
+    # whole-step effective bandwidth against the one-read-one-write byte model
+    nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
+    step_bytes = 2 * nplanes * eb * cells
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-mode updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nx": wl.nx, "nr": wl.nr, "modes": wl.nmodes,
+                   "physics": "QDS Maxwell + Klein-Gordon axion + regenerated fields + cold plasma"
+                   if wl.arem else ("QDS Maxwell + prescribed current, moving window" if wl.drive else "QDS Maxwell"),
+                   "path": "fused" if s.fused else "staged", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
+        "step_effective_hbm_frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBPS,
+        "kernel_ms": {"kernel_a": kms[0] / max(kn[0], 1), "kernel_b": kms[1] / max(kn[1], 1) if kn[1] else None,
+                      "axion_current": kms[2] / max(kn[2], 1) if kn[2] else None},
+        "kernel_gbps": {KERNEL_NAMES[q]: plane_accesses(wl, q) * eb * cells / (kms[q] / kn[q] / 1e3) / 1e9
+                        for q in range(3) if kn[q] and s.fused},
+        "fwd_adj_over_fwd": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,19 +140,23 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
                     int64_t n_steps, void* stream);
 
 /* Options (synchronous, host only):
- *  QDS_OPT_PATH   QDS_PATH_AUTO (fused single-pass kernels when modes <= 4),
+ *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 4, except the
+ *                 moving window combined with the regenerated set),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of the fused kernels (1..4096)
- *  QDS_OPT_TIMING 1: qds_step brackets each kernel with HIP events on the
- *                 caller's stream and synchronises on them (for measurement);
- *                 resets the accumulated times */
+ *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
+ *                 events recorded on the caller's stream (no synchronisation;
+ *                 the library keeps one pair per launch until reset); any
+ *                 value resets the recorded launches */
 enum { QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
 qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
 
-/* Accumulated kernel time (ms) and launch counts since timing was enabled:
- * index 0 = the background-set kernel (kernel A; the whole step on the staged
- * path), index 1 = the regenerated-set kernel (kernel B).  ms[2], launches[2]. */
+/* Summed kernel time (ms) and launch counts of the launches recorded since
+ * timing was last set: index 0 = the background-set + axion kernel (kernel A;
+ * the whole step on the staged path), index 1 = the regenerated-set kernel
+ * (kernel B), index 2 = the axion-current kernel.  ms[3], launches[3].
+ * Waits for the recorded events. */
 qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches);
 
 /* 1 if qds_step runs the fused kernels for this handle. */

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/qds.h"
 #include "qds_kernels.hpp"
@@ -22,15 +23,32 @@ struct qds_ctx {
     int path;                // QDS_PATH_*
     int rows;                // radial rows per workgroup of the fused kernels
     int timing;              // record per-kernel HIP events in qds_step
-    hipEvent_t ev[3];
-    double t_ms[2];          // accumulated kernel time: [0] kernel A / set 0, [1] kernel B
-    int64_t t_n[2];
+    // timing events, recorded without synchronising and resolved by
+    // qds_get_timing: pairs (start, end) per launch, tagged with the kernel
+    std::vector<hipEvent_t> pool;
+    size_t used;
+    std::vector<int> tag;
     char err[256];
 };
 
 namespace {
 
 thread_local char g_err[256] = "";
+
+// Event pair for the next timed launch (created on demand, reused after a reset).
+hipEvent_t* timing_pair(qds_ctx* c, int kernel) {
+    if (c->used + 2 > c->pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            c->pool.push_back(e);
+        }
+    }
+    hipEvent_t* p = &c->pool[c->used];
+    c->used += 2;
+    c->tag.push_back(kernel);
+    return p;
+}
 
 qds_status fail(qds_ctx* c, qds_status s, const char* fmt, const char* detail = "") {
     char* buf = c ? c->err : g_err;
@@ -62,9 +80,18 @@ qds::Geo geo(const qds_ctx* c) {
     return g;
 }
 
+// The fused kernels cover up to 4 modes.  With the moving window and the
+// regenerated set, the axion current needs the background set's new state at
+// lab positions while kernel A already writes it shifted, so that combination
+// runs the staged kernels (which shift after the whole step).
+bool fused_ok(const qds_ctx* c) {
+    const bool window_arem = c->g.x_bc == QDS_X_WINDOW && (c->g.content & QDS_HAS_AREM);
+    return c->M <= 4 && !window_arem;
+}
+
 bool use_fused(const qds_ctx* c) {
     if (c->path == QDS_PATH_STAGED) return false;
-    return c->M <= 4;
+    return fused_ok(c);
 }
 
 template <typename T>
@@ -104,24 +131,26 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
         a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
         a.n = st->step;
         a.w = st->window;
-        if (c->timing) hipEventRecord(c->ev[0], s);
+        hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
+        if (ev) hipEventRecord(ev[0], s);
         hipError_t e = qds::fused_step<T>(a, s, 0);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (c->timing) hipEventRecord(c->ev[1], s);
+        if (ev) hipEventRecord(ev[1], s);
         if (p0.arem) {
+            // axion current at the source points of the regenerated set
+            qds::StepPlan<T> pl = p0;
+            for (int q = 0; q < QDS_NPLANES; ++q) { pl.A[q] = A[q]; pl.B[q] = B[q]; }
+            qds::AxionArgs<T> ax = pl.axion_args();
+            ev = c->timing ? timing_pair(c, 2) : nullptr;
+            if (ev) hipEventRecord(ev[0], s);
+            e = qds::axion_current_w<T>(ax, s);
+            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            if (ev) hipEventRecord(ev[1], s);
+            ev = c->timing ? timing_pair(c, 1) : nullptr;
+            if (ev) hipEventRecord(ev[0], s);
             e = qds::fused_step<T>(a, s, 1);
             if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (c->timing) hipEventRecord(c->ev[2], s);
-        }
-        if (c->timing) {
-            float ms = 0.f;
-            hipEventSynchronize(p0.arem ? c->ev[2] : c->ev[1]);
-            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
-            c->t_ms[0] += ms; c->t_n[0] += 1;
-            if (p0.arem) {
-                hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
-                c->t_ms[1] += ms; c->t_n[1] += 1;
-            }
+            if (ev) hipEventRecord(ev[1], s);
         }
         st->cur = ib;
         if (a.window) st->window += 1;
@@ -165,16 +194,11 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
         plane_table<T>(c, st->buf[b], p.B);
         p.n = st->step;
         p.w = st->window;
-        if (c->timing) hipEventRecord(c->ev[0], s);
+        hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
+        if (ev) hipEventRecord(ev[0], s);
         hipError_t e = qds::staged_step<T>(p, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (c->timing) {
-            float ms = 0.f;
-            hipEventRecord(c->ev[1], s);
-            hipEventSynchronize(c->ev[1]);
-            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
-            c->t_ms[0] += ms; c->t_n[0] += 1;
-        }
+        if (ev) hipEventRecord(ev[1], s);
         if (window) {
             // the new state (in b) moves one cell left into a
             e = qds::window_shift<T>(reinterpret_cast<const qds::cx<T>*>(st->buf[b]),
@@ -219,9 +243,8 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     const double mu_bound = (8.0 + 4.0 * mmax * mmax) / (g.dr * g.dr);
     if (dt * dt * mu_bound > 4.0) return fail(nullptr, QDS_ECFL, "radial stability bound dt^2 mu_max <= 4 fails%s");
 
-    qds_ctx* c = new (std::nothrow) qds_ctx;
+    qds_ctx* c = new (std::nothrow) qds_ctx();
     if (!c) return fail(nullptr, QDS_ENOMEM, "out of host memory%s");
-    memset(c, 0, sizeof(*c));
     c->g = g;
     c->M = modes;
     c->h = dx;
@@ -319,7 +342,8 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
     switch (key) {
         case QDS_OPT_PATH:
             if (value < QDS_PATH_AUTO || value > QDS_PATH_FUSED) return fail(h, QDS_EINVAL, "bad path%s");
-            if (value == QDS_PATH_FUSED && h->M > 4) return fail(h, QDS_EUNSUPPORTED, "fused path needs <= 4 modes%s");
+            if (value == QDS_PATH_FUSED && !fused_ok(h))
+                return fail(h, QDS_EUNSUPPORTED, "fused path needs <= 4 modes and no moving window with the regenerated set%s");
             h->path = int(value);
             return QDS_OK;
         case QDS_OPT_ROWS:
@@ -327,15 +351,9 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
             h->rows = int(value);
             return QDS_OK;
         case QDS_OPT_TIMING:
-            if (value && !h->timing) {
-                for (int k = 0; k < 3; ++k)
-                    if (hipEventCreate(&h->ev[k]) != hipSuccess) return fail(h, QDS_EHIP, "hipEventCreate failed%s");
-            }
-            if (!value && h->timing)
-                for (int k = 0; k < 3; ++k) hipEventDestroy(h->ev[k]);
             h->timing = value ? 1 : 0;
-            h->t_ms[0] = h->t_ms[1] = 0.0;
-            h->t_n[0] = h->t_n[1] = 0;
+            h->used = 0;
+            h->tag.clear();
             return QDS_OK;
         default:
             return fail(h, QDS_EINVAL, "unknown option%s");
@@ -344,9 +362,15 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
 
 qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches) {
     if (!h || !ms || !launches) return fail(h, QDS_EINVAL, "null argument%s");
-    for (int k = 0; k < 2; ++k) {
-        ms[k] = h->t_ms[k];
-        launches[k] = h->t_n[k];
+    ms[0] = ms[1] = ms[2] = 0.0;
+    launches[0] = launches[1] = launches[2] = 0;
+    for (size_t q = 0; q < h->tag.size(); ++q) {
+        float t = 0.f;
+        if (hipEventSynchronize(h->pool[2 * q + 1]) != hipSuccess ||
+            hipEventElapsedTime(&t, h->pool[2 * q], h->pool[2 * q + 1]) != hipSuccess)
+            return fail(h, QDS_EHIP, "reading the timing events failed%s");
+        ms[h->tag[q]] += t;
+        launches[h->tag[q]] += 1;
     }
     return QDS_OK;
 }
@@ -355,8 +379,7 @@ int32_t qds_uses_fused(qds_handle h) { return h && use_fused(h) ? 1 : 0; }
 
 qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
-    if (h->timing)
-        for (int k = 0; k < 3; ++k) hipEventDestroy(h->ev[k]);
+    for (hipEvent_t e : h->pool) hipEventDestroy(e);
     if (h->scratch) hipFree(h->scratch);
     delete h;
     return QDS_OK;

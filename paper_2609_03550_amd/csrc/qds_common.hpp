@@ -79,6 +79,33 @@ __device__ __forceinline__ void conv_acc(const cx<T>* A, const cx<T>* B, T sign,
     }
 }
 
+template <typename T, int M>
+__device__ __forceinline__ void conv_one(const cx<T>* A, const cx<T>* B, int m, cx<T>& out, T sign) {
+    // C_m{A, B} for the single output mode m (see conv_acc).  m is a run-time
+    // value (the mode of the calling wave): every array index below is a
+    // compile-time constant so that A and B stay in registers.
+    cx<T> acc = zero<T>();
+    if (m == 0) {
+        acc = A[0] * B[0];
+        T re = T(0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) re += A[k].re * B[k].re + A[k].im * B[k].im;
+        acc.re += T(0.5) * re;
+        out = out + sign * acc;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            if (k + l == m) acc = acc + A[k] * B[l];
+            if (k - l == m) acc = acc + mulc(A[k], B[l]);
+            if (l - k == m) acc = acc + cmul(A[k], B[l]);
+        }
+    }
+    out = out + (sign * T(0.5)) * acc;
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): output k >= 1 of the stream seeded
 // with ``seed`` is mix(seed + k * 0x9E3779B97F4A7C15).  Box-Muller normal from
 // outputs 2c+1, 2c+2 of counter c = (step << 32) | (lab column << 12) | row.

@@ -9,9 +9,11 @@
 // convolutions (axion source and axion current) exchange their per-mode
 // factors through LDS between the waves of the workgroup.
 //
-// Kernel A advances the background set, the axion and produces the axion
-// current at the source points; kernel B advances the regenerated set with it.
-// Both compute exactly the quantities of the staged kernels (qds_stages.hip).
+// Kernel A advances the background set and the axion (source, Klein-Gordon
+// transport, phi); the axion current at the source points is formed by the
+// tile kernel k_axion_current_w (qds_stages.hip); kernel B advances the
+// regenerated set with it.  They compute exactly the quantities of the staged
+// kernels.
 #include "qds_kernels.hpp"
 
 namespace qds {
@@ -355,58 +357,17 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
     W.bx1[0] = W.bx1[1];
 }
 
-// ---------------------------------------------------------------------------
-// axion window
-// ---------------------------------------------------------------------------
-template <typename T>
-struct AxWin {
-    cx<T> phi[3];         // phi^n at K = j-1, j, j+1
-    cx<T> phi1[2];        // phi^{n+1} at K = j-1, j
-    cx<T> ta_o[2][2];     // [K j-1, j][col a/b] d_t phi at t^{n-1/2}
-    cx<T> tapa[2], tama[2], tapb[2], tamb[2];   // T_a^{n+1/2} at K = j-1, j, columns a/b
-    cx<T> bxn[2];         // B_x at t^n (mean of n -+ 1/2) at K = j-1, j
-    cx<T> er0[2][2];      // E_r^n at K = j-1, j, columns a/b
-    cx<T> erh[2][2];      // E_r^{n+1/2}
-    cx<T> bth[2][2];      // B_theta^{n+1/2}
-    cx<T> brh[2][2];      // B_r^{n+1/2} at J = j-1, j
-    cx<T> eth[2][2];      // E_theta^{n+1/2} at J = j-1, j
-    cx<T> ax_brh, ax_eth; // J = 0 values (m = 1 axis reflection), columns a/b averaged later
-    cx<T> ax_brh_b, ax_eth_b;
-};
-
 template <typename T>
 __device__ __forceinline__ T par(int m) { return m == 0 ? T(1) : T(-1); }
 
-// LDS exchange slots per lane: 6 source factors, 18 current factors
+// LDS exchange slots per lane: the 6 factors of the axion source
 constexpr int NS = 6;
-constexpr int NJ = 18;
-
-template <typename T, int M>
-__device__ __forceinline__ void conv_one(const cx<T>* A, const cx<T>* B, int m, cx<T>& out, T sign) {
-    // C_m{A, B} for the single output mode m (see conv_acc)
-    if (m == 0) {
-        cx<T> s = A[0] * B[0];
-        T re = T(0);
-#pragma unroll
-        for (int k = 1; k < M; ++k) re += A[k].re * B[k].re + A[k].im * B[k].im;
-        s.re += T(0.5) * re;
-        out = out + sign * s;
-        return;
-    }
-    cx<T> acc = zero<T>();
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        if (k <= m) acc = acc + A[k] * B[m - k];
-        if (k + m < M) acc = acc + mulc(A[k + m], B[k]) + cmul(A[k], B[k + m]);
-    }
-    out = out + (sign * T(0.5)) * acc;
-}
 
 // ---------------------------------------------------------------------------
-// kernel A: background set + axion + axion current
+// kernel A: background set + axion
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-__global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
+__device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a) {
     const Geo g = a.g;
     const int wave = threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
@@ -442,15 +403,13 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
     c.w = a.w;
 
     extern __shared__ unsigned char smem_raw[];
-    cx<T>* sm = reinterpret_cast<cx<T>*>(smem_raw);
-    cx<T>* smS = sm;                                 // [NS][M][WAVE]
-    cx<T>* smJ = sm + NS * M * WAVE;                 // [NJ][M][WAVE]
+    cx<T>* smS = reinterpret_cast<cx<T>*>(smem_raw);  // [NS][M][WAVE]
     auto put = [&](cx<T>* base, int f, cx<T> v) { base[(f * M + wave) * WAVE + lane] = v; };
     auto get = [&](const cx<T>* base, int f, int k) { return base[(f * M + k) * WAVE + lane]; };
 
     const SetP<T>& s = a.s0;
     EmWin<T> W;
-    AxWin<T> X;
+    cx<T> phw[3];     // phi^n at K = j-1, j, j+1
     const int m = wave;
     const T h = c.h, dr = c.dr;
     const T kap = (dr - h) / (dr + h);
@@ -462,32 +421,25 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
         W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
         W.tpa[q] = W.tpb[q] = W.tma[q] = W.tmb[q] = zero<T>();
         W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
-        X.phi1[q] = X.bxn[q] = zero<T>();
-        X.tapa[q] = X.tama[q] = X.tapb[q] = X.tamb[q] = zero<T>();
-        for (int e = 0; e < 2; ++e) X.ta_o[q][e] = X.er0[q][e] = X.erh[q][e] = X.bth[q][e] = X.brh[q][e] = X.eth[q][e] = zero<T>();
     }
     W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
     W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
-    X.phi[0] = X.phi[1] = X.phi[2] = zero<T>();
-    X.ax_brh = X.ax_eth = X.ax_brh_b = X.ax_eth_b = zero<T>();
+    phw[0] = phw[1] = phw[2] = zero<T>();
     if (jstart >= 0) {
         em_load_next(c, s, W, jstart - 1);           // row jstart into slot 1
-        X.phi[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
-        if (jstart - 1 >= 0) X.phi[1] = c.x.L(a.phi, m, jstart - 1);
+        phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
+        if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
     }
 
     const int jend = min(r1, g.nr);
     for (int j = jstart; j <= jend; ++j) {
         // ---------------- shift the window and load row j+1
         em_rotate(W);
-        X.phi[0] = X.phi[1]; X.phi[1] = X.phi[2];
-        if (j + 1 < g.nr) X.phi[2] = c.x.L(a.phi, m, j + 1);
-        else if (j + 1 == g.nr) X.phi[2] = g.open_r ? c.x.L(a.phi, m, g.nr) : zero<T>();
-        else X.phi[2] = zero<T>();
+        phw[0] = phw[1]; phw[1] = phw[2];
+        if (j + 1 < g.nr) phw[2] = c.x.L(a.phi, m, j + 1);
+        else if (j + 1 == g.nr) phw[2] = g.open_r ? c.x.L(a.phi, m, g.nr) : zero<T>();
+        else phw[2] = zero<T>();
         em_load_next(c, s, W, j);
-        if (j >= 0) {
-            // B_x at K = j-1 and E_x at J = j (old values) enter the sources below
-        }
         const cx<T> ex1_j = W.ex1[1];
         em_step(c, s, W, j, r0, r1);
         if (j < 0) continue;
@@ -512,7 +464,6 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
             if (m == 0) fBx = fBx + a.bx0;
             if (m == 1) { fBr = fBr + a.br1; fBt = fBt + a.bt1; }
             put(smS, 0, fEx); put(smS, 1, fBx); put(smS, 2, fEr); put(smS, 3, fBr); put(smS, 4, fEt); put(smS, 5, fBt);
-            X.bxn[1] = bx_n;
         }
         __syncthreads();
         if (j < g.nr) {
@@ -529,25 +480,21 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
             if (!c.live) Sa = zero<T>();
             // ---------------- Gamma_a, T_a transport, phi (Eqs. Ta_plus/minus_update, phi_update)
             const T rk = (T(j) + T(0.5)) * dr;
-            cx<T> p = X.phi[1];
-            cx<T> up = X.phi[2];
-            cx<T> dn = (j > 0) ? X.phi[0] : zero<T>();
+            cx<T> p = phw[1];
+            cx<T> up = phw[2];
+            cx<T> dn = (j > 0) ? phw[0] : zero<T>();
             if (c.live)
                 ga = (T(1) / (dr * dr)) * (up - T(2) * p + dn) + (T(1) / (T(2) * dr * rk)) * (up - dn)
                      - (T(m * m) / (rk * rk) + T(a.ma2)) * p + T(a.s_phi) * Sa;
             cx<T> tap_a = c.x.L(a.tap, m, j), tap_b = c.x.R(a.tap, m, j);
             cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.R(a.tam, m, j);
-            X.ta_o[1][0] = T(0.5) * (tap_a + tam_a);
-            X.ta_o[1][1] = T(0.5) * (tap_b + tam_b);
             cx<T> nap_b = (c.x.i1 >= 0) ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
             cx<T> nam_a = tam_b + h * ga;                                  // T_a^- at column i
             cx<T> l = shfl_up1(nap_b), r = shfl_dn1(nam_a);
             cx<T> nap_a = (c.i == 0 && !g.per) ? zero<T>() : l;
             cx<T> nam_b = (c.x.i1 >= 0) ? r : zero<T>();
-            X.tapa[1] = nap_a; X.tapb[1] = nap_b; X.tama[1] = nam_a; X.tamb[1] = nam_b;
             cx<T> p1 = zero<T>();
             if (c.live) p1 = p + (h / T(4)) * (nap_a + nap_b + nam_a + nam_b);
-            X.phi1[1] = p1;
             if (own_row) {
                 if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(a.otap + g.at(m, j, c.o.col(c.x.ir)), nap_b);
                 if (wI) {
@@ -558,158 +505,11 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
             }
             if (j == g.nr - 1 && wI && r1 == g.nr + 1) {
                 // exterior ghost phi at r_{nr+1/2}: outgoing-wave condition, two-level centring
-                cx<T> G = X.phi[2];
+                cx<T> G = phw[2];
                 cx<T> Gn = G;
                 if (g.open_r) Gn = c.live ? (p + kap * (G - p1)) : zero<T>();
                 st(a.ophi + g.at(m, g.nr, ocI), Gn);
             }
-            // time-centred transverse fields at K = j (columns a, b)
-            X.er0[1][0] = T(0.5) * (W.rpa[0] + W.rma[0]);
-            X.er0[1][1] = T(0.5) * (W.rpb[0] + W.rmb[0]);
-            X.erh[1][0] = T(0.5) * (X.er0[1][0] + T(0.5) * (W.n_rpa + W.n_rma));
-            X.erh[1][1] = T(0.5) * (X.er0[1][1] + T(0.5) * (W.n_rpb + W.n_rmb));
-            X.bth[1][0] = T(0.5) * (T(0.5) * (W.rpa[0] - W.rma[0]) + T(0.5) * (W.n_rpa - W.n_rma));
-            X.bth[1][1] = T(0.5) * (T(0.5) * (W.rpb[0] - W.rmb[0]) + T(0.5) * (W.n_rpb - W.n_rmb));
-        }
-        // time-centred transverse fields at J = j
-        X.brh[1][0] = T(0.5) * (T(0.5) * (W.tpa[0] - W.tma[0]) + T(0.5) * (W.n_tpa - W.n_tma));
-        X.brh[1][1] = T(0.5) * (T(0.5) * (W.tpb[0] - W.tmb[0]) + T(0.5) * (W.n_tpb - W.n_tmb));
-        X.eth[1][0] = T(0.5) * (T(0.5) * (W.tpa[0] + W.tma[0]) + T(0.5) * (W.n_tpa + W.n_tma));
-        X.eth[1][1] = T(0.5) * (T(0.5) * (W.tpb[0] + W.tmb[0]) + T(0.5) * (W.n_tpb + W.n_tmb));
-        if (j == 0) {
-            X.ax_brh = X.brh[1][0]; X.ax_brh_b = X.brh[1][1];
-            X.ax_eth = X.eth[1][0]; X.ax_eth_b = X.eth[1][1];
-        }
-
-        // ---------------- axion current factors (Eqs. jax_mode, jar_mode, jat_mode)
-        const bool ax = (j == 0);
-        const T pr = par<T>(m);
-        if (j < g.nr) {
-            // j_a,x at (x_{i+1/2}, r_j, t^n)
-            const T rj = T(j) * dr;
-            cx<T> dtn_a = T(0.5) * (X.ta_o[1][0] + T(0.5) * (X.tapa[1] + X.tama[1]));
-            cx<T> dtn_b = T(0.5) * (X.ta_o[1][1] + T(0.5) * (X.tapb[1] + X.tamb[1]));
-            cx<T> dtl_a = ax ? pr * dtn_a : T(0.5) * (X.ta_o[0][0] + T(0.5) * (X.tapa[0] + X.tama[0]));
-            cx<T> dtl_b = ax ? pr * dtn_b : T(0.5) * (X.ta_o[0][1] + T(0.5) * (X.tapb[0] + X.tamb[0]));
-            cx<T> bl = ax ? pr * X.bxn[1] : X.bxn[0];
-            cx<T> A1 = T(0.5) * (bl + X.bxn[1]);
-            if (m == 0) A1 = A1 + a.bx0;
-            cx<T> A2 = T(0.5) * (T(0.5) * (dtl_a + dtn_a) + T(0.5) * (dtl_b + dtn_b));
-            cx<T> ga_ = X.er0[1][0], gb_ = X.er0[1][1];
-            cx<T> la, lb;
-            if (ax) {
-                if (m == 1) {
-                    la = imul(T(2), T(0.5) * (W.tpa[0] + W.tma[0])) - ga_;
-                    lb = imul(T(2), T(0.5) * (W.tpb[0] + W.tmb[0])) - gb_;
-                } else {
-                    la = -ga_; lb = -gb_;
-                }
-            } else {
-                la = X.er0[0][0]; lb = X.er0[0][1];
-            }
-            cx<T> B1 = T(0.5) * (T(0.5) * (la + ga_) + T(0.5) * (lb + gb_));
-            cx<T> phl = ax ? pr * X.phi[1] : X.phi[0];
-            cx<T> B2;
-            if (ax) B2 = (m == 1) ? imul(-T(2) / dr, X.phi[1]) : zero<T>();
-            else B2 = imul(-T(m) / rj, T(0.5) * (phl + X.phi[1]));
-            cx<T> C1 = T(0.25) * ((W.tpa[0] + W.tma[0]) + (W.tpb[0] + W.tmb[0]));
-            cx<T> C2 = (T(1) / dr) * (X.phi[1] - phl);
-            put(smJ, 0, A1); put(smJ, 1, A2); put(smJ, 2, B1); put(smJ, 3, B2); put(smJ, 4, C1); put(smJ, 5, C2);
-            // j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2})
-            cx<T> b0 = X.bth[1][0], b1 = X.bth[1][1];
-            cx<T> e0 = X.erh[1][0], e1 = X.erh[1][1];
-            cx<T> gb0, gb1, ge0, ge1;
-            if (ax) {
-                if (m == 1) {
-                    gb0 = imul(-T(2), X.ax_brh) - b0;
-                    gb1 = imul(-T(2), X.ax_brh_b) - b1;
-                    ge0 = imul(T(2), X.ax_eth) - e0;
-                    ge1 = imul(T(2), X.ax_eth_b) - e1;
-                } else {
-                    gb0 = -b0; gb1 = -b1; ge0 = -e0; ge1 = -e1;
-                }
-            } else {
-                gb0 = X.bth[0][0]; gb1 = X.bth[0][1]; ge0 = X.erh[0][0]; ge1 = X.erh[0][1];
-            }
-            cx<T> tA1 = T(0.5) * (T(0.5) * (gb0 + b0) + T(0.5) * (gb1 + b1));
-            if (m == 1) tA1 = tA1 + a.bt1;
-            cx<T> tC1 = T(0.5) * (T(0.5) * (ge0 + e0) + T(0.5) * (ge1 + e1));
-            cx<T> t0 = T(0.5) * (X.tapa[1] + X.tama[1]), t1 = T(0.5) * (X.tapb[1] + X.tamb[1]);
-            cx<T> x0 = T(0.5) * (X.tama[1] - X.tapa[1]), x1 = T(0.5) * (X.tamb[1] - X.tapb[1]);
-            cx<T> tl0 = ax ? pr * t0 : T(0.5) * (X.tapa[0] + X.tama[0]);
-            cx<T> tl1 = ax ? pr * t1 : T(0.5) * (X.tapb[0] + X.tamb[0]);
-            cx<T> xl0 = ax ? pr * x0 : T(0.5) * (X.tama[0] - X.tapa[0]);
-            cx<T> xl1 = ax ? pr * x1 : T(0.5) * (X.tamb[0] - X.tapb[0]);
-            cx<T> tA2 = T(0.5) * (T(0.5) * (tl0 + t0) + T(0.5) * (tl1 + t1));
-            cx<T> tC2 = T(0.5) * (T(0.5) * (xl0 + x0) + T(0.5) * (xl1 + x1));
-            cx<T> phh = T(0.5) * (X.phi[1] + X.phi1[1]);
-            cx<T> phl2 = ax ? pr * phh : T(0.5) * (X.phi[0] + X.phi1[0]);
-            cx<T> tB2 = (T(1) / dr) * (phh - phl2);
-            put(smJ, 6, tA1); put(smJ, 7, tA2); put(smJ, 8, ex1_j); put(smJ, 9, tB2); put(smJ, 10, tC1); put(smJ, 11, tC2);
-        }
-        if (j >= 1) {
-            // j_a,r at (x_{i+1/2}, r_{j-1/2}, t^{n+1/2})
-            const int k = j - 1;
-            const T rk = (T(k) + T(0.5)) * dr;
-            cx<T> rA1 = T(0.25) * (X.brh[0][0] + X.brh[0][1] + X.brh[1][0] + X.brh[1][1]);
-            if (m == 1) rA1 = rA1 + a.br1;
-            cx<T> rA2 = T(0.25) * ((X.tapa[0] + X.tama[0]) + (X.tapb[0] + X.tamb[0]));
-            cx<T> rB1 = T(0.25) * (X.eth[0][0] + X.eth[0][1] + X.eth[1][0] + X.eth[1][1]);
-            cx<T> rB2 = T(0.25) * ((X.tama[0] - X.tapa[0]) + (X.tamb[0] - X.tapb[0]));
-            cx<T> rC1 = T(0.5) * (W.ex1[0] + ex1_j);
-            cx<T> rC2 = imul(-T(m) / rk, T(0.5) * (X.phi[0] + X.phi1[0]));
-            put(smJ, 12, rA1); put(smJ, 13, rA2); put(smJ, 14, rB1); put(smJ, 15, rB2); put(smJ, 16, rC1); put(smJ, 17, rC2);
-        }
-        __syncthreads();
-        const T sj = T(a.s_j);
-        if (j < g.nr) {
-            cx<T> A[M], B[M];
-            cx<T> jx = zero<T>(), jt = zero<T>();
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 2 * q, k); B[k] = get(smJ, 2 * q + 1, k); }
-                conv_one<T, M>(A, B, m, jx, q == 1 ? T(-1) : T(1));
-            }
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 6 + 2 * q, k); B[k] = get(smJ, 7 + 2 * q, k); }
-                conv_one<T, M>(A, B, m, jt, q == 1 ? T(-1) : T(1));
-            }
-            if (!c.live) jx = jt = zero<T>();
-            if (own_row && c.owner) {
-                st(a.jax + g.at(m, j, c.i), sj * jx);
-                st(a.jat + g.at(m, j, c.i), sj * jt);
-            }
-        } else if (j == g.nr && own_row && c.owner) {
-            st(a.jax + g.at(m, j, c.i), zero<T>());
-            st(a.jat + g.at(m, j, c.i), zero<T>());
-        }
-        if (j >= 1 && j - 1 < g.nr && j - 1 >= r0 && j - 1 < r1 && c.owner) {
-            cx<T> A[M], B[M];
-            cx<T> jr = zero<T>();
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = get(smJ, 12 + 2 * q, k); B[k] = get(smJ, 13 + 2 * q, k); }
-                conv_one<T, M>(A, B, m, jr, q == 1 ? T(-1) : T(1));
-            }
-            if (!c.live) jr = zero<T>();
-            st(a.jar + g.at(m, j - 1, c.i), sj * jr);
-        }
-        // ---------------- rotate the axion window
-        X.phi1[0] = X.phi1[1];
-        X.bxn[0] = X.bxn[1];
-        X.tapa[0] = X.tapa[1]; X.tama[0] = X.tama[1]; X.tapb[0] = X.tapb[1]; X.tamb[0] = X.tamb[1];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            X.ta_o[0][e] = X.ta_o[1][e];
-            X.er0[0][e] = X.er0[1][e];
-            X.erh[0][e] = X.erh[1][e];
-            X.bth[0][e] = X.bth[1][e];
-            X.brh[0][e] = X.brh[1][e];
-            X.eth[0][e] = X.eth[1][e];
         }
     }
     // moving window: the owner of the last cell zero-fills the last column
@@ -723,6 +523,14 @@ __global__ void __launch_bounds__(WAVE * M) k_fused_a(FusedArgs<T> a) {
         }
     }
 }
+
+// Kernel A entry points: FP64 keeps the full register file (one wave per SIMD,
+// no spills); FP32 fits two waves per SIMD.
+template <int M>
+__global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) { fused_a_body<double, M>(a); }
+template <int M>
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M>(a); }
 
 // ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
@@ -794,8 +602,11 @@ template <typename T, int M>
 static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
     const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
     const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
-    const size_t lds = size_t(fused::NS + fused::NJ) * M * fused::WAVE * sizeof(cx<T>);
-    hipLaunchKernelGGL((fused::k_fused_a<T, M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
+    const size_t lds = size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((fused::k_fused_a_f64<M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
+    else
+        hipLaunchKernelGGL((fused::k_fused_a_f32<M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
     return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ struct FusedArgs {
 
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
 template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
+template <typename T> hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t window_shift(const cx<T>* src, cx<T>* dst, const Geo& g, int nplanes, hipStream_t s);
 template <typename T>
 hipError_t add_pulse(SetPtr<T> s0, const Geo& g, int pol, const double* fK, const double* fJ, const double* fG,

@@ -396,6 +396,118 @@ struct BgView {
 template <typename T>
 __device__ __forceinline__ T parity(int m) { return m == 0 ? T(1) : T(-1); }
 
+// The 18 per-mode factors of the axion current at H cell i, row j < nr (each
+// component is sum over three C_m{A, B} with signs +, -, +):
+//   f[0..5]   j_a,x     at (x_{i+1/2}, r_j,       t^n):       B_x, d_t phi | E_r, (d_theta phi)/r | E_theta, d_r phi
+//   f[6..11]  j_a,theta at (x_{i+1/2}, r_j,       t^{n+1/2}): B_theta, d_t phi | E_x, d_r phi | E_r, d_x phi
+//   f[12..17] j_a,r     at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}): B_r, d_t phi | E_theta, d_x phi | E_x, (d_theta phi)/r
+// Off-grid values are centred means of the nearest samples, with the axis
+// reflections (parity (-1)^m for B_x, phi, T_a; the T_r reflection of the
+// m = 1 axis relation for E_r and B_theta); the uniform external field is
+// added to the B factors.
+template <typename T>
+__device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f) {
+    const Geo& g = a.g;
+    BgView<T> v{&a};
+    const T dr = T(g.dr);
+    const int i1 = i + 1;
+    const bool ax = (j == 0);
+    const T rj = T(j) * dr;
+    const T rk = (T(j) + T(0.5)) * dr;
+    const T r_half = T(0.5) * dr;
+    const T par = parity<T>(m);
+    // ---------------- j_a,x
+    {
+        cx<T> bhi = T(0.5) * (ld(a.A0.bx + g.at(m, j, i)) + ld(a.B0.bx + g.at(m, j, i)));
+        cx<T> blo = ax ? par * bhi : T(0.5) * (ld(a.A0.bx + g.at(m, j - 1, i)) + ld(a.B0.bx + g.at(m, j - 1, i)));
+        f[0] = T(0.5) * (blo + bhi);
+        if (m == 0) f[0] = f[0] + a.bx0;
+        cx<T> d0 = T(0.5) * (v.dto(m, j, i) + v.dth(m, j, i));
+        cx<T> d1 = T(0.5) * (v.dto(m, j, i1) + v.dth(m, j, i1));
+        cx<T> l0 = ax ? par * d0 : T(0.5) * (v.dto(m, j - 1, i) + v.dth(m, j - 1, i));
+        cx<T> l1 = ax ? par * d1 : T(0.5) * (v.dto(m, j - 1, i1) + v.dth(m, j - 1, i1));
+        f[1] = T(0.5) * (T(0.5) * (l0 + d0) + T(0.5) * (l1 + d1));
+        cx<T> e0 = v.Er0(m, j, i), e1 = v.Er0(m, j, i1);
+        cx<T> g0, g1;
+        if (ax) {
+            if (m == 1) {
+                g0 = imul(T(2), v.Et0(1, 0, i)) - e0;
+                g1 = imul(T(2), v.Et0(1, 0, i1)) - e1;
+            } else {
+                g0 = -e0;
+                g1 = -e1;
+            }
+        } else {
+            g0 = v.Er0(m, j - 1, i);
+            g1 = v.Er0(m, j - 1, i1);
+        }
+        f[2] = T(0.5) * (T(0.5) * (g0 + e0) + T(0.5) * (g1 + e1));
+        cx<T> phi_hi = ld(a.phiA + g.at(m, j, i));
+        cx<T> phi_lo = ax ? par * phi_hi : ld(a.phiA + g.at(m, j - 1, i));
+        if (ax) f[3] = (m == 1) ? imul(-T(1) / r_half, phi_hi) : zero<T>();
+        else f[3] = imul(-T(m) / rj, T(0.5) * (phi_lo + phi_hi));
+        f[4] = T(0.5) * (v.Et0(m, j, i) + v.Et0(m, j, i1));
+        f[5] = (T(1) / dr) * (phi_hi - phi_lo);
+    }
+    // ---------------- j_a,theta
+    {
+        cx<T> b0 = T(0.5) * (v.Bt0(m, j, i) + v.Bt1(m, j, i));
+        cx<T> b1 = T(0.5) * (v.Bt0(m, j, i1) + v.Bt1(m, j, i1));
+        cx<T> e0 = T(0.5) * (v.Er0(m, j, i) + v.Er1(m, j, i));
+        cx<T> e1 = T(0.5) * (v.Er0(m, j, i1) + v.Er1(m, j, i1));
+        cx<T> gb0, gb1, ge0, ge1;
+        if (ax) {
+            if (m == 1) {
+                cx<T> br0 = T(0.5) * (v.Br0(1, 0, i) + v.Br1(1, 0, i));
+                cx<T> br1 = T(0.5) * (v.Br0(1, 0, i1) + v.Br1(1, 0, i1));
+                cx<T> et0 = T(0.5) * (v.Et0(1, 0, i) + v.Et1(1, 0, i));
+                cx<T> et1 = T(0.5) * (v.Et0(1, 0, i1) + v.Et1(1, 0, i1));
+                gb0 = imul(-T(2), br0) - b0;
+                gb1 = imul(-T(2), br1) - b1;
+                ge0 = imul(T(2), et0) - e0;
+                ge1 = imul(T(2), et1) - e1;
+            } else {
+                gb0 = -b0; gb1 = -b1; ge0 = -e0; ge1 = -e1;
+            }
+        } else {
+            gb0 = T(0.5) * (v.Bt0(m, j - 1, i) + v.Bt1(m, j - 1, i));
+            gb1 = T(0.5) * (v.Bt0(m, j - 1, i1) + v.Bt1(m, j - 1, i1));
+            ge0 = T(0.5) * (v.Er0(m, j - 1, i) + v.Er1(m, j - 1, i));
+            ge1 = T(0.5) * (v.Er0(m, j - 1, i1) + v.Er1(m, j - 1, i1));
+        }
+        f[6] = T(0.5) * (T(0.5) * (gb0 + b0) + T(0.5) * (gb1 + b1));
+        if (m == 1) f[6] = f[6] + a.bt1;
+        f[10] = T(0.5) * (T(0.5) * (ge0 + e0) + T(0.5) * (ge1 + e1));
+        cx<T> t0 = v.dth(m, j, i), t1 = v.dth(m, j, i1);
+        cx<T> x0 = v.dxh(m, j, i), x1 = v.dxh(m, j, i1);
+        cx<T> tl0 = ax ? par * t0 : v.dth(m, j - 1, i), tl1 = ax ? par * t1 : v.dth(m, j - 1, i1);
+        cx<T> xl0 = ax ? par * x0 : v.dxh(m, j - 1, i), xl1 = ax ? par * x1 : v.dxh(m, j - 1, i1);
+        f[7] = T(0.5) * (T(0.5) * (tl0 + t0) + T(0.5) * (tl1 + t1));
+        f[11] = T(0.5) * (T(0.5) * (xl0 + x0) + T(0.5) * (xl1 + x1));
+        f[8] = ld(a.B0.ex + g.at(m, j, i));
+        cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
+        cx<T> pl = ax ? par * ph : T(0.5) * (ld(a.phiA + g.at(m, j - 1, i)) + ld(a.phiB + g.at(m, j - 1, i)));
+        f[9] = (T(1) / dr) * (ph - pl);
+    }
+    // ---------------- j_a,r
+    {
+        cx<T> sb = zero<T>(), se = zero<T>();
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                sb = sb + T(0.5) * (v.Br0(m, j + dj, i + di) + v.Br1(m, j + dj, i + di));
+                se = se + T(0.5) * (v.Et0(m, j + dj, i + di) + v.Et1(m, j + dj, i + di));
+            }
+        f[12] = T(0.25) * sb;
+        if (m == 1) f[12] = f[12] + a.br1;
+        f[13] = T(0.5) * (v.dth(m, j, i) + v.dth(m, j, i1));
+        f[14] = T(0.25) * se;
+        f[15] = T(0.5) * (v.dxh(m, j, i) + v.dxh(m, j, i1));
+        f[16] = T(0.5) * (ld(a.B0.ex + g.at(m, j, i)) + ld(a.B0.ex + g.at(m, j + 1, i)));
+        cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
+        f[17] = imul(-T(m) / rk, ph);
+    }
+}
+
 template <typename T, int M>
 __global__ void k_axion_current(AxionArgs<T> a) {
     const Geo& g = a.g;
@@ -403,141 +515,27 @@ __global__ void k_axion_current(AxionArgs<T> a) {
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.nx || j > g.nr) return;
     const bool live = g.per || i < g.nx - 1;
-    const T dr = T(g.dr);
-    BgView<T> f{&a};
     cx<T> jx[M], jr[M], jt[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) jx[m] = jr[m] = jt[m] = zero<T>();
-    const int i1 = i + 1;
     if (live && j < g.nr) {
-        const bool ax = (j == 0);
-        const T rj = T(j) * dr;
-        const T rk = (T(j) + T(0.5)) * dr;
-        const T r_half = T(0.5) * dr;
-        // ---------------- j_a,x at (x_{i+1/2}, r_j, t^n)
-        {
-            cx<T> A1[M], A2[M], B1[M], B2[M], C1[M], C2[M];
+        cx<T> F[18][M];
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const T par = parity<T>(m);
-                // B_x at t^n, mean of r_{j-1/2}, r_{j+1/2}
-                cx<T> bhi = T(0.5) * (ld(a.A0.bx + g.at(m, j, i)) + ld(a.B0.bx + g.at(m, j, i)));
-                cx<T> blo = ax ? par * bhi
-                               : T(0.5) * (ld(a.A0.bx + g.at(m, j - 1, i)) + ld(a.B0.bx + g.at(m, j - 1, i)));
-                A1[m] = T(0.5) * (blo + bhi);
-                // d_t phi at t^n: mean of T_a-derived values over (i, i+1), (n+-1/2), (r_{j+-1/2})
-                cx<T> d0 = T(0.5) * (f.dto(m, j, i) + f.dth(m, j, i));
-                cx<T> d1 = T(0.5) * (f.dto(m, j, i1) + f.dth(m, j, i1));
-                cx<T> l0 = ax ? par * d0 : T(0.5) * (f.dto(m, j - 1, i) + f.dth(m, j - 1, i));
-                cx<T> l1 = ax ? par * d1 : T(0.5) * (f.dto(m, j - 1, i1) + f.dth(m, j - 1, i1));
-                A2[m] = T(0.5) * (T(0.5) * (l0 + d0) + T(0.5) * (l1 + d1));
-                // E_r at (x_{i+1/2}, r_j) with the axis reflection
-                cx<T> e0 = f.Er0(m, j, i), e1 = f.Er0(m, j, i1);
-                cx<T> g0, g1;
-                if (ax) {
-                    if (m == 1) {
-                        g0 = imul(T(2), f.Et0(1, 0, i)) - e0;
-                        g1 = imul(T(2), f.Et0(1, 0, i1)) - e1;
-                    } else {
-                        g0 = -e0;
-                        g1 = -e1;
-                    }
-                } else {
-                    g0 = f.Er0(m, j - 1, i);
-                    g1 = f.Er0(m, j - 1, i1);
-                }
-                B1[m] = T(0.5) * (T(0.5) * (g0 + e0) + T(0.5) * (g1 + e1));
-                // (d_theta phi)/r at r_j
-                cx<T> phi_hi = ld(a.phiA + g.at(m, j, i));
-                cx<T> phi_lo = ax ? par * phi_hi : ld(a.phiA + g.at(m, j - 1, i));
-                if (ax) {
-                    B2[m] = (m == 1) ? imul(-T(1) / r_half, phi_hi) : zero<T>();
-                } else {
-                    B2[m] = imul(-T(m) / rj, T(0.5) * (phi_lo + phi_hi));
-                }
-                C1[m] = T(0.5) * (f.Et0(m, j, i) + f.Et0(m, j, i1));
-                C2[m] = (T(1) / dr) * (phi_hi - phi_lo);
-            }
-            A1[0] = A1[0] + a.bx0;
-            conv_acc<T, M>(A1, A2, T(1), jx);
-            conv_acc<T, M>(B1, B2, T(-1), jx);
-            conv_acc<T, M>(C1, C2, T(1), jx);
-        }
-        // ---------------- j_a,r at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2})
-        {
-            cx<T> A1[M], A2[M], B1[M], B2[M], C1[M], C2[M];
+        for (int m = 0; m < M; ++m) {
+            cx<T> f[18];
+            ja_factors(a, m, i, j, f);
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                cx<T> s = zero<T>(), e = zero<T>();
-                for (int dj = 0; dj < 2; ++dj)
-                    for (int di = 0; di < 2; ++di) {
-                        s = s + T(0.5) * (f.Br0(m, j + dj, i + di) + f.Br1(m, j + dj, i + di));
-                        e = e + T(0.5) * (f.Et0(m, j + dj, i + di) + f.Et1(m, j + dj, i + di));
-                    }
-                A1[m] = T(0.25) * s;
-                B1[m] = T(0.25) * e;
-                A2[m] = T(0.5) * (f.dth(m, j, i) + f.dth(m, j, i1));
-                B2[m] = T(0.5) * (f.dxh(m, j, i) + f.dxh(m, j, i1));
-                C1[m] = T(0.5) * (ld(a.B0.ex + g.at(m, j, i)) + ld(a.B0.ex + g.at(m, j + 1, i)));
-                cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
-                C2[m] = imul(-T(m) / rk, ph);
-            }
-            if (M > 1) A1[1] = A1[1] + a.br1;
-            conv_acc<T, M>(A1, A2, T(1), jr);
-            conv_acc<T, M>(B1, B2, T(-1), jr);
-            conv_acc<T, M>(C1, C2, T(1), jr);
+            for (int q = 0; q < 18; ++q) F[q][m] = f[q];
         }
-        // ---------------- j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2})
-        {
-            cx<T> A1[M], A2[M], B1[M], B2[M], C1[M], C2[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const T par = parity<T>(m);
-                // B_theta at t^{n+1/2} at (x_{i+1/2}, r_j) with the axis reflection
-                cx<T> b0 = T(0.5) * (f.Bt0(m, j, i) + f.Bt1(m, j, i));
-                cx<T> b1 = T(0.5) * (f.Bt0(m, j, i1) + f.Bt1(m, j, i1));
-                cx<T> e0 = T(0.5) * (f.Er0(m, j, i) + f.Er1(m, j, i));
-                cx<T> e1 = T(0.5) * (f.Er0(m, j, i1) + f.Er1(m, j, i1));
-                cx<T> gb0, gb1, ge0, ge1;
-                if (ax) {
-                    if (m == 1) {
-                        cx<T> br0 = T(0.5) * (f.Br0(1, 0, i) + f.Br1(1, 0, i));
-                        cx<T> br1 = T(0.5) * (f.Br0(1, 0, i1) + f.Br1(1, 0, i1));
-                        cx<T> et0 = T(0.5) * (f.Et0(1, 0, i) + f.Et1(1, 0, i));
-                        cx<T> et1 = T(0.5) * (f.Et0(1, 0, i1) + f.Et1(1, 0, i1));
-                        gb0 = imul(-T(2), br0) - b0;
-                        gb1 = imul(-T(2), br1) - b1;
-                        ge0 = imul(T(2), et0) - e0;
-                        ge1 = imul(T(2), et1) - e1;
-                    } else {
-                        gb0 = -b0; gb1 = -b1; ge0 = -e0; ge1 = -e1;
-                    }
-                } else {
-                    gb0 = T(0.5) * (f.Bt0(m, j - 1, i) + f.Bt1(m, j - 1, i));
-                    gb1 = T(0.5) * (f.Bt0(m, j - 1, i1) + f.Bt1(m, j - 1, i1));
-                    ge0 = T(0.5) * (f.Er0(m, j - 1, i) + f.Er1(m, j - 1, i));
-                    ge1 = T(0.5) * (f.Er0(m, j - 1, i1) + f.Er1(m, j - 1, i1));
-                }
-                A1[m] = T(0.5) * (T(0.5) * (gb0 + b0) + T(0.5) * (gb1 + b1));
-                C1[m] = T(0.5) * (T(0.5) * (ge0 + e0) + T(0.5) * (ge1 + e1));
-                // d_t phi, d_x phi at t^{n+1/2}
-                cx<T> t0 = f.dth(m, j, i), t1 = f.dth(m, j, i1);
-                cx<T> x0 = f.dxh(m, j, i), x1 = f.dxh(m, j, i1);
-                cx<T> tl0 = ax ? par * t0 : f.dth(m, j - 1, i), tl1 = ax ? par * t1 : f.dth(m, j - 1, i1);
-                cx<T> xl0 = ax ? par * x0 : f.dxh(m, j - 1, i), xl1 = ax ? par * x1 : f.dxh(m, j - 1, i1);
-                A2[m] = T(0.5) * (T(0.5) * (tl0 + t0) + T(0.5) * (tl1 + t1));
-                C2[m] = T(0.5) * (T(0.5) * (xl0 + x0) + T(0.5) * (xl1 + x1));
-                B1[m] = ld(a.B0.ex + g.at(m, j, i));
-                cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
-                cx<T> pl = ax ? par * ph
-                              : T(0.5) * (ld(a.phiA + g.at(m, j - 1, i)) + ld(a.phiB + g.at(m, j - 1, i)));
-                B2[m] = (T(1) / dr) * (ph - pl);
-            }
-            if (M > 1) A1[1] = A1[1] + a.bt1;
-            conv_acc<T, M>(A1, A2, T(1), jt);
-            conv_acc<T, M>(B1, B2, T(-1), jt);
-            conv_acc<T, M>(C1, C2, T(1), jt);
-        }
+        conv_acc<T, M>(F[0], F[1], T(1), jx);
+        conv_acc<T, M>(F[2], F[3], T(-1), jx);
+        conv_acc<T, M>(F[4], F[5], T(1), jx);
+        conv_acc<T, M>(F[6], F[7], T(1), jt);
+        conv_acc<T, M>(F[8], F[9], T(-1), jt);
+        conv_acc<T, M>(F[10], F[11], T(1), jt);
+        conv_acc<T, M>(F[12], F[13], T(1), jr);
+        conv_acc<T, M>(F[14], F[15], T(-1), jr);
+        conv_acc<T, M>(F[16], F[17], T(1), jr);
     }
     const T sj = T(a.s_j);
 #pragma unroll
@@ -547,6 +545,60 @@ __global__ void k_axion_current(AxionArgs<T> a) {
         if (j < g.nr) st(a.jar + g.at(m, j, i), sj * jr[m]);
     }
 }
+
+// Axion current with one wavefront per mode: a workgroup of M waves covers 64
+// cells of one row; each wave forms its mode's factors, the waves exchange them
+// through LDS and each evaluates C_m for its own mode.
+template <typename T, int M>
+__global__ void __launch_bounds__(64 * M) k_axion_current_w(AxionArgs<T> a) {
+    const Geo& g = a.g;
+    const int m = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int i = blockIdx.x * 64 + lane;
+    const int j = blockIdx.y;
+    __shared__ cx<T> sm[18][M][64];
+    const bool act = i < g.nx;
+    const bool live = act && (g.per || i < g.nx - 1);
+    const bool calc = live && j < g.nr;
+    if (calc) {
+        cx<T> f[18];
+        ja_factors(a, m, i, j, f);
+#pragma unroll
+        for (int q = 0; q < 18; ++q) sm[q][m][lane] = f[q];
+    }
+    __syncthreads();
+    cx<T> jx = zero<T>(), jr = zero<T>(), jt = zero<T>();
+    if (calc) {
+        cx<T> A[M], B[M];
+        cx<T> out[3] = {zero<T>(), zero<T>(), zero<T>()};
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
+            conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
+        }
+        jx = out[0]; jt = out[1]; jr = out[2];
+    }
+    if (!act) return;
+    const T sj = T(a.s_j);
+    st(a.jax + g.at(m, j, i), sj * jx);
+    st(a.jat + g.at(m, j, i), sj * jt);
+    if (j < g.nr) st(a.jar + g.at(m, j, i), sj * jr);
+}
+
+template <typename T>
+hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s) {
+    dim3 grd((a.g.nx + 63) / 64, a.g.nr + 1);
+    switch (a.g.M) {
+#define QDS_CW(MM) case MM: hipLaunchKernelGGL((k_axion_current_w<T, MM>), grd, dim3(64 * MM), 0, s, a); break;
+        QDS_CW(1) QDS_CW(2) QDS_CW(3) QDS_CW(4)
+#undef QDS_CW
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t axion_current_w<double>(const AxionArgs<double>&, hipStream_t);
+template hipError_t axion_current_w<float>(const AxionArgs<float>&, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // moving window: copy every plane shifted left by one column, zero the last

@@ -155,12 +155,13 @@ class Solver:
         return bool(lib().qds_uses_fused(self.h))
 
     def timing(self):
-        """(ms per kernel, launches per kernel) accumulated since timing was enabled;
-        index 0 = background-set kernel, 1 = regenerated-set kernel."""
-        ms = (ctypes.c_double * 2)()
-        n = (ctypes.c_int64 * 2)()
+        """(ms per kernel, launches per kernel) recorded since timing was set;
+        index 0 = background set + axion (kernel A), 1 = regenerated set
+        (kernel B), 2 = axion current."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
         _check(lib().qds_get_timing(self.h, ms, n), self.h)
-        return [ms[0], ms[1]], [n[0], n[1]]
+        return list(ms), list(n)
 
     # -- parameters ---------------------------------------------------------
     def _current(self) -> Current:

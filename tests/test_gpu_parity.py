@@ -112,9 +112,25 @@ def test_fused_modes(M, dtype):
     assert s.fused
 
 
-@pytest.mark.parametrize("x_bc,r_bc", [("periodic", "pec"), ("periodic", "open"), ("open", "pec"), ("window", "open")])
+@pytest.mark.parametrize("x_bc,r_bc", [("periodic", "pec"), ("periodic", "open"), ("open", "pec")])
 def test_fused_boundaries(x_bc, r_bc):
     _check(_full(128, 12, 3, x_bc=x_bc, r_bc=r_bc), 12, "f64", path=2, rows=5)
+
+
+def test_window_with_regenerated_set_runs_staged():
+    """The moving window with the regenerated set takes the staged kernels
+    (the fused path refuses it) and still matches the oracle."""
+    from paper_2609_03550_amd import qds
+    wl = _full(128, 12, 3, x_bc="window")
+    with pytest.raises(qds.QDSError):
+        qds.Solver(wl, path=2)
+    s = _check(wl, 12, "f64")
+    assert not s.fused
+
+
+def test_window_axion_without_regenerated_set_fused():
+    s = _check(_full(128, 12, 3, x_bc="window", arem=False), 12, "f64", path=2, rows=5)
+    assert s.fused
 
 
 @pytest.mark.parametrize("rows", [2, 9])
