@@ -162,6 +162,42 @@ qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches);
 /* 1 if qds_step runs the fused kernels for this handle. */
 int32_t qds_uses_fused(qds_handle h);
 
+/* Loss of the adjoint: the field energy of one mode of one set over the
+ * columns x_begin <= i < x_end at the final step (E_x, B_x at t^{N-1/2}):
+ *   L = w dx dr [ sum r_{j+1/2} (|T_r^+|^2 + |T_r^-|^2)/4 + sum r_j (|T_th^+|^2 + |T_th^-|^2)/4
+ *               + sum r_j |E_x|^2/2 + sum r_{j+1/2} |B_x|^2/2 ],
+ * w = 2 pi for mode 0 and pi otherwise (Eq. fourier_decomp), the axis row
+ * weighted by dr/8 in place of r_0 (energy-centroid diagnostic of Sec. 4.1). */
+typedef struct {
+    int32_t set;       /* 0 background, 1 regenerated */
+    int32_t mode;
+    int32_t x_begin, x_end;
+} qds_loss;
+
+/* Bytes of the device pool qds_backward needs for n_steps with a checkpoint
+ * every ckpt_every steps: ceil(n/C) checkpoints + (C+1) segment states + 2
+ * adjoint states + 3 planes + 256 B. */
+size_t qds_backward_pool_bytes(qds_handle h, int64_t n_steps, int64_t ckpt_every);
+
+/* Gradient of the loss after n_steps steps from the state u0->buf[u0->cur]
+ * with respect to that initial state, by the transposed (adjoint) step run
+ * backward in time over recomputed states: the forward is checkpointed every
+ * ckpt_every steps into ckpt_pool (caller-owned device memory of at least
+ * qds_backward_pool_bytes), and each segment is recomputed before its
+ * adjoint steps.  Gradients are over the real inner product Re sum conj(a) b
+ * of the complex state.  Writes lambda0_out (a device buffer of
+ * qds_state_bytes, same layout as a state), *loss_out (host) and, with the
+ * regenerated set, dL_ds_out[2] (host): the sensitivities to the scales
+ * s_phi of the Klein-Gordon source and s_j of the axion current.  u0 is not
+ * modified.  Synchronises the stream before returning.  Not available for the
+ * moving window, a prescribed drive or more than 4 modes (QDS_EUNSUPPORTED). */
+qds_status qds_backward(qds_handle h, const qds_state* u0, const qds_current* J, const qds_axion* axion,
+                        const qds_loss* loss, int64_t n_steps, int64_t ckpt_every, void* ckpt_pool,
+                        size_t pool_bytes, void* lambda0_out, double* dL_ds_out, double* loss_out, void* stream);
+
+/* Adds Re sum conj(a) b over two state buffers to *out_dev (a device double). */
+qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream);
+
 qds_status qds_destroy(qds_handle h);
 const char* qds_last_error(qds_handle h);
 const char* qds_version(void);

@@ -1,0 +1,932 @@
+// Adjoint (transposed, reverse-time) step of the staged QDS step.
+//
+// Every forward stage y = f(x) of qds_stages.hip has a twin here that runs
+// the same loops and branches and, for each term of f, adds the transposed
+// contribution to the adjoint of its input: over the real inner product
+// <u, v> = Re sum conj(u) v, a term y += c x gives xbar += conj(c) ybar, a term
+// y += c conj(x) gives xbar += c conj(ybar), y = Re(x) gives xbar += Re(ybar).
+// Adjoints of the new state (buffer B) also collect the contributions of the
+// later stages that read it, so the stages run in reverse order.  Inputs the
+// forward step reads from several threads receive atomic adds.
+#include "qds_stage_ops.hpp"
+
+namespace qds {
+namespace adj {
+
+// ---------------------------------------------------------------------------
+// scatter-add helpers mirroring the forward accessors
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void aadd(double* p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void aadd(float* p, float v) { atomicAdd(p, v); }
+
+template <typename T>
+__device__ __forceinline__ void cadd(cx<T>* p, cx<T> v) {
+    T* q = reinterpret_cast<T*>(p);
+    if (v.re != T(0)) aadd(q, v.re);
+    if (v.im != T(0)) aadd(q + 1, v.im);
+}
+
+// adjoint of ldx(p, g, m, row, c)
+template <typename T>
+__device__ __forceinline__ void addx(cx<T>* p, const Geo& g, int m, int row, int c, cx<T> v) {
+    if (c < 0 || c >= g.nx) {
+        if (!g.per) return;
+        c = (c + g.nx) % g.nx;
+    }
+    cadd(p + g.at(m, row, c), v);
+}
+
+template <typename T>
+struct SetBar {
+    cx<T>* trp; cx<T>* trm; cx<T>* ttp; cx<T>* ttm; cx<T>* ex; cx<T>* bx; cx<T>* jx; cx<T>* jr; cx<T>* jt;
+};
+
+// adjoints of bth / er / eth / brr (B_theta, E_r from T_r; E_theta, B_r from T_theta)
+template <typename T>
+__device__ __forceinline__ void add_bth(const SetBar<T>& s, const Geo& g, int m, int k, int c, cx<T> v) {
+    if (k == g.nr) {
+        addx(s.trp, g, m, k, c, v);
+        return;
+    }
+    addx(s.trp, g, m, k, c, T(0.5) * v);
+    addx(s.trm, g, m, k, c, -(T(0.5) * v));
+}
+template <typename T>
+__device__ __forceinline__ void add_er(const SetBar<T>& s, const Geo& g, int m, int k, int c, cx<T> v) {
+    addx(s.trp, g, m, k, c, T(0.5) * v);
+    addx(s.trm, g, m, k, c, T(0.5) * v);
+}
+template <typename T>
+__device__ __forceinline__ void add_eth(const SetBar<T>& s, const Geo& g, int m, int j, int c, cx<T> v) {
+    addx(s.ttp, g, m, j, c, T(0.5) * v);
+    addx(s.ttm, g, m, j, c, T(0.5) * v);
+}
+template <typename T>
+__device__ __forceinline__ void add_brr(const SetBar<T>& s, const Geo& g, int m, int j, int c, cx<T> v) {
+    addx(s.ttp, g, m, j, c, T(0.5) * v);
+    addx(s.ttm, g, m, j, c, -(T(0.5) * v));
+}
+// conj(i s) v = -i s v
+template <typename T>
+__device__ __forceinline__ cx<T> imul_c(T s, cx<T> v) { return imul(-s, v); }
+
+template <typename T>
+struct StageBar {
+    Geo g;
+    SetPtr<T> A, B;             // forward old / new state of this set
+    SetBar<T> Ab, Bb;           // their adjoints
+    cx<T>* jx_addb;             // adjoint of the extra currents (or null)
+    cx<T>* jr_addb;
+    cx<T>* jt_addb;
+    int plasma;
+    double wp2;
+};
+
+// adjoint of jx_total (plasma part lives in B.jx, extra current, drive = const)
+template <typename T>
+__device__ __forceinline__ void jx_total_bar(const StageBar<T>& a, int m, int j, int i, cx<T> v) {
+    const Geo& g = a.g;
+    int c = i;
+    if (g.per) c = (i + g.nx) % g.nx;
+    else if (i < 0 || i >= g.nx - 1) return;
+    if (a.plasma) cadd(a.Bb.jx + g.at(m, j, c), v);
+    if (a.jx_addb) cadd(a.jx_addb + g.at(m, j, c), v);
+}
+template <typename T>
+__device__ __forceinline__ void jr_total_bar(const StageBar<T>& a, int m, int k, int i, cx<T> v) {
+    const Geo& g = a.g;
+    if (a.plasma) {
+        addx(a.Bb.jr, g, m, k, i, T(0.5) * v);
+        addx(a.Bb.jr, g, m, k, i + 1, T(0.5) * v);
+    }
+    if (a.jr_addb) cadd(a.jr_addb + g.at(m, k, i), v);
+}
+template <typename T>
+__device__ __forceinline__ void jt_total_bar(const StageBar<T>& a, int m, int j, int i, cx<T> v) {
+    const Geo& g = a.g;
+    if (a.plasma) {
+        addx(a.Bb.jt, g, m, j, i, T(0.5) * v);
+        addx(a.Bb.jt, g, m, j, i + 1, T(0.5) * v);
+    }
+    if (a.jt_addb) cadd(a.jt_addb + g.at(m, j, i), v);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> ldv(const cx<T>* p, const Geo& g, int m, int row, int c) {
+    if (c < 0 || c >= g.nx) {
+        if (!g.per) return zero<T>();
+        c = (c + g.nx) % g.nx;
+    }
+    return ld(p + g.at(m, row, c));
+}
+
+// adjoint of bx_new_at (B_x^{n+1/2} at K = k) for the adjoint value bb
+template <typename T>
+__device__ void bx_new_bar(const StageBar<T>& a, int m, int k, int i, cx<T> bb) {
+    const Geo& g = a.g;
+    const T dr = T(g.dr), h = T(g.h);
+    const T rk = (T(k) + T(0.5)) * dr;
+    cadd(a.Ab.bx + g.at(m, k, i), bb);
+    cx<T> fx = h * bb;
+    cx<T> eavg = -(T(1) / rk) * fx;
+    cx<T> de = -fx;
+    cx<T> erav = imul_c(-T(m) / rk, fx);
+    cx<T> lo = T(0.25) * eavg - (T(1) / (T(2) * dr)) * de;
+    cx<T> hi = T(0.25) * eavg + (T(1) / (T(2) * dr)) * de;
+    add_eth(a.Ab, g, m, k, i, lo);
+    add_eth(a.Ab, g, m, k, i + 1, lo);
+    add_eth(a.Ab, g, m, k + 1, i, hi);
+    add_eth(a.Ab, g, m, k + 1, i + 1, hi);
+    add_er(a.Ab, g, m, k, i, T(0.5) * erav);
+    add_er(a.Ab, g, m, k, i + 1, T(0.5) * erav);
+}
+
+// ---- adjoint of k_ghost_bth
+template <typename T>
+__global__ void k_ghost_bth_bar(StageBar<T> a) {
+    const Geo& g = a.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nx || !g.open_r) return;
+    const int N = g.nr;
+    const T h = T(g.h), dr = T(g.dr);
+    const T rN = T(N) * dr;
+    const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+    for (int m = 0; m < g.M; ++m) {
+        cx<T> ob = ld(a.Bb.trp + g.at(m, N, i));
+        // out = I0 + kap (G0 - I1) + cR rt
+        cx<T> rt = cR * ob;
+        cx<T> I0 = ob - (T(1) / (T(2) * rN)) * (T(0.5) * rt);
+        cx<T> G0 = kap * ob - (T(1) / (T(2) * rN)) * (T(0.5) * rt);
+        cx<T> I1 = -(kap * ob);
+        cx<T> dxer = -(T(0.5) * rt);
+        cx<T> jxi = T(0.5) * rt;
+        cx<T> br = imul_c(-T(m) / (T(2) * rN), rt);
+        add_bth(a.Ab, g, m, N - 1, i, I0);
+        cadd(a.Ab.trp + g.at(m, N, i), G0);
+        cadd(a.Bb.trp + g.at(m, N - 1, i), T(0.5) * I1);
+        cadd(a.Bb.trm + g.at(m, N - 1, i), -(T(0.5) * I1));
+        add_er(a.Ab, g, m, N - 1, i + 1, (T(1) / (T(2) * h)) * dxer);
+        add_er(a.Ab, g, m, N - 1, i - 1, -((T(1) / (T(2) * h)) * dxer));
+        jx_total_bar(a, m, N, i, T(0.5) * jxi);
+        jx_total_bar(a, m, N, i - 1, T(0.5) * jxi);
+        add_brr(a.Ab, g, m, N, i, br);
+    }
+}
+
+// ---- adjoint of k_transverse
+template <typename T>
+__global__ void k_transverse_bar(StageBar<T> a) {
+    const Geo& g = a.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j > g.nr) return;
+    const T h = T(g.h), dr = T(g.dr);
+    const bool live = g.per || i < g.nx - 1;
+    const int ir = g.per ? (i + 1) % g.nx : i + 1;
+    for (int m = 0; m < g.M; ++m) {
+        if (j < g.nr) {
+            cx<T> pb = (ir < g.nx) ? ld(a.Bb.trp + g.at(m, j, ir)) : zero<T>();
+            cx<T> mb = ld(a.Bb.trm + g.at(m, j, i));
+            if (ir < g.nx) addx(a.Ab.trp, g, m, j, i, pb);
+            addx(a.Ab.trm, g, m, j, i + 1, mb);
+            if (live) {
+                const T rk = (T(j) + T(0.5)) * dr;
+                cx<T> gr = h * (pb + mb), pr = h * (pb - mb);
+                cadd(a.Bb.bx + g.at(m, j, i), imul_c(-T(m) / rk, gr));
+                jr_total_bar(a, m, j, i, -gr);
+                cadd(a.Bb.ex + g.at(m, j + 1, i), (T(1) / dr) * pr);
+                cadd(a.Bb.ex + g.at(m, j, i), -((T(1) / dr) * pr));
+            }
+        }
+        const bool zero_row = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
+        if (zero_row) continue;
+        cx<T> pb = ld(a.Bb.ttp + g.at(m, j, i));
+        cx<T> mb = (ir < g.nx) ? ld(a.Bb.ttm + g.at(m, j, ir)) : zero<T>();
+        addx(a.Ab.ttp, g, m, j, i + 1, pb);
+        if (ir < g.nx) addx(a.Ab.ttm, g, m, j, i, mb);
+        if (live) {
+            cx<T> gt = h * (pb + mb), pt = h * (pb - mb);
+            if (j == 0) {
+                cadd(a.Bb.bx + g.at(1, 0, i), -((T(2) / dr) * gt));
+                jt_total_bar(a, 1, 0, i, -gt);
+                cadd(a.Bb.ex + g.at(1, 1, i), imul_c(T(1) / dr, pt));
+            } else {
+                const T rj = T(j) * dr;
+                cadd(a.Bb.bx + g.at(m, j, i), -((T(1) / dr) * gt));
+                cadd(a.Bb.bx + g.at(m, j - 1, i), (T(1) / dr) * gt);
+                jt_total_bar(a, m, j, i, -gt);
+                cadd(a.Bb.ex + g.at(m, j, i), imul_c(T(m) / rj, pt));
+            }
+        }
+    }
+}
+
+// ---- adjoint of k_longitudinal
+template <typename T>
+__global__ void k_longitudinal_bar(StageBar<T> a) {
+    const Geo& g = a.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || j > g.nr) return;
+    const T h = T(g.h), dr = T(g.dr);
+    const bool live = g.per || i < g.nx - 1;
+    const T wp2h = T(a.wp2 * g.h);
+    // adjoint of the total j_x at this (i, j) from the E_x update: kept in a
+    // register for the plasma part below (no read-back of an atomic target)
+    cx<T> jx_here[QDS_MAX_MODES];
+    for (int m = 0; m < g.M; ++m) jx_here[m] = zero<T>();
+    auto jx_bar = [&](int m, cx<T> v) {
+        jx_here[m] = jx_here[m] + v;
+        if (a.jx_addb) cadd(a.jx_addb + g.at(m, j, i), v);
+    };
+    for (int m = 0; m < g.M; ++m) {
+        const size_t e = g.at(m, j, i);
+        // ---- E_x
+        cx<T> eb = ld(a.Bb.ex + e);
+        if (!(!live || (!g.open_r && j == g.nr))) {
+            if (j == 0) {
+                if (m == 0) {
+                    cadd(a.Ab.ex + e, eb);
+                    cx<T> gx = h * eb;
+                    cx<T> b = (T(4) / dr) * gx;
+                    add_bth(a.Ab, g, 0, 0, i, T(0.5) * b);
+                    add_bth(a.Ab, g, 0, 0, i + 1, T(0.5) * b);
+                    jx_bar(0, -gx);
+                }
+            } else {
+                const T rj = T(j) * dr;
+                cadd(a.Ab.ex + e, eb);
+                cx<T> gx = h * eb;
+                cx<T> bavg = (T(1) / rj) * gx;
+                cx<T> db = gx;
+                cx<T> brav = imul_c(T(m) / rj, gx);
+                jx_bar(m, -gx);
+                cx<T> lo = T(0.25) * bavg - (T(1) / (T(2) * dr)) * db;
+                cx<T> hi = T(0.25) * bavg + (T(1) / (T(2) * dr)) * db;
+                add_bth(a.Ab, g, m, j - 1, i, lo);
+                add_bth(a.Ab, g, m, j - 1, i + 1, lo);
+                add_bth(a.Ab, g, m, j, i, hi);
+                add_bth(a.Ab, g, m, j, i + 1, hi);
+                add_brr(a.Ab, g, m, j, i, T(0.5) * brav);
+                add_brr(a.Ab, g, m, j, i + 1, T(0.5) * brav);
+            }
+        }
+        // ---- B_x and the exterior ghost row
+        if (j < g.nr) {
+            if (live) bx_new_bar(a, m, j, i, ld(a.Bb.bx + e));
+        } else if (g.open_r && live) {
+            const int N = g.nr;
+            const T rN = T(N) * dr;
+            const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+            cx<T> gh = ld(a.Bb.bx + e);
+            cadd(a.Ab.bx + g.at(m, N - 1, i), gh);
+            cadd(a.Ab.bx + g.at(m, N, i), kap * gh);
+            bx_new_bar(a, m, N - 1, i, -(kap * gh));
+            cx<T> rx = cR * gh;
+            add_brr(a.Ab, g, m, N, i + 1, (T(0.5) / h) * rx);
+            add_brr(a.Ab, g, m, N, i, -((T(0.5) / h) * rx));
+            cx<T> ea = -(T(1) / (T(2) * rN)) * rx;
+            add_eth(a.Ab, g, m, N, i, T(0.5) * ea);
+            add_eth(a.Ab, g, m, N, i + 1, T(0.5) * ea);
+            cx<T> ra = imul_c(-T(m) / (T(2) * rN), rx);
+            add_er(a.Ab, g, m, N - 1, i, T(0.5) * ra);
+            add_er(a.Ab, g, m, N - 1, i + 1, T(0.5) * ra);
+            cx<T> jt = -(T(0.5) * rx);
+            if (a.plasma) {
+                addx(a.Ab.jt, g, m, N, i, T(0.5) * jt);
+                add_eth(a.Ab, g, m, N, i, wp2h * (T(0.5) * jt));
+                if (g.per || i + 1 < g.nx) {
+                    addx(a.Ab.jt, g, m, N, i + 1, T(0.5) * jt);
+                    add_eth(a.Ab, g, m, N, i + 1, wp2h * (T(0.5) * jt));
+                }
+            }
+            if (a.jt_addb) cadd(a.jt_addb + g.at(m, N, i), jt);
+        }
+    }
+    // ---- plasma response (read after this thread's own E_x adjoint added to B.jx)
+    if (a.plasma) {
+        for (int m = 0; m < g.M; ++m) {
+            const size_t e = g.at(m, j, i);
+            cx<T> jxb = ld(a.Bb.jx + e) + jx_here[m];
+            cadd(a.Ab.jx + e, jxb);
+            cadd(a.Ab.ex + e, wp2h * jxb);
+            if (j < g.nr) {
+                cx<T> jrb = ld(a.Bb.jr + e);
+                cadd(a.Ab.jr + e, jrb);
+                add_er(a.Ab, g, m, j, i, wp2h * jrb);
+            }
+            if (!(!g.open_r && j == g.nr)) {
+                cx<T> jtb = ld(a.Bb.jt + e);
+                cadd(a.Ab.jt + e, jtb);
+                add_eth(a.Ab, g, m, j, i, wp2h * jtb);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mode convolution transpose: given the output adjoints Ob[m], add the
+// adjoints of A and B (see conv_acc for the forward sums)
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__device__ __forceinline__ void conv_bar(const cx<T>* A, const cx<T>* B, const cx<T>* Ob, T sign, cx<T>* Ab,
+                                         cx<T>* Bb) {
+    {
+        cx<T> o = sign * Ob[0];
+        // A0 B0
+        Ab[0] = Ab[0] + conj(B[0]) * o;
+        Bb[0] = Bb[0] + conj(A[0]) * o;
+        // 1/2 Re(A_k conj(B_k)) added to the real part
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            Ab[k] = Ab[k] + (T(0.5) * o.re) * B[k];
+            Bb[k] = Bb[k] + (T(0.5) * o.re) * A[k];
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+        cx<T> o = (sign * T(0.5)) * Ob[m];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                if (k + l == m) {           // A_k B_l
+                    Ab[k] = Ab[k] + conj(B[l]) * o;
+                    Bb[l] = Bb[l] + conj(A[k]) * o;
+                }
+                if (k - l == m) {           // A_k conj(B_l)
+                    Ab[k] = Ab[k] + B[l] * o;
+                    Bb[l] = Bb[l] + A[k] * conj(o);
+                }
+                if (l - k == m) {           // conj(A_k) B_l
+                    Ab[k] = Ab[k] + B[l] * conj(o);
+                    Bb[l] = Bb[l] + A[k] * o;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+struct AxBar {
+    AxionArgs<T> f;             // forward values
+    SetBar<T> A0b, B0b;         // adjoints of the background set, old / new
+    cx<T>* phiAb; cx<T>* tapAb; cx<T>* tamAb;
+    cx<T>* phiBb; cx<T>* tapBb; cx<T>* tamBb;
+    cx<T>* jaxb; cx<T>* jarb; cx<T>* jatb;
+    double* dLds;               // [2]: dL/ds_phi, dL/ds_j accumulated
+};
+
+// ---- adjoint of k_axion_phi
+template <typename T>
+__global__ void k_axion_phi_bar(AxBar<T> a) {
+    const Geo& g = a.f.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.nx || k >= g.nr) return;
+    const T h = T(g.h), dr = T(g.dr);
+    const bool live = g.per || i < g.nx - 1;
+    const T kap = (dr - h) / (dr + h);
+    for (int m = 0; m < g.M; ++m) {
+        cx<T> pb = ld(a.phiBb + g.at(m, k, i));
+        if (k == g.nr - 1) {
+            cx<T> Gb = ld(a.phiBb + g.at(m, g.nr, i));
+            if (g.open_r) {
+                if (live) {
+                    cadd(a.phiAb + g.at(m, k, i), Gb);
+                    cadd(a.phiAb + g.at(m, g.nr, i), kap * Gb);
+                    pb = pb - kap * Gb;
+                }
+            } else {
+                cadd(a.phiAb + g.at(m, g.nr, i), Gb);
+            }
+        }
+        if (live) {
+            cadd(a.phiAb + g.at(m, k, i), pb);
+            cx<T> q = (h / T(4)) * pb;
+            addx(a.tapBb, g, m, k, i, q);
+            addx(a.tapBb, g, m, k, i + 1, q);
+            addx(a.tamBb, g, m, k, i, q);
+            addx(a.tamBb, g, m, k, i + 1, q);
+        }
+    }
+}
+
+// block reduction of one double per thread into acc (one atomic per block)
+__device__ __forceinline__ void block_sum_add(double v, double* acc) {
+    __shared__ double red[256];
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    const int n = blockDim.x * blockDim.y;
+    red[t] = v;
+    __syncthreads();
+    for (int s = n / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0 && red[0] != 0.0) atomicAdd(acc, red[0]);
+}
+
+// ---- adjoint of k_axion_ta (S_a, Gamma_a, T_a shift)
+template <typename T, int M>
+__global__ void k_axion_ta_bar(AxBar<T> a) {
+    const Geo& g = a.f.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool inb = i < g.nx && k < g.nr;
+    double dsphi = 0.0;
+    if (inb) {
+        const T h = T(g.h), dr = T(g.dr);
+        const bool live = g.per || i < g.nx - 1;
+        const int ir = g.per ? (i + 1) % g.nx : i + 1;
+        const AxionArgs<T>& f = a.f;
+        cx<T> gab[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cx<T> tp = (ir < g.nx) ? ld(a.tapBb + g.at(m, k, ir)) : zero<T>();
+            cx<T> tm = ld(a.tamBb + g.at(m, k, i));
+            if (ir < g.nx) addx(a.tapAb, g, m, k, i, tp);
+            addx(a.tamAb, g, m, k, i + 1, tm);
+            gab[m] = h * (tp + tm);
+        }
+        if (live) {
+            const T rk = (T(k) + T(0.5)) * dr;
+            cx<T> Sb[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                cx<T> gb = gab[m];
+                // Gamma_a = Lap(phi) - (m^2/r^2 + m_a^2) phi + s_phi S
+                cadd(a.phiAb + g.at(m, k, i),
+                     (-T(2) / (dr * dr) - (T(m * m) / (rk * rk) + T(f.ma2))) * gb);
+                cx<T> cu = (T(1) / (dr * dr) + T(1) / (T(2) * dr * rk)) * gb;
+                if (k + 1 < g.nr) cadd(a.phiAb + g.at(m, k + 1, i), cu);
+                else if (g.open_r) cadd(a.phiAb + g.at(m, g.nr, i), cu);
+                if (k > 0) cadd(a.phiAb + g.at(m, k - 1, i), (T(1) / (dr * dr) - T(1) / (T(2) * dr * rk)) * gb);
+                Sb[m] = T(f.s_phi) * gb;
+            }
+            // recompute the forward source factors
+            cx<T> Ex[M], Bx[M], Er[M], Br[M], Et[M], Bt[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                Er[m] = T(0.5) * (er(f.A0, g, m, k, i) + er(f.A0, g, m, k, i + 1));
+                Bt[m] = T(0.5) * (bth(f.A0, g, m, k, i) + bth(f.A0, g, m, k, i + 1));
+                Et[m] = T(0.25) * (eth(f.A0, g, m, k, i) + eth(f.A0, g, m, k + 1, i) + eth(f.A0, g, m, k, i + 1) +
+                                   eth(f.A0, g, m, k + 1, i + 1));
+                Br[m] = T(0.25) * (brr(f.A0, g, m, k, i) + brr(f.A0, g, m, k + 1, i) + brr(f.A0, g, m, k, i + 1) +
+                                   brr(f.A0, g, m, k + 1, i + 1));
+                cx<T> e0 = T(0.5) * (ld(f.A0.ex + g.at(m, k, i)) + ld(f.B0.ex + g.at(m, k, i)));
+                cx<T> e1 = T(0.5) * (ld(f.A0.ex + g.at(m, k + 1, i)) + ld(f.B0.ex + g.at(m, k + 1, i)));
+                Ex[m] = T(0.5) * (e0 + e1);
+                Bx[m] = T(0.5) * (ld(f.A0.bx + g.at(m, k, i)) + ld(f.B0.bx + g.at(m, k, i)));
+            }
+            Bx[0] = Bx[0] + f.bx0;
+            if (M > 1) {
+                Br[1] = Br[1] + f.br1;
+                Bt[1] = Bt[1] + f.bt1;
+            }
+            if (a.dLds) {
+                cx<T> S[M];
+#pragma unroll
+                for (int m = 0; m < M; ++m) S[m] = zero<T>();
+                conv_acc<T, M>(Ex, Bx, T(1), S);
+                conv_acc<T, M>(Er, Br, T(1), S);
+                conv_acc<T, M>(Et, Bt, T(1), S);
+#pragma unroll
+                for (int m = 0; m < M; ++m) dsphi += double(gab[m].re * S[m].re + gab[m].im * S[m].im);
+            }
+            cx<T> Exb[M], Bxb[M], Erb[M], Brb[M], Etb[M], Btb[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) Exb[m] = Bxb[m] = Erb[m] = Brb[m] = Etb[m] = Btb[m] = zero<T>();
+            conv_bar<T, M>(Ex, Bx, Sb, T(1), Exb, Bxb);
+            conv_bar<T, M>(Er, Br, Sb, T(1), Erb, Brb);
+            conv_bar<T, M>(Et, Bt, Sb, T(1), Etb, Btb);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                add_er(a.A0b, g, m, k, i, T(0.5) * Erb[m]);
+                add_er(a.A0b, g, m, k, i + 1, T(0.5) * Erb[m]);
+                add_bth(a.A0b, g, m, k, i, T(0.5) * Btb[m]);
+                add_bth(a.A0b, g, m, k, i + 1, T(0.5) * Btb[m]);
+                cx<T> q = T(0.25) * Etb[m];
+                add_eth(a.A0b, g, m, k, i, q);
+                add_eth(a.A0b, g, m, k + 1, i, q);
+                add_eth(a.A0b, g, m, k, i + 1, q);
+                add_eth(a.A0b, g, m, k + 1, i + 1, q);
+                cx<T> r = T(0.25) * Brb[m];
+                add_brr(a.A0b, g, m, k, i, r);
+                add_brr(a.A0b, g, m, k + 1, i, r);
+                add_brr(a.A0b, g, m, k, i + 1, r);
+                add_brr(a.A0b, g, m, k + 1, i + 1, r);
+                cx<T> ex = T(0.25) * Exb[m];
+                cadd(a.A0b.ex + g.at(m, k, i), ex);
+                cadd(a.B0b.ex + g.at(m, k, i), ex);
+                cadd(a.A0b.ex + g.at(m, k + 1, i), ex);
+                cadd(a.B0b.ex + g.at(m, k + 1, i), ex);
+                cx<T> bx = T(0.5) * Bxb[m];
+                cadd(a.A0b.bx + g.at(m, k, i), bx);
+                cadd(a.B0b.bx + g.at(m, k, i), bx);
+            }
+        }
+    }
+    if (a.dLds) block_sum_add(dsphi, a.dLds);
+}
+
+// ---- adjoint of ja_factors: distribute the 18 factor adjoints of mode m
+template <typename T>
+__device__ void ja_factors_bar(const AxBar<T>& a, int m, int i, int j, const cx<T>* fb) {
+    const AxionArgs<T>& f = a.f;
+    const Geo& g = f.g;
+    const T dr = T(g.dr);
+    const int i1 = i + 1;
+    const bool ax = (j == 0);
+    const T rj = T(j) * dr;
+    const T rk = (T(j) + T(0.5)) * dr;
+    const T r_half = T(0.5) * dr;
+    const T par = parity<T>(m);
+    // d_t phi / d_x phi adjoint helpers: dto = (tapA + tamA)/2, dth = (tapB + tamB)/2,
+    // dxh = (tamB - tapB)/2
+    auto add_dto = [&](int k, int c, cx<T> v) {
+        addx(a.tapAb, g, m, k, c, T(0.5) * v);
+        addx(a.tamAb, g, m, k, c, T(0.5) * v);
+    };
+    auto add_dth = [&](int k, int c, cx<T> v) {
+        addx(a.tapBb, g, m, k, c, T(0.5) * v);
+        addx(a.tamBb, g, m, k, c, T(0.5) * v);
+    };
+    auto add_dxh = [&](int k, int c, cx<T> v) {
+        addx(a.tamBb, g, m, k, c, T(0.5) * v);
+        addx(a.tapBb, g, m, k, c, -(T(0.5) * v));
+    };
+    // ---------------- j_a,x
+    {
+        // f0 = (blo + bhi)/2, bhi = (A.bx + B.bx)(j)/2, blo = par bhi (axis) or (A.bx + B.bx)(j-1)/2
+        cx<T> hib = T(0.5) * fb[0], lob = T(0.5) * fb[0];
+        if (ax) hib = hib + par * lob;
+        cadd(a.A0b.bx + g.at(m, j, i), T(0.5) * hib);
+        cadd(a.B0b.bx + g.at(m, j, i), T(0.5) * hib);
+        if (!ax) {
+            cadd(a.A0b.bx + g.at(m, j - 1, i), T(0.5) * lob);
+            cadd(a.B0b.bx + g.at(m, j - 1, i), T(0.5) * lob);
+        }
+        // f1 = avg over columns of (l + d)/2, d = (dto + dth)/2 at row j, l at j-1 or par d
+        cx<T> q = T(0.25) * fb[1];   // weight of each of l0, d0, l1, d1
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int c = i + c2;
+            cx<T> db = q, lb = q;
+            if (ax) db = db + par * lb;
+            add_dto(j, c, T(0.5) * db);
+            add_dth(j, c, T(0.5) * db);
+            if (!ax) {
+                add_dto(j - 1, c, T(0.5) * lb);
+                add_dth(j - 1, c, T(0.5) * lb);
+            }
+        }
+        // f2 = avg of (g + e)/2 over columns, E_r with the axis reflection
+        const cx<T> q2 = T(0.25) * fb[2];
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int c = i + c2;
+            cx<T> eb = q2, gb = q2;
+            if (ax) {
+                eb = eb - gb;                                 // g = 2i E_th(0) - e  or  -e
+                if (m == 1) add_eth(a.A0b, g, 1, 0, c, imul_c(T(2), gb));
+            } else {
+                add_er(a.A0b, g, m, j - 1, c, gb);
+            }
+            add_er(a.A0b, g, m, j, c, eb);
+        }
+        // f3 = (d_theta phi)/r
+        {
+            cx<T> f3b = fb[3];
+            if (ax) {
+                if (m == 1) cadd(a.phiAb + g.at(m, j, i), imul_c(-T(1) / r_half, f3b));
+            } else {
+                cx<T> s = T(0.5) * imul_c(-T(m) / rj, f3b);
+                cadd(a.phiAb + g.at(m, j, i), s);
+                cadd(a.phiAb + g.at(m, j - 1, i), s);
+            }
+        }
+        // f4 = mean of E_theta(j) over the columns
+        add_eth(a.A0b, g, m, j, i, T(0.5) * fb[4]);
+        add_eth(a.A0b, g, m, j, i1, T(0.5) * fb[4]);
+        // f5 = (phi_hi - phi_lo)/dr
+        {
+            cx<T> s = (T(1) / dr) * fb[5];
+            cx<T> hib2 = s, lob2 = -s;
+            if (ax) hib2 = hib2 + par * lob2;
+            cadd(a.phiAb + g.at(m, j, i), hib2);
+            if (!ax) cadd(a.phiAb + g.at(m, j - 1, i), lob2);
+        }
+    }
+    // ---------------- j_a,theta
+    {
+        // f6: B_theta^{n+1/2} at (x_{i+1/2}, r_j): mean of (gb + b)/2 over columns,
+        // b = (Bt0 + Bt1)/2 at row j; gb at row j-1, or the reflection
+        cx<T> q = T(0.25) * fb[6];
+        cx<T> qe = T(0.25) * fb[10];
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int c = i + c2;
+            cx<T> bb = q, gbb = q, ebb = qe, gebb = qe;
+            if (ax) {
+                bb = bb - gbb;
+                ebb = ebb - gebb;
+                if (m == 1) {
+                    // gb = -2i br - b, br = (Br0 + Br1)(J=0)/2; ge = 2i et - e, et = (Et0 + Et1)(J=0)/2
+                    cx<T> brb = imul_c(-T(2), gbb);
+                    add_brr(a.A0b, g, 1, 0, c, T(0.5) * brb);
+                    add_brr(a.B0b, g, 1, 0, c, T(0.5) * brb);
+                    cx<T> etb = imul_c(T(2), gebb);
+                    add_eth(a.A0b, g, 1, 0, c, T(0.5) * etb);
+                    add_eth(a.B0b, g, 1, 0, c, T(0.5) * etb);
+                }
+            } else {
+                add_bth(a.A0b, g, m, j - 1, c, T(0.5) * gbb);
+                add_bth(a.B0b, g, m, j - 1, c, T(0.5) * gbb);
+                add_er(a.A0b, g, m, j - 1, c, T(0.5) * gebb);
+                add_er(a.B0b, g, m, j - 1, c, T(0.5) * gebb);
+            }
+            add_bth(a.A0b, g, m, j, c, T(0.5) * bb);
+            add_bth(a.B0b, g, m, j, c, T(0.5) * bb);
+            add_er(a.A0b, g, m, j, c, T(0.5) * ebb);
+            add_er(a.B0b, g, m, j, c, T(0.5) * ebb);
+        }
+        // f7 (d_t phi) and f11 (d_x phi) at t^{n+1/2}
+        cx<T> qt = T(0.25) * fb[7], qx = T(0.25) * fb[11];
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int c = i + c2;
+            cx<T> tb = qt, tlb = qt, xb = qx, xlb = qx;
+            if (ax) {
+                tb = tb + par * tlb;
+                xb = xb + par * xlb;
+            } else {
+                add_dth(j - 1, c, tlb);
+                add_dxh(j - 1, c, xlb);
+            }
+            add_dth(j, c, tb);
+            add_dxh(j, c, xb);
+        }
+        // f8 = E_x^{n+1/2}(j)
+        cadd(a.B0b.ex + g.at(m, j, i), fb[8]);
+        // f9 = (ph - pl)/dr, ph = (phiA + phiB)(j)/2
+        {
+            cx<T> s = (T(1) / dr) * fb[9];
+            cx<T> phb = s, plb = -s;
+            if (ax) phb = phb + par * plb;
+            cadd(a.phiAb + g.at(m, j, i), T(0.5) * phb);
+            cadd(a.phiBb + g.at(m, j, i), T(0.5) * phb);
+            if (!ax) {
+                cadd(a.phiAb + g.at(m, j - 1, i), T(0.5) * plb);
+                cadd(a.phiBb + g.at(m, j - 1, i), T(0.5) * plb);
+            }
+        }
+    }
+    // ---------------- j_a,r
+    {
+        cx<T> sb = T(0.25) * fb[12], se = T(0.25) * fb[14];
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                add_brr(a.A0b, g, m, j + dj, i + di, T(0.5) * sb);
+                add_brr(a.B0b, g, m, j + dj, i + di, T(0.5) * sb);
+                add_eth(a.A0b, g, m, j + dj, i + di, T(0.5) * se);
+                add_eth(a.B0b, g, m, j + dj, i + di, T(0.5) * se);
+            }
+        add_dth(j, i, T(0.5) * fb[13]);
+        add_dth(j, i1, T(0.5) * fb[13]);
+        add_dxh(j, i, T(0.5) * fb[15]);
+        add_dxh(j, i1, T(0.5) * fb[15]);
+        cadd(a.B0b.ex + g.at(m, j, i), T(0.5) * fb[16]);
+        cadd(a.B0b.ex + g.at(m, j + 1, i), T(0.5) * fb[16]);
+        cx<T> ph = imul_c(-T(m) / rk, fb[17]);
+        cadd(a.phiAb + g.at(m, j, i), T(0.5) * ph);
+        cadd(a.phiBb + g.at(m, j, i), T(0.5) * ph);
+    }
+}
+
+// ---- adjoint of k_axion_current
+template <typename T, int M>
+__global__ void k_axion_current_bar(AxBar<T> a) {
+    const Geo& g = a.f.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const bool inb = i < g.nx && j < g.nr;
+    double dsj = 0.0;
+    if (inb && (g.per || i < g.nx - 1)) {
+        const T sj = T(a.f.s_j);
+        cx<T> F[18][M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cx<T> f[18];
+            ja_factors(a.f, m, i, j, f);
+#pragma unroll
+            for (int q = 0; q < 18; ++q) F[q][m] = f[q];
+        }
+        cx<T> jxb[M], jtb[M], jrb[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            jxb[m] = ld(a.jaxb + g.at(m, j, i));
+            jtb[m] = ld(a.jatb + g.at(m, j, i));
+            jrb[m] = ld(a.jarb + g.at(m, j, i));
+        }
+        if (a.dLds) {
+            cx<T> jx[M], jt[M], jr[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) jx[m] = jt[m] = jr[m] = zero<T>();
+            conv_acc<T, M>(F[0], F[1], T(1), jx);
+            conv_acc<T, M>(F[2], F[3], T(-1), jx);
+            conv_acc<T, M>(F[4], F[5], T(1), jx);
+            conv_acc<T, M>(F[6], F[7], T(1), jt);
+            conv_acc<T, M>(F[8], F[9], T(-1), jt);
+            conv_acc<T, M>(F[10], F[11], T(1), jt);
+            conv_acc<T, M>(F[12], F[13], T(1), jr);
+            conv_acc<T, M>(F[14], F[15], T(-1), jr);
+            conv_acc<T, M>(F[16], F[17], T(1), jr);
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                dsj += double(jxb[m].re * jx[m].re + jxb[m].im * jx[m].im + jtb[m].re * jt[m].re +
+                              jtb[m].im * jt[m].im + jrb[m].re * jr[m].re + jrb[m].im * jr[m].im);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            jxb[m] = sj * jxb[m];
+            jtb[m] = sj * jtb[m];
+            jrb[m] = sj * jrb[m];
+        }
+        cx<T> Fb[18][M];
+#pragma unroll
+        for (int q = 0; q < 18; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) Fb[q][m] = zero<T>();
+        conv_bar<T, M>(F[0], F[1], jxb, T(1), Fb[0], Fb[1]);
+        conv_bar<T, M>(F[2], F[3], jxb, T(-1), Fb[2], Fb[3]);
+        conv_bar<T, M>(F[4], F[5], jxb, T(1), Fb[4], Fb[5]);
+        conv_bar<T, M>(F[6], F[7], jtb, T(1), Fb[6], Fb[7]);
+        conv_bar<T, M>(F[8], F[9], jtb, T(-1), Fb[8], Fb[9]);
+        conv_bar<T, M>(F[10], F[11], jtb, T(1), Fb[10], Fb[11]);
+        conv_bar<T, M>(F[12], F[13], jrb, T(1), Fb[12], Fb[13]);
+        conv_bar<T, M>(F[14], F[15], jrb, T(-1), Fb[14], Fb[15]);
+        conv_bar<T, M>(F[16], F[17], jrb, T(1), Fb[16], Fb[17]);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cx<T> fb[18];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) fb[q] = Fb[q][m];
+            ja_factors_bar(a, m, i, j, fb);
+        }
+    }
+    if (a.dLds) block_sum_add(dsj, a.dLds + 1);
+}
+
+}  // namespace adj
+
+// ---------------------------------------------------------------------------
+// host-side adjoint of one staged step
+// ---------------------------------------------------------------------------
+template <typename T>
+static adj::SetBar<T> setbar(cx<T>* const* P, int s) {
+    const int b = 9 * s;
+    return adj::SetBar<T>{P[b + 0], P[b + 1], P[b + 2], P[b + 3], P[b + 4], P[b + 5], P[b + 6], P[b + 7], P[b + 8]};
+}
+
+template <typename T>
+static adj::StageBar<T> stage_bar(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, int s) {
+    StageArgs<T> f = p.set_args(s);
+    adj::StageBar<T> a;
+    a.g = p.g;
+    a.A = f.A;
+    a.B = f.B;
+    a.Ab = setbar(Ab, s);
+    a.Bb = setbar(Bb, s);
+    a.jx_addb = s ? jab[0] : nullptr;
+    a.jr_addb = s ? jab[1] : nullptr;
+    a.jt_addb = s ? jab[2] : nullptr;
+    a.plasma = p.plasma;
+    a.wp2 = p.wp2;
+    return a;
+}
+
+template <typename T, int M>
+static void launch_axion_bar(adj::AxBar<T>& a, bool arem, hipStream_t s) {
+    const Geo& g = a.f.g;
+    dim3 blk(64, 4);
+    dim3 grdK((g.nx + 63) / 64, (g.nr + 3) / 4);
+    if (arem) hipLaunchKernelGGL((adj::k_axion_current_bar<T, M>), grdK, blk, 0, s, a);
+    hipLaunchKernelGGL(adj::k_axion_phi_bar<T>, grdK, blk, 0, s, a);
+    hipLaunchKernelGGL((adj::k_axion_ta_bar<T, M>), grdK, blk, 0, s, a);
+}
+
+template <typename T>
+hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
+                        hipStream_t s) {
+    const Geo& g = p.g;
+    dim3 blk(64, 4);
+    dim3 grdJ((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
+    dim3 grdG((g.nx + 255) / 256);
+    if (p.axion && p.arem) {
+        adj::StageBar<T> a1 = stage_bar(p, Ab, Bb, jab, 1);
+        hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a1);
+        hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a1);
+        hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a1);
+    }
+    if (p.axion) {
+        adj::AxBar<T> ax;
+        ax.f = p.axion_args();
+        ax.A0b = setbar(Ab, 0);
+        ax.B0b = setbar(Bb, 0);
+        ax.phiAb = Ab[18]; ax.tapAb = Ab[19]; ax.tamAb = Ab[20];
+        ax.phiBb = Bb[18]; ax.tapBb = Bb[19]; ax.tamBb = Bb[20];
+        ax.jaxb = jab[0]; ax.jarb = jab[1]; ax.jatb = jab[2];
+        ax.dLds = dLds;
+        switch (g.M) {
+#define QDS_AXB(MM) case MM: launch_axion_bar<T, MM>(ax, p.arem, s); break;
+            QDS_AXB(1) QDS_AXB(2) QDS_AXB(3) QDS_AXB(4)
+#undef QDS_AXB
+            default: return hipErrorInvalidValue;
+        }
+    }
+    adj::StageBar<T> a0 = stage_bar(p, Ab, Bb, jab, 0);
+    hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a0);
+    hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a0);
+    hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a0);
+    return hipGetLastError();
+}
+
+template hipError_t adjoint_step<double>(const StepPlan<double>&, cx<double>* const*, cx<double>* const*,
+                                         cx<double>* const*, double*, hipStream_t);
+template hipError_t adjoint_step<float>(const StepPlan<float>&, cx<float>* const*, cx<float>* const*,
+                                        cx<float>* const*, double*, hipStream_t);
+
+}  // namespace qds
+
+namespace qds {
+namespace adj {
+
+// Loss: energy of one mode of one set over the columns [x0, x1):
+//   L = w h dr [ sum_K r_{k+1/2} (|T_r^+|^2 + |T_r^-|^2)/4 + sum_J r'_j (|T_th^+|^2 + |T_th^-|^2)/4
+//              + sum_J r'_j |E_x|^2/2 + sum_K r_{k+1/2} |B_x|^2/2 ]
+// with w = 2 pi (mode 0) or pi, r'_0 = dr/8, r'_j = j dr.  Writes dL/du = 2 c u
+// into the adjoint buffer and adds L to *loss.
+template <typename T>
+__global__ void k_loss_seed(SetPtr<T> u, SetBar<T> ub, Geo g, int md, int x0, int x1, double* loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double acc = 0.0;
+    if (i >= x0 && i < x1 && i < g.nx && j <= g.nr) {
+        const double pi = 3.141592653589793;
+        const double w = (md == 0 ? 2.0 * pi : pi) * g.h * g.dr;
+        const double rk = (j + 0.5) * g.dr;
+        const double rj = j == 0 ? g.dr / 8.0 : j * g.dr;
+        auto one = [&](const cx<T>* p, cx<T>* pb, double c) {
+            const size_t e = g.at(md, j, i);
+            cx<T> v = ld(p + e);
+            acc += c * (double(v.re) * v.re + double(v.im) * v.im);
+            st(pb + e, T(2.0 * c) * v);
+        };
+        if (j < g.nr) {
+            one(u.trp, ub.trp, 0.25 * w * rk);
+            one(u.trm, ub.trm, 0.25 * w * rk);
+            one(u.bx, ub.bx, 0.5 * w * rk);
+        }
+        one(u.ttp, ub.ttp, 0.25 * w * rj);
+        one(u.ttm, ub.ttm, 0.25 * w * rj);
+        one(u.ex, ub.ex, 0.5 * w * rj);
+    }
+    block_sum_add(acc, loss);
+}
+
+// real inner product sum Re(conj(a) b) over n complex elements
+template <typename T>
+__global__ void k_dot(const cx<T>* a, const cx<T>* b, size_t n, double* out) {
+    double acc = 0.0;
+    for (size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += size_t(gridDim.x) * blockDim.x) {
+        cx<T> x = ld(a + q), y = ld(b + q);
+        acc += double(x.re) * y.re + double(x.im) * y.im;
+    }
+    block_sum_add(acc, out);
+}
+
+}  // namespace adj
+
+template <typename T>
+hipError_t loss_seed(cx<T>* const* U, cx<T>* const* Ub, const Geo& g, int set, int md, int x0, int x1, double* loss,
+                     hipStream_t s) {
+    const int b = 9 * set;
+    SetPtr<T> u{U[b + 0], U[b + 1], U[b + 2], U[b + 3], U[b + 4], U[b + 5], U[b + 6], U[b + 7], U[b + 8]};
+    adj::SetBar<T> ub{Ub[b + 0], Ub[b + 1], Ub[b + 2], Ub[b + 3], Ub[b + 4], Ub[b + 5], Ub[b + 6], Ub[b + 7], Ub[b + 8]};
+    dim3 blk(64, 4);
+    dim3 grd((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
+    hipLaunchKernelGGL(adj::k_loss_seed<T>, grd, blk, 0, s, u, ub, g, md, x0, x1, loss);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dot(const void* a, const void* b, size_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(adj::k_dot<T>, dim3(1024), dim3(256), 0, s, static_cast<const cx<T>*>(a),
+                       static_cast<const cx<T>*>(b), n, out);
+    return hipGetLastError();
+}
+
+template hipError_t loss_seed<double>(cx<double>* const*, cx<double>* const*, const Geo&, int, int, int, int, double*,
+                                      hipStream_t);
+template hipError_t loss_seed<float>(cx<float>* const*, cx<float>* const*, const Geo&, int, int, int, int, double*,
+                                     hipStream_t);
+template hipError_t dot<double>(const void*, const void*, size_t, double*, hipStream_t);
+template hipError_t dot<float>(const void*, const void*, size_t, double*, hipStream_t);
+
+}  // namespace qds

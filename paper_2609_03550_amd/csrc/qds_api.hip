@@ -160,8 +160,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
 }
 
 template <typename T>
-qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
-                     hipStream_t s) {
+qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axion* ax) {
     qds::StepPlan<T> p;
     p.g = geo(c);
     p.plasma = has(c, QDS_P_JX);
@@ -180,12 +179,17 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
         p.drive.amp = J->amp; p.drive.x0 = J->x0; p.drive.v = J->v; p.drive.sx = J->sx;
         p.drive.r0 = J->r0; p.drive.sr = J->sr; p.drive.noise = J->noise; p.drive.seed = J->seed;
     }
-    qds::cx<T>* scr[3] = {nullptr, nullptr, nullptr};
-    if (c->scratch) {
-        for (int k = 0; k < 3; ++k)
-            scr[k] = reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) + size_t(k) * c->plane_elems * c->elem_bytes);
-    }
-    for (int k = 0; k < 3; ++k) p.ja[k] = scr[k];
+    for (int k = 0; k < 3; ++k)
+        p.ja[k] = c->scratch ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) +
+                                                              size_t(k) * c->plane_elems * c->elem_bytes)
+                             : nullptr;
+    return p;
+}
+
+template <typename T>
+qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
+                     hipStream_t s) {
+    qds::StepPlan<T> p = make_plan<T>(c, J, ax);
     if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
@@ -213,6 +217,103 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
     return QDS_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// adjoint driver: forward with checkpoints every C steps, loss seed, then per
+// segment (last first) recompute the states and run the transposed steps
+// ---------------------------------------------------------------------------
+size_t backward_pool_bytes(const qds_ctx* c, int64_t n, int64_t C) {
+    const size_t S = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+    const size_t P = c->plane_elems * c->elem_bytes;
+    const size_t nck = size_t((n + C - 1) / C);
+    return (nck + size_t(C) + 1 + 2) * S + 3 * P + 256;
+}
+
+template <typename T>
+qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, const qds_axion* ax,
+                         const qds_loss* L, int64_t N, int64_t C, void* pool, void* lambda0, double* dLds_out,
+                         double* loss_out, hipStream_t s) {
+    const size_t S = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+    const size_t P = c->plane_elems * c->elem_bytes;
+    const size_t nck = size_t((N + C - 1) / C);
+    char* base = static_cast<char*>(pool);
+    char* ck = base;
+    char* seg = ck + nck * S;
+    char* adjX = seg + size_t(C + 1) * S;
+    char* adjY = adjX + S;
+    char* jab = adjY + S;
+    double* red = reinterpret_cast<double*>(jab + 3 * P);
+    auto at_seg = [&](int64_t k) { return static_cast<void*>(seg + size_t(k) * S); };
+    hipError_t e = hipSuccess;
+#define QDS_TRY(x)                                                                        \
+    do {                                                                                  \
+        e = (x);                                                                          \
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "backward: %s", hipGetErrorString(e)); \
+    } while (0)
+    QDS_TRY(hipMemsetAsync(red, 0, 4 * sizeof(double), s));
+    // forward with checkpoints (two work buffers at the start of the segment area)
+    qds_state W;
+    W.buf[0] = at_seg(0);
+    W.buf[1] = at_seg(1);
+    W.cur = 0;
+    W.step = u0->step;
+    W.window = 0;
+    QDS_TRY(hipMemcpyAsync(W.buf[0], u0->buf[u0->cur], S, hipMemcpyDeviceToDevice, s));
+    for (int64_t n = 0; n < N; ++n) {
+        if (n % C == 0) QDS_TRY(hipMemcpyAsync(ck + size_t(n / C) * S, W.buf[W.cur], S, hipMemcpyDeviceToDevice, s));
+        qds_status st = run_steps<T>(c, &W, J, ax, 1, s);
+        if (st != QDS_OK) return st;
+    }
+    // loss and its gradient at step N
+    qds::cx<T>* U[QDS_NPLANES];
+    qds::cx<T>* Yb[QDS_NPLANES];
+    qds::cx<T>* Xb[QDS_NPLANES];
+    plane_table<T>(c, W.buf[W.cur], U);
+    QDS_TRY(hipMemsetAsync(adjY, 0, S, s));
+    plane_table<T>(c, adjY, Yb);
+    QDS_TRY(qds::loss_seed<T>(U, Yb, geo(c), L->set, L->mode, L->x_begin, L->x_end, red, s));
+    // reverse sweep over the segments
+    qds::StepPlan<T> p = make_plan<T>(c, J, ax);
+    qds::cx<T>* jb[3];
+    for (int k = 0; k < 3; ++k) jb[k] = reinterpret_cast<qds::cx<T>*>(jab + size_t(k) * P);
+    for (int64_t sg = int64_t(nck) - 1; sg >= 0; --sg) {
+        const int64_t n0 = sg * C, n1 = (n0 + C < N) ? n0 + C : N;
+        QDS_TRY(hipMemcpyAsync(at_seg(0), ck + size_t(sg) * S, S, hipMemcpyDeviceToDevice, s));
+        for (int64_t k = 0; k < n1 - n0; ++k) {
+            qds_state R;
+            R.buf[0] = at_seg(k);
+            R.buf[1] = at_seg(k + 1);
+            R.cur = 0;
+            R.step = u0->step + n0 + k;
+            R.window = 0;
+            qds_status st = run_steps<T>(c, &R, J, ax, 1, s);
+            if (st != QDS_OK) return st;
+        }
+        for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
+            plane_table<T>(c, at_seg(k), p.A);
+            plane_table<T>(c, at_seg(k + 1), p.B);
+            p.n = u0->step + n0 + k;
+            p.w = 0;
+            QDS_TRY(hipMemsetAsync(adjX, 0, S, s));
+            QDS_TRY(hipMemsetAsync(jab, 0, 3 * P, s));
+            plane_table<T>(c, adjX, Xb);
+            plane_table<T>(c, adjY, Yb);
+            QDS_TRY(qds::adjoint_step<T>(p, Xb, Yb, jb, red + 1, s));
+            char* t = adjX; adjX = adjY; adjY = t;
+        }
+    }
+    QDS_TRY(hipMemcpyAsync(lambda0, adjY, S, hipMemcpyDeviceToDevice, s));
+    double host[4];
+    QDS_TRY(hipMemcpyAsync(host, red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QDS_TRY(hipStreamSynchronize(s));
+#undef QDS_TRY
+    if (loss_out) *loss_out = host[0];
+    if (dLds_out) {
+        dLds_out[0] = host[1];
+        dLds_out[1] = host[2];
+    }
+    return QDS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -376,6 +477,47 @@ qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches) {
 }
 
 int32_t qds_uses_fused(qds_handle h) { return h && use_fused(h) ? 1 : 0; }
+
+
+size_t qds_backward_pool_bytes(qds_handle h, int64_t n_steps, int64_t ckpt_every) {
+    if (!h || n_steps < 1 || ckpt_every < 1) return 0;
+    return backward_pool_bytes(h, n_steps, ckpt_every);
+}
+
+qds_status qds_backward(qds_handle h, const qds_state* u0, const qds_current* J, const qds_axion* axion,
+                        const qds_loss* loss, int64_t n_steps, int64_t ckpt_every, void* ckpt_pool,
+                        size_t pool_bytes, void* lambda0_out, double* dL_ds_out, double* loss_out, void* stream) {
+    if (!h) return fail(nullptr, QDS_EINVAL, "null handle%s");
+    qds_status s = check_state(h, u0);
+    if (s != QDS_OK) return s;
+    if (!loss || !ckpt_pool || !lambda0_out) return fail(h, QDS_EINVAL, "null argument%s");
+    if (n_steps < 1 || ckpt_every < 1) return fail(h, QDS_EINVAL, "n_steps and ckpt_every must be >= 1%s");
+    if (h->g.x_bc == QDS_X_WINDOW) return fail(h, QDS_EUNSUPPORTED, "the adjoint does not cover the moving window%s");
+    if (h->M > 4) return fail(h, QDS_EUNSUPPORTED, "the adjoint covers up to 4 modes%s");
+    if (loss->set < 0 || loss->set > 1 || (loss->set == 1 && !has(h, QDS_P_SET1)))
+        return fail(h, QDS_EINVAL, "loss set not in the state%s");
+    if (loss->mode < 0 || loss->mode >= h->M) return fail(h, QDS_EINVAL, "loss mode out of range%s");
+    if (loss->x_begin < 0 || loss->x_end > h->g.nx || loss->x_begin >= loss->x_end)
+        return fail(h, QDS_EINVAL, "loss column range must satisfy 0 <= x_begin < x_end <= nx%s");
+    if (J && J->kind != QDS_J_NONE) return fail(h, QDS_EUNSUPPORTED, "the adjoint has no prescribed drive%s");
+    if (pool_bytes < backward_pool_bytes(h, n_steps, ckpt_every))
+        return fail(h, QDS_EINVAL, "checkpoint pool too small (see qds_backward_pool_bytes)%s");
+    if (u0->step + n_steps >= (int64_t(1) << 31)) return fail(h, QDS_ESTATE, "step counter would overflow%s");
+    if (h->g.dtype == QDS_F64)
+        return backward_impl<double>(h, u0, J, axion, loss, n_steps, ckpt_every, ckpt_pool, lambda0_out, dL_ds_out,
+                                     loss_out, hipStream_t(stream));
+    return backward_impl<float>(h, u0, J, axion, loss, n_steps, ckpt_every, ckpt_pool, lambda0_out, dL_ds_out,
+                                loss_out, hipStream_t(stream));
+}
+
+qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream) {
+    if (!h || !a || !b || !out_dev) return fail(h, QDS_EINVAL, "null argument%s");
+    const size_t n = size_t(h->nplanes) * h->plane_elems;
+    hipError_t e = h->g.dtype == QDS_F64 ? qds::dot<double>(a, b, n, out_dev, hipStream_t(stream))
+                                         : qds::dot<float>(a, b, n, out_dev, hipStream_t(stream));
+    if (e != hipSuccess) return fail(h, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    return QDS_OK;
+}
 
 qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;

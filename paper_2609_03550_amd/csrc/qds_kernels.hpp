@@ -143,6 +143,13 @@ struct FusedArgs {
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
 template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
 template <typename T> hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
+                        hipStream_t s);
+template <typename T>
+hipError_t loss_seed(cx<T>* const* U, cx<T>* const* Ub, const Geo& g, int set, int md, int x0, int x1, double* loss,
+                     hipStream_t s);
+template <typename T> hipError_t dot(const void* a, const void* b, size_t n, double* out, hipStream_t s);
 template <typename T> hipError_t window_shift(const cx<T>* src, cx<T>* dst, const Geo& g, int nplanes, hipStream_t s);
 template <typename T>
 hipError_t add_pulse(SetPtr<T> s0, const Geo& g, int pol, const double* fK, const double* fJ, const double* fG,

@@ -50,6 +50,11 @@ class Axion(ctypes.Structure):
                 ("bext", ctypes.c_double * 6)]
 
 
+class Loss(ctypes.Structure):
+    _fields_ = [("set", ctypes.c_int32), ("mode", ctypes.c_int32), ("x_begin", ctypes.c_int32),
+                ("x_end", ctypes.c_int32)]
+
+
 class State(ctypes.Structure):
     _fields_ = [("buf", ctypes.c_void_p * 2), ("cur", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("step", ctypes.c_int64), ("window", ctypes.c_int64)]
@@ -84,6 +89,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_get_timing.restype = i32
     lib.qds_uses_fused.argtypes = [vp]
     lib.qds_uses_fused.restype = i32
+    lib.qds_backward_pool_bytes.argtypes = [vp, i64, i64]
+    lib.qds_backward_pool_bytes.restype = ctypes.c_size_t
+    lib.qds_backward.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion),
+                                 ctypes.POINTER(Loss), i64, i64, vp, ctypes.c_size_t, vp,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.qds_backward.restype = i32
+    lib.qds_dot.argtypes = [vp, vp, vp, vp, vp]
+    lib.qds_dot.restype = i32
     return lib
 
 
@@ -258,6 +271,45 @@ class Solver:
             out["Tap"] = self.plane(P_TAP)[:, :nr]
             out["Tam"] = self.plane(P_TAM)[:, :nr]
         return {k: v.to("cpu", torch.complex128) for k, v in out.items()}
+
+    # -- adjoint ------------------------------------------------------------
+    def backward(self, n_steps: int, ckpt_every: int, loss_set: int = 1, loss_mode: int = 1,
+                 x_begin: Optional[int] = None, x_end: Optional[int] = None, stream=None):
+        """Gradient of the loss (energy of mode ``loss_mode`` of set ``loss_set``
+        over columns [x_begin, x_end) after ``n_steps``) with respect to the
+        current state, by the library's adjoint with checkpoints every
+        ``ckpt_every`` steps.  Returns (loss, lambda0 buffer, (dL/ds_phi, dL/ds_j));
+        the state itself is not advanced."""
+        wl = self.wl
+        lo = Loss(loss_set, loss_mode, max(0, wl.nx - 256) if x_begin is None else x_begin,
+                  wl.nx if x_end is None else x_end)
+        nbytes = int(lib().qds_backward_pool_bytes(self.h, n_steps, ckpt_every))
+        pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        lam = torch.zeros(self.nbytes, dtype=torch.uint8, device=self.device)
+        dlds = (ctypes.c_double * 2)()
+        loss = ctypes.c_double()
+        cur = Current()
+        ctypes.memmove(ctypes.byref(cur), ctypes.byref(self.cur), ctypes.sizeof(Current))
+        _check(lib().qds_backward(self.h, ctypes.byref(self.state), ctypes.byref(cur), ctypes.byref(self.ax),
+                                  ctypes.byref(lo), int(n_steps), int(ckpt_every), pool.data_ptr(), nbytes,
+                                  lam.data_ptr(), dlds, ctypes.byref(loss), _stream_ptr(stream)), self.h)
+        del pool
+        return loss.value, lam, (dlds[0], dlds[1])
+
+    def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
+        """Re sum conj(a) b over two state buffers (device reduction)."""
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(lib().qds_dot(self.h, a.data_ptr(), b.data_ptr(), out.data_ptr(), _stream_ptr()), self.h)
+        return float(out.item())
+
+    def buffer_fields(self, buf: torch.Tensor) -> Dict[str, torch.Tensor]:
+        """Named complex128 CPU views of an arbitrary state-layout buffer."""
+        saved = self.bufs[self.state.cur]
+        self.bufs[self.state.cur] = buf
+        try:
+            return self.fields()
+        finally:
+            self.bufs[self.state.cur] = saved
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None and self.h.value:

@@ -103,3 +103,23 @@ def axion_energy(st, g):
     dphi = (st["phi"][:, 1:] - st["phi"][:, :-1]) / g.dr
     u = u + (0.5 * dphi.abs() ** 2 * rJ * g.dr * w).sum()
     return u.item()
+
+
+def loss_energy(st, g, s=1, mode=1, x0=None, x1=None):
+    """Energy of one mode of set s over columns [x0, x1): transverse fields at
+    t^N, E_x and B_x at t^{N-1/2}, mode weight 2 pi (m=0) or pi, area r dr
+    (axis row dr^2/8), times dx.  A differentiable torch scalar."""
+    x0 = max(0, g.nx - 256) if x0 is None else x0
+    x1 = g.nx if x1 is None else x1
+    w = (2 * math.pi if mode == 0 else math.pi) * g.h * g.dr
+    rK = ((torch.arange(g.nr, dtype=torch.float64) + 0.5) * g.dr).view(-1, 1)
+    rJ = (torch.arange(g.nr + 1, dtype=torch.float64) * g.dr).clone()
+    rJ[0] = g.dr / 8
+    rJ = rJ.view(-1, 1)
+    sl = slice(x0, x1)
+    e = lambda t: (t.real ** 2 + t.imag ** 2)
+    L = (0.25 * (e(st[f"Trp{s}"][mode, :, sl]) + e(st[f"Trm{s}"][mode, :, sl])) * rK).sum()
+    L = L + (0.25 * (e(st[f"Ttp{s}"][mode, :, sl]) + e(st[f"Ttm{s}"][mode, :, sl])) * rJ).sum()
+    L = L + (0.5 * e(st[f"Ex{s}"][mode, :, sl]) * rJ).sum()
+    L = L + (0.5 * e(st[f"Bx{s}"][mode, : g.nr, sl]) * rK).sum()
+    return w * L

@@ -421,3 +421,42 @@ def test_box_muller_normals_have_unit_variance():
     assert abs(z.mean()) < 6e-3
     assert abs(z.var() - 1) < 1e-2
     assert abs((z ** 4).mean() - 3) < 5e-2
+
+
+# ---------------------------------------------------------------------------
+# the oracle's gradient (reference of the GPU adjoint)
+# ---------------------------------------------------------------------------
+
+def test_oracle_autograd_matches_finite_differences():
+    """Autograd through the oracle, projected on an envelope-coefficient
+    direction (the initial state is linear in the coefficients), equals the
+    central difference of the oracle loss."""
+    coeffs = tuple(float(c) for c in 0.02 * torch.randn(8, generator=torch.Generator().manual_seed(5),
+                                                          dtype=torch.float64))
+    fw = 10 * H
+    p1 = I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, fw, 0.45 * 44 * H, coeffs=coeffs, period=4 * fw)
+    p2 = I.Pulse("z", 0.5, 0.8, 2 * I.LAMBDA, fw, 0.45 * 44 * H)
+    wl = I.Workload("a", 44, 8, 2, 0, wp2=0.02, axion=True, arem=True, ma2=0.03, pulses=(p1, p2),
+                    bext=(0.05 + 0j, 0.1 + 0.02j, -0.02 + 0.1j))
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    leaves = {}
+    for k, v in list(st.items()):
+        if isinstance(v, torch.Tensor):
+            v = v.detach().clone().requires_grad_(True)
+            st[k] = v
+            leaves[k] = v
+    L = T.loss_energy(Q.run(st, g, ph, 8), g, 1, 1)
+    L.backward()
+    for q in (0, 3):
+        b = Q.init_state(wl, basis=(0, q))
+        grad = sum(float((leaves[k].grad.conj() * b[k]).real.sum()) for k in leaves if leaves[k].grad is not None)
+        vals = []
+        for sg in (1, -1):
+            c2 = list(coeffs)
+            c2[q] += sg * 1e-6
+            w2 = wl.with_(pulses=(I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, fw, 0.45 * 44 * H, coeffs=tuple(c2),
+                                          period=4 * fw), p2))
+            vals.append(float(T.loss_energy(Q.run(Q.init_state(w2), g, ph, 8), g, 1, 1)))
+        fd = (vals[0] - vals[1]) / 2e-6
+        assert abs(grad - fd) <= 1e-6 * abs(fd)
