@@ -79,6 +79,35 @@ def measured_traffic(wl, dtype, launches_cells):
     return d.get("hbm_bytes_per_launch")
 
 
+def adjoint_ratio(dtype, steps, ckpt):
+    """Forward + adjoint against forward alone on the 4096 x 128 x 2-mode axion
+    workload: wall time of qds_backward over ``steps`` steps (its checkpointed
+    forward sweep, the recomputation of each segment and the adjoint steps, the
+    loss being the regenerated mode-1 energy over the last 256 columns) divided
+    by the time of ``steps`` plain forward steps from the same initial state."""
+    import torch
+    from paper_2609_03550_amd import inputs as I
+    from paper_2609_03550_amd import qds
+    wl = I.adjoint_workload(steps=steps)
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_pulses()
+    f = qds.Solver(wl, dtype=dtype)
+    f.load_pulses()
+    f.step(5)
+    s.backward(20, 5)               # warm both paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L, lam, _ = s.backward(steps, ckpt)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    return {"workload": wl.name, "steps": steps, "ckpt_every": ckpt, "dtype": dtype, "fwd_s": t_fwd,
+            "fwd_adj_s": t_adj, "ratio": t_adj / t_fwd, "loss": L}
+
+
 def cpu_baseline(wl, seconds_target=15.0):
     """The FP64 oracle on this host: whole-grid steps of the same workload
     until about ``seconds_target`` of CPU work, extrapolated per update."""
@@ -109,6 +138,9 @@ def main():
     ap.add_argument("--path", type=int, default=0, help="0 auto (fused), 1 staged, 2 fused")
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the forward + adjoint timing (0 skips it)")
+    ap.add_argument("--ckpt-every", type=int, default=45)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM counters)")
     args = ap.parse_args()
@@ -192,6 +224,12 @@ def main():
                         for q in range(3) if kn[q] and s.fused},
         "fwd_adj_over_fwd": None,
     }
+    del s
+    torch.cuda.empty_cache()
+    if args.adjoint_steps > 0:
+        adj = adjoint_ratio(args.dtype, args.adjoint_steps, args.ckpt_every)
+        out["fwd_adj_over_fwd"] = adj["ratio"]
+        out["adjoint"] = adj
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -195,6 +195,13 @@ qds_status qds_backward(qds_handle h, const qds_state* u0, const qds_current* J,
                         const qds_loss* loss, int64_t n_steps, int64_t ckpt_every, void* ckpt_pool,
                         size_t pool_bytes, void* lambda0_out, double* dL_ds_out, double* loss_out, void* stream);
 
+/* Adds the loss of qds_backward evaluated on the state buffer buf to *out_dev
+ * (a device double) and writes its gradient dL/du into grad_buf (a state
+ * buffer; entries outside the loss are left untouched), or into a temporary
+ * stream-ordered allocation when grad_buf is NULL. */
+qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, double* out_dev, void* grad_buf,
+                         void* stream);
+
 /* Adds Re sum conj(a) b over two state buffers to *out_dev (a device double). */
 qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream);
 

@@ -519,6 +519,45 @@ qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, 
     return QDS_OK;
 }
 
+
+qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, double* out_dev, void* grad_buf,
+                         void* stream) {
+    if (!h || !buf || !loss || !out_dev) return fail(h, QDS_EINVAL, "null argument%s");
+    if (loss->set < 0 || loss->set > 1 || (loss->set == 1 && !has(h, QDS_P_SET1)))
+        return fail(h, QDS_EINVAL, "loss set not in the state%s");
+    if (loss->mode < 0 || loss->mode >= h->M) return fail(h, QDS_EINVAL, "loss mode out of range%s");
+    if (loss->x_begin < 0 || loss->x_end > h->g.nx || loss->x_begin >= loss->x_end)
+        return fail(h, QDS_EINVAL, "loss column range must satisfy 0 <= x_begin < x_end <= nx%s");
+    hipError_t e;
+    const size_t S = size_t(h->nplanes) * h->plane_elems * h->elem_bytes;
+    if (!grad_buf) {
+        // a scratch gradient buffer is needed by the seed kernel
+        void* tmp = nullptr;
+        if (hipMallocAsync(&tmp, S, hipStream_t(stream)) != hipSuccess) return fail(h, QDS_ENOMEM, "no memory%s");
+        grad_buf = tmp;
+        qds_status st = qds_loss_eval(h, buf, loss, out_dev, grad_buf, stream);
+        hipFreeAsync(tmp, hipStream_t(stream));
+        return st;
+    }
+    if (h->g.dtype == QDS_F64) {
+        qds::cx<double>* U[QDS_NPLANES];
+        qds::cx<double>* G[QDS_NPLANES];
+        plane_table<double>(h, const_cast<void*>(buf), U);
+        plane_table<double>(h, grad_buf, G);
+        e = qds::loss_seed<double>(U, G, geo(h), loss->set, loss->mode, loss->x_begin, loss->x_end, out_dev,
+                                   hipStream_t(stream));
+    } else {
+        qds::cx<float>* U[QDS_NPLANES];
+        qds::cx<float>* G[QDS_NPLANES];
+        plane_table<float>(h, const_cast<void*>(buf), U);
+        plane_table<float>(h, grad_buf, G);
+        e = qds::loss_seed<float>(U, G, geo(h), loss->set, loss->mode, loss->x_begin, loss->x_end, out_dev,
+                                  hipStream_t(stream));
+    }
+    if (e != hipSuccess) return fail(h, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    return QDS_OK;
+}
+
 qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
     for (hipEvent_t e : h->pool) hipEventDestroy(e);

@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_backward.restype = i32
     lib.qds_dot.argtypes = [vp, vp, vp, vp, vp]
     lib.qds_dot.restype = i32
+    lib.qds_loss_eval.argtypes = [vp, vp, ctypes.POINTER(Loss), vp, vp, vp]
+    lib.qds_loss_eval.restype = i32
     return lib
 
 
@@ -295,6 +297,18 @@ class Solver:
                                   lam.data_ptr(), dlds, ctypes.byref(loss), _stream_ptr(stream)), self.h)
         del pool
         return loss.value, lam, (dlds[0], dlds[1])
+
+    def loss(self, loss_set: int = 1, loss_mode: int = 1, x_begin: Optional[int] = None,
+             x_end: Optional[int] = None) -> float:
+        """The backward loss evaluated on the current state (device reduction)."""
+        wl = self.wl
+        lo = Loss(loss_set, loss_mode, max(0, wl.nx - 256) if x_begin is None else x_begin,
+                  wl.nx if x_end is None else x_end)
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
+        grad = torch.zeros(self.nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib().qds_loss_eval(self.h, self.bufs[self.state.cur].data_ptr(), ctypes.byref(lo), out.data_ptr(),
+                                   grad.data_ptr(), _stream_ptr()), self.h)
+        return float(out.item())
 
     def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
         """Re sum conj(a) b over two state buffers (device reduction)."""

@@ -142,3 +142,50 @@ def test_envelope_coefficient_gradients_match_finite_differences():
             vals.append(float(T.loss_energy(st, g, 1, 1)))
         fd = (vals[0] - vals[1]) / (2 * hstep)
         assert abs(grad - fd) <= 1e-5 * abs(fd) + 1e-12 * abs(L), (q, grad, fd)
+
+
+def test_loss_eval_matches_oracle_loss():
+    from paper_2609_03550_amd import qds
+    wl = _full(40, 8, 3)
+    s = qds.Solver(wl)
+    s.load_pulses()
+    s.step(7)
+    torch.cuda.synchronize()
+    g, ph = Q.grid_physics(wl)
+    st = Q.run(Q.init_state(wl), g, ph, 7)
+    for lset, lmode, x0, x1 in ((1, 1, None, None), (0, 1, 3, 29), (1, 0, 0, 40), (1, 2, 5, 40)):
+        L = s.loss(lset, lmode, x0, x1)
+        Lo = float(T.loss_energy(st, g, lset, lmode, x0, x1))
+        assert Lo > 0 and abs(L / Lo - 1) < 1e-12, (lset, lmode, L, Lo)
+
+
+def test_autograd_function_gradients():
+    """EnvelopeLoss: L(c, g) = g^4 L_hat(c); dL/dc against central differences of
+    the oracle, dL/dg = 4 L / g."""
+    from paper_2609_03550_amd.autograd import EnvelopeLoss
+    rng = torch.Generator().manual_seed(7)
+    c0 = 0.02 * torch.randn(6, generator=rng, dtype=torch.float64)
+    fw = 10 * H
+    base = _full(44, 8, 2)
+    p1 = I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, fw, 0.45 * 44 * H, coeffs=tuple(c0.tolist()), period=4 * fw)
+    wl = base.with_(pulses=(p1, base.pulses[1]))
+    c = c0.clone().requires_grad_(True)
+    gc = torch.tensor(1e-3, dtype=torch.float64, requires_grad=True)
+    L = EnvelopeLoss.apply(c, gc, wl, 8, 3)
+    L.backward()
+    gq, ph = Q.grid_physics(wl)
+    st = Q.run(Q.init_state(wl), gq, ph, 8)
+    L_hat = float(T.loss_energy(st, gq, 1, 1))
+    assert abs(float(L) / (1e-12 * L_hat) - 1) < 1e-12
+    assert abs(float(gc.grad) / (4 * float(L) / 1e-3) - 1) < 1e-12
+    hstep = 1e-6
+    for q in (0, 2, 5):
+        vals = []
+        for sgn in (1, -1):
+            c2 = c0.clone()
+            c2[q] += sgn * hstep
+            p2 = I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, fw, 0.45 * 44 * H, coeffs=tuple(c2.tolist()), period=4 * fw)
+            w2 = wl.with_(pulses=(p2, wl.pulses[1]))
+            vals.append(float(T.loss_energy(Q.run(Q.init_state(w2), gq, ph, 8), gq, 1, 1)))
+        fd = 1e-12 * (vals[0] - vals[1]) / (2 * hstep)
+        assert abs(float(c.grad[q]) - fd) <= 1e-5 * abs(fd) + 1e-12 * float(L), (q, float(c.grad[q]), fd)
