@@ -206,6 +206,57 @@ qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, do
 qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream);
 
 qds_status qds_destroy(qds_handle h);
+
+/* ---------------------------------------------------------------------------
+ * Batched forward: many independent instances (each its own handle, grid,
+ * mode count and state) advanced together.  Every step of the batch is one
+ * launch per kernel class covering the tiles of all instances still running
+ * (kernel A per mode count, the axion current per mode count, the
+ * regenerated set), and up to graph_steps such steps are captured in one HIP
+ * graph and launched as one.  The per-step update of each instance is
+ * exactly that of qds_step on the fused kernels (Sec. 2 scheme per instance).
+ * --------------------------------------------------------------------------- */
+typedef struct qds_batch_ctx* qds_batch;
+
+/* Tile slots: radial rows per workgroup of each batched kernel class. */
+enum {
+    QDS_TILE_A1 = 0,        /* kernel A (background set + axion), 1..4 modes: slots 0..3 */
+    QDS_TILE_CUR1 = 4,      /* axion current, 1..4 modes: slots 4..7 (rows per workgroup) */
+    QDS_TILE_EM0 = 8,       /* background set without the axion */
+    QDS_TILE_EM1 = 9,       /* regenerated set (kernel B) */
+    QDS_NTILES = 10
+};
+
+/* Groups ``count`` handles (1..4096, all distinct, one dtype, each able to
+ * run the fused kernels: at most 4 modes, no moving window).  The handles
+ * stay owned by the caller and must outlive the batch. */
+qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch* out);
+
+/* Advances instance k by n_steps[k] >= 0 steps.  states[count]: one state per
+ * instance (caller-owned device buffers, updated: cur and step); J[count]:
+ * per-instance currents (NULL = none; only the cold-plasma response, kind
+ * QDS_J_NONE, is accepted); axion[count]: per-instance axion parameters (may
+ * be NULL when no instance has the axion).  graph_steps >= 1 captures up to
+ * that many steps per HIP graph (graphs are kept for replay while the set of
+ * running instances is unchanged); 0 launches the kernels directly.  With
+ * tune != 0 and no tiles chosen yet, the autotuner times the first steps of
+ * the run (two passes over the candidate tilings, 8 steps; only when every
+ * running instance has that many steps left): each trial is an ordinary step
+ * of the run, and the tiling does not change any result.  Asynchronous on
+ * ``stream``; graphs of the previous call are released after waiting for it. */
+qds_status qds_batch_run(qds_batch b, qds_state* states, const qds_current* J, const qds_axion* axion,
+                         const int64_t* n_steps, int32_t graph_steps, int32_t tune, void* stream);
+
+/* Tile heights in use (int32[QDS_NTILES]) and whether the autotuner chose them. */
+qds_status qds_batch_get_tiles(qds_batch b, int32_t* tiles, int32_t* tuned);
+
+/* Sets the tile heights (each 1..1024) and marks them as chosen. */
+qds_status qds_batch_set_tiles(qds_batch b, const int32_t* tiles);
+
+const char* qds_batch_last_error(qds_batch b);
+
+/* Waits for the batch's last run and releases its graphs and tables. */
+qds_status qds_batch_destroy(qds_batch b);
 const char* qds_last_error(qds_handle h);
 const char* qds_version(void);
 

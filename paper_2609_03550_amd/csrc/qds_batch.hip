@@ -1,0 +1,434 @@
+// Batched forward over many independent instances (qds_batch_* of
+// include/qds.h): per step, one launch per kernel class covering the tiles of
+// every running instance, several steps captured in one HIP graph, and an
+// autotuner that picks each class's tile height from timed steps of the run.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "qds_ctx.hpp"
+
+using namespace qdsi;
+
+namespace {
+
+// One kernel launch of a batched step.
+struct Launch {
+    int slot;     // QDS_TILE_* slot (decides the kernel)
+    int M;        // mode count of the class (kernel A and the axion current)
+    int blocks;
+    qds::BatchList L;
+};
+
+// Launch sequence of one set of running instances, with its device lists and
+// the graphs captured for it: key (steps, parity of the first step).
+struct Plan {
+    std::vector<int> active;
+    std::vector<int> tiles;
+    std::vector<int> host;
+    void* dev = nullptr;
+    std::vector<Launch> launches;
+    std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+const int kCandRows[4] = {4, 8, 16, 32};     // kernel A and the electromagnetic sets
+const int kCandCur[4] = {1, 2, 4, 8};        // axion current
+constexpr int kTunePasses = 2;
+
+}  // namespace
+
+struct qds_batch_ctx {
+    std::vector<qds_ctx*> inst;
+    int dtype = QDS_F64;
+    int tiles[QDS_NTILES];
+    int tuned = 0;
+    hipStream_t cap = nullptr;          // capture stream (never executes work)
+    void* args = nullptr;               // per-run argument tables
+    size_t args_cap = 0;
+    std::vector<unsigned char> host_args;
+    std::vector<Plan*> plans;           // plans and graphs, kept while the tables are unchanged
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    char err[256];
+};
+
+namespace {
+
+qds_status bfail(qds_batch_ctx* b, qds_status s, const char* fmt, const char* detail = "") {
+    snprintf(b ? b->err : g_err, 256, fmt, detail);
+    return s;
+}
+
+void release(qds_batch_ctx* b) {
+    if (b->pending) {
+        hipEventSynchronize(b->done);
+        b->pending = false;
+    }
+    for (Plan* p : b->plans) {
+        for (auto& kv : p->graphs) {
+            hipGraphExecDestroy(kv.second.second);
+            hipGraphDestroy(kv.second.first);
+        }
+        if (p->dev) hipFree(p->dev);
+        delete p;
+    }
+    b->plans.clear();
+}
+
+int chunks(int nr, int rows) { return (nr + 1 + rows - 1) / rows; }
+
+// Lists of every kernel class for the running instances ``active``.
+qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStream_t s, Plan** out) {
+    Plan* P = new (std::nothrow) Plan();
+    if (!P) return bfail(b, QDS_ENOMEM, "out of host memory%s");
+    P->active = active;
+    P->tiles.assign(b->tiles, b->tiles + QDS_NTILES);
+    struct Pending { int slot, M; std::vector<int> idx, first; };
+    std::vector<Pending> pend;
+    auto add = [&](int slot, int M, auto pick, auto blocks_of) {
+        Pending q{slot, M, {}, {0}};
+        for (int k : active) {
+            const qds_ctx* c = b->inst[k];
+            if (!pick(c)) continue;
+            q.idx.push_back(k);
+            q.first.push_back(q.first.back() + blocks_of(c));
+        }
+        if (!q.idx.empty()) pend.push_back(std::move(q));
+    };
+    auto has_ax = [](const qds_ctx* c) { return has(c, QDS_P_PHI); };
+    auto has_arem = [](const qds_ctx* c) { return has(c, QDS_P_SET1); };
+    for (int M = 1; M <= 4; ++M) {
+        const int rows = b->tiles[QDS_TILE_A1 + M - 1];
+        add(QDS_TILE_A1 + M - 1, M, [&](const qds_ctx* c) { return has_ax(c) && c->M == M; },
+            [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows); });
+    }
+    {
+        const int rows = b->tiles[QDS_TILE_EM0];
+        add(QDS_TILE_EM0, 0, [&](const qds_ctx* c) { return !has_ax(c); },
+            [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows) * c->M; });
+    }
+    for (int M = 1; M <= 4; ++M) {
+        const int rows = b->tiles[QDS_TILE_CUR1 + M - 1];
+        add(QDS_TILE_CUR1 + M - 1, M, [&](const qds_ctx* c) { return has_arem(c) && c->M == M; },
+            [&](const qds_ctx* c) { return ((c->g.nx + 63) / 64) * chunks(c->g.nr, rows); });
+    }
+    {
+        const int rows = b->tiles[QDS_TILE_EM1];
+        add(QDS_TILE_EM1, 0, has_arem,
+            [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows) * c->M; });
+    }
+    size_t total = 0;
+    for (const Pending& q : pend) {
+        if (q.first.back() >= (1 << 30)) {
+            delete P;
+            return bfail(b, QDS_EUNSUPPORTED, "batched launch exceeds 2^30 workgroups%s");
+        }
+        total += q.idx.size() + q.first.size();
+    }
+    P->host.reserve(total);
+    std::vector<size_t> off;
+    for (const Pending& q : pend) {
+        off.push_back(P->host.size());
+        P->host.insert(P->host.end(), q.idx.begin(), q.idx.end());
+        P->host.insert(P->host.end(), q.first.begin(), q.first.end());
+    }
+    if (total) {
+        if (hipMalloc(&P->dev, total * sizeof(int)) != hipSuccess) {
+            delete P;
+            return bfail(b, QDS_ENOMEM, "hipMalloc of the batch lists failed%s");
+        }
+        hipError_t e = hipMemcpyAsync(P->dev, P->host.data(), total * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            hipFree(P->dev);
+            delete P;
+            return bfail(b, QDS_EHIP, "list upload failed: %s", hipGetErrorString(e));
+        }
+    }
+    for (size_t q = 0; q < pend.size(); ++q) {
+        const int* base = static_cast<const int*>(P->dev) + off[q];
+        Launch l;
+        l.slot = pend[q].slot;
+        l.M = pend[q].M;
+        l.blocks = pend[q].first.back();
+        l.L.idx = base;
+        l.L.first = base + pend[q].idx.size();
+        l.L.n = int(pend[q].idx.size());
+        l.L.rows = b->tiles[l.slot];
+        P->launches.push_back(l);
+    }
+    b->plans.push_back(P);
+    *out = P;
+    return QDS_OK;
+}
+
+template <typename T>
+hipError_t launch_step(const qds_batch_ctx* b, const Plan& P, int parity, hipStream_t s, hipEvent_t* ev) {
+    const size_t N = b->inst.size();
+    const auto* fa = static_cast<const qds::FusedArgs<T>*>(b->args) + size_t(parity) * N;
+    const auto* xa = reinterpret_cast<const qds::AxionArgs<T>*>(static_cast<const char*>(b->args) +
+                                                                 2 * N * sizeof(qds::FusedArgs<T>)) +
+                     size_t(parity) * N;
+    for (size_t q = 0; q < P.launches.size(); ++q) {
+        const Launch& l = P.launches[q];
+        if (ev) hipEventRecord(ev[2 * q], s);
+        hipError_t e;
+        if (l.slot < QDS_TILE_CUR1) e = qds::batch_a<T>(fa, l.L, l.M, l.blocks, s);
+        else if (l.slot < QDS_TILE_EM0) e = qds::batch_current<T>(xa, l.L, l.M, l.blocks, s);
+        else e = qds::batch_em<T>(fa, l.L, l.slot == QDS_TILE_EM1 ? 1 : 0, l.blocks, s);
+        if (e != hipSuccess) return e;
+        if (ev) hipEventRecord(ev[2 * q + 1], s);
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, const qds_axion* ax,
+                    const int64_t* n_steps, int graph_steps, int tune, hipStream_t s) {
+    const size_t N = b->inst.size();
+    // argument tables: parity q reads buf[(cur + q) % 2] and writes the other;
+    // the step and window counters are not used by the batched kernels (no
+    // drive, no window) and are left at zero so that equal states reuse them
+    const size_t fbytes = 2 * N * sizeof(qds::FusedArgs<T>);
+    const size_t bytes = fbytes + 2 * N * sizeof(qds::AxionArgs<T>);
+    std::vector<unsigned char> host(bytes, 0);
+    auto* fa = reinterpret_cast<qds::FusedArgs<T>*>(host.data());
+    auto* xa = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + fbytes);
+    for (size_t k = 0; k < N; ++k) {
+        const qds_ctx* c = b->inst[k];
+        const qds::StepPlan<T> p0 = make_plan<T>(c, J ? &J[k] : nullptr, ax ? &ax[k] : nullptr);
+        for (int q = 0; q < 2; ++q) {
+            void* A = states[k].buf[(states[k].cur + q) & 1];
+            void* B = states[k].buf[(states[k].cur + q + 1) & 1];
+            qds::FusedArgs<T> f = fused_args<T>(c, p0, A, B, 0, 0);
+            qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B);
+            memcpy(&fa[q * N + k], &f, sizeof(f));
+            memcpy(&xa[q * N + k], &x, sizeof(x));
+        }
+    }
+    hipError_t e;
+    if (!(b->args && host == b->host_args)) {
+        release(b);
+        b->host_args.swap(host);
+        if (bytes > b->args_cap) {
+            if (b->args) hipFree(b->args);
+            b->args = nullptr;
+            b->args_cap = 0;
+            if (hipMalloc(&b->args, bytes) != hipSuccess)
+                return bfail(b, QDS_ENOMEM, "hipMalloc of the batch tables failed%s");
+            b->args_cap = bytes;
+        }
+        e = hipMemcpyAsync(b->args, b->host_args.data(), bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            b->host_args.clear();
+            return bfail(b, QDS_EHIP, "table upload failed: %s", hipGetErrorString(e));
+        }
+    }
+
+    auto running = [&](int64_t t) {
+        std::vector<int> a;
+        for (size_t k = 0; k < N; ++k)
+            if (n_steps[k] > t) a.push_back(int(k));
+        return a;
+    };
+    int64_t t = 0;
+    qds_status st;
+    auto find_plan = [&](const std::vector<int>& act) -> Plan* {
+        for (Plan* p : b->plans)
+            if (p->active == act && std::equal(p->tiles.begin(), p->tiles.end(), b->tiles)) return p;
+        return nullptr;
+    };
+    // autotuner: timed trial steps of the run, each candidate tiling twice
+    if (tune && !b->tuned) {
+        std::vector<int> act = running(0);
+        bool enough = !act.empty();
+        for (int k : act) enough = enough && n_steps[k] >= 4 * kTunePasses;
+        if (enough) {
+            std::vector<hipEvent_t> evs;
+            std::vector<Plan*> trial;
+            for (int pass = 0; pass < kTunePasses; ++pass) {
+                for (int cand = 0; cand < 4; ++cand) {
+                    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = kCandRows[cand];
+                    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = kCandCur[cand];
+                    b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = kCandRows[cand];
+                    Plan* P;
+                    if ((st = build_plan(b, act, s, &P)) != QDS_OK) return st;
+                    trial.push_back(P);
+                    const size_t base = evs.size();
+                    for (size_t q = 0; q < 2 * P->launches.size(); ++q) {
+                        hipEvent_t ev;
+                        if (hipEventCreate(&ev) != hipSuccess) return bfail(b, QDS_EHIP, "event creation failed%s");
+                        evs.push_back(ev);
+                    }
+                    e = launch_step<T>(b, *P, int(t & 1), s, evs.data() + base);
+                    if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+                    ++t;
+                }
+            }
+            if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, QDS_EHIP, "tuning run failed%s");
+            float best[QDS_NTILES];
+            int pick[QDS_NTILES];
+            for (int q = 0; q < QDS_NTILES; ++q) { best[q] = 3.4e38f; pick[q] = -1; }
+            size_t ei = 0;
+            for (size_t tr = 0; tr < trial.size(); ++tr) {
+                const int cand = int(tr % 4);
+                for (const Launch& l : trial[tr]->launches) {
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]);
+                    ei += 2;
+                    if (ms < best[l.slot]) { best[l.slot] = ms; pick[l.slot] = cand; }
+                }
+            }
+            for (int q = 0; q < QDS_NTILES; ++q) {
+                const int cand = pick[q] < 0 ? 2 : pick[q];
+                const bool cur = q >= QDS_TILE_CUR1 && q < QDS_TILE_EM0;
+                b->tiles[q] = cur ? kCandCur[cand] : kCandRows[cand];
+            }
+            b->tuned = 1;
+            for (hipEvent_t ev : evs) hipEventDestroy(ev);
+        }
+    }
+    // the run proper, in segments over which the running set is unchanged
+    for (;;) {
+        std::vector<int> act = running(t);
+        if (act.empty()) break;
+        int64_t rem = INT64_MAX;
+        for (int k : act) rem = std::min(rem, n_steps[k] - t);
+        Plan* P = find_plan(act);
+        if (!P && (st = build_plan(b, act, s, &P)) != QDS_OK) return st;
+        if (graph_steps <= 0) {
+            for (int64_t u = 0; u < rem; ++u) {
+                e = launch_step<T>(b, *P, int((t + u) & 1), s, nullptr);
+                if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            }
+            t += rem;
+            continue;
+        }
+        while (rem > 0) {
+            const int seg = int(std::min<int64_t>(rem, graph_steps));
+            const std::pair<int, int> key(seg, int(t & 1));
+            auto it = P->graphs.find(key);
+            if (it == P->graphs.end()) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t x = nullptr;
+                e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+                if (e != hipSuccess) return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(e));
+                hipError_t le = hipSuccess;
+                for (int u = 0; u < seg && le == hipSuccess; ++u) le = launch_step<T>(b, *P, int((t + u) & 1), b->cap, nullptr);
+                e = hipStreamEndCapture(b->cap, &g);
+                if (le != hipSuccess || e != hipSuccess) {
+                    if (g) hipGraphDestroy(g);
+                    return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(le != hipSuccess ? le : e));
+                }
+                e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return bfail(b, QDS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+                }
+                it = P->graphs.emplace(key, std::make_pair(g, x)).first;
+            }
+            e = hipGraphLaunch(it->second.second, s);
+            if (e != hipSuccess) return bfail(b, QDS_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+            t += seg;
+            rem -= seg;
+        }
+    }
+    for (size_t k = 0; k < N; ++k) {
+        states[k].cur ^= int(n_steps[k] & 1);
+        states[k].step += n_steps[k];
+    }
+    hipEventRecord(b->done, s);
+    b->pending = true;
+    return QDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch* out) {
+    if (!handles || !out) return bfail(nullptr, QDS_EINVAL, "null argument%s");
+    *out = nullptr;
+    if (count < 1 || count > 4096) return bfail(nullptr, QDS_EINVAL, "count must be 1..4096%s");
+    std::vector<qds_ctx*> v(handles, handles + count);
+    for (qds_ctx* c : v) {
+        if (!c) return bfail(nullptr, QDS_EINVAL, "null handle%s");
+        if (c->g.dtype != v[0]->g.dtype) return bfail(nullptr, QDS_EINVAL, "all instances need one dtype%s");
+        if (!fused_ok(c) || c->g.x_bc == QDS_X_WINDOW)
+            return bfail(nullptr, QDS_EUNSUPPORTED, "batched instances need <= 4 modes and no moving window%s");
+    }
+    std::vector<qds_ctx*> sorted = v;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return bfail(nullptr, QDS_EINVAL, "a handle appears twice (its scratch planes would be shared)%s");
+    qds_batch_ctx* b = new (std::nothrow) qds_batch_ctx();
+    if (!b) return bfail(nullptr, QDS_ENOMEM, "out of host memory%s");
+    b->inst = v;
+    b->dtype = v[0]->g.dtype;
+    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = 16;
+    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = 1;
+    b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = 16;
+    b->err[0] = 0;
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        if (b->cap) hipStreamDestroy(b->cap);
+        delete b;
+        return bfail(nullptr, QDS_EHIP, "stream or event creation failed%s");
+    }
+    *out = b;
+    return QDS_OK;
+}
+
+qds_status qds_batch_run(qds_batch b, qds_state* states, const qds_current* J, const qds_axion* axion,
+                         const int64_t* n_steps, int32_t graph_steps, int32_t tune, void* stream) {
+    if (!b) return bfail(nullptr, QDS_EINVAL, "null batch%s");
+    if (!states || !n_steps) return bfail(b, QDS_EINVAL, "null states or step counts%s");
+    if (graph_steps < 0 || graph_steps > 100000) return bfail(b, QDS_EINVAL, "graph_steps must be 0..100000%s");
+    for (size_t k = 0; k < b->inst.size(); ++k) {
+        qds_ctx* c = b->inst[k];
+        if (check_state(c, &states[k]) != QDS_OK) return bfail(b, QDS_ESTATE, "instance state: %s", c->err);
+        if (n_steps[k] < 0) return bfail(b, QDS_EINVAL, "negative step count%s");
+        if (states[k].step + n_steps[k] >= (int64_t(1) << 31)) return bfail(b, QDS_ESTATE, "step counter would overflow%s");
+        if (J && J[k].kind != QDS_J_NONE)
+            return bfail(b, QDS_EUNSUPPORTED, "batched instances take no prescribed drive (kind must be NONE)%s");
+        if (J && J[k].wp2 != 0.0 && !has(c, QDS_P_JX))
+            return bfail(b, QDS_EINVAL, "plasma response needs the plasma planes%s");
+        if (!axion && has(c, QDS_P_PHI)) return bfail(b, QDS_EINVAL, "axion parameters missing%s");
+    }
+    if (b->dtype == QDS_F64)
+        return run_impl<double>(b, states, J, axion, n_steps, graph_steps, tune, hipStream_t(stream));
+    return run_impl<float>(b, states, J, axion, n_steps, graph_steps, tune, hipStream_t(stream));
+}
+
+qds_status qds_batch_get_tiles(qds_batch b, int32_t* tiles, int32_t* tuned) {
+    if (!b || !tiles) return bfail(b, QDS_EINVAL, "null argument%s");
+    for (int q = 0; q < QDS_NTILES; ++q) tiles[q] = b->tiles[q];
+    if (tuned) *tuned = b->tuned;
+    return QDS_OK;
+}
+
+qds_status qds_batch_set_tiles(qds_batch b, const int32_t* tiles) {
+    if (!b || !tiles) return bfail(b, QDS_EINVAL, "null argument%s");
+    for (int q = 0; q < QDS_NTILES; ++q)
+        if (tiles[q] < 1 || tiles[q] > 1024) return bfail(b, QDS_EINVAL, "tile heights must be 1..1024%s");
+    for (int q = 0; q < QDS_NTILES; ++q) b->tiles[q] = tiles[q];
+    b->tuned = 1;
+    return QDS_OK;
+}
+
+const char* qds_batch_last_error(qds_batch b) { return b ? b->err : g_err; }
+
+qds_status qds_batch_destroy(qds_batch b) {
+    if (!b) return QDS_OK;
+    release(b);
+    if (b->args) hipFree(b->args);
+    if (b->done) hipEventDestroy(b->done);
+    if (b->cap) hipStreamDestroy(b->cap);
+    delete b;
+    return QDS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Host-side handle of libqds and the helpers shared by its C ABI sources.
+#pragma once
+#include <stdio.h>
+
+#include <vector>
+
+#include "../../include/qds.h"
+#include "qds_kernels.hpp"
+
+struct qds_ctx {
+    qds_grid g;
+    int M;
+    double h;
+    int ld;
+    size_t plane_elems;      // complex elements per plane
+    size_t elem_bytes;       // 16 (F64) or 8 (F32)
+    int slot[QDS_NPLANES];   // plane -> position in the buffer, -1 if absent
+    int nplanes;
+    void* scratch;           // axion-current planes (3), library owned
+    int path;                // QDS_PATH_*
+    int rows;                // radial rows per workgroup of the fused kernels
+    int timing;              // record per-kernel HIP events in qds_step
+    // timing events, recorded without synchronising and resolved by
+    // qds_get_timing: pairs (start, end) per launch, tagged with the kernel
+    std::vector<hipEvent_t> pool;
+    size_t used;
+    std::vector<int> tag;
+    char err[256];
+};
+
+namespace qdsi {
+
+inline thread_local char g_err[256] = "";
+
+// Event pair for the next timed launch (created on demand, reused after a reset).
+inline hipEvent_t* timing_pair(qds_ctx* c, int kernel) {
+    if (c->used + 2 > c->pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            c->pool.push_back(e);
+        }
+    }
+    hipEvent_t* p = &c->pool[c->used];
+    c->used += 2;
+    c->tag.push_back(kernel);
+    return p;
+}
+
+inline qds_status fail(qds_ctx* c, qds_status s, const char* fmt, const char* detail = "") {
+    char* buf = c ? c->err : g_err;
+    snprintf(buf, 256, fmt, detail);
+    return s;
+}
+
+inline bool has(const qds_ctx* c, int plane) { return c->slot[plane] >= 0; }
+
+template <typename T>
+void plane_table(const qds_ctx* c, void* base, qds::cx<T>** out) {
+    for (int p = 0; p < QDS_NPLANES; ++p) {
+        out[p] = c->slot[p] < 0 ? nullptr
+                                : reinterpret_cast<qds::cx<T>*>(static_cast<char*>(base) +
+                                                                size_t(c->slot[p]) * c->plane_elems * c->elem_bytes);
+    }
+}
+
+inline qds::Geo geo(const qds_ctx* c) {
+    qds::Geo g;
+    g.nx = c->g.nx;
+    g.nr = c->g.nr;
+    g.M = c->M;
+    g.ld = c->ld;
+    g.h = c->h;
+    g.dr = c->g.dr;
+    g.per = c->g.x_bc == QDS_X_PERIODIC;
+    g.open_r = c->g.r_bc == QDS_R_OPEN;
+    return g;
+}
+
+// The fused kernels cover up to 4 modes.  With the moving window and the
+// regenerated set, the axion current needs the background set's new state at
+// lab positions while kernel A already writes it shifted, so that combination
+// runs the staged kernels (which shift after the whole step).
+inline bool fused_ok(const qds_ctx* c) {
+    const bool window_arem = c->g.x_bc == QDS_X_WINDOW && (c->g.content & QDS_HAS_AREM);
+    return c->M <= 4 && !window_arem;
+}
+
+inline bool use_fused(const qds_ctx* c) {
+    if (c->path == QDS_PATH_STAGED) return false;
+    return fused_ok(c);
+}
+
+template <typename T>
+qds::SetP<T> fused_set(qds::cx<T>* const* A, qds::cx<T>* const* B, int s) {
+    const int b = 9 * s;
+    qds::SetP<T> p;
+    p.trp = A[b + 0]; p.trm = A[b + 1]; p.ttp = A[b + 2]; p.ttm = A[b + 3];
+    p.ex = A[b + 4]; p.bx = A[b + 5]; p.jx = A[b + 6]; p.jr = A[b + 7]; p.jt = A[b + 8];
+    p.otrp = B[b + 0]; p.otrm = B[b + 1]; p.ottp = B[b + 2]; p.ottm = B[b + 3];
+    p.oex = B[b + 4]; p.obx = B[b + 5]; p.ojx = B[b + 6]; p.ojr = B[b + 7]; p.ojt = B[b + 8];
+    p.jxa = p.jra = p.jta = nullptr;
+    return p;
+}
+
+template <typename T>
+qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axion* ax) {
+    qds::StepPlan<T> p;
+    p.g = geo(c);
+    p.plasma = has(c, QDS_P_JX);
+    p.axion = has(c, QDS_P_PHI);
+    p.arem = has(c, QDS_P_SET1);
+    p.wp2 = J ? J->wp2 : 0.0;
+    if (!p.plasma) p.wp2 = 0.0;
+    p.ma2 = ax ? ax->ma2 : 0.0;
+    p.s_phi = ax ? ax->s_phi : 1.0;
+    p.s_j = ax ? ax->s_j : 1.0;
+    p.bx0 = ax ? qds::cx<T>{T(ax->bext[0]), T(ax->bext[1])} : qds::cx<T>{T(0), T(0)};
+    p.br1 = ax ? qds::cx<T>{T(ax->bext[2]), T(ax->bext[3])} : qds::cx<T>{T(0), T(0)};
+    p.bt1 = ax ? qds::cx<T>{T(ax->bext[4]), T(ax->bext[5])} : qds::cx<T>{T(0), T(0)};
+    p.drive.on = (J && J->kind == QDS_J_RING) ? 1 : 0;
+    if (p.drive.on) {
+        p.drive.amp = J->amp; p.drive.x0 = J->x0; p.drive.v = J->v; p.drive.sx = J->sx;
+        p.drive.r0 = J->r0; p.drive.sr = J->sr; p.drive.noise = J->noise; p.drive.seed = J->seed;
+    }
+    for (int k = 0; k < 3; ++k)
+        p.ja[k] = c->scratch ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) +
+                                                              size_t(k) * c->plane_elems * c->elem_bytes)
+                             : nullptr;
+    return p;
+}
+
+// Fused-kernel arguments of one step from buffer A (old) to buffer B (new).
+template <typename T>
+qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB, int64_t n,
+                             int64_t w) {
+    qds::FusedArgs<T> a;
+    a.g = p0.g;
+    a.plasma = p0.plasma;
+    a.axion = p0.axion;
+    a.wp2 = p0.wp2; a.ma2 = p0.ma2; a.s_phi = p0.s_phi; a.s_j = p0.s_j;
+    a.bx0 = p0.bx0; a.br1 = p0.br1; a.bt1 = p0.bt1;
+    a.drive = p0.drive;
+    a.window = c->g.x_bc == QDS_X_WINDOW;
+    a.rows = c->rows;
+    a.jax = p0.ja[0]; a.jar = p0.ja[1]; a.jat = p0.ja[2];
+    qds::cx<T>* A[QDS_NPLANES];
+    qds::cx<T>* B[QDS_NPLANES];
+    plane_table<T>(c, bufA, A);
+    plane_table<T>(c, bufB, B);
+    a.s0 = fused_set<T>(A, B, 0);
+    a.s1 = fused_set<T>(A, B, 1);
+    a.s1.jxa = a.jax; a.s1.jra = a.jar; a.s1.jta = a.jat;
+    a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
+    a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
+    a.n = n;
+    a.w = w;
+    return a;
+}
+
+// Axion-current arguments of the same step.
+template <typename T>
+qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB) {
+    qds::StepPlan<T> pl = p0;
+    plane_table<T>(c, bufA, pl.A);
+    plane_table<T>(c, bufB, pl.B);
+    return pl.axion_args();
+}
+
+inline qds_status check_state(qds_ctx* c, const qds_state* st) {
+    if (!st) return fail(c, QDS_EINVAL, "null state%s");
+    if (!st->buf[0] || !st->buf[1] || st->buf[0] == st->buf[1])
+        return fail(c, QDS_ESTATE, "state needs two distinct device buffers%s");
+    if (st->cur != 0 && st->cur != 1) return fail(c, QDS_ESTATE, "state.cur must be 0 or 1%s");
+    if (st->step < 0 || st->window < 0) return fail(c, QDS_ESTATE, "negative step or window%s");
+    if (st->step >= (int64_t(1) << 31)) return fail(c, QDS_ESTATE, "step counter out of range%s");
+    return QDS_OK;
+}
+
+}  // namespace qdsi

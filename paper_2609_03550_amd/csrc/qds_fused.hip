@@ -20,7 +20,7 @@ namespace qds {
 namespace fused {
 
 constexpr int WAVE = 64;
-constexpr int OWN = 62;   // owned cells per wave (halo lane at each end)
+constexpr int OWN = kFusedOwn;   // owned cells per wave (halo lane at each end)
 
 template <typename T>
 struct XAcc {
@@ -367,14 +367,12 @@ constexpr int NS = 6;
 // kernel A: background set + axion
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-__device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a) {
+__device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
     const Geo g = a.g;
     const int wave = threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
-    const int strip = blockIdx.x;
-    const int chunk = blockIdx.y;
-    const int r0 = chunk * a.rows;
-    const int r1 = min(g.nr + 1, r0 + a.rows);
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
     const int ncell = g.nx;                       // H cells 0..nx-1 (the last is dead unless periodic)
     Ctx<T> c;
     c.g = g;
@@ -455,15 +453,21 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a) {
             cx<T> exn1 = T(0.5) * (W.ex0[1] + W.ex1[2]);
             cx<T> fEx = T(0.5) * (exn0 + exn1);
             cx<T> fBx = bx_n;
-            cx<T> fEr = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
-            cx<T> fBt = T(0.25) * ((W.rpa[0] - W.rma[0]) + (W.rpb[0] - W.rmb[0]));
-            cx<T> fEt = T(0.125) * ((W.tpa[0] + W.tma[0]) + (W.tpa[1] + W.tma[1]) + (W.tpb[0] + W.tmb[0]) +
-                                    (W.tpb[1] + W.tmb[1]));
-            cx<T> fBr = T(0.125) * ((W.tpa[0] - W.tma[0]) + (W.tpa[1] - W.tma[1]) + (W.tpb[0] - W.tmb[0]) +
-                                    (W.tpb[1] - W.tmb[1]));
+            // transverse part from the transport variables: C{E_r, B_r} + C{E_th, B_th}
+            // = 1/2 C{T_r^+ + b_th, T_th^+ + b_r} - 1/2 C{T_r^- - b_th, T_th^- - b_r}
+            // (exact; no cancellation between two large products for co-propagating waves)
+            cx<T> fPp = T(0.25) * (W.rpa[0] + W.rpb[0]);
+            cx<T> fPm = T(-0.25) * (W.rma[0] + W.rmb[0]);
+            cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (W.tpb[0] + W.tpb[1]));
+            cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (W.tmb[0] + W.tmb[1]));
             if (m == 0) fBx = fBx + a.bx0;
-            if (m == 1) { fBr = fBr + a.br1; fBt = fBt + a.bt1; }
-            put(smS, 0, fEx); put(smS, 1, fBx); put(smS, 2, fEr); put(smS, 3, fBr); put(smS, 4, fEt); put(smS, 5, fBt);
+            if (m == 1) {
+                fPp = fPp + T(0.5) * a.bt1;
+                fPm = fPm + T(0.5) * a.bt1;
+                fQp = fQp + a.br1;
+                fQm = fQm - a.br1;
+            }
+            put(smS, 0, fEx); put(smS, 1, fBx); put(smS, 2, fPp); put(smS, 3, fQp); put(smS, 4, fPm); put(smS, 5, fQm);
         }
         __syncthreads();
         if (j < g.nr) {
@@ -527,23 +531,22 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a) {
 // Kernel A entry points: FP64 keeps the full register file (one wave per SIMD,
 // no spills); FP32 fits two waves per SIMD.
 template <int M>
-__global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) { fused_a_body<double, M>(a); }
+__global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) {
+    fused_a_body<double, M>(a, blockIdx.x, blockIdx.y, a.rows);
+}
 template <int M>
 __global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M>(a); }
+k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M>(a, blockIdx.x, blockIdx.y, a.rows); }
 
 // ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
+__device__ __forceinline__ void em_body(const FusedArgs<T>& a, int which, int strip, int chunk, int m, int rows) {
     const Geo g = a.g;
     const int lane = threadIdx.x;
-    const int strip = blockIdx.x;
-    const int chunk = blockIdx.y;
-    const int m = blockIdx.z;
-    const int r0 = chunk * a.rows;
-    const int r1 = min(g.nr + 1, r0 + a.rows);
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
     Ctx<T> c;
     c.g = g;
     c.m = m;
@@ -596,6 +599,45 @@ __global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
+    em_body<T>(a, which, blockIdx.x, blockIdx.y, blockIdx.z, a.rows);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches: block -> (instance, tile) through the launch's list; the
+// instance's arguments are read from a device table
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ args, const BatchList& L) {
+    const int b = blockIdx.x;
+    const int k = batch_find(L, b);
+    const FusedArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int strips = fused_strips(a.g.nx);
+    fused_a_body<T, M>(a, local % strips, local / strips, L.rows);
+}
+template <int M>
+__global__ void __launch_bounds__(WAVE * M) k_batch_a_f64(const FusedArgs<double>* __restrict__ args, BatchList L) {
+    batch_a_body<double, M>(args, L);
+}
+template <int M>
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_batch_a_f32(const FusedArgs<float>* __restrict__ args, BatchList L) {
+    batch_a_body<float, M>(args, L);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restrict__ args, BatchList L, int which) {
+    const int b = blockIdx.x;
+    const int k = batch_find(L, b);
+    const FusedArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int strips = fused_strips(a.g.nx);
+    const int per = strips * ((a.g.nr + 1 + L.rows - 1) / L.rows);
+    em_body<T>(a, which, local % strips, (local % per) / strips, local / per, L.rows);
+}
+
 }  // namespace fused
 
 template <typename T, int M>
@@ -631,6 +673,36 @@ hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
+    switch (M) {
+#define QDS_BA(MM)                                                                                               \
+    case MM:                                                                                                     \
+        if constexpr (sizeof(T) == 8)                                                                            \
+            hipLaunchKernelGGL((fused::k_batch_a_f64<MM>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+        else                                                                                                     \
+            hipLaunchKernelGGL((fused::k_batch_a_f32<MM>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+        break;
+        QDS_BA(1) QDS_BA(2) QDS_BA(3) QDS_BA(4)
+#undef QDS_BA
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fused::k_batch_em<T>, dim3(blocks), dim3(fused::WAVE), 0, s, args, L, which);
+    return hipGetLastError();
+}
+
+template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t fused_step<double>(const FusedArgs<double>&, hipStream_t, int);
 template hipError_t fused_step<float>(const FusedArgs<float>&, hipStream_t, int);
 

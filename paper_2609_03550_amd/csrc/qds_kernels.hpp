@@ -140,9 +140,40 @@ struct FusedArgs {
     int rows;         // radial rows per workgroup chunk
 };
 
+// Columns owned by one 64-lane strip of the r-marching kernels (two halo lanes).
+constexpr int kFusedOwn = 62;
+__host__ __device__ inline int fused_strips(int nx) { return (nx + kFusedOwn - 1) / kFusedOwn; }
+
+// One launch of a batched kernel: the instances it covers (indices into the
+// argument tables), the first block of each (n + 1 entries, first[0] = 0, the
+// last is the grid size) and the tile height in rows.
+struct BatchList {
+    const int* idx;
+    const int* first;
+    int n;
+    int rows;
+};
+
+// Instance of block b: the largest k with first[k] <= b.
+__device__ __forceinline__ int batch_find(const BatchList& L, int b) {
+    int lo = 0, hi = L.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.first[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
 template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
 template <typename T> hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s);
+// Batched launches over many instances (argument tables in device memory).
+template <typename T>
+hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
+template <typename T>
+hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
+template <typename T>
+hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
 template <typename T>
 hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
                         hipStream_t s);

@@ -76,7 +76,16 @@ __device__ __forceinline__ T parity(int m) { return m == 0 ? T(1) : T(-1); }
 // reflections (parity (-1)^m for B_x, phi, T_a; the T_r reflection of the
 // m = 1 axis relation for E_r and B_theta); the uniform external field is
 // added to the B factors.
-template <typename T>
+//
+// With TFORM the theta and r pairs are formed from the transport variables
+// instead (same value in exact arithmetic, by bilinearity and symmetry of C_m):
+//   C{B_th, d_t phi} + C{E_r, d_x phi} = 1/2 C{T_r^+, T_a^-} - 1/2 C{T_r^-, T_a^+}
+//   C{B_r, d_t phi} - C{E_th, d_x phi} = 1/2 C{T_th^+, T_a^+} - 1/2 C{T_th^-, T_a^-}
+// (T_a^+- = d_t phi -+ d_x phi; the external field enters as T_r^+- +- b_th,
+// T_th^+- +- b_r).  For co-propagating waves each product then pairs a large
+// factor with a small one, where the E/B form subtracts two large products;
+// the single-precision forward uses it for that reason.
+template <typename T, bool TFORM = false>
 __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f) {
     const Geo& g = a.g;
     BgView<T> v{&a};
@@ -121,7 +130,52 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
         f[5] = (T(1) / dr) * (phi_hi - phi_lo);
     }
     // ---------------- j_a,theta
-    {
+    if constexpr (TFORM) {
+        // T_r^+- averaged over t^n, t^{n+1} at (i or i1, j+1/2)
+        auto tr = [&](const cx<T>* p0, const cx<T>* p1, int k, int c) {
+            return T(0.5) * (ldx(p0, g, m, k, c) + ldx(p1, g, m, k, c));
+        };
+        cx<T> P0 = tr(a.A0.trp, a.B0.trp, j, i), P1 = tr(a.A0.trp, a.B0.trp, j, i1);
+        cx<T> N0 = tr(a.A0.trm, a.B0.trm, j, i), N1 = tr(a.A0.trm, a.B0.trm, j, i1);
+        cx<T> gP0, gP1, gN0, gN1;
+        if (ax) {
+            if (m == 1) {
+                // E_r, B_theta ghosts of the m = 1 axis relation, combined:
+                // T_r^+ ghost = 2i T_th^-(0) - T_r^+(1/2), T_r^- ghost = 2i T_th^+(0) - T_r^-(1/2)
+                auto tt = [&](const cx<T>* p0, const cx<T>* p1, int c) {
+                    return T(0.5) * (ldx(p0, g, 1, 0, c) + ldx(p1, g, 1, 0, c));
+                };
+                gP0 = imul(T(2), tt(a.A0.ttm, a.B0.ttm, i)) - P0;
+                gP1 = imul(T(2), tt(a.A0.ttm, a.B0.ttm, i1)) - P1;
+                gN0 = imul(T(2), tt(a.A0.ttp, a.B0.ttp, i)) - N0;
+                gN1 = imul(T(2), tt(a.A0.ttp, a.B0.ttp, i1)) - N1;
+            } else {
+                gP0 = -P0; gP1 = -P1; gN0 = -N0; gN1 = -N1;
+            }
+        } else {
+            gP0 = tr(a.A0.trp, a.B0.trp, j - 1, i);
+            gP1 = tr(a.A0.trp, a.B0.trp, j - 1, i1);
+            gN0 = tr(a.A0.trm, a.B0.trm, j - 1, i);
+            gN1 = tr(a.A0.trm, a.B0.trm, j - 1, i1);
+        }
+        cx<T> fP = T(0.5) * (T(0.5) * (gP0 + P0) + T(0.5) * (gP1 + P1));
+        cx<T> fN = T(0.5) * (T(0.5) * (gN0 + N0) + T(0.5) * (gN1 + N1));
+        if (m == 1) { fP = fP + a.bt1; fN = fN - a.bt1; }
+        const cx<T>* tpB = a.tapB;
+        const cx<T>* tmB = a.tamB;
+        cx<T> u0 = ldx(tpB, g, m, j, i), u1 = ldx(tpB, g, m, j, i1);
+        cx<T> w0 = ldx(tmB, g, m, j, i), w1 = ldx(tmB, g, m, j, i1);
+        cx<T> ul0 = ax ? par * u0 : ldx(tpB, g, m, j - 1, i), ul1 = ax ? par * u1 : ldx(tpB, g, m, j - 1, i1);
+        cx<T> wl0 = ax ? par * w0 : ldx(tmB, g, m, j - 1, i), wl1 = ax ? par * w1 : ldx(tmB, g, m, j - 1, i1);
+        f[6] = T(0.5) * fP;
+        f[7] = T(0.5) * (T(0.5) * (wl0 + w0) + T(0.5) * (wl1 + w1));      // T_a^-
+        f[10] = T(-0.5) * fN;
+        f[11] = T(0.5) * (T(0.5) * (ul0 + u0) + T(0.5) * (ul1 + u1));     // T_a^+
+        f[8] = ld(a.B0.ex + g.at(m, j, i));
+        cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
+        cx<T> pl = ax ? par * ph : T(0.5) * (ld(a.phiA + g.at(m, j - 1, i)) + ld(a.phiB + g.at(m, j - 1, i)));
+        f[9] = (T(1) / dr) * (ph - pl);
+    } else {
         cx<T> b0 = T(0.5) * (v.Bt0(m, j, i) + v.Bt1(m, j, i));
         cx<T> b1 = T(0.5) * (v.Bt0(m, j, i1) + v.Bt1(m, j, i1));
         cx<T> e0 = T(0.5) * (v.Er0(m, j, i) + v.Er1(m, j, i));
@@ -161,7 +215,23 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
         f[9] = (T(1) / dr) * (ph - pl);
     }
     // ---------------- j_a,r
-    {
+    if constexpr (TFORM) {
+        cx<T> sp = zero<T>(), sm = zero<T>();
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                sp = sp + T(0.5) * (ldx(a.A0.ttp, g, m, j + dj, i + di) + ldx(a.B0.ttp, g, m, j + dj, i + di));
+                sm = sm + T(0.5) * (ldx(a.A0.ttm, g, m, j + dj, i + di) + ldx(a.B0.ttm, g, m, j + dj, i + di));
+            }
+        cx<T> qp = T(0.25) * sp, qm = T(0.25) * sm;
+        if (m == 1) { qp = qp + a.br1; qm = qm - a.br1; }
+        f[12] = T(0.5) * qp;
+        f[13] = T(0.5) * (ldx(a.tapB, g, m, j, i) + ldx(a.tapB, g, m, j, i1));   // T_a^+
+        f[14] = T(0.5) * qm;
+        f[15] = T(0.5) * (ldx(a.tamB, g, m, j, i) + ldx(a.tamB, g, m, j, i1));   // T_a^-
+        f[16] = T(0.5) * (ld(a.B0.ex + g.at(m, j, i)) + ld(a.B0.ex + g.at(m, j + 1, i)));
+        cx<T> ph = T(0.5) * (ld(a.phiA + g.at(m, j, i)) + ld(a.phiB + g.at(m, j, i)));
+        f[17] = imul(-T(m) / rk, ph);
+    } else {
         cx<T> sb = zero<T>(), se = zero<T>();
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) {

@@ -262,15 +262,19 @@ __global__ void k_axion_ta(AxionArgs<T> a) {
 #pragma unroll
     for (int m = 0; m < M; ++m) S[m] = zero<T>();
     if (live) {
-        cx<T> Ex[M], Bx[M], Er[M], Br[M], Et[M], Bt[M];
+        // transverse part in transport variables (exact rewrite of
+        // C{E_r, B_r} + C{E_th, B_th}, free of the cancellation between the
+        // two products for co-propagating waves):
+        //   1/2 C{T_r^+ + b_th, T_th^+ + b_r} - 1/2 C{T_r^- - b_th, T_th^- - b_r}
+        cx<T> Ex[M], Bx[M], Pp[M], Qp[M], Pm[M], Qm[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            Er[m] = T(0.5) * (er(a.A0, g, m, k, i) + er(a.A0, g, m, k, i + 1));
-            Bt[m] = T(0.5) * (bth(a.A0, g, m, k, i) + bth(a.A0, g, m, k, i + 1));
-            Et[m] = T(0.25) * (eth(a.A0, g, m, k, i) + eth(a.A0, g, m, k + 1, i) + eth(a.A0, g, m, k, i + 1) +
-                               eth(a.A0, g, m, k + 1, i + 1));
-            Br[m] = T(0.25) * (brr(a.A0, g, m, k, i) + brr(a.A0, g, m, k + 1, i) + brr(a.A0, g, m, k, i + 1) +
-                               brr(a.A0, g, m, k + 1, i + 1));
+            Pp[m] = T(0.25) * (ldx(a.A0.trp, g, m, k, i) + ldx(a.A0.trp, g, m, k, i + 1));
+            Pm[m] = T(-0.25) * (ldx(a.A0.trm, g, m, k, i) + ldx(a.A0.trm, g, m, k, i + 1));
+            Qp[m] = T(0.25) * (ldx(a.A0.ttp, g, m, k, i) + ldx(a.A0.ttp, g, m, k + 1, i) + ldx(a.A0.ttp, g, m, k, i + 1) +
+                               ldx(a.A0.ttp, g, m, k + 1, i + 1));
+            Qm[m] = T(0.25) * (ldx(a.A0.ttm, g, m, k, i) + ldx(a.A0.ttm, g, m, k + 1, i) + ldx(a.A0.ttm, g, m, k, i + 1) +
+                               ldx(a.A0.ttm, g, m, k + 1, i + 1));
             cx<T> e0 = T(0.5) * (ld(a.A0.ex + g.at(m, k, i)) + ld(a.B0.ex + g.at(m, k, i)));
             cx<T> e1 = T(0.5) * (ld(a.A0.ex + g.at(m, k + 1, i)) + ld(a.B0.ex + g.at(m, k + 1, i)));
             Ex[m] = T(0.5) * (e0 + e1);
@@ -278,12 +282,14 @@ __global__ void k_axion_ta(AxionArgs<T> a) {
         }
         Bx[0] = Bx[0] + a.bx0;
         if (M > 1) {
-            Br[1] = Br[1] + a.br1;
-            Bt[1] = Bt[1] + a.bt1;
+            Pp[1] = Pp[1] + T(0.5) * a.bt1;
+            Pm[1] = Pm[1] + T(0.5) * a.bt1;
+            Qp[1] = Qp[1] + a.br1;
+            Qm[1] = Qm[1] - a.br1;
         }
         conv_acc<T, M>(Ex, Bx, T(1), S);
-        conv_acc<T, M>(Er, Br, T(1), S);
-        conv_acc<T, M>(Et, Bt, T(1), S);
+        conv_acc<T, M>(Pp, Qp, T(1), S);
+        conv_acc<T, M>(Pm, Qm, T(1), S);
     }
     const T rk = (T(k) + T(0.5)) * dr;
 #pragma unroll
@@ -350,7 +356,7 @@ __global__ void k_axion_current(AxionArgs<T> a) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             cx<T> f[18];
-            ja_factors(a, m, i, j, f);
+            ja_factors<T, true>(a, m, i, j, f);
 #pragma unroll
             for (int q = 0; q < 18; ++q) F[q][m] = f[q];
         }
@@ -377,40 +383,49 @@ __global__ void k_axion_current(AxionArgs<T> a) {
 // cells of one row; each wave forms its mode's factors, the waves exchange them
 // through LDS and each evaluates C_m for its own mode.
 template <typename T, int M>
-__global__ void __launch_bounds__(64 * M) k_axion_current_w(AxionArgs<T> a) {
+__device__ __forceinline__ void axion_current_body(const AxionArgs<T>& a, int xb, int j0, int rows) {
     const Geo& g = a.g;
     const int m = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
-    const int i = blockIdx.x * 64 + lane;
-    const int j = blockIdx.y;
+    const int i = xb * 64 + lane;
     __shared__ cx<T> sm[18][M][64];
     const bool act = i < g.nx;
     const bool live = act && (g.per || i < g.nx - 1);
-    const bool calc = live && j < g.nr;
-    if (calc) {
-        cx<T> f[18];
-        ja_factors(a, m, i, j, f);
+    const int j1 = min(j0 + rows, g.nr + 1);
+    for (int j = j0; j < j1; ++j) {
+        const bool calc = live && j < g.nr;
+        if (j > j0) __syncthreads();             // the previous row's factors are consumed
+        if (calc) {
+            cx<T> f[18];
+            ja_factors<T, true>(a, m, i, j, f);
 #pragma unroll
-        for (int q = 0; q < 18; ++q) sm[q][m][lane] = f[q];
-    }
-    __syncthreads();
-    cx<T> jx = zero<T>(), jr = zero<T>(), jt = zero<T>();
-    if (calc) {
-        cx<T> A[M], B[M];
-        cx<T> out[3] = {zero<T>(), zero<T>(), zero<T>()};
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-#pragma unroll
-            for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-            conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
+            for (int q = 0; q < 18; ++q) sm[q][m][lane] = f[q];
         }
-        jx = out[0]; jt = out[1]; jr = out[2];
+        __syncthreads();
+        cx<T> jx = zero<T>(), jr = zero<T>(), jt = zero<T>();
+        if (calc) {
+            cx<T> A[M], B[M];
+            cx<T> out[3] = {zero<T>(), zero<T>(), zero<T>()};
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
+                conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
+            }
+            jx = out[0]; jt = out[1]; jr = out[2];
+        }
+        if (act) {
+            const T sj = T(a.s_j);
+            st(a.jax + g.at(m, j, i), sj * jx);
+            st(a.jat + g.at(m, j, i), sj * jt);
+            if (j < g.nr) st(a.jar + g.at(m, j, i), sj * jr);
+        }
     }
-    if (!act) return;
-    const T sj = T(a.s_j);
-    st(a.jax + g.at(m, j, i), sj * jx);
-    st(a.jat + g.at(m, j, i), sj * jt);
-    if (j < g.nr) st(a.jar + g.at(m, j, i), sj * jr);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(64 * M) k_axion_current_w(AxionArgs<T> a) {
+    axion_current_body<T, M>(a, blockIdx.x, blockIdx.y, 1);
 }
 
 template <typename T>
@@ -424,6 +439,29 @@ hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s) {
     }
     return hipGetLastError();
 }
+template <typename T, int M>
+__global__ void __launch_bounds__(64 * M) k_batch_current(const AxionArgs<T>* __restrict__ args, BatchList L) {
+    const int b = blockIdx.x;
+    const int k = batch_find(L, b);
+    const AxionArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int xbs = (a.g.nx + 63) / 64;
+    axion_current_body<T, M>(a, local % xbs, (local / xbs) * L.rows, L.rows);
+}
+
+template <typename T>
+hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (M) {
+#define QDS_BC(MM) case MM: hipLaunchKernelGGL((k_batch_current<T, MM>), dim3(blocks), dim3(64 * MM), 0, s, args, L); break;
+        QDS_BC(1) QDS_BC(2) QDS_BC(3) QDS_BC(4)
+#undef QDS_BC
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t batch_current<double>(const AxionArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_current<float>(const AxionArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t axion_current_w<double>(const AxionArgs<double>&, hipStream_t);
 template hipError_t axion_current_w<float>(const AxionArgs<float>&, hipStream_t);
 

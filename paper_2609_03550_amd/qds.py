@@ -99,6 +99,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_dot.restype = i32
     lib.qds_loss_eval.argtypes = [vp, vp, ctypes.POINTER(Loss), vp, vp, vp]
     lib.qds_loss_eval.restype = i32
+    lib.qds_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.qds_batch_create.restype = i32
+    lib.qds_batch_run.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion),
+                                  ctypes.POINTER(i64), i32, i32, vp]
+    lib.qds_batch_run.restype = i32
+    lib.qds_batch_get_tiles.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qds_batch_get_tiles.restype = i32
+    lib.qds_batch_set_tiles.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.qds_batch_set_tiles.restype = i32
+    lib.qds_batch_last_error.argtypes = [vp]
+    lib.qds_batch_last_error.restype = ctypes.c_char_p
+    lib.qds_batch_destroy.argtypes = [vp]
+    lib.qds_batch_destroy.restype = i32
     return lib
 
 
@@ -119,6 +132,12 @@ class QDSError(RuntimeError):
 def _check(status: int, handle) -> None:
     if status != QDS_OK:
         msg = lib().qds_last_error(handle).decode()
+        raise QDSError(f"libqds status {status}: {msg}")
+
+
+def _bcheck(status: int, batch) -> None:
+    if status != QDS_OK:
+        msg = lib().qds_batch_last_error(batch).decode()
         raise QDSError(f"libqds status {status}: {msg}")
 
 
@@ -329,6 +348,62 @@ class Solver:
         if getattr(self, "h", None) is not None and self.h.value:
             lib().qds_destroy(self.h)
             self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+NTILES = 10
+TILE_A1, TILE_CUR1, TILE_EM0, TILE_EM1 = 0, 4, 8, 9
+
+
+class Batch:
+    """Many independent solvers advanced together by qds_batch_run: one launch
+    per kernel class per step over all running instances, ``graph_steps``
+    steps per captured HIP graph."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (ctypes.c_void_p * n)(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        _bcheck(lib().qds_batch_create(arr, n, ctypes.byref(h)), None)
+        self.b = h
+
+    def run(self, n_steps, graph_steps: int = 16, tune: bool = False, stream=None) -> None:
+        n = len(self.solvers)
+        if isinstance(n_steps, int):
+            n_steps = [n_steps] * n
+        states = (State * n)()
+        cur = (Current * n)()
+        ax = (Axion * n)()
+        for k, s in enumerate(self.solvers):
+            ctypes.memmove(ctypes.byref(states[k]), ctypes.byref(s.state), ctypes.sizeof(State))
+            ctypes.memmove(ctypes.byref(cur[k]), ctypes.byref(s.cur), ctypes.sizeof(Current))
+            ctypes.memmove(ctypes.byref(ax[k]), ctypes.byref(s.ax), ctypes.sizeof(Axion))
+        steps = (ctypes.c_int64 * n)(*[int(v) for v in n_steps])
+        _bcheck(lib().qds_batch_run(self.b, states, cur, ax, steps, int(graph_steps), 1 if tune else 0,
+                                    _stream_ptr(stream)), self.b)
+        for k, s in enumerate(self.solvers):
+            ctypes.memmove(ctypes.byref(s.state), ctypes.byref(states[k]), ctypes.sizeof(State))
+
+    def tiles(self):
+        t = (ctypes.c_int32 * NTILES)()
+        tuned = ctypes.c_int32()
+        _bcheck(lib().qds_batch_get_tiles(self.b, t, ctypes.byref(tuned)), self.b)
+        return list(t), bool(tuned.value)
+
+    def set_tiles(self, tiles) -> None:
+        t = (ctypes.c_int32 * NTILES)(*[int(v) for v in tiles])
+        _bcheck(lib().qds_batch_set_tiles(self.b, t), self.b)
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            lib().qds_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -1,0 +1,154 @@
+"""Batched forward (qds_batch_run): every instance of a batch advances exactly
+as it does alone under qds_step (bit for bit, whatever the graph length, the
+tiling or the autotuner's choice), and matches the oracle."""
+import pytest
+import torch
+
+from paper_2609_03550_amd import inputs as I
+import parity_tools as P
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": (1e-12, 1e-13), "f32": (1e-5, 1e-6)}
+
+
+def _solvers(wls, dtype):
+    from paper_2609_03550_amd import qds
+    out = []
+    for wl in wls:
+        s = qds.Solver(wl, dtype=dtype)
+        s.load_pulses()
+        out.append(s)
+    torch.cuda.synchronize()
+    return out
+
+
+def _twins(solvers):
+    """Independent solvers holding copies of the given solvers' states."""
+    from paper_2609_03550_amd import qds
+    out = []
+    for s in solvers:
+        t = qds.Solver(s.wl, dtype=s.dtype)
+        t.bufs[t.state.cur].copy_(s.bufs[s.state.cur])
+        out.append(t)
+    torch.cuda.synchronize()
+    return out
+
+
+def _identical(a, b):
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert x.n == y.n
+        assert torch.equal(x.bufs[x.state.cur], y.bufs[y.state.cur]), x.wl.name
+
+
+def _small(count=6, seed=11, scale=0.04):
+    return I.batched_instances(count, seed, scale)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_equals_one_at_a_time(dtype):
+    from paper_2609_03550_amd import qds
+    wls = _small()
+    bs = _solvers(wls, dtype)
+    solo = _twins(bs)
+    steps = [wl.steps for wl in wls]
+    qds.Batch(bs).run(steps, graph_steps=8)
+    for s, n in zip(solo, steps):
+        s.step(n)
+    _identical(bs, solo)
+    assert [s.n for s in bs] == steps
+
+
+@pytest.mark.parametrize("graph_steps", [0, 1, 5])
+def test_graph_length_does_not_change_results(graph_steps):
+    from paper_2609_03550_amd import qds
+    wls = _small(5, 12)
+    steps = [9, 0, 4, 13, 6]
+    ref = _solvers(wls, "f64")
+    bs = _twins(ref)
+    qds.Batch(ref).run(steps, graph_steps=16)
+    qds.Batch(bs).run(steps, graph_steps=graph_steps)
+    _identical(bs, ref)
+    assert bs[1].n == 0
+
+
+@pytest.mark.parametrize("rows", [1, 3, 32])
+def test_tiling_does_not_change_results(rows):
+    from paper_2609_03550_amd import qds
+    wls = _small(4, 13)
+    ref = _solvers(wls, "f64")
+    bs = _twins(ref)
+    qds.Batch(ref).run(7, graph_steps=4)
+    b = qds.Batch(bs)
+    b.set_tiles([rows] * qds.NTILES)
+    b.run(7, graph_steps=4)
+    _identical(bs, ref)
+
+
+def test_autotuner_picks_candidates_and_keeps_results():
+    from paper_2609_03550_amd import qds
+    wls = _small(5, 14)
+    ref = _solvers(wls, "f32")
+    bs = _twins(ref)
+    qds.Batch(ref).run(12, graph_steps=4)
+    b = qds.Batch(bs)
+    assert b.tiles()[1] is False
+    b.run(12, graph_steps=4, tune=True)
+    tiles, tuned = b.tiles()
+    assert tuned
+    assert all(t in (4, 8, 16, 32) for t in tiles[:4] + tiles[8:])
+    assert all(t in (1, 2, 4, 8) for t in tiles[4:8])
+    _identical(bs, ref)
+    # a second run reuses the chosen tiles
+    b.run(3, graph_steps=2, tune=True)
+    assert b.tiles()[0] == tiles
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_matches_oracle(dtype):
+    from paper_2609_03550_amd import qds
+    wls = _small(4, 15, 0.03)
+    bs = _solvers(wls, dtype)
+    steps = [5, 9, 3, 7]
+    qds.Batch(bs).run(steps, graph_steps=3)
+    tol, floor = TOL[dtype]
+    for s, n in zip(bs, steps):
+        ora = P.oracle_run(s.wl, n)
+        P.compare_states(s.fields(), ora, tol, floor, by_group=(dtype == "f32"))
+
+
+def test_batch_rejects_bad_arguments():
+    from paper_2609_03550_amd import qds
+    wls = _small(2, 16)
+    bs = _solvers(wls, "f64")
+    with pytest.raises(qds.QDSError, match="twice"):
+        qds.Batch([bs[0], bs[0]])
+    w32 = qds.Solver(wls[1], dtype="f32")
+    with pytest.raises(qds.QDSError, match="dtype"):
+        qds.Batch([bs[0], w32])
+    win = qds.Solver(I.driven_window(128, 16, 4), dtype="f64")
+    with pytest.raises(qds.QDSError, match="window"):
+        qds.Batch([bs[0], win])
+    b = qds.Batch(bs)
+    with pytest.raises(qds.QDSError, match="negative"):
+        b.run([1, -1])
+    with pytest.raises(qds.QDSError, match="tile"):
+        b.set_tiles([0] * qds.NTILES)
+
+
+def test_full_size_batch_equals_one_at_a_time_and_oracle_sample():
+    """The 64 uneven instances at full size, FP32: three batched steps (a graph
+    of two and one of one) equal three one-at-a-time steps of every instance;
+    the smallest instance also matches the oracle."""
+    from paper_2609_03550_amd import qds
+    wls = I.batched_instances(64, 4)
+    bs = _solvers(wls, "f32")
+    solo = _twins(bs)
+    b = qds.Batch(bs)
+    b.run(3, graph_steps=2)
+    for s in solo:
+        s.step(3)
+    _identical(bs, solo)
+    k = min(range(64), key=lambda q: wls[q].nx * wls[q].nr * wls[q].nmodes)
+    ora = P.oracle_run(wls[k], 3)
+    P.compare_states(bs[k].fields(), ora, 1e-5, 1e-6, by_group=True)
