@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-mode updates/s + % HBM peak (QDS+KG); fwd+adjoint vs fwd time"
 HBM_PEAK_GBPS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_kernel_a_axion_8192x256x3_f64.json")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
 def plane_accesses(wl, kernel):
@@ -59,24 +59,30 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current"}
+
+
 def source_digest():
+    """Digest of the kernel sources the HBM counters depend on."""
     h = hashlib.sha256()
-    for f in ("qds_fused.hip", "qds_kernels.hpp", "qds_common.hpp"):
+    for f in ("qds_fused.hip", "qds_stages.hip", "qds_stage_ops.hpp", "qds_kernels.hpp", "qds_common.hpp"):
         with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(wl, dtype, launches_cells):
-    """HBM bytes per launch of kernel A from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+def measured_traffic(wl, dtype, kernel):
+    """HBM bytes per launch of one fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), if it
+    was taken on the current kernel sources for this workload and dtype."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{wl.name}_{dtype}.json")
+    if not os.path.exists(path):
         return None
-    with open(PROFILE_TRAFFIC) as f:
+    with open(path) as f:
         d = json.load(f)
     if d.get("source_digest") != source_digest() or d.get("workload") != wl.name or d.get("dtype") != dtype:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(KERNEL_KEYS[kernel], {}).get("hbm_bytes_per_launch")
 
 
 def adjoint_ratio(dtype, steps, ckpt):
@@ -106,6 +112,46 @@ def adjoint_ratio(dtype, steps, ckpt):
     t_adj = time.perf_counter() - t0
     return {"workload": wl.name, "steps": steps, "ckpt_every": ckpt, "dtype": dtype, "fwd_s": t_fwd,
             "fwd_adj_s": t_adj, "ratio": t_adj / t_fwd, "loss": L}
+
+
+def batched_leg(steps, graph_steps, count=64):
+    """The 64 uneven single-precision instances: ``steps`` batched steps
+    (graphs of ``graph_steps`` steps, tiles from the autotuner) against the
+    same steps taken one instance at a time with qds_step."""
+    import torch
+    from paper_2609_03550_amd import inputs as I
+    from paper_2609_03550_amd import qds
+    wls = I.batched_instances(count, 4)
+    bs = []
+    for wl in wls:
+        s = qds.Solver(wl, dtype="f32")
+        s.load_pulses()
+        bs.append(s)
+    cells = sum(wl.cell_modes for wl in wls)
+    b = qds.Batch(bs)
+    b.run(8, graph_steps=graph_steps, tune=True)       # the autotuner's trial steps
+    b.run(graph_steps, graph_steps=graph_steps)        # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, graph_steps=graph_steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for s in bs:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in bs:
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    tiles, tuned = b.tiles()
+    b.close()
+    for s in bs:
+        s.close()
+    return {"instances": count, "dtype": "f32", "cell_modes_per_step": cells, "steps": steps,
+            "graph_steps": graph_steps, "tiles": tiles, "tuned": tuned,
+            "batched_updates_per_s": cells * steps / t_batch, "one_at_a_time_updates_per_s": cells * steps / t_solo,
+            "speedup": t_solo / t_batch}
 
 
 def cpu_baseline(wl, seconds_target=15.0):
@@ -141,6 +187,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward + adjoint timing (0 skips it)")
     ap.add_argument("--ckpt-every", type=int, default=45)
+    ap.add_argument("--batched-steps", type=int, default=40,
+                    help="steps of the 64-instance batched comparison (0 skips it)")
+    ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM counters)")
     args = ap.parse_args()
@@ -193,7 +242,7 @@ def main():
     if not s.fused:
         alg_bytes = sum(plane_accesses(wl, q) for q in range(3)) * eb * cells
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    traffic = measured_traffic(wl, args.dtype, cells) if (s.fused and k == 0) else None
+    traffic = measured_traffic(wl, args.dtype, k) if s.fused else None
     # whole-step effective bandwidth against the one-read-one-write byte model
     nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
     step_bytes = 2 * nplanes * eb * cells
@@ -230,6 +279,10 @@ def main():
         adj = adjoint_ratio(args.dtype, args.adjoint_steps, args.ckpt_every)
         out["fwd_adj_over_fwd"] = adj["ratio"]
         out["adjoint"] = adj
+        torch.cuda.empty_cache()
+    if args.batched_steps > 0:
+        out["batched"] = batched_leg(args.batched_steps, args.graph_steps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
