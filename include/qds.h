@@ -20,7 +20,10 @@
  *  - Work is enqueued on ``stream`` (a hipStream_t; NULL = the null stream) and
  *    is asynchronous; argument errors are returned synchronously before
  *    anything is enqueued.  A launch failure is returned as QDS_EHIP.
- *  - A handle must not be used from two host threads at once.
+ *  - A handle must not be used from two host threads at once, and its calls
+ *    must be ordered on the device: issue them on one stream, or synchronise
+ *    before switching streams (the handle keeps a device-side argument table
+ *    that a call may refresh).
  *  - On any error, qds_last_error(handle) holds a message (never NULL).
  */
 #ifndef QDS_H

@@ -13,8 +13,10 @@ using namespace qdsi;
 
 namespace {
 
+// Fused steps with a prescribed drive: argument blocks passed by value (the
+// step counter and window offset change every step).
 template <typename T>
-qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s) {
+qds_status fused_steps_drive(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s) {
     for (int64_t it = 0; it < n_steps; ++it) {
         const int ia = st->cur, ib = 1 - st->cur;
         const qds::FusedArgs<T> a = fused_args<T>(c, p0, st->buf[ia], st->buf[ib], st->step, st->window);
@@ -24,7 +26,6 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
         if (ev) hipEventRecord(ev[1], s);
         if (p0.arem) {
-            // axion current at the source points of the regenerated set
             const qds::AxionArgs<T> ax = axion_args<T>(c, p0, st->buf[ia], st->buf[ib]);
             ev = c->timing ? timing_pair(c, 2) : nullptr;
             if (ev) hipEventRecord(ev[0], s);
@@ -44,11 +45,108 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
     return QDS_OK;
 }
 
+// Makes the device argument table current for the state buffers of st
+// (uploaded on the stream only when it changed).
+template <typename T>
+qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0, hipStream_t s, KTab<T>** dev) {
+    // the table depends on the two buffers, the physics and the tile height only
+    double key[16];
+    memset(key, 0, sizeof(key));
+    memcpy(&key[0], &st->buf[0], sizeof(void*));
+    memcpy(&key[1], &st->buf[1], sizeof(void*));
+    key[2] = p0.wp2; key[3] = p0.ma2; key[4] = p0.s_phi; key[5] = p0.s_j;
+    key[6] = double(p0.bx0.re); key[7] = double(p0.bx0.im); key[8] = double(p0.br1.re); key[9] = double(p0.br1.im);
+    key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im); key[12] = double(c->rows);
+    if (!c->ktab_dev) {
+        c->ktab_bytes = sizeof(KTab<double>);
+        if (hipMalloc(&c->ktab_dev, c->ktab_bytes) != hipSuccess) {
+            c->ktab_dev = nullptr;
+            return fail(c, QDS_ENOMEM, "hipMalloc of the argument table failed%s");
+        }
+        if (hipHostMalloc(&c->ktab_pin, c->ktab_bytes, hipHostMallocDefault) != hipSuccess) {
+            c->ktab_pin = nullptr;
+            return fail(c, QDS_ENOMEM, "hipHostMalloc of the argument table failed%s");
+        }
+        if (hipEventCreateWithFlags(&c->ktab_ev, hipEventDisableTiming) != hipSuccess)
+            return fail(c, QDS_EHIP, "event creation failed%s");
+        c->ktab_valid = false;
+    }
+    *dev = static_cast<KTab<T>*>(c->ktab_dev);
+    if (c->ktab_valid && memcmp(key, c->ktab_key, sizeof(key)) == 0) return QDS_OK;
+    KTab<T> t;
+    memset(&t, 0, sizeof(t));
+    for (int q = 0; q < 2; ++q) {
+        t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q], 0, 0);
+        t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
+    }
+    const int strips = qds::fused_strips(c->g.nx);
+    const int chunks = (c->g.nr + 1 + c->rows - 1) / c->rows;
+    t.idx[0] = t.idx[1] = 0;
+    t.firstA[1] = strips * chunks;
+    t.firstC[1] = ((c->g.nx + 63) / 64) * (c->g.nr + 1);
+    t.firstB[1] = strips * chunks * c->M;
+    // the staging copy may still be read by the previous upload
+    if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
+        return fail(c, QDS_EHIP, "argument table upload failed%s");
+    memcpy(c->ktab_pin, &t, sizeof(t));
+    hipError_t e = hipMemcpyAsync(c->ktab_dev, c->ktab_pin, sizeof(t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(c, QDS_EHIP, "argument table upload failed: %s", hipGetErrorString(e));
+    hipEventRecord(c->ktab_ev, s);
+    memcpy(c->ktab_key, key, sizeof(key));
+    c->ktab_valid = true;
+    return QDS_OK;
+}
+
+template <typename T>
+qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s,
+                       bool by_value) {
+    if (p0.drive.on || by_value) return fused_steps_drive<T>(c, st, p0, n_steps, s);
+    KTab<T>* K;
+    qds_status r = sync_ktab<T>(c, st, p0, s, &K);
+    if (r != QDS_OK) return r;
+    const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
+    auto list = [&](const int* first_dev, int rows) {
+        qds::BatchList L;
+        L.idx = K->idx;
+        L.first = first_dev;
+        L.n = 1;
+        L.rows = rows;
+        return L;
+    };
+    const qds::BatchList LA = list(K->firstA, c->rows), LC = list(K->firstC, 1), LB = list(K->firstB, c->rows);
+    for (int64_t it = 0; it < n_steps; ++it) {
+        const int q = st->cur;
+        const qds::FusedArgs<T>* fa = K->fa + q;
+        hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
+        if (ev) hipEventRecord(ev[0], s);
+        hipError_t e = p0.axion ? qds::batch_a<T>(fa, LA, c->M, host.firstA[1], s)
+                                : qds::batch_em<T>(fa, LB, 0, host.firstB[1], s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (ev) hipEventRecord(ev[1], s);
+        if (p0.arem) {
+            ev = c->timing ? timing_pair(c, 2) : nullptr;
+            if (ev) hipEventRecord(ev[0], s);
+            e = qds::batch_current<T>(K->xa + q, LC, c->M, host.firstC[1], s);
+            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            if (ev) hipEventRecord(ev[1], s);
+            ev = c->timing ? timing_pair(c, 1) : nullptr;
+            if (ev) hipEventRecord(ev[0], s);
+            e = qds::batch_em<T>(fa, LB, 1, host.firstB[1], s);
+            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            if (ev) hipEventRecord(ev[1], s);
+        }
+        st->cur = 1 - q;
+        if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
+        st->step += 1;
+    }
+    return QDS_OK;
+}
+
 template <typename T>
 qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
-                     hipStream_t s) {
+                     hipStream_t s, bool by_value = false) {
     qds::StepPlan<T> p = make_plan<T>(c, J, ax);
-    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
+    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s, by_value);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
         int a = st->cur, b = 1 - st->cur;
@@ -119,7 +217,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     QDS_TRY(hipMemcpyAsync(W.buf[0], u0->buf[u0->cur], S, hipMemcpyDeviceToDevice, s));
     for (int64_t n = 0; n < N; ++n) {
         if (n % C == 0) QDS_TRY(hipMemcpyAsync(ck + size_t(n / C) * S, W.buf[W.cur], S, hipMemcpyDeviceToDevice, s));
-        qds_status st = run_steps<T>(c, &W, J, ax, 1, s);
+        qds_status st = run_steps<T>(c, &W, J, ax, 1, s, true);
         if (st != QDS_OK) return st;
     }
     // loss and its gradient at step N
@@ -144,7 +242,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
             R.cur = 0;
             R.step = u0->step + n0 + k;
             R.window = 0;
-            qds_status st = run_steps<T>(c, &R, J, ax, 1, s);
+            qds_status st = run_steps<T>(c, &R, J, ax, 1, s, true);
             if (st != QDS_OK) return st;
         }
         for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
@@ -410,6 +508,12 @@ qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
     for (hipEvent_t e : h->pool) hipEventDestroy(e);
     if (h->scratch) hipFree(h->scratch);
+    if (h->ktab_ev) {
+        hipEventSynchronize(h->ktab_ev);
+        hipEventDestroy(h->ktab_ev);
+    }
+    if (h->ktab_dev) hipFree(h->ktab_dev);
+    if (h->ktab_pin) hipHostFree(h->ktab_pin);
     delete h;
     return QDS_OK;
 }

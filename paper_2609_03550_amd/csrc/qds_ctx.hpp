@@ -25,6 +25,14 @@ struct qds_ctx {
     std::vector<hipEvent_t> pool;
     size_t used;
     std::vector<int> tag;
+    // kernel argument table of the fused kernels (device copy, pinned host
+    // staging and the event that marks the end of its last upload)
+    void* ktab_dev;
+    void* ktab_pin;
+    size_t ktab_bytes;
+    hipEvent_t ktab_ev;
+    bool ktab_valid;
+    double ktab_key[16];     // buffers and physics the uploaded table was built for
     char err[256];
 };
 
@@ -83,7 +91,9 @@ inline qds::Geo geo(const qds_ctx* c) {
 // runs the staged kernels (which shift after the whole step).
 inline bool fused_ok(const qds_ctx* c) {
     const bool window_arem = c->g.x_bc == QDS_X_WINDOW && (c->g.content & QDS_HAS_AREM);
-    return c->M <= 4 && !window_arem;
+    // the fused kernels address a plane with 32-bit byte offsets
+    const bool small_planes = c->plane_elems * c->elem_bytes < (size_t(1) << 32);
+    return c->M <= 4 && !window_arem && small_planes;
 }
 
 inline bool use_fused(const qds_ctx* c) {
@@ -176,5 +186,15 @@ inline qds_status check_state(qds_ctx* c, const qds_state* st) {
     if (st->step >= (int64_t(1) << 31)) return fail(c, QDS_ESTATE, "step counter out of range%s");
     return QDS_OK;
 }
+
+// Argument table of the fused kernels for one handle: entry q is the step that
+// reads state buffer q and writes buffer 1 - q; single-entry launch lists.
+template <typename T>
+struct KTab {
+    qds::FusedArgs<T> fa[2];
+    qds::AxionArgs<T> xa[2];
+    int idx[2];
+    int firstA[2], firstC[2], firstB[2];
+};
 
 }  // namespace qdsi

@@ -22,6 +22,22 @@ namespace fused {
 constexpr int WAVE = 64;
 constexpr int OWN = kFusedOwn;   // owned cells per wave (halo lane at each end)
 
+// Byte offset of element (m, row, c) inside a plane.  A plane is below 4 GiB
+// (checked when the handle is created), so one 32-bit per-lane offset serves
+// every plane: the loads take the uniform plane base in scalar registers.
+template <typename T>
+__device__ __forceinline__ uint32_t eoff(const Geo& g, int m, int row, int c) {
+    return (uint32_t(m * (g.nr + 1) + row) * uint32_t(g.ld) + uint32_t(c)) * uint32_t(sizeof(cx<T>));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ldo(const cx<T>* p, uint32_t o) {
+    return ld(reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) + o));
+}
+template <typename T>
+__device__ __forceinline__ void sto(cx<T>* p, uint32_t o, cx<T> v) {
+    st(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(p) + o), v);
+}
+
 template <typename T>
 struct XAcc {
     // column helpers for one lane: H cell i, integer columns i and i+1
@@ -29,14 +45,15 @@ struct XAcc {
     int i;
     int i1;          // column of x_{i+1} (wrapped if periodic, -1 outside)
     int ir;          // destination column of right movers (i+1), -1 outside
-    __device__ __forceinline__ size_t at(int m, int row, int c) const {
-        return (size_t(m) * size_t(nr1) + size_t(row)) * size_t(ld) + size_t(c);
+    __device__ __forceinline__ uint32_t ro(int m, int row) const {
+        return uint32_t(m * nr1 + row) * uint32_t(ld) * uint32_t(sizeof(cx<T>));
     }
-    __device__ __forceinline__ cx<T> L(const cx<T>* p, int m, int row) const { return ld_(p + at(m, row, i)); }
+    __device__ __forceinline__ cx<T> L(const cx<T>* p, int m, int row) const {
+        return ldo(p, ro(m, row) + uint32_t(i) * uint32_t(sizeof(cx<T>)));
+    }
     __device__ __forceinline__ cx<T> R(const cx<T>* p, int m, int row) const {
-        return i1 >= 0 ? ld_(p + at(m, row, i1)) : zero<T>();
+        return i1 >= 0 ? ldo(p, ro(m, row) + uint32_t(i1) * uint32_t(sizeof(cx<T>))) : zero<T>();
     }
-    static __device__ __forceinline__ cx<T> ld_(const cx<T>* p) { return qds::ld(p); }
 };
 
 template <typename T>
@@ -102,11 +119,28 @@ struct Ctx {
     XAcc<T> x;
     Out o;
     T h, dr;
+    T inv_dr, inv_2dr;   // 1/dr, 1/(2 dr)
+    T kap, cR;           // outer-ghost centring: (dr - h)/(dr + h), 2 h dr/(dr + h)
+    T inv_2h;            // 1/(2 h)
     T wp2h;
     int plasma;
     Drive drive;
     int64_t n, w;
 };
+
+// reciprocal radii of one march step: 1/r_{j+1}, 1/r_{j+1/2}, 1/r_j (0 on the axis)
+template <typename T>
+struct RowInv {
+    T irJ1, irK, irJ;
+};
+template <typename T>
+__device__ __forceinline__ RowInv<T> row_inv(const Ctx<T>& c, int j) {
+    RowInv<T> q;
+    q.irJ1 = T(1) / (T(j + 1) * c.dr);
+    q.irK = T(1) / ((T(j) + T(0.5)) * c.dr);
+    q.irJ = j > 0 ? T(1) / (T(j) * c.dr) : T(0);
+    return q;
+}
 
 // load the row j+1 of the window (T_r on K = j+1 or the ghost B_theta, T_theta
 // on J = j+1, E_x^{n-1/2} on J = j+1, B_x^{n-1/2} on K = j+1)
@@ -136,12 +170,12 @@ template <typename T>
 __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write) {
     cx<T> v = zero<T>();
     if (!c.live) {
-        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0) st(s.ojx + c.g.at(c.m, row, c.o.col(c.i)), v);
+        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), v);
         return v;
     }
     if (c.plasma) {
         cx<T> jn = c.x.L(s.jx, c.m, row) + c.wp2h * ex0;
-        if (write && c.owner && c.o.col(c.i) >= 0) st(s.ojx + c.g.at(c.m, row, c.o.col(c.i)), jn);
+        if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jn);
         v = jn;
     }
     if (s.jxa) v = v + c.x.L(s.jxa, c.m, row);
@@ -151,37 +185,35 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
 
 // E_x^{n+1/2} at J = j+1 from the window (Eqs. Ex_update, Gammax_explicit, axis_Ex)
 template <typename T>
-__device__ __forceinline__ cx<T> em_ex_new(const Ctx<T>& c, const EmWin<T>& W, int jj, cx<T> jx) {
-    const T h = c.h, dr = c.dr;
+__device__ __forceinline__ cx<T> em_ex_new(const Ctx<T>& c, const EmWin<T>& W, int jj, cx<T> jx, T irj) {
+    const T h = c.h;
     const int m = c.m;
     if (!c.live || (!c.g.open_r && jj == c.g.nr)) return zero<T>();
     if (jj == 0) {
         if (m != 0) return zero<T>();
         cx<T> b = T(0.25) * ((W.rpa[1] - W.rma[1]) + (W.rpb[1] - W.rmb[1]));
-        return W.ex0[1] + h * ((T(4) / dr) * b - jx);
+        return W.ex0[1] + h * ((T(4) * c.inv_dr) * b - jx);
     }
-    const T rj = T(jj) * dr;
     cx<T> lo0 = T(0.5) * (W.rpa[0] - W.rma[0]), lo1 = T(0.5) * (W.rpb[0] - W.rmb[0]);
     cx<T> hi0 = T(0.5) * (W.rpa[1] - W.rma[1]), hi1 = T(0.5) * (W.rpb[1] - W.rmb[1]);
     cx<T> bavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
-    cx<T> db = (T(1) / (T(2) * dr)) * ((hi0 + hi1) - (lo0 + lo1));
+    cx<T> db = c.inv_2dr * ((hi0 + hi1) - (lo0 + lo1));
     cx<T> bravg = T(0.25) * ((W.tpa[1] - W.tma[1]) + (W.tpb[1] - W.tmb[1]));
-    cx<T> gx = (T(1) / rj) * bavg + db + imul(T(m) / rj, bravg) - jx;
+    cx<T> gx = irj * bavg + db + imul(T(m) * irj, bravg) - jx;
     return W.ex0[1] + h * gx;
 }
 
 // B_x^{n+1/2} at K = j (Eqs. Ex_update, Phix_explicit)
 template <typename T>
-__device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, int k) {
+__device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, T irk) {
     if (!c.live) return zero<T>();
-    const T h = c.h, dr = c.dr;
-    const T rk = (T(k) + T(0.5)) * dr;
+    const T h = c.h;
     cx<T> lo0 = T(0.5) * (W.tpa[0] + W.tma[0]), lo1 = T(0.5) * (W.tpb[0] + W.tmb[0]);
     cx<T> hi0 = T(0.5) * (W.tpa[1] + W.tma[1]), hi1 = T(0.5) * (W.tpb[1] + W.tmb[1]);
     cx<T> eavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
-    cx<T> de = (T(1) / (T(2) * dr)) * ((hi0 + hi1) - (lo0 + lo1));
+    cx<T> de = c.inv_2dr * ((hi0 + hi1) - (lo0 + lo1));
     cx<T> eravg = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
-    cx<T> fx = -((T(1) / rk) * eavg + de) - imul(T(c.m) / rk, eravg);
+    cx<T> fx = -(irk * eavg + de) - imul(T(c.m) * irk, eravg);
     return W.bx0[0] + h * fx;
 }
 
@@ -193,7 +225,7 @@ __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, co
     cx<T> ja = c.x.L(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
     cx<T> jb = c.x.R(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpb[slot] + W.tmb[slot]));
     if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
-    if (write && c.owner && c.o.col(c.i) >= 0) st(s.ojt + c.g.at(c.m, row, c.o.col(c.i)), ja);
+    if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
     if (c.x.i1 < 0) jb = zero<T>();
     return T(0.5) * (ja + jb);
 }
@@ -201,7 +233,8 @@ __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, co
 // one march step of the electromagnetic set: outputs E_x(J=j+1), B_x(K=j)
 // (and the exterior ghost at j = nr-1), T_r(K=j), T_theta(J=j)
 template <typename T>
-__device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j, int r0, int r1) {
+__device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j, int r0, int r1,
+                                        const RowInv<T>& ri) {
     const Geo& g = c.g;
     const int m = c.m;
     const T h = c.h, dr = c.dr;
@@ -210,29 +243,28 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     // ---- E_x^{n+1/2} at J = j+1
     if (j + 1 <= g.nr) {
         W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1);
-        W.ex1[2] = em_ex_new(c, W, j + 1, W.jx_n1);
-        if (j + 1 >= r0 && j + 1 < r1 && wI) st(s.oex + g.at(m, j + 1, ocI), W.ex1[2]);
+        W.ex1[2] = em_ex_new(c, W, j + 1, W.jx_n1, ri.irJ1);
+        if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
         if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
     }
     if (j < 0) return;
     const bool own_row = j >= r0 && j < r1;
     // ---- B_x^{n+1/2} at K = j
     if (j < g.nr) {
-        W.bx1[1] = em_bx_new(c, W, j);
-        if (own_row && wI) st(s.obx + g.at(m, j, ocI), W.bx1[1]);
+        W.bx1[1] = em_bx_new(c, W, ri.irK);
+        if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
     }
     // ---- exterior ghost B_x^{n+1/2} at r_{nr+1/2} (Eq. em_r_open_bx)
     if (j == g.nr - 1) {
         cx<T> gh = zero<T>();
         if (g.open_r && c.live) {
             const int N = g.nr;
-            const T rN = T(N) * dr;
-            const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+            const T kap = c.kap, cR = c.cR;
             cx<T> br_a = T(0.5) * (W.tpa[1] - W.tma[1]), br_b = T(0.5) * (W.tpb[1] - W.tmb[1]);
-            cx<T> rx = (T(0.5) / h) * (br_b - br_a);
+            cx<T> rx = c.inv_2h * (br_b - br_a);
             cx<T> ea = T(0.25) * ((W.tpa[1] + W.tma[1]) + (W.tpb[1] + W.tmb[1]));
             cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
-            rx = rx - (T(1) / (T(2) * rN)) * (ea + imul(T(m), ra));
+            rx = rx - (T(0.5) * ri.irJ1) * (ea + imul(T(m), ra));
             cx<T> jt = zero<T>();
             if (c.plasma) jt = em_jt_avg(c, s, W, N, 1, false);
             if (s.jta) jt = jt + c.x.L(s.jta, m, N);
@@ -240,7 +272,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
             gh = W.bx0[0] + kap * (W.bx0[1] - W.bx1[1]) + cR * rx;
         }
         W.bx1g = gh;
-        if (r1 == g.nr + 1 && wI) st(s.obx + g.at(m, g.nr, ocI), gh);
+        if (r1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
     }
     // ---- T_r transport on K = j
     if (j < g.nr) {
@@ -248,10 +280,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         cx<T> jra = zero<T>();
         if (c.plasma) {
             jra = c.x.L(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
-            if (own_row && wI) st(s.ojr + g.at(m, j, ocI), jra);
+            if (own_row && wI) sto(s.ojr, eoff<T>(g, m, j, ocI), jra);
         }
         if (c.live) {
-            const T rk = (T(j) + T(0.5)) * dr;
             cx<T> jr = zero<T>();
             if (c.plasma) {
                 cx<T> jrb = c.x.R(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpb[0] + W.rmb[0]));
@@ -259,8 +290,8 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
                 jr = T(0.5) * (jra + jrb);
             }
             if (s.jra) jr = jr + c.x.L(s.jra, m, j);
-            cx<T> gr = -imul(T(m) / rk, W.bx1[1]) - jr;
-            cx<T> pr = (T(1) / dr) * (W.ex1[2] - W.ex1[1]);
+            cx<T> gr = -imul(T(m) * ri.irK, W.bx1[1]) - jr;
+            cx<T> pr = c.inv_dr * (W.ex1[2] - W.ex1[1]);
             sp = h * (gr + pr);
             sm = h * (gr - pr);
         }
@@ -271,9 +302,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         W.n_rpa = (c.i == 0 && !g.per) ? zero<T>() : from_left;
         W.n_rmb = (c.x.i1 >= 0) ? from_right : zero<T>();
         if (own_row) {
-            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(s.otrp + g.at(m, j, c.o.col(c.x.ir)), W.n_rpb);
-            if (wI) st(s.otrm + g.at(m, j, ocI), W.n_rma);
-            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(s.otrp + g.at(m, j, c.o.col(0)), zero<T>());
+            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_rpb);
+            if (wI) sto(s.otrm, eoff<T>(g, m, j, ocI), W.n_rma);
+            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
         }
     }
     // ---- T_theta transport on J = j (exterior ghost B_x used at j = nr)
@@ -286,13 +317,12 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         if (c.live && !zrow) {
             cx<T> gt, pt;
             if (j == 0) {
-                gt = -(T(2) / dr) * W.bx1[1] - jt;
-                pt = imul(T(1) / dr, W.ex1[2]);
+                gt = -(T(2) * c.inv_dr) * W.bx1[1] - jt;
+                pt = imul(c.inv_dr, W.ex1[2]);
             } else {
-                const T rj = T(j) * dr;
                 cx<T> bhi = (j == g.nr) ? W.bx1g : W.bx1[1];
-                gt = -(T(1) / dr) * (bhi - W.bx1[0]) - jt;
-                pt = imul(T(m) / rj, W.ex1[1]);
+                gt = -c.inv_dr * (bhi - W.bx1[0]) - jt;
+                pt = imul(T(m) * ri.irJ, W.ex1[1]);
             }
             sp = h * (gt + pt);
             sm = h * (gt - pt);
@@ -309,9 +339,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         W.n_tpb = (c.x.i1 >= 0) ? from_right : zero<T>();
         W.n_tma = (c.i == 0 && !g.per) ? zero<T>() : from_left;
         if (own_row) {
-            if (wI) st(s.ottp + g.at(m, j, ocI), W.n_tpa);
-            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(s.ottm + g.at(m, j, c.o.col(c.x.ir)), W.n_tmb);
-            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(s.ottm + g.at(m, j, c.o.col(0)), zero<T>());
+            if (wI) sto(s.ottp, eoff<T>(g, m, j, ocI), W.n_tpa);
+            if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_tmb);
+            if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
         }
     }
 }
@@ -330,20 +360,20 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
     cx<T> out = zero<T>();
     if (g.open_r) {
         const T rN = T(N) * dr;
-        const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+        const T kap = c.kap, cR = c.cR;
         cx<T> I0 = T(0.5) * (W.rpa[0] - W.rma[0]);
         cx<T> I1 = T(0.5) * (W.n_rpa - W.n_rma);
         cx<T> G0 = T(0.5) * (W.rpa[1] - W.rma[1]);          // stored ghost (see em_load_next)
         cx<T> br = T(0.5) * (W.tpa[1] - W.tma[1]);          // B_r at (x_i, r_nr)
-        cx<T> dxer = (T(1) / (T(2) * h)) * (er_b - er_l);
+        cx<T> dxer = c.inv_2h * (er_b - er_l);
         cx<T> jxi = T(0.5) * (W.jx_nr + jx_l);
         cx<T> rt = -T(0.5) * dxer - (T(1) / (T(2) * rN)) * (T(0.5) * (I0 + G0) + imul(T(m), br)) + T(0.5) * jxi;
         out = I0 + kap * (G0 - I1) + cR * rt;
     }
     const int oc = c.o.col(c.i);
     if (c.owner && oc >= 0 && r1 == g.nr + 1) {
-        st(s.otrp + g.at(m, N, oc), out);
-        st(s.otrm + g.at(m, N, oc), zero<T>());
+        sto(s.otrp, eoff<T>(g, m, N, oc), out);
+        sto(s.otrm, eoff<T>(g, m, N, oc), zero<T>());
     }
 }
 
@@ -366,7 +396,7 @@ constexpr int NS = 6;
 // ---------------------------------------------------------------------------
 // kernel A: background set + axion
 // ---------------------------------------------------------------------------
-template <typename T, int M>
+template <typename T, int M, bool DRV>
 __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
     const Geo g = a.g;
     const int wave = threadIdx.x / WAVE;
@@ -394,9 +424,15 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     c.o.nx = g.nx;
     c.h = T(g.h);
     c.dr = T(g.dr);
+    c.inv_dr = T(1) / c.dr;
+    c.inv_2dr = T(0.5) * c.inv_dr;
+    c.kap = (c.dr - c.h) / (c.dr + c.h);
+    c.cR = T(2) * c.h * c.dr / (c.dr + c.h);
+    c.inv_2h = T(0.5) / c.h;
     c.wp2h = T(a.wp2 * g.h);
     c.plasma = a.plasma;
     c.drive = a.drive;
+    if (!DRV) c.drive.on = 0;     // compiled out: no prescribed drive
     c.n = a.n;
     c.w = a.w;
 
@@ -410,7 +446,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     cx<T> phw[3];     // phi^n at K = j-1, j, j+1
     const int m = wave;
     const T h = c.h, dr = c.dr;
-    const T kap = (dr - h) / (dr + h);
+    const T kap = c.kap;
     const int ocI = c.o.col(c.i);
     const bool wI = c.owner && ocI >= 0;
     const int jstart = max(r0 - 2, -1);
@@ -439,7 +475,8 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         else phw[2] = zero<T>();
         em_load_next(c, s, W, j);
         const cx<T> ex1_j = W.ex1[1];
-        em_step(c, s, W, j, r0, r1);
+        const RowInv<T> ri = row_inv(c, j);
+        em_step(c, s, W, j, r0, r1, ri);
         if (j < 0) continue;
         const bool own_row = j >= r0 && j < r1;
         if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
@@ -483,13 +520,12 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             conv_one<T, M>(A, B, m, Sa, T(1));
             if (!c.live) Sa = zero<T>();
             // ---------------- Gamma_a, T_a transport, phi (Eqs. Ta_plus/minus_update, phi_update)
-            const T rk = (T(j) + T(0.5)) * dr;
             cx<T> p = phw[1];
             cx<T> up = phw[2];
             cx<T> dn = (j > 0) ? phw[0] : zero<T>();
             if (c.live)
-                ga = (T(1) / (dr * dr)) * (up - T(2) * p + dn) + (T(1) / (T(2) * dr * rk)) * (up - dn)
-                     - (T(m * m) / (rk * rk) + T(a.ma2)) * p + T(a.s_phi) * Sa;
+                ga = (c.inv_dr * c.inv_dr) * (up - T(2) * p + dn) + (c.inv_2dr * ri.irK) * (up - dn)
+                     - (T(m * m) * ri.irK * ri.irK + T(a.ma2)) * p + T(a.s_phi) * Sa;
             cx<T> tap_a = c.x.L(a.tap, m, j), tap_b = c.x.R(a.tap, m, j);
             cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.R(a.tam, m, j);
             cx<T> nap_b = (c.x.i1 >= 0) ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
@@ -500,49 +536,49 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             cx<T> p1 = zero<T>();
             if (c.live) p1 = p + (h / T(4)) * (nap_a + nap_b + nam_a + nam_b);
             if (own_row) {
-                if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) st(a.otap + g.at(m, j, c.o.col(c.x.ir)), nap_b);
+                if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(a.otap, eoff<T>(g, m, j, c.o.col(c.x.ir)), nap_b);
                 if (wI) {
-                    st(a.otam + g.at(m, j, ocI), nam_a);
-                    st(a.ophi + g.at(m, j, ocI), p1);
+                    sto(a.otam, eoff<T>(g, m, j, ocI), nam_a);
+                    sto(a.ophi, eoff<T>(g, m, j, ocI), p1);
                 }
-                if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) st(a.otap + g.at(m, j, c.o.col(0)), zero<T>());
+                if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(a.otap, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
             }
             if (j == g.nr - 1 && wI && r1 == g.nr + 1) {
                 // exterior ghost phi at r_{nr+1/2}: outgoing-wave condition, two-level centring
                 cx<T> G = phw[2];
                 cx<T> Gn = G;
                 if (g.open_r) Gn = c.live ? (p + kap * (G - p1)) : zero<T>();
-                st(a.ophi + g.at(m, g.nr, ocI), Gn);
+                sto(a.ophi, eoff<T>(g, m, g.nr, ocI), Gn);
             }
         }
     }
     // moving window: the owner of the last cell zero-fills the last column
     if (a.window && c.owner && c.i == g.nx - 1) {
         for (int row = r0; row < r1; ++row) {
-            const size_t e = g.at(m, row, g.nx - 1);
-            st(s.otrp + e, zero<T>()); st(s.otrm + e, zero<T>()); st(s.ottp + e, zero<T>()); st(s.ottm + e, zero<T>());
-            st(s.oex + e, zero<T>()); st(s.obx + e, zero<T>());
-            if (c.plasma) { st(s.ojx + e, zero<T>()); st(s.ojr + e, zero<T>()); st(s.ojt + e, zero<T>()); }
-            st(a.ophi + e, zero<T>()); st(a.otap + e, zero<T>()); st(a.otam + e, zero<T>());
+            const uint32_t e = eoff<T>(g, m, row, g.nx - 1);
+            sto(s.otrp, e, zero<T>()); sto(s.otrm, e, zero<T>()); sto(s.ottp, e, zero<T>()); sto(s.ottm, e, zero<T>());
+            sto(s.oex, e, zero<T>()); sto(s.obx, e, zero<T>());
+            if (c.plasma) { sto(s.ojx, e, zero<T>()); sto(s.ojr, e, zero<T>()); sto(s.ojt, e, zero<T>()); }
+            sto(a.ophi, e, zero<T>()); sto(a.otap, e, zero<T>()); sto(a.otam, e, zero<T>());
         }
     }
 }
 
 // Kernel A entry points: FP64 keeps the full register file (one wave per SIMD,
 // no spills); FP32 fits two waves per SIMD.
-template <int M>
+template <int M, bool DRV>
 __global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) {
-    fused_a_body<double, M>(a, blockIdx.x, blockIdx.y, a.rows);
+    fused_a_body<double, M, DRV>(a, blockIdx.x, blockIdx.y, a.rows);
 }
-template <int M>
-__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M>(a, blockIdx.x, blockIdx.y, a.rows); }
+template <int M, bool DRV>
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
+k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M, DRV>(a, blockIdx.x, blockIdx.y, a.rows); }
 
 // ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void em_body(const FusedArgs<T>& a, int which, int strip, int chunk, int m, int rows) {
+template <typename T, int WHICH, bool DRV>
+__device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int chunk, int m, int rows) {
     const Geo g = a.g;
     const int lane = threadIdx.x;
     const int r0 = chunk * rows;
@@ -565,13 +601,18 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int which, int st
     c.o.nx = g.nx;
     c.h = T(g.h);
     c.dr = T(g.dr);
+    c.inv_dr = T(1) / c.dr;
+    c.inv_2dr = T(0.5) * c.inv_dr;
+    c.kap = (c.dr - c.h) / (c.dr + c.h);
+    c.cR = T(2) * c.h * c.dr / (c.dr + c.h);
+    c.inv_2h = T(0.5) / c.h;
     c.wp2h = T(a.wp2 * g.h);
     c.plasma = a.plasma;
     c.drive = a.drive;
-    if (which) c.drive.on = 0;
+    if (WHICH || !DRV) c.drive.on = 0;     // compiled out without a drive
     c.n = a.n;
     c.w = a.w;
-    const SetP<T>& s = which ? a.s1 : a.s0;
+    const SetP<T>& s = WHICH ? a.s1 : a.s0;
     EmWin<T> W;
     for (int q = 0; q < 2; ++q) {
         W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
@@ -586,22 +627,22 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int which, int st
     for (int j = jstart; j <= jend; ++j) {
         em_rotate(W);
         em_load_next(c, s, W, j);
-        em_step(c, s, W, j, r0, r1);
+        em_step(c, s, W, j, r0, r1, row_inv(c, j));
         if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
     }
     if (a.window && c.owner && c.i == g.nx - 1) {
         for (int row = r0; row < r1; ++row) {
-            const size_t e = g.at(m, row, g.nx - 1);
-            st(s.otrp + e, zero<T>()); st(s.otrm + e, zero<T>()); st(s.ottp + e, zero<T>()); st(s.ottm + e, zero<T>());
-            st(s.oex + e, zero<T>()); st(s.obx + e, zero<T>());
-            if (c.plasma) { st(s.ojx + e, zero<T>()); st(s.ojr + e, zero<T>()); st(s.ojt + e, zero<T>()); }
+            const uint32_t e = eoff<T>(g, m, row, g.nx - 1);
+            sto(s.otrp, e, zero<T>()); sto(s.otrm, e, zero<T>()); sto(s.ottp, e, zero<T>()); sto(s.ottm, e, zero<T>());
+            sto(s.oex, e, zero<T>()); sto(s.obx, e, zero<T>());
+            if (c.plasma) { sto(s.ojx, e, zero<T>()); sto(s.ojr, e, zero<T>()); sto(s.ojt, e, zero<T>()); }
         }
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
-    em_body<T>(a, which, blockIdx.x, blockIdx.y, blockIdx.z, a.rows);
+template <typename T, int WHICH, bool DRV>
+__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a) {
+    em_body<T, WHICH, DRV>(a, blockIdx.x, blockIdx.y, blockIdx.z, a.rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,32 +651,34 @@ __global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a, int which) {
 // ---------------------------------------------------------------------------
 template <typename T, int M>
 __device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ args, const BatchList& L) {
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
     const FusedArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
-    const int strips = fused_strips(a.g.nx);
-    fused_a_body<T, M>(a, local % strips, local / strips, L.rows);
+    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
+    // radial chunks fastest: consecutive tiles share halo rows
+    fused_a_body<T, M, false>(a, local / chunks, local % chunks, L.rows);
 }
 template <int M>
 __global__ void __launch_bounds__(WAVE * M) k_batch_a_f64(const FusedArgs<double>* __restrict__ args, BatchList L) {
     batch_a_body<double, M>(args, L);
 }
 template <int M>
-__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch_a_f32(const FusedArgs<float>* __restrict__ args, BatchList L) {
     batch_a_body<float, M>(args, L);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restrict__ args, BatchList L, int which) {
-    const int b = blockIdx.x;
+template <typename T, int WHICH>
+__global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restrict__ args, BatchList L) {
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
     const FusedArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
-    const int strips = fused_strips(a.g.nx);
-    const int per = strips * ((a.g.nr + 1 + L.rows - 1) / L.rows);
-    em_body<T>(a, which, local % strips, (local % per) / strips, local / per, L.rows);
+    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
+    const int m = local % a.g.M;                 // the modes of one tile run side by side
+    const int t = local / a.g.M;
+    em_body<T, WHICH, false>(a, t / chunks, t % chunks, m, L.rows);
 }
 
 }  // namespace fused
@@ -645,10 +688,14 @@ static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
     const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
     const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
     const size_t lds = size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
-    if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((fused::k_fused_a_f64<M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
-    else
-        hipLaunchKernelGGL((fused::k_fused_a_f32<M>), dim3(strips, chunks), dim3(fused::WAVE * M), lds, s, a);
+    const dim3 grd(strips, chunks), blk(fused::WAVE * M);
+    if constexpr (sizeof(T) == 8) {
+        if (a.drive.on) hipLaunchKernelGGL((fused::k_fused_a_f64<M, true>), grd, blk, lds, s, a);
+        else hipLaunchKernelGGL((fused::k_fused_a_f64<M, false>), grd, blk, lds, s, a);
+    } else {
+        if (a.drive.on) hipLaunchKernelGGL((fused::k_fused_a_f32<M, true>), grd, blk, lds, s, a);
+        else hipLaunchKernelGGL((fused::k_fused_a_f32<M, false>), grd, blk, lds, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -658,7 +705,10 @@ hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
     const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
     if (stage == 0) {
         if (!a.axion) {
-            hipLaunchKernelGGL(fused::k_fused_em<T>, dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a, 0);
+            if (a.drive.on)
+                hipLaunchKernelGGL((fused::k_fused_em<T, 0, true>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
+            else
+                hipLaunchKernelGGL((fused::k_fused_em<T, 0, false>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
             return hipGetLastError();
         }
         switch (a.g.M) {
@@ -669,7 +719,7 @@ hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
             default: return hipErrorInvalidValue;
         }
     }
-    hipLaunchKernelGGL(fused::k_fused_em<T>, dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a, 1);
+    hipLaunchKernelGGL((fused::k_fused_em<T, 1, false>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
     return hipGetLastError();
 }
 
@@ -695,7 +745,10 @@ hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int bloc
 template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fused::k_batch_em<T>, dim3(blocks), dim3(fused::WAVE), 0, s, args, L, which);
+    if (which)
+        hipLaunchKernelGGL((fused::k_batch_em<T, 1>), dim3(blocks), dim3(fused::WAVE), 0, s, args, L);
+    else
+        hipLaunchKernelGGL((fused::k_batch_em<T, 0>), dim3(blocks), dim3(fused::WAVE), 0, s, args, L);
     return hipGetLastError();
 }
 

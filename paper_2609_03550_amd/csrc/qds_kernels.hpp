@@ -154,7 +154,16 @@ struct BatchList {
     int rows;
 };
 
-// Instance of block b: the largest k with first[k] <= b.
+// Tile of block b of a launch of n blocks.  Workgroups are dispatched to the
+// 8 XCDs round-robin (block b on XCD b % 8); this gives each XCD a contiguous
+// run of tiles, so tiles that share halo rows and columns run on one L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, k = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Instance of tile b: the largest k with first[k] <= b.
 __device__ __forceinline__ int batch_find(const BatchList& L, int b) {
     int lo = 0, hi = L.n - 1;
     while (lo < hi) {

@@ -441,12 +441,12 @@ hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s) {
 }
 template <typename T, int M>
 __global__ void __launch_bounds__(64 * M) k_batch_current(const AxionArgs<T>* __restrict__ args, BatchList L) {
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
     const AxionArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
-    const int xbs = (a.g.nx + 63) / 64;
-    axion_current_body<T, M>(a, local % xbs, (local / xbs) * L.rows, L.rows);
+    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
+    axion_current_body<T, M>(a, local / chunks, (local % chunks) * L.rows, L.rows);
 }
 
 template <typename T>
