@@ -83,7 +83,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     const int chunks = (c->g.nr + 1 + c->rows - 1) / c->rows;
     t.idx[0] = t.idx[1] = 0;
     t.firstA[1] = strips * chunks;
-    t.firstC[1] = ((c->g.nx + 63) / 64) * (c->g.nr + 1);
+    t.firstC[1] = qds::current_strips(c->g.nx) * chunks;
     t.firstB[1] = strips * chunks * c->M;
     // the staging copy may still be read by the previous upload
     if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
@@ -113,7 +113,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
         L.rows = rows;
         return L;
     };
-    const qds::BatchList LA = list(K->firstA, c->rows), LC = list(K->firstC, 1), LB = list(K->firstB, c->rows);
+    const qds::BatchList LA = list(K->firstA, c->rows), LC = list(K->firstC, c->rows), LB = list(K->firstB, c->rows);
     for (int64_t it = 0; it < n_steps; ++it) {
         const int q = st->cur;
         const qds::FusedArgs<T>* fa = K->fa + q;

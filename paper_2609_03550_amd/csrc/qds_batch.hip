@@ -36,7 +36,7 @@ struct Plan {
 };
 
 const int kCandRows[4] = {4, 8, 16, 32};     // kernel A and the electromagnetic sets
-const int kCandCur[4] = {1, 2, 4, 8};        // axion current
+const int kCandCur[4] = {4, 8, 16, 32};      // axion current
 constexpr int kTunePasses = 2;
 
 }  // namespace
@@ -114,7 +114,7 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
     for (int M = 1; M <= 4; ++M) {
         const int rows = b->tiles[QDS_TILE_CUR1 + M - 1];
         add(QDS_TILE_CUR1 + M - 1, M, [&](const qds_ctx* c) { return has_arem(c) && c->M == M; },
-            [&](const qds_ctx* c) { return ((c->g.nx + 63) / 64) * chunks(c->g.nr, rows); });
+            [&](const qds_ctx* c) { return qds::current_strips(c->g.nx) * chunks(c->g.nr, rows); });
     }
     {
         const int rows = b->tiles[QDS_TILE_EM1];
@@ -369,7 +369,7 @@ qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch*
     b->inst = v;
     b->dtype = v[0]->g.dtype;
     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = 16;
-    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = 1;
+    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = 16;
     b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = 16;
     b->err[0] = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||

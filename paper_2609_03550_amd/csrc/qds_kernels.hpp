@@ -183,6 +183,8 @@ template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
 template <typename T>
 hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
+// Column strips of the marching axion-current kernel (63 owned columns each).
+int current_strips(int nx);
 template <typename T>
 hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
                         hipStream_t s);

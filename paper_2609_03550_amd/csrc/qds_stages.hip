@@ -439,29 +439,6 @@ hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s) {
     }
     return hipGetLastError();
 }
-template <typename T, int M>
-__global__ void __launch_bounds__(64 * M) k_batch_current(const AxionArgs<T>* __restrict__ args, BatchList L) {
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const int k = batch_find(L, b);
-    const AxionArgs<T>& a = args[L.idx[k]];
-    const int local = b - L.first[k];
-    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
-    axion_current_body<T, M>(a, local / chunks, (local % chunks) * L.rows, L.rows);
-}
-
-template <typename T>
-hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
-    switch (M) {
-#define QDS_BC(MM) case MM: hipLaunchKernelGGL((k_batch_current<T, MM>), dim3(blocks), dim3(64 * MM), 0, s, args, L); break;
-        QDS_BC(1) QDS_BC(2) QDS_BC(3) QDS_BC(4)
-#undef QDS_BC
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-template hipError_t batch_current<double>(const AxionArgs<double>*, const BatchList&, int, int, hipStream_t);
-template hipError_t batch_current<float>(const AxionArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t axion_current_w<double>(const AxionArgs<double>&, hipStream_t);
 template hipError_t axion_current_w<float>(const AxionArgs<float>&, hipStream_t);
 

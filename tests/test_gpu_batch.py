@@ -96,8 +96,7 @@ def test_autotuner_picks_candidates_and_keeps_results():
     b.run(12, graph_steps=4, tune=True)
     tiles, tuned = b.tiles()
     assert tuned
-    assert all(t in (4, 8, 16, 32) for t in tiles[:4] + tiles[8:])
-    assert all(t in (1, 2, 4, 8) for t in tiles[4:8])
+    assert all(t in (4, 8, 16, 32) for t in tiles)
     _identical(bs, ref)
     # a second run reuses the chosen tiles
     b.run(3, graph_steps=2, tune=True)
