@@ -35,19 +35,51 @@ template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 }
 
 // Vector load/store of one complex element (16 B for double, 8 B for float).
+// Every state plane lives in device (global) memory: the accesses go through
+// the global address space, so that pointers read from argument tables in
+// memory still give global (not flat) instructions.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v2d g_cv2d;
+typedef __attribute__((address_space(1))) v2d g_v2d;
+typedef __attribute__((address_space(1))) const v2f g_cv2f;
+typedef __attribute__((address_space(1))) v2f g_v2f;
+
 __device__ __forceinline__ cx<double> ld(const cx<double>* p) {
-    double2 v = *reinterpret_cast<const double2*>(p);
+    const v2d v = *(g_cv2d*)(p);
     return {v.x, v.y};
 }
 __device__ __forceinline__ cx<float> ld(const cx<float>* p) {
-    float2 v = *reinterpret_cast<const float2*>(p);
+    const v2f v = *(g_cv2f*)(p);
     return {v.x, v.y};
 }
 __device__ __forceinline__ void st(cx<double>* p, cx<double> a) {
-    *reinterpret_cast<double2*>(p) = make_double2(a.re, a.im);
+    v2d v;
+    v.x = a.re;
+    v.y = a.im;
+    *(g_v2d*)(p) = v;
 }
 __device__ __forceinline__ void st(cx<float>* p, cx<float> a) {
-    *reinterpret_cast<float2*>(p) = make_float2(a.re, a.im);
+    v2f v;
+    v.x = a.re;
+    v.y = a.im;
+    *(g_v2f*)(p) = v;
+}
+
+// Value held by the next lane of the wavefront (DPP wave shift; lane 63
+// receives zero).  Call it with every lane active: a lane masked off by a
+// branch supplies zero.
+__device__ __forceinline__ double next_lane(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> next_lane(cx<T> v) {
+    return cx<T>{next_lane(v.re), next_lane(v.im)};
 }
 
 // Mode convolution C_m{A, B} (the azimuthal projection of a product of two

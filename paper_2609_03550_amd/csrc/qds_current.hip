@@ -19,31 +19,19 @@ namespace cur {
 constexpr int WAVE = 64;
 constexpr int OWN = 63;
 
-// value of the next lane (lane 63 receives zero)
-__device__ __forceinline__ double next_lane(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float next_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-template <typename T>
-__device__ __forceinline__ cx<T> next_lane(cx<T> v) {
-    return cx<T>{next_lane(v.re), next_lane(v.im)};
-}
-
 template <typename T>
 __device__ __forceinline__ uint32_t eoff(const Geo& g, int m, int row, int c) {
     return (uint32_t(m * (g.nr + 1) + row) * uint32_t(g.ld) + uint32_t(c)) * uint32_t(sizeof(cx<T>));
 }
+typedef __attribute__((address_space(1))) const char g_cchar;
+typedef __attribute__((address_space(1))) char g_char;
 template <typename T>
 __device__ __forceinline__ cx<T> ldo(const cx<T>* p, uint32_t o) {
-    return ld(reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) + o));
+    return ld((const cx<T>*)((g_cchar*)(p) + o));
 }
 template <typename T>
 __device__ __forceinline__ void sto(cx<T>* p, uint32_t o, cx<T> v) {
-    st(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(p) + o), v);
+    st((cx<T>*)((g_char*)(p) + o), v);
 }
 
 // per-point quantities on a half row K (at column i of the lane)

@@ -29,13 +29,15 @@ template <typename T>
 __device__ __forceinline__ uint32_t eoff(const Geo& g, int m, int row, int c) {
     return (uint32_t(m * (g.nr + 1) + row) * uint32_t(g.ld) + uint32_t(c)) * uint32_t(sizeof(cx<T>));
 }
+typedef __attribute__((address_space(1))) const char g_cchar;
+typedef __attribute__((address_space(1))) char g_char;
 template <typename T>
 __device__ __forceinline__ cx<T> ldo(const cx<T>* p, uint32_t o) {
-    return ld(reinterpret_cast<const cx<T>*>(reinterpret_cast<const char*>(p) + o));
+    return ld((const cx<T>*)((g_cchar*)(p) + o));
 }
 template <typename T>
 __device__ __forceinline__ void sto(cx<T>* p, uint32_t o, cx<T> v) {
-    st(reinterpret_cast<cx<T>*>(reinterpret_cast<char*>(p) + o), v);
+    st((cx<T>*)((g_char*)(p) + o), v);
 }
 
 template <typename T>
@@ -53,6 +55,11 @@ struct XAcc {
     }
     __device__ __forceinline__ cx<T> R(const cx<T>* p, int m, int row) const {
         return i1 >= 0 ? ldo(p, ro(m, row) + uint32_t(i1) * uint32_t(sizeof(cx<T>))) : zero<T>();
+    }
+    // column i+1 from the next lane's column-i value (all lanes active)
+    __device__ __forceinline__ cx<T> Rn(cx<T> a) const {
+        const cx<T> b = next_lane(a);
+        return i1 >= 0 ? b : zero<T>();
     }
 };
 
@@ -102,6 +109,7 @@ struct EmWin {
     cx<T> bx1g;        // exterior ghost B_x^{n+1/2}
     cx<T> jx_n1;       // total j_x at (x_{i+1/2}, r_{j+1}, t^n) (used for E_x(J=j+1))
     cx<T> jx_nr;       // total j_x at row nr (for the ghost B_theta)
+    cx<T> pjx, pjxa;   // plasma j_x^{n-1} and extra j_x on J = j+1 (loaded ahead)
     // new transverse values after the transport of this step (both columns)
     cx<T> n_rpa, n_rpb, n_rma, n_rmb;   // T_r^{n+1} at K = j
     cx<T> n_tpa, n_tpb, n_tma, n_tmb;   // T_theta^{n+1} at J = j
@@ -142,43 +150,70 @@ __device__ __forceinline__ RowInv<T> row_inv(const Ctx<T>& c, int j) {
     return q;
 }
 
-// load the row j+1 of the window (T_r on K = j+1 or the ghost B_theta, T_theta
-// on J = j+1, E_x^{n-1/2} on J = j+1, B_x^{n-1/2} on K = j+1)
+// The values of row k = j + 1 that iteration j of the march consumes, loaded
+// one iteration ahead so that their latency overlaps the arithmetic of the
+// previous row (T_r on K = k or the ghost B_theta, T_theta, E_x^{n-1/2} and
+// B_x^{n-1/2} on J/K = k, the plasma j_x and the extra j_x on J = k).
 template <typename T>
-__device__ __forceinline__ void em_load_next(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j) {
+struct EmPf {
+    cx<T> rpa, rpb, rma, rmb, tpa, tpb, tma, tmb, ex0, bx0, jx, jxa;
+};
+
+template <typename T>
+__device__ __forceinline__ EmPf<T> em_fetch(const Ctx<T>& c, const SetP<T>& s, int k) {
     const int m = c.m;
-    const int k = j + 1;
+    EmPf<T> p;
+    p.rpa = p.rpb = p.rma = p.rmb = p.tpa = p.tpb = p.tma = p.tmb = zero<T>();
+    p.ex0 = p.bx0 = p.jx = p.jxa = zero<T>();
+    if (k < 0) return p;
     if (k < c.g.nr) {
-        W.rpa[1] = c.x.L(s.trp, m, k); W.rpb[1] = c.x.R(s.trp, m, k);
-        W.rma[1] = c.x.L(s.trm, m, k); W.rmb[1] = c.x.R(s.trm, m, k);
+        p.rpa = c.x.L(s.trp, m, k);
+        p.rma = c.x.L(s.trm, m, k);
     } else if (k == c.g.nr) {
-        // exterior ghost row: B_theta stored in the T_r^+ plane; expressed as
+        // exterior ghost row: B_theta stored in the T_r^+ plane, expressed as
         // T_r^+ = B_theta, T_r^- = -B_theta so that (T+ - T-)/2 = B_theta
-        cx<T> a = c.x.L(s.trp, m, k), b = c.x.R(s.trp, m, k);
-        W.rpa[1] = a; W.rpb[1] = b; W.rma[1] = -a; W.rmb[1] = -b;
+        cx<T> a = c.x.L(s.trp, m, k);
+        p.rpa = a; p.rma = -a;
     }
     if (k <= c.g.nr) {
-        W.tpa[1] = c.x.L(s.ttp, m, k); W.tpb[1] = c.x.R(s.ttp, m, k);
-        W.tma[1] = c.x.L(s.ttm, m, k); W.tmb[1] = c.x.R(s.ttm, m, k);
-        W.ex0[1] = c.x.L(s.ex, m, k);
-        W.bx0[1] = c.x.L(s.bx, m, k);
+        p.tpa = c.x.L(s.ttp, m, k);
+        p.tma = c.x.L(s.ttm, m, k);
+        p.ex0 = c.x.L(s.ex, m, k);
+        p.bx0 = c.x.L(s.bx, m, k);
+        if (c.plasma && c.live) p.jx = c.x.L(s.jx, m, k);
+        if (s.jxa && c.live) p.jxa = c.x.L(s.jxa, m, k);
     }
+    return p;
+}
+
+// moves a fetched row into slot 1; the column i+1 values come from the next
+// lane (called in uniform control flow, every lane active)
+template <typename T>
+__device__ __forceinline__ void em_take(const Ctx<T>& c, EmWin<T>& W, const EmPf<T>& p, int k, int nr) {
+    if (k > nr) return;
+    W.rpa[1] = p.rpa; W.rpb[1] = c.x.Rn(p.rpa); W.rma[1] = p.rma; W.rmb[1] = c.x.Rn(p.rma);
+    W.tpa[1] = p.tpa; W.tpb[1] = c.x.Rn(p.tpa); W.tma[1] = p.tma; W.tmb[1] = c.x.Rn(p.tma);
+    W.ex0[1] = p.ex0;
+    W.bx0[1] = p.bx0;
+    W.pjx = p.jx;
+    W.pjxa = p.jxa;
 }
 
 // total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra + drive
 template <typename T>
-__device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write) {
+__device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write,
+                                      cx<T> jx_old, cx<T> jxa) {
     cx<T> v = zero<T>();
     if (!c.live) {
         if (c.plasma && write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), v);
         return v;
     }
     if (c.plasma) {
-        cx<T> jn = c.x.L(s.jx, c.m, row) + c.wp2h * ex0;
+        cx<T> jn = jx_old + c.wp2h * ex0;
         if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jn);
         v = jn;
     }
-    if (s.jxa) v = v + c.x.L(s.jxa, c.m, row);
+    if (s.jxa) v = v + jxa;
     if (c.drive.on && c.m == 0) v.re += T(drive_jx_f(c.drive, c.g, c.i, row, c.n, c.w));
     return v;
 }
@@ -242,7 +277,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     const bool wI = c.owner && ocI >= 0;
     // ---- E_x^{n+1/2} at J = j+1
     if (j + 1 <= g.nr) {
-        W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1);
+        W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa);
         W.ex1[2] = em_ex_new(c, W, j + 1, W.jx_n1, ri.irJ1);
         if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
         if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
@@ -449,7 +484,9 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     const T kap = c.kap;
     const int ocI = c.o.col(c.i);
     const bool wI = c.owner && ocI >= 0;
-    const int jstart = max(r0 - 2, -1);
+    // one halo row gives E_x(J = r0) and B_x(K = r0 - 1); the chunk holding the
+    // exterior ghost row also needs E_x(J = nr - 1) for the ghost B_theta
+    const int jstart = max(r0 - (r1 == g.nr + 1 ? 2 : 1), -1);
     // prime slot 1 with row jstart (so that the first em_load_next fills j+1)
     for (int q = 0; q < 2; ++q) {
         W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
@@ -460,7 +497,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
     phw[0] = phw[1] = phw[2] = zero<T>();
     if (jstart >= 0) {
-        em_load_next(c, s, W, jstart - 1);           // row jstart into slot 1
+        em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);   // row jstart into slot 1
         phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
         if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
     }
@@ -473,7 +510,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         if (j + 1 < g.nr) phw[2] = c.x.L(a.phi, m, j + 1);
         else if (j + 1 == g.nr) phw[2] = g.open_r ? c.x.L(a.phi, m, g.nr) : zero<T>();
         else phw[2] = zero<T>();
-        em_load_next(c, s, W, j);
+        em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
         const cx<T> ex1_j = W.ex1[1];
         const RowInv<T> ri = row_inv(c, j);
         em_step(c, s, W, j, r0, r1, ri);
@@ -526,8 +563,8 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             if (c.live)
                 ga = (c.inv_dr * c.inv_dr) * (up - T(2) * p + dn) + (c.inv_2dr * ri.irK) * (up - dn)
                      - (T(m * m) * ri.irK * ri.irK + T(a.ma2)) * p + T(a.s_phi) * Sa;
-            cx<T> tap_a = c.x.L(a.tap, m, j), tap_b = c.x.R(a.tap, m, j);
-            cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.R(a.tam, m, j);
+            cx<T> tap_a = c.x.L(a.tap, m, j);
+            cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.Rn(tam_a);   // uniform control flow here
             cx<T> nap_b = (c.x.i1 >= 0) ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
             cx<T> nam_a = tam_b + h * ga;                                  // T_a^- at column i
             cx<T> l = shfl_up1(nap_b), r = shfl_dn1(nam_a);
@@ -621,12 +658,17 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     }
     W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
     W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
-    const int jstart = max(r0 - 2, -1);
-    if (jstart >= 0) em_load_next(c, s, W, jstart - 1);
+    // one halo row gives E_x(J = r0) and B_x(K = r0 - 1); the chunk holding the
+    // exterior ghost row also needs E_x(J = nr - 1) for the ghost B_theta
+    const int jstart = max(r0 - (r1 == g.nr + 1 ? 2 : 1), -1);
+    W.pjx = W.pjxa = zero<T>();
+    if (jstart >= 0) em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);
+    EmPf<T> pf = em_fetch(c, s, jstart + 1);
     const int jend = min(r1, g.nr);
     for (int j = jstart; j <= jend; ++j) {
         em_rotate(W);
-        em_load_next(c, s, W, j);
+        em_take(c, W, pf, j + 1, g.nr);
+        pf = em_fetch(c, s, j + 2);          // next row's loads overlap this row's work
         em_step(c, s, W, j, r0, r1, row_inv(c, j));
         if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
     }

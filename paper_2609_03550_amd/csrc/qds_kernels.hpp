@@ -140,8 +140,9 @@ struct FusedArgs {
     int rows;         // radial rows per workgroup chunk
 };
 
-// Columns owned by one 64-lane strip of the r-marching kernels (two halo lanes).
-constexpr int kFusedOwn = 62;
+// Columns owned by one 64-lane strip of the r-marching kernels: lane 0 is the
+// left halo, lanes 62 and 63 the right halo (lane 63 only lends its column).
+constexpr int kFusedOwn = 61;
 __host__ __device__ inline int fused_strips(int nx) { return (nx + kFusedOwn - 1) / kFusedOwn; }
 
 // One launch of a batched kernel: the instances it covers (indices into the
