@@ -206,6 +206,8 @@ def main():
     dev = torch.device("cuda:0")
     s = qds.Solver(wl, dtype=args.dtype, device="cuda:0", path=args.path, rows=args.rows)
     s.load_pulses()
+    if args.rows is None and args.warmup >= 8:
+        s.set_option(qds.OPT_TUNE, 1)      # tile heights chosen on the first warm-up steps
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -272,6 +274,7 @@ def main():
         "kernel_gbps": {KERNEL_NAMES[q]: plane_accesses(wl, q) * eb * cells / (kms[q] / kn[q] / 1e3) / 1e9
                         for q in range(3) if kn[q] and s.fused},
         "fwd_adj_over_fwd": None,
+        "tiles": dict(zip(("kernel_a", "axion_current", "kernel_b"), s.tiles()[0]), tuned=s.tiles()[1]),
     }
     del s
     torch.cuda.empty_cache()

@@ -146,12 +146,18 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 4, except the
  *                 moving window combined with the regenerated set),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
- *  QDS_OPT_ROWS   radial rows per workgroup chunk of the fused kernels (1..4096)
+ *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)
+ *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
+ *                 times its first 8 steps (two passes over the tile heights
+ *                 8, 16, 32, 64, HIP events around every launch) and keeps the
+ *                 fastest height for each kernel; the trial steps are ordinary
+ *                 steps (the tiling changes no result).  Waits for the stream
+ *                 once, after the trials.
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
  *                 value resets the recorded launches */
-enum { QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3 };
+enum { QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
 qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
 
@@ -161,6 +167,12 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
  * (kernel B), index 2 = the axion-current kernel.  ms[3], launches[3].
  * Waits for the recorded events. */
 qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches);
+
+/* Tile heights (radial rows per workgroup) of the fused kernels in use:
+ * rows[0] kernel A (or the background set without the axion), rows[1] the
+ * axion current, rows[2] the regenerated set; *tuned = 1 once the autotuner
+ * (QDS_OPT_TUNE) has chosen them. */
+qds_status qds_get_tiles(qds_handle h, int32_t* rows, int32_t* tuned);
 
 /* 1 if qds_step runs the fused kernels for this handle. */
 int32_t qds_uses_fused(qds_handle h);

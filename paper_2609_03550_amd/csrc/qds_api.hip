@@ -56,7 +56,8 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     memcpy(&key[1], &st->buf[1], sizeof(void*));
     key[2] = p0.wp2; key[3] = p0.ma2; key[4] = p0.s_phi; key[5] = p0.s_j;
     key[6] = double(p0.bx0.re); key[7] = double(p0.bx0.im); key[8] = double(p0.br1.re); key[9] = double(p0.br1.im);
-    key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im); key[12] = double(c->rows);
+    key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im);
+    key[12] = double(c->trows[0]); key[13] = double(c->trows[1]); key[14] = double(c->trows[2]);
     if (!c->ktab_dev) {
         c->ktab_bytes = sizeof(KTab<double>);
         if (hipMalloc(&c->ktab_dev, c->ktab_bytes) != hipSuccess) {
@@ -80,11 +81,11 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
         t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
     }
     const int strips = qds::fused_strips(c->g.nx);
-    const int chunks = (c->g.nr + 1 + c->rows - 1) / c->rows;
+    auto chunks = [&](int rows) { return (c->g.nr + 1 + rows - 1) / rows; };
     t.idx[0] = t.idx[1] = 0;
-    t.firstA[1] = strips * chunks;
-    t.firstC[1] = qds::current_strips(c->g.nx) * chunks;
-    t.firstB[1] = strips * chunks * c->M;
+    t.firstA[1] = strips * chunks(c->trows[0]);
+    t.firstC[1] = qds::current_strips(c->g.nx) * chunks(c->trows[1]);
+    t.firstB[1] = strips * chunks(c->trows[2]) * c->M;
     // the staging copy may still be read by the previous upload
     if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
         return fail(c, QDS_EHIP, "argument table upload failed%s");
@@ -97,14 +98,12 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     return QDS_OK;
 }
 
+// One fused step through the argument table (kernel A or the background
+// set, then the axion current and the regenerated set), each launch
+// bracketed by the event pair ev[2k], ev[2k+1] when ev is given.
 template <typename T>
-qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s,
-                       bool by_value) {
-    if (p0.drive.on || by_value) return fused_steps_drive<T>(c, st, p0, n_steps, s);
-    KTab<T>* K;
-    qds_status r = sync_ktab<T>(c, st, p0, s, &K);
-    if (r != QDS_OK) return r;
-    const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
+qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
+                      hipStream_t s, hipEvent_t* ev) {
     auto list = [&](const int* first_dev, int rows) {
         qds::BatchList L;
         L.idx = K->idx;
@@ -113,32 +112,81 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
         L.rows = rows;
         return L;
     };
-    const qds::BatchList LA = list(K->firstA, c->rows), LC = list(K->firstC, c->rows), LB = list(K->firstB, c->rows);
-    for (int64_t it = 0; it < n_steps; ++it) {
-        const int q = st->cur;
-        const qds::FusedArgs<T>* fa = K->fa + q;
-        hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
-        if (ev) hipEventRecord(ev[0], s);
-        hipError_t e = p0.axion ? qds::batch_a<T>(fa, LA, c->M, host.firstA[1], s)
-                                : qds::batch_em<T>(fa, LB, 0, host.firstB[1], s);
-        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (ev) hipEventRecord(ev[1], s);
-        if (p0.arem) {
-            ev = c->timing ? timing_pair(c, 2) : nullptr;
-            if (ev) hipEventRecord(ev[0], s);
-            e = qds::batch_current<T>(K->xa + q, LC, c->M, host.firstC[1], s);
-            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev) hipEventRecord(ev[1], s);
-            ev = c->timing ? timing_pair(c, 1) : nullptr;
-            if (ev) hipEventRecord(ev[0], s);
-            e = qds::batch_em<T>(fa, LB, 1, host.firstB[1], s);
-            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev) hipEventRecord(ev[1], s);
-        }
-        st->cur = 1 - q;
-        if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
-        st->step += 1;
+    const qds::BatchList LA = list(K->firstA, c->trows[0]), LC = list(K->firstC, c->trows[1]),
+                         LB = list(K->firstB, c->trows[2]), LB0 = list(K->firstB, c->trows[0]);
+    const int q = st->cur;
+    const qds::FusedArgs<T>* fa = K->fa + q;
+    hipEvent_t* e0 = ev ? ev : (c->timing ? timing_pair(c, 0) : nullptr);
+    if (e0) hipEventRecord(e0[0], s);
+    hipError_t e;
+    if (p0.axion) {
+        e = qds::batch_a<T>(fa, LA, c->M, host.firstA[1], s);
+    } else {
+        // the background set alone: the kernel-B march with the kernel-A tile
+        const int strips = qds::fused_strips(c->g.nx);
+        e = qds::batch_em<T>(fa, LB0, 0, strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
     }
+    if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    if (e0) hipEventRecord(e0[1], s);
+    if (p0.arem) {
+        hipEvent_t* e2 = ev ? ev + 2 : (c->timing ? timing_pair(c, 2) : nullptr);
+        if (e2) hipEventRecord(e2[0], s);
+        e = qds::batch_current<T>(K->xa + q, LC, c->M, host.firstC[1], s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (e2) hipEventRecord(e2[1], s);
+        hipEvent_t* e1 = ev ? ev + 4 : (c->timing ? timing_pair(c, 1) : nullptr);
+        if (e1) hipEventRecord(e1[0], s);
+        e = qds::batch_em<T>(fa, LB, 1, host.firstB[1], s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+        if (e1) hipEventRecord(e1[1], s);
+    }
+    st->cur = 1 - q;
+    if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
+    st->step += 1;
+    return QDS_OK;
+}
+
+template <typename T>
+qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s,
+                       bool by_value) {
+    if (p0.drive.on || by_value) return fused_steps_drive<T>(c, st, p0, n_steps, s);
+    KTab<T>* K;
+    qds_status r;
+    int64_t done = 0;
+    constexpr int kTrials = 8;
+    if (c->tune && n_steps >= kTrials) {
+        // autotuner: timed ordinary steps, two passes over four tile heights
+        static const int cand[4] = {8, 16, 32, 64};
+        std::vector<hipEvent_t> ev(6 * kTrials);
+        for (hipEvent_t& x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
+        for (int t = 0; t < kTrials; ++t) {
+            c->trows[0] = c->trows[1] = c->trows[2] = cand[t % 4];
+            if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
+            const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
+            if ((r = table_step<T>(c, st, p0, K, host, s, ev.data() + 6 * t)) != QDS_OK) return r;
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(c, QDS_EHIP, "tuning steps failed%s");
+        float best[3] = {3.4e38f, 3.4e38f, 3.4e38f};
+        int pick[3] = {16, 16, 16};
+        for (int t = 0; t < kTrials; ++t)
+            for (int k = 0; k < 3; ++k) {
+                if (k > 0 && !p0.arem) continue;
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[6 * t + 2 * k], ev[6 * t + 2 * k + 1]) != hipSuccess) continue;
+                const int slot = k == 0 ? 0 : (k == 1 ? 1 : 2);
+                if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[t % 4]; }
+            }
+        for (hipEvent_t x : ev) hipEventDestroy(x);
+        for (int k = 0; k < 3; ++k) c->trows[k] = pick[k];
+        c->tune = 0;
+        c->tuned = 1;
+        done = kTrials;
+    }
+    if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
+    const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
+    for (int64_t it = done; it < n_steps; ++it)
+        if ((r = table_step<T>(c, st, p0, K, host, s, nullptr)) != QDS_OK) return r;
     return QDS_OK;
 }
 
@@ -323,6 +371,7 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     c->nplanes = n;
     c->path = QDS_PATH_AUTO;
     c->rows = 16;
+    c->trows[0] = c->trows[1] = c->trows[2] = 16;
     if (g.content & QDS_HAS_AREM) {
         hipError_t e = hipMalloc(&c->scratch, 3 * c->plane_elems * c->elem_bytes);
         if (e != hipSuccess) {
@@ -396,6 +445,10 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
         case QDS_OPT_ROWS:
             if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");
             h->rows = int(value);
+            h->trows[0] = h->trows[1] = h->trows[2] = int(value);
+            return QDS_OK;
+        case QDS_OPT_TUNE:
+            h->tune = value ? 1 : 0;
             return QDS_OK;
         case QDS_OPT_TIMING:
             h->timing = value ? 1 : 0;
@@ -419,6 +472,13 @@ qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches) {
         ms[h->tag[q]] += t;
         launches[h->tag[q]] += 1;
     }
+    return QDS_OK;
+}
+
+qds_status qds_get_tiles(qds_handle h, int32_t* rows, int32_t* tuned) {
+    if (!h || !rows) return fail(h, QDS_EINVAL, "null argument%s");
+    for (int k = 0; k < 3; ++k) rows[k] = h->trows[k];
+    if (tuned) *tuned = h->tuned;
     return QDS_OK;
 }
 

@@ -18,7 +18,10 @@ struct qds_ctx {
     int nplanes;
     void* scratch;           // axion-current planes (3), library owned
     int path;                // QDS_PATH_*
-    int rows;                // radial rows per workgroup of the fused kernels
+    int rows;                // radial rows per workgroup of the by-value fused kernels
+    int trows[3];            // tile heights of the table-driven kernels: A, current, B
+    int tune;                // autotune the tile heights on the next long enough qds_step
+    int tuned;
     int timing;              // record per-kernel HIP events in qds_step
     // timing events, recorded without synchronising and resolved by
     // qds_get_timing: pairs (start, end) per launch, tagged with the kernel

@@ -502,14 +502,20 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
     }
 
-    const int jend = min(r1, g.nr);
+    // phi on half row k (the exterior ghost on row nr with the open boundary)
+    auto phi_row = [&](int k) {
+        if (k < g.nr) return c.x.L(a.phi, m, k);
+        if (k == g.nr && g.open_r) return c.x.L(a.phi, m, g.nr);
+        return zero<T>();
+    };
+    // rows [r0, r1) are owned; the last iteration is r1 - 1 except for the
+    // chunk holding the exterior ghost row, which ends on row nr
+    const int jend = r1 == g.nr + 1 ? g.nr : r1 - 1;
     for (int j = jstart; j <= jend; ++j) {
         // ---------------- shift the window and load row j+1
         em_rotate(W);
         phw[0] = phw[1]; phw[1] = phw[2];
-        if (j + 1 < g.nr) phw[2] = c.x.L(a.phi, m, j + 1);
-        else if (j + 1 == g.nr) phw[2] = g.open_r ? c.x.L(a.phi, m, g.nr) : zero<T>();
-        else phw[2] = zero<T>();
+        phw[2] = phi_row(j + 1);
         em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
         const cx<T> ex1_j = W.ex1[1];
         const RowInv<T> ri = row_inv(c, j);
@@ -664,11 +670,13 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     W.pjx = W.pjxa = zero<T>();
     if (jstart >= 0) em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);
     EmPf<T> pf = em_fetch(c, s, jstart + 1);
-    const int jend = min(r1, g.nr);
+    // rows [r0, r1) are owned; the last iteration is r1 - 1 except for the
+    // chunk holding the exterior ghost row, which ends on row nr
+    const int jend = r1 == g.nr + 1 ? g.nr : r1 - 1;
     for (int j = jstart; j <= jend; ++j) {
         em_rotate(W);
         em_take(c, W, pf, j + 1, g.nr);
-        pf = em_fetch(c, s, j + 2);          // next row's loads overlap this row's work
+        if (j < jend) pf = em_fetch(c, s, j + 2);   // next row's loads overlap this row's work
         em_step(c, s, W, j, r0, r1, row_inv(c, j));
         if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
     }

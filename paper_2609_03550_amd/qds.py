@@ -28,7 +28,7 @@ J_NONE, J_RING = 0, 1
 P_TRP, P_TRM, P_TTP, P_TTM, P_EX, P_BX, P_JX, P_JR, P_JT = range(9)
 P_SET1, P_PHI, P_TAP, P_TAM = 9, 18, 19, 20
 
-OPT_PATH, OPT_ROWS, OPT_TIMING = 1, 2, 3
+OPT_PATH, OPT_ROWS, OPT_TIMING, OPT_TUNE = 1, 2, 3, 4
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 
 
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_set_option.restype = i32
     lib.qds_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.qds_get_timing.restype = i32
+    lib.qds_get_tiles.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qds_get_tiles.restype = i32
     lib.qds_uses_fused.argtypes = [vp]
     lib.qds_uses_fused.restype = i32
     lib.qds_backward_pool_bytes.argtypes = [vp, i64, i64]
@@ -187,6 +189,14 @@ class Solver:
     @property
     def fused(self) -> bool:
         return bool(lib().qds_uses_fused(self.h))
+
+    def tiles(self):
+        """Tile heights (rows per workgroup) of kernel A, the axion current and
+        kernel B, and whether the autotuner chose them."""
+        t = (ctypes.c_int32 * 3)()
+        tuned = ctypes.c_int32()
+        _check(lib().qds_get_tiles(self.h, t, ctypes.byref(tuned)), self.h)
+        return list(t), bool(tuned.value)
 
     def timing(self):
         """(ms per kernel, launches per kernel) recorded since timing was set;

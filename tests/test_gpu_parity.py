@@ -152,3 +152,24 @@ def test_fused_matches_staged_on_a_long_run():
     b.step(300)
     torch.cuda.synchronize()
     P.compare_states(b.fields(), a.fields(), 1e-11, 1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autotuned_tiles_change_no_result(dtype):
+    """qds_step with the autotuner on: its 8 trial steps (four tile heights,
+    twice) and the chosen tiles give bit-identical states to the default
+    tiling, and the chosen heights are candidates."""
+    from paper_2609_03550_amd import qds
+    wl = _full(70, 20, 3)
+    a = qds.Solver(wl, dtype=dtype)
+    a.load_pulses()
+    b = qds.Solver(wl, dtype=dtype)
+    b.load_pulses()
+    b.set_option(qds.OPT_TUNE, 1)
+    a.step(12)
+    b.step(12)
+    torch.cuda.synchronize()
+    rows, tuned = b.tiles()
+    assert tuned and all(r in (8, 16, 32, 64) for r in rows)
+    assert a.tiles() == ([16, 16, 16], False)
+    assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
