@@ -143,7 +143,7 @@ __device__ void bx_new_bar(const StageBar<T>& a, int m, int k, int i, cx<T> bb) 
 
 // ---- adjoint of k_ghost_bth
 template <typename T>
-__global__ void k_ghost_bth_bar(StageBar<T> a) {
+__global__ void __launch_bounds__(256) k_ghost_bth_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nx || !g.open_r) return;
@@ -175,7 +175,7 @@ __global__ void k_ghost_bth_bar(StageBar<T> a) {
 
 // ---- adjoint of k_transverse
 template <typename T>
-__global__ void k_transverse_bar(StageBar<T> a) {
+__global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -223,7 +223,7 @@ __global__ void k_transverse_bar(StageBar<T> a) {
 
 // ---- adjoint of k_longitudinal
 template <typename T>
-__global__ void k_longitudinal_bar(StageBar<T> a) {
+__global__ void __launch_bounds__(256) k_longitudinal_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -379,7 +379,7 @@ struct AxBar {
 
 // ---- adjoint of k_axion_phi
 template <typename T>
-__global__ void k_axion_phi_bar(AxBar<T> a) {
+__global__ void __launch_bounds__(256) k_axion_phi_bar(AxBar<T> a) {
     const Geo& g = a.f.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
@@ -428,7 +428,7 @@ __device__ __forceinline__ void block_sum_add(double v, double* acc) {
 
 // ---- adjoint of k_axion_ta (S_a, Gamma_a, T_a shift)
 template <typename T, int M>
-__global__ void k_axion_ta_bar(AxBar<T> a) {
+__global__ void __launch_bounds__(256) k_axion_ta_bar(AxBar<T> a) {
     const Geo& g = a.f.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
@@ -699,14 +699,222 @@ __device__ void ja_factors_bar(const AxBar<T>& a, int m, int i, int j, const cx<
     }
 }
 
+// ---- the same adjoint with the contributions combined before the atomics:
+// per destination plane and point in registers, and the column i+1 share
+// handed to the next lane (which holds column i+1) by a DPP shift, so each
+// point receives one atomic add per lane.  Called by every lane of a wave
+// (uniform control flow), with fb = 0 where the cell computes nothing.
+__device__ __forceinline__ double prev_lane(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float prev_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> prev_lane(cx<T> v) {
+    return cx<T>{prev_lane(v.re), prev_lane(v.im)};
+}
+
+// two planes, rows r0 and r0 + 1, columns i and i + 1
+template <typename T>
+struct Acc2x2 {
+    cx<T> p[2][2], q[2][2];
+    __device__ __forceinline__ Acc2x2() {
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) p[r][c] = q[r][c] = zero<T>();
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void flush2x2(const Geo& g, int m, int i, int lane, int r0, int rmax, cx<T>* P, cx<T>* Q,
+                                         const Acc2x2<T>& A) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int row = r0 + r;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            cx<T>* pl = w ? Q : P;
+            const cx<T> v0 = w ? A.q[r][0] : A.p[r][0];
+            const cx<T> v1 = w ? A.q[r][1] : A.p[r][1];
+            const cx<T> got = prev_lane(v1);                 // column i of this lane from lane - 1
+            const cx<T> own = lane > 0 ? v0 + got : v0;
+            if (row < 0 || row > rmax) continue;
+            if (i < g.nx) cadd(pl + g.at(m, row, i), own);
+            if (lane == 63 || (g.per && i == g.nx - 1)) addx(pl, g, m, row, i + 1, v1);
+        }
+    }
+}
+
+template <typename T>
+__device__ void ja_factors_bar_comb(const AxBar<T>& a, int m, int i, int j, int lane, const cx<T>* fb) {
+    const AxionArgs<T>& f = a.f;
+    const Geo& g = f.g;
+    const T dr = T(g.dr);
+    const bool ax = (j == 0);
+    const T rj = T(j) * dr;
+    const T rk = (T(j) + T(0.5)) * dr;
+    const T r_half = T(0.5) * dr;
+    const T par = parity<T>(m);
+    const T h = T(0.5);
+    // ---- T_r at the old and new levels (half rows j-1, j): E_r -> (+1/2, +1/2), B_theta -> (+1/2, -1/2)
+    {
+        Acc2x2<T> A, B;
+        const cx<T> q2 = T(0.25) * fb[2];
+        const cx<T> q = T(0.25) * fb[6], qe = T(0.25) * fb[10];
+        for (int cc = 0; cc < 2; ++cc) {
+            // f2: E_r^n of j_a,x
+            cx<T> eb = q2, gb = q2;
+            if (ax) eb = eb - gb;
+            else { A.p[0][cc] = A.p[0][cc] + h * gb; A.q[0][cc] = A.q[0][cc] + h * gb; }
+            A.p[1][cc] = A.p[1][cc] + h * eb; A.q[1][cc] = A.q[1][cc] + h * eb;
+            // f6 (B_theta) and f10 (E_r) of j_a,theta, both levels
+            cx<T> bb = q, gbb = q, ebb = qe, gebb = qe;
+            if (ax) {
+                bb = bb - gbb;
+                ebb = ebb - gebb;
+            } else {
+                const cx<T> tp = h * (h * gbb) + h * (h * gebb), tm = h * (h * gebb) - h * (h * gbb);
+                A.p[0][cc] = A.p[0][cc] + tp; A.q[0][cc] = A.q[0][cc] + tm;
+                B.p[0][cc] = B.p[0][cc] + tp; B.q[0][cc] = B.q[0][cc] + tm;
+            }
+            const cx<T> tp = h * (h * bb) + h * (h * ebb), tm = h * (h * ebb) - h * (h * bb);
+            A.p[1][cc] = A.p[1][cc] + tp; A.q[1][cc] = A.q[1][cc] + tm;
+            B.p[1][cc] = B.p[1][cc] + tp; B.q[1][cc] = B.q[1][cc] + tm;
+        }
+        flush2x2(g, m, i, lane, j - 1, g.nr - 1, a.A0b.trp, a.A0b.trm, A);
+        flush2x2(g, m, i, lane, j - 1, g.nr - 1, a.B0b.trp, a.B0b.trm, B);
+    }
+    // ---- T_theta at both levels (rows j, j+1; the m = 1 axis terms on row 0):
+    // E_theta -> (+1/2, +1/2), B_r -> (+1/2, -1/2)
+    {
+        Acc2x2<T> A, B;
+        auto eth = [&](Acc2x2<T>& X, int r, int cc, cx<T> v) {
+            X.p[r][cc] = X.p[r][cc] + h * v; X.q[r][cc] = X.q[r][cc] + h * v;
+        };
+        auto brr = [&](Acc2x2<T>& X, int r, int cc, cx<T> v) {
+            X.p[r][cc] = X.p[r][cc] + h * v; X.q[r][cc] = X.q[r][cc] - h * v;
+        };
+        // f4: E_theta^n(j) averaged over the columns
+        eth(A, 0, 0, h * fb[4]);
+        eth(A, 0, 1, h * fb[4]);
+        if (ax && m == 1) {
+            const cx<T> q2 = T(0.25) * fb[2], q = T(0.25) * fb[6], qe = T(0.25) * fb[10];
+            for (int cc = 0; cc < 2; ++cc) {
+                eth(A, 0, cc, imul_c(T(2), q2));                 // f2 axis: g = 2i E_th(0) - e
+                const cx<T> brb = imul_c(-T(2), q);               // f6 axis: gb = -2i br - b
+                brr(A, 0, cc, h * brb);
+                brr(B, 0, cc, h * brb);
+                const cx<T> etb = imul_c(T(2), qe);               // f10 axis: ge = 2i et - e
+                eth(A, 0, cc, h * etb);
+                eth(B, 0, cc, h * etb);
+            }
+        }
+        // f12 (B_r) and f14 (E_theta) of j_a,r over rows j, j+1 and both columns
+        const cx<T> sb = T(0.25) * fb[12], se = T(0.25) * fb[14];
+        for (int dj = 0; dj < 2; ++dj)
+            for (int cc = 0; cc < 2; ++cc) {
+                brr(A, dj, cc, h * sb);
+                brr(B, dj, cc, h * sb);
+                eth(A, dj, cc, h * se);
+                eth(B, dj, cc, h * se);
+            }
+        flush2x2(g, m, i, lane, j, g.nr, a.A0b.ttp, a.A0b.ttm, A);
+        flush2x2(g, m, i, lane, j, g.nr, a.B0b.ttp, a.B0b.ttm, B);
+    }
+    // ---- T_a at t^{n-1/2} (A) and t^{n+1/2} (B), half rows j-1, j:
+    // dto -> A (+1/2, +1/2), dth -> B (+1/2, +1/2), dxh -> B (-1/2, +1/2)
+    {
+        Acc2x2<T> A, B;
+        auto dto = [&](int r, int cc, cx<T> v) { A.p[r][cc] = A.p[r][cc] + h * v; A.q[r][cc] = A.q[r][cc] + h * v; };
+        auto dth = [&](int r, int cc, cx<T> v) { B.p[r][cc] = B.p[r][cc] + h * v; B.q[r][cc] = B.q[r][cc] + h * v; };
+        auto dxh = [&](int r, int cc, cx<T> v) { B.p[r][cc] = B.p[r][cc] - h * v; B.q[r][cc] = B.q[r][cc] + h * v; };
+        const cx<T> q = T(0.25) * fb[1];
+        const cx<T> qt = T(0.25) * fb[7], qx = T(0.25) * fb[11];
+        for (int cc = 0; cc < 2; ++cc) {
+            // f1: d_t phi at t^n = (dto + dth)/2 on rows j-1, j
+            cx<T> db = q, lb = q;
+            if (ax) db = db + par * lb;
+            dto(1, cc, h * db);
+            dth(1, cc, h * db);
+            if (!ax) { dto(0, cc, h * lb); dth(0, cc, h * lb); }
+            // f7 (d_t phi) and f11 (d_x phi) at t^{n+1/2}
+            cx<T> tb = qt, tlb = qt, xb = qx, xlb = qx;
+            if (ax) { tb = tb + par * tlb; xb = xb + par * xlb; }
+            else { dth(0, cc, tlb); dxh(0, cc, xlb); }
+            dth(1, cc, tb);
+            dxh(1, cc, xb);
+            // f13, f15 of j_a,r (row j)
+            dth(1, cc, h * fb[13]);
+            dxh(1, cc, h * fb[15]);
+        }
+        flush2x2(g, m, i, lane, j - 1, g.nr - 1, a.tapAb, a.tamAb, A);
+        flush2x2(g, m, i, lane, j - 1, g.nr - 1, a.tapBb, a.tamBb, B);
+    }
+    if (j >= g.nr || i >= g.nx) return;
+    // ---- column-i planes: B_x (both levels), phi (both levels), E_x^{n+1/2}
+    {
+        // f0
+        cx<T> hib = h * fb[0], lob = h * fb[0];
+        if (ax) hib = hib + par * lob;
+        cx<T> bx_hi = h * hib, bx_lo = ax ? zero<T>() : h * lob;
+        // phi: f3, f5 (phiA), f9, f17 (both)
+        cx<T> pA_hi = zero<T>(), pA_lo = zero<T>(), pB_hi = zero<T>(), pB_lo = zero<T>();
+        if (ax) {
+            if (m == 1) pA_hi = pA_hi + imul_c(-T(1) / r_half, fb[3]);
+        } else {
+            const cx<T> s3 = h * imul_c(-T(m) / rj, fb[3]);
+            pA_hi = pA_hi + s3;
+            pA_lo = pA_lo + s3;
+        }
+        {
+            const cx<T> s5 = (T(1) / dr) * fb[5];
+            cx<T> hi5 = s5, lo5 = -s5;
+            if (ax) hi5 = hi5 + par * lo5;
+            pA_hi = pA_hi + hi5;
+            if (!ax) pA_lo = pA_lo + lo5;
+        }
+        {
+            const cx<T> s9 = (T(1) / dr) * fb[9];
+            cx<T> phb = s9, plb = -s9;
+            if (ax) phb = phb + par * plb;
+            pA_hi = pA_hi + h * phb; pB_hi = pB_hi + h * phb;
+            if (!ax) { pA_lo = pA_lo + h * plb; pB_lo = pB_lo + h * plb; }
+        }
+        {
+            const cx<T> ph = imul_c(-T(m) / rk, fb[17]);
+            pA_hi = pA_hi + h * ph; pB_hi = pB_hi + h * ph;
+        }
+        cadd(a.A0b.bx + g.at(m, j, i), bx_hi);
+        cadd(a.B0b.bx + g.at(m, j, i), bx_hi);
+        cadd(a.phiAb + g.at(m, j, i), pA_hi);
+        cadd(a.phiBb + g.at(m, j, i), pB_hi);
+        if (!ax) {
+            cadd(a.A0b.bx + g.at(m, j - 1, i), bx_lo);
+            cadd(a.B0b.bx + g.at(m, j - 1, i), bx_lo);
+            cadd(a.phiAb + g.at(m, j - 1, i), pA_lo);
+            cadd(a.phiBb + g.at(m, j - 1, i), pB_lo);
+        }
+        // f8, f16
+        cadd(a.B0b.ex + g.at(m, j, i), fb[8] + h * fb[16]);
+        cadd(a.B0b.ex + g.at(m, j + 1, i), h * fb[16]);
+    }
+}
+
 // ---- adjoint of k_axion_current
 template <typename T, int M>
-__global__ void k_axion_current_bar(AxBar<T> a) {
+__global__ void __launch_bounds__(256) k_axion_current_bar(AxBar<T> a) {
     const Geo& g = a.f.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const bool inb = i < g.nx && j < g.nr;
     double dsj = 0.0;
+    cx<T> Fb[18][M];
+#pragma unroll
+    for (int q = 0; q < 18; ++q)
+#pragma unroll
+        for (int m = 0; m < M; ++m) Fb[q][m] = zero<T>();
     if (inb && (g.per || i < g.nx - 1)) {
         const T sj = T(a.f.s_j);
         cx<T> F[18][M];
@@ -748,11 +956,6 @@ __global__ void k_axion_current_bar(AxBar<T> a) {
             jtb[m] = sj * jtb[m];
             jrb[m] = sj * jrb[m];
         }
-        cx<T> Fb[18][M];
-#pragma unroll
-        for (int q = 0; q < 18; ++q)
-#pragma unroll
-            for (int m = 0; m < M; ++m) Fb[q][m] = zero<T>();
         conv_bar<T, M>(F[0], F[1], jxb, T(1), Fb[0], Fb[1]);
         conv_bar<T, M>(F[2], F[3], jxb, T(-1), Fb[2], Fb[3]);
         conv_bar<T, M>(F[4], F[5], jxb, T(1), Fb[4], Fb[5]);
@@ -762,12 +965,16 @@ __global__ void k_axion_current_bar(AxBar<T> a) {
         conv_bar<T, M>(F[12], F[13], jrb, T(1), Fb[12], Fb[13]);
         conv_bar<T, M>(F[14], F[15], jrb, T(-1), Fb[14], Fb[15]);
         conv_bar<T, M>(F[16], F[17], jrb, T(1), Fb[16], Fb[17]);
+    }
+    // scatter in uniform control flow (the combining shifts need every lane);
+    // rows at or beyond nr compute nothing
+    if (j < g.nr) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             cx<T> fb[18];
 #pragma unroll
             for (int q = 0; q < 18; ++q) fb[q] = Fb[q][m];
-            ja_factors_bar(a, m, i, j, fb);
+            ja_factors_bar_comb(a, m, i, j, int(threadIdx.x), fb);
         }
     }
     if (a.dLds) block_sum_add(dsj, a.dLds + 1);
@@ -863,7 +1070,7 @@ namespace adj {
 // with w = 2 pi (mode 0) or pi, r'_0 = dr/8, r'_j = j dr.  Writes dL/du = 2 c u
 // into the adjoint buffer and adds L to *loss.
 template <typename T>
-__global__ void k_loss_seed(SetPtr<T> u, SetBar<T> ub, Geo g, int md, int x0, int x1, double* loss) {
+__global__ void __launch_bounds__(256) k_loss_seed(SetPtr<T> u, SetBar<T> ub, Geo g, int md, int x0, int x1, double* loss) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     double acc = 0.0;
@@ -892,7 +1099,7 @@ __global__ void k_loss_seed(SetPtr<T> u, SetBar<T> ub, Geo g, int md, int x0, in
 
 // real inner product sum Re(conj(a) b) over n complex elements
 template <typename T>
-__global__ void k_dot(const cx<T>* a, const cx<T>* b, size_t n, double* out) {
+__global__ void __launch_bounds__(256) k_dot(const cx<T>* a, const cx<T>* b, size_t n, double* out) {
     double acc = 0.0;
     for (size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += size_t(gridDim.x) * blockDim.x) {
         cx<T> x = ld(a + q), y = ld(b + q);

@@ -81,7 +81,7 @@ __device__ cx<T> bx_new_at(const StageArgs<T>& a, int m, int k, int i) {
 }
 
 template <typename T>
-__global__ void k_longitudinal(StageArgs<T> a) {
+__global__ void __launch_bounds__(256) k_longitudinal(StageArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -164,7 +164,7 @@ __global__ void k_longitudinal(StageArgs<T> a) {
 // movers at column i+1 and the left movers at column i
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_transverse(StageArgs<T> a) {
+__global__ void __launch_bounds__(256) k_transverse(StageArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -220,7 +220,7 @@ __global__ void k_transverse(StageArgs<T> a) {
 // per column
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_ghost_bth(StageArgs<T> a) {
+__global__ void __launch_bounds__(256) k_ghost_bth(StageArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nx) return;
@@ -250,7 +250,7 @@ __global__ void k_ghost_bth(StageArgs<T> a) {
 // mode_convolution, Ta_plus_update, Ta_minus_update, axion_x_open)
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-__global__ void k_axion_ta(AxionArgs<T> a) {
+__global__ void __launch_bounds__(256) k_axion_ta(AxionArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
@@ -311,7 +311,7 @@ __global__ void k_axion_ta(AxionArgs<T> a) {
 
 // stage 5: phi^{n+1} from T_a^{n+1/2} (Eq. phi_update) and the exterior ghost
 template <typename T>
-__global__ void k_axion_phi(AxionArgs<T> a) {
+__global__ void __launch_bounds__(256) k_axion_phi(AxionArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
@@ -342,7 +342,7 @@ __global__ void k_axion_phi(AxionArgs<T> a) {
 // j_a,r at (r_{j+1/2}, t^{n+1/2}), j_a,theta at (r_j, t^{n+1/2})
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-__global__ void k_axion_current(AxionArgs<T> a) {
+__global__ void __launch_bounds__(256) k_axion_current(AxionArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -446,7 +446,7 @@ template hipError_t axion_current_w<float>(const AxionArgs<float>&, hipStream_t)
 // moving window: copy every plane shifted left by one column, zero the last
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_window_shift(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Geo g, int nplanes) {
+__global__ void __launch_bounds__(256) k_window_shift(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Geo g, int nplanes) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;           // over planes * modes * (nr+1)
     if (i >= g.nx) return;
@@ -460,7 +460,7 @@ __global__ void k_window_shift(const cx<T>* __restrict__ src, cx<T>* __restrict_
 // radial or azimuthal polarisation with B = x_hat x E)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_add_pulse(SetPtr<T> s, Geo g, int pol, const double* fK, const double* fJ, const double* fG) {
+__global__ void __launch_bounds__(256) k_add_pulse(SetPtr<T> s, Geo g, int pol, const double* fK, const double* fJ, const double* fG) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= g.nx || j > g.nr) return;
