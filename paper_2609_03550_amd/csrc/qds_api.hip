@@ -98,49 +98,73 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     return QDS_OK;
 }
 
-// One fused step through the argument table (kernel A or the background
+// Device view of one step's entry in an argument table: the kernel
+// arguments, the single-entry launch lists and their block counts.
+template <typename T>
+struct TabView {
+    const qds::FusedArgs<T>* fa;
+    const qds::AxionArgs<T>* xa;
+    const int* idx;
+    const int* firstA;
+    const int* firstC;
+    const int* firstB;
+    int nA, nC, nB;
+};
+
+template <typename T>
+TabView<T> ktab_view(KTab<T>* K, const KTab<T>& host, int q) {
+    return TabView<T>{K->fa + q, K->xa + q, K->idx, K->firstA, K->firstC, K->firstB,
+                      host.firstA[1], host.firstC[1], host.firstB[1]};
+}
+
+// One fused step through an argument-table entry (kernel A or the background
 // set, then the axion current and the regenerated set), each launch
 // bracketed by the event pair ev[2k], ev[2k+1] when ev is given.
 template <typename T>
-qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
-                      hipStream_t s, hipEvent_t* ev) {
+qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, hipStream_t s, hipEvent_t* ev) {
     auto list = [&](const int* first_dev, int rows) {
         qds::BatchList L;
-        L.idx = K->idx;
+        L.idx = v.idx;
         L.first = first_dev;
         L.n = 1;
         L.rows = rows;
         return L;
     };
-    const qds::BatchList LA = list(K->firstA, c->trows[0]), LC = list(K->firstC, c->trows[1]),
-                         LB = list(K->firstB, c->trows[2]), LB0 = list(K->firstB, c->trows[0]);
-    const int q = st->cur;
-    const qds::FusedArgs<T>* fa = K->fa + q;
+    const qds::BatchList LA = list(v.firstA, c->trows[0]), LC = list(v.firstC, c->trows[1]),
+                         LB = list(v.firstB, c->trows[2]), LB0 = list(v.firstB, c->trows[0]);
     hipEvent_t* e0 = ev ? ev : (c->timing ? timing_pair(c, 0) : nullptr);
     if (e0) hipEventRecord(e0[0], s);
     hipError_t e;
     if (p0.axion) {
-        e = qds::batch_a<T>(fa, LA, c->M, host.firstA[1], s);
+        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, s);
     } else {
         // the background set alone: the kernel-B march with the kernel-A tile
         const int strips = qds::fused_strips(c->g.nx);
-        e = qds::batch_em<T>(fa, LB0, 0, strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
+        e = qds::batch_em<T>(v.fa, LB0, 0, strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
     }
     if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     if (e0) hipEventRecord(e0[1], s);
     if (p0.arem) {
         hipEvent_t* e2 = ev ? ev + 2 : (c->timing ? timing_pair(c, 2) : nullptr);
         if (e2) hipEventRecord(e2[0], s);
-        e = qds::batch_current<T>(K->xa + q, LC, c->M, host.firstC[1], s);
+        e = qds::batch_current<T>(v.xa, LC, c->M, v.nC, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
         if (e2) hipEventRecord(e2[1], s);
         hipEvent_t* e1 = ev ? ev + 4 : (c->timing ? timing_pair(c, 1) : nullptr);
         if (e1) hipEventRecord(e1[0], s);
-        e = qds::batch_em<T>(fa, LB, 1, host.firstB[1], s);
+        e = qds::batch_em<T>(v.fa, LB, 1, v.nB, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
         if (e1) hipEventRecord(e1[1], s);
     }
-    st->cur = 1 - q;
+    return QDS_OK;
+}
+
+template <typename T>
+qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
+                      hipStream_t s, hipEvent_t* ev) {
+    const qds_status r = table_launch<T>(c, p0, ktab_view<T>(K, host, st->cur), s, ev);
+    if (r != QDS_OK) return r;
+    st->cur = 1 - st->cur;
     if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
     st->step += 1;
     return QDS_OK;
@@ -265,7 +289,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     QDS_TRY(hipMemcpyAsync(W.buf[0], u0->buf[u0->cur], S, hipMemcpyDeviceToDevice, s));
     for (int64_t n = 0; n < N; ++n) {
         if (n % C == 0) QDS_TRY(hipMemcpyAsync(ck + size_t(n / C) * S, W.buf[W.cur], S, hipMemcpyDeviceToDevice, s));
-        qds_status st = run_steps<T>(c, &W, J, ax, 1, s, true);
+        qds_status st = run_steps<T>(c, &W, J, ax, 1, s);
         if (st != QDS_OK) return st;
     }
     // loss and its gradient at step N
@@ -278,12 +302,54 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     QDS_TRY(qds::loss_seed<T>(U, Yb, geo(c), L->set, L->mode, L->x_begin, L->x_end, red, s));
     // reverse sweep over the segments
     qds::StepPlan<T> p = make_plan<T>(c, J, ax);
+    // argument table of the recomputation: entry k advances segment state k
+    // into k + 1 (the segment buffers stay in place for the whole sweep)
+    qds::FusedArgs<T>* tab = nullptr;
+    qds::AxionArgs<T>* xtab = nullptr;
+    KTab<T>* K = nullptr;
+    KTab<T> khost;
+    if (use_fused(c)) {
+        qds_state W2 = W;
+        if (sync_ktab<T>(c, &W2, p, s, &K) != QDS_OK) return QDS_EHIP;
+        khost = *static_cast<const KTab<T>*>(c->ktab_pin);
+        const size_t fb = size_t(C) * sizeof(qds::FusedArgs<T>), xb = size_t(C) * sizeof(qds::AxionArgs<T>);
+        std::vector<unsigned char> host(fb + xb, 0);
+        auto* hf = reinterpret_cast<qds::FusedArgs<T>*>(host.data());
+        auto* hx = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + fb);
+        for (int64_t k = 0; k < C; ++k) {
+            hf[k] = fused_args<T>(c, p, at_seg(k), at_seg(k + 1), 0, 0);
+            hx[k] = axion_args<T>(c, p, at_seg(k), at_seg(k + 1));
+        }
+        void* dtab = nullptr;
+        QDS_TRY(hipMalloc(&dtab, fb + xb));
+        e = hipMemcpy(dtab, host.data(), fb + xb, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dtab);
+            return fail(c, QDS_EHIP, "backward: %s", hipGetErrorString(e));
+        }
+        tab = static_cast<qds::FusedArgs<T>*>(dtab);
+        xtab = reinterpret_cast<qds::AxionArgs<T>*>(static_cast<char*>(dtab) + fb);
+    }
+    struct FreeTab {
+        void* p;
+        ~FreeTab() {
+            if (p) hipFree(p);
+        }
+    } free_tab{tab};
     qds::cx<T>* jb[3];
     for (int k = 0; k < 3; ++k) jb[k] = reinterpret_cast<qds::cx<T>*>(jab + size_t(k) * P);
     for (int64_t sg = int64_t(nck) - 1; sg >= 0; --sg) {
         const int64_t n0 = sg * C, n1 = (n0 + C < N) ? n0 + C : N;
         QDS_TRY(hipMemcpyAsync(at_seg(0), ck + size_t(sg) * S, S, hipMemcpyDeviceToDevice, s));
         for (int64_t k = 0; k < n1 - n0; ++k) {
+            if (tab) {
+                // fused kernels through the segment's argument table
+                const TabView<T> v{tab + k, xtab + k, K->idx, K->firstA, K->firstC, K->firstB,
+                                   khost.firstA[1], khost.firstC[1], khost.firstB[1]};
+                qds_status st = table_launch<T>(c, p, v, s, nullptr);
+                if (st != QDS_OK) return st;
+                continue;
+            }
             qds_state R;
             R.buf[0] = at_seg(k);
             R.buf[1] = at_seg(k + 1);
