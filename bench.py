@@ -65,7 +65,8 @@ KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current"}
 def source_digest():
     """Digest of the kernel sources the HBM counters depend on."""
     h = hashlib.sha256()
-    for f in ("qds_fused.hip", "qds_stages.hip", "qds_stage_ops.hpp", "qds_kernels.hpp", "qds_common.hpp"):
+    for f in ("qds_fused.hip", "qds_current.hip", "qds_stages.hip", "qds_stage_ops.hpp", "qds_kernels.hpp",
+              "qds_common.hpp"):
         with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -152,6 +153,35 @@ def batched_leg(steps, graph_steps, count=64):
             "graph_steps": graph_steps, "tiles": tiles, "tuned": tuned,
             "batched_updates_per_s": cells * steps / t_batch, "one_at_a_time_updates_per_s": cells * steps / t_solo,
             "speedup": t_solo / t_batch}
+
+
+def stream_reference(nbytes=1 << 31, reps=10):
+    """Bandwidth a plain device copy (read + write) and a plain fill (write
+    only) reach in the same process: the practical ceiling next to the 8 TB/s
+    peak for kernels that both read and write their planes."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    t_copy = timed(lambda: b.copy_(a))
+    t_fill = timed(lambda: b.fill_(3))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_read_write_gbps": 2 * nbytes / t_copy / 1e9, "fill_write_gbps": nbytes / t_fill / 1e9,
+            "bytes": nbytes}
 
 
 def cpu_baseline(wl, seconds_target=15.0):
@@ -286,6 +316,8 @@ def main():
     if args.batched_steps > 0:
         out["batched"] = batched_leg(args.batched_steps, args.graph_steps)
         torch.cuda.empty_cache()
+    out["stream_reference"] = stream_reference()
+    out["roofline"]["frac_of_copy"] = achieved / out["stream_reference"]["copy_read_write_gbps"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
