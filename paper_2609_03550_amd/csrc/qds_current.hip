@@ -8,8 +8,8 @@
 // use (time averages of T^+-, E_r and E_theta at t^n, d_t phi at t^n, ...), so
 // every input plane is read once per step; the values of column i+1 come from
 // the next lane by a DPP shift.  The 18 per-mode factors are exchanged through
-// LDS between the waves, one component (6 factors) at a time, and each wave
-// evaluates C_m for its own mode.  The factors are those of ja_factors with
+// LDS between the waves (two barriers per row), and each wave evaluates C_m
+// for its own mode.  The factors are those of ja_factors with
 // the transport-variable form of the theta and r components.
 #include "qds_kernels.hpp"
 
@@ -113,7 +113,7 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     const T sj = T(a.s_j);
     const cx<T> zc = zero<T>();
 
-    __shared__ cx<T> sm[6][M][WAVE];
+    __shared__ cx<T> sm[18][M][WAVE];
     auto put = [&](int f, cx<T> v) { sm[f][m][lane] = v; };
 
     // window: K row j-1, J row j (and the m = 1 axis values of J row 0)
@@ -165,17 +165,6 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
             cx<T> f5 = inv_dr * (kc.ph0 - plo);
             put(0, f0); put(1, f1); put(2, f2); put(3, f3); put(4, f4); put(5, f5);
         }
-        __syncthreads();
-        if (calc) {
-            cx<T> A[M], B[M];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-                conv_one<T, M>(A, B, m, out[0], c == 1 ? T(-1) : T(1));
-            }
-        }
-        __syncthreads();
         // ---------------- j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2}) in transport form
         if (calc) {
             cx<T> gP0, gP1, gN0, gN1;
@@ -198,45 +187,34 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
             cx<T> ul0 = ax ? par * kc.up : kp.up, ul1 = ax ? par * up1 : upl1;
             cx<T> wl0 = ax ? par * kc.wm : kp.wm, wl1 = ax ? par * wm1 : wml1;
             cx<T> pl = ax ? par * kc.phm : kp.phm;
-            put(0, T(0.5) * fP);
-            put(1, T(0.5) * (T(0.5) * (wl0 + kc.wm) + T(0.5) * (wl1 + wm1)));
-            put(2, jc.ex);
-            put(3, inv_dr * (kc.phm - pl));
-            put(4, T(-0.5) * fN);
-            put(5, T(0.5) * (T(0.5) * (ul0 + kc.up) + T(0.5) * (ul1 + up1)));
+            put(6, T(0.5) * fP);
+            put(7, T(0.5) * (T(0.5) * (wl0 + kc.wm) + T(0.5) * (wl1 + wm1)));
+            put(8, jc.ex);
+            put(9, inv_dr * (kc.phm - pl));
+            put(10, T(-0.5) * fN);
+            put(11, T(0.5) * (T(0.5) * (ul0 + kc.up) + T(0.5) * (ul1 + up1)));
         }
-        __syncthreads();
-        if (calc) {
-            cx<T> A[M], B[M];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-                conv_one<T, M>(A, B, m, out[1], c == 1 ? T(-1) : T(1));
-            }
-        }
-        __syncthreads();
         // ---------------- j_a,r at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}) in transport form
         if (calc) {
             cx<T> qp = T(0.25) * ((jc.Qp + Qp1) + (jn.Qp + Qpn1));
             cx<T> qm = T(0.25) * ((jc.Qm + Qm1) + (jn.Qm + Qmn1));
             if (m == 1) { qp = qp + a.br1; qm = qm - a.br1; }
             const T irk = T(1) / ((T(j) + T(0.5)) * dr);
-            put(0, T(0.5) * qp);
-            put(1, T(0.5) * (kc.up + up1));
-            put(2, T(0.5) * qm);
-            put(3, T(0.5) * (kc.wm + wm1));
-            put(4, T(0.5) * (jc.ex + jn.ex));
-            put(5, imul(-T(m) * irk, kc.phm));
+            put(12, T(0.5) * qp);
+            put(13, T(0.5) * (kc.up + up1));
+            put(14, T(0.5) * qm);
+            put(15, T(0.5) * (kc.wm + wm1));
+            put(16, T(0.5) * (jc.ex + jn.ex));
+            put(17, imul(-T(m) * irk, kc.phm));
         }
         __syncthreads();
         if (calc) {
             cx<T> A[M], B[M];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < 9; ++c) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-                conv_one<T, M>(A, B, m, out[2], c == 1 ? T(-1) : T(1));
+                conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
             }
         }
         if (owner) {
