@@ -65,6 +65,10 @@ class Physics:
     bext: Tuple[complex, complex, complex] = (0j, 0j, 0j)
     drive: Optional[object] = None   # inputs.Drive
     axion_rbc: str = "mur"           # mur | three_level (the latter only for its instability test)
+    # evaluation order of the transverse products in S_a and in the theta and r
+    # components of j_a: "transport" collects them in the transport variables
+    # (see axion_source), "eb" forms the literal E and B products
+    product_form: str = "transport"
 
 
 def grid_physics(wl) -> Tuple[Grid, Physics]:
@@ -319,6 +323,9 @@ def _bg_fields(c: _Ctx, st: Dict, new: Dict, bext):
     f["Bt1"] = 0.5 * (new["Trp0"] - new["Trm0"])
     f["Et1"] = 0.5 * (new["Ttp0"] + new["Ttm0"])
     f["Br1"] = 0.5 * (new["Ttp0"] - new["Ttm0"])
+    for k in ("Trp0", "Trm0", "Ttp0", "Ttm0"):
+        f[k.replace("0", "") + "_o"] = st[k]
+        f[k.replace("0", "") + "_n"] = new[k]
     f["Exo"], f["Exh"] = st["Ex0"], new["Ex0"]
     f["Bxo"], f["Bxh"] = st["Bx0"][:, : c.nr], new["Bx0"][:, : c.nr]
     return f
@@ -336,17 +343,34 @@ def _ext(c: _Ctx, bext, comp: int) -> torch.Tensor:
     return v
 
 
-def axion_source(c: _Ctx, f: Dict, bext) -> torch.Tensor:
-    """S_a^n = sum_alpha C_m{E_alpha, B_alpha} at (x_{i+1/2}, r_{j+1/2}, t^n)."""
+def axion_source(c: _Ctx, f: Dict, bext, form: str = "transport") -> torch.Tensor:
+    """S_a^n = sum_alpha C_m{E_alpha, B_alpha} at (x_{i+1/2}, r_{j+1/2}, t^n)
+    (Eqs. source_mode_zero, source_mode_m).
+
+    With E_r, B_theta = (T_r^+ +- T_r^-)/2 and E_theta, B_r = (T_theta^+ +-
+    T_theta^-)/2 (Eq. Tdefs), and C_m bilinear and symmetric, the transverse
+    products collect exactly into
+        C{E_r, B_r} + C{E_theta, B_theta}
+            = 1/2 C{T_r^+ + b_theta, T_theta^+ + b_r} - 1/2 C{T_r^- - b_theta, T_theta^- - b_r}
+    (b = the uniform external field).  ``form="transport"`` evaluates this
+    collected form, whose products pair a large factor with a small one for
+    co-propagating waves; ``form="eb"`` the literal products, which cancel to a
+    few parts in 10^13 there."""
     nr = c.nr
-    Er = c.xavg(f["Er0"])
-    Bt = c.xavg(f["Bt0"]) + _ext(c, bext, 2)
-    Et = 0.25 * (f["Et0"][:, :nr] + f["Et0"][:, 1:] + c.xp(f["Et0"][:, :nr]) + c.xp(f["Et0"][:, 1:]))
-    Br = 0.25 * (f["Br0"][:, :nr] + f["Br0"][:, 1:] + c.xp(f["Br0"][:, :nr]) + c.xp(f["Br0"][:, 1:])) \
-        + _ext(c, bext, 1)
     Exn = 0.5 * (f["Exo"] + f["Exh"])
     Ex = 0.5 * (Exn[:, :nr] + Exn[:, 1:])
     Bx = 0.5 * (f["Bxo"] + f["Bxh"]) + _ext(c, bext, 0)
+    x4 = lambda F: 0.25 * (F[:, :nr] + F[:, 1:] + c.xp(F[:, :nr]) + c.xp(F[:, 1:]))
+    if form == "transport":
+        bt, br = _ext(c, bext, 2), _ext(c, bext, 1)
+        Pp, Pm = c.xavg(f["Trp_o"]), c.xavg(f["Trm_o"])
+        Qp, Qm = x4(f["Ttp_o"]), x4(f["Ttm_o"])
+        S = mode_conv(Ex, Bx) + 0.5 * mode_conv(Pp + bt, Qp + br) - 0.5 * mode_conv(Pm - bt, Qm - br)
+        return S * c.live
+    Er = c.xavg(f["Er0"])
+    Bt = c.xavg(f["Bt0"]) + _ext(c, bext, 2)
+    Et = x4(f["Et0"])
+    Br = x4(f["Br0"]) + _ext(c, bext, 1)
     S = mode_conv(Ex, Bx) + mode_conv(Er, Br) + mode_conv(Et, Bt)
     return S * c.live
 
@@ -469,14 +493,22 @@ def _ghost_Bt(c: _Ctx, Bt: torch.Tensor, Br: torch.Tensor) -> torch.Tensor:
     return g
 
 
-def axion_current(c: _Ctx, f: Dict, st: Dict, kg: Dict, bext) -> Tuple[torch.Tensor, ...]:
+def axion_current(c: _Ctx, f: Dict, st: Dict, kg: Dict, bext, form: str = "transport") -> Tuple[torch.Tensor, ...]:
     """Mode expansion of j_a = B_0 d_t phi - E_0 x grad phi (Eqs. jax_mode,
     jar_mode, jat_mode), each component evaluated directly at the source point
     of the regenerated set: j_a,x at (x_{i+1/2}, r_j, t^n), j_a,r at
     (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}), j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2}).
     Off-grid values are centred means of the nearest samples; d_t phi and d_x phi
     come from T_a (Eq. phi_update); d_theta phi^(l) = -i l phi^(l).  The
-    components on the outer integer row r_nr are set to zero."""
+    components on the outer integer row r_nr are set to zero.
+
+    ``form="transport"`` collects the theta and r components in the transport
+    variables (T_a^+- = d_t phi -+ d_x phi, Eq. T_axion_def; Eq. Tdefs):
+        C{B_theta, d_t phi} + C{E_r, d_x phi} = 1/2 C{T_r^+ + b_theta, T_a^-} - 1/2 C{T_r^- - b_theta, T_a^+}
+        C{B_r, d_t phi} - C{E_theta, d_x phi} = 1/2 C{T_theta^+ + b_r, T_a^+} - 1/2 C{T_theta^- - b_r, T_a^-}
+    with every factor brought to the source point by the same means (the axis
+    ghosts combine likewise: T_r^+- at r_{-1/2} = 2i T_theta^-+(0) - T_r^+-(1/2)
+    for m = 1)."""
     M, nr, dr = c.M, c.nr, c.dr
     mv = c.m.to(CDT)
     phi0, phi1 = st["phi"], kg["phi"]
@@ -517,26 +549,52 @@ def axion_current(c: _Ctx, f: Dict, st: Dict, kg: Dict, bext) -> Tuple[torch.Ten
     jax = ja_x_modes(BxJ, dtJ, ErJ, pthJ, EtJ, drJ)
 
     # ---- j_a,r at t^{n+1/2}
-    Brh = 0.5 * (f["Br0"] + f["Br1"])
-    Eth = 0.5 * (f["Et0"] + f["Et1"])
-    BrK = 0.25 * (Brh[:, :nr] + Brh[:, 1:] + c.xp(Brh[:, :nr]) + c.xp(Brh[:, 1:])) + _ext(c, bext, 1)
-    EtK = 0.25 * (Eth[:, :nr] + Eth[:, 1:] + c.xp(Eth[:, :nr]) + c.xp(Eth[:, 1:]))
-    dtK = c.xavg(dt_h)
-    dxK = c.xavg(dx_h)
+    x4 = lambda F: 0.25 * (F[:, :nr] + F[:, 1:] + c.xp(F[:, :nr]) + c.xp(F[:, 1:]))
     ExK = 0.5 * (f["Exh"][:, :nr] + f["Exh"][:, 1:])
     pthK = -1j * mv * phih / c.rK
-    jar = ja_r_modes(BrK, dtK, EtK, dxK, ExK, pthK)
+    br, bt = _ext(c, bext, 1), _ext(c, bext, 2)
+    if form == "transport":
+        Qp = x4(0.5 * (f["Ttp_o"] + f["Ttp_n"]))
+        Qm = x4(0.5 * (f["Ttm_o"] + f["Ttm_n"]))
+        ApK, AmK = c.xavg(kg["Tap"]), c.xavg(kg["Tam"])
+        jar = (0.5 * mode_conv(Qp + br, ApK) - 0.5 * mode_conv(Qm - br, AmK) + mode_conv(ExK, pthK))
+    else:
+        Brh = 0.5 * (f["Br0"] + f["Br1"])
+        Eth = 0.5 * (f["Et0"] + f["Et1"])
+        BrK = x4(Brh) + br
+        EtK = x4(Eth)
+        dtK = c.xavg(dt_h)
+        dxK = c.xavg(dx_h)
+        jar = ja_r_modes(BrK, dtK, EtK, dxK, ExK, pthK)
 
     # ---- j_a,theta at t^{n+1/2}
-    Bth = 0.5 * (f["Bt0"] + f["Bt1"])
-    Erh = 0.5 * (f["Er0"] + f["Er1"])
-    BtJ = c.xavg(_k2j(c, Bth, _ghost_Bt(c, Bth, Brh))) + _ext(c, bext, 2)
-    dtJh = c.xavg(k2j_par(dt_h))
     ExJ = f["Exh"][:, :nr]
     drJh = dr_par(phih)
-    ErJh = c.xavg(_k2j(c, Erh, _ghost_Er(c, Erh, Eth)))
-    dxJh = c.xavg(k2j_par(dx_h))
-    jat = ja_t_modes(BtJ, dtJh, ExJ, drJh, ErJh, dxJh)
+    if form == "transport":
+        Ph = 0.5 * (f["Trp_o"] + f["Trp_n"])
+        Nh = 0.5 * (f["Trm_o"] + f["Trm_n"])
+        Tph = 0.5 * (f["Ttp_o"] + f["Ttp_n"])
+        Tmh = 0.5 * (f["Ttm_o"] + f["Ttm_n"])
+        # axis ghosts at r_{-1/2}: odd for m != 1, the axis relation for m = 1
+        gP, gN = -Ph[:, 0], -Nh[:, 0]
+        if M > 1:
+            gP = torch.cat([gP[:1], (2j * Tmh[1, 0] - Ph[1, 0]).view(1, -1), gP[2:]], dim=0)
+            gN = torch.cat([gN[:1], (2j * Tph[1, 0] - Nh[1, 0]).view(1, -1), gN[2:]], dim=0)
+        PJ = c.xavg(_k2j(c, Ph, gP)) + bt
+        NJ = c.xavg(_k2j(c, Nh, gN)) - bt
+        AmJ = c.xavg(k2j_par(kg["Tam"]))
+        ApJ = c.xavg(k2j_par(kg["Tap"]))
+        jat = 0.5 * mode_conv(PJ, AmJ) - 0.5 * mode_conv(NJ, ApJ) - mode_conv(ExJ, drJh)
+    else:
+        Brh = 0.5 * (f["Br0"] + f["Br1"])
+        Eth = 0.5 * (f["Et0"] + f["Et1"])
+        Bth = 0.5 * (f["Bt0"] + f["Bt1"])
+        Erh = 0.5 * (f["Er0"] + f["Er1"])
+        BtJ = c.xavg(_k2j(c, Bth, _ghost_Bt(c, Bth, Brh))) + bt
+        dtJh = c.xavg(k2j_par(dt_h))
+        ErJh = c.xavg(_k2j(c, Erh, _ghost_Er(c, Erh, Eth)))
+        dxJh = c.xavg(k2j_par(dx_h))
+        jat = ja_t_modes(BtJ, dtJh, ExJ, drJh, ErJh, dxJh)
 
     return zrow(jax), jar * c.live, zrow(jat)
 
@@ -555,11 +613,11 @@ def step(st: Dict, g: Grid, ph: Physics) -> Dict:
     new = em_set(c, st, 0, ph.wp2, jx_drive, zK, zJ)
     if ph.axion:
         f = _bg_fields(c, st, new, ph.bext)
-        S = axion_source(c, f, ph.bext)
+        S = axion_source(c, f, ph.bext, ph.product_form)
         kg = kg_update(c, st, S, ph)
         new.update(kg)
         if ph.arem:
-            jax, jar, jat = axion_current(c, f, st, kg, ph.bext)
+            jax, jar, jat = axion_current(c, f, st, kg, ph.bext, ph.product_form)
             new.update(em_set(c, st, 1, ph.wp2, ph.s_j * jax, ph.s_j * jar, ph.s_j * jat))
     for k, v in st.items():
         if k not in new and k not in ("n", "w"):

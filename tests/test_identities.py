@@ -63,3 +63,27 @@ def test_transport_form_removes_the_single_precision_cancellation():
     tf = 0.5 * mode_conv(c(Tp), c(Sp)) - 0.5 * mode_conv(c(Tm), c(Sm))
     err = lambda x: float((x.to(torch.complex128) - ref).norm() / ref.norm())
     assert err(tf) < 1e-6 < err(eb)
+
+
+def test_oracle_product_forms_agree():
+    """The oracle evaluates the transverse products of S_a and of the theta and
+    r components of j_a in the collected transport form by default; on a full
+    physics run with an external field and two crossed colours it agrees with
+    the literal E/B products to rounding (the E/B products lose a few digits to
+    cancellation, the difference stays far below the FP32 bound)."""
+    from dataclasses import replace
+    from oracle import qds as Q
+    from paper_2609_03550_amd import inputs as I
+    H = I.H
+    p1 = I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, 10 * H, 0.45 * 48 * H)
+    p2 = I.Pulse("z", 0.5, 0.8, 2 * I.LAMBDA, 10 * H, 0.45 * 48 * H)
+    wl = I.Workload("forms", 48, 10, 3, 0, wp2=0.02, axion=True, arem=True, ma2=0.03,
+                    pulses=(p1, p2), bext=(0.05 + 0j, 0.1 + 0.02j, -0.02 + 0.1j))
+    g, ph = Q.grid_physics(wl)
+    assert ph.product_form == "transport"
+    out = {}
+    for form in ("transport", "eb"):
+        out[form] = Q.run(Q.init_state(wl), g, replace(ph, product_form=form), 9)
+    for k, v in out["eb"].items():
+        if isinstance(v, torch.Tensor) and v.is_complex() and float(v.norm()) > 0:
+            assert float((out["transport"][k] - v).norm() / v.norm()) < 1e-10, k
