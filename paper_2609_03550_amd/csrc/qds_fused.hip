@@ -98,10 +98,11 @@ struct Out {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct EmWin {
-    // T_r^+- at K rows j (slot 0) and j+1 (slot 1), columns i (a) and i+1 (b)
-    cx<T> rpa[2], rpb[2], rma[2], rmb[2];
+    // T_r^+- at K rows j (slot 0) and j+1 (slot 1), column i (the values of
+    // column i+1 are the next lane's, see EmB)
+    cx<T> rpa[2], rma[2];
     // T_theta^+- at J rows j (slot 0) and j+1 (slot 1)
-    cx<T> tpa[2], tpb[2], tma[2], tmb[2];
+    cx<T> tpa[2], tma[2];
     cx<T> ex0[2];      // E_x^{n-1/2} at J = j, j+1
     cx<T> ex1[3];      // E_x^{n+1/2} at J = j-1, j, j+1
     cx<T> bx0[2];      // B_x^{n-1/2} at K = j, j+1
@@ -115,6 +116,13 @@ struct EmWin {
     cx<T> n_tpa, n_tpb, n_tma, n_tmb;   // T_theta^{n+1} at J = j
 };
 
+
+// Column i+1 of the window's transverse values for one march step, taken
+// from the next lane (built in uniform control flow at the top of the step).
+template <typename T>
+struct EmB {
+    cx<T> rpb[2], rmb[2], tpb[2], tmb[2];
+};
 
 template <typename T>
 struct Ctx {
@@ -186,17 +194,30 @@ __device__ __forceinline__ EmPf<T> em_fetch(const Ctx<T>& c, const SetP<T>& s, i
     return p;
 }
 
-// moves a fetched row into slot 1; the column i+1 values come from the next
-// lane (called in uniform control flow, every lane active)
+// moves a fetched row into slot 1
 template <typename T>
 __device__ __forceinline__ void em_take(const Ctx<T>& c, EmWin<T>& W, const EmPf<T>& p, int k, int nr) {
     if (k > nr) return;
-    W.rpa[1] = p.rpa; W.rpb[1] = c.x.Rn(p.rpa); W.rma[1] = p.rma; W.rmb[1] = c.x.Rn(p.rma);
-    W.tpa[1] = p.tpa; W.tpb[1] = c.x.Rn(p.tpa); W.tma[1] = p.tma; W.tmb[1] = c.x.Rn(p.tma);
+    W.rpa[1] = p.rpa; W.rma[1] = p.rma;
+    W.tpa[1] = p.tpa; W.tma[1] = p.tma;
     W.ex0[1] = p.ex0;
     W.bx0[1] = p.bx0;
     W.pjx = p.jx;
     W.pjxa = p.jxa;
+}
+
+// column i+1 of both window slots from the next lane (every lane active)
+template <typename T>
+__device__ __forceinline__ EmB<T> em_bvals(const Ctx<T>& c, const EmWin<T>& W) {
+    EmB<T> B;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        B.rpb[q] = c.x.Rn(W.rpa[q]);
+        B.rmb[q] = c.x.Rn(W.rma[q]);
+        B.tpb[q] = c.x.Rn(W.tpa[q]);
+        B.tmb[q] = c.x.Rn(W.tma[q]);
+    }
+    return B;
 }
 
 // total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra + drive
@@ -220,34 +241,35 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
 
 // E_x^{n+1/2} at J = j+1 from the window (Eqs. Ex_update, Gammax_explicit, axis_Ex)
 template <typename T>
-__device__ __forceinline__ cx<T> em_ex_new(const Ctx<T>& c, const EmWin<T>& W, int jj, cx<T> jx, T irj) {
+__device__ __forceinline__ cx<T> em_ex_new(const Ctx<T>& c, const EmWin<T>& W, const EmB<T>& B, int jj, cx<T> jx,
+                                          T irj) {
     const T h = c.h;
     const int m = c.m;
     if (!c.live || (!c.g.open_r && jj == c.g.nr)) return zero<T>();
     if (jj == 0) {
         if (m != 0) return zero<T>();
-        cx<T> b = T(0.25) * ((W.rpa[1] - W.rma[1]) + (W.rpb[1] - W.rmb[1]));
+        cx<T> b = T(0.25) * ((W.rpa[1] - W.rma[1]) + (B.rpb[1] - B.rmb[1]));
         return W.ex0[1] + h * ((T(4) * c.inv_dr) * b - jx);
     }
-    cx<T> lo0 = T(0.5) * (W.rpa[0] - W.rma[0]), lo1 = T(0.5) * (W.rpb[0] - W.rmb[0]);
-    cx<T> hi0 = T(0.5) * (W.rpa[1] - W.rma[1]), hi1 = T(0.5) * (W.rpb[1] - W.rmb[1]);
+    cx<T> lo0 = T(0.5) * (W.rpa[0] - W.rma[0]), lo1 = T(0.5) * (B.rpb[0] - B.rmb[0]);
+    cx<T> hi0 = T(0.5) * (W.rpa[1] - W.rma[1]), hi1 = T(0.5) * (B.rpb[1] - B.rmb[1]);
     cx<T> bavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
     cx<T> db = c.inv_2dr * ((hi0 + hi1) - (lo0 + lo1));
-    cx<T> bravg = T(0.25) * ((W.tpa[1] - W.tma[1]) + (W.tpb[1] - W.tmb[1]));
+    cx<T> bravg = T(0.25) * ((W.tpa[1] - W.tma[1]) + (B.tpb[1] - B.tmb[1]));
     cx<T> gx = irj * bavg + db + imul(T(m) * irj, bravg) - jx;
     return W.ex0[1] + h * gx;
 }
 
 // B_x^{n+1/2} at K = j (Eqs. Ex_update, Phix_explicit)
 template <typename T>
-__device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, T irk) {
+__device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, const EmB<T>& B, T irk) {
     if (!c.live) return zero<T>();
     const T h = c.h;
-    cx<T> lo0 = T(0.5) * (W.tpa[0] + W.tma[0]), lo1 = T(0.5) * (W.tpb[0] + W.tmb[0]);
-    cx<T> hi0 = T(0.5) * (W.tpa[1] + W.tma[1]), hi1 = T(0.5) * (W.tpb[1] + W.tmb[1]);
+    cx<T> lo0 = T(0.5) * (W.tpa[0] + W.tma[0]), lo1 = T(0.5) * (B.tpb[0] + B.tmb[0]);
+    cx<T> hi0 = T(0.5) * (W.tpa[1] + W.tma[1]), hi1 = T(0.5) * (B.tpb[1] + B.tmb[1]);
     cx<T> eavg = T(0.25) * (lo0 + hi0 + lo1 + hi1);
     cx<T> de = c.inv_2dr * ((hi0 + hi1) - (lo0 + lo1));
-    cx<T> eravg = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
+    cx<T> eravg = T(0.25) * ((W.rpa[0] + W.rma[0]) + (B.rpb[0] + B.rmb[0]));
     cx<T> fx = -(irk * eavg + de) - imul(T(c.m) * irk, eravg);
     return W.bx0[0] + h * fx;
 }
@@ -255,10 +277,10 @@ __device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, T
 // plasma j_theta at (x_{i+1/2}, r_j, t^{n+1/2}) from the window slot s, writing
 // the new plasma j_theta at the integer column i
 template <typename T>
-__device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, int row, int slot,
-                                           bool write) {
+__device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, const EmB<T>& B,
+                                           int row, int slot, bool write) {
     cx<T> ja = c.x.L(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
-    cx<T> jb = c.x.R(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpb[slot] + W.tmb[slot]));
+    cx<T> jb = c.x.R(s.jt, c.m, row) + c.wp2h * (T(0.5) * (B.tpb[slot] + B.tmb[slot]));
     if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
     if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
     if (c.x.i1 < 0) jb = zero<T>();
@@ -268,8 +290,8 @@ __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, co
 // one march step of the electromagnetic set: outputs E_x(J=j+1), B_x(K=j)
 // (and the exterior ghost at j = nr-1), T_r(K=j), T_theta(J=j)
 template <typename T>
-__device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, int j, int r0, int r1,
-                                        const RowInv<T>& ri) {
+__device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, const EmB<T>& B, int j,
+                                        int r0, int r1, const RowInv<T>& ri) {
     const Geo& g = c.g;
     const int m = c.m;
     const T h = c.h, dr = c.dr;
@@ -278,7 +300,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     // ---- E_x^{n+1/2} at J = j+1
     if (j + 1 <= g.nr) {
         W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa);
-        W.ex1[2] = em_ex_new(c, W, j + 1, W.jx_n1, ri.irJ1);
+        W.ex1[2] = em_ex_new(c, W, B, j + 1, W.jx_n1, ri.irJ1);
         if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
         if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
     }
@@ -286,7 +308,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     const bool own_row = j >= r0 && j < r1;
     // ---- B_x^{n+1/2} at K = j
     if (j < g.nr) {
-        W.bx1[1] = em_bx_new(c, W, ri.irK);
+        W.bx1[1] = em_bx_new(c, W, B, ri.irK);
         if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
     }
     // ---- exterior ghost B_x^{n+1/2} at r_{nr+1/2} (Eq. em_r_open_bx)
@@ -295,13 +317,13 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         if (g.open_r && c.live) {
             const int N = g.nr;
             const T kap = c.kap, cR = c.cR;
-            cx<T> br_a = T(0.5) * (W.tpa[1] - W.tma[1]), br_b = T(0.5) * (W.tpb[1] - W.tmb[1]);
+            cx<T> br_a = T(0.5) * (W.tpa[1] - W.tma[1]), br_b = T(0.5) * (B.tpb[1] - B.tmb[1]);
             cx<T> rx = c.inv_2h * (br_b - br_a);
-            cx<T> ea = T(0.25) * ((W.tpa[1] + W.tma[1]) + (W.tpb[1] + W.tmb[1]));
-            cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (W.rpb[0] + W.rmb[0]));
+            cx<T> ea = T(0.25) * ((W.tpa[1] + W.tma[1]) + (B.tpb[1] + B.tmb[1]));
+            cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (B.rpb[0] + B.rmb[0]));
             rx = rx - (T(0.5) * ri.irJ1) * (ea + imul(T(m), ra));
             cx<T> jt = zero<T>();
-            if (c.plasma) jt = em_jt_avg(c, s, W, N, 1, false);
+            if (c.plasma) jt = em_jt_avg(c, s, W, B, N, 1, false);
             if (s.jta) jt = jt + c.x.L(s.jta, m, N);
             rx = rx - T(0.5) * jt;
             gh = W.bx0[0] + kap * (W.bx0[1] - W.bx1[1]) + cR * rx;
@@ -320,7 +342,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         if (c.live) {
             cx<T> jr = zero<T>();
             if (c.plasma) {
-                cx<T> jrb = c.x.R(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpb[0] + W.rmb[0]));
+                cx<T> jrb = c.x.R(s.jr, m, j) + c.wp2h * (T(0.5) * (B.rpb[0] + B.rmb[0]));
                 if (c.x.i1 < 0) jrb = zero<T>();
                 jr = T(0.5) * (jra + jrb);
             }
@@ -331,7 +353,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
             sm = h * (gr - pr);
         }
         W.n_rpb = (c.x.i1 >= 0) ? W.rpa[0] + sp : zero<T>();       // T_r^+ at column i+1
-        W.n_rma = W.rmb[0] + sm;                                     // T_r^- at column i
+        W.n_rma = B.rmb[0] + sm;                                     // T_r^- at column i
         cx<T> from_left = shfl_up1(W.n_rpb);
         cx<T> from_right = shfl_dn1(W.n_rma);
         W.n_rpa = (c.i == 0 && !g.per) ? zero<T>() : from_left;
@@ -346,7 +368,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     {
         const bool zrow = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
         cx<T> jt = zero<T>();
-        if (c.plasma) jt = em_jt_avg(c, s, W, j, 0, own_row);
+        if (c.plasma) jt = em_jt_avg(c, s, W, B, j, 0, own_row);
         if (s.jta && c.live) jt = jt + c.x.L(s.jta, m, j);
         cx<T> sp = zero<T>(), sm = zero<T>();
         if (c.live && !zrow) {
@@ -366,7 +388,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
             W.n_tpa = zero<T>();
             W.n_tmb = zero<T>();
         } else {
-            W.n_tpa = W.tpb[0] + sp;                                      // T_theta^+ at column i
+            W.n_tpa = B.tpb[0] + sp;                                      // T_theta^+ at column i
             W.n_tmb = (c.x.i1 >= 0) ? W.tma[0] + sm : zero<T>();          // T_theta^- at column i+1
         }
         cx<T> from_right = shfl_dn1(W.n_tpa);
@@ -383,12 +405,13 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
 
 // exterior ghost B_theta at r_{nr+1/2} (Eq. em_r_open_bt), at j = nr - 1 after em_step
 template <typename T>
-__device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, int r1) {
+__device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, const EmB<T>& B,
+                                             int r1) {
     const Geo& g = c.g;
     const int m = c.m, N = g.nr;
     const T h = c.h, dr = c.dr;
     cx<T> er_a = T(0.5) * (W.rpa[0] + W.rma[0]);
-    cx<T> er_b = T(0.5) * (W.rpb[0] + W.rmb[0]);
+    cx<T> er_b = T(0.5) * (B.rpb[0] + B.rmb[0]);
     cx<T> er_l = shfl_up1(er_a);                        // E_r at column i-1
     cx<T> jx_l = shfl_up1(W.jx_nr);                     // j_x at (x_{i-1/2}, r_nr)
     if (c.i == 0 && !g.per) er_l = jx_l = zero<T>();
@@ -414,8 +437,8 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
 
 template <typename T>
 __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
-    W.rpa[0] = W.rpa[1]; W.rpb[0] = W.rpb[1]; W.rma[0] = W.rma[1]; W.rmb[0] = W.rmb[1];
-    W.tpa[0] = W.tpa[1]; W.tpb[0] = W.tpb[1]; W.tma[0] = W.tma[1]; W.tmb[0] = W.tmb[1];
+    W.rpa[0] = W.rpa[1]; W.rma[0] = W.rma[1];
+    W.tpa[0] = W.tpa[1]; W.tma[0] = W.tma[1];
     W.ex0[0] = W.ex0[1];
     W.ex1[0] = W.ex1[1]; W.ex1[1] = W.ex1[2];
     W.bx0[0] = W.bx0[1];
@@ -489,8 +512,8 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     const int jstart = max(r0 - (r1 == g.nr + 1 ? 2 : 1), -1);
     // prime slot 1 with row jstart (so that the first em_load_next fills j+1)
     for (int q = 0; q < 2; ++q) {
-        W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
-        W.tpa[q] = W.tpb[q] = W.tma[q] = W.tmb[q] = zero<T>();
+        W.rpa[q] = W.rma[q] = zero<T>();
+        W.tpa[q] = W.tma[q] = zero<T>();
         W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
     }
     W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
@@ -517,12 +540,13 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         phw[0] = phw[1]; phw[1] = phw[2];
         phw[2] = phi_row(j + 1);
         em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
+        const EmB<T> B = em_bvals(c, W);
         const cx<T> ex1_j = W.ex1[1];
         const RowInv<T> ri = row_inv(c, j);
-        em_step(c, s, W, j, r0, r1, ri);
+        em_step(c, s, W, B, j, r0, r1, ri);
         if (j < 0) continue;
         const bool own_row = j >= r0 && j < r1;
-        if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
+        if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
 
         // ---------------- axion source S_a at K = j (Eqs. source_mode_zero/_m)
         cx<T> Sa = zero<T>();
@@ -536,10 +560,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             // transverse part from the transport variables: C{E_r, B_r} + C{E_th, B_th}
             // = 1/2 C{T_r^+ + b_th, T_th^+ + b_r} - 1/2 C{T_r^- - b_th, T_th^- - b_r}
             // (exact; no cancellation between two large products for co-propagating waves)
-            cx<T> fPp = T(0.25) * (W.rpa[0] + W.rpb[0]);
-            cx<T> fPm = T(-0.25) * (W.rma[0] + W.rmb[0]);
-            cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (W.tpb[0] + W.tpb[1]));
-            cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (W.tmb[0] + W.tmb[1]));
+            cx<T> fPp = T(0.25) * (W.rpa[0] + B.rpb[0]);
+            cx<T> fPm = T(-0.25) * (W.rma[0] + B.rmb[0]);
+            cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (B.tpb[0] + B.tpb[1]));
+            cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (B.tmb[0] + B.tmb[1]));
             if (m == 0) fBx = fBx + a.bx0;
             if (m == 1) {
                 fPp = fPp + T(0.5) * a.bt1;
@@ -658,8 +682,8 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     const SetP<T>& s = WHICH ? a.s1 : a.s0;
     EmWin<T> W;
     for (int q = 0; q < 2; ++q) {
-        W.rpa[q] = W.rpb[q] = W.rma[q] = W.rmb[q] = zero<T>();
-        W.tpa[q] = W.tpb[q] = W.tma[q] = W.tmb[q] = zero<T>();
+        W.rpa[q] = W.rma[q] = zero<T>();
+        W.tpa[q] = W.tma[q] = zero<T>();
         W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
     }
     W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
@@ -677,8 +701,9 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
         em_rotate(W);
         em_take(c, W, pf, j + 1, g.nr);
         if (j < jend) pf = em_fetch(c, s, j + 2);   // next row's loads overlap this row's work
-        em_step(c, s, W, j, r0, r1, row_inv(c, j));
-        if (j == g.nr - 1) em_ghost_bth(c, s, W, r1);
+        const EmB<T> B = em_bvals(c, W);
+        em_step(c, s, W, B, j, r0, r1, row_inv(c, j));
+        if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
     }
     if (a.window && c.owner && c.i == g.nx - 1) {
         for (int row = r0; row < r1; ++row) {
