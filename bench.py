@@ -100,8 +100,10 @@ def adjoint_ratio(dtype, steps, ckpt):
     s.load_pulses()
     f = qds.Solver(wl, dtype=dtype)
     f.load_pulses()
-    f.step(5)
-    s.backward(20, 5)               # warm both paths
+    f.set_option(qds.OPT_TUNE, 1)
+    f.step(10)                      # the forward's autotuner, then warm
+    s.set_option(qds.OPT_TUNE, 1)
+    s.backward(20, 10)              # tunes on its checkpoint pass; warms the adjoint
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     f.step(steps)

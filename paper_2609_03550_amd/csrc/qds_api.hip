@@ -287,9 +287,10 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     W.step = u0->step;
     W.window = 0;
     QDS_TRY(hipMemcpyAsync(W.buf[0], u0->buf[u0->cur], S, hipMemcpyDeviceToDevice, s));
-    for (int64_t n = 0; n < N; ++n) {
-        if (n % C == 0) QDS_TRY(hipMemcpyAsync(ck + size_t(n / C) * S, W.buf[W.cur], S, hipMemcpyDeviceToDevice, s));
-        qds_status st = run_steps<T>(c, &W, J, ax, 1, s);
+    for (int64_t n = 0; n < N; n += C) {
+        // one segment at a time (a pending autotune runs on the first one)
+        QDS_TRY(hipMemcpyAsync(ck + size_t(n / C) * S, W.buf[W.cur], S, hipMemcpyDeviceToDevice, s));
+        qds_status st = run_steps<T>(c, &W, J, ax, (n + C < N) ? C : N - n, s);
         if (st != QDS_OK) return st;
     }
     // loss and its gradient at step N
