@@ -113,115 +113,137 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     const T sj = T(a.s_j);
     const cx<T> zc = zero<T>();
 
-    __shared__ cx<T> sm[18][M][WAVE];
+    // factor exchange in two phases: j_a,x and j_a,r (12 factors), then j_a,theta (6)
+    __shared__ cx<T> sm[12][M][WAVE];
     auto put = [&](int f, cx<T> v) { sm[f][m][lane] = v; };
+    // out += sum over the np factor pairs from pair c0 on of +-C_m (pair sgn_pair negated)
+    auto convs = [&](int c0, int np, cx<T>& out, int sgn_pair) {
+        cx<T> A[M], B[M];
+#pragma unroll
+        for (int c = 0; c < np; ++c) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = sm[2 * (c0 + c)][k][lane]; B[k] = sm[2 * (c0 + c) + 1][k][lane]; }
+            conv_one<T, M>(A, B, m, out, (c == sgn_pair) ? T(-1) : T(1));
+        }
+    };
 
     // window: K row j-1, J row j (and the m = 1 axis values of J row 0)
     KRow<T> kp = r0 >= 1 ? load_k(a, eoff<T>(g, m, r0 - 1, i)) : zero_k<T>();
     JRow<T> jc = load_j(a, eoff<T>(g, m, r0, i));
+    // column i+1 of a value: the shift runs on every lane (a DPP read from a
+    // lane masked off by a branch would return zero); the missing column is
+    // zeroed after it
+    auto nx1 = [&](cx<T> v) {
+        const cx<T> w = next_lane(v);
+        return has1 ? w : zc;
+    };
     for (int j = r0; j < r1; ++j) {
         const bool calc = live && j < g.nr;
         KRow<T> kc = j < g.nr ? load_k(a, eoff<T>(g, m, j, i)) : zero_k<T>();
         JRow<T> jn = j + 1 <= g.nr ? load_j(a, eoff<T>(g, m, j + 1, i)) : zero_j<T>();
         const bool ax = j == 0;
-        // column i+1 of the rows in use
-        // the shift runs on every lane (a DPP read from a lane masked off by
-        // a branch would return zero); the missing column is zeroed after it
-        auto nx1 = [&](cx<T> v) {
-            const cx<T> w = next_lane(v);
-            return has1 ? w : zc;
-        };
-        const cx<T> dt1 = nx1(kc.dt0), er1 = nx1(kc.er0), et1 = nx1(jc.et0);
-        const cx<T> P1 = nx1(kc.P), N1 = nx1(kc.N), up1 = nx1(kc.up), wm1 = nx1(kc.wm);
-        const cx<T> Qp1 = nx1(jc.Qp), Qm1 = nx1(jc.Qm), Qpn1 = nx1(jn.Qp), Qmn1 = nx1(jn.Qm);
-        const cx<T> dtl1 = nx1(kp.dt0), erl1 = nx1(kp.er0), Pl1 = nx1(kp.P), Nl1 = nx1(kp.N);
-        const cx<T> upl1 = nx1(kp.up), wml1 = nx1(kp.wm);
-        cx<T> out[3] = {zc, zc, zc};
-        // ---------------- j_a,x at (x_{i+1/2}, r_j, t^n): B_x, d_t phi | E_r, d_theta phi / r | E_theta, d_r phi
-        if (calc) {
-            cx<T> blo = ax ? par * kc.bxn : kp.bxn;
-            cx<T> f0 = T(0.5) * (blo + kc.bxn);
-            if (m == 0) f0 = f0 + a.bx0;
-            cx<T> l0 = ax ? par * kc.dt0 : kp.dt0, l1 = ax ? par * dt1 : dtl1;
-            cx<T> f1 = T(0.5) * (T(0.5) * (l0 + kc.dt0) + T(0.5) * (l1 + dt1));
-            cx<T> g0, g1;
-            if (ax) {
-                if (m == 1) {
-                    g0 = imul(T(2), jc.et0) - kc.er0;
-                    g1 = imul(T(2), et1) - er1;
+        const uint32_t o = eoff<T>(g, m, j, i);
+        {
+            // ------------ j_a,x at (x_{i+1/2}, r_j, t^n): B_x, d_t phi | E_r, d_theta phi / r | E_theta, d_r phi
+            const cx<T> dt1 = nx1(kc.dt0), er1 = nx1(kc.er0), et1 = nx1(jc.et0);
+            const cx<T> dtl1 = nx1(kp.dt0), erl1 = nx1(kp.er0);
+            if (calc) {
+                cx<T> blo = ax ? par * kc.bxn : kp.bxn;
+                cx<T> f0 = T(0.5) * (blo + kc.bxn);
+                if (m == 0) f0 = f0 + a.bx0;
+                cx<T> l0 = ax ? par * kc.dt0 : kp.dt0, l1 = ax ? par * dt1 : dtl1;
+                cx<T> f1 = T(0.5) * (T(0.5) * (l0 + kc.dt0) + T(0.5) * (l1 + dt1));
+                cx<T> g0, g1;
+                if (ax) {
+                    if (m == 1) {
+                        g0 = imul(T(2), jc.et0) - kc.er0;
+                        g1 = imul(T(2), et1) - er1;
+                    } else {
+                        g0 = -kc.er0;
+                        g1 = -er1;
+                    }
                 } else {
-                    g0 = -kc.er0;
-                    g1 = -er1;
+                    g0 = kp.er0;
+                    g1 = erl1;
                 }
-            } else {
-                g0 = kp.er0;
-                g1 = erl1;
+                cx<T> f2 = T(0.5) * (T(0.5) * (g0 + kc.er0) + T(0.5) * (g1 + er1));
+                cx<T> plo = ax ? par * kc.ph0 : kp.ph0;
+                cx<T> f3 = ax ? ((m == 1) ? imul(-T(2) * inv_dr, kc.ph0) : zc)
+                              : imul(-T(m) * inv_dr / T(j), T(0.5) * (plo + kc.ph0));
+                cx<T> f4 = T(0.5) * (jc.et0 + et1);
+                cx<T> f5 = inv_dr * (kc.ph0 - plo);
+                put(0, f0); put(1, f1); put(2, f2); put(3, f3); put(4, f4); put(5, f5);
             }
-            cx<T> f2 = T(0.5) * (T(0.5) * (g0 + kc.er0) + T(0.5) * (g1 + er1));
-            cx<T> plo = ax ? par * kc.ph0 : kp.ph0;
-            cx<T> f3 = ax ? ((m == 1) ? imul(-T(2) * inv_dr, kc.ph0) : zc)
-                          : imul(-T(m) * inv_dr / T(j), T(0.5) * (plo + kc.ph0));
-            cx<T> f4 = T(0.5) * (jc.et0 + et1);
-            cx<T> f5 = inv_dr * (kc.ph0 - plo);
-            put(0, f0); put(1, f1); put(2, f2); put(3, f3); put(4, f4); put(5, f5);
         }
-        // ---------------- j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2}) in transport form
-        if (calc) {
-            cx<T> gP0, gP1, gN0, gN1;
-            if (ax) {
-                if (m == 1) {
-                    // axis relation of mode 1 (T_r^+ ghost 2i T_th^-(0) - T_r^+(1/2), T_r^- ghost 2i T_th^+(0) - T_r^-(1/2))
-                    gP0 = imul(T(2), jc.Qm) - kc.P;
-                    gP1 = imul(T(2), Qm1) - P1;
-                    gN0 = imul(T(2), jc.Qp) - kc.N;
-                    gN1 = imul(T(2), Qp1) - N1;
-                } else {
-                    gP0 = -kc.P; gP1 = -P1; gN0 = -kc.N; gN1 = -N1;
-                }
-            } else {
-                gP0 = kp.P; gP1 = Pl1; gN0 = kp.N; gN1 = Nl1;
+        {
+            // ------------ j_a,r at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}) in transport form
+            const cx<T> Qp1 = nx1(jc.Qp), Qm1 = nx1(jc.Qm), Qpn1 = nx1(jn.Qp), Qmn1 = nx1(jn.Qm);
+            const cx<T> up1 = nx1(kc.up), wm1 = nx1(kc.wm);
+            if (calc) {
+                cx<T> qp = T(0.25) * ((jc.Qp + Qp1) + (jn.Qp + Qpn1));
+                cx<T> qm = T(0.25) * ((jc.Qm + Qm1) + (jn.Qm + Qmn1));
+                if (m == 1) { qp = qp + a.br1; qm = qm - a.br1; }
+                const T irk = T(1) / ((T(j) + T(0.5)) * dr);
+                put(6, T(0.5) * qp);
+                put(7, T(0.5) * (kc.up + up1));
+                put(8, T(0.5) * qm);
+                put(9, T(0.5) * (kc.wm + wm1));
+                put(10, T(0.5) * (jc.ex + jn.ex));
+                put(11, imul(-T(m) * irk, kc.phm));
             }
-            cx<T> fP = T(0.5) * (T(0.5) * (gP0 + kc.P) + T(0.5) * (gP1 + P1));
-            cx<T> fN = T(0.5) * (T(0.5) * (gN0 + kc.N) + T(0.5) * (gN1 + N1));
-            if (m == 1) { fP = fP + a.bt1; fN = fN - a.bt1; }
-            cx<T> ul0 = ax ? par * kc.up : kp.up, ul1 = ax ? par * up1 : upl1;
-            cx<T> wl0 = ax ? par * kc.wm : kp.wm, wl1 = ax ? par * wm1 : wml1;
-            cx<T> pl = ax ? par * kc.phm : kp.phm;
-            put(6, T(0.5) * fP);
-            put(7, T(0.5) * (T(0.5) * (wl0 + kc.wm) + T(0.5) * (wl1 + wm1)));
-            put(8, jc.ex);
-            put(9, inv_dr * (kc.phm - pl));
-            put(10, T(-0.5) * fN);
-            put(11, T(0.5) * (T(0.5) * (ul0 + kc.up) + T(0.5) * (ul1 + up1)));
-        }
-        // ---------------- j_a,r at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}) in transport form
-        if (calc) {
-            cx<T> qp = T(0.25) * ((jc.Qp + Qp1) + (jn.Qp + Qpn1));
-            cx<T> qm = T(0.25) * ((jc.Qm + Qm1) + (jn.Qm + Qmn1));
-            if (m == 1) { qp = qp + a.br1; qm = qm - a.br1; }
-            const T irk = T(1) / ((T(j) + T(0.5)) * dr);
-            put(12, T(0.5) * qp);
-            put(13, T(0.5) * (kc.up + up1));
-            put(14, T(0.5) * qm);
-            put(15, T(0.5) * (kc.wm + wm1));
-            put(16, T(0.5) * (jc.ex + jn.ex));
-            put(17, imul(-T(m) * irk, kc.phm));
         }
         __syncthreads();
-        if (calc) {
-            cx<T> A[M], B[M];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-                conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
+        {
+            cx<T> ox = zc, orr = zc;
+            if (calc) {
+                convs(0, 3, ox, 1);
+                convs(3, 3, orr, 1);
+            }
+            if (owner) {
+                sto(a.jax, o, sj * ox);
+                if (j < g.nr) sto(a.jar, o, sj * orr);
             }
         }
-        if (owner) {
-            const uint32_t o = eoff<T>(g, m, j, i);
-            sto(a.jax, o, sj * out[0]);
-            sto(a.jat, o, sj * out[1]);
-            if (j < g.nr) sto(a.jar, o, sj * out[2]);
+        __syncthreads();
+        {
+            // ------------ j_a,theta at (x_{i+1/2}, r_j, t^{n+1/2}) in transport form
+            const cx<T> P1 = nx1(kc.P), N1 = nx1(kc.N), up1 = nx1(kc.up), wm1 = nx1(kc.wm);
+            const cx<T> Pl1 = nx1(kp.P), Nl1 = nx1(kp.N), upl1 = nx1(kp.up), wml1 = nx1(kp.wm);
+            const cx<T> Qp1 = nx1(jc.Qp), Qm1 = nx1(jc.Qm);
+            if (calc) {
+                cx<T> gP0, gP1, gN0, gN1;
+                if (ax) {
+                    if (m == 1) {
+                        // axis relation of mode 1 (T_r^+ ghost 2i T_th^-(0) - T_r^+(1/2), T_r^- ghost 2i T_th^+(0) - T_r^-(1/2))
+                        gP0 = imul(T(2), jc.Qm) - kc.P;
+                        gP1 = imul(T(2), Qm1) - P1;
+                        gN0 = imul(T(2), jc.Qp) - kc.N;
+                        gN1 = imul(T(2), Qp1) - N1;
+                    } else {
+                        gP0 = -kc.P; gP1 = -P1; gN0 = -kc.N; gN1 = -N1;
+                    }
+                } else {
+                    gP0 = kp.P; gP1 = Pl1; gN0 = kp.N; gN1 = Nl1;
+                }
+                cx<T> fP = T(0.5) * (T(0.5) * (gP0 + kc.P) + T(0.5) * (gP1 + P1));
+                cx<T> fN = T(0.5) * (T(0.5) * (gN0 + kc.N) + T(0.5) * (gN1 + N1));
+                if (m == 1) { fP = fP + a.bt1; fN = fN - a.bt1; }
+                cx<T> ul0 = ax ? par * kc.up : kp.up, ul1 = ax ? par * up1 : upl1;
+                cx<T> wl0 = ax ? par * kc.wm : kp.wm, wl1 = ax ? par * wm1 : wml1;
+                cx<T> pl = ax ? par * kc.phm : kp.phm;
+                put(0, T(0.5) * fP);
+                put(1, T(0.5) * (T(0.5) * (wl0 + kc.wm) + T(0.5) * (wl1 + wm1)));
+                put(2, jc.ex);
+                put(3, inv_dr * (kc.phm - pl));
+                put(4, T(-0.5) * fN);
+                put(5, T(0.5) * (T(0.5) * (ul0 + kc.up) + T(0.5) * (ul1 + up1)));
+            }
+        }
+        __syncthreads();
+        {
+            cx<T> ot = zc;
+            if (calc) convs(0, 3, ot, 1);
+            if (owner) sto(a.jat, o, sj * ot);
         }
         kp = kc;
         jc = jn;
