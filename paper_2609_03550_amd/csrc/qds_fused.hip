@@ -206,6 +206,27 @@ __device__ __forceinline__ void em_take(const Ctx<T>& c, EmWin<T>& W, const EmPf
     W.pjxa = p.jxa;
 }
 
+// The currents of row j that iteration j of the march reads at column i
+// (plasma j_r, j_theta; the extra j_r, j_theta of the regenerated set), issued
+// together at the top of the iteration; column i+1 comes from the next lane.
+template <typename T>
+struct EmRowX {
+    cx<T> jr, jt, jra, jta;
+};
+template <typename T>
+__device__ __forceinline__ EmRowX<T> em_fetch_x(const Ctx<T>& c, const SetP<T>& s, int j) {
+    EmRowX<T> x;
+    x.jr = x.jt = x.jra = x.jta = zero<T>();
+    if (j < 0) return x;
+    if (c.plasma) {
+        if (j < c.g.nr) x.jr = c.x.L(s.jr, c.m, j);
+        x.jt = c.x.L(s.jt, c.m, j);
+    }
+    if (s.jra && j < c.g.nr) x.jra = c.x.L(s.jra, c.m, j);
+    if (s.jta) x.jta = c.x.L(s.jta, c.m, j);
+    return x;
+}
+
 // column i+1 of both window slots from the next lane (every lane active)
 template <typename T>
 __device__ __forceinline__ EmB<T> em_bvals(const Ctx<T>& c, const EmWin<T>& W) {
@@ -274,13 +295,14 @@ __device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, c
     return W.bx0[0] + h * fx;
 }
 
-// plasma j_theta at (x_{i+1/2}, r_j, t^{n+1/2}) from the window slot s, writing
-// the new plasma j_theta at the integer column i
+// plasma j_theta at (x_{i+1/2}, r_j, t^{n+1/2}) from the window slot s and the
+// old plasma j_theta at columns i (jti) and i+1 (jti1), writing the new plasma
+// j_theta at the integer column i
 template <typename T>
 __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, const EmB<T>& B,
-                                           int row, int slot, bool write) {
-    cx<T> ja = c.x.L(s.jt, c.m, row) + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
-    cx<T> jb = c.x.R(s.jt, c.m, row) + c.wp2h * (T(0.5) * (B.tpb[slot] + B.tmb[slot]));
+                                           int row, int slot, bool write, cx<T> jti, cx<T> jti1) {
+    cx<T> ja = jti + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
+    cx<T> jb = jti1 + c.wp2h * (T(0.5) * (B.tpb[slot] + B.tmb[slot]));
     if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
     if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
     if (c.x.i1 < 0) jb = zero<T>();
@@ -291,7 +313,7 @@ __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, co
 // (and the exterior ghost at j = nr-1), T_r(K=j), T_theta(J=j)
 template <typename T>
 __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, const EmB<T>& B, int j,
-                                        int r0, int r1, const RowInv<T>& ri) {
+                                        int r0, int r1, const RowInv<T>& ri, const EmRowX<T>& X) {
     const Geo& g = c.g;
     const int m = c.m;
     const T h = c.h, dr = c.dr;
@@ -323,7 +345,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
             cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (B.rpb[0] + B.rmb[0]));
             rx = rx - (T(0.5) * ri.irJ1) * (ea + imul(T(m), ra));
             cx<T> jt = zero<T>();
-            if (c.plasma) jt = em_jt_avg(c, s, W, B, N, 1, false);
+            if (c.plasma) jt = em_jt_avg(c, s, W, B, N, 1, false, c.x.L(s.jt, m, N), c.x.R(s.jt, m, N));
             if (s.jta) jt = jt + c.x.L(s.jta, m, N);
             rx = rx - T(0.5) * jt;
             gh = W.bx0[0] + kap * (W.bx0[1] - W.bx1[1]) + cR * rx;
@@ -335,18 +357,19 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     if (j < g.nr) {
         cx<T> sp = zero<T>(), sm = zero<T>();
         cx<T> jra = zero<T>();
+        const cx<T> jr1 = c.plasma ? c.x.Rn(X.jr) : zero<T>();   // uniform control flow here
         if (c.plasma) {
-            jra = c.x.L(s.jr, m, j) + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
+            jra = X.jr + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
             if (own_row && wI) sto(s.ojr, eoff<T>(g, m, j, ocI), jra);
         }
         if (c.live) {
             cx<T> jr = zero<T>();
             if (c.plasma) {
-                cx<T> jrb = c.x.R(s.jr, m, j) + c.wp2h * (T(0.5) * (B.rpb[0] + B.rmb[0]));
+                cx<T> jrb = jr1 + c.wp2h * (T(0.5) * (B.rpb[0] + B.rmb[0]));
                 if (c.x.i1 < 0) jrb = zero<T>();
                 jr = T(0.5) * (jra + jrb);
             }
-            if (s.jra) jr = jr + c.x.L(s.jra, m, j);
+            if (s.jra) jr = jr + X.jra;
             cx<T> gr = -imul(T(m) * ri.irK, W.bx1[1]) - jr;
             cx<T> pr = c.inv_dr * (W.ex1[2] - W.ex1[1]);
             sp = h * (gr + pr);
@@ -368,8 +391,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     {
         const bool zrow = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
         cx<T> jt = zero<T>();
-        if (c.plasma) jt = em_jt_avg(c, s, W, B, j, 0, own_row);
-        if (s.jta && c.live) jt = jt + c.x.L(s.jta, m, j);
+        const cx<T> jt1 = c.plasma ? c.x.Rn(X.jt) : zero<T>();   // uniform control flow here
+        if (c.plasma) jt = em_jt_avg(c, s, W, B, j, 0, own_row, X.jt, jt1);
+        if (s.jta && c.live) jt = jt + X.jta;
         cx<T> sp = zero<T>(), sm = zero<T>();
         if (c.live && !zrow) {
             cx<T> gt, pt;
@@ -519,18 +543,20 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
     W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
     phw[0] = phw[1] = phw[2] = zero<T>();
-    if (jstart >= 0) {
-        em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);   // row jstart into slot 1
-        phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
-        if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
-    }
-
     // phi on half row k (the exterior ghost on row nr with the open boundary)
     auto phi_row = [&](int k) {
         if (k < g.nr) return c.x.L(a.phi, m, k);
         if (k == g.nr && g.open_r) return c.x.L(a.phi, m, g.nr);
         return zero<T>();
     };
+    if (jstart >= 0) {
+        em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);   // row jstart into slot 1
+        phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
+        if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
+    }
+    // FP64 issues the axion transport loads of row j with the row's other
+    // loads; FP32 loads them where they are used, to keep four waves per SIMD
+    constexpr bool HOIST = sizeof(T) == 8;
     // rows [r0, r1) are owned; the last iteration is r1 - 1 except for the
     // chunk holding the exterior ghost row, which ends on row nr
     const int jend = r1 == g.nr + 1 ? g.nr : r1 - 1;
@@ -540,10 +566,16 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         phw[0] = phw[1]; phw[1] = phw[2];
         phw[2] = phi_row(j + 1);
         em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
+        const EmRowX<T> X = em_fetch_x(c, s, j);
+        cx<T> tap_a = zero<T>(), tam_a = zero<T>();
+        if (HOIST && j >= 0 && j < g.nr) {
+            tap_a = c.x.L(a.tap, m, j);
+            tam_a = c.x.L(a.tam, m, j);
+        }
         const EmB<T> B = em_bvals(c, W);
         const cx<T> ex1_j = W.ex1[1];
         const RowInv<T> ri = row_inv(c, j);
-        em_step(c, s, W, B, j, r0, r1, ri);
+        em_step(c, s, W, B, j, r0, r1, ri, X);
         if (j < 0) continue;
         const bool own_row = j >= r0 && j < r1;
         if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
@@ -593,8 +625,11 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             if (c.live)
                 ga = (c.inv_dr * c.inv_dr) * (up - T(2) * p + dn) + (c.inv_2dr * ri.irK) * (up - dn)
                      - (T(m * m) * ri.irK * ri.irK + T(a.ma2)) * p + T(a.s_phi) * Sa;
-            cx<T> tap_a = c.x.L(a.tap, m, j);
-            cx<T> tam_a = c.x.L(a.tam, m, j), tam_b = c.x.Rn(tam_a);   // uniform control flow here
+            if (!HOIST) {
+                tap_a = c.x.L(a.tap, m, j);
+                tam_a = c.x.L(a.tam, m, j);
+            }
+            const cx<T> tam_b = c.x.Rn(tam_a);   // uniform control flow here
             cx<T> nap_b = (c.x.i1 >= 0) ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
             cx<T> nam_a = tam_b + h * ga;                                  // T_a^- at column i
             cx<T> l = shfl_up1(nap_b), r = shfl_dn1(nam_a);
@@ -701,8 +736,9 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
         em_rotate(W);
         em_take(c, W, pf, j + 1, g.nr);
         if (j < jend) pf = em_fetch(c, s, j + 2);   // next row's loads overlap this row's work
+        const EmRowX<T> X = em_fetch_x(c, s, j);
         const EmB<T> B = em_bvals(c, W);
-        em_step(c, s, W, B, j, r0, r1, row_inv(c, j));
+        em_step(c, s, W, B, j, r0, r1, row_inv(c, j), X);
         if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
     }
     if (a.window && c.owner && c.i == g.nx - 1) {
