@@ -103,14 +103,18 @@ def adjoint_ratio(dtype, steps, ckpt):
     f.set_option(qds.OPT_TUNE, 1)
     f.step(10)                      # the forward's autotuner, then warm
     s.set_option(qds.OPT_TUNE, 1)
-    s.backward(20, 10)              # tunes on its checkpoint pass; warms the adjoint
+    # the caller-owned checkpoint pool and lambda buffer are allocated once,
+    # as a caller repeating the gradient would keep them
+    pool = torch.empty(s.backward_pool_bytes(steps, ckpt), dtype=torch.uint8, device=s.device)
+    lam = torch.empty(s.nbytes, dtype=torch.uint8, device=s.device)
+    s.backward(20, 10, pool=pool, out=lam)    # tunes on its checkpoint pass; warms the adjoint
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     f.step(steps)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     t0 = time.perf_counter()
-    L, lam, _ = s.backward(steps, ckpt)
+    L, lam, _ = s.backward(steps, ckpt, pool=pool, out=lam)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     return {"workload": wl.name, "steps": steps, "ckpt_every": ckpt, "dtype": dtype, "fwd_s": t_fwd,

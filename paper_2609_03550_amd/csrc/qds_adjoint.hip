@@ -9,6 +9,7 @@
 // later stages that read it, so the stages run in reverse order.  Inputs the
 // forward step reads from several threads receive atomic adds.
 #include "qds_stage_ops.hpp"
+#include "qds_current_rows.hpp"
 
 namespace qds {
 namespace adj {
@@ -980,6 +981,393 @@ __global__ void __launch_bounds__(256) k_axion_current_bar(AxBar<T> a) {
     if (a.dLds) block_sum_add(dsj, a.dLds + 1);
 }
 
+
+// ---- adjoint of the marched axion current (qds_current.hip)
+//
+// Work layout of the forward march: a workgroup is M waves (one per mode) over
+// a strip of 64 cells and a chunk of cell rows; lanes 1..62 own their column.
+// For each cell row j a wave recomputes its mode's factors from the row window
+// (qds_current_rows.hpp), exchanges the factors and its j_a adjoints with the
+// other modes through LDS, forms the adjoints of its own mode's factors (the
+// transpose of C_m) and transposes the factor expressions into adjoints of the
+// window quantities.  Those of column i+1 go to the next lane by a DPP shift.
+// After row j the K row j-1 and the J row j have all their contributions and
+// are transposed into the planes: rows inside the chunk with plain accesses
+// (a store for the old-level planes, which hold zero before this kernel; a
+// read-add-write for the new-level planes), the rows the chunk shares with its
+// neighbours with atomic adds.
+namespace curb {
+
+using cur::FacC;
+using cur::JRow;
+using cur::KRow;
+using cur::NbR;
+using cur::NbT;
+using cur::NbX;
+constexpr int WAVE = cur::WAVE;
+constexpr int OWN = 62;
+
+template <typename T>
+__device__ __forceinline__ void prev_add(cx<T>& acc, cx<T> v) {
+    acc = acc + prev_lane(v);
+}
+
+// Ab, Bb of the own mode k of the adjoint of out_m += sign C_m{A, B} (all m),
+// given Ob (the adjoint of out): the k-th entries of conv_bar
+template <typename T, int M>
+__device__ __forceinline__ void conv_bar_one(const cx<T>* A, const cx<T>* B, const cx<T>* Ob, T sign, int k,
+                                             cx<T>& Ab, cx<T>& Bb) {
+    {
+        const cx<T> o = sign * Ob[0];
+        if (k == 0) {
+            Ab = Ab + cmul(B[0], o);
+            Bb = Bb + cmul(A[0], o);
+        } else {
+#pragma unroll
+            for (int q = 1; q < M; ++q)
+                if (q == k) {
+                    Ab = Ab + (T(0.5) * o.re) * B[q];
+                    Bb = Bb + (T(0.5) * o.re) * A[q];
+                }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+        const cx<T> o = (sign * T(0.5)) * Ob[m];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            // Ab[k]: terms A_k B_l (k + l = m), A_k conj(B_l) (k - l = m), conj(A_k) B_l (l - k = m)
+            if (k + l == m) Ab = Ab + cmul(B[l], o);
+            if (k - l == m) Ab = Ab + B[l] * o;
+            if (l - k == m) Ab = Ab + mulc(B[l], o);
+            // Bb[k]: terms A_l B_k (l + k = m), A_l conj(B_k) (l - k = m), conj(A_l) B_k (k - l = m)
+            if (l + k == m) Bb = Bb + cmul(A[l], o);
+            if (l - k == m) Bb = Bb + mulc(A[l], o);
+            if (k - l == m) Bb = Bb + A[l] * o;
+        }
+    }
+}
+
+// transposes of cur::fac_x, fac_r, fac_t: factor adjoints b[6] into the
+// adjoints of the window (kpb: K row j-1, kcb: K row j, jcb: J row j, jnb: J
+// row j+1, n: the column-i+1 values)
+template <typename T>
+__device__ __forceinline__ void fac_x_bar(const FacC<T>& c, int j, const cx<T>* b, KRow<T>& kpb, KRow<T>& kcb,
+                                          JRow<T>& jcb, NbX<T>& n) {
+    const bool ax = j == 0;
+    const int m = c.m;
+    const T par = c.par;
+    {
+        const cx<T> q = T(0.5) * b[0];
+        kcb.bxn = kcb.bxn + q;
+        if (ax) kcb.bxn = kcb.bxn + par * q;
+        else kpb.bxn = kpb.bxn + q;
+    }
+    {
+        const cx<T> q = T(0.25) * b[1];
+        kcb.dt0 = kcb.dt0 + q;
+        n.dt1 = n.dt1 + q;
+        if (ax) {
+            kcb.dt0 = kcb.dt0 + par * q;
+            n.dt1 = n.dt1 + par * q;
+        } else {
+            kpb.dt0 = kpb.dt0 + q;
+            n.dtl1 = n.dtl1 + q;
+        }
+    }
+    {
+        const cx<T> q = T(0.25) * b[2];
+        kcb.er0 = kcb.er0 + q;
+        n.er1 = n.er1 + q;
+        if (ax) {
+            if (m == 1) {
+                jcb.et0 = jcb.et0 + imul(-T(2), q);
+                n.et1 = n.et1 + imul(-T(2), q);
+            }
+            kcb.er0 = kcb.er0 - q;
+            n.er1 = n.er1 - q;
+        } else {
+            kpb.er0 = kpb.er0 + q;
+            n.erl1 = n.erl1 + q;
+        }
+    }
+    if (ax) {
+        if (m == 1) kcb.ph0 = kcb.ph0 + imul(T(2) * c.inv_dr, b[3]);
+    } else {
+        const cx<T> t = T(0.5) * imul(T(m) * c.inv_dr / T(j), b[3]);
+        kcb.ph0 = kcb.ph0 + t;
+        kpb.ph0 = kpb.ph0 + t;
+    }
+    {
+        const cx<T> q = T(0.5) * b[4];
+        jcb.et0 = jcb.et0 + q;
+        n.et1 = n.et1 + q;
+    }
+    {
+        const cx<T> s = c.inv_dr * b[5];
+        kcb.ph0 = kcb.ph0 + s;
+        if (ax) kcb.ph0 = kcb.ph0 - par * s;
+        else kpb.ph0 = kpb.ph0 - s;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void fac_r_bar(const FacC<T>& c, int j, const cx<T>* b, KRow<T>& kcb, JRow<T>& jcb,
+                                          JRow<T>& jnb, NbR<T>& n) {
+    {
+        const cx<T> q = T(0.125) * b[0];
+        jcb.Qp = jcb.Qp + q; n.Qp1 = n.Qp1 + q; jnb.Qp = jnb.Qp + q; n.Qpn1 = n.Qpn1 + q;
+    }
+    {
+        const cx<T> q = T(0.5) * b[1];
+        kcb.up = kcb.up + q; n.up1 = n.up1 + q;
+    }
+    {
+        const cx<T> q = T(0.125) * b[2];
+        jcb.Qm = jcb.Qm + q; n.Qm1 = n.Qm1 + q; jnb.Qm = jnb.Qm + q; n.Qmn1 = n.Qmn1 + q;
+    }
+    {
+        const cx<T> q = T(0.5) * b[3];
+        kcb.wm = kcb.wm + q; n.wm1 = n.wm1 + q;
+    }
+    {
+        const cx<T> q = T(0.5) * b[4];
+        jcb.ex = jcb.ex + q; jnb.ex = jnb.ex + q;
+    }
+    const T irk = T(1) / ((T(j) + T(0.5)) * c.dr);
+    kcb.phm = kcb.phm + imul(T(c.m) * irk, b[5]);
+}
+template <typename T>
+__device__ __forceinline__ void fac_t_bar(const FacC<T>& c, int j, const cx<T>* b, KRow<T>& kpb, KRow<T>& kcb,
+                                          JRow<T>& jcb, NbT<T>& n) {
+    const bool ax = j == 0;
+    const int m = c.m;
+    const T par = c.par;
+    {
+        // f0 = fP / 2 with fP = (gP0 + kc.P + gP1 + P1) / 4
+        const cx<T> q = T(0.125) * b[0];
+        kcb.P = kcb.P + q; n.P1 = n.P1 + q;
+        if (ax) {
+            if (m == 1) {
+                jcb.Qm = jcb.Qm + imul(-T(2), q);
+                n.Qm1 = n.Qm1 + imul(-T(2), q);
+            }
+            kcb.P = kcb.P - q; n.P1 = n.P1 - q;
+        } else {
+            kpb.P = kpb.P + q; n.Pl1 = n.Pl1 + q;
+        }
+    }
+    {
+        // f4 = -fN / 2
+        const cx<T> q = T(-0.125) * b[4];
+        kcb.N = kcb.N + q; n.N1 = n.N1 + q;
+        if (ax) {
+            if (m == 1) {
+                jcb.Qp = jcb.Qp + imul(-T(2), q);
+                n.Qp1 = n.Qp1 + imul(-T(2), q);
+            }
+            kcb.N = kcb.N - q; n.N1 = n.N1 - q;
+        } else {
+            kpb.N = kpb.N + q; n.Nl1 = n.Nl1 + q;
+        }
+    }
+    {
+        const cx<T> q = T(0.25) * b[1];
+        kcb.wm = kcb.wm + q; n.wm1 = n.wm1 + q;
+        if (ax) {
+            kcb.wm = kcb.wm + par * q; n.wm1 = n.wm1 + par * q;
+        } else {
+            kpb.wm = kpb.wm + q; n.wml1 = n.wml1 + q;
+        }
+    }
+    jcb.ex = jcb.ex + b[2];
+    {
+        const cx<T> s = c.inv_dr * b[3];
+        kcb.phm = kcb.phm + s;
+        if (ax) kcb.phm = kcb.phm - par * s;
+        else kpb.phm = kpb.phm - s;
+    }
+    {
+        const cx<T> q = T(0.25) * b[5];
+        kcb.up = kcb.up + q; n.up1 = n.up1 + q;
+        if (ax) {
+            kcb.up = kcb.up + par * q; n.up1 = n.up1 + par * q;
+        } else {
+            kpb.up = kpb.up + q; n.upl1 = n.upl1 + q;
+        }
+    }
+}
+
+// p[o] += v: plain (read-add-write, or a store where the plane holds zero) or atomic
+template <typename T>
+__device__ __forceinline__ void put_new(cx<T>* p, uint32_t o, cx<T> v, bool atomic) {
+    if (atomic) cadd((cx<T>*)((char*)p + o), v);
+    else cur::sto(p, o, cur::ldo(p, o) + v);
+}
+template <typename T>
+__device__ __forceinline__ void put_old(cx<T>* p, uint32_t o, cx<T> v, bool atomic) {
+    if (atomic) cadd((cx<T>*)((char*)p + o), v);
+    else cur::sto(p, o, v);
+}
+
+// transposes of cur::load_k / load_j into the plane adjoints
+template <typename T>
+__device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRow<T>& b, bool atomic) {
+    const cx<T> d = T(0.25) * b.dt0;
+    put_old(a.A0b.bx, o, T(0.5) * b.bxn, atomic);
+    put_old(a.tapAb, o, d, atomic);
+    put_old(a.tamAb, o, d, atomic);
+    put_old(a.A0b.trp, o, T(0.5) * (b.er0 + b.P), atomic);
+    put_old(a.A0b.trm, o, T(0.5) * (b.er0 + b.N), atomic);
+    put_old(a.phiAb, o, b.ph0 + T(0.5) * b.phm, atomic);
+    put_new(a.B0b.bx, o, T(0.5) * b.bxn, atomic);
+    put_new(a.tapBb, o, d + b.up, atomic);
+    put_new(a.tamBb, o, d + b.wm, atomic);
+    put_new(a.B0b.trp, o, T(0.5) * b.P, atomic);
+    put_new(a.B0b.trm, o, T(0.5) * b.N, atomic);
+    put_new(a.phiBb, o, T(0.5) * b.phm, atomic);
+}
+template <typename T>
+__device__ __forceinline__ void flush_j(const AxBar<T>& a, uint32_t o, const JRow<T>& b, bool atomic) {
+    put_old(a.A0b.ttp, o, T(0.5) * (b.et0 + b.Qp), atomic);
+    put_old(a.A0b.ttm, o, T(0.5) * (b.et0 + b.Qm), atomic);
+    put_new(a.B0b.ttp, o, T(0.5) * b.Qp, atomic);
+    put_new(a.B0b.ttm, o, T(0.5) * b.Qm, atomic);
+    put_new(a.B0b.ex, o, b.ex, atomic);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int rows) {
+    const AxionArgs<T>& f = a.f;
+    const Geo& g = f.g;
+    const int m = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int chunks = (g.nr + rows - 1) / rows;
+    const int strip = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+    const int raw = strip * OWN - 1 + lane;
+    // halo lanes wrap with periodic x and are clamped otherwise
+    const int i = g.per ? ((raw % g.nx) + g.nx) % g.nx : min(max(raw, 0), g.nx - 1);
+    const bool owner = lane >= 1 && lane <= OWN && raw < g.nx;
+    const bool has1 = g.per || i + 1 < g.nx;
+    // cells computed here: inside the domain, not the dead last cell, and for a
+    // clamped halo lane not a copy of the first cell
+    const bool live = (g.per || i < g.nx - 1) && (g.per || raw >= 0);
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr, r0 + rows);
+    const T dr = T(g.dr);
+    const FacC<T> fc{m, m == 0 ? T(1) : T(-1), dr, T(1) / dr, f.bx0, f.br1, f.bt1};
+    const T sj = T(f.s_j);
+    const cx<T> zc = zero<T>();
+
+    // two exchange buffers used alternately by the three phases of a row, so
+    // one barrier per phase keeps writers behind the last readers
+    __shared__ cx<T> sm[2][7][M][WAVE];
+    int ph = 0;
+    double dsj = 0.0;
+
+    // one phase: exchange the own factors f and own j_a adjoint jb, then the
+    // adjoints fb of the own factors (and the own-mode output for dL/ds_j,
+    // counted once per cell: on the lane that owns its column)
+    auto phase = [&](const cx<T>* fo, cx<T> jbo, bool calc, cx<T>* fb) {
+        if (calc) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sm[ph][q][m][lane] = fo[q];
+            sm[ph][6][m][lane] = jbo;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 6; ++q) fb[q] = zc;
+        if (calc) {
+            cx<T> Ob[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) Ob[k] = sj * sm[ph][6][k][lane];
+            cx<T> out = zc;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                cx<T> A[M], B[M];
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    A[k] = sm[ph][2 * p][k][lane];
+                    B[k] = sm[ph][2 * p + 1][k][lane];
+                }
+                const T sgn = p == 1 ? T(-1) : T(1);
+                conv_bar_one<T, M>(A, B, Ob, sgn, m, fb[2 * p], fb[2 * p + 1]);
+                if (a.dLds) conv_one<T, M>(A, B, m, out, sgn);
+            }
+            if (owner) dsj += double(jbo.re) * double(out.re) + double(jbo.im) * double(out.im);
+        }
+        ph ^= 1;
+    };
+
+    KRow<T> kp = r0 >= 1 ? cur::load_k(f, cur::eoff<T>(g, m, r0 - 1, i)) : cur::zero_k<T>();
+    JRow<T> jc = cur::load_j(f, cur::eoff<T>(g, m, r0, i));
+    KRow<T> kpb = cur::zero_k<T>();   // adjoint of K row j-1 (its share from row j-1)
+    JRow<T> jcb = cur::zero_j<T>();   // adjoint of J row j (its share from row j-1)
+    for (int j = r0; j < r1; ++j) {
+        const uint32_t o = cur::eoff<T>(g, m, j, i);
+        const KRow<T> kc = cur::load_k(f, o);
+        const JRow<T> jn = cur::load_j(f, cur::eoff<T>(g, m, j + 1, i));
+        const cx<T> jxb = cur::ldo(a.jaxb, o), jrb = cur::ldo(a.jarb, o), jtb = cur::ldo(a.jatb, o);
+        KRow<T> kcb = cur::zero_k<T>();
+        JRow<T> jnb = cur::zero_j<T>();
+        {
+            // j_a,x
+            const NbX<T> nx = cur::nb_x(kp, kc, jc, has1);
+            cx<T> fo[6], fb[6];
+            if (live) cur::fac_x(fc, j, kp, kc, jc, nx, fo);
+            phase(fo, jxb, live, fb);
+            NbX<T> nb{zc, zc, zc, zc, zc};
+            if (live) fac_x_bar(fc, j, fb, kpb, kcb, jcb, nb);
+            prev_add(kcb.dt0, nb.dt1); prev_add(kcb.er0, nb.er1); prev_add(jcb.et0, nb.et1);
+            prev_add(kpb.dt0, nb.dtl1); prev_add(kpb.er0, nb.erl1);
+        }
+        {
+            // j_a,r
+            const NbR<T> nr = cur::nb_r(kc, jc, jn, has1);
+            cx<T> fo[6], fb[6];
+            if (live) cur::fac_r(fc, j, kc, jc, jn, nr, fo);
+            phase(fo, jrb, live, fb);
+            NbR<T> nb{zc, zc, zc, zc, zc, zc};
+            if (live) fac_r_bar(fc, j, fb, kcb, jcb, jnb, nb);
+            prev_add(jcb.Qp, nb.Qp1); prev_add(jcb.Qm, nb.Qm1); prev_add(jnb.Qp, nb.Qpn1);
+            prev_add(jnb.Qm, nb.Qmn1); prev_add(kcb.up, nb.up1); prev_add(kcb.wm, nb.wm1);
+        }
+        {
+            // j_a,theta
+            const NbT<T> nt = cur::nb_t(kp, kc, jc, has1);
+            cx<T> fo[6], fb[6];
+            if (live) cur::fac_t(fc, j, kp, kc, jc, nt, fo);
+            phase(fo, jtb, live, fb);
+            NbT<T> nb{zc, zc, zc, zc, zc, zc, zc, zc, zc, zc};
+            if (live) fac_t_bar(fc, j, fb, kpb, kcb, jcb, nb);
+            prev_add(kcb.P, nb.P1); prev_add(kcb.N, nb.N1); prev_add(kcb.up, nb.up1); prev_add(kcb.wm, nb.wm1);
+            prev_add(kpb.P, nb.Pl1); prev_add(kpb.N, nb.Nl1); prev_add(kpb.up, nb.upl1); prev_add(kpb.wm, nb.wml1);
+            prev_add(jcb.Qp, nb.Qp1); prev_add(jcb.Qm, nb.Qm1);
+        }
+        if (owner) {
+            // K row j-1 and J row j are complete, except for the rows shared with the chunk below
+            if (j >= 1) flush_k(a, cur::eoff<T>(g, m, j - 1, i), kpb, j == r0);
+            flush_j(a, o, jcb, j == r0 && r0 > 0);
+        }
+        kp = kc;
+        jc = jn;
+        kpb = kcb;
+        jcb = jnb;
+    }
+    if (owner) {
+        // K row r1-1 and J row r1: complete in the last chunk, shared otherwise
+        flush_k(a, cur::eoff<T>(g, m, r1 - 1, i), kpb, r1 != g.nr);
+        flush_j(a, cur::eoff<T>(g, m, r1, i), jcb, r1 != g.nr);
+    }
+    if (a.dLds) {
+        // one atomic per wave
+#pragma unroll
+        for (int s = WAVE / 2; s > 0; s >>= 1) dsj += __shfl_xor(dsj, s, WAVE);
+        if (lane == 0 && dsj != 0.0) atomicAdd(a.dLds + 1, dsj);
+    }
+}
+
+}  // namespace curb
+
 }  // namespace adj
 
 // ---------------------------------------------------------------------------
@@ -1008,12 +1396,27 @@ static adj::StageBar<T> stage_bar(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>*
     return a;
 }
 
+// cell rows per workgroup of the marched current adjoint
+constexpr int kCurBarRows = 8;
+
 template <typename T, int M>
 static void launch_axion_bar(adj::AxBar<T>& a, bool arem, hipStream_t s) {
     const Geo& g = a.f.g;
     dim3 blk(64, 4);
     dim3 grdK((g.nx + 63) / 64, (g.nr + 3) / 4);
-    if (arem) hipLaunchKernelGGL((adj::k_axion_current_bar<T, M>), grdK, blk, 0, s, a);
+    if (arem) {
+        // the march addresses a plane through 32-bit byte offsets
+        const size_t plane = size_t(g.M) * size_t(g.nr + 1) * size_t(g.ld) * sizeof(cx<T>);
+        if (plane < (size_t(1) << 32)) {
+            const int rows = kCurBarRows;
+            const int strips = (g.nx + adj::curb::OWN - 1) / adj::curb::OWN;
+            const int chunks = (g.nr + rows - 1) / rows;
+            hipLaunchKernelGGL((adj::curb::k_current_bar_march<T, M>), dim3(strips * chunks),
+                               dim3(adj::curb::WAVE * M), 0, s, a, rows);
+        } else {
+            hipLaunchKernelGGL((adj::k_axion_current_bar<T, M>), grdK, blk, 0, s, a);
+        }
+    }
     hipLaunchKernelGGL(adj::k_axion_phi_bar<T>, grdK, blk, 0, s, a);
     hipLaunchKernelGGL((adj::k_axion_ta_bar<T, M>), grdK, blk, 0, s, a);
 }

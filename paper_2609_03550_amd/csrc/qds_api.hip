@@ -264,13 +264,15 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     const size_t S = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
     const size_t P = c->plane_elems * c->elem_bytes;
     const size_t nck = size_t((N + C - 1) / C);
+    // pool layout: the adjoint state pair, the j_a adjoints and the reductions
+    // first, then the segment states and the checkpoints
     char* base = static_cast<char*>(pool);
-    char* ck = base;
-    char* seg = ck + nck * S;
-    char* adjX = seg + size_t(C + 1) * S;
+    char* adjX = base;
     char* adjY = adjX + S;
     char* jab = adjY + S;
     double* red = reinterpret_cast<double*>(jab + 3 * P);
+    char* seg = jab + 3 * P + 256;
+    char* ck = seg + size_t(C + 1) * S;
     auto at_seg = [&](int64_t k) { return static_cast<void*>(seg + size_t(k) * S); };
     hipError_t e = hipSuccess;
 #define QDS_TRY(x)                                                                        \

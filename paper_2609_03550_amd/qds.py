@@ -304,19 +304,35 @@ class Solver:
         return {k: v.to("cpu", torch.complex128) for k, v in out.items()}
 
     # -- adjoint ------------------------------------------------------------
+    def backward_pool_bytes(self, n_steps: int, ckpt_every: int) -> int:
+        """Bytes of the caller-owned work pool of ``backward(n_steps, ckpt_every)``."""
+        return int(lib().qds_backward_pool_bytes(self.h, n_steps, ckpt_every))
+
     def backward(self, n_steps: int, ckpt_every: int, loss_set: int = 1, loss_mode: int = 1,
-                 x_begin: Optional[int] = None, x_end: Optional[int] = None, stream=None):
+                 x_begin: Optional[int] = None, x_end: Optional[int] = None, stream=None,
+                 pool: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
         """Gradient of the loss (energy of mode ``loss_mode`` of set ``loss_set``
         over columns [x_begin, x_end) after ``n_steps``) with respect to the
         current state, by the library's adjoint with checkpoints every
         ``ckpt_every`` steps.  Returns (loss, lambda0 buffer, (dL/ds_phi, dL/ds_j));
-        the state itself is not advanced."""
+        the state itself is not advanced.  ``pool`` (a uint8 device tensor of at
+        least backward_pool_bytes bytes) and ``out`` (a state-sized uint8 device
+        tensor for lambda0) let a caller that repeats the call keep its memory;
+        by default both are allocated here."""
         wl = self.wl
         lo = Loss(loss_set, loss_mode, max(0, wl.nx - 256) if x_begin is None else x_begin,
                   wl.nx if x_end is None else x_end)
-        nbytes = int(lib().qds_backward_pool_bytes(self.h, n_steps, ckpt_every))
-        pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        lam = torch.zeros(self.nbytes, dtype=torch.uint8, device=self.device)
+        nbytes = self.backward_pool_bytes(n_steps, ckpt_every)
+        if pool is None:
+            pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif pool.dtype != torch.uint8 or pool.device != self.device or pool.numel() < nbytes or not pool.is_contiguous():
+            raise ValueError(f"pool must be a contiguous uint8 tensor of at least {nbytes} bytes on {self.device}")
+        if out is None:
+            lam = torch.zeros(self.nbytes, dtype=torch.uint8, device=self.device)
+        elif out.dtype != torch.uint8 or out.device != self.device or out.numel() != self.nbytes or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous uint8 tensor of {self.nbytes} bytes on {self.device}")
+        else:
+            lam = out
         dlds = (ctypes.c_double * 2)()
         loss = ctypes.c_double()
         cur = Current()

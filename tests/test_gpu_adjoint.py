@@ -86,6 +86,18 @@ def test_full_adjoint_matches_autograd(M):
     assert abs(dlds[1] / (2 * L) - 1) < 1e-9
 
 
+@pytest.mark.parametrize("x_bc,r_bc", [("open", "open"), ("periodic", "pec")])
+def test_full_adjoint_several_tiles(x_bc, r_bc):
+    """Three x strips and three radial chunks with ragged tails (the marched
+    current adjoint's shared chunk rows and strip edges)."""
+    wl = _full(150, 21, 3, x_bc=x_bc, r_bc=r_bc)
+    _, L, lam, dlds = _gpu(wl, 5, 2, 1, 1)
+    Lo, go = _oracle_grad(wl, 5, 1, 1)
+    assert L > 0 and abs(L / Lo - 1) < 1e-11
+    _compare_grad(lam, go, 1e-9)
+    assert abs(dlds[1] / (2 * L) - 1) < 1e-9
+
+
 @pytest.mark.parametrize("x_bc,r_bc", [("periodic", "pec"), ("open", "pec")])
 def test_full_adjoint_boundaries(x_bc, r_bc):
     wl = _full(36, 8, 2, x_bc=x_bc, r_bc=r_bc)
