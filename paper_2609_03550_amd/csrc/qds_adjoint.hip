@@ -1197,11 +1197,12 @@ __device__ __forceinline__ void fac_t_bar(const FacC<T>& c, int j, const cx<T>* 
     }
 }
 
-// p[o] += v: plain (read-add-write, or a store where the plane holds zero) or atomic
+// p[o] += v: plain (the old value was read ahead into old, or a store where the
+// plane holds zero) or atomic
 template <typename T>
-__device__ __forceinline__ void put_new(cx<T>* p, uint32_t o, cx<T> v, bool atomic) {
+__device__ __forceinline__ void put_new(cx<T>* p, uint32_t o, cx<T> old, cx<T> v, bool atomic) {
     if (atomic) cadd((cx<T>*)((char*)p + o), v);
-    else cur::sto(p, o, cur::ldo(p, o) + v);
+    else cur::sto(p, o, old + v);
 }
 template <typename T>
 __device__ __forceinline__ void put_old(cx<T>* p, uint32_t o, cx<T> v, bool atomic) {
@@ -1209,9 +1210,29 @@ __device__ __forceinline__ void put_old(cx<T>* p, uint32_t o, cx<T> v, bool atom
     else cur::sto(p, o, v);
 }
 
+// the new-level plane values a K row / J row flush adds to, read ahead
+template <typename T>
+struct OldK {
+    cx<T> bx, tap, tam, trp, trm, phi;
+};
+template <typename T>
+struct OldJ {
+    cx<T> ttp, ttm, ex;
+};
+template <typename T>
+__device__ __forceinline__ OldK<T> old_k(const AxBar<T>& a, uint32_t o) {
+    return OldK<T>{cur::ldo(a.B0b.bx, o),  cur::ldo(a.tapBb, o),   cur::ldo(a.tamBb, o),
+                   cur::ldo(a.B0b.trp, o), cur::ldo(a.B0b.trm, o), cur::ldo(a.phiBb, o)};
+}
+template <typename T>
+__device__ __forceinline__ OldJ<T> old_j(const AxBar<T>& a, uint32_t o) {
+    return OldJ<T>{cur::ldo(a.B0b.ttp, o), cur::ldo(a.B0b.ttm, o), cur::ldo(a.B0b.ex, o)};
+}
+
 // transposes of cur::load_k / load_j into the plane adjoints
 template <typename T>
-__device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRow<T>& b, bool atomic) {
+__device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRow<T>& b, const OldK<T>& q,
+                                        bool atomic) {
     const cx<T> d = T(0.25) * b.dt0;
     put_old(a.A0b.bx, o, T(0.5) * b.bxn, atomic);
     put_old(a.tapAb, o, d, atomic);
@@ -1219,20 +1240,21 @@ __device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRo
     put_old(a.A0b.trp, o, T(0.5) * (b.er0 + b.P), atomic);
     put_old(a.A0b.trm, o, T(0.5) * (b.er0 + b.N), atomic);
     put_old(a.phiAb, o, b.ph0 + T(0.5) * b.phm, atomic);
-    put_new(a.B0b.bx, o, T(0.5) * b.bxn, atomic);
-    put_new(a.tapBb, o, d + b.up, atomic);
-    put_new(a.tamBb, o, d + b.wm, atomic);
-    put_new(a.B0b.trp, o, T(0.5) * b.P, atomic);
-    put_new(a.B0b.trm, o, T(0.5) * b.N, atomic);
-    put_new(a.phiBb, o, T(0.5) * b.phm, atomic);
+    put_new(a.B0b.bx, o, q.bx, T(0.5) * b.bxn, atomic);
+    put_new(a.tapBb, o, q.tap, d + b.up, atomic);
+    put_new(a.tamBb, o, q.tam, d + b.wm, atomic);
+    put_new(a.B0b.trp, o, q.trp, T(0.5) * b.P, atomic);
+    put_new(a.B0b.trm, o, q.trm, T(0.5) * b.N, atomic);
+    put_new(a.phiBb, o, q.phi, T(0.5) * b.phm, atomic);
 }
 template <typename T>
-__device__ __forceinline__ void flush_j(const AxBar<T>& a, uint32_t o, const JRow<T>& b, bool atomic) {
+__device__ __forceinline__ void flush_j(const AxBar<T>& a, uint32_t o, const JRow<T>& b, const OldJ<T>& q,
+                                        bool atomic) {
     put_old(a.A0b.ttp, o, T(0.5) * (b.et0 + b.Qp), atomic);
     put_old(a.A0b.ttm, o, T(0.5) * (b.et0 + b.Qm), atomic);
-    put_new(a.B0b.ttp, o, T(0.5) * b.Qp, atomic);
-    put_new(a.B0b.ttm, o, T(0.5) * b.Qm, atomic);
-    put_new(a.B0b.ex, o, b.ex, atomic);
+    put_new(a.B0b.ttp, o, q.ttp, T(0.5) * b.Qp, atomic);
+    put_new(a.B0b.ttm, o, q.ttm, T(0.5) * b.Qm, atomic);
+    put_new(a.B0b.ex, o, q.ex, b.ex, atomic);
 }
 
 template <typename T, int M>
@@ -1307,6 +1329,11 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
         const KRow<T> kc = cur::load_k(f, o);
         const JRow<T> jn = cur::load_j(f, cur::eoff<T>(g, m, j + 1, i));
         const cx<T> jxb = cur::ldo(a.jaxb, o), jrb = cur::ldo(a.jarb, o), jtb = cur::ldo(a.jatb, o);
+        // the new-level values this row's flushes add to (K row j-1, J row j),
+        // issued after the row's inputs so that they arrive during the phases
+        const uint32_t ok = cur::eoff<T>(g, m, j >= 1 ? j - 1 : 0, i);
+        const OldK<T> qk = old_k(a, ok);
+        const OldJ<T> qj = old_j(a, o);
         KRow<T> kcb = cur::zero_k<T>();
         JRow<T> jnb = cur::zero_j<T>();
         {
@@ -1345,8 +1372,8 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
         }
         if (owner) {
             // K row j-1 and J row j are complete, except for the rows shared with the chunk below
-            if (j >= 1) flush_k(a, cur::eoff<T>(g, m, j - 1, i), kpb, j == r0);
-            flush_j(a, o, jcb, j == r0 && r0 > 0);
+            if (j >= 1) flush_k(a, ok, kpb, qk, j == r0);
+            flush_j(a, o, jcb, qj, j == r0 && r0 > 0);
         }
         kp = kc;
         jc = jn;
@@ -1355,8 +1382,9 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
     }
     if (owner) {
         // K row r1-1 and J row r1: complete in the last chunk, shared otherwise
-        flush_k(a, cur::eoff<T>(g, m, r1 - 1, i), kpb, r1 != g.nr);
-        flush_j(a, cur::eoff<T>(g, m, r1, i), jcb, r1 != g.nr);
+        const uint32_t ok = cur::eoff<T>(g, m, r1 - 1, i), oj = cur::eoff<T>(g, m, r1, i);
+        flush_k(a, ok, kpb, old_k(a, ok), r1 != g.nr);
+        flush_j(a, oj, jcb, old_j(a, oj), r1 != g.nr);
     }
     if (a.dLds) {
         // one atomic per wave
