@@ -1425,7 +1425,7 @@ static adj::StageBar<T> stage_bar(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>*
 }
 
 // cell rows per workgroup of the marched current adjoint
-constexpr int kCurBarRows = 8;
+constexpr int kCurBarRows = 4;
 
 template <typename T, int M>
 static void launch_axion_bar(adj::AxBar<T>& a, bool arem, hipStream_t s) {
