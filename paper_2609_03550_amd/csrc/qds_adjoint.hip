@@ -142,6 +142,54 @@ __device__ void bx_new_bar(const StageBar<T>& a, int m, int k, int i, cx<T> bb) 
     add_er(a.Ab, g, m, k, i + 1, T(0.5) * erav);
 }
 
+// ---- combining scatter: contributions to two planes over two rows and the
+// columns i, i+1 are collected in registers, and the column i+1 share is
+// handed to the next lane (which holds column i+1) by a DPP shift, so each
+// point receives one atomic add per row from a wave.  flush2x2 is called by
+// every lane of a wave (uniform control flow); lanes without work hold zeros.
+__device__ __forceinline__ double prev_lane(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float prev_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> prev_lane(cx<T> v) {
+    return cx<T>{prev_lane(v.re), prev_lane(v.im)};
+}
+
+// two planes, rows r0 and r0 + 1, columns i and i + 1
+template <typename T>
+struct Acc2x2 {
+    cx<T> p[2][2], q[2][2];
+    __device__ __forceinline__ Acc2x2() {
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) p[r][c] = q[r][c] = zero<T>();
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void flush2x2(const Geo& g, int m, int i, int lane, int r0, int rmax, cx<T>* P, cx<T>* Q,
+                                         const Acc2x2<T>& A) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int row = r0 + r;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            cx<T>* pl = w ? Q : P;
+            const cx<T> v0 = w ? A.q[r][0] : A.p[r][0];
+            const cx<T> v1 = w ? A.q[r][1] : A.p[r][1];
+            const cx<T> got = prev_lane(v1);                 // column i of this lane from lane - 1
+            const cx<T> own = lane > 0 ? v0 + got : v0;
+            if (row < 0 || row > rmax) continue;
+            if (i < g.nx) cadd(pl + g.at(m, row, i), own);
+            if (lane == 63 || (g.per && i == g.nx - 1)) addx(pl, g, m, row, i + 1, v1);
+        }
+    }
+}
+
 // ---- adjoint of k_ghost_bth
 template <typename T>
 __global__ void __launch_bounds__(256) k_ghost_bth_bar(StageBar<T> a) {
@@ -223,105 +271,163 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
 }
 
 // ---- adjoint of k_longitudinal
+//
+// One thread per point (i, j), one wave per row j.  The points' own planes
+// (E_x, B_x, the currents) have this thread as their only writer here and take
+// a plain read-add-write; the transverse planes collect the 2 x 2 stencils of
+// B_theta / E_r (rows j-1, j) and B_r / E_theta (rows j, j+1) in registers and
+// leave through the combining scatter.  The exterior ghost row's B_x adjoint
+// writes to neighbouring points and runs afterwards in k_longitudinal_ghost_bar.
+template <typename T>
+__device__ __forceinline__ void rmw(cx<T>* p, cx<T> v) {
+    st(p, ld(p) + v);
+}
 template <typename T>
 __global__ void __launch_bounds__(256) k_longitudinal_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.nx || j > g.nr) return;
+    const int lane = threadIdx.x;           // blockDim.x is one wave: a wave shares j
+    if (j > g.nr) return;                   // uniform over the wave
+    const bool in = i < g.nx;
     const T h = T(g.h), dr = T(g.dr);
-    const bool live = g.per || i < g.nx - 1;
+    const bool live = in && (g.per || i < g.nx - 1);
     const T wp2h = T(a.wp2 * g.h);
-    // adjoint of the total j_x at this (i, j) from the E_x update: kept in a
-    // register for the plasma part below (no read-back of an atomic target)
-    cx<T> jx_here[QDS_MAX_MODES];
-    for (int m = 0; m < g.M; ++m) jx_here[m] = zero<T>();
-    auto jx_bar = [&](int m, cx<T> v) {
-        jx_here[m] = jx_here[m] + v;
-        if (a.jx_addb) cadd(a.jx_addb + g.at(m, j, i), v);
-    };
+    const T half = T(0.5);
     for (int m = 0; m < g.M; ++m) {
         const size_t e = g.at(m, j, i);
-        // ---- E_x
-        cx<T> eb = ld(a.Bb.ex + e);
-        if (!(!live || (!g.open_r && j == g.nr))) {
-            if (j == 0) {
-                if (m == 0) {
-                    cadd(a.Ab.ex + e, eb);
-                    cx<T> gx = h * eb;
-                    cx<T> b = (T(4) / dr) * gx;
-                    add_bth(a.Ab, g, 0, 0, i, T(0.5) * b);
-                    add_bth(a.Ab, g, 0, 0, i + 1, T(0.5) * b);
-                    jx_bar(0, -gx);
-                }
-            } else {
-                const T rj = T(j) * dr;
-                cadd(a.Ab.ex + e, eb);
-                cx<T> gx = h * eb;
-                cx<T> bavg = (T(1) / rj) * gx;
-                cx<T> db = gx;
-                cx<T> brav = imul_c(T(m) / rj, gx);
-                jx_bar(m, -gx);
-                cx<T> lo = T(0.25) * bavg - (T(1) / (T(2) * dr)) * db;
-                cx<T> hi = T(0.25) * bavg + (T(1) / (T(2) * dr)) * db;
-                add_bth(a.Ab, g, m, j - 1, i, lo);
-                add_bth(a.Ab, g, m, j - 1, i + 1, lo);
-                add_bth(a.Ab, g, m, j, i, hi);
-                add_bth(a.Ab, g, m, j, i + 1, hi);
-                add_brr(a.Ab, g, m, j, i, T(0.5) * brav);
-                add_brr(a.Ab, g, m, j, i + 1, T(0.5) * brav);
+        Acc2x2<T> R;    // T_r^+ (p) and T_r^- (q) on K rows j-1 (0), j (1); columns i, i+1
+        Acc2x2<T> Q;    // T_theta^+ (p) and T_theta^- (q) on J rows j (0), j+1 (1)
+        // B_theta / E_r into K row r (the exterior ghost row holds B_theta in T_r^+)
+        auto bth = [&](int r, int c, cx<T> v) {
+            if (j - 1 + r == g.nr) {
+                R.p[r][c] = R.p[r][c] + v;
+                return;
             }
-        }
-        // ---- B_x and the exterior ghost row
-        if (j < g.nr) {
-            if (live) bx_new_bar(a, m, j, i, ld(a.Bb.bx + e));
-        } else if (g.open_r && live) {
-            const int N = g.nr;
-            const T rN = T(N) * dr;
-            const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
-            cx<T> gh = ld(a.Bb.bx + e);
-            cadd(a.Ab.bx + g.at(m, N - 1, i), gh);
-            cadd(a.Ab.bx + g.at(m, N, i), kap * gh);
-            bx_new_bar(a, m, N - 1, i, -(kap * gh));
-            cx<T> rx = cR * gh;
-            add_brr(a.Ab, g, m, N, i + 1, (T(0.5) / h) * rx);
-            add_brr(a.Ab, g, m, N, i, -((T(0.5) / h) * rx));
-            cx<T> ea = -(T(1) / (T(2) * rN)) * rx;
-            add_eth(a.Ab, g, m, N, i, T(0.5) * ea);
-            add_eth(a.Ab, g, m, N, i + 1, T(0.5) * ea);
-            cx<T> ra = imul_c(-T(m) / (T(2) * rN), rx);
-            add_er(a.Ab, g, m, N - 1, i, T(0.5) * ra);
-            add_er(a.Ab, g, m, N - 1, i + 1, T(0.5) * ra);
-            cx<T> jt = -(T(0.5) * rx);
+            R.p[r][c] = R.p[r][c] + half * v;
+            R.q[r][c] = R.q[r][c] - half * v;
+        };
+        auto er = [&](int r, int c, cx<T> v) {
+            R.p[r][c] = R.p[r][c] + half * v;
+            R.q[r][c] = R.q[r][c] + half * v;
+        };
+        auto eth = [&](int r, int c, cx<T> v) {
+            Q.p[r][c] = Q.p[r][c] + half * v;
+            Q.q[r][c] = Q.q[r][c] + half * v;
+        };
+        auto brr = [&](int r, int c, cx<T> v) {
+            Q.p[r][c] = Q.p[r][c] + half * v;
+            Q.q[r][c] = Q.q[r][c] - half * v;
+        };
+        if (in) {
+            cx<T> exb = zero<T>();      // adjoint into A.ex at this point
+            cx<T> jxh = zero<T>();      // adjoint of the total j_x at this point
+            // ---- E_x
+            const cx<T> eb = ld(a.Bb.ex + e);
+            if (live && !(!g.open_r && j == g.nr)) {
+                if (j == 0) {
+                    if (m == 0) {
+                        exb = exb + eb;
+                        const cx<T> gx = h * eb;
+                        const cx<T> b = (T(4) / dr) * gx;
+                        bth(1, 0, half * b);
+                        bth(1, 1, half * b);
+                        jxh = jxh - gx;
+                    }
+                } else {
+                    const T rj = T(j) * dr;
+                    exb = exb + eb;
+                    const cx<T> gx = h * eb;
+                    const cx<T> bavg = (T(1) / rj) * gx;
+                    const cx<T> brav = imul_c(T(m) / rj, gx);
+                    jxh = jxh - gx;
+                    const cx<T> lo = T(0.25) * bavg - (T(1) / (T(2) * dr)) * gx;
+                    const cx<T> hi = T(0.25) * bavg + (T(1) / (T(2) * dr)) * gx;
+                    bth(0, 0, lo);
+                    bth(0, 1, lo);
+                    bth(1, 0, hi);
+                    bth(1, 1, hi);
+                    brr(0, 0, half * brav);
+                    brr(0, 1, half * brav);
+                }
+            }
+            if (a.jx_addb && (jxh.re != T(0) || jxh.im != T(0))) rmw(a.jx_addb + e, jxh);
+            // ---- B_x (the exterior ghost row: k_longitudinal_ghost_bar)
+            if (j < g.nr && live) {
+                const cx<T> bb = ld(a.Bb.bx + e);
+                const T rk = (T(j) + T(0.5)) * dr;
+                rmw(a.Ab.bx + e, bb);
+                const cx<T> fx = h * bb;
+                const cx<T> eavg = -(T(1) / rk) * fx;
+                const cx<T> erav = imul_c(-T(m) / rk, fx);
+                const cx<T> lo = T(0.25) * eavg + (T(1) / (T(2) * dr)) * fx;
+                const cx<T> hi = T(0.25) * eavg - (T(1) / (T(2) * dr)) * fx;
+                eth(0, 0, lo);
+                eth(0, 1, lo);
+                eth(1, 0, hi);
+                eth(1, 1, hi);
+                er(1, 0, half * erav);
+                er(1, 1, half * erav);
+            }
+            // ---- plasma response
             if (a.plasma) {
-                addx(a.Ab.jt, g, m, N, i, T(0.5) * jt);
-                add_eth(a.Ab, g, m, N, i, wp2h * (T(0.5) * jt));
-                if (g.per || i + 1 < g.nx) {
-                    addx(a.Ab.jt, g, m, N, i + 1, T(0.5) * jt);
-                    add_eth(a.Ab, g, m, N, i + 1, wp2h * (T(0.5) * jt));
+                const cx<T> jxb = ld(a.Bb.jx + e) + jxh;
+                rmw(a.Ab.jx + e, jxb);
+                exb = exb + wp2h * jxb;
+                if (j < g.nr) {
+                    const cx<T> jrb = ld(a.Bb.jr + e);
+                    rmw(a.Ab.jr + e, jrb);
+                    er(1, 0, wp2h * jrb);
+                }
+                if (!(!g.open_r && j == g.nr)) {
+                    const cx<T> jtb = ld(a.Bb.jt + e);
+                    rmw(a.Ab.jt + e, jtb);
+                    eth(0, 0, wp2h * jtb);
                 }
             }
-            if (a.jt_addb) cadd(a.jt_addb + g.at(m, N, i), jt);
+            if (exb.re != T(0) || exb.im != T(0)) rmw(a.Ab.ex + e, exb);
         }
+        flush2x2(g, m, i, lane, j - 1, g.nr, a.Ab.trp, a.Ab.trm, R);
+        flush2x2(g, m, i, lane, j, g.nr, a.Ab.ttp, a.Ab.ttm, Q);
     }
-    // ---- plasma response (read after this thread's own E_x adjoint added to B.jx)
-    if (a.plasma) {
-        for (int m = 0; m < g.M; ++m) {
-            const size_t e = g.at(m, j, i);
-            cx<T> jxb = ld(a.Bb.jx + e) + jx_here[m];
-            cadd(a.Ab.jx + e, jxb);
-            cadd(a.Ab.ex + e, wp2h * jxb);
-            if (j < g.nr) {
-                cx<T> jrb = ld(a.Bb.jr + e);
-                cadd(a.Ab.jr + e, jrb);
-                add_er(a.Ab, g, m, j, i, wp2h * jrb);
-            }
-            if (!(!g.open_r && j == g.nr)) {
-                cx<T> jtb = ld(a.Bb.jt + e);
-                cadd(a.Ab.jt + e, jtb);
-                add_eth(a.Ab, g, m, j, i, wp2h * jtb);
+}
+
+// ---- adjoint of the exterior ghost B_x of k_longitudinal (row nr), after k_longitudinal_bar
+template <typename T>
+__global__ void __launch_bounds__(256) k_longitudinal_ghost_bar(StageBar<T> a) {
+    const Geo& g = a.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nx || !g.open_r) return;
+    if (!(g.per || i < g.nx - 1)) return;
+    const int N = g.nr;
+    const T h = T(g.h), dr = T(g.dr);
+    const T rN = T(N) * dr;
+    const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
+    const T wp2h = T(a.wp2 * g.h);
+    for (int m = 0; m < g.M; ++m) {
+        cx<T> gh = ld(a.Bb.bx + g.at(m, N, i));
+        cadd(a.Ab.bx + g.at(m, N - 1, i), gh);
+        cadd(a.Ab.bx + g.at(m, N, i), kap * gh);
+        bx_new_bar(a, m, N - 1, i, -(kap * gh));
+        cx<T> rx = cR * gh;
+        add_brr(a.Ab, g, m, N, i + 1, (T(0.5) / h) * rx);
+        add_brr(a.Ab, g, m, N, i, -((T(0.5) / h) * rx));
+        cx<T> ea = -(T(1) / (T(2) * rN)) * rx;
+        add_eth(a.Ab, g, m, N, i, T(0.5) * ea);
+        add_eth(a.Ab, g, m, N, i + 1, T(0.5) * ea);
+        cx<T> ra = imul_c(-T(m) / (T(2) * rN), rx);
+        add_er(a.Ab, g, m, N - 1, i, T(0.5) * ra);
+        add_er(a.Ab, g, m, N - 1, i + 1, T(0.5) * ra);
+        cx<T> jt = -(T(0.5) * rx);
+        if (a.plasma) {
+            addx(a.Ab.jt, g, m, N, i, T(0.5) * jt);
+            add_eth(a.Ab, g, m, N, i, wp2h * (T(0.5) * jt));
+            if (g.per || i + 1 < g.nx) {
+                addx(a.Ab.jt, g, m, N, i + 1, T(0.5) * jt);
+                add_eth(a.Ab, g, m, N, i + 1, wp2h * (T(0.5) * jt));
             }
         }
+        if (a.jt_addb) cadd(a.jt_addb + g.at(m, N, i), jt);
     }
 }
 
@@ -697,54 +803,6 @@ __device__ void ja_factors_bar(const AxBar<T>& a, int m, int i, int j, const cx<
         cx<T> ph = imul_c(-T(m) / rk, fb[17]);
         cadd(a.phiAb + g.at(m, j, i), T(0.5) * ph);
         cadd(a.phiBb + g.at(m, j, i), T(0.5) * ph);
-    }
-}
-
-// ---- the same adjoint with the contributions combined before the atomics:
-// per destination plane and point in registers, and the column i+1 share
-// handed to the next lane (which holds column i+1) by a DPP shift, so each
-// point receives one atomic add per lane.  Called by every lane of a wave
-// (uniform control flow), with fb = 0 where the cell computes nothing.
-__device__ __forceinline__ double prev_lane(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float prev_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-template <typename T>
-__device__ __forceinline__ cx<T> prev_lane(cx<T> v) {
-    return cx<T>{prev_lane(v.re), prev_lane(v.im)};
-}
-
-// two planes, rows r0 and r0 + 1, columns i and i + 1
-template <typename T>
-struct Acc2x2 {
-    cx<T> p[2][2], q[2][2];
-    __device__ __forceinline__ Acc2x2() {
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c) p[r][c] = q[r][c] = zero<T>();
-    }
-};
-
-template <typename T>
-__device__ __forceinline__ void flush2x2(const Geo& g, int m, int i, int lane, int r0, int rmax, cx<T>* P, cx<T>* Q,
-                                         const Acc2x2<T>& A) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int row = r0 + r;
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            cx<T>* pl = w ? Q : P;
-            const cx<T> v0 = w ? A.q[r][0] : A.p[r][0];
-            const cx<T> v1 = w ? A.q[r][1] : A.p[r][1];
-            const cx<T> got = prev_lane(v1);                 // column i of this lane from lane - 1
-            const cx<T> own = lane > 0 ? v0 + got : v0;
-            if (row < 0 || row > rmax) continue;
-            if (i < g.nx) cadd(pl + g.at(m, row, i), own);
-            if (lane == 63 || (g.per && i == g.nx - 1)) addx(pl, g, m, row, i + 1, v1);
-        }
     }
 }
 
@@ -1461,6 +1519,7 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
         hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a1);
         hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a1);
         hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a1);
+        if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a1);
     }
     if (p.axion) {
         adj::AxBar<T> ax;
@@ -1482,6 +1541,7 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
     hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a0);
     hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a0);
     hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a0);
+    if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a0);
     return hipGetLastError();
 }
 
