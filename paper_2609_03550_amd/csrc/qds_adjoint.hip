@@ -223,49 +223,85 @@ __global__ void __launch_bounds__(256) k_ghost_bth_bar(StageBar<T> a) {
 }
 
 // ---- adjoint of k_transverse
+//
+// One thread per point (i, j), one wave per row j.  The shifted transport
+// adjoints have a single writer per point here and take a plain
+// read-add-write; the plasma j_r / j_theta adjoints (columns i, i+1) leave
+// through the combining scatter; the B_x and E_x adjoints (rows j-1..j+1)
+// take atomic adds.
+template <typename T>
+__device__ __forceinline__ void rmw(cx<T>* p, cx<T> v) {
+    st(p, ld(p) + v);
+}
+// one row of the combining scatter: v0 into column i, v1 into column i+1
+template <typename T>
+__device__ __forceinline__ void flush_row2(const Geo& g, int m, int i, int lane, int row, cx<T>* P, cx<T> v0,
+                                           cx<T> v1) {
+    const cx<T> got = prev_lane(v1);
+    const cx<T> own = lane > 0 ? v0 + got : v0;
+    if (i < g.nx) cadd(P + g.at(m, row, i), own);
+    if (lane == 63 || (g.per && i == g.nx - 1)) addx(P, g, m, row, i + 1, v1);
+}
 template <typename T>
 __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.nx || j > g.nr) return;
+    const int lane = threadIdx.x;           // blockDim.x is one wave: a wave shares j
+    if (j > g.nr) return;                   // uniform over the wave
+    const bool in = i < g.nx;
     const T h = T(g.h), dr = T(g.dr);
-    const bool live = g.per || i < g.nx - 1;
+    const bool live = in && (g.per || i < g.nx - 1);
     const int ir = g.per ? (i + 1) % g.nx : i + 1;
+    const bool hasr = in && ir < g.nx;      // column i+1 exists
+    const cx<T> zc = zero<T>();
     for (int m = 0; m < g.M; ++m) {
-        if (j < g.nr) {
-            cx<T> pb = (ir < g.nx) ? ld(a.Bb.trp + g.at(m, j, ir)) : zero<T>();
-            cx<T> mb = ld(a.Bb.trm + g.at(m, j, i));
-            if (ir < g.nx) addx(a.Ab.trp, g, m, j, i, pb);
-            addx(a.Ab.trm, g, m, j, i + 1, mb);
+        cx<T> jr0 = zc, jr1 = zc;           // plasma j_r adjoint, columns i, i+1 of row j
+        cx<T> jt0 = zc, jt1 = zc;           // plasma j_theta adjoint, columns i, i+1 of row j
+        if (in && j < g.nr) {
+            const cx<T> pb = hasr ? ld(a.Bb.trp + g.at(m, j, ir)) : zc;
+            const cx<T> mb = ld(a.Bb.trm + g.at(m, j, i));
+            if (hasr) {
+                rmw(a.Ab.trp + g.at(m, j, i), pb);
+                rmw(a.Ab.trm + g.at(m, j, ir), mb);
+            }
             if (live) {
                 const T rk = (T(j) + T(0.5)) * dr;
-                cx<T> gr = h * (pb + mb), pr = h * (pb - mb);
+                const cx<T> gr = h * (pb + mb), pr = h * (pb - mb);
                 cadd(a.Bb.bx + g.at(m, j, i), imul_c(-T(m) / rk, gr));
-                jr_total_bar(a, m, j, i, -gr);
+                if (a.plasma) jr0 = jr1 = T(-0.5) * gr;
+                if (a.jr_addb) rmw(a.jr_addb + g.at(m, j, i), -gr);
                 cadd(a.Bb.ex + g.at(m, j + 1, i), (T(1) / dr) * pr);
                 cadd(a.Bb.ex + g.at(m, j, i), -((T(1) / dr) * pr));
             }
         }
         const bool zero_row = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
-        if (zero_row) continue;
-        cx<T> pb = ld(a.Bb.ttp + g.at(m, j, i));
-        cx<T> mb = (ir < g.nx) ? ld(a.Bb.ttm + g.at(m, j, ir)) : zero<T>();
-        addx(a.Ab.ttp, g, m, j, i + 1, pb);
-        if (ir < g.nx) addx(a.Ab.ttm, g, m, j, i, mb);
-        if (live) {
-            cx<T> gt = h * (pb + mb), pt = h * (pb - mb);
-            if (j == 0) {
-                cadd(a.Bb.bx + g.at(1, 0, i), -((T(2) / dr) * gt));
-                jt_total_bar(a, 1, 0, i, -gt);
-                cadd(a.Bb.ex + g.at(1, 1, i), imul_c(T(1) / dr, pt));
-            } else {
-                const T rj = T(j) * dr;
-                cadd(a.Bb.bx + g.at(m, j, i), -((T(1) / dr) * gt));
-                cadd(a.Bb.bx + g.at(m, j - 1, i), (T(1) / dr) * gt);
-                jt_total_bar(a, m, j, i, -gt);
-                cadd(a.Bb.ex + g.at(m, j, i), imul_c(T(m) / rj, pt));
+        if (in && !zero_row) {
+            const cx<T> pb = ld(a.Bb.ttp + g.at(m, j, i));
+            const cx<T> mb = hasr ? ld(a.Bb.ttm + g.at(m, j, ir)) : zc;
+            if (hasr) {
+                rmw(a.Ab.ttp + g.at(m, j, ir), pb);
+                rmw(a.Ab.ttm + g.at(m, j, i), mb);
             }
+            if (live) {
+                const cx<T> gt = h * (pb + mb), pt = h * (pb - mb);
+                // (on the axis only mode 1 gets here: its axis relations)
+                if (j == 0) {
+                    cadd(a.Bb.bx + g.at(m, 0, i), -((T(2) / dr) * gt));
+                    cadd(a.Bb.ex + g.at(m, 1, i), imul_c(T(1) / dr, pt));
+                } else {
+                    const T rj = T(j) * dr;
+                    cadd(a.Bb.bx + g.at(m, j, i), -((T(1) / dr) * gt));
+                    cadd(a.Bb.bx + g.at(m, j - 1, i), (T(1) / dr) * gt);
+                    cadd(a.Bb.ex + g.at(m, j, i), imul_c(T(m) / rj, pt));
+                }
+                if (a.plasma) jt0 = jt1 = T(-0.5) * gt;
+                if (a.jt_addb) rmw(a.jt_addb + g.at(m, j, i), -gt);
+            }
+        }
+        if (a.plasma) {
+            if (j < g.nr) flush_row2(g, m, i, lane, j, a.Bb.jr, jr0, jr1);
+            flush_row2(g, m, i, lane, j, a.Bb.jt, jt0, jt1);
         }
     }
 }
@@ -278,10 +314,6 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
 // B_theta / E_r (rows j-1, j) and B_r / E_theta (rows j, j+1) in registers and
 // leave through the combining scatter.  The exterior ghost row's B_x adjoint
 // writes to neighbouring points and runs afterwards in k_longitudinal_ghost_bar.
-template <typename T>
-__device__ __forceinline__ void rmw(cx<T>* p, cx<T> v) {
-    st(p, ld(p) + v);
-}
 template <typename T>
 __global__ void __launch_bounds__(256) k_longitudinal_bar(StageBar<T> a) {
     const Geo& g = a.g;
