@@ -566,103 +566,122 @@ __device__ __forceinline__ void block_sum_add(double v, double* acc) {
 }
 
 // ---- adjoint of k_axion_ta (S_a, Gamma_a, T_a shift)
+//
+// One thread per half point (i, k), one wave per row k.  The T_a shift
+// adjoints and the point's own B_x adjoints have a single writer here (plain
+// read-add-write); the transverse stencils of the source leave through the
+// combining scatter; phi and E_x (rows k-1..k+1) take atomic adds.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_axion_ta_bar(AxBar<T> a) {
     const Geo& g = a.f.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    const int lane = threadIdx.x;           // blockDim.x is one wave: a wave shares k
     const bool inb = i < g.nx && k < g.nr;
+    const T h = T(g.h), dr = T(g.dr);
+    const bool live = inb && (g.per || i < g.nx - 1);
+    const int ir = g.per ? (i + 1) % g.nx : i + 1;
+    const bool hasr = inb && ir < g.nx;
+    const AxionArgs<T>& f = a.f;
+    const T half = T(0.5);
     double dsphi = 0.0;
+    cx<T> gab[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) gab[m] = zero<T>();
     if (inb) {
-        const T h = T(g.h), dr = T(g.dr);
-        const bool live = g.per || i < g.nx - 1;
-        const int ir = g.per ? (i + 1) % g.nx : i + 1;
-        const AxionArgs<T>& f = a.f;
-        cx<T> gab[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            cx<T> tp = (ir < g.nx) ? ld(a.tapBb + g.at(m, k, ir)) : zero<T>();
-            cx<T> tm = ld(a.tamBb + g.at(m, k, i));
-            if (ir < g.nx) addx(a.tapAb, g, m, k, i, tp);
-            addx(a.tamAb, g, m, k, i + 1, tm);
+            const cx<T> tp = hasr ? ld(a.tapBb + g.at(m, k, ir)) : zero<T>();
+            const cx<T> tm = ld(a.tamBb + g.at(m, k, i));
+            if (hasr) {
+                rmw(a.tapAb + g.at(m, k, i), tp);
+                rmw(a.tamAb + g.at(m, k, ir), tm);
+            }
             gab[m] = h * (tp + tm);
         }
+    }
+    cx<T> Exb[M], Bxb[M], Erb[M], Brb[M], Etb[M], Btb[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) Exb[m] = Bxb[m] = Erb[m] = Brb[m] = Etb[m] = Btb[m] = zero<T>();
+    if (live) {
+        const T rk = (T(k) + T(0.5)) * dr;
+        cx<T> Sb[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cx<T> gb = gab[m];
+            // Gamma_a = Lap(phi) - (m^2/r^2 + m_a^2) phi + s_phi S
+            cadd(a.phiAb + g.at(m, k, i), (-T(2) / (dr * dr) - (T(m * m) / (rk * rk) + T(f.ma2))) * gb);
+            cx<T> cu = (T(1) / (dr * dr) + T(1) / (T(2) * dr * rk)) * gb;
+            if (k + 1 < g.nr) cadd(a.phiAb + g.at(m, k + 1, i), cu);
+            else if (g.open_r) cadd(a.phiAb + g.at(m, g.nr, i), cu);
+            if (k > 0) cadd(a.phiAb + g.at(m, k - 1, i), (T(1) / (dr * dr) - T(1) / (T(2) * dr * rk)) * gb);
+            Sb[m] = T(f.s_phi) * gb;
+        }
+        // recompute the forward source factors
+        cx<T> Ex[M], Bx[M], Er[M], Br[M], Et[M], Bt[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            Er[m] = T(0.5) * (er(f.A0, g, m, k, i) + er(f.A0, g, m, k, i + 1));
+            Bt[m] = T(0.5) * (bth(f.A0, g, m, k, i) + bth(f.A0, g, m, k, i + 1));
+            Et[m] = T(0.25) * (eth(f.A0, g, m, k, i) + eth(f.A0, g, m, k + 1, i) + eth(f.A0, g, m, k, i + 1) +
+                               eth(f.A0, g, m, k + 1, i + 1));
+            Br[m] = T(0.25) * (brr(f.A0, g, m, k, i) + brr(f.A0, g, m, k + 1, i) + brr(f.A0, g, m, k, i + 1) +
+                               brr(f.A0, g, m, k + 1, i + 1));
+            cx<T> e0 = T(0.5) * (ld(f.A0.ex + g.at(m, k, i)) + ld(f.B0.ex + g.at(m, k, i)));
+            cx<T> e1 = T(0.5) * (ld(f.A0.ex + g.at(m, k + 1, i)) + ld(f.B0.ex + g.at(m, k + 1, i)));
+            Ex[m] = T(0.5) * (e0 + e1);
+            Bx[m] = T(0.5) * (ld(f.A0.bx + g.at(m, k, i)) + ld(f.B0.bx + g.at(m, k, i)));
+        }
+        Bx[0] = Bx[0] + f.bx0;
+        if (M > 1) {
+            Br[1] = Br[1] + f.br1;
+            Bt[1] = Bt[1] + f.bt1;
+        }
+        if (a.dLds) {
+            cx<T> S[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) S[m] = zero<T>();
+            conv_acc<T, M>(Ex, Bx, T(1), S);
+            conv_acc<T, M>(Er, Br, T(1), S);
+            conv_acc<T, M>(Et, Bt, T(1), S);
+#pragma unroll
+            for (int m = 0; m < M; ++m) dsphi += double(gab[m].re * S[m].re + gab[m].im * S[m].im);
+        }
+        conv_bar<T, M>(Ex, Bx, Sb, T(1), Exb, Bxb);
+        conv_bar<T, M>(Er, Br, Sb, T(1), Erb, Brb);
+        conv_bar<T, M>(Et, Bt, Sb, T(1), Etb, Btb);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        Acc2x2<T> R;    // T_r^+ (p), T_r^- (q) on the half row k (slot 0)
+        Acc2x2<T> Q;    // T_theta^+ (p), T_theta^- (q) on the rows k (slot 0), k+1 (slot 1)
         if (live) {
-            const T rk = (T(k) + T(0.5)) * dr;
-            cx<T> Sb[M];
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                cx<T> gb = gab[m];
-                // Gamma_a = Lap(phi) - (m^2/r^2 + m_a^2) phi + s_phi S
-                cadd(a.phiAb + g.at(m, k, i),
-                     (-T(2) / (dr * dr) - (T(m * m) / (rk * rk) + T(f.ma2))) * gb);
-                cx<T> cu = (T(1) / (dr * dr) + T(1) / (T(2) * dr * rk)) * gb;
-                if (k + 1 < g.nr) cadd(a.phiAb + g.at(m, k + 1, i), cu);
-                else if (g.open_r) cadd(a.phiAb + g.at(m, g.nr, i), cu);
-                if (k > 0) cadd(a.phiAb + g.at(m, k - 1, i), (T(1) / (dr * dr) - T(1) / (T(2) * dr * rk)) * gb);
-                Sb[m] = T(f.s_phi) * gb;
+            for (int c = 0; c < 2; ++c) {
+                // E_r and B_theta averaged over the columns i, i+1
+                const cx<T> e = half * (half * Erb[m]), b = half * (half * Btb[m]);
+                R.p[0][c] = R.p[0][c] + e + b;
+                R.q[0][c] = R.q[0][c] + e - b;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    // E_theta and B_r averaged over the rows k, k+1 and the columns
+                    const cx<T> et = half * (T(0.25) * Etb[m]), br = half * (T(0.25) * Brb[m]);
+                    Q.p[r][c] = Q.p[r][c] + et + br;
+                    Q.q[r][c] = Q.q[r][c] + et - br;
+                }
             }
-            // recompute the forward source factors
-            cx<T> Ex[M], Bx[M], Er[M], Br[M], Et[M], Bt[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                Er[m] = T(0.5) * (er(f.A0, g, m, k, i) + er(f.A0, g, m, k, i + 1));
-                Bt[m] = T(0.5) * (bth(f.A0, g, m, k, i) + bth(f.A0, g, m, k, i + 1));
-                Et[m] = T(0.25) * (eth(f.A0, g, m, k, i) + eth(f.A0, g, m, k + 1, i) + eth(f.A0, g, m, k, i + 1) +
-                                   eth(f.A0, g, m, k + 1, i + 1));
-                Br[m] = T(0.25) * (brr(f.A0, g, m, k, i) + brr(f.A0, g, m, k + 1, i) + brr(f.A0, g, m, k, i + 1) +
-                                   brr(f.A0, g, m, k + 1, i + 1));
-                cx<T> e0 = T(0.5) * (ld(f.A0.ex + g.at(m, k, i)) + ld(f.B0.ex + g.at(m, k, i)));
-                cx<T> e1 = T(0.5) * (ld(f.A0.ex + g.at(m, k + 1, i)) + ld(f.B0.ex + g.at(m, k + 1, i)));
-                Ex[m] = T(0.5) * (e0 + e1);
-                Bx[m] = T(0.5) * (ld(f.A0.bx + g.at(m, k, i)) + ld(f.B0.bx + g.at(m, k, i)));
-            }
-            Bx[0] = Bx[0] + f.bx0;
-            if (M > 1) {
-                Br[1] = Br[1] + f.br1;
-                Bt[1] = Bt[1] + f.bt1;
-            }
-            if (a.dLds) {
-                cx<T> S[M];
-#pragma unroll
-                for (int m = 0; m < M; ++m) S[m] = zero<T>();
-                conv_acc<T, M>(Ex, Bx, T(1), S);
-                conv_acc<T, M>(Er, Br, T(1), S);
-                conv_acc<T, M>(Et, Bt, T(1), S);
-#pragma unroll
-                for (int m = 0; m < M; ++m) dsphi += double(gab[m].re * S[m].re + gab[m].im * S[m].im);
-            }
-            cx<T> Exb[M], Bxb[M], Erb[M], Brb[M], Etb[M], Btb[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) Exb[m] = Bxb[m] = Erb[m] = Brb[m] = Etb[m] = Btb[m] = zero<T>();
-            conv_bar<T, M>(Ex, Bx, Sb, T(1), Exb, Bxb);
-            conv_bar<T, M>(Er, Br, Sb, T(1), Erb, Brb);
-            conv_bar<T, M>(Et, Bt, Sb, T(1), Etb, Btb);
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                add_er(a.A0b, g, m, k, i, T(0.5) * Erb[m]);
-                add_er(a.A0b, g, m, k, i + 1, T(0.5) * Erb[m]);
-                add_bth(a.A0b, g, m, k, i, T(0.5) * Btb[m]);
-                add_bth(a.A0b, g, m, k, i + 1, T(0.5) * Btb[m]);
-                cx<T> q = T(0.25) * Etb[m];
-                add_eth(a.A0b, g, m, k, i, q);
-                add_eth(a.A0b, g, m, k + 1, i, q);
-                add_eth(a.A0b, g, m, k, i + 1, q);
-                add_eth(a.A0b, g, m, k + 1, i + 1, q);
-                cx<T> r = T(0.25) * Brb[m];
-                add_brr(a.A0b, g, m, k, i, r);
-                add_brr(a.A0b, g, m, k + 1, i, r);
-                add_brr(a.A0b, g, m, k, i + 1, r);
-                add_brr(a.A0b, g, m, k + 1, i + 1, r);
-                cx<T> ex = T(0.25) * Exb[m];
-                cadd(a.A0b.ex + g.at(m, k, i), ex);
-                cadd(a.B0b.ex + g.at(m, k, i), ex);
-                cadd(a.A0b.ex + g.at(m, k + 1, i), ex);
-                cadd(a.B0b.ex + g.at(m, k + 1, i), ex);
-                cx<T> bx = T(0.5) * Bxb[m];
-                cadd(a.A0b.bx + g.at(m, k, i), bx);
-                cadd(a.B0b.bx + g.at(m, k, i), bx);
-            }
+            const cx<T> ex = T(0.25) * Exb[m];
+            cadd(a.A0b.ex + g.at(m, k, i), ex);
+            cadd(a.B0b.ex + g.at(m, k, i), ex);
+            cadd(a.A0b.ex + g.at(m, k + 1, i), ex);
+            cadd(a.B0b.ex + g.at(m, k + 1, i), ex);
+            const cx<T> bx = T(0.5) * Bxb[m];
+            rmw(a.A0b.bx + g.at(m, k, i), bx);
+            rmw(a.B0b.bx + g.at(m, k, i), bx);
+        }
+        if (k < g.nr) {
+            flush2x2(g, m, i, lane, k, g.nr - 1, a.A0b.trp, a.A0b.trm, R);
+            flush2x2(g, m, i, lane, k, g.nr, a.A0b.ttp, a.A0b.ttm, Q);
         }
     }
     if (a.dLds) block_sum_add(dsphi, a.dLds);
