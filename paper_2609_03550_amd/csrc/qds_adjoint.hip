@@ -1537,14 +1537,14 @@ static adj::StageBar<T> stage_bar(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>*
 constexpr int kCurBarRows = 4;
 
 template <typename T, int M>
-static void launch_axion_bar(adj::AxBar<T>& a, bool arem, hipStream_t s) {
+static void launch_axion_bar(adj::AxBar<T>& a, bool arem, bool march, hipStream_t s) {
     const Geo& g = a.f.g;
     dim3 blk(64, 4);
     dim3 grdK((g.nx + 63) / 64, (g.nr + 3) / 4);
     if (arem) {
         // the march addresses a plane through 32-bit byte offsets
         const size_t plane = size_t(g.M) * size_t(g.nr + 1) * size_t(g.ld) * sizeof(cx<T>);
-        if (plane < (size_t(1) << 32)) {
+        if (march && plane < (size_t(1) << 32)) {
             const int rows = kCurBarRows;
             const int strips = (g.nx + adj::curb::OWN - 1) / adj::curb::OWN;
             const int chunks = (g.nr + rows - 1) / rows;
@@ -1560,7 +1560,7 @@ static void launch_axion_bar(adj::AxBar<T>& a, bool arem, hipStream_t s) {
 
 template <typename T>
 hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
-                        hipStream_t s) {
+                        bool march, hipStream_t s) {
     const Geo& g = p.g;
     dim3 blk(64, 4);
     dim3 grdJ((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
@@ -1582,7 +1582,7 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
         ax.jaxb = jab[0]; ax.jarb = jab[1]; ax.jatb = jab[2];
         ax.dLds = dLds;
         switch (g.M) {
-#define QDS_AXB(MM) case MM: launch_axion_bar<T, MM>(ax, p.arem, s); break;
+#define QDS_AXB(MM) case MM: launch_axion_bar<T, MM>(ax, p.arem, march, s); break;
             QDS_AXB(1) QDS_AXB(2) QDS_AXB(3) QDS_AXB(4)
 #undef QDS_AXB
             default: return hipErrorInvalidValue;
@@ -1597,9 +1597,9 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
 }
 
 template hipError_t adjoint_step<double>(const StepPlan<double>&, cx<double>* const*, cx<double>* const*,
-                                         cx<double>* const*, double*, hipStream_t);
+                                         cx<double>* const*, double*, bool, hipStream_t);
 template hipError_t adjoint_step<float>(const StepPlan<float>&, cx<float>* const*, cx<float>* const*,
-                                        cx<float>* const*, double*, hipStream_t);
+                                        cx<float>* const*, double*, bool, hipStream_t);
 
 }  // namespace qds
 

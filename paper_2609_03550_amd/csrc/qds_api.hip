@@ -371,7 +371,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
             QDS_TRY(hipMemsetAsync(jab, 0, 3 * P, s));
             plane_table<T>(c, adjX, Xb);
             plane_table<T>(c, adjY, Yb);
-            QDS_TRY(qds::adjoint_step<T>(p, Xb, Yb, jb, red + 1, s));
+            QDS_TRY(qds::adjoint_step<T>(p, Xb, Yb, jb, red + 1, use_fused(c), s));
             char* t = adjX; adjX = adjY; adjY = t;
         }
     }

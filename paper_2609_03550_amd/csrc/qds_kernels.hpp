@@ -186,9 +186,11 @@ template <typename T>
 hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
 // Column strips of the marching axion-current kernel (63 owned columns each).
 int current_strips(int nx);
+// One transposed step.  march: the axion-current transpose marches in r
+// (needs planes below 4 GiB); otherwise one thread per cell with atomic adds.
 template <typename T>
 hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb, cx<T>* const* jab, double* dLds,
-                        hipStream_t s);
+                        bool march, hipStream_t s);
 template <typename T>
 hipError_t loss_seed(cx<T>* const* U, cx<T>* const* Ub, const Geo& g, int set, int md, int x0, int x1, double* loss,
                      hipStream_t s);

@@ -31,9 +31,9 @@ def _oracle_grad(wl, nsteps, lset, lmode, x0=None, x1=None):
     return float(L), {k: (v.grad if v.grad is not None else torch.zeros_like(v)) for k, v in leaves.items()}
 
 
-def _gpu(wl, nsteps, ckpt, lset, lmode, dtype="f64", x0=None, x1=None):
+def _gpu(wl, nsteps, ckpt, lset, lmode, dtype="f64", x0=None, x1=None, path=0):
     from paper_2609_03550_amd import qds
-    s = qds.Solver(wl, dtype=dtype)
+    s = qds.Solver(wl, dtype=dtype, path=path)
     s.load_pulses()
     L, lam, dlds = s.backward(nsteps, ckpt, lset, lmode, x0, x1)
     return s, L, s.buffer_fields(lam), dlds
@@ -92,6 +92,17 @@ def test_full_adjoint_several_tiles(x_bc, r_bc):
     current adjoint's shared chunk rows and strip edges)."""
     wl = _full(150, 21, 3, x_bc=x_bc, r_bc=r_bc)
     _, L, lam, dlds = _gpu(wl, 5, 2, 1, 1)
+    Lo, go = _oracle_grad(wl, 5, 1, 1)
+    assert L > 0 and abs(L / Lo - 1) < 1e-11
+    _compare_grad(lam, go, 1e-9)
+    assert abs(dlds[1] / (2 * L) - 1) < 1e-9
+
+
+def test_full_adjoint_staged_path():
+    """The staged path (one thread per cell, atomic adds for the axion-current
+    transpose) over several tiles."""
+    wl = _full(150, 21, 3)
+    _, L, lam, dlds = _gpu(wl, 5, 2, 1, 1, path=1)
     Lo, go = _oracle_grad(wl, 5, 1, 1)
     assert L > 0 and abs(L / Lo - 1) < 1e-11
     _compare_grad(lam, go, 1e-9)
