@@ -1101,10 +1101,10 @@ __global__ void __launch_bounds__(256) k_axion_current_bar(AxBar<T> a) {
 // transpose of C_m) and transposes the factor expressions into adjoints of the
 // window quantities.  Those of column i+1 go to the next lane by a DPP shift.
 // After row j the K row j-1 and the J row j have all their contributions and
-// are transposed into the planes: rows inside the chunk with plain accesses
-// (a store for the old-level planes, which hold zero before this kernel; a
-// read-add-write for the new-level planes), the rows the chunk shares with its
-// neighbours with atomic adds.
+// are transposed into the planes: the old-level planes, which hold zero before
+// this kernel, take a plain store in the rows inside the chunk and atomic adds
+// in the rows the chunk shares with its neighbours; the new-level planes take
+// one atomic add per point.
 namespace curb {
 
 using cur::FacC;
@@ -1306,42 +1306,23 @@ __device__ __forceinline__ void fac_t_bar(const FacC<T>& c, int j, const cx<T>* 
     }
 }
 
-// p[o] += v: plain (the old value was read ahead into old, or a store where the
-// plane holds zero) or atomic
+// p[o] += v into a new-level plane: an atomic add (it is not waited for, and
+// measured faster than a read-add-write whose read has to be held in registers)
 template <typename T>
-__device__ __forceinline__ void put_new(cx<T>* p, uint32_t o, cx<T> old, cx<T> v, bool atomic) {
-    if (atomic) cadd((cx<T>*)((char*)p + o), v);
-    else cur::sto(p, o, old + v);
+__device__ __forceinline__ void put_new(cx<T>* p, uint32_t o, cx<T> v) {
+    cadd((cx<T>*)((char*)p + o), v);
 }
+// p[o] += v into an old-level plane, which holds zero before this kernel: a
+// store where this lane is the point's only writer, else an atomic add
 template <typename T>
 __device__ __forceinline__ void put_old(cx<T>* p, uint32_t o, cx<T> v, bool atomic) {
     if (atomic) cadd((cx<T>*)((char*)p + o), v);
     else cur::sto(p, o, v);
 }
 
-// the new-level plane values a K row / J row flush adds to, read ahead
-template <typename T>
-struct OldK {
-    cx<T> bx, tap, tam, trp, trm, phi;
-};
-template <typename T>
-struct OldJ {
-    cx<T> ttp, ttm, ex;
-};
-template <typename T>
-__device__ __forceinline__ OldK<T> old_k(const AxBar<T>& a, uint32_t o) {
-    return OldK<T>{cur::ldo(a.B0b.bx, o),  cur::ldo(a.tapBb, o),   cur::ldo(a.tamBb, o),
-                   cur::ldo(a.B0b.trp, o), cur::ldo(a.B0b.trm, o), cur::ldo(a.phiBb, o)};
-}
-template <typename T>
-__device__ __forceinline__ OldJ<T> old_j(const AxBar<T>& a, uint32_t o) {
-    return OldJ<T>{cur::ldo(a.B0b.ttp, o), cur::ldo(a.B0b.ttm, o), cur::ldo(a.B0b.ex, o)};
-}
-
 // transposes of cur::load_k / load_j into the plane adjoints
 template <typename T>
-__device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRow<T>& b, const OldK<T>& q,
-                                        bool atomic) {
+__device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRow<T>& b, bool atomic) {
     const cx<T> d = T(0.25) * b.dt0;
     put_old(a.A0b.bx, o, T(0.5) * b.bxn, atomic);
     put_old(a.tapAb, o, d, atomic);
@@ -1349,21 +1330,20 @@ __device__ __forceinline__ void flush_k(const AxBar<T>& a, uint32_t o, const KRo
     put_old(a.A0b.trp, o, T(0.5) * (b.er0 + b.P), atomic);
     put_old(a.A0b.trm, o, T(0.5) * (b.er0 + b.N), atomic);
     put_old(a.phiAb, o, b.ph0 + T(0.5) * b.phm, atomic);
-    put_new(a.B0b.bx, o, q.bx, T(0.5) * b.bxn, atomic);
-    put_new(a.tapBb, o, q.tap, d + b.up, atomic);
-    put_new(a.tamBb, o, q.tam, d + b.wm, atomic);
-    put_new(a.B0b.trp, o, q.trp, T(0.5) * b.P, atomic);
-    put_new(a.B0b.trm, o, q.trm, T(0.5) * b.N, atomic);
-    put_new(a.phiBb, o, q.phi, T(0.5) * b.phm, atomic);
+    put_new(a.B0b.bx, o, T(0.5) * b.bxn);
+    put_new(a.tapBb, o, d + b.up);
+    put_new(a.tamBb, o, d + b.wm);
+    put_new(a.B0b.trp, o, T(0.5) * b.P);
+    put_new(a.B0b.trm, o, T(0.5) * b.N);
+    put_new(a.phiBb, o, T(0.5) * b.phm);
 }
 template <typename T>
-__device__ __forceinline__ void flush_j(const AxBar<T>& a, uint32_t o, const JRow<T>& b, const OldJ<T>& q,
-                                        bool atomic) {
+__device__ __forceinline__ void flush_j(const AxBar<T>& a, uint32_t o, const JRow<T>& b, bool atomic) {
     put_old(a.A0b.ttp, o, T(0.5) * (b.et0 + b.Qp), atomic);
     put_old(a.A0b.ttm, o, T(0.5) * (b.et0 + b.Qm), atomic);
-    put_new(a.B0b.ttp, o, q.ttp, T(0.5) * b.Qp, atomic);
-    put_new(a.B0b.ttm, o, q.ttm, T(0.5) * b.Qm, atomic);
-    put_new(a.B0b.ex, o, q.ex, b.ex, atomic);
+    put_new(a.B0b.ttp, o, T(0.5) * b.Qp);
+    put_new(a.B0b.ttm, o, T(0.5) * b.Qm);
+    put_new(a.B0b.ex, o, b.ex);
 }
 
 template <typename T, int M>
@@ -1438,35 +1418,9 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
         const KRow<T> kc = cur::load_k(f, o);
         const JRow<T> jn = cur::load_j(f, cur::eoff<T>(g, m, j + 1, i));
         const cx<T> jxb = cur::ldo(a.jaxb, o), jrb = cur::ldo(a.jarb, o), jtb = cur::ldo(a.jatb, o);
-        // the new-level values this row's flushes add to (K row j-1, J row j),
-        // issued after the row's inputs so that they arrive during the phases
         const uint32_t ok = cur::eoff<T>(g, m, j >= 1 ? j - 1 : 0, i);
-        const OldK<T> qk = old_k(a, ok);
-        const OldJ<T> qj = old_j(a, o);
         KRow<T> kcb = cur::zero_k<T>();
         JRow<T> jnb = cur::zero_j<T>();
-        {
-            // j_a,x
-            const NbX<T> nx = cur::nb_x(kp, kc, jc, has1);
-            cx<T> fo[6], fb[6];
-            if (live) cur::fac_x(fc, j, kp, kc, jc, nx, fo);
-            phase(fo, jxb, live, fb);
-            NbX<T> nb{zc, zc, zc, zc, zc};
-            if (live) fac_x_bar(fc, j, fb, kpb, kcb, jcb, nb);
-            prev_add(kcb.dt0, nb.dt1); prev_add(kcb.er0, nb.er1); prev_add(jcb.et0, nb.et1);
-            prev_add(kpb.dt0, nb.dtl1); prev_add(kpb.er0, nb.erl1);
-        }
-        {
-            // j_a,r
-            const NbR<T> nr = cur::nb_r(kc, jc, jn, has1);
-            cx<T> fo[6], fb[6];
-            if (live) cur::fac_r(fc, j, kc, jc, jn, nr, fo);
-            phase(fo, jrb, live, fb);
-            NbR<T> nb{zc, zc, zc, zc, zc, zc};
-            if (live) fac_r_bar(fc, j, fb, kcb, jcb, jnb, nb);
-            prev_add(jcb.Qp, nb.Qp1); prev_add(jcb.Qm, nb.Qm1); prev_add(jnb.Qp, nb.Qpn1);
-            prev_add(jnb.Qm, nb.Qmn1); prev_add(kcb.up, nb.up1); prev_add(kcb.wm, nb.wm1);
-        }
         {
             // j_a,theta
             const NbT<T> nt = cur::nb_t(kp, kc, jc, has1);
@@ -1479,11 +1433,33 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
             prev_add(kpb.P, nb.Pl1); prev_add(kpb.N, nb.Nl1); prev_add(kpb.up, nb.upl1); prev_add(kpb.wm, nb.wml1);
             prev_add(jcb.Qp, nb.Qp1); prev_add(jcb.Qm, nb.Qm1);
         }
-        if (owner) {
-            // K row j-1 and J row j are complete, except for the rows shared with the chunk below
-            if (j >= 1) flush_k(a, ok, kpb, qk, j == r0);
-            flush_j(a, o, jcb, qj, j == r0 && r0 > 0);
+        {
+            // j_a,x
+            const NbX<T> nx = cur::nb_x(kp, kc, jc, has1);
+            cx<T> fo[6], fb[6];
+            if (live) cur::fac_x(fc, j, kp, kc, jc, nx, fo);
+            phase(fo, jxb, live, fb);
+            NbX<T> nb{zc, zc, zc, zc, zc};
+            if (live) fac_x_bar(fc, j, fb, kpb, kcb, jcb, nb);
+            prev_add(kcb.dt0, nb.dt1); prev_add(kcb.er0, nb.er1); prev_add(jcb.et0, nb.et1);
+            prev_add(kpb.dt0, nb.dtl1); prev_add(kpb.er0, nb.erl1);
         }
+        // K row j-1 is complete (only the theta and x factors read it), except
+        // for the row shared with the chunk below
+        if (owner && j >= 1) flush_k(a, ok, kpb, j == r0);
+        {
+            // j_a,r
+            const NbR<T> nr = cur::nb_r(kc, jc, jn, has1);
+            cx<T> fo[6], fb[6];
+            if (live) cur::fac_r(fc, j, kc, jc, jn, nr, fo);
+            phase(fo, jrb, live, fb);
+            NbR<T> nb{zc, zc, zc, zc, zc, zc};
+            if (live) fac_r_bar(fc, j, fb, kcb, jcb, jnb, nb);
+            prev_add(jcb.Qp, nb.Qp1); prev_add(jcb.Qm, nb.Qm1); prev_add(jnb.Qp, nb.Qpn1);
+            prev_add(jnb.Qm, nb.Qmn1); prev_add(kcb.up, nb.up1); prev_add(kcb.wm, nb.wm1);
+        }
+        // J row j is complete, except for the row shared with the chunk below
+        if (owner) flush_j(a, o, jcb, j == r0 && r0 > 0);
         kp = kc;
         jc = jn;
         kpb = kcb;
@@ -1492,8 +1468,8 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
     if (owner) {
         // K row r1-1 and J row r1: complete in the last chunk, shared otherwise
         const uint32_t ok = cur::eoff<T>(g, m, r1 - 1, i), oj = cur::eoff<T>(g, m, r1, i);
-        flush_k(a, ok, kpb, old_k(a, ok), r1 != g.nr);
-        flush_j(a, oj, jcb, old_j(a, oj), r1 != g.nr);
+        flush_k(a, ok, kpb, r1 != g.nr);
+        flush_j(a, oj, jcb, r1 != g.nr);
     }
     if (a.dLds) {
         // one atomic per wave
