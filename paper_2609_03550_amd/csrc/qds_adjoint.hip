@@ -226,9 +226,10 @@ __global__ void __launch_bounds__(256) k_ghost_bth_bar(StageBar<T> a) {
 //
 // One thread per point (i, j), one wave per row j.  The shifted transport
 // adjoints have a single writer per point here and take a plain
-// read-add-write; the plasma j_r / j_theta adjoints (columns i, i+1) leave
-// through the combining scatter; the B_x and E_x adjoints (rows j-1..j+1)
-// take atomic adds.
+// read-add-write; so do the B_x and E_x adjoints, which each thread gathers for
+// its own point (the shares of the rows j-1 and j+1 are recomputed from their
+// transport adjoints); the plasma j_r / j_theta adjoints (columns i, i+1) leave
+// through the combining scatter.
 template <typename T>
 __device__ __forceinline__ void rmw(cx<T>* p, cx<T> v) {
     st(p, ld(p) + v);
@@ -251,13 +252,17 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
     if (j > g.nr) return;                   // uniform over the wave
     const bool in = i < g.nx;
     const T h = T(g.h), dr = T(g.dr);
-    const bool live = in && (g.per || i < g.nx - 1);
+    const bool live = in && (g.per || i < g.nx - 1);   // (implies column i+1 exists)
     const int ir = g.per ? (i + 1) % g.nx : i + 1;
     const bool hasr = in && ir < g.nx;      // column i+1 exists
     const cx<T> zc = zero<T>();
+    // T_theta rows without transport: the wall row, and the axis row for m != 1
+    auto zero_row = [&](int row, int m) { return (!g.open_r && row == g.nr) || (row == 0 && m != 1); };
     for (int m = 0; m < g.M; ++m) {
         cx<T> jr0 = zc, jr1 = zc;           // plasma j_r adjoint, columns i, i+1 of row j
         cx<T> jt0 = zc, jt1 = zc;           // plasma j_theta adjoint, columns i, i+1 of row j
+        cx<T> exb = zc, bxb = zc;           // E_x and B_x adjoints at this point
+        // ---- T_r on K = j
         if (in && j < g.nr) {
             const cx<T> pb = hasr ? ld(a.Bb.trp + g.at(m, j, ir)) : zc;
             const cx<T> mb = ld(a.Bb.trm + g.at(m, j, i));
@@ -268,15 +273,20 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
             if (live) {
                 const T rk = (T(j) + T(0.5)) * dr;
                 const cx<T> gr = h * (pb + mb), pr = h * (pb - mb);
-                cadd(a.Bb.bx + g.at(m, j, i), imul_c(-T(m) / rk, gr));
+                bxb = bxb + imul_c(-T(m) / rk, gr);
                 if (a.plasma) jr0 = jr1 = T(-0.5) * gr;
                 if (a.jr_addb) rmw(a.jr_addb + g.at(m, j, i), -gr);
-                cadd(a.Bb.ex + g.at(m, j + 1, i), (T(1) / dr) * pr);
-                cadd(a.Bb.ex + g.at(m, j, i), -((T(1) / dr) * pr));
+                exb = exb - (T(1) / dr) * pr;
             }
         }
-        const bool zero_row = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
-        if (in && !zero_row) {
+        // ---- the E_x share of T_r on K = j - 1
+        if (live && j >= 1 && j - 1 < g.nr) {
+            const cx<T> pb = ld(a.Bb.trp + g.at(m, j - 1, ir));
+            const cx<T> mb = ld(a.Bb.trm + g.at(m, j - 1, i));
+            exb = exb + (T(1) / dr) * (h * (pb - mb));
+        }
+        // ---- T_theta on J = j
+        if (in && !zero_row(j, m)) {
             const cx<T> pb = ld(a.Bb.ttp + g.at(m, j, i));
             const cx<T> mb = hasr ? ld(a.Bb.ttm + g.at(m, j, ir)) : zc;
             if (hasr) {
@@ -285,20 +295,33 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
             }
             if (live) {
                 const cx<T> gt = h * (pb + mb), pt = h * (pb - mb);
-                // (on the axis only mode 1 gets here: its axis relations)
                 if (j == 0) {
-                    cadd(a.Bb.bx + g.at(m, 0, i), -((T(2) / dr) * gt));
-                    cadd(a.Bb.ex + g.at(m, 1, i), imul_c(T(1) / dr, pt));
+                    // (on the axis only mode 1 gets here: its axis relation; its
+                    // E_x share goes to row 1, gathered there)
+                    bxb = bxb - (T(2) / dr) * gt;
                 } else {
                     const T rj = T(j) * dr;
-                    cadd(a.Bb.bx + g.at(m, j, i), -((T(1) / dr) * gt));
-                    cadd(a.Bb.bx + g.at(m, j - 1, i), (T(1) / dr) * gt);
-                    cadd(a.Bb.ex + g.at(m, j, i), imul_c(T(m) / rj, pt));
+                    bxb = bxb - (T(1) / dr) * gt;
+                    exb = exb + imul_c(T(m) / rj, pt);
                 }
                 if (a.plasma) jt0 = jt1 = T(-0.5) * gt;
                 if (a.jt_addb) rmw(a.jt_addb + g.at(m, j, i), -gt);
             }
         }
+        // ---- the B_x share of T_theta on J = j + 1
+        if (live && j + 1 <= g.nr && !zero_row(j + 1, m)) {
+            const cx<T> pb = ld(a.Bb.ttp + g.at(m, j + 1, i));
+            const cx<T> mb = ld(a.Bb.ttm + g.at(m, j + 1, ir));
+            bxb = bxb + (T(1) / dr) * (h * (pb + mb));
+        }
+        // ---- the E_x share of the mode-1 axis relation on J = 0, at row 1
+        if (live && j == 1 && m == 1) {
+            const cx<T> pb = ld(a.Bb.ttp + g.at(m, 0, i));
+            const cx<T> mb = ld(a.Bb.ttm + g.at(m, 0, ir));
+            exb = exb + imul_c(T(1) / dr, h * (pb - mb));
+        }
+        if (exb.re != T(0) || exb.im != T(0)) rmw(a.Bb.ex + g.at(m, j, i), exb);
+        if (bxb.re != T(0) || bxb.im != T(0)) rmw(a.Bb.bx + g.at(m, j, i), bxb);
         if (a.plasma) {
             if (j < g.nr) flush_row2(g, m, i, lane, j, a.Bb.jr, jr0, jr1);
             flush_row2(g, m, i, lane, j, a.Bb.jt, jt0, jt1);
