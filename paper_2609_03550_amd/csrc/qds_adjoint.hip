@@ -331,119 +331,132 @@ __global__ void __launch_bounds__(256) k_transverse_bar(StageBar<T> a) {
 
 // ---- adjoint of k_longitudinal
 //
-// One thread per point (i, j), one wave per row j.  The points' own planes
-// (E_x, B_x, the currents) have this thread as their only writer here and take
-// a plain read-add-write; the transverse planes collect the 2 x 2 stencils of
-// B_theta / E_r (rows j-1, j) and B_r / E_theta (rows j, j+1) in registers and
-// leave through the combining scatter.  The exterior ghost row's B_x adjoint
-// writes to neighbouring points and runs afterwards in k_longitudinal_ghost_bar.
+// One thread per point (i, j), one wave per row j over 63 columns (lane 0 is a
+// halo: it computes column i-1 for lane 1 and writes nothing).  Every plane
+// point has one writer: the point's own planes (E_x, B_x, the currents) take a
+// plain read-add-write, and so do the transverse planes, whose values each
+// thread gathers for its own point: the B_theta / E_r and B_r / E_theta
+// stencils of E_x on J = j, j+1 and of B_x on K = j-1, j (the neighbouring
+// rows' shares recomputed from their adjoints), the column i-1 shares from the
+// previous lane by a DPP shift.  The exterior ghost row's B_x adjoint writes to
+// points other threads own and runs afterwards in k_longitudinal_ghost_bar.
+constexpr int kLongOwn = 63;
 template <typename T>
 __global__ void __launch_bounds__(256) k_longitudinal_bar(StageBar<T> a) {
     const Geo& g = a.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int lane = threadIdx.x;           // blockDim.x is one wave: a wave shares j
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (j > g.nr) return;                   // uniform over the wave
-    const bool in = i < g.nx;
+    const int raw = blockIdx.x * kLongOwn - 1 + lane;
+    const int i = g.per ? ((raw % g.nx) + g.nx) % g.nx : min(max(raw, 0), g.nx - 1);
+    const bool in = g.per || (raw >= 0 && raw < g.nx);    // a column of its own
+    const bool owner = lane >= 1 && raw < g.nx;
     const T h = T(g.h), dr = T(g.dr);
     const bool live = in && (g.per || i < g.nx - 1);
     const T wp2h = T(a.wp2 * g.h);
     const T half = T(0.5);
+    const T i2dr = T(1) / (T(2) * dr);
+    const bool wall_j = !g.open_r && j == g.nr;           // E_x and T_theta fixed on the wall row
+    const bool wall_j1 = !g.open_r && j + 1 == g.nr;
     for (int m = 0; m < g.M; ++m) {
         const size_t e = g.at(m, j, i);
-        Acc2x2<T> R;    // T_r^+ (p) and T_r^- (q) on K rows j-1 (0), j (1); columns i, i+1
-        Acc2x2<T> Q;    // T_theta^+ (p) and T_theta^- (q) on J rows j (0), j+1 (1)
-        // B_theta / E_r into K row r (the exterior ghost row holds B_theta in T_r^+)
-        auto bth = [&](int r, int c, cx<T> v) {
-            if (j - 1 + r == g.nr) {
-                R.p[r][c] = R.p[r][c] + v;
+        // stencil values of this column's cell, which go to the columns i and i+1 alike
+        cx<T> Sp = zero<T>(), Sq = zero<T>();     // T_r^+, T_r^- on K row j
+        cx<T> Tp = zero<T>(), Tq = zero<T>();     // T_theta^+, T_theta^- on J row j
+        cx<T> Op = zero<T>(), Oq = zero<T>();     // T_r^+- of this column only (plasma)
+        cx<T> Up = zero<T>(), Uq = zero<T>();     // T_theta^+- of this column only (plasma)
+        // B_theta / E_r into K row j (the exterior ghost row holds B_theta in T_r^+)
+        auto bth = [&](cx<T> v) {
+            if (j == g.nr) {
+                Sp = Sp + v;
                 return;
             }
-            R.p[r][c] = R.p[r][c] + half * v;
-            R.q[r][c] = R.q[r][c] - half * v;
-        };
-        auto er = [&](int r, int c, cx<T> v) {
-            R.p[r][c] = R.p[r][c] + half * v;
-            R.q[r][c] = R.q[r][c] + half * v;
-        };
-        auto eth = [&](int r, int c, cx<T> v) {
-            Q.p[r][c] = Q.p[r][c] + half * v;
-            Q.q[r][c] = Q.q[r][c] + half * v;
-        };
-        auto brr = [&](int r, int c, cx<T> v) {
-            Q.p[r][c] = Q.p[r][c] + half * v;
-            Q.q[r][c] = Q.q[r][c] - half * v;
+            Sp = Sp + half * v;
+            Sq = Sq - half * v;
         };
         if (in) {
             cx<T> exb = zero<T>();      // adjoint into A.ex at this point
             cx<T> jxh = zero<T>();      // adjoint of the total j_x at this point
-            // ---- E_x
+            // ---- E_x on J = j: K row j (hi) and J row j (B_r)
             const cx<T> eb = ld(a.Bb.ex + e);
-            if (live && !(!g.open_r && j == g.nr)) {
+            if (live && !wall_j) {
                 if (j == 0) {
                     if (m == 0) {
                         exb = exb + eb;
                         const cx<T> gx = h * eb;
-                        const cx<T> b = (T(4) / dr) * gx;
-                        bth(1, 0, half * b);
-                        bth(1, 1, half * b);
+                        bth(half * ((T(4) / dr) * gx));
                         jxh = jxh - gx;
                     }
                 } else {
                     const T rj = T(j) * dr;
                     exb = exb + eb;
                     const cx<T> gx = h * eb;
-                    const cx<T> bavg = (T(1) / rj) * gx;
-                    const cx<T> brav = imul_c(T(m) / rj, gx);
                     jxh = jxh - gx;
-                    const cx<T> lo = T(0.25) * bavg - (T(1) / (T(2) * dr)) * gx;
-                    const cx<T> hi = T(0.25) * bavg + (T(1) / (T(2) * dr)) * gx;
-                    bth(0, 0, lo);
-                    bth(0, 1, lo);
-                    bth(1, 0, hi);
-                    bth(1, 1, hi);
-                    brr(0, 0, half * brav);
-                    brr(0, 1, half * brav);
+                    bth(T(0.25) * ((T(1) / rj) * gx) + i2dr * gx);
+                    const cx<T> brav = half * imul_c(T(m) / rj, gx);
+                    Tp = Tp + half * brav;
+                    Tq = Tq - half * brav;
                 }
             }
-            if (a.jx_addb && (jxh.re != T(0) || jxh.im != T(0))) rmw(a.jx_addb + e, jxh);
-            // ---- B_x (the exterior ghost row: k_longitudinal_ghost_bar)
+            // ---- E_x on J = j+1: its K row j share (lo)
+            if (live && j + 1 <= g.nr && !wall_j1) {
+                const cx<T> gx = h * ld(a.Bb.ex + g.at(m, j + 1, i));
+                const T rj = T(j + 1) * dr;
+                const cx<T> lo = T(0.25) * ((T(1) / rj) * gx) - i2dr * gx;
+                Sp = Sp + half * lo;
+                Sq = Sq - half * lo;
+            }
+            if (owner && a.jx_addb && (jxh.re != T(0) || jxh.im != T(0))) rmw(a.jx_addb + e, jxh);
+            // ---- B_x on K = j: J row j (lo) and K row j (E_r); its J row j+1 share is gathered there
             if (j < g.nr && live) {
                 const cx<T> bb = ld(a.Bb.bx + e);
                 const T rk = (T(j) + T(0.5)) * dr;
-                rmw(a.Ab.bx + e, bb);
+                if (owner) rmw(a.Ab.bx + e, bb);
                 const cx<T> fx = h * bb;
-                const cx<T> eavg = -(T(1) / rk) * fx;
-                const cx<T> erav = imul_c(-T(m) / rk, fx);
-                const cx<T> lo = T(0.25) * eavg + (T(1) / (T(2) * dr)) * fx;
-                const cx<T> hi = T(0.25) * eavg - (T(1) / (T(2) * dr)) * fx;
-                eth(0, 0, lo);
-                eth(0, 1, lo);
-                eth(1, 0, hi);
-                eth(1, 1, hi);
-                er(1, 0, half * erav);
-                er(1, 1, half * erav);
+                const cx<T> lo = T(0.25) * (-(T(1) / rk) * fx) + i2dr * fx;
+                Tp = Tp + half * lo;
+                Tq = Tq + half * lo;
+                const cx<T> erav = half * imul_c(-T(m) / rk, fx);
+                Sp = Sp + half * erav;
+                Sq = Sq + half * erav;
+            }
+            // ---- B_x on K = j-1: its J row j share (hi)
+            if (j >= 1 && j - 1 < g.nr && live) {
+                const cx<T> fx = h * ld(a.Bb.bx + g.at(m, j - 1, i));
+                const T rk = (T(j) - T(0.5)) * dr;
+                const cx<T> hi = T(0.25) * (-(T(1) / rk) * fx) - i2dr * fx;
+                Tp = Tp + half * hi;
+                Tq = Tq + half * hi;
             }
             // ---- plasma response
             if (a.plasma) {
                 const cx<T> jxb = ld(a.Bb.jx + e) + jxh;
-                rmw(a.Ab.jx + e, jxb);
+                if (owner) rmw(a.Ab.jx + e, jxb);
                 exb = exb + wp2h * jxb;
                 if (j < g.nr) {
                     const cx<T> jrb = ld(a.Bb.jr + e);
-                    rmw(a.Ab.jr + e, jrb);
-                    er(1, 0, wp2h * jrb);
+                    if (owner) rmw(a.Ab.jr + e, jrb);
+                    Op = Op + half * (wp2h * jrb);
+                    Oq = Oq + half * (wp2h * jrb);
                 }
-                if (!(!g.open_r && j == g.nr)) {
+                if (!wall_j) {
                     const cx<T> jtb = ld(a.Bb.jt + e);
-                    rmw(a.Ab.jt + e, jtb);
-                    eth(0, 0, wp2h * jtb);
+                    if (owner) rmw(a.Ab.jt + e, jtb);
+                    Up = Up + half * (wp2h * jtb);
+                    Uq = Uq + half * (wp2h * jtb);
                 }
             }
-            if (exb.re != T(0) || exb.im != T(0)) rmw(a.Ab.ex + e, exb);
+            if (owner && (exb.re != T(0) || exb.im != T(0))) rmw(a.Ab.ex + e, exb);
         }
-        flush2x2(g, m, i, lane, j - 1, g.nr, a.Ab.trp, a.Ab.trm, R);
-        flush2x2(g, m, i, lane, j, g.nr, a.Ab.ttp, a.Ab.ttm, Q);
+        // column i: this cell's stencil, the previous column's, and this column's own terms
+        const cx<T> rp = Sp + prev_lane(Sp) + Op, rq = Sq + prev_lane(Sq) + Oq;
+        const cx<T> tp = Tp + prev_lane(Tp) + Up, tq = Tq + prev_lane(Tq) + Uq;
+        if (owner) {
+            if (rp.re != T(0) || rp.im != T(0)) rmw(a.Ab.trp + e, rp);
+            if (rq.re != T(0) || rq.im != T(0)) rmw(a.Ab.trm + e, rq);
+            if (tp.re != T(0) || tp.im != T(0)) rmw(a.Ab.ttp + e, tp);
+            if (tq.re != T(0) || tq.im != T(0)) rmw(a.Ab.ttm + e, tq);
+        }
     }
 }
 
@@ -1564,11 +1577,12 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
     dim3 blk(64, 4);
     dim3 grdJ((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
     dim3 grdG((g.nx + 255) / 256);
+    dim3 grdL((g.nx + adj::kLongOwn - 1) / adj::kLongOwn, (g.nr + 1 + 3) / 4);
     if (p.axion && p.arem) {
         adj::StageBar<T> a1 = stage_bar(p, Ab, Bb, jab, 1);
         hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a1);
         hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a1);
-        hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a1);
+        hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdL, blk, 0, s, a1);
         if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a1);
     }
     if (p.axion) {
@@ -1590,7 +1604,7 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
     adj::StageBar<T> a0 = stage_bar(p, Ab, Bb, jab, 0);
     hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a0);
     hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a0);
-    hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdJ, blk, 0, s, a0);
+    hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdL, blk, 0, s, a0);
     if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a0);
     return hipGetLastError();
 }
