@@ -21,22 +21,22 @@ qds_status fused_steps_drive(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& 
         const int ia = st->cur, ib = 1 - st->cur;
         const qds::FusedArgs<T> a = fused_args<T>(c, p0, st->buf[ia], st->buf[ib], st->step, st->window);
         hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
-        if (ev) hipEventRecord(ev[0], s);
+        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         hipError_t e = qds::fused_step<T>(a, s, 0);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (ev) hipEventRecord(ev[1], s);
+        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         if (p0.arem) {
             const qds::AxionArgs<T> ax = axion_args<T>(c, p0, st->buf[ia], st->buf[ib]);
             ev = c->timing ? timing_pair(c, 2) : nullptr;
-            if (ev) hipEventRecord(ev[0], s);
+            if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
             e = qds::axion_current_w<T>(ax, s);
             if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev) hipEventRecord(ev[1], s);
+            if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
             ev = c->timing ? timing_pair(c, 1) : nullptr;
-            if (ev) hipEventRecord(ev[0], s);
+            if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
             e = qds::fused_step<T>(a, s, 1);
             if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev) hipEventRecord(ev[1], s);
+            if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         }
         st->cur = ib;
         if (a.window) st->window += 1;
@@ -92,7 +92,8 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     memcpy(c->ktab_pin, &t, sizeof(t));
     hipError_t e = hipMemcpyAsync(c->ktab_dev, c->ktab_pin, sizeof(t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return fail(c, QDS_EHIP, "argument table upload failed: %s", hipGetErrorString(e));
-    hipEventRecord(c->ktab_ev, s);
+    e = hipEventRecord(c->ktab_ev, s);
+    if (e != hipSuccess) return fail(c, QDS_EHIP, "argument table upload failed: %s", hipGetErrorString(e));
     memcpy(c->ktab_key, key, sizeof(key));
     c->ktab_valid = true;
     return QDS_OK;
@@ -133,7 +134,7 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
     const qds::BatchList LA = list(v.firstA, c->trows[0]), LC = list(v.firstC, c->trows[1]),
                          LB = list(v.firstB, c->trows[2]), LB0 = list(v.firstB, c->trows[0]);
     hipEvent_t* e0 = ev ? ev : (c->timing ? timing_pair(c, 0) : nullptr);
-    if (e0) hipEventRecord(e0[0], s);
+    if (e0 && hipEventRecord(e0[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t e;
     if (p0.axion) {
         e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, s);
@@ -143,18 +144,18 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
         e = qds::batch_em<T>(v.fa, LB0, 0, strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
     }
     if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-    if (e0) hipEventRecord(e0[1], s);
+    if (e0 && hipEventRecord(e0[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     if (p0.arem) {
         hipEvent_t* e2 = ev ? ev + 2 : (c->timing ? timing_pair(c, 2) : nullptr);
-        if (e2) hipEventRecord(e2[0], s);
+        if (e2 && hipEventRecord(e2[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         e = qds::batch_current<T>(v.xa, LC, c->M, v.nC, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (e2) hipEventRecord(e2[1], s);
+        if (e2 && hipEventRecord(e2[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         hipEvent_t* e1 = ev ? ev + 4 : (c->timing ? timing_pair(c, 1) : nullptr);
-        if (e1) hipEventRecord(e1[0], s);
+        if (e1 && hipEventRecord(e1[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         e = qds::batch_em<T>(v.fa, LB, 1, v.nB, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (e1) hipEventRecord(e1[1], s);
+        if (e1 && hipEventRecord(e1[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     }
     return QDS_OK;
 }
@@ -201,7 +202,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
                 const int slot = k == 0 ? 0 : (k == 1 ? 1 : 2);
                 if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[t % 4]; }
             }
-        for (hipEvent_t x : ev) hipEventDestroy(x);
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
         for (int k = 0; k < 3; ++k) c->trows[k] = pick[k];
         c->tune = 0;
         c->tuned = 1;
@@ -227,10 +228,10 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
         p.n = st->step;
         p.w = st->window;
         hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
-        if (ev) hipEventRecord(ev[0], s);
+        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         hipError_t e = qds::staged_step<T>(p, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (ev) hipEventRecord(ev[1], s);
+        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         if (window) {
             // the new state (in b) moves one cell left into a
             e = qds::window_shift<T>(reinterpret_cast<const qds::cx<T>*>(st->buf[b]),
@@ -327,7 +328,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
         QDS_TRY(hipMalloc(&dtab, fb + xb));
         e = hipMemcpy(dtab, host.data(), fb + xb, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            hipFree(dtab);
+            (void)hipFree(dtab);
             return fail(c, QDS_EHIP, "backward: %s", hipGetErrorString(e));
         }
         tab = static_cast<qds::FusedArgs<T>*>(dtab);
@@ -336,7 +337,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
     struct FreeTab {
         void* p;
         ~FreeTab() {
-            if (p) hipFree(p);
+            if (p) (void)hipFree(p);
         }
     } free_tab{tab};
     qds::cx<T>* jb[3];
@@ -447,7 +448,12 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
             delete c;
             return fail(nullptr, QDS_ENOMEM, "hipMalloc of the axion-current scratch failed: %s", hipGetErrorString(e));
         }
-        hipMemset(c->scratch, 0, 3 * c->plane_elems * c->elem_bytes);
+        e = hipMemset(c->scratch, 0, 3 * c->plane_elems * c->elem_bytes);
+        if (e != hipSuccess) {
+            (void)hipFree(c->scratch);
+            delete c;
+            return fail(nullptr, QDS_EHIP, "clearing the axion-current scratch failed: %s", hipGetErrorString(e));
+        }
     }
     *out = c;
     return QDS_OK;
@@ -611,7 +617,7 @@ qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, do
         if (hipMallocAsync(&tmp, S, hipStream_t(stream)) != hipSuccess) return fail(h, QDS_ENOMEM, "no memory%s");
         grad_buf = tmp;
         qds_status st = qds_loss_eval(h, buf, loss, out_dev, grad_buf, stream);
-        hipFreeAsync(tmp, hipStream_t(stream));
+        (void)hipFreeAsync(tmp, hipStream_t(stream));
         return st;
     }
     if (h->g.dtype == QDS_F64) {
@@ -635,14 +641,14 @@ qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, do
 
 qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
-    for (hipEvent_t e : h->pool) hipEventDestroy(e);
-    if (h->scratch) hipFree(h->scratch);
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    if (h->scratch) (void)hipFree(h->scratch);
     if (h->ktab_ev) {
-        hipEventSynchronize(h->ktab_ev);
-        hipEventDestroy(h->ktab_ev);
+        (void)hipEventSynchronize(h->ktab_ev);
+        (void)hipEventDestroy(h->ktab_ev);
     }
-    if (h->ktab_dev) hipFree(h->ktab_dev);
-    if (h->ktab_pin) hipHostFree(h->ktab_pin);
+    if (h->ktab_dev) (void)hipFree(h->ktab_dev);
+    if (h->ktab_pin) (void)hipHostFree(h->ktab_pin);
     delete h;
     return QDS_OK;
 }

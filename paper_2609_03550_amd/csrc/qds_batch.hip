@@ -65,15 +65,15 @@ qds_status bfail(qds_batch_ctx* b, qds_status s, const char* fmt, const char* de
 
 void release(qds_batch_ctx* b) {
     if (b->pending) {
-        hipEventSynchronize(b->done);
+        (void)hipEventSynchronize(b->done);
         b->pending = false;
     }
     for (Plan* p : b->plans) {
         for (auto& kv : p->graphs) {
-            hipGraphExecDestroy(kv.second.second);
-            hipGraphDestroy(kv.second.first);
+            (void)hipGraphExecDestroy(kv.second.second);
+            (void)hipGraphDestroy(kv.second.first);
         }
-        if (p->dev) hipFree(p->dev);
+        if (p->dev) (void)hipFree(p->dev);
         delete p;
     }
     b->plans.clear();
@@ -143,7 +143,7 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
         }
         hipError_t e = hipMemcpyAsync(P->dev, P->host.data(), total * sizeof(int), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
-            hipFree(P->dev);
+            (void)hipFree(P->dev);
             delete P;
             return bfail(b, QDS_EHIP, "list upload failed: %s", hipGetErrorString(e));
         }
@@ -174,13 +174,13 @@ hipError_t launch_step(const qds_batch_ctx* b, const Plan& P, int parity, hipStr
                      size_t(parity) * N;
     for (size_t q = 0; q < P.launches.size(); ++q) {
         const Launch& l = P.launches[q];
-        if (ev) hipEventRecord(ev[2 * q], s);
         hipError_t e;
+        if (ev && (e = hipEventRecord(ev[2 * q], s)) != hipSuccess) return e;
         if (l.slot < QDS_TILE_CUR1) e = qds::batch_a<T>(fa, l.L, l.M, l.blocks, s);
         else if (l.slot < QDS_TILE_EM0) e = qds::batch_current<T>(xa, l.L, l.M, l.blocks, s);
         else e = qds::batch_em<T>(fa, l.L, l.slot == QDS_TILE_EM1 ? 1 : 0, l.blocks, s);
         if (e != hipSuccess) return e;
-        if (ev) hipEventRecord(ev[2 * q + 1], s);
+        if (ev && (e = hipEventRecord(ev[2 * q + 1], s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -214,7 +214,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         release(b);
         b->host_args.swap(host);
         if (bytes > b->args_cap) {
-            if (b->args) hipFree(b->args);
+            if (b->args) (void)hipFree(b->args);
             b->args = nullptr;
             b->args_cap = 0;
             if (hipMalloc(&b->args, bytes) != hipSuccess)
@@ -277,7 +277,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 const int cand = int(tr % 4);
                 for (const Launch& l : trial[tr]->launches) {
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]);
+                    if (hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]) != hipSuccess) ms = 3.4e38f;
                     ei += 2;
                     if (ms < best[l.slot]) { best[l.slot] = ms; pick[l.slot] = cand; }
                 }
@@ -288,7 +288,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 b->tiles[q] = cur ? kCandCur[cand] : kCandRows[cand];
             }
             b->tuned = 1;
-            for (hipEvent_t ev : evs) hipEventDestroy(ev);
+            for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
         }
     }
     // the run proper, in segments over which the running set is unchanged
@@ -320,12 +320,12 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 for (int u = 0; u < seg && le == hipSuccess; ++u) le = launch_step<T>(b, *P, int((t + u) & 1), b->cap, nullptr);
                 e = hipStreamEndCapture(b->cap, &g);
                 if (le != hipSuccess || e != hipSuccess) {
-                    if (g) hipGraphDestroy(g);
+                    if (g) (void)hipGraphDestroy(g);
                     return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(le != hipSuccess ? le : e));
                 }
                 e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
                 if (e != hipSuccess) {
-                    hipGraphDestroy(g);
+                    (void)hipGraphDestroy(g);
                     return bfail(b, QDS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
                 }
                 it = P->graphs.emplace(key, std::make_pair(g, x)).first;
@@ -340,7 +340,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         states[k].cur ^= int(n_steps[k] & 1);
         states[k].step += n_steps[k];
     }
-    hipEventRecord(b->done, s);
+    if (hipEventRecord(b->done, s) != hipSuccess) return bfail(b, QDS_EHIP, "event record failed%s");
     b->pending = true;
     return QDS_OK;
 }
@@ -374,7 +374,7 @@ qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch*
     b->err[0] = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
-        if (b->cap) hipStreamDestroy(b->cap);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
         delete b;
         return bfail(nullptr, QDS_EHIP, "stream or event creation failed%s");
     }
@@ -424,9 +424,9 @@ const char* qds_batch_last_error(qds_batch b) { return b ? b->err : g_err; }
 qds_status qds_batch_destroy(qds_batch b) {
     if (!b) return QDS_OK;
     release(b);
-    if (b->args) hipFree(b->args);
-    if (b->done) hipEventDestroy(b->done);
-    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->args) (void)hipFree(b->args);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return QDS_OK;
 }
