@@ -65,8 +65,8 @@ KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current"}
 def source_digest():
     """Digest of the kernel sources the HBM counters depend on."""
     h = hashlib.sha256()
-    for f in ("qds_fused.hip", "qds_current.hip", "qds_stages.hip", "qds_stage_ops.hpp", "qds_kernels.hpp",
-              "qds_common.hpp"):
+    for f in ("qds_fused.hip", "qds_current.hip", "qds_current_rows.hpp", "qds_stages.hip", "qds_stage_ops.hpp",
+              "qds_kernels.hpp", "qds_common.hpp"):
         with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
