@@ -123,7 +123,8 @@ __global__ void __launch_bounds__(WAVE * M) k_batch_current_march(const AxionArg
     const AxionArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
     const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
-    current_body<T, M>(a, local / chunks, local % chunks, L.rows);
+    const int strips = (a.g.nx + OWN - 1) / OWN;   // strips fastest, as kernel A
+    current_body<T, M>(a, local % strips, local / strips, L.rows);
 }
 
 }  // namespace cur
