@@ -1389,7 +1389,10 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
     const int m = threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
     const int chunks = (g.nr + rows - 1) / rows;
-    const int strip = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+    // XCD-contiguous runs of tiles, strips fastest (as the forward kernels)
+    const int strips = (g.nx + OWN - 1) / OWN;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int strip = tile % strips, chunk = tile / strips;
     const int raw = strip * OWN - 1 + lane;
     // halo lanes wrap with periodic x and are clamped otherwise
     const int i = g.per ? ((raw % g.nx) + g.nx) % g.nx : min(max(raw, 0), g.nx - 1);
