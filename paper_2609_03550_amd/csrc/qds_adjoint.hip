@@ -1388,7 +1388,6 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
     const Geo& g = f.g;
     const int m = threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
-    const int chunks = (g.nr + rows - 1) / rows;
     // XCD-contiguous runs of tiles, strips fastest (as the forward kernels)
     const int strips = (g.nx + OWN - 1) / OWN;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);

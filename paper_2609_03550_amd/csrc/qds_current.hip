@@ -122,7 +122,6 @@ __global__ void __launch_bounds__(WAVE * M) k_batch_current_march(const AxionArg
     const int k = batch_find(L, b);
     const AxionArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
-    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
     const int strips = (a.g.nx + OWN - 1) / OWN;   // strips fastest, as kernel A
     current_body<T, M>(a, local % strips, local / strips, L.rows);
 }
