@@ -766,7 +766,6 @@ __device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ ar
     const int k = batch_find(L, b);
     const FusedArgs<T>& a = args[L.idx[k]];
     const int local = b - L.first[k];
-    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
     // strips fastest: the tiles an XCD runs together are neighbouring strips of
     // one radial chunk, which share the cache lines at their edges (measured 8%
     // faster for the FP64 step than radial chunks fastest)
