@@ -148,9 +148,11 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
- *                 times its first 8 steps (two passes over the tile heights
- *                 8, 16, 32, 64, HIP events around every launch) and keeps the
- *                 fastest height for each kernel; the trial steps are ordinary
+ *                 times its first 8 steps (two passes over four tile heights
+ *                 per kernel: 8, 16, 24, 32 for the background set, 4, 6, 8,
+ *                 16 for the axion current, 16, 32, 48, 64 for the regenerated
+ *                 set; HIP events around every launch) and keeps the fastest
+ *                 height for each kernel; the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream
  *                 once, after the trials.
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP

@@ -180,13 +180,16 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
     int64_t done = 0;
     constexpr int kTrials = 8;
     if (c->tune && n_steps >= kTrials) {
-        // autotuner: timed ordinary steps, two passes over four tile heights
-        static const int cand[4] = {8, 16, 32, 64};
+        // autotuner: timed ordinary steps, two passes over four tile heights per
+        // kernel (candidates around each kernel's measured optimum)
+        static const int cand[3][4] = {{8, 16, 24, 32},    // kernel A
+                                       {4, 6, 8, 16},      // axion current
+                                       {16, 32, 48, 64}};  // kernel B
         std::vector<hipEvent_t> ev(6 * kTrials);
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
         for (int t = 0; t < kTrials; ++t) {
-            c->trows[0] = c->trows[1] = c->trows[2] = cand[t % 4];
+            for (int k = 0; k < 3; ++k) c->trows[k] = cand[k][t % 4];
             if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
             const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
             if ((r = table_step<T>(c, st, p0, K, host, s, ev.data() + 6 * t)) != QDS_OK) return r;
@@ -200,7 +203,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[6 * t + 2 * k], ev[6 * t + 2 * k + 1]) != hipSuccess) continue;
                 const int slot = k == 0 ? 0 : (k == 1 ? 1 : 2);
-                if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[t % 4]; }
+                if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[slot][t % 4]; }
             }
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
         for (int k = 0; k < 3; ++k) c->trows[k] = pick[k];
