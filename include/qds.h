@@ -150,7 +150,7 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
  *                 times its first 8 steps (two passes over four tile heights
  *                 per kernel: 8, 16, 24, 32 for the background set, 4, 6, 8,
- *                 16 for the axion current, 16, 32, 48, 64 for the regenerated
+ *                 16 for the axion current, 16, 32, 52, 64 for the regenerated
  *                 set; HIP events around every launch) and keeps the fastest
  *                 height for each kernel; the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream

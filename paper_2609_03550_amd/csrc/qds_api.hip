@@ -184,7 +184,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
         // kernel (candidates around each kernel's measured optimum)
         static const int cand[3][4] = {{8, 16, 24, 32},    // kernel A
                                        {4, 6, 8, 16},      // axion current
-                                       {16, 32, 48, 64}};  // kernel B
+                                       {16, 32, 52, 64}};  // kernel B
         std::vector<hipEvent_t> ev(6 * kTrials);
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
