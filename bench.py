@@ -72,10 +72,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(wl, dtype, kernel):
+def measured_traffic(wl, dtype, kernel, tiles):
     """HBM bytes per launch of one fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), if it
-    was taken on the current kernel sources for this workload and dtype."""
+    was taken on the current kernel sources for this workload and dtype at the
+    same tile height (the halo rows a tile re-reads depend on it)."""
     path = os.path.join(PROFILE_DIR, f"traffic_{wl.name}_{dtype}.json")
     if not os.path.exists(path):
         return None
@@ -83,7 +84,10 @@ def measured_traffic(wl, dtype, kernel):
         d = json.load(f)
     if d.get("source_digest") != source_digest() or d.get("workload") != wl.name or d.get("dtype") != dtype:
         return None
-    return d.get("kernels", {}).get(KERNEL_KEYS[kernel], {}).get("hbm_bytes_per_launch")
+    key = KERNEL_KEYS[kernel]
+    if d.get("tiles", {}).get(key) != tiles.get(key):
+        return None
+    return d.get("kernels", {}).get(key, {}).get("hbm_bytes_per_launch")
 
 
 def adjoint_ratio(dtype, steps, ckpt):
@@ -219,6 +223,8 @@ def main():
     ap.add_argument("--workload", default="axion", choices=["axion", "window", "vacuum"])
     ap.add_argument("--path", type=int, default=0, help="0 auto (fused), 1 staged, 2 fused")
     ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--tiles", default=None,
+                    help="tile heights of kernel A, the axion current and kernel B (a,c,b) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward + adjoint timing (0 skips it)")
@@ -242,7 +248,10 @@ def main():
     dev = torch.device("cuda:0")
     s = qds.Solver(wl, dtype=args.dtype, device="cuda:0", path=args.path, rows=args.rows)
     s.load_pulses()
-    if args.rows is None and args.warmup >= 8:
+    if args.tiles:
+        for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), args.tiles.split(",")):
+            s.set_option(opt, int(v))
+    elif args.rows is None and args.warmup >= 8:
         s.set_option(qds.OPT_TUNE, 1)      # tile heights chosen on the first warm-up steps
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
@@ -280,7 +289,8 @@ def main():
     if not s.fused:
         alg_bytes = sum(plane_accesses(wl, q) for q in range(3)) * eb * cells
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    traffic = measured_traffic(wl, args.dtype, k) if s.fused else None
+    run_tiles = dict(zip(("kernel_a", "axion_current", "kernel_b"), s.tiles()[0]))
+    traffic = measured_traffic(wl, args.dtype, k, run_tiles) if s.fused else None
     # whole-step effective bandwidth against the one-read-one-write byte model
     nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
     step_bytes = 2 * nplanes * eb * cells

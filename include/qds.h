@@ -147,6 +147,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 moving window combined with the regenerated set),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)
+ *  QDS_OPT_ROWS_A, QDS_OPT_ROWS_CUR, QDS_OPT_ROWS_B
+ *                 the same for one kernel (background set, axion current,
+ *                 regenerated set), e.g. to replay heights the tuner chose
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
  *                 times its first 8 steps (two passes over four tile heights
  *                 per kernel: 8, 16, 24, 32 for the background set, 4, 6, 8,
@@ -159,7 +162,10 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
  *                 value resets the recorded launches */
-enum { QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4 };
+enum {
+    QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
+    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7
+};
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
 qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
 

@@ -525,6 +525,13 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
             h->rows = int(value);
             h->trows[0] = h->trows[1] = h->trows[2] = int(value);
             return QDS_OK;
+        case QDS_OPT_ROWS_A:
+        case QDS_OPT_ROWS_CUR:
+        case QDS_OPT_ROWS_B:
+            if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");
+            h->trows[key - QDS_OPT_ROWS_A] = int(value);
+            h->tuned = 0;
+            return QDS_OK;
         case QDS_OPT_TUNE:
             h->tune = value ? 1 : 0;
             return QDS_OK;

@@ -29,6 +29,7 @@ P_TRP, P_TRM, P_TTP, P_TTM, P_EX, P_BX, P_JX, P_JR, P_JT = range(9)
 P_SET1, P_PHI, P_TAP, P_TAM = 9, 18, 19, 20
 
 OPT_PATH, OPT_ROWS, OPT_TIMING, OPT_TUNE = 1, 2, 3, 4
+OPT_ROWS_A, OPT_ROWS_CUR, OPT_ROWS_B = 5, 6, 7       # one kernel's tile height
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 
 
