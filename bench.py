@@ -85,9 +85,7 @@ def measured_traffic(wl, dtype, kernel, tiles):
     if d.get("source_digest") != source_digest() or d.get("workload") != wl.name or d.get("dtype") != dtype:
         return None
     key = KERNEL_KEYS[kernel]
-    if d.get("tiles", {}).get(key) != tiles.get(key):
-        return None
-    return d.get("kernels", {}).get(key, {}).get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(key, {}).get("by_tile", {}).get(str(tiles.get(key)), {}).get("hbm_bytes_per_launch")
 
 
 def adjoint_ratio(dtype, steps, ckpt):
