@@ -62,13 +62,21 @@ def workload(name):
 KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current"}
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_digest():
-    """Digest of the kernel sources the HBM counters depend on."""
+    """Digest of the code (comments aside) of the kernel sources the HBM counters depend on."""
     h = hashlib.sha256()
     for f in ("qds_fused.hip", "qds_current.hip", "qds_current_rows.hpp", "qds_stages.hip", "qds_stage_ops.hpp",
               "qds_kernels.hpp", "qds_common.hpp"):
-        with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2609_03550_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,17 +1,20 @@
 // Fused single-pass QDS step for gfx950.
 //
-// Layout of the work: a workgroup is NW = number of modes wavefronts; wave w
-// advances mode m = w of one strip of 64 half-x cells (lanes; 62 owned, one
-// halo lane on each side) over one chunk of radial rows.  Each lane marches
-// the rows in increasing r keeping a sliding window of rows in registers, so
-// every state plane is read once and written once per step; the neighbouring
-// cells' new transport values come from lane shuffles.  The azimuthal mode
-// convolutions (axion source and axion current) exchange their per-mode
-// factors through LDS between the waves of the workgroup.
+// Layout of the work: a workgroup of kernel A is one wavefront per mode; wave
+// w advances mode m = w of one strip of 64 half-x cells (lanes; 61 owned, lane
+// 0 a left halo, lanes 62-63 a right halo) over one chunk of radial rows.
+// Each lane marches the rows in increasing r keeping a sliding window of rows
+// in registers, so every state plane is read once and written once per step;
+// the values of column i+1 come from the next lane by a DPP shift and the
+// neighbouring cells' new transport values from lane shuffles.  The azimuthal
+// mode convolution of the axion source exchanges its per-mode factors through
+// LDS between the waves of the workgroup.  Kernel B is the same march for one
+// set, one wave per (strip, chunk, mode).
 //
 // Kernel A advances the background set and the axion (source, Klein-Gordon
 // transport, phi); the axion current at the source points is formed by the
-// tile kernel k_axion_current_w (qds_stages.hip); kernel B advances the
+// marched kernel of qds_current.hip (with a prescribed drive, by the tile
+// kernel k_axion_current_w of qds_stages.hip); kernel B advances the
 // regenerated set with it.  They compute exactly the quantities of the staged
 // kernels.
 #include "qds_kernels.hpp"
@@ -20,7 +23,7 @@ namespace qds {
 namespace fused {
 
 constexpr int WAVE = 64;
-constexpr int OWN = kFusedOwn;   // owned cells per wave (halo lane at each end)
+constexpr int OWN = kFusedOwn;   // owned cells per wave (lane 0 and lanes 62-63 are halos)
 
 // Byte offset of element (m, row, c) inside a plane.  A plane is below 4 GiB
 // (checked when the handle is created), so one 32-bit per-lane offset serves
