@@ -173,3 +173,26 @@ def test_autotuned_tiles_change_no_result(dtype):
     assert tuned and rows[0] in (8, 16, 24, 32) and rows[1] in (4, 6, 8, 16) and rows[2] in (16, 32, 52, 64)
     assert a.tiles() == ([16, 16, 16], False)
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
+
+
+def test_per_kernel_tile_heights_change_no_result():
+    """QDS_OPT_ROWS_A / _CUR / _B set one kernel's tile height each (used to
+    replay the autotuner's choice): uneven heights that leave ragged last
+    chunks give bit-identical states; out-of-range heights are rejected."""
+    from paper_2609_03550_amd import qds
+    wl = _full(131, 21, 3)
+    a = qds.Solver(wl, dtype="f64")
+    a.load_pulses()
+    b = qds.Solver(wl, dtype="f64")
+    b.load_pulses()
+    for opt, v in ((qds.OPT_ROWS_A, 5), (qds.OPT_ROWS_CUR, 3), (qds.OPT_ROWS_B, 13)):
+        b.set_option(opt, v)
+    assert b.tiles() == ([5, 3, 13], False)
+    a.step(9)
+    b.step(9)
+    torch.cuda.synchronize()
+    assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
+    for bad in (0, 4097):
+        with pytest.raises(qds.QDSError):
+            b.set_option(qds.OPT_ROWS_CUR, bad)
+    assert b.tiles() == ([5, 3, 13], False)
