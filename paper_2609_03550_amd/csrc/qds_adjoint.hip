@@ -192,15 +192,16 @@ __device__ __forceinline__ void flush2x2(const Geo& g, int m, int i, int lane, i
 
 // ---- adjoint of k_ghost_bth
 template <typename T>
-__global__ void __launch_bounds__(256) k_ghost_bth_bar(StageBar<T> a) {
+__global__ void __launch_bounds__(64) k_ghost_bth_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;                   // one mode per grid row
     if (i >= g.nx || !g.open_r) return;
     const int N = g.nr;
     const T h = T(g.h), dr = T(g.dr);
     const T rN = T(N) * dr;
     const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
-    for (int m = 0; m < g.M; ++m) {
+    {
         cx<T> ob = ld(a.Bb.trp + g.at(m, N, i));
         // out = I0 + kap (G0 - I1) + cR rt
         cx<T> rt = cR * ob;
@@ -462,9 +463,10 @@ __global__ void __launch_bounds__(256) k_longitudinal_bar(StageBar<T> a) {
 
 // ---- adjoint of the exterior ghost B_x of k_longitudinal (row nr), after k_longitudinal_bar
 template <typename T>
-__global__ void __launch_bounds__(256) k_longitudinal_ghost_bar(StageBar<T> a) {
+__global__ void __launch_bounds__(64) k_longitudinal_ghost_bar(StageBar<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;                   // one mode per grid row
     if (i >= g.nx || !g.open_r) return;
     if (!(g.per || i < g.nx - 1)) return;
     const int N = g.nr;
@@ -472,7 +474,7 @@ __global__ void __launch_bounds__(256) k_longitudinal_ghost_bar(StageBar<T> a) {
     const T rN = T(N) * dr;
     const T kap = (dr - h) / (dr + h), cR = T(2) * h * dr / (dr + h);
     const T wp2h = T(a.wp2 * g.h);
-    for (int m = 0; m < g.M; ++m) {
+    {
         cx<T> gh = ld(a.Bb.bx + g.at(m, N, i));
         cadd(a.Ab.bx + g.at(m, N - 1, i), gh);
         cadd(a.Ab.bx + g.at(m, N, i), kap * gh);
@@ -1578,14 +1580,14 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
     const Geo& g = p.g;
     dim3 blk(64, 4);
     dim3 grdJ((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
-    dim3 grdG((g.nx + 255) / 256);
+    dim3 grdG((g.nx + 63) / 64, g.M);          // exterior ghost row: one wave per 64 columns and mode
     dim3 grdL((g.nx + adj::kLongOwn - 1) / adj::kLongOwn, (g.nr + 1 + 3) / 4);
     if (p.axion && p.arem) {
         adj::StageBar<T> a1 = stage_bar(p, Ab, Bb, jab, 1);
-        hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a1);
+        hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(64), 0, s, a1);
         hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a1);
         hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdL, blk, 0, s, a1);
-        if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a1);
+        if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(64), 0, s, a1);
     }
     if (p.axion) {
         adj::AxBar<T> ax;
@@ -1604,10 +1606,10 @@ hipError_t adjoint_step(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>* const* Bb
         }
     }
     adj::StageBar<T> a0 = stage_bar(p, Ab, Bb, jab, 0);
-    hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(256), 0, s, a0);
+    hipLaunchKernelGGL(adj::k_ghost_bth_bar<T>, grdG, dim3(64), 0, s, a0);
     hipLaunchKernelGGL(adj::k_transverse_bar<T>, grdJ, blk, 0, s, a0);
     hipLaunchKernelGGL(adj::k_longitudinal_bar<T>, grdL, blk, 0, s, a0);
-    if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(256), 0, s, a0);
+    if (g.open_r) hipLaunchKernelGGL(adj::k_longitudinal_ghost_bar<T>, grdG, dim3(64), 0, s, a0);
     return hipGetLastError();
 }
 
