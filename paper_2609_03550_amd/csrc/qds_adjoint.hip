@@ -557,35 +557,44 @@ struct AxBar {
 // ---- adjoint of k_axion_phi
 template <typename T>
 __global__ void __launch_bounds__(256) k_axion_phi_bar(AxBar<T> a) {
+    // one thread per half point (i, k), one wave per row k: the phi adjoints of
+    // the point (and of the exterior ghost row, from k = nr - 1 only) have one
+    // writer (plain read-add-write); the T_a^+- shares of the columns i, i+1
+    // are combined across lanes before one atomic add per point
     const Geo& g = a.f.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= g.nx || k >= g.nr) return;
+    const int lane = threadIdx.x;               // blockDim.x is one wave: a wave shares k
+    if (k >= g.nr) return;                      // uniform over the wave
+    const bool in = i < g.nx;
     const T h = T(g.h), dr = T(g.dr);
-    const bool live = g.per || i < g.nx - 1;
+    const bool live = in && (g.per || i < g.nx - 1);
     const T kap = (dr - h) / (dr + h);
     for (int m = 0; m < g.M; ++m) {
-        cx<T> pb = ld(a.phiBb + g.at(m, k, i));
-        if (k == g.nr - 1) {
-            cx<T> Gb = ld(a.phiBb + g.at(m, g.nr, i));
-            if (g.open_r) {
-                if (live) {
-                    cadd(a.phiAb + g.at(m, k, i), Gb);
-                    cadd(a.phiAb + g.at(m, g.nr, i), kap * Gb);
-                    pb = pb - kap * Gb;
+        cx<T> q = zero<T>();
+        if (in) {
+            cx<T> pb = ld(a.phiBb + g.at(m, k, i));
+            cx<T> own = zero<T>();
+            if (k == g.nr - 1) {
+                const cx<T> Gb = ld(a.phiBb + g.at(m, g.nr, i));
+                if (g.open_r) {
+                    if (live) {
+                        own = own + Gb;
+                        rmw(a.phiAb + g.at(m, g.nr, i), kap * Gb);
+                        pb = pb - kap * Gb;
+                    }
+                } else {
+                    rmw(a.phiAb + g.at(m, g.nr, i), Gb);
                 }
-            } else {
-                cadd(a.phiAb + g.at(m, g.nr, i), Gb);
             }
+            if (live) {
+                own = own + pb;
+                q = (h / T(4)) * pb;
+            }
+            if (own.re != T(0) || own.im != T(0)) rmw(a.phiAb + g.at(m, k, i), own);
         }
-        if (live) {
-            cadd(a.phiAb + g.at(m, k, i), pb);
-            cx<T> q = (h / T(4)) * pb;
-            addx(a.tapBb, g, m, k, i, q);
-            addx(a.tapBb, g, m, k, i + 1, q);
-            addx(a.tamBb, g, m, k, i, q);
-            addx(a.tamBb, g, m, k, i + 1, q);
-        }
+        flush_row2(g, m, i, lane, k, a.tapBb, q, q);
+        flush_row2(g, m, i, lane, k, a.tamBb, q, q);
     }
 }
 
