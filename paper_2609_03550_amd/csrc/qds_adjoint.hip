@@ -1559,7 +1559,7 @@ static adj::StageBar<T> stage_bar(const StepPlan<T>& p, cx<T>* const* Ab, cx<T>*
 }
 
 // cell rows per workgroup of the marched current adjoint
-constexpr int kCurBarRows = 4;
+constexpr int kCurBarRows = 6;
 
 template <typename T, int M>
 static void launch_axion_bar(adj::AxBar<T>& a, bool arem, bool march, hipStream_t s) {
