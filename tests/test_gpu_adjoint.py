@@ -28,7 +28,7 @@ def _oracle_grad(wl, nsteps, lset, lmode, x0=None, x1=None):
     out = Q.run(st, g, ph, nsteps)
     L = T.loss_energy(out, g, lset, lmode, x0, x1)
     L.backward()
-    return float(L), {k: (v.grad if v.grad is not None else torch.zeros_like(v)) for k, v in leaves.items()}
+    return float(L.detach()), {k: (v.grad if v.grad is not None else torch.zeros_like(v)) for k, v in leaves.items()}
 
 
 def _gpu(wl, nsteps, ckpt, lset, lmode, dtype="f64", x0=None, x1=None, path=0):
@@ -47,6 +47,10 @@ def _em(nx, nr, M, **kw):
 def _full(nx, nr, M, **kw):
     p1 = I.Pulse("y", 0.5, 1.0, 2 * I.LAMBDA, 10 * H, 0.45 * nx * H)
     p2 = I.Pulse("z", 0.5, 0.8, 2 * I.LAMBDA, 10 * H, 0.45 * nx * H)
+    if M == 1:
+        # mode 0 alone: radially and azimuthally polarised pulses
+        p1 = I.Pulse("r", 0.5, 1.0, 2 * I.LAMBDA, 10 * H, 0.45 * nx * H)
+        p2 = I.Pulse("t", 0.5, 0.8, 2 * I.LAMBDA, 10 * H, 0.45 * nx * H)
     wl = I.Workload("adj_full", nx, nr, M, 0, wp2=0.02, axion=True, arem=True, ma2=0.03,
                     pulses=(p1, p2), bext=(0.05 + 0j, 0.1 + 0.02j, -0.02 + 0.1j))
     return wl.with_(**kw)
@@ -74,11 +78,11 @@ def test_em_plasma_adjoint_matches_autograd():
     _compare_grad(lam, go, 1e-10)
 
 
-@pytest.mark.parametrize("M", [2, 3])
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
 def test_full_adjoint_matches_autograd(M):
     wl = _full(40, 8, M)
-    _, L, lam, dlds = _gpu(wl, 8, 3, 1, 1)
-    Lo, go = _oracle_grad(wl, 8, 1, 1)
+    _, L, lam, dlds = _gpu(wl, 8, 3, 1, 0 if M == 1 else 1)
+    Lo, go = _oracle_grad(wl, 8, 1, 0 if M == 1 else 1)
     assert L > 0 and abs(L / Lo - 1) < 1e-11
     _compare_grad(lam, go, 1e-9)
     # scaled units: L is quadratic in s_phi and in s_j, so each sensitivity is 2L
@@ -126,8 +130,9 @@ def test_checkpoint_interval_does_not_change_the_gradient():
         P.compare_states(lam, res[0][2], 1e-12, 1e-14, by_group=True)
 
 
-def test_single_precision_adjoint_tracks_double():
-    wl = _full(40, 8, 2)
+@pytest.mark.parametrize("nx,nr", [(40, 8), (150, 21)])
+def test_single_precision_adjoint_tracks_double(nx, nr):
+    wl = _full(nx, nr, 2)
     _, L64, lam64, _ = _gpu(wl, 6, 3, 1, 1, "f64")
     _, L32, lam32, _ = _gpu(wl, 6, 3, 1, 1, "f32")
     assert abs(L32 / L64 - 1) < 1e-4
