@@ -191,7 +191,7 @@ __device__ __forceinline__ EmPf<T> em_fetch(const Ctx<T>& c, const SetP<T>& s, i
         p.tma = c.x.L(s.ttm, m, k);
         p.ex0 = c.x.L(s.ex, m, k);
         p.bx0 = c.x.L(s.bx, m, k);
-        if (c.plasma && c.live) p.jx = c.x.L(s.jx, m, k);
+        if (c.plasma) p.jx = c.x.L(s.jx, m, k);
         if (s.jxa && c.live) p.jxa = c.x.L(s.jxa, m, k);
     }
     return p;
@@ -250,7 +250,9 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
                                       cx<T> jx_old, cx<T> jxa) {
     cx<T> v = zero<T>();
     if (!c.live) {
-        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), v);
+        // the dead last cell: its plasma current still advances (it enters no field)
+        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0)
+            sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jx_old + c.wp2h * ex0);
         return v;
     }
     if (c.plasma) {

@@ -304,6 +304,38 @@ class Solver:
             out["Tam"] = self.plane(P_TAM)[:, :nr]
         return {k: v.to("cpu", torch.complex128) for k, v in out.items()}
 
+    def load_fields(self, f: Dict[str, torch.Tensor]) -> None:
+        """Overwrite the current state with named complex tensors (the names
+        and shapes fields() returns); rows and planes not named are zeroed."""
+        nr = self.wl.nr
+        self.bufs[self.state.cur].zero_()
+        cdt = torch.complex128 if self.dtype == "f64" else torch.complex64
+
+        def put(plane, rows, key):
+            if key in f:
+                v = self.plane(plane)
+                v[:, rows] = f[key].to(self.device, cdt)
+        sets = [0, 1] if self.wl.arem else [0]
+        for s in sets:
+            b = 9 * s
+            put(b + P_TRP, slice(0, nr), f"Trp{s}")
+            put(b + P_TRP, nr, f"Bg{s}")
+            put(b + P_TRM, slice(0, nr), f"Trm{s}")
+            put(b + P_TTP, slice(None), f"Ttp{s}")
+            put(b + P_TTM, slice(None), f"Ttm{s}")
+            put(b + P_EX, slice(None), f"Ex{s}")
+            put(b + P_BX, slice(None), f"Bx{s}")
+            if self.wl.wp2 != 0.0:
+                put(b + P_JX, slice(None), f"jx{s}")
+                put(b + P_JR, slice(0, nr), f"jr{s}")
+                put(b + P_JT, slice(None), f"jt{s}")
+        if self.wl.axion:
+            put(P_PHI, slice(0, nr), "phi")
+            put(P_PHI, nr, "phig")
+            put(P_TAP, slice(0, nr), "Tap")
+            put(P_TAM, slice(0, nr), "Tam")
+        torch.cuda.current_stream().synchronize()
+
     # -- adjoint ------------------------------------------------------------
     def backward_pool_bytes(self, n_steps: int, ckpt_every: int) -> int:
         """Bytes of the caller-owned work pool of ``backward(n_steps, ckpt_every)``."""

@@ -196,3 +196,30 @@ def test_per_kernel_tile_heights_change_no_result():
         with pytest.raises(qds.QDSError):
             b.set_option(qds.OPT_ROWS_CUR, bad)
     assert b.tiles() == ([5, 3, 13], False)
+
+
+@pytest.mark.parametrize("dtype,x_bc,r_bc", [("f64", "open", "open"), ("f64", "periodic", "pec"),
+                                             ("f32", "open", "open")])
+def test_random_full_state(dtype, x_bc, r_bc):
+    """Every plane of both sets, the plasma currents and the axion start at
+    O(1) seeded random values (so every term of the step, the couplings
+    included, weighs as much as the transport): one oracle step makes it a
+    state the scheme can reach (fixed axis rows, ghosts), then GPU and oracle
+    take 4 steps from it over three x strips and several radial chunks."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = _full(131, 21, 3, x_bc=x_bc, r_bc=r_bc)
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    gen = torch.Generator().manual_seed(2609)
+    for k, v in st.items():
+        if isinstance(v, torch.Tensor) and v.is_complex():
+            st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    st = Q.step(st, g, ph)
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_fields(st)
+    s.step(4)
+    torch.cuda.synchronize()
+    ref = Q.run(st, g, ph, 4)
+    tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
+    P.compare_states(s.fields(), ref, tol, floor, by_group=(dtype == "f32"))
