@@ -306,7 +306,9 @@ class Solver:
 
     def load_fields(self, f: Dict[str, torch.Tensor]) -> None:
         """Overwrite the current state with named complex tensors (the names
-        and shapes fields() returns); rows and planes not named are zeroed."""
+        and shapes fields() returns); rows and planes not named are zeroed.
+        Integer entries "n" (step) and "w" (window offset), if present, set
+        the state's counters."""
         nr = self.wl.nr
         self.bufs[self.state.cur].zero_()
         cdt = torch.complex128 if self.dtype == "f64" else torch.complex64
@@ -334,6 +336,10 @@ class Solver:
             put(P_PHI, nr, "phig")
             put(P_TAP, slice(0, nr), "Tap")
             put(P_TAM, slice(0, nr), "Tam")
+        if "n" in f:
+            self.state.step = int(f["n"])
+        if "w" in f:
+            self.state.window = int(f["w"])
         torch.cuda.current_stream().synchronize()
 
     # -- adjoint ------------------------------------------------------------

@@ -217,3 +217,35 @@ def test_autograd_function_gradients():
             vals.append(float(T.loss_energy(Q.run(Q.init_state(w2), gq, ph, 8), gq, 1, 1)))
         fd = 1e-12 * (vals[0] - vals[1]) / (2 * hstep)
         assert abs(float(c.grad[q]) - fd) <= 1e-5 * abs(fd) + 1e-12 * float(L), (q, float(c.grad[q]), fd)
+
+
+def test_adjoint_from_random_full_state():
+    """The adjoint from a state whose every plane (both sets, plasma currents,
+    axion) holds O(1) seeded random values, one oracle step after drawing them
+    (a state the scheme can reach), against autograd through the oracle, over
+    three x strips and several radial chunks: the coupling transposes weigh as
+    much as the transport's."""
+    from paper_2609_03550_amd import qds
+    wl = _full(150, 21, 3)
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    gen = torch.Generator().manual_seed(3550)
+    for k, v in st.items():
+        if isinstance(v, torch.Tensor) and v.is_complex():
+            st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    st = Q.step(st, g, ph)
+    s = qds.Solver(wl)
+    s.load_fields(st)
+    L, lam, _ = s.backward(4, 2, 1, 1)
+    lam = s.buffer_fields(lam)
+    leaves = {}
+    for k, v in list(st.items()):
+        if isinstance(v, torch.Tensor):
+            v = v.detach().clone().requires_grad_(True)
+            st[k] = v
+            leaves[k] = v
+    Lo = T.loss_energy(Q.run(st, g, ph, 4), g, 1, 1, None, None)
+    Lo.backward()
+    go = {k: (v.grad if v.grad is not None else torch.zeros_like(v)) for k, v in leaves.items()}
+    assert L > 0 and abs(L / float(Lo.detach()) - 1) < 1e-11
+    _compare_grad(lam, go, 1e-9)

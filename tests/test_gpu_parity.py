@@ -198,9 +198,9 @@ def test_per_kernel_tile_heights_change_no_result():
     assert b.tiles() == ([5, 3, 13], False)
 
 
-@pytest.mark.parametrize("dtype,x_bc,r_bc", [("f64", "open", "open"), ("f64", "periodic", "pec"),
-                                             ("f32", "open", "open")])
-def test_random_full_state(dtype, x_bc, r_bc):
+@pytest.mark.parametrize("dtype,x_bc,r_bc,arem", [("f64", "open", "open", True), ("f64", "periodic", "pec", True),
+                                                  ("f32", "open", "open", True), ("f64", "window", "open", False)])
+def test_random_full_state(dtype, x_bc, r_bc, arem):
     """Every plane of both sets, the plasma currents and the axion start at
     O(1) seeded random values (so every term of the step, the couplings
     included, weighs as much as the transport): one oracle step makes it a
@@ -208,7 +208,7 @@ def test_random_full_state(dtype, x_bc, r_bc):
     take 4 steps from it over three x strips and several radial chunks."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
-    wl = _full(131, 21, 3, x_bc=x_bc, r_bc=r_bc)
+    wl = _full(131, 21, 3, x_bc=x_bc, r_bc=r_bc, arem=arem)
     g, ph = Q.grid_physics(wl)
     st = Q.init_state(wl)
     gen = torch.Generator().manual_seed(2609)
@@ -218,6 +218,7 @@ def test_random_full_state(dtype, x_bc, r_bc):
     st = Q.step(st, g, ph)
     s = qds.Solver(wl, dtype=dtype)
     s.load_fields(st)
+    assert s.fused
     s.step(4)
     torch.cuda.synchronize()
     ref = Q.run(st, g, ph, 4)
