@@ -226,3 +226,27 @@ def test_random_full_state(dtype, x_bc, r_bc, arem):
     ref = Q.run(st, g, ph, 4)
     tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
     P.compare_states(s.fields(), ref, tol, floor, by_group=(dtype == "f32"))
+
+
+def test_random_state_with_drive():
+    """The prescribed drive (with its noise) on a random full state in the
+    moving window: the by-value drive kernels against the oracle."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = I.driven_window(nx=200, nr=20, steps=0)
+    d = wl.drive
+    wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed), pulses=())
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    s = qds.Solver(wl)
+    held = set(s.fields())        # no plasma here: the current planes stay zero
+    gen = torch.Generator().manual_seed(1)
+    for k, v in st.items():
+        if k in held:
+            st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    st = Q.step(st, g, ph)
+    s.load_fields(st)
+    s.step(5)
+    torch.cuda.synchronize()
+    ref = Q.run(st, g, ph, 5)
+    P.compare_states(s.fields(), ref, 1e-12, 1e-14)
