@@ -134,7 +134,8 @@ def adjoint_ratio(dtype, steps, ckpt):
 def batched_leg(steps, graph_steps, count=64):
     """The 64 uneven single-precision instances: ``steps`` batched steps
     (graphs of ``graph_steps`` steps, tiles from the autotuner) against the
-    same steps taken one instance at a time with qds_step."""
+    same steps taken one instance at a time with qds_step (each instance with
+    the tiles its own autotuner chose)."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
@@ -154,7 +155,8 @@ def batched_leg(steps, graph_steps, count=64):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     for s in bs:
-        s.step(2)
+        s.set_option(qds.OPT_TUNE, 1)      # each instance's own autotuner, untimed
+        s.step(8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in bs:

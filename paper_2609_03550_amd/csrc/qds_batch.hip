@@ -35,8 +35,9 @@ struct Plan {
     std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
-const int kCandRows[4] = {4, 8, 16, 32};     // kernel A and the electromagnetic sets
-const int kCandCur[4] = {4, 8, 16, 32};      // axion current
+const int kCandA[4] = {8, 16, 24, 32};       // kernel A
+const int kCandCur[4] = {4, 6, 8, 16};       // axion current
+const int kCandEm[4] = {8, 16, 32, 52};      // the electromagnetic sets alone (kernel B)
 constexpr int kTunePasses = 2;
 
 }  // namespace
@@ -251,9 +252,9 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             std::vector<Plan*> trial;
             for (int pass = 0; pass < kTunePasses; ++pass) {
                 for (int cand = 0; cand < 4; ++cand) {
-                    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = kCandRows[cand];
+                    for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = kCandA[cand];
                     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = kCandCur[cand];
-                    b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = kCandRows[cand];
+                    b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = kCandEm[cand];
                     Plan* P;
                     if ((st = build_plan(b, act, s, &P)) != QDS_OK) return st;
                     trial.push_back(P);
@@ -284,8 +285,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             }
             for (int q = 0; q < QDS_NTILES; ++q) {
                 const int cand = pick[q] < 0 ? 2 : pick[q];
-                const bool cur = q >= QDS_TILE_CUR1 && q < QDS_TILE_EM0;
-                b->tiles[q] = cur ? kCandCur[cand] : kCandRows[cand];
+                b->tiles[q] = q < QDS_TILE_CUR1 ? kCandA[cand] : (q < QDS_TILE_EM0 ? kCandCur[cand] : kCandEm[cand]);
             }
             b->tuned = 1;
             for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);

@@ -96,7 +96,10 @@ def test_autotuner_picks_candidates_and_keeps_results():
     b.run(12, graph_steps=4, tune=True)
     tiles, tuned = b.tiles()
     assert tuned
-    assert all(t in (4, 8, 16, 32) for t in tiles)
+    # kernel A (slots 0-3), axion current (4-7), electromagnetic sets alone (8, 9)
+    assert all(t in (8, 16, 24, 32) for t in tiles[:4])
+    assert all(t in (4, 6, 8, 16) for t in tiles[4:8])
+    assert all(t in (8, 16, 32, 52) for t in tiles[8:])
     _identical(bs, ref)
     # a second run reuses the chosen tiles
     b.run(3, graph_steps=2, tune=True)
