@@ -253,3 +253,28 @@ def test_random_state_with_drive():
     torch.cuda.synchronize()
     ref = Q.run(st, g, ph, 5)
     P.compare_states(s.fields(), ref, 1e-12, 1e-14)
+
+
+def test_stop_save_reload_continue_is_bitwise():
+    """Checkpoint and resume: 5 steps, the state saved through fields() and
+    loaded into a fresh solver (counters included), 6 more steps, equals 11
+    uninterrupted steps bit for bit (FP64; the moving window with the drive,
+    whose lab position and noise depend on the counters)."""
+    from paper_2609_03550_amd import qds
+    wl = I.driven_window(nx=200, nr=20, steps=0)
+    d = wl.drive
+    wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed),
+                  pulses=(wl.pulses[0].__class__("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 140 * H),))
+    a = _solver(wl, "f64")
+    a.step(11)
+    b = _solver(wl, "f64")
+    b.step(5)
+    saved = dict(b.fields(), n=b.n, w=b.window)
+    c = qds.Solver(wl, dtype="f64")
+    c.load_fields(saved)
+    c.step(6)
+    torch.cuda.synchronize()
+    assert (c.n, c.window) == (a.n, a.window)
+    fa, fc = a.fields(), c.fields()
+    for k in fa:
+        assert torch.equal(fa[k], fc[k]), k
