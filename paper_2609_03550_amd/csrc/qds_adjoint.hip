@@ -734,176 +734,8 @@ __global__ void __launch_bounds__(256) k_axion_ta_bar(AxBar<T> a) {
     if (a.dLds) block_sum_add(dsphi, a.dLds);
 }
 
-// ---- adjoint of ja_factors: distribute the 18 factor adjoints of mode m
-template <typename T>
-__device__ void ja_factors_bar(const AxBar<T>& a, int m, int i, int j, const cx<T>* fb) {
-    const AxionArgs<T>& f = a.f;
-    const Geo& g = f.g;
-    const T dr = T(g.dr);
-    const int i1 = i + 1;
-    const bool ax = (j == 0);
-    const T rj = T(j) * dr;
-    const T rk = (T(j) + T(0.5)) * dr;
-    const T r_half = T(0.5) * dr;
-    const T par = parity<T>(m);
-    // d_t phi / d_x phi adjoint helpers: dto = (tapA + tamA)/2, dth = (tapB + tamB)/2,
-    // dxh = (tamB - tapB)/2
-    auto add_dto = [&](int k, int c, cx<T> v) {
-        addx(a.tapAb, g, m, k, c, T(0.5) * v);
-        addx(a.tamAb, g, m, k, c, T(0.5) * v);
-    };
-    auto add_dth = [&](int k, int c, cx<T> v) {
-        addx(a.tapBb, g, m, k, c, T(0.5) * v);
-        addx(a.tamBb, g, m, k, c, T(0.5) * v);
-    };
-    auto add_dxh = [&](int k, int c, cx<T> v) {
-        addx(a.tamBb, g, m, k, c, T(0.5) * v);
-        addx(a.tapBb, g, m, k, c, -(T(0.5) * v));
-    };
-    // ---------------- j_a,x
-    {
-        // f0 = (blo + bhi)/2, bhi = (A.bx + B.bx)(j)/2, blo = par bhi (axis) or (A.bx + B.bx)(j-1)/2
-        cx<T> hib = T(0.5) * fb[0], lob = T(0.5) * fb[0];
-        if (ax) hib = hib + par * lob;
-        cadd(a.A0b.bx + g.at(m, j, i), T(0.5) * hib);
-        cadd(a.B0b.bx + g.at(m, j, i), T(0.5) * hib);
-        if (!ax) {
-            cadd(a.A0b.bx + g.at(m, j - 1, i), T(0.5) * lob);
-            cadd(a.B0b.bx + g.at(m, j - 1, i), T(0.5) * lob);
-        }
-        // f1 = avg over columns of (l + d)/2, d = (dto + dth)/2 at row j, l at j-1 or par d
-        cx<T> q = T(0.25) * fb[1];   // weight of each of l0, d0, l1, d1
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const int c = i + c2;
-            cx<T> db = q, lb = q;
-            if (ax) db = db + par * lb;
-            add_dto(j, c, T(0.5) * db);
-            add_dth(j, c, T(0.5) * db);
-            if (!ax) {
-                add_dto(j - 1, c, T(0.5) * lb);
-                add_dth(j - 1, c, T(0.5) * lb);
-            }
-        }
-        // f2 = avg of (g + e)/2 over columns, E_r with the axis reflection
-        const cx<T> q2 = T(0.25) * fb[2];
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const int c = i + c2;
-            cx<T> eb = q2, gb = q2;
-            if (ax) {
-                eb = eb - gb;                                 // g = 2i E_th(0) - e  or  -e
-                if (m == 1) add_eth(a.A0b, g, 1, 0, c, imul_c(T(2), gb));
-            } else {
-                add_er(a.A0b, g, m, j - 1, c, gb);
-            }
-            add_er(a.A0b, g, m, j, c, eb);
-        }
-        // f3 = (d_theta phi)/r
-        {
-            cx<T> f3b = fb[3];
-            if (ax) {
-                if (m == 1) cadd(a.phiAb + g.at(m, j, i), imul_c(-T(1) / r_half, f3b));
-            } else {
-                cx<T> s = T(0.5) * imul_c(-T(m) / rj, f3b);
-                cadd(a.phiAb + g.at(m, j, i), s);
-                cadd(a.phiAb + g.at(m, j - 1, i), s);
-            }
-        }
-        // f4 = mean of E_theta(j) over the columns
-        add_eth(a.A0b, g, m, j, i, T(0.5) * fb[4]);
-        add_eth(a.A0b, g, m, j, i1, T(0.5) * fb[4]);
-        // f5 = (phi_hi - phi_lo)/dr
-        {
-            cx<T> s = (T(1) / dr) * fb[5];
-            cx<T> hib2 = s, lob2 = -s;
-            if (ax) hib2 = hib2 + par * lob2;
-            cadd(a.phiAb + g.at(m, j, i), hib2);
-            if (!ax) cadd(a.phiAb + g.at(m, j - 1, i), lob2);
-        }
-    }
-    // ---------------- j_a,theta
-    {
-        // f6: B_theta^{n+1/2} at (x_{i+1/2}, r_j): mean of (gb + b)/2 over columns,
-        // b = (Bt0 + Bt1)/2 at row j; gb at row j-1, or the reflection
-        cx<T> q = T(0.25) * fb[6];
-        cx<T> qe = T(0.25) * fb[10];
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const int c = i + c2;
-            cx<T> bb = q, gbb = q, ebb = qe, gebb = qe;
-            if (ax) {
-                bb = bb - gbb;
-                ebb = ebb - gebb;
-                if (m == 1) {
-                    // gb = -2i br - b, br = (Br0 + Br1)(J=0)/2; ge = 2i et - e, et = (Et0 + Et1)(J=0)/2
-                    cx<T> brb = imul_c(-T(2), gbb);
-                    add_brr(a.A0b, g, 1, 0, c, T(0.5) * brb);
-                    add_brr(a.B0b, g, 1, 0, c, T(0.5) * brb);
-                    cx<T> etb = imul_c(T(2), gebb);
-                    add_eth(a.A0b, g, 1, 0, c, T(0.5) * etb);
-                    add_eth(a.B0b, g, 1, 0, c, T(0.5) * etb);
-                }
-            } else {
-                add_bth(a.A0b, g, m, j - 1, c, T(0.5) * gbb);
-                add_bth(a.B0b, g, m, j - 1, c, T(0.5) * gbb);
-                add_er(a.A0b, g, m, j - 1, c, T(0.5) * gebb);
-                add_er(a.B0b, g, m, j - 1, c, T(0.5) * gebb);
-            }
-            add_bth(a.A0b, g, m, j, c, T(0.5) * bb);
-            add_bth(a.B0b, g, m, j, c, T(0.5) * bb);
-            add_er(a.A0b, g, m, j, c, T(0.5) * ebb);
-            add_er(a.B0b, g, m, j, c, T(0.5) * ebb);
-        }
-        // f7 (d_t phi) and f11 (d_x phi) at t^{n+1/2}
-        cx<T> qt = T(0.25) * fb[7], qx = T(0.25) * fb[11];
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const int c = i + c2;
-            cx<T> tb = qt, tlb = qt, xb = qx, xlb = qx;
-            if (ax) {
-                tb = tb + par * tlb;
-                xb = xb + par * xlb;
-            } else {
-                add_dth(j - 1, c, tlb);
-                add_dxh(j - 1, c, xlb);
-            }
-            add_dth(j, c, tb);
-            add_dxh(j, c, xb);
-        }
-        // f8 = E_x^{n+1/2}(j)
-        cadd(a.B0b.ex + g.at(m, j, i), fb[8]);
-        // f9 = (ph - pl)/dr, ph = (phiA + phiB)(j)/2
-        {
-            cx<T> s = (T(1) / dr) * fb[9];
-            cx<T> phb = s, plb = -s;
-            if (ax) phb = phb + par * plb;
-            cadd(a.phiAb + g.at(m, j, i), T(0.5) * phb);
-            cadd(a.phiBb + g.at(m, j, i), T(0.5) * phb);
-            if (!ax) {
-                cadd(a.phiAb + g.at(m, j - 1, i), T(0.5) * plb);
-                cadd(a.phiBb + g.at(m, j - 1, i), T(0.5) * plb);
-            }
-        }
-    }
-    // ---------------- j_a,r
-    {
-        cx<T> sb = T(0.25) * fb[12], se = T(0.25) * fb[14];
-        for (int dj = 0; dj < 2; ++dj)
-            for (int di = 0; di < 2; ++di) {
-                add_brr(a.A0b, g, m, j + dj, i + di, T(0.5) * sb);
-                add_brr(a.B0b, g, m, j + dj, i + di, T(0.5) * sb);
-                add_eth(a.A0b, g, m, j + dj, i + di, T(0.5) * se);
-                add_eth(a.B0b, g, m, j + dj, i + di, T(0.5) * se);
-            }
-        add_dth(j, i, T(0.5) * fb[13]);
-        add_dth(j, i1, T(0.5) * fb[13]);
-        add_dxh(j, i, T(0.5) * fb[15]);
-        add_dxh(j, i1, T(0.5) * fb[15]);
-        cadd(a.B0b.ex + g.at(m, j, i), T(0.5) * fb[16]);
-        cadd(a.B0b.ex + g.at(m, j + 1, i), T(0.5) * fb[16]);
-        cx<T> ph = imul_c(-T(m) / rk, fb[17]);
-        cadd(a.phiAb + g.at(m, j, i), T(0.5) * ph);
-        cadd(a.phiBb + g.at(m, j, i), T(0.5) * ph);
-    }
-}
-
+// ---- adjoint of ja_factors for one cell: the 18 factor adjoints of mode m
+// into the adjoints of the planes they read, with the combining scatter
 template <typename T>
 __device__ void ja_factors_bar_comb(const AxBar<T>& a, int m, int i, int j, int lane, const cx<T>* fb) {
     const AxionArgs<T>& f = a.f;
