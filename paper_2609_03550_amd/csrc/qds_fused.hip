@@ -477,7 +477,8 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
 template <typename T>
 __device__ __forceinline__ T par(int m) { return m == 0 ? T(1) : T(-1); }
 
-// LDS exchange slots per lane: the 6 factors of the axion source
+// LDS exchange slots per lane: the 6 factors of the axion source (two such
+// buffers, alternating by row)
 constexpr int NS = 6;
 
 // ---------------------------------------------------------------------------
@@ -524,7 +525,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     c.w = a.w;
 
     extern __shared__ unsigned char smem_raw[];
-    cx<T>* smS = reinterpret_cast<cx<T>*>(smem_raw);  // [NS][M][WAVE]
+    // two exchange buffers [NS][M][WAVE], alternating by row: the one barrier
+    // per row (after the writes) then also keeps the next row's writes behind
+    // every wave's reads of this row
+    cx<T>* const smS2 = reinterpret_cast<cx<T>*>(smem_raw);
     auto put = [&](cx<T>* base, int f, cx<T> v) { base[(f * M + wave) * WAVE + lane] = v; };
     auto get = [&](const cx<T>* base, int f, int k) { return base[(f * M + k) * WAVE + lane]; };
 
@@ -586,6 +590,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
 
         // ---------------- axion source S_a at K = j (Eqs. source_mode_zero/_m)
+        cx<T>* const smS = smS2 + (j & 1) * (NS * M * WAVE);
         cx<T> Sa = zero<T>();
         cx<T> ga = zero<T>();
         if (j < g.nr) {
@@ -805,7 +810,7 @@ template <typename T, int M>
 static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
     const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
     const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
-    const size_t lds = size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
+    const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
     const dim3 grd(strips, chunks), blk(fused::WAVE * M);
     if constexpr (sizeof(T) == 8) {
         if (a.drive.on) hipLaunchKernelGGL((fused::k_fused_a_f64<M, true>), grd, blk, lds, s, a);
@@ -844,7 +849,7 @@ hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
 template <typename T>
 hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    const size_t lds = size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
+    const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
     switch (M) {
 #define QDS_BA(MM)                                                                                               \
     case MM:                                                                                                     \
