@@ -19,14 +19,14 @@ template <typename T>
 qds_status fused_steps_drive(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s) {
     for (int64_t it = 0; it < n_steps; ++it) {
         const int ia = st->cur, ib = 1 - st->cur;
-        const qds::FusedArgs<T> a = fused_args<T>(c, p0, st->buf[ia], st->buf[ib], st->step, st->window);
+        const qds::FusedArgs<T> a = fused_args<T>(c, p0, st->buf[ia], st->buf[ib], st->step, st->window, false);
         hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
         if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         hipError_t e = qds::fused_step<T>(a, s, 0);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
         if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
         if (p0.arem) {
-            const qds::AxionArgs<T> ax = axion_args<T>(c, p0, st->buf[ia], st->buf[ib]);
+            const qds::AxionArgs<T> ax = axion_args<T>(c, p0, st->buf[ia], st->buf[ib], false);
             ev = c->timing ? timing_pair(c, 2) : nullptr;
             if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
             e = qds::axion_current_w<T>(ax, s);
@@ -77,8 +77,8 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     KTab<T> t;
     memset(&t, 0, sizeof(t));
     for (int q = 0; q < 2; ++q) {
-        t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q], 0, 0);
-        t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
+        t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q], 0, 0, true);
+        t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q], true);
     }
     const int strips = qds::fused_strips(c->g.nx);
     auto chunks = [&](int rows) { return (c->g.nr + 1 + rows - 1) / rows; };
@@ -137,7 +137,7 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
     if (e0 && hipEventRecord(e0[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t e;
     if (p0.axion) {
-        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, s);
+        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, !march_axion(c, p0, true), s);
     } else {
         // the background set alone: the kernel-B march with the kernel-A tile
         const int strips = qds::fused_strips(c->g.nx);
@@ -324,8 +324,8 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
         auto* hf = reinterpret_cast<qds::FusedArgs<T>*>(host.data());
         auto* hx = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + fb);
         for (int64_t k = 0; k < C; ++k) {
-            hf[k] = fused_args<T>(c, p, at_seg(k), at_seg(k + 1), 0, 0);
-            hx[k] = axion_args<T>(c, p, at_seg(k), at_seg(k + 1));
+            hf[k] = fused_args<T>(c, p, at_seg(k), at_seg(k + 1), 0, 0, true);
+            hx[k] = axion_args<T>(c, p, at_seg(k), at_seg(k + 1), true);
         }
         void* dtab = nullptr;
         QDS_TRY(hipMalloc(&dtab, fb + xb));
@@ -446,12 +446,13 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     c->rows = 16;
     c->trows[0] = c->trows[1] = c->trows[2] = 16;
     if (g.content & QDS_HAS_AREM) {
-        hipError_t e = hipMalloc(&c->scratch, 3 * c->plane_elems * c->elem_bytes);
+        // j_a,x, j_a,r, j_a,theta at the source points and the axion source S_a
+        hipError_t e = hipMalloc(&c->scratch, 4 * c->plane_elems * c->elem_bytes);
         if (e != hipSuccess) {
             delete c;
             return fail(nullptr, QDS_ENOMEM, "hipMalloc of the axion-current scratch failed: %s", hipGetErrorString(e));
         }
-        e = hipMemset(c->scratch, 0, 3 * c->plane_elems * c->elem_bytes);
+        e = hipMemset(c->scratch, 0, 4 * c->plane_elems * c->elem_bytes);
         if (e != hipSuccess) {
             (void)hipFree(c->scratch);
             delete c;

@@ -20,6 +20,7 @@ namespace {
 struct Launch {
     int slot;     // QDS_TILE_* slot (decides the kernel)
     int M;        // mode count of the class (kernel A and the axion current)
+    bool axt;     // kernel A: it advances the axion (instances without the regenerated set)
     int blocks;
     qds::BatchList L;
 };
@@ -88,10 +89,10 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
     if (!P) return bfail(b, QDS_ENOMEM, "out of host memory%s");
     P->active = active;
     P->tiles.assign(b->tiles, b->tiles + QDS_NTILES);
-    struct Pending { int slot, M; std::vector<int> idx, first; };
+    struct Pending { int slot, M; bool axt; std::vector<int> idx, first; };
     std::vector<Pending> pend;
-    auto add = [&](int slot, int M, auto pick, auto blocks_of) {
-        Pending q{slot, M, {}, {0}};
+    auto add = [&](int slot, int M, auto pick, auto blocks_of, bool axt = true) {
+        Pending q{slot, M, axt, {}, {0}};
         for (int k : active) {
             const qds_ctx* c = b->inst[k];
             if (!pick(c)) continue;
@@ -102,11 +103,15 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
     };
     auto has_ax = [](const qds_ctx* c) { return has(c, QDS_P_PHI); };
     auto has_arem = [](const qds_ctx* c) { return has(c, QDS_P_SET1); };
-    for (int M = 1; M <= 4; ++M) {
-        const int rows = b->tiles[QDS_TILE_A1 + M - 1];
-        add(QDS_TILE_A1 + M - 1, M, [&](const qds_ctx* c) { return has_ax(c) && c->M == M; },
-            [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows); });
-    }
+    // kernel A in two launches per mode count: instances with the regenerated
+    // set (the axion current advances their axion) and those without
+    for (int M = 1; M <= 4; ++M)
+        for (int axt = 0; axt < 2; ++axt) {
+            const int rows = b->tiles[QDS_TILE_A1 + M - 1];
+            add(QDS_TILE_A1 + M - 1, M,
+                [&](const qds_ctx* c) { return has_ax(c) && c->M == M && has_arem(c) == !axt; },
+                [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows); }, axt != 0);
+        }
     {
         const int rows = b->tiles[QDS_TILE_EM0];
         add(QDS_TILE_EM0, 0, [&](const qds_ctx* c) { return !has_ax(c); },
@@ -154,6 +159,7 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
         Launch l;
         l.slot = pend[q].slot;
         l.M = pend[q].M;
+        l.axt = pend[q].axt;
         l.blocks = pend[q].first.back();
         l.L.idx = base;
         l.L.first = base + pend[q].idx.size();
@@ -177,7 +183,7 @@ hipError_t launch_step(const qds_batch_ctx* b, const Plan& P, int parity, hipStr
         const Launch& l = P.launches[q];
         hipError_t e;
         if (ev && (e = hipEventRecord(ev[2 * q], s)) != hipSuccess) return e;
-        if (l.slot < QDS_TILE_CUR1) e = qds::batch_a<T>(fa, l.L, l.M, l.blocks, s);
+        if (l.slot < QDS_TILE_CUR1) e = qds::batch_a<T>(fa, l.L, l.M, l.blocks, l.axt, s);
         else if (l.slot < QDS_TILE_EM0) e = qds::batch_current<T>(xa, l.L, l.M, l.blocks, s);
         else e = qds::batch_em<T>(fa, l.L, l.slot == QDS_TILE_EM1 ? 1 : 0, l.blocks, s);
         if (e != hipSuccess) return e;
@@ -204,8 +210,8 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         for (int q = 0; q < 2; ++q) {
             void* A = states[k].buf[(states[k].cur + q) & 1];
             void* B = states[k].buf[(states[k].cur + q + 1) & 1];
-            qds::FusedArgs<T> f = fused_args<T>(c, p0, A, B, 0, 0);
-            qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B);
+            qds::FusedArgs<T> f = fused_args<T>(c, p0, A, B, 0, 0, true);
+            qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B, true);
             memcpy(&fa[q * N + k], &f, sizeof(f));
             memcpy(&xa[q * N + k], &x, sizeof(x));
         }
@@ -270,18 +276,25 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 }
             }
             if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, QDS_EHIP, "tuning run failed%s");
+            // per trial, the summed time of the launches of each slot
             float best[QDS_NTILES];
             int pick[QDS_NTILES];
             for (int q = 0; q < QDS_NTILES; ++q) { best[q] = 3.4e38f; pick[q] = -1; }
             size_t ei = 0;
             for (size_t tr = 0; tr < trial.size(); ++tr) {
                 const int cand = int(tr % 4);
+                float sum[QDS_NTILES];
+                bool seen[QDS_NTILES];
+                for (int q = 0; q < QDS_NTILES; ++q) { sum[q] = 0.f; seen[q] = false; }
                 for (const Launch& l : trial[tr]->launches) {
                     float ms = 0.f;
                     if (hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]) != hipSuccess) ms = 3.4e38f;
                     ei += 2;
-                    if (ms < best[l.slot]) { best[l.slot] = ms; pick[l.slot] = cand; }
+                    sum[l.slot] += ms;
+                    seen[l.slot] = true;
                 }
+                for (int q = 0; q < QDS_NTILES; ++q)
+                    if (seen[q] && sum[q] < best[q]) { best[q] = sum[q]; pick[q] = cand; }
             }
             for (int q = 0; q < QDS_NTILES; ++q) {
                 const int cand = pick[q] < 0 ? 2 : pick[q];

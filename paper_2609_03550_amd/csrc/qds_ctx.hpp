@@ -136,17 +136,30 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
         p.drive.amp = J->amp; p.drive.x0 = J->x0; p.drive.v = J->v; p.drive.sx = J->sx;
         p.drive.r0 = J->r0; p.drive.sr = J->sr; p.drive.noise = J->noise; p.drive.seed = J->seed;
     }
-    for (int k = 0; k < 3; ++k)
-        p.ja[k] = c->scratch ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) +
-                                                              size_t(k) * c->plane_elems * c->elem_bytes)
-                             : nullptr;
+    // scratch planes: j_a,x, j_a,r, j_a,theta, S_a
+    qds::cx<T>* sc[4];
+    for (int k = 0; k < 4; ++k)
+        sc[k] = c->scratch ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->scratch) +
+                                                           size_t(k) * c->plane_elems * c->elem_bytes)
+                           : nullptr;
+    for (int k = 0; k < 3; ++k) p.ja[k] = sc[k];
+    p.sa = sc[3];
     return p;
 }
 
+// Whether T_a and phi move from kernel A to the marched axion current.
+template <typename T>
+bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0, bool march) {
+    return march && p0.axion && p0.arem && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW && p0.sa != nullptr;
+}
+
 // Fused-kernel arguments of one step from buffer A (old) to buffer B (new).
+// march: the step runs the marched axion current, which then also advances
+// T_a and phi from the S_a that kernel A leaves in scratch (regenerated set,
+// no drive, no moving window).
 template <typename T>
 qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB, int64_t n,
-                             int64_t w) {
+                             int64_t w, bool march) {
     qds::FusedArgs<T> a;
     a.g = p0.g;
     a.plasma = p0.plasma;
@@ -157,6 +170,7 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     a.window = c->g.x_bc == QDS_X_WINDOW;
     a.rows = c->rows;
     a.jax = p0.ja[0]; a.jar = p0.ja[1]; a.jat = p0.ja[2];
+    a.sa = march_axion(c, p0, march) ? p0.sa : nullptr;
     qds::cx<T>* A[QDS_NPLANES];
     qds::cx<T>* B[QDS_NPLANES];
     plane_table<T>(c, bufA, A);
@@ -171,13 +185,15 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     return a;
 }
 
-// Axion-current arguments of the same step.
+// Axion-current arguments of the same step (march as for fused_args).
 template <typename T>
-qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB) {
+qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB, bool march) {
     qds::StepPlan<T> pl = p0;
     plane_table<T>(c, bufA, pl.A);
     plane_table<T>(c, bufB, pl.B);
-    return pl.axion_args();
+    qds::AxionArgs<T> x = pl.axion_args();
+    x.sa = march_axion(c, p0, march) ? p0.sa : nullptr;
+    return x;
 }
 
 inline qds_status check_state(qds_ctx* c, const qds_state* st) {

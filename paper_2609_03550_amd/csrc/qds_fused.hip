@@ -11,12 +11,14 @@
 // LDS between the waves of the workgroup.  Kernel B is the same march for one
 // set, one wave per (strip, chunk, mode).
 //
-// Kernel A advances the background set and the axion (source, Klein-Gordon
-// transport, phi); the axion current at the source points is formed by the
-// marched kernel of qds_current.hip (with a prescribed drive, by the tile
-// kernel k_axion_current_w of qds_stages.hip); kernel B advances the
-// regenerated set with it.  They compute exactly the quantities of the staged
-// kernels.
+// Kernel A advances the background set and forms the axion source S_a.  With
+// the regenerated set (and no drive or moving window) it leaves S_a in a
+// scratch plane and the marched kernel of qds_current.hip advances the axion
+// (Klein-Gordon transport, phi) together with the axion current at the
+// source points; otherwise kernel A advances the axion itself and, with a
+// drive, the tile kernel k_axion_current_w of qds_stages.hip forms the
+// current.  Kernel B advances the regenerated set with it.  They compute
+// exactly the quantities of the staged kernels.
 #include "qds_kernels.hpp"
 
 namespace qds {
@@ -484,7 +486,9 @@ constexpr int NS = 6;
 // ---------------------------------------------------------------------------
 // kernel A: background set + axion
 // ---------------------------------------------------------------------------
-template <typename T, int M, bool DRV>
+// AXT: kernel A advances the axion (T_a, phi); otherwise it writes S_a to a.sa
+// for the marched axion current, which advances the axion instead.
+template <typename T, int M, bool DRV, bool AXT>
 __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
     const Geo g = a.g;
     const int wave = threadIdx.x / WAVE;
@@ -558,10 +562,13 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         if (k == g.nr && g.open_r) return c.x.L(a.phi, m, g.nr);
         return zero<T>();
     };
+    constexpr bool axt = AXT;
     if (jstart >= 0) {
         em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);   // row jstart into slot 1
-        phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
-        if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
+        if (axt) {
+            phw[2] = (jstart < g.nr) ? c.x.L(a.phi, m, jstart) : zero<T>();
+            if (jstart - 1 >= 0) phw[1] = c.x.L(a.phi, m, jstart - 1);
+        }
     }
     // FP64 issues the axion transport loads of row j with the row's other
     // loads; FP32 loads them where they are used, to keep four waves per SIMD
@@ -573,11 +580,11 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         // ---------------- shift the window and load row j+1
         em_rotate(W);
         phw[0] = phw[1]; phw[1] = phw[2];
-        phw[2] = phi_row(j + 1);
+        if (axt) phw[2] = phi_row(j + 1);
         em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
         const EmRowX<T> X = em_fetch_x(c, s, j);
         cx<T> tap_a = zero<T>(), tam_a = zero<T>();
-        if (HOIST && j >= 0 && j < g.nr) {
+        if (HOIST && axt && j >= 0 && j < g.nr) {
             tap_a = c.x.L(a.tap, m, j);
             tam_a = c.x.L(a.tam, m, j);
         }
@@ -628,6 +635,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
             for (int k = 0; k < M; ++k) { A[k] = get(smS, 4, k); B[k] = get(smS, 5, k); }
             conv_one<T, M>(A, B, m, Sa, T(1));
             if (!c.live) Sa = zero<T>();
+            if (!axt) {
+                if (own_row && c.owner) sto(a.sa, eoff<T>(g, m, j, c.i), Sa);
+                continue;
+            }
             // ---------------- Gamma_a, T_a transport, phi (Eqs. Ta_plus/minus_update, phi_update)
             cx<T> p = phw[1];
             cx<T> up = phw[2];
@@ -676,15 +687,16 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     }
 }
 
-// Kernel A entry points: FP64 keeps the full register file (one wave per SIMD,
-// no spills); FP32 fits two waves per SIMD.
+// Kernel A entry points with arguments by value (the drive path: kernel A
+// advances the axion): FP64 keeps the full register file (no spills); FP32
+// fits two waves per SIMD.
 template <int M, bool DRV>
 __global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) {
-    fused_a_body<double, M, DRV>(a, blockIdx.x, blockIdx.y, a.rows);
+    fused_a_body<double, M, DRV, true>(a, blockIdx.x, blockIdx.y, a.rows);
 }
 template <int M, bool DRV>
 __global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
-k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M, DRV>(a, blockIdx.x, blockIdx.y, a.rows); }
+k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M, DRV, true>(a, blockIdx.x, blockIdx.y, a.rows); }
 
 // ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
@@ -770,7 +782,7 @@ __global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a) {
 // batched launches: block -> (instance, tile) through the launch's list; the
 // instance's arguments are read from a device table
 // ---------------------------------------------------------------------------
-template <typename T, int M>
+template <typename T, int M, bool AXT>
 __device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ args, const BatchList& L) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
@@ -780,16 +792,16 @@ __device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ ar
     // one radial chunk, which share the cache lines at their edges (measured 8%
     // faster for the FP64 step than radial chunks fastest)
     const int strips = fused_strips(a.g.nx);
-    fused_a_body<T, M, false>(a, local % strips, local / strips, L.rows);
+    fused_a_body<T, M, false, AXT>(a, local % strips, local / strips, L.rows);
 }
-template <int M>
+template <int M, bool AXT>
 __global__ void __launch_bounds__(WAVE * M) k_batch_a_f64(const FusedArgs<double>* __restrict__ args, BatchList L) {
-    batch_a_body<double, M>(args, L);
+    batch_a_body<double, M, AXT>(args, L);
 }
-template <int M>
+template <int M, bool AXT>
 __global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch_a_f32(const FusedArgs<float>* __restrict__ args, BatchList L) {
-    batch_a_body<float, M>(args, L);
+    batch_a_body<float, M, AXT>(args, L);
 }
 
 template <typename T, int WHICH>
@@ -808,6 +820,7 @@ __global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restric
 
 template <typename T, int M>
 static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
+    if (a.sa) return hipErrorInvalidValue;   // by value, kernel A advances the axion
     const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
     const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
     const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
@@ -846,23 +859,28 @@ hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
+template <typename T, bool AXT>
+static hipError_t batch_a_mode(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
     const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
     switch (M) {
-#define QDS_BA(MM)                                                                                               \
-    case MM:                                                                                                     \
-        if constexpr (sizeof(T) == 8)                                                                            \
-            hipLaunchKernelGGL((fused::k_batch_a_f64<MM>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
-        else                                                                                                     \
-            hipLaunchKernelGGL((fused::k_batch_a_f32<MM>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+#define QDS_BA(MM)                                                                                                      \
+    case MM:                                                                                                            \
+        if constexpr (sizeof(T) == 8)                                                                                   \
+            hipLaunchKernelGGL((fused::k_batch_a_f64<MM, AXT>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+        else                                                                                                            \
+            hipLaunchKernelGGL((fused::k_batch_a_f32<MM, AXT>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
         break;
         QDS_BA(1) QDS_BA(2) QDS_BA(3) QDS_BA(4)
 #undef QDS_BA
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, bool axt, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    return axt ? batch_a_mode<T, true>(args, L, M, blocks, s) : batch_a_mode<T, false>(args, L, M, blocks, s);
 }
 
 template <typename T>
@@ -875,8 +893,8 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
     return hipGetLastError();
 }
 
-template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
-template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, bool, hipStream_t);
+template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t fused_step<double>(const FusedArgs<double>&, hipStream_t, int);

@@ -61,6 +61,9 @@ struct AxionArgs {
     cx<T>* jax;                 // scratch: axion current at the source points
     cx<T>* jar;
     cx<T>* jat;
+    // scratch S_a (kernel A's output) when the marched current kernel also
+    // advances T_a and phi; null when kernel A does
+    const cx<T>* sa;
     double ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;        // uniform external field (B_x^(0), B_r^(1), B_theta^(1))
 };
@@ -73,6 +76,7 @@ struct StepPlan {
     cx<T>* A[21];
     cx<T>* B[21];
     cx<T>* ja[3];
+    cx<T>* sa;                  // scratch S_a plane (regenerated set only)
     int plasma, axion, arem;
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
@@ -107,6 +111,7 @@ struct StepPlan {
         x.phiA = A[18]; x.tapA = A[19]; x.tamA = A[20];
         x.phiB = B[18]; x.tapB = B[19]; x.tamB = B[20];
         x.jax = ja[0]; x.jar = ja[1]; x.jat = ja[2];
+        x.sa = nullptr;
         x.ma2 = ma2; x.s_phi = s_phi; x.s_j = s_j;
         x.bx0 = bx0; x.br1 = br1; x.bt1 = bt1;
         return x;
@@ -131,6 +136,9 @@ struct FusedArgs {
     const cx<T>* phi; const cx<T>* tap; const cx<T>* tam;
     cx<T>* ophi; cx<T>* otap; cx<T>* otam;
     cx<T>* jax; cx<T>* jar; cx<T>* jat;   // axion current scratch
+    // non-null: kernel A writes the axion source S_a here (unshifted columns,
+    // no moving window) and leaves T_a and phi to the axion-current march
+    cx<T>* sa;
     int plasma, axion;
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
@@ -178,13 +186,16 @@ template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s
 template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
 template <typename T> hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s);
 // Batched launches over many instances (argument tables in device memory).
+// axt: kernel A advances the axion (every instance of the list has sa null);
+// otherwise every instance has sa set and the axion current advances it.
 template <typename T>
-hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
+hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, bool axt, hipStream_t s);
 template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
 template <typename T>
 hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
-// Column strips of the marching axion-current kernel (63 owned columns each).
+// Column strips of the marching axion-current kernel (61 owned columns each,
+// as kernel A).
 int current_strips(int nx);
 // One transposed step.  march: the axion-current transpose marches in r
 // (needs planes below 4 GiB); otherwise one thread per cell with atomic adds.
