@@ -135,9 +135,9 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     JRow<T> jc = load_j(a, eoff<T>(g, m, r0, i));
     for (int j = r0; j < r1; ++j) {
         const bool calc = live && j < g.nr;
-        JRow<T> jn = j + 1 <= g.nr ? load_j(a, eoff<T>(g, m, j + 1, i)) : zero_j<T>();
         const cx<T> ph_up = phi_row(j + 1);
         const KRow<T> kc = j < g.nr ? krow(j, kp.ph0, ph_c, ph_up, true) : zero_k<T>();
+        JRow<T> jn = j + 1 <= g.nr ? load_j(a, eoff<T>(g, m, j + 1, i)) : zero_j<T>();
         const uint32_t o = eoff<T>(g, m, j, i);
         {
             // j_a,x into slots 0-5
