@@ -122,7 +122,8 @@ typedef struct qds_ctx* qds_handle;
  * Fails with QDS_ECFL unless |dt - dx| <= 4 ulp(dx) (exact one-cell shift,
  * Sec. 2.1) and dt^2 mu_max <= 4 for a Gershgorin bound mu_max of the radial
  * operators (the factorised dispersion relation of the scheme).  Allocates
- * the library's own scratch (axion-current planes) in device memory. */
+ * the library's own scratch in device memory: with the regenerated set, four
+ * planes (the three axion-current components and the axion source S_a). */
 qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out);
 
 /* Bytes of one state buffer, the row pitch in elements, and the byte offset

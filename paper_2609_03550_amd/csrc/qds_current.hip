@@ -196,7 +196,7 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
 }
 
 // three waves per SIMD (FP64 spills a few values to scratch for it: measured
-// 18% faster than two waves without spills; FP32 runs four)
+// 20% faster than two waves without spills; FP32 runs four)
 template <typename T, int M>
 __global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(3))) k_batch_current_march(const AxionArgs<T>* __restrict__ args, BatchList L) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
