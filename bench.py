@@ -265,8 +265,12 @@ def main():
     if args.tiles:
         for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), args.tiles.split(",")):
             s.set_option(opt, int(v))
-    elif args.rows is None and args.warmup >= 8:
-        s.set_option(qds.OPT_TUNE, 1)      # tile heights chosen on the first warm-up steps
+    elif args.rows is None:
+        # tile heights chosen by the library's autotuner on 8 untimed steps of
+        # the run, before the warm-up steps
+        s.set_option(qds.OPT_TUNE, 1)
+        s.step(8)
+        torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

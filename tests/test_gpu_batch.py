@@ -59,6 +59,31 @@ def test_batch_equals_one_at_a_time(dtype):
     assert [s.n for s in bs] == steps
 
 
+def test_mixed_content_batch_equals_one_at_a_time():
+    """Instances with and without the regenerated set (and one without the
+    axion) in one batch: kernel A runs in two launches per mode count, one
+    advancing the axion itself and one leaving it to the axion kernel; every
+    instance still advances exactly as it does alone."""
+    from paper_2609_03550_amd import qds
+    wls = _small(6, 17)
+    wls[1] = wls[1].with_(arem=False)
+    wls[4] = wls[4].with_(arem=False)
+    wls[2] = wls[2].with_(axion=False, arem=False)
+    assert any(w.arem for w in wls) and {w.nmodes for w in wls if not w.arem} & {w.nmodes for w in wls if w.arem}
+    bs = _solvers(wls, "f64")
+    solo = _twins(bs)
+    steps = [12, 9, 10, 8, 12, 9]
+    b = qds.Batch(bs)
+    b.run(steps, graph_steps=3, tune=True)     # the tuner's trials time both kernel-A launches
+    assert b.tiles()[1]
+    for s, n in zip(solo, steps):
+        s.step(n)
+    _identical(bs, solo)
+    for s, n in zip(bs, steps):
+        if not s.wl.arem:
+            P.compare_states(s.fields(), P.oracle_run(s.wl, n), *TOL["f64"])
+
+
 @pytest.mark.parametrize("graph_steps", [0, 1, 5])
 def test_graph_length_does_not_change_results(graph_steps):
     from paper_2609_03550_amd import qds
