@@ -73,3 +73,38 @@ def test_layout_queries_on_cpu(lib):
     st = qds.State()
     assert lib.qds_step(h, ctypes.byref(st), None, None, 1, None) == qds.QDS_ESTATE
     assert lib.qds_destroy(h) == qds.QDS_OK
+
+
+def test_path_selection_at_the_limits(lib):
+    """The fused kernels address a plane with 32-bit byte offsets and run up
+    to 4 modes: a plane of exactly 4 GiB, or 5 modes, selects the staged
+    kernels; one row pitch less, or 4 modes, the fused ones.  The largest
+    grid qds_init accepts (nx < 2^20, nr < 4096) and the smallest (nx = 8,
+    nr = 4) create handles; one beyond either is rejected.  (No device memory
+    is needed without the regenerated set.)"""
+    from paper_2609_03550_amd import qds
+
+    def handle(nx, nr, modes, dr=8.0):
+        h = ctypes.c_void_p()
+        g = qds.Grid(nx, nr, qds.F64, 0, 0, 0, dr)
+        st = lib.qds_init(ctypes.byref(g), modes, 0.25, 0.25, ctypes.byref(h))
+        return st, h
+
+    cases = [((65536, 4095, 1), 0),      # 4096 rows x 65536 x 16 B = 2^32 B
+             ((65504, 4095, 1), 1),      # one 32-column pitch less
+             ((1000, 50, 5), 0),
+             ((1000, 50, 4), 1),
+             ((8, 4, 1), 1)]
+    for (nx, nr, m), fused in cases:
+        st, h = handle(nx, nr, m)
+        assert st == qds.QDS_OK, (nx, nr, m)
+        assert lib.qds_row_pitch(h) == (nx + 31) // 32 * 32
+        assert lib.qds_uses_fused(h) == fused, (nx, nr, m)
+        assert lib.qds_destroy(h) == qds.QDS_OK
+    st, h = handle((1 << 20) - 1, 4095, 1)
+    assert st == qds.QDS_OK
+    assert lib.qds_uses_fused(h) == 0
+    assert lib.qds_destroy(h) == qds.QDS_OK
+    for nx, nr in ((1 << 20, 100), (100, 4096), (7, 10), (100, 3)):
+        st, h = handle(nx, nr, 1)
+        assert st == qds.QDS_EINVAL, (nx, nr)
