@@ -251,8 +251,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (every box has one MI355X); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the x-slab sharding is a "
+              "design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
