@@ -5,7 +5,9 @@
 // A lane holds column i of one mode; a half row K = j carries the per-point
 // combinations of the old (A) and new (B) background set, axion and T_a that
 // the factors read, an integer row J = j those of T_theta and E_x.  Values of
-// column i+1 come from the next lane.
+// column i+1 come from the next lane.  The adjoint loads a K row with load_k
+// (the new axion values from the recomputed state); the forward march forms
+// the new T_a and phi of the row itself.
 #pragma once
 #include "qds_kernels.hpp"
 
