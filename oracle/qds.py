@@ -22,6 +22,15 @@ the last column (i = nx-1) lies outside the domain and is kept at zero.
 Row nr of the K arrays is the exterior ghost row r_{nr+1/2} used by the outer
 radial boundary.
 
+Pins (tests/test_oracle_pins.py) hold it to what the paper and the mathematics
+fix: dispersion relations, waveguide spectra, exact one-cell transport, the
+theta-product form of the mode convolutions, photon-axion conversion, plasma
+oscillation, outgoing waves leaving through the open outer boundary, and
+more.  Parity unpinned (checked only against the GPU path): the curvature and
+transverse terms of the outer radial ghost updates beyond that absorption
+test, the interpolation of j_a to its source points and its axis limits, and
+the drive's noise model beyond the generator outputs.
+
 State keys (s = 0 background set, s = 1 axion-regenerated set):
   Trp{s} Trm{s} [M,nr,nx]   Ttp{s} Ttm{s} [M,nr+1,nx]   Ex{s} [M,nr+1,nx]
   Bx{s} [M,nr+1,nx] (row nr = ghost)   Bg{s} [M,nx] ghost B_theta at r_{nr+1/2}

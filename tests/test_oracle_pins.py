@@ -383,6 +383,86 @@ def test_axion_outer_boundary_mur_stable_three_level_not():
     assert np.abs(lam3).max() > 1.01
 
 
+def _outgoing_shell(kind, r_bc, nsteps, nr=60, r0=25.0, sig=3.0):
+    """Energy (relative to the start) after 80 and after ``nsteps`` steps of
+    a radially outgoing mode-0 shell, uniform in x (periodic x, k_x = 0).
+    The profile is f(r - t) / sqrt(r), f a Mexican-hat pulse of width sig
+    cells centred r0 cells out (zero mean, so the 2-D wake behind the shell is
+    negligible).  Outgoing means, for the TM wave (E_x, B_theta)
+    B_theta = -E_x, for the TE wave (B_x, E_theta) E_theta = B_x, for the
+    axion d_t phi = -f'(r - t) / sqrt(r); each field at its own position and
+    time level of the staggered grid."""
+    g = Q.Grid(8, nr, 1, H, DR, "periodic", r_bc)
+    ph = Q.Physics(axion=(kind == "axion"))
+    st = Q.zero_state(g, ph)
+    rK = DR * (torch.arange(nr, dtype=torch.float64) + 0.5)
+    rJ = DR * torch.arange(nr + 1, dtype=torch.float64)
+    rJs = rJ.clone()
+    rJs[0] = 1.0
+
+    def f(r):
+        u = (r / DR - r0) / sig
+        return (1 - u * u) * torch.exp(-0.5 * u * u)
+
+    def df(r):   # d f / d r
+        u = (r / DR - r0) / sig
+        return (u * u * u - 3 * u) * torch.exp(-0.5 * u * u) / (sig * DR)
+
+    def col(v, n):
+        return v.view(-1, 1).to(torch.complex128).expand(n, 8).clone()
+
+    if kind == "tm":        # E_x on J rows at t^{-1/2}, B_theta on K rows at t^0
+        ex = f(rJ + 0.5 * H) / rJs.sqrt()
+        ex[0] = 0.0
+        bt = -f(rK) / rK.sqrt()
+        st["Ex0"][0], st["Trp0"][0], st["Trm0"][0] = col(ex, nr + 1), col(bt, nr), col(-bt, nr)
+    elif kind == "te":      # B_x on K rows at t^{-1/2}, E_theta on J rows at t^0
+        et = f(rJ) / rJs.sqrt()
+        et[0] = 0.0
+        bx = torch.zeros(nr + 1, dtype=torch.float64)
+        bx[:nr] = f(rK + 0.5 * H) / rK.sqrt()
+        st["Bx0"][0], st["Ttp0"][0], st["Ttm0"][0] = col(bx, nr + 1), col(et, nr + 1), col(et, nr + 1)
+    else:                   # phi^0 on K rows, T_a^+- = d_t phi at t^{-1/2}
+        st["phi"][0] = col(f(rK) / rK.sqrt(), nr)
+        st["Tap"][0] = col(-df(rK + 0.5 * H) / rK.sqrt(), nr)
+        st["Tam"][0] = st["Tap"][0].clone()
+
+    def energy(s):
+        wK, wJ = rK.view(-1, 1), rJ.view(-1, 1)
+        if kind == "tm":
+            b = 0.5 * (s["Trp0"][0] - s["Trm0"][0])
+            return float((wK * b.abs() ** 2).sum() + (wJ * s["Ex0"][0].abs() ** 2).sum())
+        if kind == "te":
+            e = 0.5 * (s["Ttp0"][0] + s["Ttm0"][0])
+            return float((wK * s["Bx0"][0, :nr].abs() ** 2).sum() + (wJ * e.abs() ** 2).sum())
+        # (d_t phi)^2 + (d_x phi)^2 from T_a^+-, (d_r phi)^2 between half rows
+        kin = (wK * 0.5 * (s["Tap"][0].abs() ** 2 + s["Tam"][0].abs() ** 2)).sum()
+        grad = (wJ[1:nr] * ((s["phi"][0, 1:] - s["phi"][0, :-1]) / DR).abs() ** 2).sum()
+        return float(kin + grad)
+
+    e0 = energy(st)
+    st = Q.run(st, g, ph, 80)
+    e80 = energy(st)
+    st = Q.run(st, g, ph, nsteps - 80)
+    return e80 / e0, energy(st) / e0
+
+
+@pytest.mark.parametrize("kind", ["tm", "te", "axion"])
+def test_outer_boundary_lets_outgoing_waves_leave(kind):
+    """The outer radial boundary conditions (the exterior B_theta and B_x
+    ghosts of the field sets, the outgoing-wave ghost of phi) let a radially
+    outgoing mode-0 shell leave the domain: 240 steps after it started 35
+    cells inside r_max, under 1% of its energy is left (a wrong sign or
+    coefficient in a ghost update reflects or amplifies it), while the
+    conducting wall (Dirichlet ghost) keeps all of it."""
+    before, left = _outgoing_shell(kind, "open", 240)
+    assert abs(before - 1.0) < 0.01          # the shell is outgoing and has not reached r_max yet
+    assert left < 0.01, left
+    before, kept = _outgoing_shell(kind, "pec", 240)
+    assert abs(before - 1.0) < 0.01
+    assert kept > 0.9, kept
+
+
 # ---------------------------------------------------------------------------
 # moving window, counter-based noise
 # ---------------------------------------------------------------------------
