@@ -300,6 +300,39 @@ def test_photon_axion_conversion_in_static_field():
     assert abs(ratio / textbook - 1) < (kh * kh) / 4 * 1.1
 
 
+def test_axion_photon_regeneration_in_static_field():
+    """The reverse conversion, which runs through the axion current j_a (Eqs.
+    jax_mode, jar_mode, jat_mode) and the regenerated set: a mode-0 axion
+    pulse moving along +x (T_a^- = 0) in the uniform transverse field B0,
+    m_a = 0, vacuum, regenerates photons with U_gamma1 / U_a = (B0 L / 2)^2
+    (scaled units; the textbook result for the current g(B0 d_t phi) of the
+    axion-modified Ampere law).  j_a is formed at the source points from the
+    two-point x mean of d_t phi, which for a wave of wavenumber k is cos(k h/2)
+    of the point value."""
+    B0, a, k = 1.0, 0.01, 1.0
+    g = Q.Grid(320, 176, 2, H, DR, "open", "open")
+    ph = Q.Physics(axion=True, arem=True, ma2=0.0, bext=(0j, complex(B0), complex(-1j * B0)))
+    st = Q.zero_state(g, ph)
+    w0, x0 = 20 * I.LAMBDA, 100 * H
+    tau = 40 * H / (2 * math.sqrt(2 * math.log(2)))
+    s = (torch.arange(g.nx, dtype=torch.float64) + 0.5) * H - x0        # x_{i+1/2} - x0
+    env = torch.exp(-s ** 2 / (2 * tau ** 2))
+    F = a * env * torch.cos(k * s)                                       # phi(x, t) = F(x - t) A(r)
+    dF = a * env * (-k * torch.sin(k * s) - s / tau ** 2 * torch.cos(k * s))
+    A = torch.exp(-(((torch.arange(g.nr, dtype=torch.float64) + 0.5) * DR) / w0) ** 2).view(-1, 1)
+    F[-1] = 0.0                                                          # the dead last cell
+    st["phi"][0] = (A * F.view(1, -1)).to(torch.complex128)
+    # T_a^+ = d_t phi - d_x phi = -2 F' at (x_i, t^{-1/2}), i.e. at x - t = x_{i+1/2}
+    st["Tap"][0] = (A * (-2 * dF).view(1, -1)).to(torch.complex128)
+    n = 80
+    st = Q.run(st, g, ph, n)
+    ratio = T.em_energy(st, g, 1) / T.axion_energy(st, g)
+    textbook = (B0 * n * g.h / 2) ** 2
+    kh = k * g.h
+    assert abs(ratio / (textbook * math.cos(kh / 2) ** 2) - 1) < 0.005
+    assert abs(ratio / textbook - 1) < (kh * kh) / 4 * 1.1
+
+
 # ---------------------------------------------------------------------------
 # plasma response, coupling scale, realness, stability
 # ---------------------------------------------------------------------------
