@@ -26,11 +26,10 @@ Pins (tests/test_oracle_pins.py) hold it to what the paper and the mathematics
 fix: dispersion relations, waveguide spectra, exact one-cell transport, the
 theta-product form of the mode convolutions, photon-axion conversion, plasma
 oscillation, axion-photon regeneration through j_a, outgoing waves leaving
-through the open outer boundary, and more.  Parity unpinned (checked only
+through the open outer boundary, white lab-frame drive noise, and more.  Parity unpinned (checked only
 against the GPU path): the curvature and transverse terms of the outer radial
 ghost updates beyond that absorption test, the interpolation of j_a to its
-source points and its axis limits beyond the static-field regeneration test,
-and the drive's noise model beyond the generator outputs.
+source points and its axis limits beyond the static-field regeneration test.
 
 State keys (s = 0 background set, s = 1 axion-regenerated set):
   Trp{s} Trm{s} [M,nr,nx]   Ttp{s} Ttm{s} [M,nr+1,nx]   Ex{s} [M,nr+1,nx]

@@ -536,6 +536,51 @@ def test_box_muller_normals_have_unit_variance():
     assert abs((z ** 4).mean() - 3) < 5e-2
 
 
+def test_drive_noise_is_white_and_attached_to_the_lab_frame():
+    """The prescribed drive is amp g(x - x0 - vt) g(r - r0) (1 + eps xi): the
+    relative deviation of the drive from the noiseless ring, divided by eps,
+    is a standard normal per (step, lab column, row), uncorrelated between
+    neighbouring columns, rows and steps (a packing of the counter that let
+    two cells share a draw would correlate them), and a function of the lab
+    column, so a cell keeps its draw when the window moves."""
+    d = I.Drive(amp=2.0, x0=60 * H, v=0.999, sx=300 * H, r0=0.0, sr=400 * DR, noise=1e-3, seed=2)
+    g = Q.Grid(256, 200, 1, H, DR, "window", "open")
+    c = Q._Ctx(g)
+    ph0 = Q.Physics(drive=d.__class__(d.amp, d.x0, d.v, d.sx, d.r0, d.sr, 0.0, d.seed))
+    xs = []
+    for n in range(4):
+        w = 10 + n                                           # the window moves one cell per step
+        noisy = Q.drive_jx(c, d, n, w)[0].real
+        ring = Q.drive_jx(c, ph0.drive, n, w)[0].real
+        live = ring > 1e-3 * d.amp
+        xi = torch.where(live, (noisy / torch.where(live, ring, 1.0) - 1.0) / d.noise, torch.nan)
+        xs.append(xi)
+    z = torch.stack(xs)                                      # [step, row, cell]
+    ok = ~torch.isnan(z)
+    v = z[ok]
+    assert v.numel() > 150000
+    assert abs(float(v.mean())) < 0.01 and abs(float(v.var()) - 1.0) < 0.02
+
+    def corr(a, b):
+        m = ~torch.isnan(a) & ~torch.isnan(b)
+        a, b = a[m] - a[m].mean(), b[m] - b[m].mean()
+        return float((a * b).mean() / (a.std() * b.std()))
+
+    for a, b in ((z[:, :, 1:], z[:, :, :-1]), (z[:, 1:], z[:, :-1]), (z[1:], z[:-1])):
+        assert abs(corr(a, b)) < 0.02
+    # lab frame: cell i at step n (window w) and cell i - 1 at the same step
+    # with the window one cell further draw the same variate
+    a = R.normal_field(d.seed, 3, 256, 200, 40)
+    b = R.normal_field(d.seed, 3, 256, 200, 41)
+    assert torch.equal(a[:, 1:], b[:, :-1])
+    # the counter is one-to-one over the rows and lab columns qds_init accepts
+    rows = np.array([0, 1, 4095], dtype=np.uint64)
+    cols = np.array([0, 1, (1 << 20) - 1], dtype=np.uint64)
+    ctr = R.counter(7, cols[:, None], rows[None, :]).ravel()
+    assert len(set(ctr.tolist())) == ctr.size
+    assert R.counter(7, np.uint64(0), np.uint64(0)) != R.counter(8, np.uint64(0), np.uint64(0))
+
+
 # ---------------------------------------------------------------------------
 # the oracle's gradient (reference of the GPU adjoint)
 # ---------------------------------------------------------------------------
