@@ -201,7 +201,8 @@ def test_per_kernel_tile_heights_change_no_result():
 @pytest.mark.parametrize("dtype,x_bc,r_bc,arem,M", [("f64", "open", "open", True, 3), ("f64", "periodic", "pec", True, 3),
                                                     ("f32", "open", "open", True, 3), ("f64", "window", "open", False, 3),
                                                     ("f64", "window", "pec", True, 3), ("f64", "open", "open", True, 1),
-                                                    ("f64", "open", "open", True, 4), ("f64", "open", "pec", True, 5)])
+                                                    ("f64", "open", "open", True, 4), ("f64", "open", "pec", True, 5),
+                                                    ("f64", "periodic", "open", False, 2)])
 def test_random_full_state(dtype, x_bc, r_bc, arem, M):
     """Every plane of both sets, the plasma currents and the axion start at
     O(1) seeded random values (so every term of the step, the couplings
