@@ -26,28 +26,29 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 def plane_accesses(wl, kernel):
     """Complex planes read + written per cell-mode by one launch of each fused
-    kernel (their algorithmic bytes).  With the regenerated set (no drive, no
-    moving window) the axion advance runs in the axion-current kernel:
+    kernel (their algorithmic bytes).  With the regenerated set the axion
+    advance runs in the axion-current kernel:
       kernel 0 (A): reads and writes the background set (T_r^+-, T_theta^+-,
         E_x, B_x and, with plasma, j_x, j_r, j_theta), writes S_a;
       kernel 1 (B): reads and writes the regenerated set, reads the axion current;
       kernel 2 (axion current): reads T^n and T^{n+1} of the background set
         (4 + 4), B_x at t^{n-1/2} and t^{n+1/2}, E_x at t^{n+1/2}, T_a^{n-1/2}
         (2), phi^n and S_a; writes T_a^{n+1/2} (2), phi^{n+1} and j_a (3).
-    Otherwise kernel A also reads and writes the axion (phi, T_a^+-) and the
-    axion current (drive path) reads T_a and phi at both times (20 planes).
-    Electromagnetic-only: kernel 0 reads and writes the 6 (or 9) planes."""
+    Without it kernel A also reads and writes the axion (phi, T_a^+-).
+    Electromagnetic-only: kernel 0 reads and writes the 6 (or 9) planes, and
+    with a prescribed drive reads its j_x^(0) plane for mode 0 (1/M of a plane
+    per cell-mode; the drive kernel that writes it is not counted)."""
     em = 6 + (3 if wl.wp2 else 0)
     if not wl.axion:
-        return 2 * em if kernel == 0 else 0
-    march = wl.arem and wl.drive is None and wl.x_bc != "window"
+        if kernel != 0:
+            return 0
+        return 2 * em + (1.0 / wl.nmodes if wl.drive is not None else 0.0)
+    drv = 1.0 / wl.nmodes if wl.drive is not None else 0.0
     if kernel == 0:
-        return 2 * em + 1 if march else 2 * (em + 3)
+        return (2 * em + 1 if wl.arem else 2 * (em + 3)) + drv
     if kernel == 1:
         return (2 * em + 3) if wl.arem else 0
-    if not wl.arem:
-        return 0
-    return 21 if march else 20
+    return 21 if wl.arem else 0
 
 
 KERNEL_NAMES = {0: "kernel A (background set, axion source)", 1: "kernel B (regenerated set)",

@@ -153,7 +153,8 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 regenerated set), e.g. to replay heights the tuner chose
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
  *                 times its first 8 steps (two passes over four tile heights
- *                 per kernel: 8, 16, 24, 32 for the background set, 4, 6, 8,
+ *                 per kernel: 8, 16, 24, 32 for the background set with the
+ *                 axion, 8, 16, 26, 52 for the background set alone, 4, 6, 8,
  *                 16 for the axion current, 16, 32, 52, 64 for the regenerated
  *                 set; HIP events around every launch) and keeps the fastest
  *                 height for each kernel; the trial steps are ordinary

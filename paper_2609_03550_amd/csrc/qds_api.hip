@@ -13,37 +13,16 @@ using namespace qdsi;
 
 namespace {
 
-// Fused steps with a prescribed drive: argument blocks passed by value (the
-// step counter and window offset change every step).
-template <typename T>
-qds_status fused_steps_drive(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s) {
-    for (int64_t it = 0; it < n_steps; ++it) {
-        const int ia = st->cur, ib = 1 - st->cur;
-        const qds::FusedArgs<T> a = fused_args<T>(c, p0, st->buf[ia], st->buf[ib], st->step, st->window, false);
-        hipEvent_t* ev = c->timing ? timing_pair(c, 0) : nullptr;
-        if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        hipError_t e = qds::fused_step<T>(a, s, 0);
-        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        if (p0.arem) {
-            const qds::AxionArgs<T> ax = axion_args<T>(c, p0, st->buf[ia], st->buf[ib], false);
-            ev = c->timing ? timing_pair(c, 2) : nullptr;
-            if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-            e = qds::axion_current_w<T>(ax, s);
-            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-            ev = c->timing ? timing_pair(c, 1) : nullptr;
-            if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-            e = qds::fused_step<T>(a, s, 1);
-            if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        }
-        st->cur = ib;
-        if (a.window) st->window += 1;
-        st->step += 1;
-    }
-    return QDS_OK;
-}
+// Tile-height candidates of the autotuner (two passes over four per kernel
+// class): kernel A (the background set with the axion), the marched axion
+// kernel, kernel B (the regenerated set), and the background set alone, whose
+// one-wave tiles want tall chunks on large grids (26 rows fill the GPU once at
+// 4096 x 256 x 3) and short ones on small grids.
+const int kCandA[4] = {8, 16, 24, 32};
+const int kCandCur[4] = {4, 6, 8, 16};
+const int kCandB[4] = {16, 32, 52, 64};
+const int kCandEm[4] = {8, 16, 26, 52};
+constexpr int kTrials = 8;
 
 // Makes the device argument table current for the state buffers of st
 // (uploaded on the stream only when it changed).
@@ -58,6 +37,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     key[6] = double(p0.bx0.re); key[7] = double(p0.bx0.im); key[8] = double(p0.br1.re); key[9] = double(p0.br1.im);
     key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im);
     key[12] = double(c->trows[0]); key[13] = double(c->trows[1]); key[14] = double(c->trows[2]);
+    key[15] = double(p0.drive.on);
     if (!c->ktab_dev) {
         c->ktab_bytes = sizeof(KTab<double>);
         if (hipMalloc(&c->ktab_dev, c->ktab_bytes) != hipSuccess) {
@@ -77,8 +57,8 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     KTab<T> t;
     memset(&t, 0, sizeof(t));
     for (int q = 0; q < 2; ++q) {
-        t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q], 0, 0, true);
-        t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q], true);
+        t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
+        t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
     }
     const int strips = qds::fused_strips(c->g.nx);
     auto chunks = [&](int rows) { return (c->g.nr + 1 + rows - 1) / rows; };
@@ -137,7 +117,7 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
     if (e0 && hipEventRecord(e0[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t e;
     if (p0.axion) {
-        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, !march_axion(c, p0, true), s);
+        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, !march_axion(c, p0), s);
     } else {
         // the background set alone: the kernel-B march with the kernel-A tile
         const int strips = qds::fused_strips(c->g.nx);
@@ -163,6 +143,11 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
 template <typename T>
 qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
                       hipStream_t s, hipEvent_t* ev) {
+    if (p0.drive.on) {
+        // this step's j_x^(0), read by the background set as its extra j_x
+        const hipError_t e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, st->step, st->window, s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    }
     const qds_status r = table_launch<T>(c, p0, ktab_view<T>(K, host, st->cur), s, ev);
     if (r != QDS_OK) return r;
     st->cur = 1 - st->cur;
@@ -172,19 +157,23 @@ qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTa
 }
 
 template <typename T>
-qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, int64_t n_steps, hipStream_t s,
-                       bool by_value) {
-    if (p0.drive.on || by_value) return fused_steps_drive<T>(c, st, p0, n_steps, s);
+qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, int64_t n_steps, hipStream_t s) {
     KTab<T>* K;
     qds_status r;
     int64_t done = 0;
-    constexpr int kTrials = 8;
+    qds::StepPlan<T> p0 = p1;
+    if (p0.drive.on && !c->drive_plane) {
+        // the drive plane (mode 0 of one plane), allocated on first use
+        if (hipMalloc(&c->drive_plane, size_t(c->g.nr + 1) * size_t(c->ld) * c->elem_bytes) != hipSuccess) {
+            c->drive_plane = nullptr;
+            return fail(c, QDS_ENOMEM, "hipMalloc of the drive plane failed%s");
+        }
+    }
+    p0.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
     if (c->tune && n_steps >= kTrials) {
         // autotuner: timed ordinary steps, two passes over four tile heights per
         // kernel (candidates around each kernel's measured optimum)
-        static const int cand[3][4] = {{8, 16, 24, 32},    // kernel A
-                                       {4, 6, 8, 16},      // axion current
-                                       {16, 32, 52, 64}};  // kernel B
+        const int* cand[3] = {p0.axion ? kCandA : kCandEm, kCandCur, kCandB};
         std::vector<hipEvent_t> ev(6 * kTrials);
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
@@ -220,9 +209,9 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, in
 
 template <typename T>
 qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
-                     hipStream_t s, bool by_value = false) {
+                     hipStream_t s) {
     qds::StepPlan<T> p = make_plan<T>(c, J, ax);
-    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s, by_value);
+    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
         int a = st->cur, b = 1 - st->cur;
@@ -324,8 +313,8 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
         auto* hf = reinterpret_cast<qds::FusedArgs<T>*>(host.data());
         auto* hx = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + fb);
         for (int64_t k = 0; k < C; ++k) {
-            hf[k] = fused_args<T>(c, p, at_seg(k), at_seg(k + 1), 0, 0, true);
-            hx[k] = axion_args<T>(c, p, at_seg(k), at_seg(k + 1), true);
+            hf[k] = fused_args<T>(c, p, at_seg(k), at_seg(k + 1));
+            hx[k] = axion_args<T>(c, p, at_seg(k), at_seg(k + 1));
         }
         void* dtab = nullptr;
         QDS_TRY(hipMalloc(&dtab, fb + xb));
@@ -363,7 +352,7 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
             R.cur = 0;
             R.step = u0->step + n0 + k;
             R.window = 0;
-            qds_status st = run_steps<T>(c, &R, J, ax, 1, s, true);
+            qds_status st = run_steps<T>(c, &R, J, ax, 1, s);
             if (st != QDS_OK) return st;
         }
         for (int64_t k = n1 - n0 - 1; k >= 0; --k) {
@@ -654,6 +643,7 @@ qds_status qds_destroy(qds_handle h) {
     if (!h) return QDS_OK;
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->drive_plane) (void)hipFree(h->drive_plane);
     if (h->ktab_ev) {
         (void)hipEventSynchronize(h->ktab_ev);
         (void)hipEventDestroy(h->ktab_ev);

@@ -210,8 +210,8 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         for (int q = 0; q < 2; ++q) {
             void* A = states[k].buf[(states[k].cur + q) & 1];
             void* B = states[k].buf[(states[k].cur + q + 1) & 1];
-            qds::FusedArgs<T> f = fused_args<T>(c, p0, A, B, 0, 0, true);
-            qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B, true);
+            qds::FusedArgs<T> f = fused_args<T>(c, p0, A, B);
+            qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B);
             memcpy(&fa[q * N + k], &f, sizeof(f));
             memcpy(&xa[q * N + k], &x, sizeof(x));
         }

@@ -16,9 +16,10 @@ struct qds_ctx {
     size_t elem_bytes;       // 16 (F64) or 8 (F32)
     int slot[QDS_NPLANES];   // plane -> position in the buffer, -1 if absent
     int nplanes;
-    void* scratch;           // axion-current planes (3), library owned
+    void* scratch;           // axion-current planes (3) and S_a, library owned
+    void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0 (allocated on first use)
     int path;                // QDS_PATH_*
-    int rows;                // radial rows per workgroup of the by-value fused kernels
+    int rows;                // the last QDS_OPT_ROWS value (also copied into trows)
     int trows[3];            // tile heights of the table-driven kernels: A, current, B
     int tune;                // autotune the tile heights on the next long enough qds_step
     int tuned;
@@ -113,6 +114,7 @@ qds::SetP<T> fused_set(qds::cx<T>* const* A, qds::cx<T>* const* B, int s) {
     p.otrp = B[b + 0]; p.otrm = B[b + 1]; p.ottp = B[b + 2]; p.ottm = B[b + 3];
     p.oex = B[b + 4]; p.obx = B[b + 5]; p.ojx = B[b + 6]; p.ojr = B[b + 7]; p.ojt = B[b + 8];
     p.jxa = p.jra = p.jta = nullptr;
+    p.jxa_m0 = 0;
     return p;
 }
 
@@ -144,33 +146,32 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
                            : nullptr;
     for (int k = 0; k < 3; ++k) p.ja[k] = sc[k];
     p.sa = sc[3];
+    p.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
     return p;
 }
 
-// Whether T_a and phi move from kernel A to the marched axion current.
+// Whether T_a and phi move from kernel A to the marched axion current, which
+// then advances them from the S_a that kernel A leaves in scratch (with the
+// regenerated set; the fused kernels do not take it with the moving window).
 template <typename T>
-bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0, bool march) {
-    return march && p0.axion && p0.arem && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW && p0.sa != nullptr;
+bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0) {
+    return p0.axion && p0.arem && c->g.x_bc != QDS_X_WINDOW && p0.sa != nullptr;
 }
 
 // Fused-kernel arguments of one step from buffer A (old) to buffer B (new).
-// march: the step runs the marched axion current, which then also advances
-// T_a and phi from the S_a that kernel A leaves in scratch (regenerated set,
-// no drive, no moving window).
+// With a prescribed drive the background set reads the drive plane, which
+// holds j_x^(0) of the step, as its extra j_x of mode 0.
 template <typename T>
-qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB, int64_t n,
-                             int64_t w, bool march) {
-    qds::FusedArgs<T> a;
+qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB) {
+    qds::FusedArgs<T> a{};
     a.g = p0.g;
     a.plasma = p0.plasma;
     a.axion = p0.axion;
     a.wp2 = p0.wp2; a.ma2 = p0.ma2; a.s_phi = p0.s_phi; a.s_j = p0.s_j;
     a.bx0 = p0.bx0; a.br1 = p0.br1; a.bt1 = p0.bt1;
-    a.drive = p0.drive;
     a.window = c->g.x_bc == QDS_X_WINDOW;
-    a.rows = c->rows;
     a.jax = p0.ja[0]; a.jar = p0.ja[1]; a.jat = p0.ja[2];
-    a.sa = march_axion(c, p0, march) ? p0.sa : nullptr;
+    a.sa = march_axion(c, p0) ? p0.sa : nullptr;
     qds::cx<T>* A[QDS_NPLANES];
     qds::cx<T>* B[QDS_NPLANES];
     plane_table<T>(c, bufA, A);
@@ -178,21 +179,23 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     a.s0 = fused_set<T>(A, B, 0);
     a.s1 = fused_set<T>(A, B, 1);
     a.s1.jxa = a.jax; a.s1.jra = a.jar; a.s1.jta = a.jat;
+    if (p0.drive.on) {
+        a.s0.jxa = p0.jdrv;
+        a.s0.jxa_m0 = 1;
+    }
     a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
     a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
-    a.n = n;
-    a.w = w;
     return a;
 }
 
-// Axion-current arguments of the same step (march as for fused_args).
+// Axion-current arguments of the same step.
 template <typename T>
-qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB, bool march) {
+qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB) {
     qds::StepPlan<T> pl = p0;
     plane_table<T>(c, bufA, pl.A);
     plane_table<T>(c, bufB, pl.B);
     qds::AxionArgs<T> x = pl.axion_args();
-    x.sa = march_axion(c, p0, march) ? p0.sa : nullptr;
+    x.sa = march_axion(c, p0) ? p0.sa : nullptr;
     return x;
 }
 

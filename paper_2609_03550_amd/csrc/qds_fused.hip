@@ -12,13 +12,14 @@
 // set, one wave per (strip, chunk, mode).
 //
 // Kernel A advances the background set and forms the axion source S_a.  With
-// the regenerated set (and no drive or moving window) it leaves S_a in a
-// scratch plane and the marched kernel of qds_current.hip advances the axion
-// (Klein-Gordon transport, phi) together with the axion current at the
-// source points; otherwise kernel A advances the axion itself and, with a
-// drive, the tile kernel k_axion_current_w of qds_stages.hip forms the
-// current.  Kernel B advances the regenerated set with it.  They compute
-// exactly the quantities of the staged kernels.
+// the regenerated set (and no moving window) it leaves S_a in a scratch plane
+// and the marched kernel of qds_current.hip advances the axion (Klein-Gordon
+// transport, phi) together with the axion current at the source points;
+// otherwise kernel A advances the axion itself.  Kernel B advances the
+// regenerated set with the axion current.  A prescribed drive is evaluated
+// per step into a plane of its own (k_drive_plane) that the background set
+// reads as an extra j_x of mode 0.  They compute exactly the quantities of
+// the staged kernels.
 #include "qds_kernels.hpp"
 
 namespace qds {
@@ -77,8 +78,15 @@ __device__ __forceinline__ cx<T> shfl_dn1(cx<T> v) {
     return cx<T>{__shfl_down(v.re, 1, WAVE), __shfl_down(v.im, 1, WAVE)};
 }
 
-// prescribed j_x^(0) at (x_{i+1/2}, r_j, t^n), lab column i + w
-__device__ __forceinline__ double drive_jx_f(const Drive& d, const Geo& g, int i, int j, int64_t n, int64_t w) {
+// Prescribed j_x^(0) of step n at (x_{i+1/2}, r_j, t^n), lab column i + w,
+// into the mode-0 rows of out (row pitch g.ld): one thread per point, so the
+// marching kernels, which read it as an extra current, carry none of its
+// exponentials and normal variates in their registers.
+template <typename T>
+__global__ void __launch_bounds__(256) k_drive_plane(Drive d, Geo g, cx<T>* out, int64_t n, int64_t w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= g.nx || j > g.nr) return;
     const double x = (double(i) + 0.5 + double(w)) * g.h;
     const double t = double(n) * g.h;
     const double r = double(j) * g.dr;
@@ -87,7 +95,8 @@ __device__ __forceinline__ double drive_jx_f(const Drive& d, const Geo& g, int i
     const double gx = exp(-ax * ax / (2.0 * d.sx * d.sx));
     const double gr = exp(-ar * ar / (2.0 * d.sr * d.sr));
     const uint64_t c = (uint64_t(n) << 32) | (uint64_t(int64_t(i) + w) << 12) | uint64_t(j);
-    return d.amp * gr * gx * (1.0 + d.noise * normal_ctr(d.seed, c));
+    const double v = d.amp * gr * gx * (1.0 + d.noise * normal_ctr(d.seed, c));
+    st(out + size_t(j) * size_t(g.ld) + size_t(i), cx<T>{T(v), T(0)});
 }
 
 // Output addressing: with the moving window every write lands one column to
@@ -145,8 +154,6 @@ struct Ctx {
     T inv_2h;            // 1/(2 h)
     T wp2h;
     int plasma;
-    Drive drive;
-    int64_t n, w;
 };
 
 // reciprocal radii of one march step: 1/r_{j+1}, 1/r_{j+1/2}, 1/r_j (0 on the axis)
@@ -194,7 +201,7 @@ __device__ __forceinline__ EmPf<T> em_fetch(const Ctx<T>& c, const SetP<T>& s, i
         p.ex0 = c.x.L(s.ex, m, k);
         p.bx0 = c.x.L(s.bx, m, k);
         if (c.plasma) p.jx = c.x.L(s.jx, m, k);
-        if (s.jxa && c.live) p.jxa = c.x.L(s.jxa, m, k);
+        if (s.jxa && c.live && (!s.jxa_m0 || m == 0)) p.jxa = c.x.L(s.jxa, m, k);
     }
     return p;
 }
@@ -246,7 +253,8 @@ __device__ __forceinline__ EmB<T> em_bvals(const Ctx<T>& c, const EmWin<T>& W) {
     return B;
 }
 
-// total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra + drive
+// total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra (the axion
+// current, or the prescribed drive)
 template <typename T>
 __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write,
                                       cx<T> jx_old, cx<T> jxa) {
@@ -263,7 +271,6 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
         v = jn;
     }
     if (s.jxa) v = v + jxa;
-    if (c.drive.on && c.m == 0) v.re += T(drive_jx_f(c.drive, c.g, c.i, row, c.n, c.w));
     return v;
 }
 
@@ -488,7 +495,7 @@ constexpr int NS = 6;
 // ---------------------------------------------------------------------------
 // AXT: kernel A advances the axion (T_a, phi); otherwise it writes S_a to a.sa
 // for the marched axion current, which advances the axion instead.
-template <typename T, int M, bool DRV, bool AXT>
+template <typename T, int M, bool AXT>
 __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
     const Geo g = a.g;
     const int wave = threadIdx.x / WAVE;
@@ -523,10 +530,6 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     c.inv_2h = T(0.5) / c.h;
     c.wp2h = T(a.wp2 * g.h);
     c.plasma = a.plasma;
-    c.drive = a.drive;
-    if (!DRV) c.drive.on = 0;     // compiled out: no prescribed drive
-    c.n = a.n;
-    c.w = a.w;
 
     extern __shared__ unsigned char smem_raw[];
     // two exchange buffers [NS][M][WAVE], alternating by row: the one barrier
@@ -687,21 +690,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     }
 }
 
-// Kernel A entry points with arguments by value (the drive path: kernel A
-// advances the axion): FP64 keeps the full register file (no spills); FP32
-// fits two waves per SIMD.
-template <int M, bool DRV>
-__global__ void __launch_bounds__(WAVE * M) k_fused_a_f64(FusedArgs<double> a) {
-    fused_a_body<double, M, DRV, true>(a, blockIdx.x, blockIdx.y, a.rows);
-}
-template <int M, bool DRV>
-__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
-k_fused_a_f32(FusedArgs<float> a) { fused_a_body<float, M, DRV, true>(a, blockIdx.x, blockIdx.y, a.rows); }
-
 // ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
 // ---------------------------------------------------------------------------
-template <typename T, int WHICH, bool DRV>
+template <typename T, int WHICH>
 __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int chunk, int m, int rows) {
     const Geo g = a.g;
     const int lane = threadIdx.x;
@@ -732,10 +724,6 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     c.inv_2h = T(0.5) / c.h;
     c.wp2h = T(a.wp2 * g.h);
     c.plasma = a.plasma;
-    c.drive = a.drive;
-    if (WHICH || !DRV) c.drive.on = 0;     // compiled out without a drive
-    c.n = a.n;
-    c.w = a.w;
     const SetP<T>& s = WHICH ? a.s1 : a.s0;
     EmWin<T> W;
     for (int q = 0; q < 2; ++q) {
@@ -773,11 +761,6 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     }
 }
 
-template <typename T, int WHICH, bool DRV>
-__global__ void __launch_bounds__(WAVE) k_fused_em(FusedArgs<T> a) {
-    em_body<T, WHICH, DRV>(a, blockIdx.x, blockIdx.y, blockIdx.z, a.rows);
-}
-
 // ---------------------------------------------------------------------------
 // batched launches: block -> (instance, tile) through the launch's list; the
 // instance's arguments are read from a device table
@@ -792,7 +775,7 @@ __device__ __forceinline__ void batch_a_body(const FusedArgs<T>* __restrict__ ar
     // one radial chunk, which share the cache lines at their edges (measured 8%
     // faster for the FP64 step than radial chunks fastest)
     const int strips = fused_strips(a.g.nx);
-    fused_a_body<T, M, false, AXT>(a, local % strips, local / strips, L.rows);
+    fused_a_body<T, M, AXT>(a, local % strips, local / strips, L.rows);
 }
 template <int M, bool AXT>
 __global__ void __launch_bounds__(WAVE * M) k_batch_a_f64(const FusedArgs<double>* __restrict__ args, BatchList L) {
@@ -813,49 +796,14 @@ __global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restric
     const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
     const int m = local % a.g.M;                 // the modes of one tile run side by side
     const int t = local / a.g.M;
-    em_body<T, WHICH, false>(a, t / chunks, t % chunks, m, L.rows);
+    em_body<T, WHICH>(a, t / chunks, t % chunks, m, L.rows);
 }
 
 }  // namespace fused
 
-template <typename T, int M>
-static hipError_t launch_a(const FusedArgs<T>& a, hipStream_t s) {
-    if (a.sa) return hipErrorInvalidValue;   // by value, kernel A advances the axion
-    const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
-    const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
-    const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
-    const dim3 grd(strips, chunks), blk(fused::WAVE * M);
-    if constexpr (sizeof(T) == 8) {
-        if (a.drive.on) hipLaunchKernelGGL((fused::k_fused_a_f64<M, true>), grd, blk, lds, s, a);
-        else hipLaunchKernelGGL((fused::k_fused_a_f64<M, false>), grd, blk, lds, s, a);
-    } else {
-        if (a.drive.on) hipLaunchKernelGGL((fused::k_fused_a_f32<M, true>), grd, blk, lds, s, a);
-        else hipLaunchKernelGGL((fused::k_fused_a_f32<M, false>), grd, blk, lds, s, a);
-    }
-    return hipGetLastError();
-}
-
 template <typename T>
-hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage) {
-    const int strips = (a.g.nx + fused::OWN - 1) / fused::OWN;
-    const int chunks = (a.g.nr + 1 + a.rows - 1) / a.rows;
-    if (stage == 0) {
-        if (!a.axion) {
-            if (a.drive.on)
-                hipLaunchKernelGGL((fused::k_fused_em<T, 0, true>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
-            else
-                hipLaunchKernelGGL((fused::k_fused_em<T, 0, false>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
-            return hipGetLastError();
-        }
-        switch (a.g.M) {
-            case 1: return launch_a<T, 1>(a, s);
-            case 2: return launch_a<T, 2>(a, s);
-            case 3: return launch_a<T, 3>(a, s);
-            case 4: return launch_a<T, 4>(a, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    hipLaunchKernelGGL((fused::k_fused_em<T, 1, false>), dim3(strips, chunks, a.g.M), dim3(fused::WAVE), 0, s, a);
+hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, int64_t n, int64_t w, hipStream_t s) {
+    hipLaunchKernelGGL((fused::k_drive_plane<T>), dim3((g.nx + 255) / 256, g.nr + 1), dim3(256), 0, s, d, g, out, n, w);
     return hipGetLastError();
 }
 
@@ -897,7 +845,7 @@ template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, 
 template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
-template hipError_t fused_step<double>(const FusedArgs<double>&, hipStream_t, int);
-template hipError_t fused_step<float>(const FusedArgs<float>&, hipStream_t, int);
+template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);
+template hipError_t drive_plane<float>(const Drive&, const Geo&, cx<float>*, int64_t, int64_t, hipStream_t);
 
 }  // namespace qds

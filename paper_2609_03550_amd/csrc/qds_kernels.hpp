@@ -77,6 +77,7 @@ struct StepPlan {
     cx<T>* B[21];
     cx<T>* ja[3];
     cx<T>* sa;                  // scratch S_a plane (regenerated set only)
+    cx<T>* jdrv;                // drive plane (j_x^(0) of mode 0; null until first used)
     int plasma, axion, arem;
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
@@ -127,6 +128,7 @@ struct SetP {
     cx<T>* otrp; cx<T>* otrm; cx<T>* ottp; cx<T>* ottm;
     cx<T>* oex; cx<T>* obx; cx<T>* ojx; cx<T>* ojr; cx<T>* ojt;
     const cx<T>* jxa; const cx<T>* jra; const cx<T>* jta;
+    int jxa_m0;   // jxa holds mode 0 only (the prescribed drive); other modes add nothing
 };
 
 template <typename T>
@@ -142,10 +144,7 @@ struct FusedArgs {
     int plasma, axion;
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
-    Drive drive;
-    int64_t n, w;
     int window;       // 1: moving window (outputs one column to the left)
-    int rows;         // radial rows per workgroup chunk
 };
 
 // Columns owned by one 64-lane strip of the r-marching kernels: lane 0 is the
@@ -183,8 +182,11 @@ __device__ __forceinline__ int batch_find(const BatchList& L, int b) {
 }
 
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
-template <typename T> hipError_t fused_step(const FusedArgs<T>& a, hipStream_t s, int stage);
-template <typename T> hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s);
+// The prescribed drive's j_x^(0) of step n (window offset w) into the mode-0
+// rows of out (one plane of row pitch g.ld), read by the background set of the
+// fused kernels as its extra j_x.
+template <typename T>
+hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, int64_t n, int64_t w, hipStream_t s);
 // Batched launches over many instances (argument tables in device memory).
 // axt: kernel A advances the axion (every instance of the list has sa null);
 // otherwise every instance has sa set and the axion current advances it.

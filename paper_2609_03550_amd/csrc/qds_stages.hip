@@ -379,68 +379,6 @@ __global__ void __launch_bounds__(256) k_axion_current(AxionArgs<T> a) {
     }
 }
 
-// Axion current with one wavefront per mode: a workgroup of M waves covers 64
-// cells of one row; each wave forms its mode's factors, the waves exchange them
-// through LDS and each evaluates C_m for its own mode.
-template <typename T, int M>
-__device__ __forceinline__ void axion_current_body(const AxionArgs<T>& a, int xb, int j0, int rows) {
-    const Geo& g = a.g;
-    const int m = threadIdx.x / 64;
-    const int lane = threadIdx.x % 64;
-    const int i = xb * 64 + lane;
-    __shared__ cx<T> sm[18][M][64];
-    const bool act = i < g.nx;
-    const bool live = act && (g.per || i < g.nx - 1);
-    const int j1 = min(j0 + rows, g.nr + 1);
-    for (int j = j0; j < j1; ++j) {
-        const bool calc = live && j < g.nr;
-        if (j > j0) __syncthreads();             // the previous row's factors are consumed
-        if (calc) {
-            cx<T> f[18];
-            ja_factors<T, true>(a, m, i, j, f);
-#pragma unroll
-            for (int q = 0; q < 18; ++q) sm[q][m][lane] = f[q];
-        }
-        __syncthreads();
-        cx<T> jx = zero<T>(), jr = zero<T>(), jt = zero<T>();
-        if (calc) {
-            cx<T> A[M], B[M];
-            cx<T> out[3] = {zero<T>(), zero<T>(), zero<T>()};
-#pragma unroll
-            for (int c = 0; c < 9; ++c) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) { A[k] = sm[2 * c][k][lane]; B[k] = sm[2 * c + 1][k][lane]; }
-                conv_one<T, M>(A, B, m, out[c / 3], (c % 3 == 1) ? T(-1) : T(1));
-            }
-            jx = out[0]; jt = out[1]; jr = out[2];
-        }
-        if (act) {
-            const T sj = T(a.s_j);
-            st(a.jax + g.at(m, j, i), sj * jx);
-            st(a.jat + g.at(m, j, i), sj * jt);
-            if (j < g.nr) st(a.jar + g.at(m, j, i), sj * jr);
-        }
-    }
-}
-
-template <typename T, int M>
-__global__ void __launch_bounds__(64 * M) k_axion_current_w(AxionArgs<T> a) {
-    axion_current_body<T, M>(a, blockIdx.x, blockIdx.y, 1);
-}
-
-template <typename T>
-hipError_t axion_current_w(const AxionArgs<T>& a, hipStream_t s) {
-    dim3 grd((a.g.nx + 63) / 64, a.g.nr + 1);
-    switch (a.g.M) {
-#define QDS_CW(MM) case MM: hipLaunchKernelGGL((k_axion_current_w<T, MM>), grd, dim3(64 * MM), 0, s, a); break;
-        QDS_CW(1) QDS_CW(2) QDS_CW(3) QDS_CW(4)
-#undef QDS_CW
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-template hipError_t axion_current_w<double>(const AxionArgs<double>&, hipStream_t);
-template hipError_t axion_current_w<float>(const AxionArgs<float>&, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // moving window: copy every plane shifted left by one column, zero the last

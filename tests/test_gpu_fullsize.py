@@ -42,9 +42,8 @@ def _gpu_full(wl, dtype, nsteps):
     s.set_option(qds.OPT_TUNE, 1)
     s.step(nsteps)
     torch.cuda.synchronize()
-    # the autotuner serves the table-driven kernels; a prescribed drive runs
-    # the by-value kernels at the default tile height
-    assert s.tiles()[1] == (wl.drive is None)
+    # the autotuner has run on the first 8 steps (with or without a drive)
+    assert s.tiles()[1]
     return s.fields()
 
 

@@ -175,6 +175,26 @@ def test_autotuned_tiles_change_no_result(dtype):
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
+def test_autotuned_tiles_with_a_drive_change_no_result():
+    """With a prescribed drive (moving window, no axion; the drive plane is
+    filled before every step) the autotuner's choice for the background set
+    is one of the candidates of the background set alone and the states are
+    bit-identical to the default tiling."""
+    from paper_2609_03550_amd import qds
+    wl = I.driven_window(nx=200, nr=20, steps=0)
+    d = wl.drive
+    wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed))
+    a = _solver(wl, "f64")
+    b = _solver(wl, "f64")
+    b.set_option(qds.OPT_TUNE, 1)
+    a.step(12)
+    b.step(12)
+    torch.cuda.synchronize()
+    rows, tuned = b.tiles()
+    assert tuned and rows[0] in (8, 16, 26, 52)
+    assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
+
+
 def test_per_kernel_tile_heights_change_no_result():
     """QDS_OPT_ROWS_A / _CUR / _B set one kernel's tile height each (used to
     replay the autotuner's choice): uneven heights that leave ragged last
