@@ -254,12 +254,11 @@ def test_random_full_state(dtype, x_bc, r_bc, arem, M):
 
 @pytest.mark.parametrize("x_bc,r_bc", [("open", "open"), ("periodic", "pec")])
 def test_axion_advance_in_current_march_equals_kernel_a(x_bc, r_bc):
-    """Two placements of the axion advance on one random full state: the
-    marched axion current (which reads S_a back from scratch) and kernel A
-    (taken when a prescribed drive is on; here of zero amplitude, which adds
-    exact zeros).  The background set and the axion do not depend on the
-    regenerated set, so after 6 steps they agree bit for bit; the regenerated
-    set differs only by the rounding of the two j_a kernels."""
+    """Two placements of the axion advance on one random full state: with the
+    regenerated set the marched axion kernel advances T_a and phi from the
+    S_a that kernel A leaves in scratch; without it kernel A advances them
+    itself.  The background set and the axion do not depend on the
+    regenerated set, so after 6 steps the two runs agree on them bit for bit."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
     wl = _full(131, 21, 3, x_bc=x_bc, r_bc=r_bc)
@@ -273,23 +272,21 @@ def test_axion_advance_in_current_march_equals_kernel_a(x_bc, r_bc):
     a = qds.Solver(wl, dtype="f64")
     a.load_fields(st)
     a.step(6)
-    b = qds.Solver(wl.with_(drive=I.Drive(0.0, 60 * H, 1.0, 10 * H, 0.0, 4 * DR, 0.0, 1)), dtype="f64")
+    b = qds.Solver(wl.with_(arem=False), dtype="f64")
     b.load_fields(st)
     b.step(6)
     torch.cuda.synchronize()
     assert a.fused and b.fused
     fa, fb = a.fields(), b.fields()
-    for k in fa:
-        if k.endswith("1"):
-            d = (fa[k] - fb[k]).abs().max().item()
-            assert d <= 1e-13 * max(fa[k].abs().max().item(), 1.0), (k, d)
-        else:
-            assert torch.equal(fa[k], fb[k]), k
+    assert set(fb) and set(fb) < set(fa)
+    for k in fb:
+        assert torch.equal(fa[k], fb[k]), k
 
 
 def test_random_state_with_drive():
     """The prescribed drive (with its noise) on a random full state in the
-    moving window: the by-value drive kernels against the oracle."""
+    moving window: the drive plane of each step, read by the background set,
+    against the oracle."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
     wl = I.driven_window(nx=200, nr=20, steps=0)
