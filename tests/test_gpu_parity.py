@@ -308,6 +308,33 @@ def test_random_state_with_drive():
     P.compare_states(s.fields(), ref, 1e-12, 1e-14)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_state_with_drive_and_regenerated_set(dtype):
+    """The prescribed drive together with the plasma, the axion and the
+    regenerated set (open x, no window): the drive plane feeds kernel A's
+    background set while the marched axion kernel and kernel B run as without
+    a drive; a random full state, 4 steps, against the oracle."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    d = I.Drive(amp=50.0, x0=60 * H, v=0.999, sx=10 * H, r0=0.0, sr=4 * DR, noise=1e-3, seed=3)
+    wl = _full(131, 21, 3).with_(drive=d)
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    gen = torch.Generator().manual_seed(11)
+    for k, v in st.items():
+        if isinstance(v, torch.Tensor) and v.is_complex():
+            st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    st = Q.step(st, g, ph)
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_fields(st)
+    assert s.fused
+    s.step(4)
+    torch.cuda.synchronize()
+    ref = Q.run(st, g, ph, 4)
+    tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
+    P.compare_states(s.fields(), ref, tol, floor, by_group=(dtype == "f32"))
+
+
 def test_stop_save_reload_continue_is_bitwise():
     """Checkpoint and resume: 5 steps, the state saved through fields() and
     loaded into a fresh solver (counters included), 6 more steps, equals 11
