@@ -139,7 +139,10 @@ int64_t qds_plane_offset(qds_handle h, int32_t plane);
 qds_status qds_add_pulse(qds_handle h, qds_state* st, int32_t pol, const double* f_K,
                          const double* f_J, const double* f_G, void* stream);
 
-/* Advance n_steps steps (background set, axion, regenerated set). */
+/* Advance n_steps steps (background set, axion, regenerated set).  With a
+ * prescribed drive the library evaluates j_x^(0) of each step into a plane
+ * of its own (allocated on the first such call, (nr+1) x row pitch elements),
+ * which the fused kernels read as an extra current of mode 0. */
 qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const qds_axion* axion,
                     int64_t n_steps, void* stream);
 

@@ -330,7 +330,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
                                         int r0, int r1, const RowInv<T>& ri, const EmRowX<T>& X) {
     const Geo& g = c.g;
     const int m = c.m;
-    const T h = c.h, dr = c.dr;
+    const T h = c.h;
     const int ocI = c.o.col(c.i);     // output column of integer column i
     const bool wI = c.owner && ocI >= 0;
     // ---- E_x^{n+1/2} at J = j+1
@@ -447,7 +447,7 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
                                              int r1) {
     const Geo& g = c.g;
     const int m = c.m, N = g.nr;
-    const T h = c.h, dr = c.dr;
+    const T dr = c.dr;
     cx<T> er_a = T(0.5) * (W.rpa[0] + W.rma[0]);
     cx<T> er_b = T(0.5) * (B.rpb[0] + B.rmb[0]);
     cx<T> er_l = shfl_up1(er_a);                        // E_r at column i-1
@@ -543,7 +543,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     EmWin<T> W;
     cx<T> phw[3];     // phi^n at K = j-1, j, j+1
     const int m = wave;
-    const T h = c.h, dr = c.dr;
+    const T h = c.h;
     const T kap = c.kap;
     const int ocI = c.o.col(c.i);
     const bool wI = c.owner && ocI >= 0;
