@@ -65,6 +65,20 @@ __device__ __forceinline__ void st(cx<float>* p, cx<float> a) {
     v.y = a.im;
     *(g_v2f*)(p) = v;
 }
+// Streaming store (the non-temporal hint of a vector store): the line is not
+// kept in the caches for reuse.
+__device__ __forceinline__ void st_nt(cx<double>* p, cx<double> a) {
+    v2d v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, (g_v2d*)(p));
+}
+__device__ __forceinline__ void st_nt(cx<float>* p, cx<float> a) {
+    v2f v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, (g_v2f*)(p));
+}
 
 // Value held by the next lane of the wavefront (DPP wave shift; lane 63
 // receives zero).  Call it with every lane active: a lane masked off by a
