@@ -230,6 +230,19 @@ qds_status qds_backward(qds_handle h, const qds_state* u0, const qds_current* J,
 qds_status qds_loss_eval(qds_handle h, const void* buf, const qds_loss* loss, double* out_dev, void* grad_buf,
                          void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the loss of qds_loss_eval
+ * added to *out_dev (a device double) without its gradient and without any
+ * allocation.  Each 64-column x 4-row tile of the loss window leaves a partial
+ * sum in a static device array of 65536 doubles (512 KiB per GPU, held until
+ * the process ends), which one more workgroup adds in a fixed order.  Fails
+ * with QDS_EINVAL when ceil((x_end - x_begin)/64) * ceil((nr+1)/4) > 65536.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams without ordering) race; calls on one stream do not.
+ * The array is looked up (hipGetSymbolAddress) on the first call on each
+ * device, with that device current. */
+qds_status qds_loss_eval_noalloc(qds_handle h, const void* buf, const qds_loss* loss, double* out_dev, void* stream);
+
 /* Adds Re sum conj(a) b over two state buffers to *out_dev (a device double). */
 qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream);
 
