@@ -118,9 +118,13 @@ class _Ctx:
         self.im = 1j * self.m.to(CDT)
         self.rJ = (g.dr * torch.arange(g.nr + 1, dtype=RDT)).view(1, -1, 1)
         self.rK = (g.dr * (torch.arange(g.nr, dtype=RDT) + 0.5)).view(1, -1, 1)
-        # ghost parity across the axis for B_x, phi and T_a: mirror for m = 0
-        # (Neumann), odd for m >= 1 (the field vanishes on the axis)
-        self.par = torch.tensor([1.0] + [-1.0] * (g.nmodes - 1), dtype=RDT).view(-1, 1)
+        # ghost parity across the axis (Sec. 2.3 regularity): a scalar or
+        # longitudinal mode m (B_x, phi, T_a) behaves as r^m near the axis, so
+        # its ghost at r_{-1/2} is (-1)^m times the value at r_{1/2}; a
+        # transverse component (E_r, B_theta) of mode m != 1 as r^|m-1|,
+        # parity (-1)^(m-1) (mode 1 takes the axis relation instead)
+        self.par = torch.tensor([(-1.0) ** m for m in range(g.nmodes)], dtype=RDT).view(-1, 1)
+        self.tpar = torch.tensor([(-1.0) ** (m - 1) for m in range(g.nmodes)], dtype=RDT).view(-1, 1)
 
     def xp(self, a):   # value at i+1
         return _sx(a, 1, self.per)
@@ -486,8 +490,9 @@ def _ghost_par(c: _Ctx, F: torch.Tensor) -> torch.Tensor:
 
 def _ghost_Er(c: _Ctx, Er: torch.Tensor, Et: torch.Tensor) -> torch.Tensor:
     """E_r at r_{-1/2}: the m = 1 reflection through the axis relation
-    T_r^+-(-1/2) = 2i T_th^-+(0) - T_r^+-(1/2) (Eq. axis_Tr), odd otherwise."""
-    g = -Er[:, 0]
+    T_r^+-(-1/2) = 2i T_th^-+(0) - T_r^+-(1/2) (Eq. axis_Tr), parity
+    (-1)^(m-1) otherwise."""
+    g = c.tpar.to(Er.dtype) * Er[:, 0]
     if c.M > 1:
         g = torch.cat([g[:1], (2j * Et[1, 0] - Er[1, 0]).view(1, -1), g[2:]], dim=0)
     return g
@@ -495,8 +500,8 @@ def _ghost_Er(c: _Ctx, Er: torch.Tensor, Et: torch.Tensor) -> torch.Tensor:
 
 def _ghost_Bt(c: _Ctx, Bt: torch.Tensor, Br: torch.Tensor) -> torch.Tensor:
     """B_theta at r_{-1/2} from the same reflection: -2i B_r(0) - B_theta(1/2)
-    for m = 1, odd otherwise."""
-    g = -Bt[:, 0]
+    for m = 1, parity (-1)^(m-1) otherwise."""
+    g = c.tpar.to(Bt.dtype) * Bt[:, 0]
     if c.M > 1:
         g = torch.cat([g[:1], (-2j * Br[1, 0] - Bt[1, 0]).view(1, -1), g[2:]], dim=0)
     return g
@@ -584,8 +589,10 @@ def axion_current(c: _Ctx, f: Dict, st: Dict, kg: Dict, bext, form: str = "trans
         Nh = 0.5 * (f["Trm_o"] + f["Trm_n"])
         Tph = 0.5 * (f["Ttp_o"] + f["Ttp_n"])
         Tmh = 0.5 * (f["Ttm_o"] + f["Ttm_n"])
-        # axis ghosts at r_{-1/2}: odd for m != 1, the axis relation for m = 1
-        gP, gN = -Ph[:, 0], -Nh[:, 0]
+        # axis ghosts at r_{-1/2}: parity (-1)^(m-1) for m != 1, the axis
+        # relation for m = 1
+        tp = c.tpar.to(Ph.dtype)
+        gP, gN = tp * Ph[:, 0], tp * Nh[:, 0]
         if M > 1:
             gP = torch.cat([gP[:1], (2j * Tmh[1, 0] - Ph[1, 0]).view(1, -1), gP[2:]], dim=0)
             gN = torch.cat([gN[:1], (2j * Tph[1, 0] - Nh[1, 0]).view(1, -1), gN[2:]], dim=0)

@@ -746,6 +746,7 @@ __device__ void ja_factors_bar_comb(const AxBar<T>& a, int m, int i, int j, int 
     const T rk = (T(j) + T(0.5)) * dr;
     const T r_half = T(0.5) * dr;
     const T par = parity<T>(m);
+    const T tg = tghost<T>(m);
     const T h = T(0.5);
     // ---- T_r at the old and new levels (half rows j-1, j): E_r -> (+1/2, +1/2), B_theta -> (+1/2, -1/2)
     {
@@ -755,14 +756,14 @@ __device__ void ja_factors_bar_comb(const AxBar<T>& a, int m, int i, int j, int 
         for (int cc = 0; cc < 2; ++cc) {
             // f2: E_r^n of j_a,x
             cx<T> eb = q2, gb = q2;
-            if (ax) eb = eb - gb;
+            if (ax) eb = eb + tg * gb;
             else { A.p[0][cc] = A.p[0][cc] + h * gb; A.q[0][cc] = A.q[0][cc] + h * gb; }
             A.p[1][cc] = A.p[1][cc] + h * eb; A.q[1][cc] = A.q[1][cc] + h * eb;
             // f6 (B_theta) and f10 (E_r) of j_a,theta, both levels
             cx<T> bb = q, gbb = q, ebb = qe, gebb = qe;
             if (ax) {
-                bb = bb - gbb;
-                ebb = ebb - gebb;
+                bb = bb + tg * gbb;
+                ebb = ebb + tg * gebb;
             } else {
                 const cx<T> tp = h * (h * gbb) + h * (h * gebb), tm = h * (h * gebb) - h * (h * gbb);
                 A.p[0][cc] = A.p[0][cc] + tp; A.q[0][cc] = A.q[0][cc] + tm;
@@ -1072,8 +1073,8 @@ __device__ __forceinline__ void fac_x_bar(const FacC<T>& c, int j, const cx<T>* 
                 jcb.et0 = jcb.et0 + imul(-T(2), q);
                 n.et1 = n.et1 + imul(-T(2), q);
             }
-            kcb.er0 = kcb.er0 - q;
-            n.er1 = n.er1 - q;
+            kcb.er0 = kcb.er0 + c.tg * q;
+            n.er1 = n.er1 + c.tg * q;
         } else {
             kpb.er0 = kpb.er0 + q;
             n.erl1 = n.erl1 + q;
@@ -1139,7 +1140,7 @@ __device__ __forceinline__ void fac_t_bar(const FacC<T>& c, int j, const cx<T>* 
                 jcb.Qm = jcb.Qm + imul(-T(2), q);
                 n.Qm1 = n.Qm1 + imul(-T(2), q);
             }
-            kcb.P = kcb.P - q; n.P1 = n.P1 - q;
+            kcb.P = kcb.P + c.tg * q; n.P1 = n.P1 + c.tg * q;
         } else {
             kpb.P = kpb.P + q; n.Pl1 = n.Pl1 + q;
         }
@@ -1153,7 +1154,7 @@ __device__ __forceinline__ void fac_t_bar(const FacC<T>& c, int j, const cx<T>* 
                 jcb.Qp = jcb.Qp + imul(-T(2), q);
                 n.Qp1 = n.Qp1 + imul(-T(2), q);
             }
-            kcb.N = kcb.N - q; n.N1 = n.N1 - q;
+            kcb.N = kcb.N + c.tg * q; n.N1 = n.N1 + c.tg * q;
         } else {
             kpb.N = kpb.N + q; n.Nl1 = n.Nl1 + q;
         }
@@ -1246,7 +1247,7 @@ __global__ void __launch_bounds__(WAVE * M) k_current_bar_march(AxBar<T> a, int 
     const int r0 = chunk * rows;
     const int r1 = min(g.nr, r0 + rows);
     const T dr = T(g.dr);
-    const FacC<T> fc{m, m == 0 ? T(1) : T(-1), dr, T(1) / dr, f.bx0, f.br1, f.bt1};
+    const FacC<T> fc{m, parity<T>(m), tghost<T>(m), dr, T(1) / dr, f.bx0, f.br1, f.bt1};
     const T sj = T(f.s_j);
     const cx<T> zc = zero<T>();
 

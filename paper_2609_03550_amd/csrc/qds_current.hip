@@ -59,7 +59,7 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     const int i1 = (i + 1 < g.nx) ? i + 1 : (g.per ? 0 : -1);
     const int r0 = chunk * rows;
     const int r1 = min(g.nr + 1, r0 + rows);
-    const T par = m == 0 ? T(1) : T(-1);
+    const T par = parity<T>(m);
     const T h = T(g.h);
     const T dr = T(g.dr);
     const T inv_dr = T(1) / dr;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
         }
     };
 
-    const FacC<T> fc{m, par, dr, inv_dr, a.bx0, a.br1, a.bt1};
+    const FacC<T> fc{m, par, tghost<T>(m), dr, inv_dr, a.bx0, a.br1, a.bt1};
 
     // phi^n on half row k (the exterior ghost on row nr with the open boundary)
     auto phi_row = [&](int k) {

@@ -132,7 +132,8 @@ __device__ __forceinline__ NbT<T> nb_t(const KRow<T>& kp, const KRow<T>& kc, con
 template <typename T>
 struct FacC {
     int m;
-    T par;              // parity of the mode across the axis (+1 for m = 0)
+    T par;              // axis parity of B_x, phi, T_a: (-1)^m
+    T tg;               // coefficient of T_r(1/2) in its axis ghost: (-1)^(m-1), -1 for m = 1
     T dr, inv_dr;
     cx<T> bx0, br1, bt1;   // uniform external field
 };
@@ -156,8 +157,8 @@ __device__ __forceinline__ void fac_x(const FacC<T>& c, int j, const KRow<T>& kp
             g0 = imul(T(2), jc.et0) - kc.er0;
             g1 = imul(T(2), n.et1) - n.er1;
         } else {
-            g0 = -kc.er0;
-            g1 = -n.er1;
+            g0 = c.tg * kc.er0;
+            g1 = c.tg * n.er1;
         }
     } else {
         g0 = kp.er0;
@@ -206,7 +207,7 @@ __device__ __forceinline__ void fac_t(const FacC<T>& c, int j, const KRow<T>& kp
             gN0 = imul(T(2), jc.Qp) - kc.N;
             gN1 = imul(T(2), n.Qp1) - n.N1;
         } else {
-            gP0 = -kc.P; gP1 = -n.P1; gN0 = -kc.N; gN1 = -n.N1;
+            gP0 = c.tg * kc.P; gP1 = c.tg * n.P1; gN0 = c.tg * kc.N; gN1 = c.tg * n.N1;
         }
     } else {
         gP0 = kp.P; gP1 = n.Pl1; gN0 = kp.N; gN1 = n.Nl1;

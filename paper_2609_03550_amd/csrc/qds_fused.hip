@@ -483,9 +483,6 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
     W.bx1[0] = W.bx1[1];
 }
 
-template <typename T>
-__device__ __forceinline__ T par(int m) { return m == 0 ? T(1) : T(-1); }
-
 // LDS exchange slots per lane: the 6 factors of the axion source (two such
 // buffers, alternating by row)
 constexpr int NS = 6;

@@ -4,6 +4,17 @@
 
 namespace qds {
 
+// Axis reflections (Sec. 2.3 regularity).  A scalar or longitudinal mode m
+// (B_x, phi, T_a) behaves as r^m near the axis: its ghost at r_{-1/2} is
+// (-1)^m times the value at r_{1/2}.  A transverse component (E_r, B_theta,
+// T_r) of mode m behaves as r^|m-1|: parity (-1)^(m-1) for m != 1, while mode
+// 1 takes the axis relation ghost = 2i T_theta(0) - T_r(1/2); tghost is the
+// coefficient of T_r(1/2) in either.
+template <typename T>
+__device__ __forceinline__ T parity(int m) { return (m & 1) ? T(-1) : T(1); }
+template <typename T>
+__device__ __forceinline__ T tghost(int m) { return (m & 1) && m != 1 ? T(1) : T(-1); }
+
 // Grid geometry and plane addressing: element (mode m, row, column c) of a
 // plane is at (m * (nr + 1) + row) * ld + c.
 struct Geo {

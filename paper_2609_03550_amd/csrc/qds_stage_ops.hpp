@@ -64,17 +64,14 @@ struct BgView {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ T parity(int m) { return m == 0 ? T(1) : T(-1); }
-
 // The 18 per-mode factors of the axion current at H cell i, row j < nr (each
 // component is sum over three C_m{A, B} with signs +, -, +):
 //   f[0..5]   j_a,x     at (x_{i+1/2}, r_j,       t^n):       B_x, d_t phi | E_r, (d_theta phi)/r | E_theta, d_r phi
 //   f[6..11]  j_a,theta at (x_{i+1/2}, r_j,       t^{n+1/2}): B_theta, d_t phi | E_x, d_r phi | E_r, d_x phi
 //   f[12..17] j_a,r     at (x_{i+1/2}, r_{j+1/2}, t^{n+1/2}): B_r, d_t phi | E_theta, d_x phi | E_x, (d_theta phi)/r
 // Off-grid values are centred means of the nearest samples, with the axis
-// reflections (parity (-1)^m for B_x, phi, T_a; the T_r reflection of the
-// m = 1 axis relation for E_r and B_theta); the uniform external field is
+// reflections (parity (-1)^m for B_x, phi, T_a; (-1)^(m-1) for E_r and
+// B_theta, whose mode 1 takes the axis relation); the uniform external field is
 // added to the B factors.
 //
 // With TFORM the theta and r pairs are formed from the transport variables
@@ -96,6 +93,7 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
     const T rk = (T(j) + T(0.5)) * dr;
     const T r_half = T(0.5) * dr;
     const T par = parity<T>(m);
+    const T tg = tghost<T>(m);
     // ---------------- j_a,x
     {
         cx<T> bhi = T(0.5) * (ld(a.A0.bx + g.at(m, j, i)) + ld(a.B0.bx + g.at(m, j, i)));
@@ -114,8 +112,8 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
                 g0 = imul(T(2), v.Et0(1, 0, i)) - e0;
                 g1 = imul(T(2), v.Et0(1, 0, i1)) - e1;
             } else {
-                g0 = -e0;
-                g1 = -e1;
+                g0 = tg * e0;
+                g1 = tg * e1;
             }
         } else {
             g0 = v.Er0(m, j - 1, i);
@@ -150,7 +148,7 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
                 gN0 = imul(T(2), tt(a.A0.ttp, a.B0.ttp, i)) - N0;
                 gN1 = imul(T(2), tt(a.A0.ttp, a.B0.ttp, i1)) - N1;
             } else {
-                gP0 = -P0; gP1 = -P1; gN0 = -N0; gN1 = -N1;
+                gP0 = tg * P0; gP1 = tg * P1; gN0 = tg * N0; gN1 = tg * N1;
             }
         } else {
             gP0 = tr(a.A0.trp, a.B0.trp, j - 1, i);
@@ -192,7 +190,7 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
                 ge0 = imul(T(2), et0) - e0;
                 ge1 = imul(T(2), et1) - e1;
             } else {
-                gb0 = -b0; gb1 = -b1; ge0 = -e0; ge1 = -e1;
+                gb0 = tg * b0; gb1 = tg * b1; ge0 = tg * e0; ge1 = tg * e1;
             }
         } else {
             gb0 = T(0.5) * (v.Bt0(m, j - 1, i) + v.Bt1(m, j - 1, i));
