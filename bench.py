@@ -180,6 +180,34 @@ def batched_leg(steps, graph_steps, count=64):
             "speedup": t_solo / t_batch}
 
 
+def f32_leg(wl, steps):
+    """The same workload in single precision: autotuned tiles, 10 warm-up
+    steps, then ``steps`` timed steps; the whole step against its
+    one-read-one-write byte model (336 B per cell-mode with every plane)."""
+    import torch
+    from paper_2609_03550_amd import qds
+    s = qds.Solver(wl, dtype="f32")
+    s.load_pulses()
+    s.set_option(qds.OPT_TUNE, 1)
+    s.step(8)
+    s.step(10)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
+    step_bytes = 2 * nplanes * 8 * wl.cell_modes
+    tiles = s.tiles()
+    s.close()
+    return {"dtype": "f32", "steps": steps, "ms_per_step": ms, "value": wl.cell_modes / (ms / 1e3),
+            "unit": "cell-mode updates/s", "roofline_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+            "tiles": tiles[0]}
+
+
 def stream_reference(nbytes=1 << 31, reps=10):
     """Bandwidth a plain device copy (read + write) and a plain fill (write
     only) reach in the same process: the practical ceiling next to the 8 TB/s
@@ -247,6 +275,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=40,
                     help="steps of the 64-instance batched comparison (0 skips it)")
     ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--f32-steps", type=int, default=100,
+                    help="steps of the single-precision figure of the same workload (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM counters)")
     args = ap.parse_args()
@@ -298,21 +328,29 @@ def main():
     cells = wl.cell_modes
     value = cells * args.steps / (total_ms / 1e3)
     eb = 16 if args.dtype == "f64" else 8
-    # dominant kernel: the one with the largest summed time
-    k = max(range(3), key=lambda q: kms[q])
-    kname = KERNEL_NAMES[k] if wl.axion else "electromagnetic set"
-    if not s.fused:
-        kname = "staged step (all stage kernels)"
-    avg_ms = kms[k] / max(kn[k], 1)
-    alg_bytes = plane_accesses(wl, k) * eb * cells
-    if not s.fused:
-        alg_bytes = sum(plane_accesses(wl, q) for q in range(3)) * eb * cells
-    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     run_tiles = dict(zip(("kernel_a", "axion_current", "kernel_b"), s.tiles()[0]))
-    traffic = measured_traffic(wl, args.dtype, k, run_tiles) if s.fused else None
-    # whole-step effective bandwidth against the one-read-one-write byte model
+    kernels = {}
+    for q in range(3):
+        if not kn[q]:
+            continue
+        avg = kms[q] / kn[q]
+        name = KERNEL_NAMES[q] if (s.fused and wl.axion) else ("electromagnetic set" if s.fused else
+                                                                 "staged step (all stage kernels)")
+        alg = (plane_accesses(wl, q) if s.fused else sum(plane_accesses(wl, k) for k in range(3))) * eb * cells
+        kernels[KERNEL_KEYS[q]] = {"name": name, "avg_launch_ms": avg, "launches": kn[q],
+                                   "plane_passes": alg / eb / cells, "algorithmic_bytes_per_launch": alg,
+                                   "achieved_gbps": alg / (avg / 1e3) / 1e9,
+                                   "hbm_bytes_per_launch": measured_traffic(wl, args.dtype, q, run_tiles)
+                                   if s.fused else None}
+    # the whole step against the one-read-one-write byte model: every state
+    # plane read once and written once per step
     nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
     step_bytes = 2 * nplanes * eb * cells
+    kernel_sum_ms = sum(k["avg_launch_ms"] * k["launches"] for k in kernels.values()) / args.steps
+    achieved = step_bytes / (ms_per_step / 1e3) / 1e9
+    traffic = None
+    if s.fused and all(k["hbm_bytes_per_launch"] is not None for k in kernels.values()):
+        traffic = sum(k["hbm_bytes_per_launch"] * k["launches"] for k in kernels.values()) / args.steps
     out = {
         "metric": METRIC,
         "value": value,
@@ -330,16 +368,16 @@ def main():
                    "physics": "QDS Maxwell + Klein-Gordon axion + regenerated fields + cold plasma"
                    if wl.arem else ("QDS Maxwell + prescribed current, moving window" if wl.drive else "QDS Maxwell"),
                    "path": "fused" if s.fused else "staged", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms},
-        "step_effective_hbm_frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBPS,
-        "kernel_ms": {"kernel_a": kms[0] / max(kn[0], 1), "kernel_b": kms[1] / max(kn[1], 1) if kn[1] else None,
-                      "axion_current": kms[2] / max(kn[2], 1) if kn[2] else None},
-        "kernel_gbps": {KERNEL_NAMES[q]: plane_accesses(wl, q) * eb * cells / (kms[q] / kn[q] / 1e3) / 1e9
-                        for q in range(3) if kn[q] and s.fused},
+        # the dominant unit is the whole step (its kernels run back to back):
+        # algorithmic bytes = every state plane read once and written once
+        "roofline": {"bound": "hbm", "kernel": "whole step (" + " + ".join(k["name"] for k in kernels.values()) + ")",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic, "traffic_over_model": traffic / step_bytes if traffic else None,
+                     "bytes_per_step": step_bytes, "bytes_per_cell_mode": 2 * nplanes * eb,
+                     "step_ms": ms_per_step, "kernel_sum_ms": kernel_sum_ms},
+        "kernels": kernels,
         "fwd_adj_over_fwd": None,
-        "tiles": dict(zip(("kernel_a", "axion_current", "kernel_b"), s.tiles()[0]), tuned=s.tiles()[1]),
+        "tiles": dict(run_tiles, tuned=s.tiles()[1]),
     }
     del s
     torch.cuda.empty_cache()
@@ -350,6 +388,9 @@ def main():
         torch.cuda.empty_cache()
     if args.batched_steps > 0:
         out["batched"] = batched_leg(args.batched_steps, args.graph_steps)
+        torch.cuda.empty_cache()
+    if args.f32_steps > 0 and args.dtype == "f64" and args.workload == "axion":
+        out["f32"] = f32_leg(wl, args.f32_steps)
         torch.cuda.empty_cache()
     out["stream_reference"] = stream_reference()
     out["roofline"]["frac_of_copy"] = achieved / out["stream_reference"]["copy_read_write_gbps"]

@@ -142,7 +142,10 @@ qds_status qds_add_pulse(qds_handle h, qds_state* st, int32_t pol, const double*
 /* Advance n_steps steps (background set, axion, regenerated set).  With a
  * prescribed drive the library evaluates j_x^(0) of each step into a plane
  * of its own (allocated on the first such call, (nr+1) x row pitch elements),
- * which the fused kernels read as an extra current of mode 0. */
+ * which the fused kernels read as an extra current of mode 0.  The drive's
+ * noise counter packs (step, lab column, row) as step << 32 | column << 12 |
+ * row, so a call that would reach lab column 2^20 (nx - 1 + window, plus
+ * n_steps with the moving window) fails with QDS_ESTATE. */
 qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const qds_axion* axion,
                     int64_t n_steps, void* stream);
 

@@ -22,6 +22,9 @@ class EnvelopeLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, coeffs: torch.Tensor, g: torch.Tensor, wl: I.Workload, n_steps: int, ckpt_every: int,
                 dtype: str = "f64", loss_mode: int = 1, x_begin: Optional[int] = None):
+        if wl.s_phi != 1.0 or wl.s_j != 1.0:
+            # L = g^4 L_hat and dL/dg = 4 g^3 L_hat hold in scaled units only
+            raise ValueError("EnvelopeLoss needs the scaled units s_phi = s_j = 1 (the coupling enters as g^4)")
         c = tuple(float(v) for v in coeffs.detach().cpu().tolist())
         p0 = replace(wl.pulses[0], coeffs=c)
         wl2 = wl.with_(pulses=(p0,) + tuple(wl.pulses[1:]))

@@ -497,6 +497,14 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
         return fail(h, QDS_EINVAL, "drive widths must be positive%s");
     if (J && J->wp2 != 0.0 && !has(h, QDS_P_JX)) return fail(h, QDS_EINVAL, "plasma response needs the plasma planes%s");
     if (fields->step + n_steps >= (int64_t(1) << 31)) return fail(h, QDS_ESTATE, "step counter would overflow%s");
+    // the drive noise is keyed on (step, lab column, row) packed as
+    // step << 32 | column << 12 | row: every lab column must stay below 2^20
+    if (J && J->kind == QDS_J_RING) {
+        const int64_t last_col = int64_t(h->g.nx) - 1 + fields->window +
+                                 (h->g.x_bc == QDS_X_WINDOW ? n_steps : int64_t(0));
+        if (last_col >= (int64_t(1) << 20))
+            return fail(h, QDS_ESTATE, "drive noise counter: lab column would reach 2^20 (window + nx + n_steps)%s");
+    }
     if (h->g.dtype == QDS_F64) return run_steps<double>(h, fields, J, axion, n_steps, hipStream_t(stream));
     return run_steps<float>(h, fields, J, axion, n_steps, hipStream_t(stream));
 }

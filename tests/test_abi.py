@@ -128,3 +128,23 @@ def test_noalloc_loss_rejects_beyond_its_scratch_on_cpu(lib):
     assert lib.qds_loss_eval_noalloc(h, ctypes.c_void_p(64), ctypes.byref(lo), ctypes.byref(out), None) == qds.QDS_EINVAL
     assert lib.qds_destroy(h) == qds.QDS_OK
 
+
+def test_step_refuses_drive_noise_counter_overflow(lib):
+    """The drive noise is keyed on step << 32 | lab column << 12 | row: with
+    the moving window, a call whose last lab column would reach 2^20 is
+    refused before anything runs (checked on the CPU; the buffers are never
+    dereferenced)."""
+    from paper_2609_03550_amd import qds
+    h = ctypes.c_void_p()
+    g = qds.Grid(4096, 16, qds.F64, qds.X_BC["window"], 0, 0, 8.0)
+    assert lib.qds_init(ctypes.byref(g), 1, 0.25, 0.25, ctypes.byref(h)) == qds.QDS_OK
+    st = qds.State()
+    st.buf[0], st.buf[1] = 64, 128
+    st.window = (1 << 20) - 4096 - 5
+    J = qds.Current()
+    J.kind = qds.J_RING
+    J.sx = J.sr = 1.0
+    # last lab column = 4095 + window + 6 = 2^20
+    assert lib.qds_step(h, ctypes.byref(st), ctypes.byref(J), None, 6, None) == qds.QDS_ESTATE
+    assert b"2^20" in lib.qds_last_error(h)
+    assert lib.qds_destroy(h) == qds.QDS_OK

@@ -56,9 +56,12 @@ def _full(nx, nr, M, **kw):
     return wl.with_(**kw)
 
 
-def _compare_grad(gpu, ora, tol):
+def _compare_grad(gpu, ora, tol, by_group=False):
+    """Relative L2 of each adjoint field and mode against its own norm (floored
+    at 1e-9 of that field's norm over all modes: a mode the loss does not reach
+    holds only rounding); single precision against its field set's norm."""
     ora = {k: v for k, v in ora.items() if k in gpu}
-    P.compare_states(gpu, ora, tol, 1e-12, by_group=True)
+    P.compare_states(gpu, ora, tol, 1e-9, by_group=by_group)
 
 
 @pytest.mark.parametrize("x_bc,r_bc", [("open", "open"), ("periodic", "pec"), ("open", "pec"), ("periodic", "open")])
@@ -127,7 +130,7 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     res = [_gpu(wl, 9, c, 1, 1) for c in (1, 4, 9)]
     for _, L, lam, _ in res[1:]:
         assert abs(L / res[0][1] - 1) < 1e-14
-        P.compare_states(lam, res[0][2], 1e-12, 1e-14, by_group=True)
+        P.compare_states(lam, res[0][2], 1e-12, 1e-9)
 
 
 @pytest.mark.parametrize("nx,nr", [(40, 8), (150, 21)])
@@ -137,6 +140,25 @@ def test_single_precision_adjoint_tracks_double(nx, nr):
     _, L32, lam32, _ = _gpu(wl, 6, 3, 1, 1, "f32")
     assert abs(L32 / L64 - 1) < 1e-4
     P.compare_states(lam32, lam64, 1e-4, 1e-6, by_group=True)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_long_horizon_matches_autograd(dtype):
+    """128 steps of the full physics on a 256 x 24 x 2 grid (five x strips,
+    checkpoints every 16 steps, the loss over the last 64 columns the pulses
+    reach): the adjoint against autograd through the oracle, per field in
+    double precision; single precision against its field set's norm."""
+    wl = _full(256, 24, 2)
+    _, L, lam, dlds = _gpu(wl, 128, 16, 1, 1, dtype, x0=192, x1=256)
+    Lo, go = _oracle_grad(wl, 128, 1, 1, 192, 256)
+    assert L > 0
+    if dtype == "f64":
+        assert abs(L / Lo - 1) < 1e-11
+        _compare_grad(lam, go, 1e-9)
+        assert abs(dlds[0] / (2 * L) - 1) < 1e-9 and abs(dlds[1] / (2 * L) - 1) < 1e-9
+    else:
+        assert abs(L / Lo - 1) < 1e-4
+        _compare_grad(lam, go, 1e-4, by_group=True)
 
 
 def test_envelope_coefficient_gradients_match_finite_differences():
