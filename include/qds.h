@@ -118,10 +118,25 @@ typedef struct {
 
 typedef struct qds_ctx* qds_handle;
 
+/* Largest eigenvalues of the discrete radial operators over modes 0..modes-1
+ * (host only, no device work).  With c dt = dx the one-step map of the
+ * scheme factorises per mode and axial wavenumber k (Sec. 2.1: exact x
+ * transport, explicit radial sources) as
+ *   sin^2(w dt/2) = sin^2(k dx/2) + (dt/2)^2 mu cos^2(k dx/2),
+ * mu an eigenvalue of the radial operator of E_x (integer rows) or B_x
+ * (half rows); the Klein-Gordon step (Sec. 2.2) likewise with mu + m_a^2 of
+ * the operator of phi.  *mu_em is the electromagnetic maximum, *mu_kg the
+ * Klein-Gordon one without m_a^2.  r_bc = QDS_R_PEC gives the exact values
+ * for a conducting wall; QDS_R_OPEN the larger of the outer row with and
+ * without its exterior flux.  QDS_EINVAL for nr < 2, dr <= 0, modes outside
+ * 1..8 or a bad r_bc. */
+qds_status qds_radial_mu_max(int32_t nr, double dr, int32_t modes, int32_t r_bc, double* mu_em, double* mu_kg);
+
 /* Create a handle.  ``modes`` retained azimuthal modes m = 0..modes-1 (1..8).
  * Fails with QDS_ECFL unless |dt - dx| <= 4 ulp(dx) (exact one-cell shift,
- * Sec. 2.1) and dt^2 mu_max <= 4 for a Gershgorin bound mu_max of the radial
- * operators (the factorised dispersion relation of the scheme).  Allocates
+ * Sec. 2.1) and dt^2 mu_em <= 4 (qds_radial_mu_max: the step is stable
+ * exactly then).  qds_step fails with QDS_ECFL when the axion is advanced
+ * and dt^2 (mu_kg + m_a^2) > 4.  Allocates
  * the library's own scratch in device memory: with the regenerated set, four
  * planes (the three axion-current components and the axion source S_a). */
 qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out);

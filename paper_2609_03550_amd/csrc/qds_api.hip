@@ -240,6 +240,99 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
 
 
 // ---------------------------------------------------------------------------
+// radial stability bound (the factorised dispersion relation of the scheme)
+// ---------------------------------------------------------------------------
+// With c dt = dx the one-step map of a mode factorises (periodic x, closed r)
+// as sin^2(w dt/2) = sin^2(k dx/2) + (dt/2)^2 mu cos^2(k dx/2) with mu an
+// eigenvalue of the discrete radial operator of E_x (integer rows) or B_x
+// (half rows), so the step is stable iff dt^2 mu_max <= 4.  Both operators
+// are conservative three-point fluxes,
+//   (-L F)_j = [c_{j+1/2} (F_j - F_{j+1}) + c_{j-1/2} (F_j - F_{j-1})] / w_j + m^2 F_j / r_j^2,
+// symmetric in the inner product sum w_j F_j G_j: E_x rows w_j = r_j (dr/8 on
+// the axis), c_{j+1/2} = r_{j+1/2} / dr^2, E_x(0) = 0 for m >= 1; B_x rows
+// w = r_{k+1/2}, c = r_k / dr^2 (zero on the axis).  Their largest eigenvalue
+// is found by bisection with Sturm counts of the symmetrised tridiagonal
+// matrix.  The outer row is taken both with and without its exterior flux
+// (conducting wall / open ghost) and the larger value kept.  The Klein-Gordon
+// operator is the B_x one plus m_a^2.
+
+// number of eigenvalues below x of the symmetric tridiagonal (a, b)
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int neg = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        d = (a[i] - x) - (i ? b[i - 1] * b[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++neg;
+    }
+    return neg;
+}
+
+double trid_max(const std::vector<double>& w, const std::vector<double>& clo, const std::vector<double>& chi,
+                const std::vector<double>& extra) {
+    const size_t n = w.size();
+    if (n == 0) return 0.0;
+    std::vector<double> a(n), b(n > 1 ? n - 1 : 0);
+    double hi = 0.0;
+    for (size_t j = 0; j < n; ++j) {
+        a[j] = (clo[j] + chi[j]) / w[j] + extra[j];
+        if (j + 1 < n) b[j] = -chi[j] / sqrt(w[j] * w[j + 1]);
+    }
+    for (size_t j = 0; j < n; ++j) hi = fmax(hi, a[j] + (j ? fabs(b[j - 1]) : 0.0) + (j + 1 < n ? fabs(b[j]) : 0.0));
+    double lo = 0.0;
+    hi *= 1.0 + 1e-12;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(a, b, mid) == int(n)) hi = mid;   // every eigenvalue below mid
+        else lo = mid;
+    }
+    return hi;
+}
+
+// mu_max over modes 0..M-1 of the electromagnetic operators (E_x rows, B_x
+// rows) and of the Klein-Gordon operator (phi rows, without m_a^2).  A
+// conducting wall has E_x(nr) = 0 (a zero neighbour), no flux of E_theta
+// through r_nr for B_x, and a zero exterior phi; the open boundary takes the
+// larger value with and without the outer row's exterior flux.
+void radial_mu_max(int nr, double dr, int M, bool pec, double* mu_em, double* mu_kg) {
+    double em = 0.0, kg = 0.0;
+    std::vector<double> w, clo, chi, ex;
+    auto reset = [&]() { w.clear(); clo.clear(); chi.clear(); ex.clear(); };
+    for (int m = 0; m < M; ++m) {
+        for (int outer = 0; outer < 2; ++outer) {
+            if (pec && outer == 0) continue;   // one exact variant per operator below
+            // E_x rows (the axis row only for m = 0; E_x(nr) = 0 at a wall)
+            reset();
+            const int jend = pec ? nr - 1 : nr;
+            for (int j = (m == 0 ? 0 : 1); j <= jend; ++j) {
+                w.push_back(j == 0 ? dr / 8.0 : j * dr);
+                clo.push_back(j >= 1 ? (j - 0.5) / dr : 0.0);
+                chi.push_back(j < jend || pec || outer ? (j + 0.5) / dr : 0.0);
+                ex.push_back(j > 0 ? double(m) * m / ((j * dr) * (j * dr)) : 0.0);
+            }
+            em = fmax(em, trid_max(w, clo, chi, ex));
+            // half rows: B_x (no flux through a wall) and phi (zero exterior ghost at a wall)
+            for (int kgop = 0; kgop < 2; ++kgop) {
+                reset();
+                for (int k = 0; k < nr; ++k) {
+                    const double rk = (k + 0.5) * dr;
+                    const bool flux = k + 1 < nr || (pec ? kgop == 1 : outer == 1);
+                    w.push_back(rk);
+                    clo.push_back(k / dr);
+                    chi.push_back(flux ? (k + 1) / dr : 0.0);
+                    ex.push_back(double(m) * m / (rk * rk));
+                }
+                const double v = trid_max(w, clo, chi, ex);
+                if (kgop == 0) em = fmax(em, v);
+                else kg = fmax(kg, v);
+            }
+        }
+    }
+    *mu_em = em;
+    *mu_kg = kg;
+}
+
+// ---------------------------------------------------------------------------
 // adjoint driver: forward with checkpoints every C steps, loss seed, then per
 // segment (last first) recompute the states and run the transposed steps
 // ---------------------------------------------------------------------------
@@ -386,6 +479,13 @@ extern "C" {
 
 const char* qds_version(void) { return "qds-mi355x 0.1"; }
 
+qds_status qds_radial_mu_max(int32_t nr, double dr, int32_t modes, int32_t r_bc, double* mu_em, double* mu_kg) {
+    if (!mu_em || !mu_kg || nr < 2 || !(dr > 0) || modes < 1 || modes > QDS_MAX_MODES || r_bc < 0 || r_bc > 1)
+        return fail(nullptr, QDS_EINVAL, "bad argument%s");
+    radial_mu_max(nr, dr, modes, r_bc == QDS_R_PEC, mu_em, mu_kg);
+    return QDS_OK;
+}
+
 const char* qds_last_error(qds_handle h) { return h ? h->err : g_err; }
 
 qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out) {
@@ -403,18 +503,19 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     // exact one-cell transport needs c dt = dx (Sec. 2.1)
     if (fabs(dt - dx) > 4.0 * (nextafter(dx, 2 * dx) - dx))
         return fail(nullptr, QDS_ECFL, "c dt must equal dx%s");
-    // radial stability: dt^2 mu_max <= 4 with mu_max bounded by row sums of the
-    // radial operators (|Laplacian| <= 4/dr^2 plus the coupling terms, and
-    // m^2/r^2 <= 4 m^2/dr^2 on the first half row)
-    const double mmax = modes - 1;
-    const double mu_bound = (8.0 + 4.0 * mmax * mmax) / (g.dr * g.dr);
-    if (dt * dt * mu_bound > 4.0) return fail(nullptr, QDS_ECFL, "radial stability bound dt^2 mu_max <= 4 fails%s");
+    // radial stability: dt^2 mu_max <= 4 for the largest eigenvalue of the
+    // discrete radial operators (see radial_mu_max)
+    double mu_em = 0.0, mu_half = 0.0;
+    radial_mu_max(g.nr, g.dr, modes, g.r_bc == QDS_R_PEC, &mu_em, &mu_half);
+    if (dt * dt * mu_em > 4.0 * (1.0 + 1e-12))
+        return fail(nullptr, QDS_ECFL, "radial stability bound dt^2 mu_max <= 4 fails%s");
 
     qds_ctx* c = new (std::nothrow) qds_ctx();
     if (!c) return fail(nullptr, QDS_ENOMEM, "out of host memory%s");
     c->g = g;
     c->M = modes;
     c->h = dx;
+    c->mu_half = mu_half;
     c->ld = (g.nx + 31) / 32 * 32;
     c->plane_elems = size_t(modes) * size_t(g.nr + 1) * size_t(c->ld);
     c->elem_bytes = g.dtype == QDS_F64 ? 16 : 8;
@@ -505,6 +606,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
         if (last_col >= (int64_t(1) << 20))
             return fail(h, QDS_ESTATE, "drive noise counter: lab column would reach 2^20 (window + nx + n_steps)%s");
     }
+    // the Klein-Gordon operator adds m_a^2 to the half-row radial operator
+    if (axion && has(h, QDS_P_PHI) && h->h * h->h * (h->mu_half + axion->ma2) > 4.0 * (1.0 + 1e-12))
+        return fail(h, QDS_ECFL, "axion stability bound dt^2 (mu_max + m_a^2) <= 4 fails%s");
     if (h->g.dtype == QDS_F64) return run_steps<double>(h, fields, J, axion, n_steps, hipStream_t(stream));
     return run_steps<float>(h, fields, J, axion, n_steps, hipStream_t(stream));
 }

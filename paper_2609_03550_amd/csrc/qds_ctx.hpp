@@ -11,6 +11,7 @@ struct qds_ctx {
     qds_grid g;
     int M;
     double h;
+    double mu_half;          // largest eigenvalue of the half-row radial operator (Klein-Gordon bound)
     int ld;
     size_t plane_elems;      // complex elements per plane
     size_t elem_bytes;       // 16 (F64) or 8 (F32)

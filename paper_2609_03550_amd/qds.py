@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_loss_eval.restype = i32
     lib.qds_loss_eval_noalloc.argtypes = [vp, vp, ctypes.POINTER(Loss), vp, vp]
     lib.qds_loss_eval_noalloc.restype = i32
+    lib.qds_radial_mu_max.argtypes = [i32, dbl, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.qds_radial_mu_max.restype = i32
     lib.qds_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     lib.qds_batch_create.restype = i32
     lib.qds_batch_run.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion),

@@ -131,10 +131,10 @@ def test_em_dispersion_factorises(m):
     ph = Q.Physics()
     lam1, mu1 = _mu_set(g, ph, EM_KEYS, m, 1)
     lam3, mu3 = _mu_set(g, ph, EM_KEYS, m, 3)
-    assert np.abs(np.abs(lam1) - 1).max() < 1e-6
-    assert np.abs(np.abs(lam3) - 1).max() < 1e-6
+    assert np.abs(np.abs(lam1) - 1).max() < 1e-12
+    assert np.abs(np.abs(lam3) - 1).max() < 1e-12
     assert len(mu1) == len(mu3)
-    assert np.abs(mu1 - mu3).max() < 1e-6 * max(1.0, np.abs(mu1).max())
+    assert np.abs(mu1 - mu3).max() < 1e-12 * max(1.0, np.abs(mu1).max())
     assert mu1.min() > -1e-9
     assert mu1.max() * H * H <= 4.0           # stable: (c dt)^2 mu_max <= 4
 
@@ -170,8 +170,9 @@ def test_kg_dispersion_factorises_and_converges(m):
     ph = Q.Physics(axion=True, ma2=ma2)
     lam1, mu1 = _mu_set(g, ph, KG_KEYS, m, 1)
     lam3, mu3 = _mu_set(g, ph, KG_KEYS, m, 3)
-    assert np.abs(np.abs(lam1) - 1).max() < 1e-9
-    assert np.abs(mu1 - mu3).max() < 1e-8
+    assert np.abs(np.abs(lam1) - 1).max() < 1e-12
+    assert np.abs(np.abs(lam3) - 1).max() < 1e-12
+    assert np.abs(mu1 - mu3).max() < 1e-12
     assert mu1.min() > ma2 - 1e-9
     errs = []
     Rp = 10.5 * DR
