@@ -181,14 +181,21 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 height for each kernel; the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream
  *                 once, after the trials.
+ *  QDS_OPT_PRODUCTS QDS_PRODUCTS_DIRECT (default): the mode products of the
+ *                 axion source and current by the direct convolution C_m
+ *                 (Eq. mode_convolution); QDS_PRODUCTS_THETA: by a transform
+ *                 pair through a theta grid of 3*modes - 2 points, exact for
+ *                 modes 0..modes-1 (Sec. 3.3), on the staged kernels (the
+ *                 handle then runs the staged path)
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
  *                 value resets the recorded launches */
 enum {
     QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
-    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7
+    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8
 };
+enum { QDS_PRODUCTS_DIRECT = 0, QDS_PRODUCTS_THETA = 1 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
 qds_status qds_set_option(qds_handle h, int32_t key, int64_t value);
 

@@ -637,6 +637,11 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
         case QDS_OPT_TUNE:
             h->tune = value ? 1 : 0;
             return QDS_OK;
+        case QDS_OPT_PRODUCTS:
+            if (value != QDS_PRODUCTS_DIRECT && value != QDS_PRODUCTS_THETA)
+                return fail(h, QDS_EINVAL, "products must be QDS_PRODUCTS_DIRECT or QDS_PRODUCTS_THETA%s");
+            h->theta = value == QDS_PRODUCTS_THETA ? 1 : 0;
+            return QDS_OK;
         case QDS_OPT_TIMING:
             h->timing = value ? 1 : 0;
             h->used = 0;

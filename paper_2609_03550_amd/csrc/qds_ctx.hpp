@@ -20,6 +20,7 @@ struct qds_ctx {
     void* scratch;           // axion-current planes (3) and S_a, library owned
     void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0 (allocated on first use)
     int path;                // QDS_PATH_*
+    int theta;               // QDS_PRODUCTS_THETA: theta-grid products (staged path)
     int rows;                // the last QDS_OPT_ROWS value (also copied into trows)
     int trows[3];            // tile heights of the table-driven kernels: A, current, B
     int tune;                // autotune the tile heights on the next long enough qds_step
@@ -102,7 +103,7 @@ inline bool fused_ok(const qds_ctx* c) {
 }
 
 inline bool use_fused(const qds_ctx* c) {
-    if (c->path == QDS_PATH_STAGED) return false;
+    if (c->path == QDS_PATH_STAGED || c->theta) return false;
     return fused_ok(c);
 }
 
@@ -126,6 +127,7 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
     p.plasma = has(c, QDS_P_JX);
     p.axion = has(c, QDS_P_PHI);
     p.arem = has(c, QDS_P_SET1);
+    p.theta = c->theta;
     p.wp2 = J ? J->wp2 : 0.0;
     if (!p.plasma) p.wp2 = 0.0;
     p.ma2 = ax ? ax->ma2 : 0.0;

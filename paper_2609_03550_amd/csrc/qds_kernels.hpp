@@ -90,6 +90,7 @@ struct StepPlan {
     cx<T>* sa;                  // scratch S_a plane (regenerated set only)
     cx<T>* jdrv;                // drive plane (j_x^(0) of mode 0; null until first used)
     int plasma, axion, arem;
+    int theta;                  // staged path: theta-grid products instead of the direct convolution
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
     Drive drive;

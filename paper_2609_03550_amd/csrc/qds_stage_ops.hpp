@@ -82,7 +82,9 @@ struct BgView {
 // T_th^+- +- b_r).  For co-propagating waves each product then pairs a large
 // factor with a small one, where the E/B form subtracts two large products;
 // the single-precision forward uses it for that reason.
-template <typename T, bool TFORM = false>
+// PART selects one component's six factors (0: j_a,x into f[0..5],
+// 1: j_a,theta into f[6..11], 2: j_a,r into f[12..17]); -1 forms all 18.
+template <typename T, bool TFORM = false, int PART = -1>
 __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f) {
     const Geo& g = a.g;
     BgView<T> v{&a};
@@ -95,7 +97,7 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
     const T par = parity<T>(m);
     const T tg = tghost<T>(m);
     // ---------------- j_a,x
-    {
+    if constexpr (PART < 0 || PART == 0) {
         cx<T> bhi = T(0.5) * (ld(a.A0.bx + g.at(m, j, i)) + ld(a.B0.bx + g.at(m, j, i)));
         cx<T> blo = ax ? par * bhi : T(0.5) * (ld(a.A0.bx + g.at(m, j - 1, i)) + ld(a.B0.bx + g.at(m, j - 1, i)));
         f[0] = T(0.5) * (blo + bhi);
@@ -128,7 +130,8 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
         f[5] = (T(1) / dr) * (phi_hi - phi_lo);
     }
     // ---------------- j_a,theta
-    if constexpr (TFORM) {
+    if constexpr (PART >= 0 && PART != 1) {
+    } else if constexpr (TFORM) {
         // T_r^+- averaged over t^n, t^{n+1} at (i or i1, j+1/2)
         auto tr = [&](const cx<T>* p0, const cx<T>* p1, int k, int c) {
             return T(0.5) * (ldx(p0, g, m, k, c) + ldx(p1, g, m, k, c));
@@ -213,7 +216,8 @@ __device__ void ja_factors(const AxionArgs<T>& a, int m, int i, int j, cx<T>* f)
         f[9] = (T(1) / dr) * (ph - pl);
     }
     // ---------------- j_a,r
-    if constexpr (TFORM) {
+    if constexpr (PART >= 0 && PART != 2) {
+    } else if constexpr (TFORM) {
         cx<T> sp = zero<T>(), sm = zero<T>();
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) {

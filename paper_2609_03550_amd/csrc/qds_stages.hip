@@ -246,14 +246,91 @@ __global__ void __launch_bounds__(256) k_ghost_bth(StageArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// theta-grid evaluation of the mode products (Sec. 3.3: transform the factors
+// to a discrete theta grid, multiply pointwise, transform back), in place of
+// the direct convolution C_m.  A product of two fields with modes below M
+// has modes up to 2M - 2; on N equispaced points the coefficient of mode
+// m < M picks up the alias N - m of the product, so N = 3M - 2 points are the
+// fewest that leave modes 0..M-1 exact.  At these N a table-driven DFT (the
+// table in LDS, filled once per block) does the transforms.  Real samples see
+// only Re A^(0); the literal convolution's mode 0 uses the complex product
+// A^(0) B^(0) (while its modes m >= 1 use Re A^(0), Re B^(0) like the grid),
+// so the difference A^(0) B^(0) - Re A^(0) Re B^(0) is added to mode 0.
+// ---------------------------------------------------------------------------
+template <int M>
+__host__ __device__ constexpr int theta_points() { return 3 * M - 2; }
+
+template <int M>
+__device__ void theta_table(double* tc, double* ts) {
+    constexpr int N = theta_points<M>();
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int q = t; q < M * N; q += blockDim.x * blockDim.y) {
+        const int m = q / N, k = q % N;
+        double sn, cs;
+        sincospi(2.0 * double((m * k) % N) / double(N), &sn, &cs);
+        tc[q] = cs;
+        ts[q] = sn;
+    }
+    __syncthreads();
+}
+
+// Re sum_m A^(m) e^{-i m theta_k}
+template <typename T, int M>
+__device__ __forceinline__ T theta_eval(const cx<T>* A, const double* tc, const double* ts, int k) {
+    constexpr int N = theta_points<M>();
+    T v = A[0].re;
+#pragma unroll
+    for (int m = 1; m < M; ++m) v += A[m].re * T(tc[m * N + k]) + A[m].im * T(ts[m * N + k]);
+    return v;
+}
+
+// out^(m) += (1 or 2)/N p_k e^{i m theta_k}
+template <typename T, int M>
+__device__ __forceinline__ void theta_project(T p, cx<T>* out, const double* tc, const double* ts, int k) {
+    constexpr int N = theta_points<M>();
+    const T w0 = T(1.0 / N), w = T(2.0 / N);
+    out[0].re += w0 * p;
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+        out[m].re += (w * p) * T(tc[m * N + k]);
+        out[m].im += (w * p) * T(ts[m * N + k]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void theta_mode0_fix(cx<T> a, cx<T> b, T sign, cx<T>& out0) {
+    out0 = out0 + sign * cx<T>{-a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// out += s0 C{A0, B0} + s1 C{A1, B1} + s2 C{A2, B2} on the theta grid
+template <typename T, int M>
+__device__ __forceinline__ void theta_acc3(const cx<T>* A0, const cx<T>* B0, T s0, const cx<T>* A1, const cx<T>* B1,
+                                           T s1, const cx<T>* A2, const cx<T>* B2, T s2, cx<T>* out,
+                                           const double* tc, const double* ts) {
+    constexpr int N = theta_points<M>();
+#pragma unroll 2
+    for (int k = 0; k < N; ++k) {
+        const T p = s0 * theta_eval<T, M>(A0, tc, ts, k) * theta_eval<T, M>(B0, tc, ts, k) +
+                    s1 * theta_eval<T, M>(A1, tc, ts, k) * theta_eval<T, M>(B1, tc, ts, k) +
+                    s2 * theta_eval<T, M>(A2, tc, ts, k) * theta_eval<T, M>(B2, tc, ts, k);
+        theta_project<T, M>(p, out, tc, ts, k);
+    }
+    theta_mode0_fix(A0[0], B0[0], s0, out[0]);
+    theta_mode0_fix(A1[0], B1[0], s1, out[0]);
+    theta_mode0_fix(A2[0], B2[0], s2, out[0]);
+}
+
+// ---------------------------------------------------------------------------
 // stage 4: axion source S_a, Gamma_a and the T_a shift (Eqs.
 // mode_convolution, Ta_plus_update, Ta_minus_update, axion_x_open)
 // ---------------------------------------------------------------------------
-template <typename T, int M>
+template <typename T, int M, bool THETA>
 __global__ void __launch_bounds__(256) k_axion_ta(AxionArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    __shared__ double tc[THETA ? M * theta_points<M>() : 1], ts[THETA ? M * theta_points<M>() : 1];
+    if constexpr (THETA) theta_table<M>(tc, ts);
     if (i >= g.nx || k >= g.nr) return;
     const T h = T(g.h), dr = T(g.dr);
     const bool live = g.per || i < g.nx - 1;
@@ -287,9 +364,13 @@ __global__ void __launch_bounds__(256) k_axion_ta(AxionArgs<T> a) {
             Qp[1] = Qp[1] + a.br1;
             Qm[1] = Qm[1] - a.br1;
         }
-        conv_acc<T, M>(Ex, Bx, T(1), S);
-        conv_acc<T, M>(Pp, Qp, T(1), S);
-        conv_acc<T, M>(Pm, Qm, T(1), S);
+        if constexpr (THETA) {
+            theta_acc3<T, M>(Ex, Bx, T(1), Pp, Qp, T(1), Pm, Qm, T(1), S, tc, ts);
+        } else {
+            conv_acc<T, M>(Ex, Bx, T(1), S);
+            conv_acc<T, M>(Pp, Qp, T(1), S);
+            conv_acc<T, M>(Pm, Qm, T(1), S);
+        }
     }
     const T rk = (T(k) + T(0.5)) * dr;
 #pragma unroll
@@ -341,34 +422,68 @@ __global__ void __launch_bounds__(256) k_axion_phi(AxionArgs<T> a) {
 // jar_mode, jat_mode) at the source points x_{i+1/2}: j_a,x at (r_j, t^n),
 // j_a,r at (r_{j+1/2}, t^{n+1/2}), j_a,theta at (r_j, t^{n+1/2})
 // ---------------------------------------------------------------------------
-template <typename T, int M>
+// One component of the axion current (PART 0: j_a,x, 1: j_a,theta, 2: j_a,r):
+// out += C{f0, f1} - C{f2, f3} + C{f4, f5} of that component's factors.
+template <typename T, int M, bool THETA, int PART>
+__device__ __forceinline__ void comp_products(const AxionArgs<T>& a, int i, int j, cx<T>* out, const double* tc,
+                                              const double* ts) {
+    cx<T> F[6][M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        cx<T> f[18];
+        ja_factors<T, true, PART>(a, m, i, j, f);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) F[q][m] = f[6 * PART + q];
+    }
+    if constexpr (THETA) {
+        theta_acc3<T, M>(F[0], F[1], T(1), F[2], F[3], T(-1), F[4], F[5], T(1), out, tc, ts);
+    } else {
+        conv_acc<T, M>(F[0], F[1], T(1), out);
+        conv_acc<T, M>(F[2], F[3], T(-1), out);
+        conv_acc<T, M>(F[4], F[5], T(1), out);
+    }
+}
+
+template <typename T, int M, bool THETA>
 __global__ void __launch_bounds__(256) k_axion_current(AxionArgs<T> a) {
     const Geo& g = a.g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    __shared__ double tc[THETA ? M * theta_points<M>() : 1], ts[THETA ? M * theta_points<M>() : 1];
+    if constexpr (THETA) theta_table<M>(tc, ts);
     if (i >= g.nx || j > g.nr) return;
     const bool live = g.per || i < g.nx - 1;
     cx<T> jx[M], jr[M], jt[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) jx[m] = jr[m] = jt[m] = zero<T>();
     if (live && j < g.nr) {
-        cx<T> F[18][M];
+        if constexpr (THETA) {
+            // one component at a time (its six factor arrays): the theta-grid
+            // products of the many-mode cases then stay close to the register
+            // file (the direct convolution spills more this way and keeps all
+            // 18 factor arrays)
+            comp_products<T, M, THETA, 0>(a, i, j, jx, tc, ts);
+            comp_products<T, M, THETA, 1>(a, i, j, jt, tc, ts);
+            comp_products<T, M, THETA, 2>(a, i, j, jr, tc, ts);
+        } else {
+            cx<T> F[18][M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            cx<T> f[18];
-            ja_factors<T, true>(a, m, i, j, f);
+            for (int m = 0; m < M; ++m) {
+                cx<T> f[18];
+                ja_factors<T, true>(a, m, i, j, f);
 #pragma unroll
-            for (int q = 0; q < 18; ++q) F[q][m] = f[q];
+                for (int q = 0; q < 18; ++q) F[q][m] = f[q];
+            }
+            conv_acc<T, M>(F[0], F[1], T(1), jx);
+            conv_acc<T, M>(F[2], F[3], T(-1), jx);
+            conv_acc<T, M>(F[4], F[5], T(1), jx);
+            conv_acc<T, M>(F[6], F[7], T(1), jt);
+            conv_acc<T, M>(F[8], F[9], T(-1), jt);
+            conv_acc<T, M>(F[10], F[11], T(1), jt);
+            conv_acc<T, M>(F[12], F[13], T(1), jr);
+            conv_acc<T, M>(F[14], F[15], T(-1), jr);
+            conv_acc<T, M>(F[16], F[17], T(1), jr);
         }
-        conv_acc<T, M>(F[0], F[1], T(1), jx);
-        conv_acc<T, M>(F[2], F[3], T(-1), jx);
-        conv_acc<T, M>(F[4], F[5], T(1), jx);
-        conv_acc<T, M>(F[6], F[7], T(1), jt);
-        conv_acc<T, M>(F[8], F[9], T(-1), jt);
-        conv_acc<T, M>(F[10], F[11], T(1), jt);
-        conv_acc<T, M>(F[12], F[13], T(1), jr);
-        conv_acc<T, M>(F[14], F[15], T(-1), jr);
-        conv_acc<T, M>(F[16], F[17], T(1), jr);
     }
     const T sj = T(a.s_j);
 #pragma unroll
@@ -435,14 +550,18 @@ __global__ void __launch_bounds__(256) k_add_pulse(SetPtr<T> s, Geo g, int pol, 
 // host-side launch sequence of the staged step
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-static void launch_axion(AxionArgs<T>& ax, bool arem, hipStream_t s) {
+static void launch_axion(AxionArgs<T>& ax, bool arem, bool theta, hipStream_t s) {
     const Geo& g = ax.g;
     dim3 blk(64, 4);
     dim3 grdK((g.nx + 63) / 64, (g.nr + 3) / 4);
     dim3 grdJ((g.nx + 63) / 64, (g.nr + 1 + 3) / 4);
-    hipLaunchKernelGGL((k_axion_ta<T, M>), grdK, blk, 0, s, ax);
+    if (theta) hipLaunchKernelGGL((k_axion_ta<T, M, true>), grdK, blk, 0, s, ax);
+    else hipLaunchKernelGGL((k_axion_ta<T, M, false>), grdK, blk, 0, s, ax);
     hipLaunchKernelGGL(k_axion_phi<T>, grdK, blk, 0, s, ax);
-    if (arem) hipLaunchKernelGGL((k_axion_current<T, M>), grdJ, blk, 0, s, ax);
+    if (arem) {
+        if (theta) hipLaunchKernelGGL((k_axion_current<T, M, true>), grdJ, blk, 0, s, ax);
+        else hipLaunchKernelGGL((k_axion_current<T, M, false>), grdJ, blk, 0, s, ax);
+    }
 }
 
 template <typename T>
@@ -459,7 +578,7 @@ hipError_t staged_step(const StepPlan<T>& p, hipStream_t s) {
     if (p.axion) {
         AxionArgs<T> ax = p.axion_args();
         switch (g.M) {
-#define QDS_AX_CASE(MM) case MM: launch_axion<T, MM>(ax, p.arem, s); break;
+#define QDS_AX_CASE(MM) case MM: launch_axion<T, MM>(ax, p.arem, p.theta != 0, s); break;
             QDS_AX_CASE(1) QDS_AX_CASE(2) QDS_AX_CASE(3) QDS_AX_CASE(4)
             QDS_AX_CASE(5) QDS_AX_CASE(6) QDS_AX_CASE(7) QDS_AX_CASE(8)
 #undef QDS_AX_CASE
