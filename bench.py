@@ -138,46 +138,64 @@ def adjoint_ratio(dtype, steps, ckpt):
             "fwd_adj_s": t_adj, "ratio": t_adj / t_fwd, "loss": L}
 
 
-def batched_leg(steps, graph_steps, count=64):
-    """The 64 uneven single-precision instances: ``steps`` batched steps
-    (graphs of ``graph_steps`` steps, tiles from the autotuner) against the
-    same steps taken one instance at a time with qds_step (each instance with
-    the tiles its own autotuner chose)."""
+def batched_leg(step_scale, graph_steps, count=64):
+    """The 64 uneven single-precision instances, each for its own seeded step
+    count (500..3000) times ``step_scale``, so that instances finish at
+    different steps and the set of running instances changes along the run:
+    the batch (one launch per kernel class per step over every running
+    instance, ``graph_steps`` steps per HIP graph, tiles from the batch's
+    autotuner) against the same schedule launched without graphs and against
+    each instance advanced alone with qds_step (each with the tiles its own
+    autotuner chose).  Graphs are captured on an untimed first pass of the
+    schedule and replayed on the timed one."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
     wls = I.batched_instances(count, 4)
+    steps = [max(1, int(round(wl.steps * step_scale))) for wl in wls]
     bs = []
     for wl in wls:
         s = qds.Solver(wl, dtype="f32")
         s.load_pulses()
         bs.append(s)
-    cells = sum(wl.cell_modes for wl in wls)
+    updates = sum(wl.cell_modes * n for wl, n in zip(wls, steps))
     b = qds.Batch(bs)
     b.run(8, graph_steps=graph_steps, tune=True)       # the autotuner's trial steps
-    b.run(graph_steps, graph_steps=graph_steps)        # capture
+    b.run(steps, graph_steps=graph_steps)              # capture pass
     torch.cuda.synchronize()
+    s0 = b.stats()
     t0 = time.perf_counter()
     b.run(steps, graph_steps=graph_steps)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    s1 = b.stats()
+    t0 = time.perf_counter()
+    b.run(steps, graph_steps=0)
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t0
+    s2 = b.stats()
     for s in bs:
         s.set_option(qds.OPT_TUNE, 1)      # each instance's own autotuner, untimed
         s.step(8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in bs:
-        s.step(steps)
+    for s, n in zip(bs, steps):
+        s.step(n)
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
     tiles, tuned = b.tiles()
     b.close()
     for s in bs:
         s.close()
-    return {"instances": count, "dtype": "f32", "cell_modes_per_step": cells, "steps": steps,
-            "graph_steps": graph_steps, "tiles": tiles, "tuned": tuned,
-            "batched_updates_per_s": cells * steps / t_batch, "one_at_a_time_updates_per_s": cells * steps / t_solo,
-            "speedup": t_solo / t_batch}
+    kernel_launches_direct = s2[2] - s1[2]
+    return {"instances": count, "dtype": "f32", "steps_per_instance": {"min": min(steps), "max": max(steps),
+                                                                        "scale": step_scale},
+            "cell_mode_updates": updates, "graph_steps": graph_steps, "tiles": tiles, "tuned": tuned,
+            "graph_launches_per_run": s1[0] - s0[0], "kernel_launches_per_run": kernel_launches_direct,
+            "batched_updates_per_s": updates / t_batch, "batched_no_graph_updates_per_s": updates / t_direct,
+            "one_at_a_time_updates_per_s": updates / t_solo, "speedup": t_solo / t_batch,
+            "graph_gain_s": t_direct - t_batch,
+            "launch_overhead_us_per_kernel": (t_direct - t_batch) / max(kernel_launches_direct, 1) * 1e6}
 
 
 def f32_leg(wl, steps):
@@ -206,6 +224,39 @@ def f32_leg(wl, steps):
     return {"dtype": "f32", "steps": steps, "ms_per_step": ms, "value": wl.cell_modes / (ms / 1e3),
             "unit": "cell-mode updates/s", "roofline_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
             "tiles": tiles[0]}
+
+
+def theta_leg(steps=20):
+    """Axion source and current by the theta-grid transform pair against the
+    direct mode convolution, both on the staged kernels: 6 and 8 modes of the
+    full physics on a 2048 x 64 grid with dr = 8 dx (what the radial stability
+    bound allows for 8 modes), FP64, ``steps`` timed steps after 3 untimed."""
+    import torch
+    from paper_2609_03550_amd import inputs as I
+    from paper_2609_03550_amd import qds
+    out = {}
+    for M in (6, 8):
+        p1 = I.Pulse("y", 0.5, 1.0, 12 * I.LAMBDA, 299.8 * I.H, 1100 * I.H)
+        p2 = I.Pulse("z", 0.5, 0.8, 12 * I.LAMBDA, 299.8 * I.H, 1100 * I.H)
+        wl = I.Workload(f"theta_2048x64x{M}", 2048, 64, M, 0, wp2=5.7407e-5, axion=True, arem=True, ma2=2.325e-4,
+                        pulses=(p1, p2), dr=8 * I.H)
+        res = {}
+        for name, prod in (("direct", qds.PRODUCTS_DIRECT), ("theta", qds.PRODUCTS_THETA)):
+            s = qds.Solver(wl, dtype="f64", path=qds.PATH_STAGED)
+            s.set_option(qds.OPT_PRODUCTS, prod)
+            s.load_pulses()
+            s.step(3)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            res[name + "_ms_per_step"] = e0.elapsed_time(e1) / steps
+            s.close()
+        res["theta_over_direct"] = res["theta_ms_per_step"] / res["direct_ms_per_step"]
+        out[f"modes_{M}"] = res
+    return out
 
 
 def stream_reference(nbytes=1 << 31, reps=10):
@@ -272,9 +323,12 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward + adjoint timing (0 skips it)")
     ap.add_argument("--ckpt-every", type=int, default=45)
-    ap.add_argument("--batched-steps", type=int, default=40,
-                    help="steps of the 64-instance batched comparison (0 skips it)")
+    ap.add_argument("--batched-scale", type=float, default=0.04,
+                    help="factor on the 64 instances' seeded step counts (500..3000) for the batched "
+                         "comparison (0 skips it)")
     ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--theta-steps", type=int, default=20,
+                    help="steps of the theta-grid vs direct product comparison at 6 and 8 modes (0 skips it)")
     ap.add_argument("--f32-steps", type=int, default=100,
                     help="steps of the single-precision figure of the same workload (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -386,11 +440,14 @@ def main():
         out["fwd_adj_over_fwd"] = adj["ratio"]
         out["adjoint"] = adj
         torch.cuda.empty_cache()
-    if args.batched_steps > 0:
-        out["batched"] = batched_leg(args.batched_steps, args.graph_steps)
+    if args.batched_scale > 0:
+        out["batched"] = batched_leg(args.batched_scale, args.graph_steps)
         torch.cuda.empty_cache()
     if args.f32_steps > 0 and args.dtype == "f64" and args.workload == "axion":
         out["f32"] = f32_leg(wl, args.f32_steps)
+        torch.cuda.empty_cache()
+    if args.theta_steps > 0:
+        out["theta_grid_products"] = theta_leg(args.theta_steps)
         torch.cuda.empty_cache()
     out["stream_reference"] = stream_reference()
     out["roofline"]["frac_of_copy"] = achieved / out["stream_reference"]["copy_read_write_gbps"]

@@ -319,6 +319,12 @@ qds_status qds_batch_get_tiles(qds_batch b, int32_t* tiles, int32_t* tuned);
 /* Sets the tile heights (each 1..1024) and marks them as chosen. */
 qds_status qds_batch_set_tiles(qds_batch b, const int32_t* tiles);
 
+/* Launch counters since the batch was created (int64[4]): graph launches,
+ * graphs instantiated, kernel launches issued outside graphs (graph_steps 0
+ * and the autotuner's trial steps are not counted), and kernel launches
+ * carried by the launched graphs. */
+qds_status qds_batch_stats(qds_batch b, int64_t* stats);
+
 const char* qds_batch_last_error(qds_batch b);
 
 /* Waits for the batch's last run and releases its graphs and tables. */

@@ -55,6 +55,9 @@ struct qds_batch_ctx {
     std::vector<Plan*> plans;           // plans and graphs, kept while the tables are unchanged
     hipEvent_t done = nullptr;
     bool pending = false;
+    // counters since creation: graph launches, graphs instantiated, kernel
+    // launches outside graphs, kernel launches inside the launched graphs
+    int64_t stats[4] = {0, 0, 0, 0};
     char err[256];
 };
 
@@ -317,6 +320,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 e = launch_step<T>(b, *P, int((t + u) & 1), s, nullptr);
                 if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
             }
+            b->stats[2] += rem * int64_t(P->launches.size());
             t += rem;
             continue;
         }
@@ -342,9 +346,12 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                     return bfail(b, QDS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
                 }
                 it = P->graphs.emplace(key, std::make_pair(g, x)).first;
+                b->stats[1] += 1;
             }
             e = hipGraphLaunch(it->second.second, s);
             if (e != hipSuccess) return bfail(b, QDS_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+            b->stats[0] += 1;
+            b->stats[3] += int64_t(seg) * int64_t(P->launches.size());
             t += seg;
             rem -= seg;
         }
@@ -429,6 +436,12 @@ qds_status qds_batch_set_tiles(qds_batch b, const int32_t* tiles) {
         if (tiles[q] < 1 || tiles[q] > 1024) return bfail(b, QDS_EINVAL, "tile heights must be 1..1024%s");
     for (int q = 0; q < QDS_NTILES; ++q) b->tiles[q] = tiles[q];
     b->tuned = 1;
+    return QDS_OK;
+}
+
+qds_status qds_batch_stats(qds_batch b, int64_t* stats) {
+    if (!b || !stats) return bfail(b, QDS_EINVAL, "null argument%s");
+    for (int q = 0; q < 4; ++q) stats[q] = b->stats[q];
     return QDS_OK;
 }
 

@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_batch_get_tiles.restype = i32
     lib.qds_batch_set_tiles.argtypes = [vp, ctypes.POINTER(i32)]
     lib.qds_batch_set_tiles.restype = i32
+    lib.qds_batch_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.qds_batch_stats.restype = i32
     lib.qds_batch_last_error.argtypes = [vp]
     lib.qds_batch_last_error.restype = ctypes.c_char_p
     lib.qds_batch_destroy.argtypes = [vp]
@@ -466,6 +468,13 @@ class Batch:
         tuned = ctypes.c_int32()
         _bcheck(lib().qds_batch_get_tiles(self.b, t, ctypes.byref(tuned)), self.b)
         return list(t), bool(tuned.value)
+
+    def stats(self):
+        """(graph launches, graphs instantiated, kernel launches outside graphs,
+        kernel launches inside launched graphs) since creation."""
+        v = (ctypes.c_int64 * 4)()
+        _bcheck(lib().qds_batch_stats(self.b, v), self.b)
+        return list(v)
 
     def set_tiles(self, tiles) -> None:
         t = (ctypes.c_int32 * NTILES)(*[int(v) for v in tiles])
