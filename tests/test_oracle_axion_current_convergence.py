@@ -243,3 +243,67 @@ def test_odd_ghost_for_every_mode_fails_the_pin(fields, monkeypatch):
         self.tpar = torch.tensor([-1.0] * g.nmodes, dtype=Q.RDT).view(-1, 1)
     monkeypatch.setattr(Q._Ctx, "__init__", init)
     assert pin_failures(_errors(fields)) != []
+
+
+def _source_errors(F, form="transport", shift=None):
+    """Per level: r-weighted L2, axis-row and fixed-radius errors of the
+    oracle's S_a = E.B at (x_{i+1/2}, r_{j+1/2}, t^n) against the Cartesian
+    dot product of the analytic fields."""
+    out = []
+    for nx, nr, h, dr in LEVELS:
+        g = Q.Grid(nx, nr, M, h, dr, "open", "open")
+        c = Q._Ctx(g)
+        xI = np.arange(nx) * h
+        xH = xI + 0.5 * h
+        rK = (np.arange(nr + 1) + 0.5) * dr
+        rJ = np.arange(nr + 1) * dr
+
+        def smp(name, xs, rs, t):
+            if shift and shift[0] == name:
+                xs, rs = (xs + 0.5 * h, rs) if shift[1] == "x" else (xs, rs + 0.5 * dr)
+            return F.modes(name, xs, rs, t)
+
+        def state(t, te):
+            Er, Bt = smp("Er", xI, rK[:nr], t), smp("Bt", xI, rK[:nr], t)
+            Et, Br = smp("Et", xI, rJ, t), smp("Br", xI, rJ, t)
+            return {"Trp0": Er + Bt, "Trm0": Er - Bt, "Ttp0": Et + Br, "Ttm0": Et - Br,
+                    "Ex0": smp("Ex", xH, rJ, te), "Bx0": smp("Bx", xH, rK, te)}
+        f = Q._bg_fields(c, state(0.0, -0.5 * h), state(h, 0.5 * h), (0j, 0j, 0j))
+        S = Q.axion_source(c, f, (0j, 0j, 0j), form).numpy()
+        Tn = 16
+        th = 2 * math.pi * np.arange(Tn) / Tn
+        g_ = {k: F.real(k, xH, rK[:nr], 0.0, th) for k in ("Ex", "Er", "Et", "Bx", "Br", "Bt")}
+        dot = g_["Ex"] * g_["Bx"] + g_["Er"] * g_["Br"] + g_["Et"] * g_["Bt"]
+        ee = np.exp(1j * np.outer(np.arange(M), th))
+        ref = np.einsum("mt,trx->mrx", ee, dot) / Tn
+        ref[1:] *= 2
+        sl = slice(3, nx - 3)
+        d, ref = S[:, : nr - 1, sl], ref[:, : nr - 1, sl]
+        rr = rK[: nr - 1]
+        err = np.abs(d - ref) / np.abs(ref).max()
+        w = rr * dr * h
+        l2 = np.sqrt((err ** 2 * w[None, :, None]).sum() / (w.sum() * err.shape[0] * err.shape[2]))
+        out.append((l2, err[:, 0].max(), err[:, rr >= R_BAND].max()))
+    return out
+
+
+def _source_failures(errs):
+    bad = []
+    for which in range(3):
+        e = [lev[which] for lev in errs]
+        if not (e[0] / e[1] >= 3.5 and e[1] / e[2] >= 3.5 and e[2] < 2e-3):
+            bad.append((["r-weighted L2", "first half row", "r >= 1"][which], e))
+    return bad
+
+
+@pytest.mark.parametrize("form", ["transport", "eb"])
+def test_axion_source_converges_at_second_order(fields, form):
+    """S_a (Eqs. source_mode_zero, source_mode_m: E.B of the background set
+    brought to (x_{i+1/2}, r_{j+1/2}) at t^n) converges at second order to
+    the Cartesian dot product of the analytic fields, in both product orders."""
+    assert _source_failures(_source_errors(fields, form)) == []
+
+
+@pytest.mark.parametrize("shift", [("Er", "r"), ("Et", "r"), ("Br", "x"), ("Bt", "x"), ("Ex", "r"), ("Bx", "x")])
+def test_source_half_cell_shift_breaks_second_order(fields, shift):
+    assert _source_failures(_source_errors(fields, shift=shift)) != [], shift
