@@ -271,6 +271,49 @@ qds_status qds_loss_eval_noalloc(qds_handle h, const void* buf, const qds_loss* 
 /* Adds Re sum conj(a) b over two state buffers to *out_dev (a device double). */
 qds_status qds_dot(qds_handle h, const void* a, const void* b, double* out_dev, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Particles of the PIC coupling (Sec. 3.1): field gather (Eq.
+ * particle_field_gather), relativistic Boris push (Eqs. boris_parameters,
+ * boris_update) and the charge-conserving modal current deposition (Eqs.
+ * particle_deposition_path, particle_mode_weight, particle_modal_currents,
+ * particle_azimuthal_current, face_current_x, face_current_r), which makes
+ * the deposited current obey Eq. discrete_continuity in every retained mode.
+ * Units: c = 1, momenta u = p/(m c), fields as in the state, charge-to-mass
+ * ratio qm in code units (-1 for electrons), currents added to the planes in
+ * the units of the field equations (d_t E = curl B - j).
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    double* x; double* y; double* z;       /* Cartesian positions at t^n (device, float64), updated to t^{n+1} */
+    double* ux; double* uy; double* uz;    /* u at t^{n-1/2}, updated to t^{n+1/2} */
+    const double* q;                       /* per-particle macro-charge Q_p (device), or NULL: ``charge`` each */
+    int64_t count;
+    double charge;
+    double qm;
+} qds_particles;
+
+/* Advance every particle one step dt = dx in the fields of fields->buf[cur]
+ * and add its current at t^{n+1/2} to three caller-owned planes (each
+ * [modes][nr+1][row pitch] complex in the handle's dtype, the layout of a
+ * state plane; not cleared): jx at (x_{i+1/2}, r_j) (half column i), jr at
+ * (x_i, r_{j+1/2}) (row j), jt at (x_i, r_j).
+ *  - Gather: transverse fields at t^n from T^n of the background set; E_x and
+ *    B_x at t^{n-1/2}, or, with extrapolate != 0, extrapolated to t^n as
+ *    3/2 F^{n-1/2} - 1/2 F^{n-3/2} with F^{n-3/2} from fields->buf[1 - cur]
+ *    (the previous state after a qds_step).  The QDS B_x, B_r, B_theta are
+ *    averaged along x onto x_i, x_{i+1/2}, x_{i+1/2} first.  Triangular shape
+ *    (quadratic-spline weights on each grid); weights on rows below the axis
+ *    go to the mirror row.
+ *  - Push: Boris with dt = dx, then x^{n+1} = x^n + dt u^{n+1/2}/gamma.
+ *  - Deposit: along x^n -> x^{n+1}; the angular current carries the path's
+ *    angular displacement (j_theta = Q dtheta <g_x g_r>_m / (2 pi dx dr dt)),
+ *    areas and volumes of the axis row with r_0 -> dr/8.
+ * A particle whose old or new position leaves 2 <= x/dx <= nx - 3,
+ * r/dr <= nr - 2 is left unchanged, deposits nothing and is counted in
+ * *skipped_dev (a device counter, may be NULL).  Open x boundaries only
+ * (QDS_EUNSUPPORTED otherwise).  Asynchronous on ``stream``. */
+qds_status qds_particles_step(qds_handle h, const qds_state* fields, int32_t extrapolate, qds_particles* particles,
+                              void* jx, void* jr, void* jt, unsigned long long* skipped_dev, void* stream);
+
 qds_status qds_destroy(qds_handle h);
 
 /* ---------------------------------------------------------------------------

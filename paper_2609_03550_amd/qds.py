@@ -58,6 +58,13 @@ class Loss(ctypes.Structure):
                 ("x_end", ctypes.c_int32)]
 
 
+class Particles(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
+                ("q", ctypes.c_void_p), ("count", ctypes.c_int64), ("charge", ctypes.c_double),
+                ("qm", ctypes.c_double)]
+
+
 class State(ctypes.Structure):
     _fields_ = [("buf", ctypes.c_void_p * 2), ("cur", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("step", ctypes.c_int64), ("window", ctypes.c_int64)]
@@ -108,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_loss_eval_noalloc.restype = i32
     lib.qds_radial_mu_max.argtypes = [i32, dbl, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.qds_radial_mu_max.restype = i32
+    lib.qds_particles_step.argtypes = [vp, ctypes.POINTER(State), i32, ctypes.POINTER(Particles), vp, vp, vp, vp, vp]
+    lib.qds_particles_step.restype = i32
     lib.qds_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     lib.qds_batch_create.restype = i32
     lib.qds_batch_run.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion),
@@ -401,6 +410,39 @@ class Solver:
         _check(lib().qds_loss_eval(self.h, self.bufs[self.state.cur].data_ptr(), ctypes.byref(lo), out.data_ptr(),
                                    grad.data_ptr(), _stream_ptr()), self.h)
         return float(out.item())
+
+    def current_planes(self):
+        """Three zeroed complex planes [M, nr+1, row pitch] (j_x, j_r, j_theta)
+        in the state's dtype, for particles_step."""
+        cdt = torch.complex128 if self.dtype == "f64" else torch.complex64
+        return [torch.zeros(self.wl.nmodes, self.wl.nr + 1, self.ld, dtype=cdt, device=self.device) for _ in range(3)]
+
+    def particles_step(self, pos: torch.Tensor, u: torch.Tensor, qm: float, charge=1.0, planes=None,
+                       extrapolate: bool = False, stream=None):
+        """One particle step in the current fields (qds_particles_step).
+        ``pos`` and ``u`` are float64 device tensors [3, n] (rows x, y, z and
+        u_x, u_y, u_z), updated in place; ``charge`` a float or a float64
+        device tensor [n].  Returns (jx, jr, jt planes, skipped count)."""
+        if pos.dtype != torch.float64 or u.dtype != torch.float64 or pos.shape[0] != 3 or u.shape != pos.shape \
+                or not pos.is_contiguous() or not u.is_contiguous():
+            raise ValueError("pos and u must be contiguous float64 tensors of shape [3, n]")
+        planes = self.current_planes() if planes is None else planes
+        n = pos.shape[1]
+        P = Particles()
+        P.x, P.y, P.z = pos[0].data_ptr(), pos[1].data_ptr(), pos[2].data_ptr()
+        P.ux, P.uy, P.uz = u[0].data_ptr(), u[1].data_ptr(), u[2].data_ptr()
+        if isinstance(charge, torch.Tensor):
+            P.q = charge.data_ptr()
+        else:
+            P.q = None
+            P.charge = float(charge)
+        P.count = n
+        P.qm = float(qm)
+        skipped = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().qds_particles_step(self.h, ctypes.byref(self.state), 1 if extrapolate else 0, ctypes.byref(P),
+                                        planes[0].data_ptr(), planes[1].data_ptr(), planes[2].data_ptr(),
+                                        skipped.data_ptr(), _stream_ptr(stream)), self.h)
+        return planes, skipped
 
     def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
         """Re sum conj(a) b over two state buffers (device reduction)."""
