@@ -50,7 +50,7 @@ enum { QDS_F64 = 0, QDS_F32 = 1 };
 enum { QDS_X_OPEN = 0, QDS_X_PERIODIC = 1, QDS_X_WINDOW = 2 };
 enum { QDS_R_OPEN = 0, QDS_R_PEC = 1 };
 enum { QDS_HAS_PLASMA = 1, QDS_HAS_AXION = 2, QDS_HAS_AREM = 4 };
-enum { QDS_J_NONE = 0, QDS_J_RING = 1 };
+enum { QDS_J_NONE = 0, QDS_J_RING = 1, QDS_J_PARTICLES = 2 };
 
 /* Planes of the state (each [modes][nr+1][ld] complex, x contiguous). */
 enum {
@@ -90,10 +90,21 @@ typedef struct {
  * xi a SplitMix64 + Box-Muller normal per (step, lab column, row) from seed. */
 typedef struct {
     double wp2;
-    int32_t kind;      /* QDS_J_NONE | QDS_J_RING */
+    int32_t kind;      /* QDS_J_NONE | QDS_J_RING | QDS_J_PARTICLES */
     int32_t pad_;
     double amp, x0, v, sx, r0, sr, noise;
     uint64_t seed;
+    /* QDS_J_PARTICLES: currents deposited by qds_particles_step, added to the
+     * background set (planes in the layout of a state plane, the handle's
+     * dtype): j_x^n = (pjx_prev + pjx_next)/2 with pjx_prev the deposit of the
+     * step ending at t^{n-1/2} (may be NULL: taken as zero) and pjx_next that
+     * of the step ending at t^{n+1/2}; j_r and j_theta of the latter (pjr,
+     * pjt, on integer columns) are averaged along x onto the source points
+     * x_{i+1/2} (Sec. 3.1, last paragraph).  Runs the staged kernels. */
+    const void* pjx_prev;
+    const void* pjx_next;
+    const void* pjr;
+    const void* pjt;
 } qds_current;
 
 /* Axion parameters (ignored unless the grid content has QDS_HAS_AXION). */
@@ -289,12 +300,14 @@ typedef struct {
     int64_t count;
     double charge;
     double qm;
+    int32_t clear;                         /* nonzero: zero the three current planes before depositing */
+    int32_t pad_;
 } qds_particles;
 
 /* Advance every particle one step dt = dx in the fields of fields->buf[cur]
  * and add its current at t^{n+1/2} to three caller-owned planes (each
  * [modes][nr+1][row pitch] complex in the handle's dtype, the layout of a
- * state plane; not cleared): jx at (x_{i+1/2}, r_j) (half column i), jr at
+ * state plane; cleared first when particles->clear): jx at (x_{i+1/2}, r_j) (half column i), jr at
  * (x_i, r_{j+1/2}) (row j), jt at (x_i, r_j).
  *  - Gather: transverse fields at t^n from T^n of the background set; E_x and
  *    B_x at t^{n-1/2}, or, with extrapolate != 0, extrapolated to t^n as

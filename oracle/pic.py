@@ -315,3 +315,46 @@ def particle_step(fields: Dict[str, np.ndarray], long_prev: Optional[Dict[str, n
         new_pos[p] = xn
         new_u[p] = un
     return new_pos, new_u, (jx, jr, jt)
+
+
+# ---------------------------------------------------------------------------
+# the coupled PIC step: particles, then the field advance with their current
+# ---------------------------------------------------------------------------
+
+def source_currents(jx_prev, jx_new, jr, jt):
+    """The deposits brought to the source points of the field step: j_x^n as
+    the mean of the deposits of the steps ending at t^{n-1/2} (jx_prev, or
+    None) and t^{n+1/2}; j_r, j_theta of the latter averaged along x from x_i,
+    x_{i+1} onto x_{i+1/2} (Sec. 3.1, last paragraph), zero beyond the last
+    column."""
+    def xavg(a):
+        b = np.zeros_like(a)
+        b[..., :-1] = 0.5 * (a[..., :-1] + a[..., 1:])
+        b[..., -1] = 0.5 * a[..., -1]
+        return b
+    jx = 0.5 * jx_new if jx_prev is None else 0.5 * (jx_prev + jx_new)
+    return jx, xavg(jr)[:, :-1], xavg(jt)
+
+
+def fields_of(st):
+    """The gather's inputs from an oracle state: background set only."""
+    return {"Ex": st["Ex0"].numpy(), "Bx": st["Bx0"].numpy(),
+            "Er": (0.5 * (st["Trp0"] + st["Trm0"])).numpy(), "Bt": (0.5 * (st["Trp0"] - st["Trm0"])).numpy(),
+            "Et": (0.5 * (st["Ttp0"] + st["Ttm0"])).numpy(), "Br": (0.5 * (st["Ttp0"] - st["Ttm0"])).numpy()}
+
+
+def coupled_steps(st, g, ph, pos, u, Q, qm, nsteps):
+    """``nsteps`` PIC steps on the oracle: particle step in the state's fields
+    (E_x, B_x extrapolated from the previous state from the second step on),
+    then one field step (oracle.qds.step) with the particle currents."""
+    import torch
+    from oracle import qds as OQ
+    prev_state, prev_jx = None, None
+    for _ in range(nsteps):
+        lp = None if prev_state is None else {"Ex": prev_state["Ex0"].numpy(), "Bx": prev_state["Bx0"].numpy()}
+        pos, u, (jx, jr, jt) = particle_step(fields_of(st), lp, pos, u, Q, qm, g.h, g.dr, g.h)
+        ext = tuple(torch.from_numpy(np.ascontiguousarray(a)) for a in source_currents(prev_jx, jx, jr, jt))
+        prev_state = st
+        st = OQ.step(st, g, ph, ext)
+        prev_jx = jx
+    return st, pos, u

@@ -619,14 +619,21 @@ def axion_current(c: _Ctx, f: Dict, st: Dict, kg: Dict, bext, form: str = "trans
 # one full step and runs
 # ----------------------------------------------------------------------------
 
-def step(st: Dict, g: Grid, ph: Physics) -> Dict:
-    """One step n -> n+1 of the whole advance: background set, axion, regenerated set."""
+def step(st: Dict, g: Grid, ph: Physics, ext: Optional[Tuple[torch.Tensor, ...]] = None) -> Dict:
+    """One step n -> n+1 of the whole advance: background set, axion, regenerated set.
+    ``ext`` = (j_x at t^n [M,nr+1,nx], j_r at t^{n+1/2} [M,nr,nx], j_theta at
+    t^{n+1/2} [M,nr+1,nx]), already at the source points x_{i+1/2}, is an
+    extra current of the background set (the particle currents of the PIC
+    coupling)."""
     c = _Ctx(g)
     n, w = st["n"], st["w"]
     zJ = torch.zeros(c.M, c.nr + 1, c.nx, dtype=CDT)
     zK = torch.zeros(c.M, c.nr, c.nx, dtype=CDT)
     jx_drive = drive_jx(c, ph.drive, n, w) if ph.drive is not None else zJ
-    new = em_set(c, st, 0, ph.wp2, jx_drive, zK, zJ)
+    if ext is None:
+        new = em_set(c, st, 0, ph.wp2, jx_drive, zK, zJ)
+    else:
+        new = em_set(c, st, 0, ph.wp2, jx_drive + ext[0], ext[1], ext[2])
     if ph.axion:
         f = _bg_fields(c, st, new, ph.bext)
         S = axion_source(c, f, ph.bext, ph.product_form)

@@ -211,7 +211,8 @@ template <typename T>
 qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_axion* ax, int64_t n_steps,
                      hipStream_t s) {
     qds::StepPlan<T> p = make_plan<T>(c, J, ax);
-    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
+    // particle currents run on the staged kernels
+    if (use_fused(c) && !(J && J->kind == QDS_J_PARTICLES)) return fused_steps<T>(c, st, p, n_steps, s);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
         int a = st->cur, b = 1 - st->cur;
@@ -593,7 +594,12 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
     qds_status s = check_state(h, fields);
     if (s != QDS_OK) return s;
     if (n_steps < 0) return fail(h, QDS_EINVAL, "negative step count%s");
-    if (J && J->kind != QDS_J_NONE && J->kind != QDS_J_RING) return fail(h, QDS_EINVAL, "bad current kind%s");
+    if (J && J->kind != QDS_J_NONE && J->kind != QDS_J_RING && J->kind != QDS_J_PARTICLES)
+        return fail(h, QDS_EINVAL, "bad current kind%s");
+    if (J && J->kind == QDS_J_PARTICLES && (!J->pjx_next || !J->pjr || !J->pjt))
+        return fail(h, QDS_EINVAL, "particle currents need pjx_next, pjr and pjt%s");
+    if (J && J->kind == QDS_J_PARTICLES && h->g.x_bc == QDS_X_WINDOW)
+        return fail(h, QDS_EUNSUPPORTED, "particle currents take no moving window%s");
     if (J && J->kind == QDS_J_RING && (!(J->sx > 0) || !(J->sr > 0)))
         return fail(h, QDS_EINVAL, "drive widths must be positive%s");
     if (J && J->wp2 != 0.0 && !has(h, QDS_P_JX)) return fail(h, QDS_EINVAL, "plasma response needs the plasma planes%s");

@@ -150,6 +150,11 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
     for (int k = 0; k < 3; ++k) p.ja[k] = sc[k];
     p.sa = sc[3];
     p.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
+    const bool part = J && J->kind == QDS_J_PARTICLES;
+    p.pj[0] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_prev)) : nullptr;
+    p.pj[1] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_next)) : nullptr;
+    p.pj[2] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjr)) : nullptr;
+    p.pj[3] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjt)) : nullptr;
     return p;
 }
 

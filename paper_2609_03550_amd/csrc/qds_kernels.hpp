@@ -53,6 +53,14 @@ struct StageArgs {
     const cx<T>* jx_add;        // extra currents at the source points (or null)
     const cx<T>* jr_add;
     const cx<T>* jt_add;
+    // particle currents of the background set (deposits of the PIC coupling):
+    // j_x at (x_{i+1/2}, r_j) from the steps ending at t^{n-1/2} and t^{n+1/2}
+    // (j_x^n is their mean; either may be null), j_r and j_theta at t^{n+1/2}
+    // on integer columns (averaged here to x_{i+1/2}); null when absent
+    const cx<T>* pjx0;
+    const cx<T>* pjx1;
+    const cx<T>* pjr;
+    const cx<T>* pjt;
     int plasma;
     double wp2;
     Drive drive;                // prescribed j_x^(0) (background set only)
@@ -94,6 +102,7 @@ struct StepPlan {
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
     Drive drive;
+    const cx<T>* pj[4];         // particle currents of set 0 (StageArgs::pjx0 ..), or null
     int64_t n, w;
 
     SetPtr<T> set(cx<T>* const* P, int s) const {
@@ -112,6 +121,10 @@ struct StepPlan {
         a.wp2 = wp2;
         a.drive = drive;
         if (s) a.drive.on = 0;
+        a.pjx0 = s ? nullptr : pj[0];
+        a.pjx1 = s ? nullptr : pj[1];
+        a.pjr = s ? nullptr : pj[2];
+        a.pjt = s ? nullptr : pj[3];
         a.n = n;
         a.w = w;
         return a;

@@ -280,6 +280,17 @@ hipError_t particle_step(const PartArgs<T>& a, int M, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zeroes three current planes of n 8-byte words each (a fill kernel rather
+// than a memset node, so that the call may sit in a captured graph).
+__global__ void k_zero_planes(uint2* a, uint2* b, uint2* c, size_t n) {
+    const uint2 z = make_uint2(0u, 0u);
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+        a[i] = z;
+        b[i] = z;
+        c[i] = z;
+    }
+}
+
 }  // namespace pic
 }  // namespace qds
 
@@ -308,6 +319,16 @@ qds_status run(qds_ctx* h, const qds_state* st, int32_t extrapolate, qds_particl
     a.jr = static_cast<qds::cx<T>*>(jr);
     a.jt = static_cast<qds::cx<T>*>(jt);
     a.skipped = skipped;
+    if (pp->clear) {
+        // every plane is plane_elems complex values of elem_bytes (8 or 16) bytes
+        const size_t words = h->plane_elems * h->elem_bytes / 8;
+        const unsigned blocks = unsigned(std::min<size_t>((words + 255) / 256, 4096));
+        hipLaunchKernelGGL(qds::pic::k_zero_planes, dim3(blocks), dim3(256), 0, s, static_cast<uint2*>(jx),
+                           static_cast<uint2*>(jr), static_cast<uint2*>(jt), words);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(h, QDS_EHIP, "clearing the current planes failed: %s", hipGetErrorString(e));
+    }
+    if (pp->count == 0) return QDS_OK;
     const hipError_t e = qds::pic::particle_step<T>(a, h->M, s);
     if (e != hipSuccess) return fail(h, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     return QDS_OK;
@@ -327,7 +348,6 @@ extern "C" qds_status qds_particles_step(qds_handle h, const qds_state* fields, 
                                  !particles->uy || !particles->uz))
         return fail(h, QDS_EINVAL, "null particle array%s");
     if (h->g.x_bc != QDS_X_OPEN) return fail(h, QDS_EUNSUPPORTED, "particles need open x boundaries%s");
-    if (particles->count == 0) return QDS_OK;
     if (particles->count > (int64_t(1) << 40)) return fail(h, QDS_EINVAL, "too many particles%s");
     if (h->g.dtype == QDS_F64)
         return run<double>(h, fields, extrapolate, particles, jx, jr, jt, skipped_dev, hipStream_t(stream));

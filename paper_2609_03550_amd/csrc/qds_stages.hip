@@ -38,6 +38,9 @@ __device__ __forceinline__ cx<T> jx_total(const StageArgs<T>& a, int m, int j, i
     if (a.plasma) v = ld(a.B.jx + g.at(m, j, c));     // j_x^n, written by the longitudinal stage
     if (a.jx_add) v = v + ld(a.jx_add + g.at(m, j, c));
     if (a.drive.on && m == 0) v.re += drive_jx<T>(a.drive, g, c, j, a.n, a.w);
+    // particle deposits: j_x^n as the mean of the steps ending at t^{n-1/2}, t^{n+1/2}
+    if (a.pjx0) v = v + T(0.5) * ld(a.pjx0 + g.at(m, j, c));
+    if (a.pjx1) v = v + T(0.5) * ld(a.pjx1 + g.at(m, j, c));
     return v;
 }
 
@@ -49,6 +52,7 @@ __device__ __forceinline__ cx<T> jr_total(const StageArgs<T>& a, int m, int k, i
     cx<T> v = zero<T>();
     if (a.plasma) v = T(0.5) * (ldx(a.B.jr, g, m, k, i) + ldx(a.B.jr, g, m, k, i + 1));
     if (a.jr_add) v = v + ld(a.jr_add + g.at(m, k, i));
+    if (a.pjr) v = v + T(0.5) * (ldx(a.pjr, g, m, k, i) + ldx(a.pjr, g, m, k, i + 1));
     return v;
 }
 template <typename T>
@@ -57,6 +61,7 @@ __device__ __forceinline__ cx<T> jt_total(const StageArgs<T>& a, int m, int j, i
     cx<T> v = zero<T>();
     if (a.plasma) v = T(0.5) * (ldx(a.B.jt, g, m, j, i) + ldx(a.B.jt, g, m, j, i + 1));
     if (a.jt_add) v = v + ld(a.jt_add + g.at(m, j, i));
+    if (a.pjt) v = v + T(0.5) * (ldx(a.pjt, g, m, j, i) + ldx(a.pjt, g, m, j, i + 1));
     return v;
 }
 
@@ -147,6 +152,7 @@ __global__ void __launch_bounds__(256) k_longitudinal(StageArgs<T> a) {
                     jt = T(0.5) * (j0 + j1);
                 }
                 if (a.jt_add) jt = jt + ld(a.jt_add + g.at(m, N, i));
+                if (a.pjt) jt = jt + T(0.5) * (ldx(a.pjt, g, m, N, i) + ldx(a.pjt, g, m, N, i + 1));
                 rx = rx - T(0.5) * jt;
                 cx<T> I0 = ld(a.A.bx + g.at(m, N - 1, i));
                 cx<T> I1 = bx_new_at(a, m, N - 1, i);

@@ -24,13 +24,14 @@ F64, F32 = 0, 1
 X_BC = {"open": 0, "periodic": 1, "window": 2}
 R_BC = {"open": 0, "pec": 1}
 HAS_PLASMA, HAS_AXION, HAS_AREM = 1, 2, 4
-J_NONE, J_RING = 0, 1
+J_NONE, J_RING, J_PARTICLES = 0, 1, 2
 P_TRP, P_TRM, P_TTP, P_TTM, P_EX, P_BX, P_JX, P_JR, P_JT = range(9)
 P_SET1, P_PHI, P_TAP, P_TAM = 9, 18, 19, 20
 
 OPT_PATH, OPT_ROWS, OPT_TIMING, OPT_TUNE = 1, 2, 3, 4
 OPT_ROWS_A, OPT_ROWS_CUR, OPT_ROWS_B = 5, 6, 7       # one kernel's tile height
 OPT_PRODUCTS = 8
+OPT_OVERLAP = 9
 PRODUCTS_DIRECT, PRODUCTS_THETA = 0, 1
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 
@@ -45,7 +46,9 @@ class Current(ctypes.Structure):
     _fields_ = [("wp2", ctypes.c_double), ("kind", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("amp", ctypes.c_double), ("x0", ctypes.c_double), ("v", ctypes.c_double),
                 ("sx", ctypes.c_double), ("r0", ctypes.c_double), ("sr", ctypes.c_double),
-                ("noise", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("pjx_prev", ctypes.c_void_p), ("pjx_next", ctypes.c_void_p), ("pjr", ctypes.c_void_p),
+                ("pjt", ctypes.c_void_p)]
 
 
 class Axion(ctypes.Structure):
@@ -62,7 +65,7 @@ class Particles(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
                 ("q", ctypes.c_void_p), ("count", ctypes.c_int64), ("charge", ctypes.c_double),
-                ("qm", ctypes.c_double)]
+                ("qm", ctypes.c_double), ("clear", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -418,7 +421,7 @@ class Solver:
         return [torch.zeros(self.wl.nmodes, self.wl.nr + 1, self.ld, dtype=cdt, device=self.device) for _ in range(3)]
 
     def particles_step(self, pos: torch.Tensor, u: torch.Tensor, qm: float, charge=1.0, planes=None,
-                       extrapolate: bool = False, stream=None):
+                       extrapolate: bool = False, clear: bool = False, stream=None):
         """One particle step in the current fields (qds_particles_step).
         ``pos`` and ``u`` are float64 device tensors [3, n] (rows x, y, z and
         u_x, u_y, u_z), updated in place; ``charge`` a float or a float64
@@ -438,11 +441,38 @@ class Solver:
             P.charge = float(charge)
         P.count = n
         P.qm = float(qm)
+        P.clear = 1 if clear else 0
         skipped = torch.zeros(1, dtype=torch.int64, device=self.device)
         _check(lib().qds_particles_step(self.h, ctypes.byref(self.state), 1 if extrapolate else 0, ctypes.byref(P),
                                         planes[0].data_ptr(), planes[1].data_ptr(), planes[2].data_ptr(),
                                         skipped.data_ptr(), _stream_ptr(stream)), self.h)
         return planes, skipped
+
+    def pic_steps(self, pos: torch.Tensor, u: torch.Tensor, qm: float, charge, n: int, coupling=None):
+        """``n`` coupled PIC steps (Sec. 3.1): per step qds_particles_step in
+        the current fields (E_x, B_x extrapolated to t^n once a previous state
+        exists) depositing into fresh planes, then qds_step with those
+        currents (kind QDS_J_PARTICLES: j_x^n the mean of this and the
+        previous step's deposit).  ``coupling`` carries the deposit planes
+        between calls; returns it (and the skipped-particle counters)."""
+        if coupling is None:
+            coupling = {"planes": [self.current_planes(), self.current_planes()], "prev": None, "steps": 0}
+        skipped = []
+        for _ in range(n):
+            new = coupling["planes"][0] if coupling["prev"] is not coupling["planes"][0] else coupling["planes"][1]
+            _, sk = self.particles_step(pos, u, qm, charge, planes=new, extrapolate=coupling["steps"] > 0,
+                                        clear=True)
+            skipped.append(sk)
+            J = Current()
+            ctypes.memmove(ctypes.byref(J), ctypes.byref(self.cur), ctypes.sizeof(Current))
+            J.kind = J_PARTICLES
+            J.pjx_prev = coupling["prev"][0].data_ptr() if coupling["prev"] is not None else None
+            J.pjx_next, J.pjr, J.pjt = new[0].data_ptr(), new[1].data_ptr(), new[2].data_ptr()
+            _check(lib().qds_step(self.h, ctypes.byref(self.state), ctypes.byref(J), ctypes.byref(self.ax), 1,
+                                  _stream_ptr()), self.h)
+            coupling["prev"] = new
+            coupling["steps"] += 1
+        return coupling, skipped
 
     def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
         """Re sum conj(a) b over two state buffers (device reduction)."""

@@ -111,3 +111,70 @@ def test_particles_outside_the_grid_are_skipped_and_counted():
     assert int(skipped.item()) == 8
     assert np.array_equal(P.cpu().numpy()[:, :8], pos[:, :8])
     assert not np.array_equal(P.cpu().numpy()[:, 8:], pos[:, 8:])
+
+
+@pytest.mark.parametrize("M,dtype", [(2, "f64"), (3, "f64"), (3, "f32")])
+def test_coupled_pic_steps_match_the_oracle(M, dtype):
+    """Eight coupled steps (particle step in the fields, then the field step
+    with the deposited current, QDS_J_PARTICLES on the staged kernels) of a
+    laser pulse and 300 electrons near it: fields and particles against the
+    oracle's coupled loop."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    import parity_tools as PT
+    nx, nr = 96, 12
+    p = I.Pulse("y", 0.3, 1.0, 3 * I.LAMBDA, 12 * H, 0.55 * nx * H)
+    wl = I.Workload("pic_coupled", nx, nr, M, 0, pulses=(p,))
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_pulses()
+    rng = np.random.default_rng(31)
+    n = 300
+    x = rng.uniform(0.35 * nx * H, 0.75 * nx * H, n)
+    r = (nr - 4) * wl.dr * np.sqrt(rng.uniform(0, 1, n))
+    th = rng.uniform(-math.pi, math.pi, n)
+    pos = np.stack([x, r * np.cos(th), r * np.sin(th)])
+    u = 0.05 * rng.normal(size=(3, n))
+    qch = -0.02 * rng.uniform(0.5, 1.5, n)
+    P = torch.from_numpy(pos.copy()).to(s.device)
+    U = torch.from_numpy(u.copy()).to(s.device)
+    _, sk = s.pic_steps(P, U, -1.0, torch.from_numpy(qch.copy()).to(s.device), 8)
+    torch.cuda.synchronize()
+    assert sum(int(k.item()) for k in sk) == 0
+    g, ph = Q.grid_physics(wl)
+    st, opos, ou = OP.coupled_steps(Q.init_state(wl), g, ph, pos.T.copy(), u.T.copy(), qch, -1.0, 8)
+    tp = 1e-12 if dtype == "f64" else 1e-5
+    assert np.abs(P.cpu().numpy() - opos.T).max() < tp * np.abs(opos).max()
+    assert np.abs(U.cpu().numpy() - ou.T).max() < max(tp * np.abs(ou).max(), 1e-14)
+    tol, floor = (1e-12, 1e-13) if dtype == "f64" else (1e-5, 1e-6)
+    got = s.fields()
+    PT.compare_states(got, {k: st[k] for k in got}, tol, floor, set_floor=PT.SET_FLOOR, phys=True)
+
+
+@pytest.mark.parametrize("n", [0, 40])
+def test_clear_zeroes_the_planes_before_depositing(n):
+    """particles->clear zeroes the three current planes before the deposit,
+    with or without particles; without clear the deposit adds to them."""
+    s, _, _, pos, u, Q = _setup(2, "f64", n=max(n, 1), near_axis=0)
+    pos, u = pos[:, :n].copy(), u[:, :n].copy()
+    planes = s.current_planes()
+    for pl in planes:
+        pl.fill_(0.25 + 0.5j)
+    P = torch.from_numpy(pos).to(s.device)
+    U = torch.from_numpy(u).to(s.device)
+    _, sk = s.particles_step(P.clone(), U.clone(), -1.0, 1.0, planes=planes, clear=True)
+    fresh = s.current_planes()
+    s.particles_step(P.clone(), U.clone(), -1.0, 1.0, planes=fresh)
+    torch.cuda.synchronize()
+    assert int(sk.item()) == 0
+    if n == 0:
+        assert all(int(torch.count_nonzero(a)) == 0 for a in planes)
+        return
+    # the deposit adds with atomics, in no fixed order: equal to rounding
+    scale = max(float(b.abs().max()) for b in fresh)
+    assert scale > 0
+    for a, b in zip(planes, fresh):
+        assert float((a - b).abs().max()) <= 1e-13 * scale
+    s.particles_step(P.clone(), U.clone(), -1.0, 1.0, planes=planes)
+    torch.cuda.synchronize()
+    for a, b in zip(planes, fresh):
+        assert float((a - 2 * b).abs().max()) <= 1e-13 * scale
