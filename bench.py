@@ -226,6 +226,35 @@ def f32_leg(wl, steps):
             "tiles": tiles[0]}
 
 
+def overlap_leg(wl, dtype, tiles, steps):
+    """The main workload with and without QDS_OPT_OVERLAP (kernel A of step
+    k+1 on a second stream beside the regenerated set of step k), both with
+    the main run's tiles, ``steps`` timed steps each after 10 untimed, in
+    alternating order twice."""
+    import torch
+    from paper_2609_03550_amd import qds
+    res = {"serial": [], "overlap": []}
+    for rep in range(2):
+        for name in (("serial", "overlap") if rep == 0 else ("overlap", "serial")):
+            s = qds.Solver(wl, dtype=dtype)
+            s.load_pulses()
+            for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), tiles):
+                s.set_option(opt, int(v))
+            s.set_option(qds.OPT_OVERLAP, 1 if name == "overlap" else 0)
+            s.step(10)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            res[name].append(e0.elapsed_time(e1) / steps)
+            s.close()
+    out = {"steps": steps, "serial_ms_per_step": min(res["serial"]), "overlap_ms_per_step": min(res["overlap"])}
+    out["overlap_over_serial"] = out["overlap_ms_per_step"] / out["serial_ms_per_step"]
+    return out
+
+
 def theta_leg(steps=20):
     """Axion source and current by the theta-grid transform pair against the
     direct mode convolution, both on the staged kernels: 6 and 8 modes of the
@@ -260,10 +289,13 @@ def theta_leg(steps=20):
 
 
 def stream_reference(nbytes=1 << 31, reps=10):
-    """Bandwidth a plain device copy (read + write) and a plain fill (write
-    only) reach in the same process: the practical ceiling next to the 8 TB/s
-    peak for kernels that both read and write their planes."""
+    """Bandwidth of plain device copies (read + write) and a fill (write only)
+    in the same process: torch's copy and fill, and the library's 16-byte-per-
+    lane copy (qds_stream_copy) with and without the streaming hint over 65536
+    workgroups -- the practical ceiling next to the 8 TB/s peak for kernels
+    that both read and write their planes."""
     import torch
+    from paper_2609_03550_amd import qds
     dev = torch.device("cuda:0")
     a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
@@ -280,12 +312,23 @@ def stream_reference(nbytes=1 << 31, reps=10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps / 1e3
 
+    stream = torch.cuda.current_stream().cuda_stream
+    lib = qds.lib()
+
+    def lib_copy(streaming):
+        st = lib.qds_stream_copy(b.data_ptr(), a.data_ptr(), nbytes, streaming, 65536, stream)
+        if st != 0:
+            raise RuntimeError(f"qds_stream_copy failed ({st})")
+
     t_copy = timed(lambda: b.copy_(a))
     t_fill = timed(lambda: b.fill_(3))
+    t_lib = timed(lambda: lib_copy(0))
+    t_nt = timed(lambda: lib_copy(1))
     del a, b
     torch.cuda.empty_cache()
     return {"copy_read_write_gbps": 2 * nbytes / t_copy / 1e9, "fill_write_gbps": nbytes / t_fill / 1e9,
-            "bytes": nbytes}
+            "lib_copy_read_write_gbps": 2 * nbytes / t_lib / 1e9,
+            "lib_streaming_copy_read_write_gbps": 2 * nbytes / t_nt / 1e9, "bytes": nbytes}
 
 
 def cpu_baseline(wl, seconds_target=15.0):
@@ -331,6 +374,12 @@ def main():
                     help="steps of the theta-grid vs direct product comparison at 6 and 8 modes (0 skips it)")
     ap.add_argument("--f32-steps", type=int, default=100,
                     help="steps of the single-precision figure of the same workload (0 skips it)")
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="1 runs kernel A of the next step beside the regenerated set (QDS_OPT_OVERLAP)")
+    ap.add_argument("--overlap-steps", type=int, default=100,
+                    help="steps of the overlap on/off comparison (0 skips it)")
+    ap.add_argument("--stream-reference", type=int, default=1,
+                    help="1 times plain device copies for the copy-relative roofline fractions (0 skips them)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for the HBM counters)")
     args = ap.parse_args()
@@ -347,6 +396,7 @@ def main():
     dev = torch.device("cuda:0")
     s = qds.Solver(wl, dtype=args.dtype, device="cuda:0", path=args.path, rows=args.rows)
     s.load_pulses()
+    s.set_option(qds.OPT_OVERLAP, args.overlap)
     if args.tiles:
         for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), args.tiles.split(",")):
             s.set_option(opt, int(v))
@@ -421,7 +471,8 @@ def main():
         "config": {"workload": wl.name, "nx": wl.nx, "nr": wl.nr, "modes": wl.nmodes,
                    "physics": "QDS Maxwell + Klein-Gordon axion + regenerated fields + cold plasma"
                    if wl.arem else ("QDS Maxwell + prescribed current, moving window" if wl.drive else "QDS Maxwell"),
-                   "path": "fused" if s.fused else "staged", "parallelism": "single GPU"},
+                   "path": "fused" if s.fused else "staged", "overlap": bool(args.overlap),
+                   "parallelism": "single GPU"},
         # the dominant unit is the whole step (its kernels run back to back):
         # algorithmic bytes = every state plane read once and written once
         "roofline": {"bound": "hbm", "kernel": "whole step (" + " + ".join(k["name"] for k in kernels.values()) + ")",
@@ -433,6 +484,7 @@ def main():
         "fwd_adj_over_fwd": None,
         "tiles": dict(run_tiles, tuned=s.tiles()[1]),
     }
+    s_fused = s.fused
     del s
     torch.cuda.empty_cache()
     if args.adjoint_steps > 0:
@@ -446,11 +498,18 @@ def main():
     if args.f32_steps > 0 and args.dtype == "f64" and args.workload == "axion":
         out["f32"] = f32_leg(wl, args.f32_steps)
         torch.cuda.empty_cache()
+    if args.overlap_steps > 0 and wl.arem and s_fused:
+        out["overlap"] = overlap_leg(wl, args.dtype, [run_tiles[k] for k in ("kernel_a", "axion_current", "kernel_b")],
+                                     args.overlap_steps)
+        torch.cuda.empty_cache()
     if args.theta_steps > 0:
         out["theta_grid_products"] = theta_leg(args.theta_steps)
         torch.cuda.empty_cache()
-    out["stream_reference"] = stream_reference()
-    out["roofline"]["frac_of_copy"] = achieved / out["stream_reference"]["copy_read_write_gbps"]
+    if args.stream_reference:
+        out["stream_reference"] = stream_reference()
+        out["roofline"]["frac_of_copy"] = achieved / out["stream_reference"]["copy_read_write_gbps"]
+        out["roofline"]["frac_of_streaming_copy"] = (achieved /
+                                                     out["stream_reference"]["lib_streaming_copy_read_write_gbps"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

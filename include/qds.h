@@ -198,13 +198,19 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 pair through a theta grid of 3*modes - 2 points, exact for
  *                 modes 0..modes-1 (Sec. 3.3), on the staged kernels (the
  *                 handle then runs the staged path)
+ *  QDS_OPT_OVERLAP 1: with the regenerated set on the fused kernels (and no
+ *                 prescribed drive), kernel A of step k+1 runs on a second
+ *                 stream of the handle beside kernel B of step k (they share
+ *                 no plane); events order it after the axion kernel of step
+ *                 k, and every launch is joined back into the caller's
+ *                 stream before qds_step returns.  0: one stream.
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
  *                 value resets the recorded launches */
 enum {
     QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
-    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8
+    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8, QDS_OPT_OVERLAP = 9
 };
 enum { QDS_PRODUCTS_DIRECT = 0, QDS_PRODUCTS_THETA = 1 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
@@ -387,6 +393,13 @@ const char* qds_batch_last_error(qds_batch b);
 qds_status qds_batch_destroy(qds_batch b);
 const char* qds_last_error(qds_handle h);
 const char* qds_version(void);
+
+/* Measurement of the read + write bandwidth ceiling the marched kernels are
+ * compared with: copies ``bytes`` (a multiple of 16) from src to dst, 16 bytes
+ * per lane in a grid-stride loop over ``blocks`` workgroups of 256, with the
+ * non-temporal (streaming) hint on loads and stores when streaming != 0.
+ * QDS_EINVAL for null pointers, a size not a multiple of 16 or blocks < 1. */
+qds_status qds_stream_copy(void* dst, const void* src, size_t bytes, int32_t streaming, int32_t blocks, void* stream);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqds.so")
-SOURCES = ["qds_api.hip", "qds_batch.hip", "qds_stages.hip", "qds_fused.hip", "qds_current.hip", "qds_adjoint.hip", "qds_noalloc.hip", "qds_particles.hip"]
+SOURCES = ["qds_api.hip", "qds_batch.hip", "qds_stages.hip", "qds_fused.hip", "qds_current.hip", "qds_adjoint.hip", "qds_noalloc.hip", "qds_particles.hip", "qds_copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 OBJDIR = os.path.join(HERE, "_build")

@@ -98,11 +98,15 @@ TabView<T> ktab_view(KTab<T>* K, const KTab<T>& host, int q) {
                       host.firstA[1], host.firstC[1], host.firstB[1]};
 }
 
-// One fused step through an argument-table entry (kernel A or the background
-// set, then the axion current and the regenerated set), each launch
-// bracketed by the event pair ev[2k], ev[2k+1] when ev is given.
+// The three launches of one fused step through an argument-table entry:
+// kernel A (or the background set alone), the axion kernel and the
+// regenerated set, each on stream s and bracketed by the event pair e when
+// given (or by a timing pair when timing is on).
+enum { kLaunchA = 0, kLaunchX = 1, kLaunchB = 2 };
+
 template <typename T>
-qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, hipStream_t s, hipEvent_t* ev) {
+qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, int which, hipStream_t s,
+                            hipEvent_t* e) {
     auto list = [&](const int* first_dev, int rows) {
         qds::BatchList L;
         L.idx = v.idx;
@@ -111,33 +115,39 @@ qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>
         L.rows = rows;
         return L;
     };
-    const qds::BatchList LA = list(v.firstA, c->trows[0]), LC = list(v.firstC, c->trows[1]),
-                         LB = list(v.firstB, c->trows[2]), LB0 = list(v.firstB, c->trows[0]);
-    hipEvent_t* e0 = ev ? ev : (c->timing ? timing_pair(c, 0) : nullptr);
-    if (e0 && hipEventRecord(e0[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-    hipError_t e;
-    if (p0.axion) {
-        e = qds::batch_a<T>(v.fa, LA, c->M, v.nA, !march_axion(c, p0), s);
+    // timing slots: 0 kernel A, 1 the regenerated set, 2 the axion kernel
+    const int slot = which == kLaunchA ? 0 : (which == kLaunchX ? 2 : 1);
+    hipEvent_t* ev = e ? e : (c->timing ? timing_pair(c, slot) : nullptr);
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
+    hipError_t err = hipSuccess;
+    if (which == kLaunchA) {
+        if (p0.axion) {
+            err = qds::batch_a<T>(v.fa, list(v.firstA, c->trows[0]), c->M, v.nA, !march_axion(c, p0), s);
+        } else {
+            // the background set alone: the kernel-B march with the kernel-A tile
+            const int strips = qds::fused_strips(c->g.nx);
+            err = qds::batch_em<T>(v.fa, list(v.firstB, c->trows[0]), 0,
+                                   strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
+        }
+    } else if (which == kLaunchX) {
+        err = qds::batch_current<T>(v.xa, list(v.firstC, c->trows[1]), c->M, v.nC, s);
     } else {
-        // the background set alone: the kernel-B march with the kernel-A tile
-        const int strips = qds::fused_strips(c->g.nx);
-        e = qds::batch_em<T>(v.fa, LB0, 0, strips * ((c->g.nr + c->trows[0]) / c->trows[0]) * c->M, s);
+        err = qds::batch_em<T>(v.fa, list(v.firstB, c->trows[2]), 1, v.nB, s);
     }
-    if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-    if (e0 && hipEventRecord(e0[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-    if (p0.arem) {
-        hipEvent_t* e2 = ev ? ev + 2 : (c->timing ? timing_pair(c, 2) : nullptr);
-        if (e2 && hipEventRecord(e2[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        e = qds::batch_current<T>(v.xa, LC, c->M, v.nC, s);
-        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (e2 && hipEventRecord(e2[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        hipEvent_t* e1 = ev ? ev + 4 : (c->timing ? timing_pair(c, 1) : nullptr);
-        if (e1 && hipEventRecord(e1[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-        e = qds::batch_em<T>(v.fa, LB, 1, v.nB, s);
-        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-        if (e1 && hipEventRecord(e1[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
-    }
+    if (err != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(err));
+    if (ev && hipEventRecord(ev[1], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     return QDS_OK;
+}
+
+// One fused step (kernel A or the background set, then the axion current
+// and the regenerated set), each launch bracketed by the event pair
+// ev[2k], ev[2k+1] when ev is given.
+template <typename T>
+qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, hipStream_t s, hipEvent_t* ev) {
+    qds_status r = table_launch_one<T>(c, p0, v, kLaunchA, s, ev);
+    if (r != QDS_OK || !p0.arem) return r;
+    if ((r = table_launch_one<T>(c, p0, v, kLaunchX, s, ev ? ev + 2 : nullptr)) != QDS_OK) return r;
+    return table_launch_one<T>(c, p0, v, kLaunchB, s, ev ? ev + 4 : nullptr);
 }
 
 template <typename T>
@@ -153,6 +163,49 @@ qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTa
     st->cur = 1 - st->cur;
     if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
     st->step += 1;
+    return QDS_OK;
+}
+
+// Steps with kernel A of step k+1 running on a second stream beside kernel B
+// of step k.  A(k+1) reads and writes the background set and S_a; B(k) reads
+// the regenerated set and j_a and writes the regenerated set: they share no
+// plane.  A(k+1) waits for the axion kernel of step k (the last reader of
+// S_a and of the background buffer A(k+1) overwrites); the axion kernel of
+// step k+1 waits for A(k+1) and, on the caller's stream, for B(k) (the reader
+// of the j_a it overwrites).  Every side-stream launch is joined back into
+// the caller's stream before the call returns.
+template <typename T>
+qds_status overlapped_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
+                            int64_t n, hipStream_t s) {
+    if (!c->side) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+            c->side = nullptr;
+            return fail(c, QDS_EHIP, "side stream creation failed%s");
+        }
+        if (hipEventCreateWithFlags(&c->ev_x, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming) != hipSuccess)
+            return fail(c, QDS_EHIP, "event creation failed%s");
+    }
+    qds_status r = table_launch_one<T>(c, p0, ktab_view<T>(K, host, st->cur), kLaunchA, s, nullptr);
+    if (r != QDS_OK) return r;
+    for (int64_t k = 0; k < n; ++k) {
+        const TabView<T> v = ktab_view<T>(K, host, st->cur);
+        if ((r = table_launch_one<T>(c, p0, v, kLaunchX, s, nullptr)) != QDS_OK) return r;
+        const bool more = k + 1 < n;
+        if (more) {
+            if (hipEventRecord(c->ev_x, s) != hipSuccess || hipStreamWaitEvent(c->side, c->ev_x, 0) != hipSuccess)
+                return fail(c, QDS_EHIP, "stream ordering failed%s");
+            // the next step reads the buffer this step writes
+            if ((r = table_launch_one<T>(c, p0, ktab_view<T>(K, host, 1 - st->cur), kLaunchA, c->side, nullptr)) !=
+                QDS_OK)
+                return r;
+            if (hipEventRecord(c->ev_a, c->side) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
+        }
+        if ((r = table_launch_one<T>(c, p0, v, kLaunchB, s, nullptr)) != QDS_OK) return r;
+        st->cur = 1 - st->cur;
+        st->step += 1;
+        if (more && hipStreamWaitEvent(s, c->ev_a, 0) != hipSuccess) return fail(c, QDS_EHIP, "stream ordering failed%s");
+    }
     return QDS_OK;
 }
 
@@ -202,6 +255,9 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
     }
     if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
     const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
+    if (c->overlap && p0.arem && march_axion(c, p0) && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW &&
+        n_steps - done >= 2)
+        return overlapped_steps<T>(c, st, p0, K, host, n_steps - done, s);
     for (int64_t it = done; it < n_steps; ++it)
         if ((r = table_step<T>(c, st, p0, K, host, s, nullptr)) != QDS_OK) return r;
     return QDS_OK;
@@ -643,6 +699,9 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
         case QDS_OPT_TUNE:
             h->tune = value ? 1 : 0;
             return QDS_OK;
+        case QDS_OPT_OVERLAP:
+            h->overlap = value ? 1 : 0;
+            return QDS_OK;
         case QDS_OPT_PRODUCTS:
             if (value != QDS_PRODUCTS_DIRECT && value != QDS_PRODUCTS_THETA)
                 return fail(h, QDS_EINVAL, "products must be QDS_PRODUCTS_DIRECT or QDS_PRODUCTS_THETA%s");
@@ -771,6 +830,12 @@ qds_status qds_destroy(qds_handle h) {
         (void)hipEventSynchronize(h->ktab_ev);
         (void)hipEventDestroy(h->ktab_ev);
     }
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->ev_x) (void)hipEventDestroy(h->ev_x);
+    if (h->ev_a) (void)hipEventDestroy(h->ev_a);
     if (h->ktab_dev) (void)hipFree(h->ktab_dev);
     if (h->ktab_pin) (void)hipHostFree(h->ktab_pin);
     delete h;

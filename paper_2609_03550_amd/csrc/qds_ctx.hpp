@@ -26,6 +26,9 @@ struct qds_ctx {
     int tune;                // autotune the tile heights on the next long enough qds_step
     int tuned;
     int timing;              // record per-kernel HIP events in qds_step
+    int overlap;             // kernel A of step k+1 on a second stream beside kernel B of step k
+    hipStream_t side;        // that stream (created on first use, default priority)
+    hipEvent_t ev_x, ev_a;   // its ordering events
     // timing events, recorded without synchronising and resolved by
     // qds_get_timing: pairs (start, end) per launch, tagged with the kernel
     std::vector<hipEvent_t> pool;

@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qds_radial_mu_max.restype = i32
     lib.qds_particles_step.argtypes = [vp, ctypes.POINTER(State), i32, ctypes.POINTER(Particles), vp, vp, vp, vp, vp]
     lib.qds_particles_step.restype = i32
+    lib.qds_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, i32, vp]
+    lib.qds_stream_copy.restype = i32
     lib.qds_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     lib.qds_batch_create.restype = i32
     lib.qds_batch_run.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(Current), ctypes.POINTER(Axion),

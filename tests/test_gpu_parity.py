@@ -195,6 +195,32 @@ def test_autotuned_tiles_with_a_drive_change_no_result():
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc", [("f64", 3, "open", "open"), ("f32", 3, "open", "open"),
+                                               ("f64", 4, "periodic", "pec"), ("f64", 1, "open", "pec")])
+def test_overlapped_steps_change_no_result(dtype, M, x_bc, r_bc):
+    """QDS_OPT_OVERLAP runs kernel A of step k+1 on a second stream beside the
+    regenerated set of step k: calls of 1, 2 and 7 steps (the last with the
+    per-kernel timing events on) give bit-identical states to the serial
+    order, and the overlapped solver still matches the oracle."""
+    from paper_2609_03550_amd import qds
+    wl = _full(190, 20, M, x_bc=x_bc, r_bc=r_bc)
+    a = qds.Solver(wl, dtype=dtype)
+    a.load_pulses()
+    b = qds.Solver(wl, dtype=dtype)
+    b.load_pulses()
+    b.set_option(qds.OPT_OVERLAP, 1)
+    for n in (1, 2, 7):
+        if n == 7:
+            b.set_option(qds.OPT_TIMING, 1)
+        a.step(n)
+        b.step(n)
+        torch.cuda.synchronize()
+        assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur]), n
+    assert b.n == 10
+    tol, floor = TOL[dtype]
+    P.compare_states(b.fields(), P.oracle_run(wl, 10), tol, floor, set_floor=P.SET_FLOOR, phys=True)
+
+
 def test_per_kernel_tile_heights_change_no_result():
     """QDS_OPT_ROWS_A / _CUR / _B set one kernel's tile height each (used to
     replay the autotuner's choice): uneven heights that leave ragged last
