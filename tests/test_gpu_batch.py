@@ -141,7 +141,7 @@ def test_batch_matches_oracle(dtype):
     tol, floor = TOL[dtype]
     for s, n in zip(bs, steps):
         ora = P.oracle_run(s.wl, n)
-        P.compare_states(s.fields(), ora, tol, floor, by_group=(dtype == "f32"))
+        P.compare_states(s.fields(), ora, tol, floor, set_floor=P.SET_FLOOR, phys=True)
 
 
 def test_batch_rejects_bad_arguments():
@@ -164,18 +164,20 @@ def test_batch_rejects_bad_arguments():
 
 
 def test_full_size_batch_equals_one_at_a_time_and_oracle_sample():
-    """The 64 uneven instances at full size, FP32: three batched steps (a graph
-    of two and one of one) equal three one-at-a-time steps of every instance;
-    the smallest instance also matches the oracle."""
+    """The 64 uneven instances at full size, FP32: 20 batched steps (graphs of
+    8, 8 and 4) equal 20 one-at-a-time steps of every instance bit for bit;
+    the three smallest instances also match the oracle per physical field
+    (within 1e-5, or 4x what single-precision storage alone does to it)."""
     from paper_2609_03550_amd import qds
     wls = I.batched_instances(64, 4)
     bs = _solvers(wls, "f32")
     solo = _twins(bs)
     b = qds.Batch(bs)
-    b.run(3, graph_steps=2)
+    b.run(20, graph_steps=8)
     for s in solo:
-        s.step(3)
+        s.step(20)
     _identical(bs, solo)
-    k = min(range(64), key=lambda q: wls[q].nx * wls[q].nr * wls[q].nmodes)
-    ora = P.oracle_run(wls[k], 3)
-    P.compare_states(bs[k].fields(), ora, 1e-5, 1e-6, by_group=True)
+    small = sorted(range(64), key=lambda q: wls[q].nx * wls[q].nr * wls[q].nmodes)[:3]
+    for k in small:
+        ora = P.oracle_run(wls[k], 20)
+        P.compare_band(bs[k].fields(), ora, P.oracle_run_rounded(wls[k], 20, "f32"), 1e-5)

@@ -55,7 +55,7 @@ def test_theta_products_match_the_oracle(dtype, M, x_bc, r_bc):
     got = _gpu(wl, st, dtype, qds.PRODUCTS_THETA, 4)
     ref = Q.run(st, g, ph, 4)
     tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
-    P.compare_states(got, ref, tol, floor, by_group=(dtype == "f32"))
+    P.compare_states(got, ref, tol, floor, set_floor=P.SET_FLOOR, phys=True)
 
 
 @pytest.mark.parametrize("M", [6, 8])
