@@ -24,7 +24,7 @@ HBM_PEAK_GBPS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
-def plane_accesses(wl, kernel):
+def plane_accesses(wl, kernel, split=True):
     """Complex planes read + written per cell-mode by one launch of each fused
     kernel (their algorithmic bytes).  With the regenerated set the axion
     advance runs in the axion-current kernel:
@@ -35,6 +35,9 @@ def plane_accesses(wl, kernel):
         (4 + 4), B_x at t^{n-1/2} and t^{n+1/2}, E_x at t^{n+1/2}, T_a^{n-1/2}
         (2), phi^n and S_a; writes T_a^{n+1/2} (2), phi^{n+1} and j_a (3).
     Without it kernel A also reads and writes the axion (phi, T_a^+-).
+    With ``split`` false (the option kernel AX) one launch does the work of
+    kernel A and the axion kernel: it reads and writes the background set and
+    the axion once and writes j_a (27 planes), and kernel 2 does not run.
     Electromagnetic-only: kernel 0 reads and writes the 6 (or 9) planes, and
     with a prescribed drive reads its j_x^(0) plane for mode 0 (1/M of a plane
     per cell-mode; the drive kernel that writes it is not counted)."""
@@ -44,6 +47,8 @@ def plane_accesses(wl, kernel):
             return 0
         return 2 * em + (1.0 / wl.nmodes if wl.drive is not None else 0.0)
     drv = 1.0 / wl.nmodes if wl.drive is not None else 0.0
+    if wl.arem and not split:
+        return {0: 2 * (em + 3) + 3 + drv, 1: 2 * em + 3, 2: 0}[kernel]
     if kernel == 0:
         return (2 * em + 1 if wl.arem else 2 * (em + 3)) + drv
     if kernel == 1:
@@ -53,6 +58,7 @@ def plane_accesses(wl, kernel):
 
 KERNEL_NAMES = {0: "kernel A (background set, axion source)", 1: "kernel B (regenerated set)",
                 2: "axion kernel (axion advance, axion current)"}
+KERNEL_NAME_AX = "kernel AX (background set, axion source, axion advance, axion current)"
 
 
 def workload(name):
@@ -226,21 +232,28 @@ def f32_leg(wl, steps):
             "tiles": tiles[0]}
 
 
-def overlap_leg(wl, dtype, tiles, steps):
-    """The main workload with and without QDS_OPT_OVERLAP (kernel A of step
-    k+1 on a second stream beside the regenerated set of step k), both with
-    the main run's tiles, ``steps`` timed steps each after 10 untimed, in
-    alternating order twice."""
+def kernel_variants_leg(wl, dtype, steps):
+    """The main workload on its three launch arrangements: the split kernels
+    (kernel A, the marched axion kernel, kernel B; the default) in one
+    stream, the same with kernel A of step k+1 on a second stream beside
+    kernel B of step k (QDS_OPT_OVERLAP), and the one-pass kernel AX then
+    kernel B (QDS_OPT_KERNEL_AX).
+    Each solver picks its tiles with its own autotuner on 8 untimed steps,
+    then runs 10 untimed and ``steps`` timed steps; the three run twice in
+    rotating order and the faster run of each is kept."""
     import torch
     from paper_2609_03550_amd import qds
-    res = {"serial": [], "overlap": []}
+    names = ("split", "split_overlap", "ax")
+    res = {n: [] for n in names}
+    tiles = {}
     for rep in range(2):
-        for name in (("serial", "overlap") if rep == 0 else ("overlap", "serial")):
+        for name in (names if rep == 0 else names[::-1]):
             s = qds.Solver(wl, dtype=dtype)
             s.load_pulses()
-            for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), tiles):
-                s.set_option(opt, int(v))
-            s.set_option(qds.OPT_OVERLAP, 1 if name == "overlap" else 0)
+            s.set_option(qds.OPT_KERNEL_AX, 1 if name == "ax" else 0)
+            s.set_option(qds.OPT_OVERLAP, 1 if name == "split_overlap" else 0)
+            s.set_option(qds.OPT_TUNE, 1)
+            s.step(8)
             s.step(10)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -249,9 +262,14 @@ def overlap_leg(wl, dtype, tiles, steps):
             e1.record()
             torch.cuda.synchronize()
             res[name].append(e0.elapsed_time(e1) / steps)
+            tiles[name] = s.tiles()[0]
             s.close()
-    out = {"steps": steps, "serial_ms_per_step": min(res["serial"]), "overlap_ms_per_step": min(res["overlap"])}
-    out["overlap_over_serial"] = out["overlap_ms_per_step"] / out["serial_ms_per_step"]
+    out = {"steps": steps}
+    for n in names:
+        out[n + "_ms_per_step"] = min(res[n])
+        out[n + "_tiles"] = tiles[n]
+    out["ax_over_split"] = out["ax_ms_per_step"] / out["split_ms_per_step"]
+    out["overlap_over_split"] = out["split_overlap_ms_per_step"] / out["split_ms_per_step"]
     return out
 
 
@@ -374,10 +392,14 @@ def main():
                     help="steps of the theta-grid vs direct product comparison at 6 and 8 modes (0 skips it)")
     ap.add_argument("--f32-steps", type=int, default=100,
                     help="steps of the single-precision figure of the same workload (0 skips it)")
+    ap.add_argument("--kernel-ax", type=int, default=0,
+                    help="1 runs the one-pass kernel AX instead of kernel A and the marched axion kernel "
+                         "(QDS_OPT_KERNEL_AX)")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1 runs kernel A of the next step beside the regenerated set (QDS_OPT_OVERLAP)")
-    ap.add_argument("--overlap-steps", type=int, default=100,
-                    help="steps of the overlap on/off comparison (0 skips it)")
+    ap.add_argument("--variant-steps", type=int, default=100,
+                    help="steps of the comparison of kernel AX with the split kernels, with and without "
+                         "the overlap (0 skips it)")
     ap.add_argument("--stream-reference", type=int, default=1,
                     help="1 times plain device copies for the copy-relative roofline fractions (0 skips them)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -396,6 +418,7 @@ def main():
     dev = torch.device("cuda:0")
     s = qds.Solver(wl, dtype=args.dtype, device="cuda:0", path=args.path, rows=args.rows)
     s.load_pulses()
+    s.set_option(qds.OPT_KERNEL_AX, args.kernel_ax)
     s.set_option(qds.OPT_OVERLAP, args.overlap)
     if args.tiles:
         for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), args.tiles.split(",")):
@@ -416,7 +439,8 @@ def main():
     s.step(args.warmup)
     torch.cuda.synchronize()
 
-    s.set_option(qds.OPT_TIMING, 1)
+    # the timed region: K steps with nothing between the launches but the
+    # launches themselves (events only at its two ends)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -425,6 +449,16 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
+    # per-kernel breakdown: a second pass of K steps with a HIP event pair
+    # around every launch (the events add a few per cent to each kernel, so
+    # this pass is not the headline)
+    s.set_option(qds.OPT_TIMING, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    breakdown_ms = e0.elapsed_time(e1) / args.steps
     kms, kn = s.timing()
     s.set_option(qds.OPT_TIMING, 0)
 
@@ -440,7 +474,10 @@ def main():
         avg = kms[q] / kn[q]
         name = KERNEL_NAMES[q] if (s.fused and wl.axion) else ("electromagnetic set" if s.fused else
                                                                  "staged step (all stage kernels)")
-        alg = (plane_accesses(wl, q) if s.fused else sum(plane_accesses(wl, k) for k in range(3))) * eb * cells
+        if s.fused and wl.arem and args.kernel_ax and q == 0:
+            name = KERNEL_NAME_AX
+        alg = (plane_accesses(wl, q, not args.kernel_ax) if s.fused
+               else sum(plane_accesses(wl, k, True) for k in range(3))) * eb * cells
         kernels[KERNEL_KEYS[q]] = {"name": name, "avg_launch_ms": avg, "launches": kn[q],
                                    "plane_passes": alg / eb / cells, "algorithmic_bytes_per_launch": alg,
                                    "achieved_gbps": alg / (avg / 1e3) / 1e9,
@@ -472,6 +509,7 @@ def main():
                    "physics": "QDS Maxwell + Klein-Gordon axion + regenerated fields + cold plasma"
                    if wl.arem else ("QDS Maxwell + prescribed current, moving window" if wl.drive else "QDS Maxwell"),
                    "path": "fused" if s.fused else "staged", "overlap": bool(args.overlap),
+                   "kernels": ("AX, B" if args.kernel_ax else "A, axion, B") if (s.fused and wl.arem) else None,
                    "parallelism": "single GPU"},
         # the dominant unit is the whole step (its kernels run back to back):
         # algorithmic bytes = every state plane read once and written once
@@ -479,7 +517,8 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "traffic_over_model": traffic / step_bytes if traffic else None,
                      "bytes_per_step": step_bytes, "bytes_per_cell_mode": 2 * nplanes * eb,
-                     "step_ms": ms_per_step, "kernel_sum_ms": kernel_sum_ms},
+                     "step_ms": ms_per_step, "kernel_sum_ms": kernel_sum_ms,
+                     "breakdown_pass_step_ms": breakdown_ms},
         "kernels": kernels,
         "fwd_adj_over_fwd": None,
         "tiles": dict(run_tiles, tuned=s.tiles()[1]),
@@ -498,9 +537,8 @@ def main():
     if args.f32_steps > 0 and args.dtype == "f64" and args.workload == "axion":
         out["f32"] = f32_leg(wl, args.f32_steps)
         torch.cuda.empty_cache()
-    if args.overlap_steps > 0 and wl.arem and s_fused:
-        out["overlap"] = overlap_leg(wl, args.dtype, [run_tiles[k] for k in ("kernel_a", "axion_current", "kernel_b")],
-                                     args.overlap_steps)
+    if args.variant_steps > 0 and wl.arem and s_fused:
+        out["kernel_variants"] = kernel_variants_leg(wl, args.dtype, args.variant_steps)
         torch.cuda.empty_cache()
     if args.theta_steps > 0:
         out["theta_grid_products"] = theta_leg(args.theta_steps)

@@ -186,7 +186,8 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
  *                 times its first 8 steps (two passes over four tile heights
  *                 per kernel: 8, 16, 24, 32 for the background set with the
- *                 axion, 8, 16, 26, 52 for the background set alone, 4, 6, 8,
+ *                 axion, 16, 24, 32, 48 for kernel AX, 8, 16, 26, 52 for the
+ *                 background set alone, 4, 6, 8,
  *                 16 for the axion current, 16, 32, 52, 64 for the regenerated
  *                 set; HIP events around every launch) and keeps the fastest
  *                 height for each kernel; the trial steps are ordinary
@@ -198,19 +199,33 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 pair through a theta grid of 3*modes - 2 points, exact for
  *                 modes 0..modes-1 (Sec. 3.3), on the staged kernels (the
  *                 handle then runs the staged path)
- *  QDS_OPT_OVERLAP 1: with the regenerated set on the fused kernels (and no
- *                 prescribed drive), kernel A of step k+1 runs on a second
+ *  QDS_OPT_OVERLAP 1: with the regenerated set on the fused kernels (kernel
+ *                 A and the axion kernel, no prescribed drive), kernel A of
+ *                 step k+1 runs on a second
  *                 stream of the handle beside kernel B of step k (they share
  *                 no plane); events order it after the axion kernel of step
  *                 k, and every launch is joined back into the caller's
  *                 stream before qds_step returns.  0: one stream.
+ *  QDS_OPT_KERNEL_AX 1: with the regenerated set on the fused kernels (no
+ *                 moving window), one launch (kernel AX) advances the
+ *                 background set, forms the axion source, advances the axion
+ *                 and forms the axion current from one read of the background
+ *                 set and the axion (Sec. 2.1, Sec. 2.2 and Eqs. jax_mode,
+ *                 jar_mode, jat_mode: 48 plane passes per step with kernel B
+ *                 instead of 61), tile height QDS_OPT_ROWS_A (tuner
+ *                 candidates 16, 24, 32, 48).  0 (default): kernel A writes
+ *                 the axion source to scratch and the marched axion kernel
+ *                 re-reads the background set to advance the axion and form
+ *                 its current (measured faster on MI355X: the one-pass march
+ *                 holds both windows, which halves its occupancy).
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
  *                 value resets the recorded launches */
 enum {
     QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
-    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8, QDS_OPT_OVERLAP = 9
+    QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8, QDS_OPT_OVERLAP = 9,
+    QDS_OPT_KERNEL_AX = 10
 };
 enum { QDS_PRODUCTS_DIRECT = 0, QDS_PRODUCTS_THETA = 1 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };

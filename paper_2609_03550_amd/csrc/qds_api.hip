@@ -14,11 +14,13 @@ using namespace qdsi;
 namespace {
 
 // Tile-height candidates of the autotuner (two passes over four per kernel
-// class): kernel A (the background set with the axion), the marched axion
+// class): kernel A (the background set with the axion), kernel AX (the
+// background set, the axion and its current in one pass), the marched axion
 // kernel, kernel B (the regenerated set), and the background set alone, whose
 // one-wave tiles want tall chunks on large grids (26 rows fill the GPU once at
 // 4096 x 256 x 3) and short ones on small grids.
 const int kCandA[4] = {8, 16, 24, 32};
+const int kCandAX[4] = {16, 24, 32, 48};
 const int kCandCur[4] = {4, 6, 8, 16};
 const int kCandB[4] = {16, 32, 52, 64};
 const int kCandEm[4] = {8, 16, 26, 52};
@@ -121,7 +123,9 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t err = hipSuccess;
     if (which == kLaunchA) {
-        if (p0.axion) {
+        if (fuse_ax(c, p0)) {
+            err = qds::batch_ax<T>(v.fa, list(v.firstA, c->trows[0]), c->M, v.nA, s);
+        } else if (p0.axion) {
             err = qds::batch_a<T>(v.fa, list(v.firstA, c->trows[0]), c->M, v.nA, !march_axion(c, p0), s);
         } else {
             // the background set alone: the kernel-B march with the kernel-A tile
@@ -146,7 +150,8 @@ template <typename T>
 qds_status table_launch(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, hipStream_t s, hipEvent_t* ev) {
     qds_status r = table_launch_one<T>(c, p0, v, kLaunchA, s, ev);
     if (r != QDS_OK || !p0.arem) return r;
-    if ((r = table_launch_one<T>(c, p0, v, kLaunchX, s, ev ? ev + 2 : nullptr)) != QDS_OK) return r;
+    if (!fuse_ax(c, p0) && (r = table_launch_one<T>(c, p0, v, kLaunchX, s, ev ? ev + 2 : nullptr)) != QDS_OK)
+        return r;
     return table_launch_one<T>(c, p0, v, kLaunchB, s, ev ? ev + 4 : nullptr);
 }
 
@@ -226,7 +231,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
     if (c->tune && n_steps >= kTrials) {
         // autotuner: timed ordinary steps, two passes over four tile heights per
         // kernel (candidates around each kernel's measured optimum)
-        const int* cand[3] = {p0.axion ? kCandA : kCandEm, kCandCur, kCandB};
+        const int* cand[3] = {fuse_ax(c, p0) ? kCandAX : (p0.axion ? kCandA : kCandEm), kCandCur, kCandB};
         std::vector<hipEvent_t> ev(6 * kTrials);
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
@@ -242,8 +247,12 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
         for (int t = 0; t < kTrials; ++t)
             for (int k = 0; k < 3; ++k) {
                 if (k > 0 && !p0.arem) continue;
+                if (k == 1 && fuse_ax(c, p0)) continue;      // no separate axion kernel
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[6 * t + 2 * k], ev[6 * t + 2 * k + 1]) != hipSuccess) continue;
+                if (hipEventElapsedTime(&ms, ev[6 * t + 2 * k], ev[6 * t + 2 * k + 1]) != hipSuccess) {
+                    (void)hipGetLastError();   // do not leave the error for the next launch check
+                    continue;
+                }
                 const int slot = k == 0 ? 0 : (k == 1 ? 1 : 2);
                 if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[slot][t % 4]; }
             }
@@ -255,7 +264,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
     }
     if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
     const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
-    if (c->overlap && p0.arem && march_axion(c, p0) && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW &&
+    if (c->overlap && p0.arem && march_axion(c, p0) && !fuse_ax(c, p0) && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW &&
         n_steps - done >= 2)
         return overlapped_steps<T>(c, st, p0, K, host, n_steps - done, s);
     for (int64_t it = done; it < n_steps; ++it)
@@ -701,6 +710,9 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
             return QDS_OK;
         case QDS_OPT_OVERLAP:
             h->overlap = value ? 1 : 0;
+            return QDS_OK;
+        case QDS_OPT_KERNEL_AX:
+            h->kernel_ax = value ? 1 : 0;
             return QDS_OK;
         case QDS_OPT_PRODUCTS:
             if (value != QDS_PRODUCTS_DIRECT && value != QDS_PRODUCTS_THETA)

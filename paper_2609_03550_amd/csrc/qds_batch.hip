@@ -291,7 +291,10 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 for (int q = 0; q < QDS_NTILES; ++q) { sum[q] = 0.f; seen[q] = false; }
                 for (const Launch& l : trial[tr]->launches) {
                     float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]) != hipSuccess) ms = 3.4e38f;
+                    if (hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]) != hipSuccess) {
+                        ms = 3.4e38f;
+                        (void)hipGetLastError();   // not left for the next launch check
+                    }
                     ei += 2;
                     sum[l.slot] += ms;
                     seen[l.slot] = true;

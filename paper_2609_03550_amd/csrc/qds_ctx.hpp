@@ -27,6 +27,7 @@ struct qds_ctx {
     int tuned;
     int timing;              // record per-kernel HIP events in qds_step
     int overlap;             // kernel A of step k+1 on a second stream beside kernel B of step k
+    int kernel_ax;           // 1: one-pass kernel AX instead of kernel A and the marched axion kernel
     hipStream_t side;        // that stream (created on first use, default priority)
     hipEvent_t ev_x, ev_a;   // its ordering events
     // timing events, recorded without synchronising and resolved by
@@ -167,6 +168,13 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
 template <typename T>
 bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0) {
     return p0.axion && p0.arem && c->g.x_bc != QDS_X_WINDOW && p0.sa != nullptr;
+}
+
+// Whether one launch of kernel AX advances the background set, the axion and
+// the axion current together (QDS_OPT_KERNEL_AX, where the axion march applies).
+template <typename T>
+bool fuse_ax(const qds_ctx* c, const qds::StepPlan<T>& p0) {
+    return c->kernel_ax && march_axion(c, p0);
 }
 
 // Fused-kernel arguments of one step from buffer A (old) to buffer B (new).

@@ -20,7 +20,7 @@
 // per step into a plane of its own (k_drive_plane) that the background set
 // reads as an extra j_x of mode 0.  They compute exactly the quantities of
 // the staged kernels.
-#include "qds_kernels.hpp"
+#include "qds_current_rows.hpp"
 
 namespace qds {
 namespace fused {
@@ -483,32 +483,20 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
     W.bx1[0] = W.bx1[1];
 }
 
-// LDS exchange slots per lane: the 6 factors of the axion source (two such
-// buffers, alternating by row)
-constexpr int NS = 6;
-
-// ---------------------------------------------------------------------------
-// kernel A: background set + axion
-// ---------------------------------------------------------------------------
-// AXT: kernel A advances the axion (T_a, phi); otherwise it writes S_a to a.sa
-// for the marched axion current, which advances the axion instead.
-template <typename T, int M, bool AXT>
-__device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
-    const Geo g = a.g;
-    const int wave = threadIdx.x / WAVE;
-    const int lane = threadIdx.x % WAVE;
-    const int r0 = chunk * rows;
-    const int r1 = min(g.nr + 1, r0 + rows);
-    const int ncell = g.nx;                       // H cells 0..nx-1 (the last is dead unless periodic)
+// Per-lane context of a marching wave of mode m over one strip: column of
+// the lane (halo lanes wrap with periodic x; otherwise they are clamped, and
+// their results only reach owned lanes through terms the x boundary zeroes),
+// ownership and the step's constants.
+template <typename T>
+__device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int m, int lane) {
+    const Geo& g = a.g;
     Ctx<T> c;
     c.g = g;
-    c.m = wave;
+    c.m = m;
     c.lane = lane;
     const int raw = strip * OWN - 1 + lane;
-    const bool inrange = raw >= 0 && raw < ncell;
-    // halo lanes wrap with periodic x; otherwise they are clamped (their
-    // results only reach owned lanes through terms the x boundary zeroes)
-    c.i = g.per ? ((raw % ncell) + ncell) % ncell : (raw < 0 ? 0 : (raw >= ncell ? ncell - 1 : raw));
+    const bool inrange = raw >= 0 && raw < g.nx;
+    c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
     c.owner = inrange && lane >= 1 && lane <= OWN;
     c.live = g.per || c.i < g.nx - 1;
     c.x.nr1 = g.nr + 1;
@@ -527,6 +515,26 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     c.inv_2h = T(0.5) / c.h;
     c.wp2h = T(a.wp2 * g.h);
     c.plasma = a.plasma;
+    return c;
+}
+
+// LDS exchange slots per lane: the 6 factors of the axion source (two such
+// buffers, alternating by row)
+constexpr int NS = 6;
+
+// ---------------------------------------------------------------------------
+// kernel A: background set + axion
+// ---------------------------------------------------------------------------
+// AXT: kernel A advances the axion (T_a, phi); otherwise it writes S_a to a.sa
+// for the marched axion current, which advances the axion instead.
+template <typename T, int M, bool AXT>
+__device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
+    const Geo g = a.g;
+    const int wave = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
+    const Ctx<T> c = make_ctx<T>(a, strip, wave, lane);
 
     extern __shared__ unsigned char smem_raw[];
     // two exchange buffers [NS][M][WAVE], alternating by row: the one barrier
@@ -688,6 +696,263 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
 }
 
 // ---------------------------------------------------------------------------
+// kernel AX: the background set, the axion source, the axion advance and the
+// axion current in one r-march (the regenerated set follows in kernel B)
+// ---------------------------------------------------------------------------
+// A workgroup is M wavefronts (one per mode) over one strip and a chunk of
+// rows, as kernel A.  On row j a wave advances the background set (em_step),
+// forms S_a at K = j through the LDS exchange of its factors, advances the
+// axion on K = j (Gamma_a, the T_a^+- transport and phi^{n+1}), and then
+// builds the per-point combinations of K = j and J = j that the axion current
+// reads from the values already in its registers: the old and new transport
+// variables, E_x and B_x at both levels, and the old and new axion.  Nothing
+// of the background set is read twice and S_a never leaves the chip.  The
+// current's factors of j_a,x and j_a,theta at row j and of j_a,r at K = j - 1
+// (which needs T_theta^{n+1} on J = j) go through a second LDS exchange.  A
+// chunk [r0, r1) owns the rows of the background set, the axion and j_a,x,
+// j_a,theta in [r0, r1), and the j_a,r rows K in [r0 - 1, r1 - 1) (so no row
+// above the chunk is needed); it marches from the halo row r0 - 2, whose
+// E_x^{n+1/2}(J = r0 - 1) completes S_a and the row windows of K = r0 - 1.
+// LDS: area X holds the 6 factors of S_a, area Y the 18 of j_a; two barriers
+// per row order the writes of one row after every wave's reads of the last.
+constexpr int NJ = 18;
+
+// Output stores of the axion and its current: streaming in FP64 (kernel B,
+// which runs next, measured faster with T_a, phi and j_a kept out of the
+// caches), plain in FP32.
+template <typename T>
+__device__ __forceinline__ void sto_ax(cx<T>* p, uint32_t o, cx<T> v) {
+    cx<T>* q = (cx<T>*)((g_char*)(p) + o);
+    if constexpr (sizeof(T) == 8) st_nt(q, v);
+    else st(q, v);
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void fused_ax_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
+    const Geo g = a.g;
+    const int wave = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
+    const Ctx<T> c = make_ctx<T>(a, strip, wave, lane);
+    const int m = wave;
+
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* const smX = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* const smY = smX + NS * M * WAVE;
+    auto put = [&](cx<T>* base, int f, cx<T> v) { base[(f * M + wave) * WAVE + lane] = v; };
+    auto get = [&](const cx<T>* base, int f, int k) { return base[(f * M + k) * WAVE + lane]; };
+    // out += C{f0, f1} - C{f2, f3} + C{f4, f5} over the six factors from slot f0
+    auto conv3 = [&](int f0, cx<T>& out) {
+        cx<T> A[M], B[M];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) { A[k] = get(smY, f0 + 2 * q, k); B[k] = get(smY, f0 + 2 * q + 1, k); }
+            conv_one<T, M>(A, B, m, out, q == 1 ? T(-1) : T(1));
+        }
+    };
+
+    const SetP<T>& s = a.s0;
+    EmWin<T> W;
+    for (int q = 0; q < 2; ++q) {
+        W.rpa[q] = W.rma[q] = zero<T>();
+        W.tpa[q] = W.tma[q] = zero<T>();
+        W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
+    }
+    W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
+    W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
+    W.pjx = W.pjxa = zero<T>();
+    cx<T> phw[3];     // phi^n at K = j-1, j, j+1
+    phw[0] = phw[1] = phw[2] = zero<T>();
+    const T h = c.h;
+    const T kap = c.kap;
+    const T sj = T(a.s_j);
+    const bool has1 = c.x.i1 >= 0;
+    const cur::FacC<T> fc{m, parity<T>(m), tghost<T>(m), c.dr, c.inv_dr, a.bx0, a.br1, a.bt1};
+    auto phi_row = [&](int k) {
+        if (k < 0) return zero<T>();
+        if (k < g.nr) return c.x.L(a.phi, m, k);
+        if (k == g.nr && g.open_r) return c.x.L(a.phi, m, g.nr);
+        return zero<T>();
+    };
+    const int jstart = max(r0 - 2, -1);
+    // first row whose S_a, axion advance and row windows are complete
+    const int jfull = max(r0 - 1, 0);
+    if (jstart >= 0) {
+        em_take(c, W, em_fetch(c, s, jstart), jstart, g.nr);   // row jstart into slot 1
+        phw[2] = phi_row(jstart);
+        phw[1] = phi_row(jstart - 1);
+    }
+    cur::KRow<T> kp = cur::zero_k<T>();   // K row j - 1
+    cur::JRow<T> jp = cur::zero_j<T>();   // J row j - 1
+    const int jend = r1 == g.nr + 1 ? g.nr : r1 - 1;
+    for (int j = jstart; j <= jend; ++j) {
+        // ---------------- shift the window and load row j+1 (issued together
+        // with the row's currents and T_a, and consumed at once: a prefetch of
+        // the next row one iteration ahead, kept across the axion part,
+        // measured slower, its registers costing a wave per SIMD in FP32 and
+        // spills in FP64)
+        em_rotate(W);
+        phw[0] = phw[1]; phw[1] = phw[2];
+        phw[2] = phi_row(j + 1);
+        em_take(c, W, em_fetch(c, s, j + 1), j + 1, g.nr);
+        // FP64 issues the T_a loads of row j with the row's other loads; FP32
+        // loads them where they are used (as kernel A)
+        constexpr bool HOIST = sizeof(T) == 8;
+        cx<T> tap_a = zero<T>(), tam_a = zero<T>();
+        if (HOIST && j >= jfull && j < g.nr) {
+            tap_a = c.x.L(a.tap, m, j);
+            tam_a = c.x.L(a.tam, m, j);
+        }
+        const EmRowX<T> X = em_fetch_x(c, s, j);
+        const EmB<T> B = em_bvals(c, W);
+        const cx<T> ex1_j = W.ex1[1];
+        const RowInv<T> ri = row_inv(c, j);
+        em_step(c, s, W, B, j, r0, r1, ri, X);
+        if (j < 0) continue;
+        if (j == g.nr - 1) em_ghost_bth(c, s, W, B, r1);
+        if (j < jfull) continue;      // the same for every wave of the workgroup
+        const bool own_row = j >= r0 && j < r1;
+
+        // ---------------- axion source S_a at K = j (Eqs. source_mode_zero/_m)
+        if (j < g.nr) {
+            cx<T> bx_n = T(0.5) * (W.bx0[0] + W.bx1[1]);
+            cx<T> exn0 = T(0.5) * (W.ex0[0] + ex1_j);
+            cx<T> exn1 = T(0.5) * (W.ex0[1] + W.ex1[2]);
+            cx<T> fEx = T(0.5) * (exn0 + exn1);
+            cx<T> fBx = bx_n;
+            cx<T> fPp = T(0.25) * (W.rpa[0] + B.rpb[0]);
+            cx<T> fPm = T(-0.25) * (W.rma[0] + B.rmb[0]);
+            cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (B.tpb[0] + B.tpb[1]));
+            cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (B.tmb[0] + B.tmb[1]));
+            if (m == 0) fBx = fBx + a.bx0;
+            if (m == 1) {
+                fPp = fPp + T(0.5) * a.bt1;
+                fPm = fPm + T(0.5) * a.bt1;
+                fQp = fQp + a.br1;
+                fQm = fQm - a.br1;
+            }
+            put(smX, 0, fEx); put(smX, 1, fBx); put(smX, 2, fPp); put(smX, 3, fQp); put(smX, 4, fPm); put(smX, 5, fQm);
+        }
+        __syncthreads();
+        cur::KRow<T> kc = cur::zero_k<T>();
+        if (j < g.nr) {
+            cx<T> Sa = zero<T>();
+            cx<T> A[M], Bq[M];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { A[k] = get(smX, 2 * q, k); Bq[k] = get(smX, 2 * q + 1, k); }
+                conv_one<T, M>(A, Bq, m, Sa, T(1));
+            }
+            if (!c.live) Sa = zero<T>();
+            // ---------------- Gamma_a, T_a transport, phi (Eqs. Ta_plus/minus_update, phi_update)
+            const cx<T> p = phw[1];
+            const cx<T> up = phw[2];
+            const cx<T> dn = (j > 0) ? phw[0] : zero<T>();
+            cx<T> ga = zero<T>();
+            if (c.live)
+                ga = (c.inv_dr * c.inv_dr) * (up - T(2) * p + dn) + (c.inv_2dr * ri.irK) * (up - dn)
+                     - (T(m * m) * ri.irK * ri.irK + T(a.ma2)) * p + T(a.s_phi) * Sa;
+            if (!HOIST) {
+                tap_a = c.x.L(a.tap, m, j);
+                tam_a = c.x.L(a.tam, m, j);
+            }
+            const cx<T> tam_b = c.x.Rn(tam_a);   // uniform control flow here
+            const cx<T> nap_b = has1 ? tap_a + h * ga : zero<T>();     // T_a^+ at column i+1
+            const cx<T> nam_a = tam_b + h * ga;                         // T_a^- at column i
+            const cx<T> l = shfl_up1(nap_b), rr = shfl_dn1(nam_a);
+            const cx<T> nap_a = (c.i == 0 && !g.per) ? zero<T>() : l;
+            const cx<T> nam_b = has1 ? rr : zero<T>();
+            cx<T> p1 = zero<T>();
+            if (c.live) p1 = p + (h / T(4)) * (nap_a + nap_b + nam_a + nam_b);
+            if (own_row && c.owner) {
+                if (has1) sto_ax(a.otap, eoff<T>(g, m, j, c.x.i1), nap_b);
+                sto_ax(a.otam, eoff<T>(g, m, j, c.i), nam_a);
+                sto_ax(a.ophi, eoff<T>(g, m, j, c.i), p1);
+                if (c.i == 0 && !g.per) sto_ax(a.otap, eoff<T>(g, m, j, c.i), zero<T>());
+                if (j == g.nr - 1) {
+                    // exterior ghost phi at r_{nr+1/2}: outgoing-wave condition, two-level centring
+                    cx<T> Gn = up;
+                    if (g.open_r) Gn = c.live ? (p + kap * (up - p1)) : zero<T>();
+                    sto_ax(a.ophi, eoff<T>(g, m, g.nr, c.i), Gn);
+                }
+            }
+            // ---------------- the current's combinations on K = j
+            const T q = T(0.5);
+            kc.bxn = q * (W.bx0[0] + W.bx1[1]);
+            kc.er0 = q * (W.rpa[0] + W.rma[0]);
+            kc.P = q * (W.rpa[0] + W.n_rpa);
+            kc.N = q * (W.rma[0] + W.n_rma);
+            kc.ph0 = p;
+            kc.up = nap_a;
+            kc.wm = nam_a;
+            kc.dt0 = q * (q * (tap_a + tam_a) + q * (nap_a + nam_a));
+            kc.phm = q * (p + p1);
+        }
+        // ... and on J = j
+        cur::JRow<T> jc;
+        {
+            const T q = T(0.5);
+            jc.et0 = q * (W.tpa[0] + W.tma[0]);
+            jc.Qp = q * (W.tpa[0] + W.n_tpa);
+            jc.Qm = q * (W.tma[0] + W.n_tma);
+            jc.ex = ex1_j;
+        }
+        // ---------------- axion current (Eqs. jax_mode, jat_mode at row j; jar_mode at K = j - 1)
+        const bool do_xt = own_row;
+        const bool do_r = j >= r0 && j >= 1;
+        const bool calc_xt = do_xt && c.live && j < g.nr;
+        const bool calc_r = do_r && c.live;
+        {
+            const cur::NbX<T> nx = cur::nb_x(kp, kc, jc, has1);
+            if (calc_xt) {
+                cx<T> f[6];
+                cur::fac_x(fc, j, kp, kc, jc, nx, f);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) put(smY, k, f[k]);
+            }
+        }
+        {
+            const cur::NbT<T> nt = cur::nb_t(kp, kc, jc, has1);
+            if (calc_xt) {
+                cx<T> f[6];
+                cur::fac_t(fc, j, kp, kc, jc, nt, f);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) put(smY, 6 + k, f[k]);
+            }
+        }
+        {
+            const cur::NbR<T> nr = cur::nb_r(kp, jp, jc, has1);
+            if (calc_r) {
+                cx<T> f[6];
+                cur::fac_r(fc, j - 1, kp, jp, jc, nr, f);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) put(smY, 12 + k, f[k]);
+            }
+        }
+        __syncthreads();
+        if (do_xt && c.owner) {
+            cx<T> ox = zero<T>(), ot = zero<T>();
+            if (calc_xt) {
+                conv3(0, ox);
+                conv3(6, ot);
+            }
+            sto_ax(a.jax, eoff<T>(g, m, j, c.i), sj * ox);
+            sto_ax(a.jat, eoff<T>(g, m, j, c.i), sj * ot);
+        }
+        if (do_r && c.owner) {
+            cx<T> orr = zero<T>();
+            if (calc_r) conv3(12, orr);
+            sto_ax(a.jar, eoff<T>(g, m, j - 1, c.i), sj * orr);
+        }
+        kp = kc;
+        jp = jc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // kernel B (and the electromagnetic-only step): one set, marched in r
 // ---------------------------------------------------------------------------
 template <typename T, int WHICH>
@@ -696,31 +961,7 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
     const int lane = threadIdx.x;
     const int r0 = chunk * rows;
     const int r1 = min(g.nr + 1, r0 + rows);
-    Ctx<T> c;
-    c.g = g;
-    c.m = m;
-    c.lane = lane;
-    const int raw = strip * OWN - 1 + lane;
-    const bool inrange = raw >= 0 && raw < g.nx;
-    c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
-    c.owner = inrange && lane >= 1 && lane <= OWN;
-    c.live = g.per || c.i < g.nx - 1;
-    c.x.nr1 = g.nr + 1;
-    c.x.ld = g.ld;
-    c.x.i = c.i;
-    c.x.i1 = (c.i + 1 < g.nx) ? c.i + 1 : (g.per ? 0 : -1);
-    c.x.ir = c.x.i1;
-    c.o.shift = a.window;
-    c.o.nx = g.nx;
-    c.h = T(g.h);
-    c.dr = T(g.dr);
-    c.inv_dr = T(1) / c.dr;
-    c.inv_2dr = T(0.5) * c.inv_dr;
-    c.kap = (c.dr - c.h) / (c.dr + c.h);
-    c.cR = T(2) * c.h * c.dr / (c.dr + c.h);
-    c.inv_2h = T(0.5) / c.h;
-    c.wp2h = T(a.wp2 * g.h);
-    c.plasma = a.plasma;
+    const Ctx<T> c = make_ctx<T>(a, strip, m, lane);
     const SetP<T>& s = WHICH ? a.s1 : a.s0;
     EmWin<T> W;
     for (int q = 0; q < 2; ++q) {
@@ -784,6 +1025,21 @@ k_batch_a_f32(const FusedArgs<float>* __restrict__ args, BatchList L) {
     batch_a_body<float, M, AXT>(args, L);
 }
 
+template <typename T, int M>
+__device__ __forceinline__ void batch_ax_body(const FusedArgs<T>* __restrict__ args, const BatchList& L) {
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = batch_find(L, b);
+    const FusedArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int strips = fused_strips(a.g.nx);   // strips fastest, as kernel A
+    fused_ax_body<T, M>(a, local % strips, local / strips, L.rows);
+}
+template <typename T, int M>
+__global__ void __launch_bounds__(WAVE * M) __attribute__((amdgpu_waves_per_eu(2)))
+k_batch_ax(const FusedArgs<T>* __restrict__ args, BatchList L) {
+    batch_ax_body<T, M>(args, L);
+}
+
 template <typename T, int WHICH>
 __global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restrict__ args, BatchList L) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -829,6 +1085,28 @@ hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int bloc
 }
 
 template <typename T>
+hipError_t batch_ax(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = size_t(fused::NS + fused::NJ) * M * fused::WAVE * sizeof(cx<T>);
+    switch (M) {
+#define QDS_BX(MM)                                                                                     \
+    case MM: {                                                                                         \
+        /* above 64 KiB of LDS per workgroup (FP64, three or four modes) */                            \
+        static const hipError_t attr = hipFuncSetAttribute(                                            \
+            reinterpret_cast<const void*>(&fused::k_batch_ax<T, MM>),                                  \
+            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));                                     \
+        if (attr != hipSuccess) return attr;                                                           \
+        hipLaunchKernelGGL((fused::k_batch_ax<T, MM>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+        break;                                                                                         \
+    }
+        QDS_BX(1) QDS_BX(2) QDS_BX(3) QDS_BX(4)
+#undef QDS_BX
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     if (which)
@@ -840,6 +1118,8 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
 
 template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, bool, hipStream_t);
+template hipError_t batch_ax<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_ax<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);

@@ -219,6 +219,10 @@ template <typename T>
 hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, bool axt, hipStream_t s);
 template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
+// Kernel AX: the background set, the axion source, the axion advance and the
+// axion current in one launch (every instance of the list has sa set).
+template <typename T>
+hipError_t batch_ax(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
 template <typename T>
 hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
 // Column strips of the marching axion-current kernel (61 owned columns each,

@@ -32,6 +32,7 @@ OPT_PATH, OPT_ROWS, OPT_TIMING, OPT_TUNE = 1, 2, 3, 4
 OPT_ROWS_A, OPT_ROWS_CUR, OPT_ROWS_B = 5, 6, 7       # one kernel's tile height
 OPT_PRODUCTS = 8
 OPT_OVERLAP = 9
+OPT_KERNEL_AX = 10
 PRODUCTS_DIRECT, PRODUCTS_THETA = 0, 1
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 

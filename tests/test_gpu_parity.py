@@ -278,13 +278,27 @@ def test_random_full_state(dtype, x_bc, r_bc, arem, M):
     P.compare_states(s.fields(), ref, tol, floor, set_floor=P.SET_FLOOR, phys=True)
 
 
+def _random_reachable_state(wl, seed):
+    """O(1) seeded random values in every complex plane, then one oracle step
+    (fixed axis rows, ghosts): a state the scheme can reach."""
+    from oracle import qds as Q
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    gen = torch.Generator().manual_seed(seed)
+    for k, v in st.items():
+        if isinstance(v, torch.Tensor) and v.is_complex():
+            st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    return Q.step(st, g, ph), g, ph
+
+
+@pytest.mark.parametrize("kernel_ax", [0, 1])
 @pytest.mark.parametrize("x_bc,r_bc", [("open", "open"), ("periodic", "pec")])
-def test_axion_advance_in_current_march_equals_kernel_a(x_bc, r_bc):
-    """Two placements of the axion advance on one random full state: with the
-    regenerated set the marched axion kernel advances T_a and phi from the
-    S_a that kernel A leaves in scratch; without it kernel A advances them
+def test_axion_advance_in_current_march_equals_kernel_a(x_bc, r_bc, kernel_ax):
+    """Placements of the axion advance on one random full state: with the
+    regenerated set, the marched axion kernel after kernel A (kernel_ax 0) or
+    the one-pass kernel AX (kernel_ax 1) advances T_a and phi; without it kernel A advances them
     itself.  The background set and the axion do not depend on the
-    regenerated set, so after 6 steps the two runs agree on them bit for bit."""
+    regenerated set, so after 6 steps the runs agree on them bit for bit."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
     wl = _full(131, 21, 3, x_bc=x_bc, r_bc=r_bc)
@@ -296,6 +310,7 @@ def test_axion_advance_in_current_march_equals_kernel_a(x_bc, r_bc):
             st[k] = torch.randn(v.shape, dtype=torch.complex128, generator=gen)
     st = Q.step(st, g, ph)
     a = qds.Solver(wl, dtype="f64")
+    a.set_option(qds.OPT_KERNEL_AX, kernel_ax)
     a.load_fields(st)
     a.step(6)
     b = qds.Solver(wl.with_(arem=False), dtype="f64")
@@ -384,3 +399,38 @@ def test_stop_save_reload_continue_is_bitwise():
     fa, fc = a.fields(), c.fields()
     for k in fa:
         assert torch.equal(fa[k], fc[k]), k
+
+
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows", [
+    ("f64", 3, "open", "open", 1), ("f64", 3, "open", "open", 2), ("f64", 3, "open", "open", 5),
+    ("f64", 3, "periodic", "pec", 3), ("f64", 3, "open", "pec", 24), ("f64", 1, "open", "open", 4),
+    ("f64", 2, "periodic", "open", 7), ("f64", 4, "open", "open", 6), ("f32", 3, "open", "open", 4),
+    ("f32", 2, "open", "pec", 1), ("f32", 4, "periodic", "pec", 9)])
+def test_kernel_ax_equals_split_kernels_and_oracle(dtype, M, x_bc, r_bc, rows):
+    """Kernel AX (the background set, the axion source, the axion advance and
+    the axion current in one r-march, j_a,r rows owned one row down) against
+    the split kernels (kernel A writing S_a, the marched axion kernel
+    re-reading the background set) on a random full state, at chunk heights
+    from one row up (the two lower halo rows, the ghost chunk, ragged last
+    chunks): every plane agrees to rounding after 5 steps, and both match the
+    oracle per field."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = _full(190, 23, M, x_bc=x_bc, r_bc=r_bc)
+    st, g, ph = _random_reachable_state(wl, 31 + rows)
+    out = []
+    for kernel_ax in (1, 0):
+        s = qds.Solver(wl, dtype=dtype)
+        s.set_option(qds.OPT_KERNEL_AX, kernel_ax)
+        s.set_option(qds.OPT_ROWS, rows)
+        s.load_fields(st)
+        assert s.fused
+        s.step(5)
+        torch.cuda.synchronize()
+        out.append(s.fields())
+    ref = Q.run(st, g, ph, 5)
+    tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
+    for f in out:
+        P.compare_states(f, ref, tol, floor, set_floor=P.SET_FLOOR, phys=True)
+    close = (1e-14, 1e-15) if dtype == "f64" else (2e-6, 1e-7)
+    P.compare_states(out[0], out[1], *close)
