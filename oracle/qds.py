@@ -22,14 +22,16 @@ the last column (i = nx-1) lies outside the domain and is kept at zero.
 Row nr of the K arrays is the exterior ghost row r_{nr+1/2} used by the outer
 radial boundary.
 
-Pins (tests/test_oracle_pins.py) hold it to what the paper and the mathematics
-fix: dispersion relations, waveguide spectra, exact one-cell transport, the
-theta-product form of the mode convolutions, photon-axion conversion, plasma
-oscillation, axion-photon regeneration through j_a, outgoing waves leaving
-through the open outer boundary, white lab-frame drive noise, and more.  Parity unpinned (checked only
-against the GPU path): the curvature and transverse terms of the outer radial
-ghost updates beyond that absorption test, the interpolation of j_a to its
-source points and its axis limits beyond the static-field regeneration test.
+Pins hold it to what the paper and the mathematics fix (tests/test_oracle_pins.py,
+test_oracle_axion_current_convergence.py, test_oracle_outer_boundary.py,
+test_stability_bound.py, test_theta_grid_pin.py, test_identities.py): dispersion
+relations, waveguide spectra, exact one-cell transport, the theta-product form
+of the mode convolutions, photon-axion conversion and its reverse through j_a,
+plasma oscillation, second-order convergence of S_a and of j_a at every source
+point (axis rows included) to the continuous E.B and B d_t phi - E x grad phi,
+the exterior ghosts of the open radial boundary against exact outgoing Hankel
+waves at second order, outgoing shells, white lab-frame drive noise, and more.
+No function here is parity-unpinned.
 
 State keys (s = 0 background set, s = 1 axion-regenerated set):
   Trp{s} Trm{s} [M,nr,nx]   Ttp{s} Ttm{s} [M,nr+1,nx]   Ex{s} [M,nr+1,nx]

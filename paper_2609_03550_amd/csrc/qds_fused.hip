@@ -536,7 +536,7 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
     const int r1 = min(g.nr + 1, r0 + rows);
     const Ctx<T> c = make_ctx<T>(a, strip, wave, lane);
 
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     // two exchange buffers [NS][M][WAVE], alternating by row: the one barrier
     // per row (after the writes) then also keeps the next row's writes behind
     // every wave's reads of this row
@@ -737,7 +737,7 @@ __device__ __forceinline__ void fused_ax_body(const FusedArgs<T>& a, int strip, 
     const Ctx<T> c = make_ctx<T>(a, strip, wave, lane);
     const int m = wave;
 
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* const smX = reinterpret_cast<cx<T>*>(smem_raw);
     cx<T>* const smY = smX + NS * M * WAVE;
     auto put = [&](cx<T>* base, int f, cx<T> v) { base[(f * M + wave) * WAVE + lane] = v; };
