@@ -275,9 +275,12 @@ def kernel_variants_leg(wl, dtype, steps):
 
 def theta_leg(steps=20):
     """Axion source and current by the theta-grid transform pair against the
-    direct mode convolution, both on the staged kernels: 6 and 8 modes of the
-    full physics on a 2048 x 64 grid with dr = 8 dx (what the radial stability
-    bound allows for 8 modes), FP64, ``steps`` timed steps after 3 untimed."""
+    direct mode convolution on the staged kernels (one thread per point and
+    every mode), and the direct convolution on the fused kernels (one
+    wavefront per mode, autotuned tiles): 6 and 8 modes of the full physics on
+    a 2048 x 64 grid with dr = 8 dx (what the radial stability bound allows
+    for 8 modes), FP64, ``steps`` timed steps after 3 untimed (and the
+    autotuner's 8 on the fused kernels)."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
@@ -288,10 +291,15 @@ def theta_leg(steps=20):
         wl = I.Workload(f"theta_2048x64x{M}", 2048, 64, M, 0, wp2=5.7407e-5, axion=True, arem=True, ma2=2.325e-4,
                         pulses=(p1, p2), dr=8 * I.H)
         res = {}
-        for name, prod in (("direct", qds.PRODUCTS_DIRECT), ("theta", qds.PRODUCTS_THETA)):
-            s = qds.Solver(wl, dtype="f64", path=qds.PATH_STAGED)
+        for name, prod, path in (("direct", qds.PRODUCTS_DIRECT, qds.PATH_STAGED),
+                                 ("theta", qds.PRODUCTS_THETA, qds.PATH_STAGED),
+                                 ("fused_direct", qds.PRODUCTS_DIRECT, qds.PATH_FUSED)):
+            s = qds.Solver(wl, dtype="f64", path=path)
             s.set_option(qds.OPT_PRODUCTS, prod)
             s.load_pulses()
+            if path == qds.PATH_FUSED:
+                s.set_option(qds.OPT_TUNE, 1)
+                s.step(8)
             s.step(3)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -302,6 +310,7 @@ def theta_leg(steps=20):
             res[name + "_ms_per_step"] = e0.elapsed_time(e1) / steps
             s.close()
         res["theta_over_direct"] = res["theta_ms_per_step"] / res["direct_ms_per_step"]
+        res["fused_direct_over_direct"] = res["fused_direct_ms_per_step"] / res["direct_ms_per_step"]
         out[f"modes_{M}"] = res
     return out
 

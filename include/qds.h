@@ -176,7 +176,7 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
                     int64_t n_steps, void* stream);
 
 /* Options (synchronous, host only):
- *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 4, except the
+ *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 8, except the
  *                 moving window combined with the regenerated set),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)

@@ -690,7 +690,7 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
         case QDS_OPT_PATH:
             if (value < QDS_PATH_AUTO || value > QDS_PATH_FUSED) return fail(h, QDS_EINVAL, "bad path%s");
             if (value == QDS_PATH_FUSED && !fused_ok(h))
-                return fail(h, QDS_EUNSUPPORTED, "fused path needs <= 4 modes and no moving window with the regenerated set%s");
+                return fail(h, QDS_EUNSUPPORTED, "fused path needs <= 8 modes and no moving window with the regenerated set%s");
             h->path = int(value);
             return QDS_OK;
         case QDS_OPT_ROWS:

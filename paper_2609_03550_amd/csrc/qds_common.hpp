@@ -152,6 +152,52 @@ __device__ __forceinline__ void conv_one(const cx<T>* A, const cx<T>* B, int m, 
     out = out + (sign * T(0.5)) * acc;
 }
 
+// The same C_m{A, B} with the factors of every mode held elsewhere (LDS):
+// fa(k), fb(k) return mode k of the two factors.  Each A_k is loaded once and
+// its partners B_{m-k}, B_{k-m}, B_{k+m} as they are needed, so many modes do
+// not keep both arrays in registers.
+template <typename T, int M, typename FA, typename FB>
+__device__ __forceinline__ void conv_stream(FA fa, FB fb, int m, cx<T>& out, T sign) {
+    cx<T> acc = zero<T>();
+    if (m == 0) {
+        acc = fa(0) * fb(0);
+        T re = T(0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const cx<T> a = fa(k), b = fb(k);
+            re += a.re * b.re + a.im * b.im;
+        }
+        acc.re += T(0.5) * re;
+        out = out + sign * acc;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const cx<T> a = fa(k);
+        if (m - k >= 0) acc = acc + a * fb(m - k);
+        if (k - m >= 0) acc = acc + mulc(a, fb(k - m));
+        if (k + m < M) acc = acc + cmul(a, fb(k + m));
+    }
+    out = out + (sign * T(0.5)) * acc;
+}
+
+// out += sign C_m{F_fa, F_fb} for factors read through get(f, k) (factor f of
+// mode k at this lane): register arrays up to four modes, streamed above that.
+template <typename T, int M, typename G>
+__device__ __forceinline__ void conv_pair(G get, int fa, int fb, int m, cx<T>& out, T sign) {
+    if constexpr (M <= 4) {
+        cx<T> A[M], B[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            A[k] = get(fa, k);
+            B[k] = get(fb, k);
+        }
+        conv_one<T, M>(A, B, m, out, sign);
+    } else {
+        conv_stream<T, M>([&](int k) { return get(fa, k); }, [&](int k) { return get(fb, k); }, m, out, sign);
+    }
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): output k >= 1 of the stream seeded
 // with ``seed`` is mix(seed + k * 0x9E3779B97F4A7C15).  Box-Muller normal from
 // outputs 2c+1, 2c+2 of counter c = (step << 32) | (lab column << 12) | row.

@@ -95,7 +95,8 @@ inline qds::Geo geo(const qds_ctx* c) {
     return g;
 }
 
-// The fused kernels cover up to 4 modes.  With the moving window and the
+// The fused kernels cover up to 8 modes (one wavefront per mode; kernel AX up
+// to 4).  With the moving window and the
 // regenerated set, the axion current needs the background set's new state at
 // lab positions while kernel A already writes it shifted, so that combination
 // runs the staged kernels (which shift after the whole step).
@@ -103,7 +104,7 @@ inline bool fused_ok(const qds_ctx* c) {
     const bool window_arem = c->g.x_bc == QDS_X_WINDOW && (c->g.content & QDS_HAS_AREM);
     // the fused kernels address a plane with 32-bit byte offsets
     const bool small_planes = c->plane_elems * c->elem_bytes < (size_t(1) << 32);
-    return c->M <= 4 && !window_arem && small_planes;
+    return c->M <= 8 && !window_arem && small_planes;
 }
 
 inline bool use_fused(const qds_ctx* c) {
@@ -174,7 +175,7 @@ bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0) {
 // the axion current together (QDS_OPT_KERNEL_AX, where the axion march applies).
 template <typename T>
 bool fuse_ax(const qds_ctx* c, const qds::StepPlan<T>& p0) {
-    return c->kernel_ax && march_axion(c, p0);
+    return c->kernel_ax && c->M <= 4 && march_axion(c, p0);
 }
 
 // Fused-kernel arguments of one step from buffer A (old) to buffer B (new).

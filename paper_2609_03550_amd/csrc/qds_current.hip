@@ -72,14 +72,11 @@ __device__ __forceinline__ void current_body(const AxionArgs<T>& a, int strip, i
     __shared__ cx<T> sm[12][M][WAVE];
     auto put = [&](int f, cx<T> v) { sm[f][m][lane] = v; };
     // out += sum over the np factor pairs from pair c0 on of +-C_m (pair sgn_pair negated)
+    auto gsm = [&](int f, int k) { return sm[f][k][lane]; };
     auto convs = [&](int c0, int np, cx<T>& out, int sgn_pair) {
-        cx<T> A[M], B[M];
 #pragma unroll
-        for (int c = 0; c < np; ++c) {
-#pragma unroll
-            for (int k = 0; k < M; ++k) { A[k] = sm[2 * (c0 + c)][k][lane]; B[k] = sm[2 * (c0 + c) + 1][k][lane]; }
-            conv_one<T, M>(A, B, m, out, (c == sgn_pair) ? T(-1) : T(1));
-        }
+        for (int c = 0; c < np; ++c)
+            conv_pair<T, M>(gsm, 2 * (c0 + c), 2 * (c0 + c) + 1, m, out, (c == sgn_pair) ? T(-1) : T(1));
     };
 
     const FacC<T> fc{m, par, tghost<T>(m), dr, inv_dr, a.bx0, a.br1, a.bt1};
@@ -232,7 +229,7 @@ hipError_t batch_current(const AxionArgs<T>* args, const BatchList& L, int M, in
     case MM:                                                                                                \
         hipLaunchKernelGGL((cur::k_batch_current_march<T, MM>), dim3(blocks), dim3(cur::WAVE * MM), 0, s, args, L); \
         break;
-        QDS_BC(1) QDS_BC(2) QDS_BC(3) QDS_BC(4)
+        QDS_BC(1) QDS_BC(2) QDS_BC(3) QDS_BC(4) QDS_BC(5) QDS_BC(6) QDS_BC(7) QDS_BC(8)
 #undef QDS_BC
         default: return hipErrorInvalidValue;
     }

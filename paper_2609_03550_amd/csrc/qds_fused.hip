@@ -632,16 +632,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         }
         __syncthreads();
         if (j < g.nr) {
-            cx<T> A[M], B[M];
-#pragma unroll
-            for (int k = 0; k < M; ++k) { A[k] = get(smS, 0, k); B[k] = get(smS, 1, k); }
-            conv_one<T, M>(A, B, m, Sa, T(1));
-#pragma unroll
-            for (int k = 0; k < M; ++k) { A[k] = get(smS, 2, k); B[k] = get(smS, 3, k); }
-            conv_one<T, M>(A, B, m, Sa, T(1));
-#pragma unroll
-            for (int k = 0; k < M; ++k) { A[k] = get(smS, 4, k); B[k] = get(smS, 5, k); }
-            conv_one<T, M>(A, B, m, Sa, T(1));
+            auto gS = [&](int f, int k) { return get(smS, f, k); };
+            conv_pair<T, M>(gS, 0, 1, m, Sa, T(1));
+            conv_pair<T, M>(gS, 2, 3, m, Sa, T(1));
+            conv_pair<T, M>(gS, 4, 5, m, Sa, T(1));
             if (!c.live) Sa = zero<T>();
             if (!axt) {
                 if (own_row && c.owner) sto(a.sa, eoff<T>(g, m, j, c.i), Sa);
@@ -1060,18 +1054,30 @@ hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, int64_t n, int6
     return hipGetLastError();
 }
 
+// Raises a kernel's dynamic LDS limit once per process (needed above 64 KiB:
+// the exchange buffers of kernel A at 6 or more modes in FP64).
+static hipError_t allow_lds(const void* kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
 template <typename T, bool AXT>
 static hipError_t batch_a_mode(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
     const size_t lds = 2 * size_t(fused::NS) * M * fused::WAVE * sizeof(cx<T>);
     switch (M) {
 #define QDS_BA(MM)                                                                                                      \
     case MM:                                                                                                            \
-        if constexpr (sizeof(T) == 8)                                                                                   \
+        if constexpr (sizeof(T) == 8) {                                                                                 \
+            static const hipError_t attr = allow_lds(reinterpret_cast<const void*>(&fused::k_batch_a_f64<MM, AXT>), lds); \
+            if (attr != hipSuccess) return attr;                                                                        \
             hipLaunchKernelGGL((fused::k_batch_a_f64<MM, AXT>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
-        else                                                                                                            \
+        } else {                                                                                                        \
+            static const hipError_t attr = allow_lds(reinterpret_cast<const void*>(&fused::k_batch_a_f32<MM, AXT>), lds); \
+            if (attr != hipSuccess) return attr;                                                                        \
             hipLaunchKernelGGL((fused::k_batch_a_f32<MM, AXT>), dim3(blocks), dim3(fused::WAVE * MM), lds, s, args, L); \
+        }                                                                                                               \
         break;
-        QDS_BA(1) QDS_BA(2) QDS_BA(3) QDS_BA(4)
+        QDS_BA(1) QDS_BA(2) QDS_BA(3) QDS_BA(4) QDS_BA(5) QDS_BA(6) QDS_BA(7) QDS_BA(8)
 #undef QDS_BA
         default: return hipErrorInvalidValue;
     }

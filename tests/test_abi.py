@@ -77,8 +77,9 @@ def test_layout_queries_on_cpu(lib):
 
 def test_path_selection_at_the_limits(lib):
     """The fused kernels address a plane with 32-bit byte offsets and run up
-    to 4 modes: a plane of exactly 4 GiB, or 5 modes, selects the staged
-    kernels; one row pitch less, or 4 modes, the fused ones.  The largest
+    to 8 modes (every mode count qds_init accepts): a plane of exactly 4 GiB
+    selects the staged kernels, one row pitch less the fused ones, at 1, 4, 5
+    and 8 modes alike.  The largest
     grid qds_init accepts (nx < 2^20, nr < 4096) and the smallest (nx = 8,
     nr = 4) create handles; one beyond either is rejected.  (No device memory
     is needed without the regenerated set.)"""
@@ -92,7 +93,8 @@ def test_path_selection_at_the_limits(lib):
 
     cases = [((65536, 4095, 1), 0),      # 4096 rows x 65536 x 16 B = 2^32 B
              ((65504, 4095, 1), 1),      # one 32-column pitch less
-             ((1000, 50, 5), 0),
+             ((1000, 50, 5), 1),
+             ((1000, 50, 8), 1),
              ((1000, 50, 4), 1),
              ((8, 4, 1), 1)]
     for (nx, nr, m), fused in cases:

@@ -269,8 +269,8 @@ def test_random_full_state(dtype, x_bc, r_bc, arem, M):
     st = Q.step(st, g, ph)
     s = qds.Solver(wl, dtype=dtype)
     s.load_fields(st)
-    # the window with the regenerated set, and more than 4 modes, run staged
-    assert s.fused == ((x_bc != "window" or not arem) and M <= 4)
+    # the window with the regenerated set runs staged
+    assert s.fused == (x_bc != "window" or not arem)
     s.step(4)
     torch.cuda.synchronize()
     ref = Q.run(st, g, ph, 4)
@@ -434,3 +434,32 @@ def test_kernel_ax_equals_split_kernels_and_oracle(dtype, M, x_bc, r_bc, rows):
         P.compare_states(f, ref, tol, floor, set_floor=P.SET_FLOOR, phys=True)
     close = (1e-14, 1e-15) if dtype == "f64" else (2e-6, 1e-7)
     P.compare_states(out[0], out[1], *close)
+
+
+@pytest.mark.parametrize("dtype,M,arem,rows", [("f64", 5, True, 7), ("f64", 6, True, 4), ("f64", 7, True, 9),
+                                              ("f64", 8, True, 5), ("f64", 6, False, 6), ("f32", 6, True, 5),
+                                              ("f32", 8, True, 3)])
+def test_fused_kernels_beyond_four_modes(dtype, M, arem, rows):
+    """5 to 8 modes on the fused kernels (one wavefront per mode, workgroups of
+    up to 512 threads, the mode convolutions reading their factors from LDS as
+    needed; dr = M dx, what the radial stability bound allows): a random full
+    state against the oracle, and against the staged kernels (one thread per
+    point and every mode) to rounding, over 4 steps and several chunks."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = _full(131, 21, M, arem=arem, dr=M * H)
+    st, g, ph = _random_reachable_state(wl, 40 + M)
+    out = {}
+    for path in (qds.PATH_FUSED, qds.PATH_STAGED):
+        s = qds.Solver(wl, dtype=dtype, path=path)
+        s.set_option(qds.OPT_ROWS, rows)
+        s.load_fields(st)
+        assert s.fused == (path == qds.PATH_FUSED)
+        s.step(4)
+        torch.cuda.synchronize()
+        out[path] = s.fields()
+    ref = Q.run(st, g, ph, 4)
+    tol, floor = (1e-12, 1e-14) if dtype == "f64" else (1e-5, 1e-7)
+    P.compare_states(out[qds.PATH_FUSED], ref, tol, floor, set_floor=P.SET_FLOOR, phys=True)
+    close = (1e-13, 1e-15) if dtype == "f64" else (2e-6, 1e-7)
+    P.compare_states(out[qds.PATH_FUSED], out[qds.PATH_STAGED], *close)
