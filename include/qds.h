@@ -176,8 +176,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
                     int64_t n_steps, void* stream);
 
 /* Options (synchronous, host only):
- *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 8, except the
- *                 moving window combined with the regenerated set),
+ *  QDS_OPT_PATH   QDS_PATH_AUTO (fused kernels when modes <= 8, and <= 4
+ *                 for the moving window combined with the regenerated set,
+ *                 which runs kernel AX),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)
  *  QDS_OPT_ROWS_A, QDS_OPT_ROWS_CUR, QDS_OPT_ROWS_B
@@ -206,8 +207,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 no plane); events order it after the axion kernel of step
  *                 k, and every launch is joined back into the caller's
  *                 stream before qds_step returns.  0: one stream.
- *  QDS_OPT_KERNEL_AX 1: with the regenerated set on the fused kernels (no
- *                 moving window), one launch (kernel AX) advances the
+ *  QDS_OPT_KERNEL_AX 1: with the regenerated set on the fused kernels (up
+ *                 to 4 modes; always with the moving window), one launch
+ *                 (kernel AX) advances the
  *                 background set, forms the axion source, advances the axion
  *                 and forms the axion current from one read of the background
  *                 set and the axion (Sec. 2.1, Sec. 2.2 and Eqs. jax_mode,

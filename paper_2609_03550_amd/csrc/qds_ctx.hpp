@@ -96,15 +96,16 @@ inline qds::Geo geo(const qds_ctx* c) {
 }
 
 // The fused kernels cover up to 8 modes (one wavefront per mode; kernel AX up
-// to 4).  With the moving window and the
-// regenerated set, the axion current needs the background set's new state at
-// lab positions while kernel A already writes it shifted, so that combination
-// runs the staged kernels (which shift after the whole step).
+// to 4).  With the moving window and the regenerated set, the axion current
+// needs the background set's new state at the old state's columns while the
+// background march writes it one column left: only kernel AX, which forms the
+// current from the values in its registers, takes that combination (up to 4
+// modes; beyond, the staged kernels, which shift after the whole step).
 inline bool fused_ok(const qds_ctx* c) {
     const bool window_arem = c->g.x_bc == QDS_X_WINDOW && (c->g.content & QDS_HAS_AREM);
     // the fused kernels address a plane with 32-bit byte offsets
     const bool small_planes = c->plane_elems * c->elem_bytes < (size_t(1) << 32);
-    return c->M <= 8 && !window_arem && small_planes;
+    return c->M <= 8 && (!window_arem || c->M <= 4) && small_planes;
 }
 
 inline bool use_fused(const qds_ctx* c) {
@@ -172,10 +173,12 @@ bool march_axion(const qds_ctx* c, const qds::StepPlan<T>& p0) {
 }
 
 // Whether one launch of kernel AX advances the background set, the axion and
-// the axion current together (QDS_OPT_KERNEL_AX, where the axion march applies).
+// the axion current together: with the regenerated set, up to 4 modes, when
+// QDS_OPT_KERNEL_AX asks for it or the moving window needs it.
 template <typename T>
 bool fuse_ax(const qds_ctx* c, const qds::StepPlan<T>& p0) {
-    return c->kernel_ax && c->M <= 4 && march_axion(c, p0);
+    if (!(p0.axion && p0.arem && p0.sa != nullptr) || c->M > 4) return false;
+    return c->kernel_ax || c->g.x_bc == QDS_X_WINDOW;
 }
 
 // Fused-kernel arguments of one step from buffer A (old) to buffer B (new).

@@ -861,16 +861,20 @@ __device__ __forceinline__ void fused_ax_body(const FusedArgs<T>& a, int strip, 
             const cx<T> nam_b = has1 ? rr : zero<T>();
             cx<T> p1 = zero<T>();
             if (c.live) p1 = p + (h / T(4)) * (nap_a + nap_b + nam_a + nam_b);
+            // (with the moving window every new value lands one column left)
+            const int oc = c.o.col(c.i);
             if (own_row && c.owner) {
-                if (has1) sto_ax(a.otap, eoff<T>(g, m, j, c.x.i1), nap_b);
-                sto_ax(a.otam, eoff<T>(g, m, j, c.i), nam_a);
-                sto_ax(a.ophi, eoff<T>(g, m, j, c.i), p1);
-                if (c.i == 0 && !g.per) sto_ax(a.otap, eoff<T>(g, m, j, c.i), zero<T>());
-                if (j == g.nr - 1) {
+                if (has1 && c.o.col(c.x.i1) >= 0) sto_ax(a.otap, eoff<T>(g, m, j, c.o.col(c.x.i1)), nap_b);
+                if (oc >= 0) {
+                    sto_ax(a.otam, eoff<T>(g, m, j, oc), nam_a);
+                    sto_ax(a.ophi, eoff<T>(g, m, j, oc), p1);
+                    if (c.i == 0 && !g.per) sto_ax(a.otap, eoff<T>(g, m, j, oc), zero<T>());
+                }
+                if (j == g.nr - 1 && oc >= 0) {
                     // exterior ghost phi at r_{nr+1/2}: outgoing-wave condition, two-level centring
                     cx<T> Gn = up;
                     if (g.open_r) Gn = c.live ? (p + kap * (up - p1)) : zero<T>();
-                    sto_ax(a.ophi, eoff<T>(g, m, g.nr, c.i), Gn);
+                    sto_ax(a.ophi, eoff<T>(g, m, g.nr, oc), Gn);
                 }
             }
             // ---------------- the current's combinations on K = j
@@ -943,6 +947,17 @@ __device__ __forceinline__ void fused_ax_body(const FusedArgs<T>& a, int strip, 
         }
         kp = kc;
         jp = jc;
+    }
+    // moving window: the owner of the last cell zero-fills the last column of
+    // the new state (j_a stays at the old state's columns, where kernel B reads it)
+    if (a.window && c.owner && c.i == g.nx - 1) {
+        for (int row = r0; row < r1; ++row) {
+            const uint32_t e = eoff<T>(g, m, row, g.nx - 1);
+            sto(s.otrp, e, zero<T>()); sto(s.otrm, e, zero<T>()); sto(s.ottp, e, zero<T>()); sto(s.ottm, e, zero<T>());
+            sto(s.oex, e, zero<T>()); sto(s.obx, e, zero<T>());
+            if (c.plasma) { sto(s.ojx, e, zero<T>()); sto(s.ojr, e, zero<T>()); sto(s.ojt, e, zero<T>()); }
+            sto(a.ophi, e, zero<T>()); sto(a.otap, e, zero<T>()); sto(a.otam, e, zero<T>());
+        }
     }
 }
 

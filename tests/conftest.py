@@ -9,6 +9,12 @@ for _p in (ROOT, os.path.join(ROOT, "tests")):
         sys.path.insert(0, _p)
 
 
+if os.environ.get("PYTEST_XDIST_WORKER"):
+    # several test processes share the host's cores: one intra-op thread each
+    import torch
+    torch.set_num_threads(1)
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
     config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")

@@ -117,15 +117,25 @@ def test_fused_boundaries(x_bc, r_bc):
     _check(_full(128, 12, 3, x_bc=x_bc, r_bc=r_bc), 12, "f64", path=2, rows=5)
 
 
-def test_window_with_regenerated_set_runs_staged():
-    """The moving window with the regenerated set takes the staged kernels
-    (the fused path refuses it) and still matches the oracle."""
+@pytest.mark.parametrize("dtype,M,rows", [("f64", 3, 5), ("f64", 1, 3), ("f32", 3, 4), ("f64", 4, 1)])
+def test_window_with_regenerated_set_runs_kernel_ax(dtype, M, rows):
+    """The moving window with the regenerated set runs kernel AX (the axion
+    current from the background set's old columns, held in registers, while
+    every new value lands one column left): it matches the oracle and the
+    staged kernels (which shift after the whole step) to rounding; beyond 4
+    modes the fused path refuses the combination."""
     from paper_2609_03550_amd import qds
-    wl = _full(128, 12, 3, x_bc="window")
+    wl = _full(128, 12, M, x_bc="window")
+    s = _check(wl, 12, dtype, rows=rows)
+    assert s.fused
+    st = qds.Solver(wl, dtype=dtype, path=qds.PATH_STAGED)
+    st.load_pulses()
+    st.step(12)
+    torch.cuda.synchronize()
+    close = (1e-13, 1e-15) if dtype == "f64" else (2e-6, 1e-7)
+    P.compare_states(s.fields(), st.fields(), *close)
     with pytest.raises(qds.QDSError):
-        qds.Solver(wl, path=2)
-    s = _check(wl, 12, "f64")
-    assert not s.fused
+        qds.Solver(_full(128, 12, 5, x_bc="window", dr=5 * H), path=qds.PATH_FUSED)
 
 
 def test_window_axion_without_regenerated_set_fused():
@@ -269,8 +279,7 @@ def test_random_full_state(dtype, x_bc, r_bc, arem, M):
     st = Q.step(st, g, ph)
     s = qds.Solver(wl, dtype=dtype)
     s.load_fields(st)
-    # the window with the regenerated set runs staged
-    assert s.fused == (x_bc != "window" or not arem)
+    assert s.fused
     s.step(4)
     torch.cuda.synchronize()
     ref = Q.run(st, g, ph, 4)
@@ -349,16 +358,17 @@ def test_random_state_with_drive():
     P.compare_states(s.fields(), ref, 1e-12, 1e-14)
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_random_state_with_drive_and_regenerated_set(dtype):
+@pytest.mark.parametrize("dtype,x_bc", [("f64", "open"), ("f32", "open"), ("f64", "window"), ("f32", "window")])
+def test_random_state_with_drive_and_regenerated_set(dtype, x_bc):
     """The prescribed drive together with the plasma, the axion and the
-    regenerated set (open x, no window): the drive plane feeds kernel A's
-    background set while the marched axion kernel and kernel B run as without
-    a drive; a random full state, 4 steps, against the oracle."""
+    regenerated set: the drive plane feeds the background set while the axion
+    and kernel B run as without a drive (open x: kernel A and the marched
+    axion kernel; the moving window: kernel AX); a random full state, 4
+    steps, against the oracle."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
     d = I.Drive(amp=50.0, x0=60 * H, v=0.999, sx=10 * H, r0=0.0, sr=4 * DR, noise=1e-3, seed=3)
-    wl = _full(131, 21, 3).with_(drive=d)
+    wl = _full(131, 21, 3, x_bc=x_bc).with_(drive=d)
     g, ph = Q.grid_physics(wl)
     st = Q.init_state(wl)
     gen = torch.Generator().manual_seed(11)
