@@ -358,24 +358,52 @@ def stream_reference(nbytes=1 << 31, reps=10):
             "lib_streaming_copy_read_write_gbps": 2 * nbytes / t_nt / 1e9, "bytes": nbytes}
 
 
-def cpu_baseline(wl, seconds_target=15.0):
-    """The FP64 oracle on this host: whole-grid steps of the same workload
-    until about ``seconds_target`` of CPU work, extrapolated per update."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, seconds_target=10.0, one_thread_seconds=6.0):
+    """The FP64 oracle on this host, as it stands: whole-grid steps of the same
+    workload with torch's default intra-op threads until about
+    ``seconds_target`` of work (the reported value), then steps of a
+    1024-column x-crop of it on one thread (the one-core rate, per update, and
+    the linear-scaling ceiling it implies over the cores this process may use)."""
     import torch
     from oracle import qds as Q
-    g, ph = Q.grid_physics(wl)
-    st = Q.init_state(wl)
-    st = Q.step(st, g, ph)                  # first step outside the timing
-    n, t0 = 0, time.perf_counter()
-    while True:
-        st = Q.step(st, g, ph)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > seconds_target or n >= 20:
-            break
-    return {"value": wl.cell_modes * n / el, "unit": "cell-mode updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} whole-grid steps of {wl.name} (FP64 oracle, after 1 untimed step), {el:.1f} s"}
+
+    def rate(w, target, max_steps):
+        g, ph = Q.grid_physics(w)
+        st = Q.init_state(w)
+        st = Q.step(st, g, ph)                  # first step outside the timing
+        n, t0 = 0, time.perf_counter()
+        while True:
+            st = Q.step(st, g, ph)
+            n += 1
+            el = time.perf_counter() - t0
+            if el > target or n >= max_steps:
+                return w.cell_modes * n / el, n, el
+
+    threads = torch.get_num_threads()
+    v, n, el = rate(wl, seconds_target, 20)
+    crop = wl.with_(nx=min(wl.nx, 1024))
+    torch.set_num_threads(1)
+    try:
+        v1, n1, el1 = rate(crop, one_thread_seconds, 20)
+    finally:
+        torch.set_num_threads(threads)
+    cores = len(os.sched_getaffinity(0))
+    return {"value": v, "unit": "cell-mode updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} whole-grid steps of {wl.name} (FP64 oracle, {threads} intra-op threads, after 1 "
+                      f"untimed step), {el:.1f} s; one thread: {n1} steps of a {crop.nx}-column x-crop, {el1:.1f} s",
+            "cpu_model": _cpu_model(), "affinity_cores": cores, "one_thread_value": v1,
+            "linear_scaling_ceiling": v1 * cores}
 
 
 def main():
