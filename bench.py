@@ -315,6 +315,60 @@ def theta_leg(steps=20):
     return out
 
 
+def pic_leg(steps, ppc=2, dtype="f64"):
+    """The coupled PIC loop (Sec. 3.1) in place of the prescribed ring drive:
+    the laser of the moving-window workload (4096 x 256 x 3 modes, a0 = 2,
+    w0 = 10 lambda, 30 fs) in a cold electron slab of n_e = 1e17 cm^-3 over
+    the middle half of the grid and r < 240 dr, ``ppc`` macro-electrons per
+    (x, r) cell placed at seeded random positions (uniform in x, in r^2 and in
+    theta), on a fixed grid (particles take no moving window).  Each step is
+    qds_particles_step (gather, Boris, modal charge-conserving deposit) then
+    qds_step with the deposit (fused kernels).  ``steps`` timed coupled steps
+    after 3 untimed, then the same number of particle steps alone."""
+    import numpy as np
+    import torch
+    from paper_2609_03550_amd import inputs as I
+    from paper_2609_03550_amd import qds
+    base = I.driven_window(4096, 256, 4000)
+    wl = base.with_(name="pic_4096x256x3", x_bc="open", drive=None)
+    s = qds.Solver(wl, dtype=dtype)
+    s.load_pulses()
+    rng = np.random.default_rng(17)
+    nx, nr = wl.nx, wl.nr
+    x_lo, x_hi, r_max = 0.25 * nx * wl.h, 0.75 * nx * wl.h, 240 * wl.dr
+    n = int(ppc * (0.5 * nx) * 240)
+    x = rng.uniform(x_lo, x_hi, n)
+    r = r_max * np.sqrt(rng.uniform(0, 1, n))
+    th = rng.uniform(-np.pi, np.pi, n)
+    pos = torch.from_numpy(np.stack([x, r * np.cos(th), r * np.sin(th)])).to(s.device).contiguous()
+    u = torch.zeros_like(pos)
+    ne = 1e17 / I.NC_CM3                       # density in units of the critical density
+    charge = -ne * (x_hi - x_lo) * np.pi * r_max ** 2 / n
+    cpl = None
+    cpl, _ = s.pic_steps(pos, u, -1.0, charge, 3, cpl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    cpl, sk = s.pic_steps(pos, u, -1.0, charge, steps, cpl)
+    e1.record()
+    torch.cuda.synchronize()
+    t_all = e0.elapsed_time(e1) / steps
+    skipped = sum(int(k.item()) for k in sk)
+    planes = s.current_planes()
+    e0.record()
+    for _ in range(steps):
+        s.particles_step(pos, u, -1.0, charge, planes=planes, extrapolate=True, clear=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_part = e0.elapsed_time(e1) / steps
+    fused = s.fused
+    s.close()
+    return {"workload": wl.name, "dtype": dtype, "particles": n, "steps": steps, "path": "fused" if fused else "staged",
+            "coupled_ms_per_step": t_all, "particle_ms_per_step": t_part, "field_ms_per_step": t_all - t_part,
+            "particle_pushes_per_s": n / (t_part / 1e3), "field_cell_mode_updates_per_s": wl.cell_modes / ((t_all - t_part) / 1e3),
+            "skipped_particles": skipped}
+
+
 def stream_reference(nbytes=1 << 31, reps=10):
     """Bandwidth of plain device copies (read + write) and a fill (write only)
     in the same process: torch's copy and fill, and the library's 16-byte-per-
@@ -437,6 +491,8 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=100,
                     help="steps of the comparison of kernel AX with the split kernels, with and without "
                          "the overlap (0 skips it)")
+    ap.add_argument("--pic-steps", type=int, default=10,
+                    help="steps of the coupled particle-in-cell leg (0 skips it)")
     ap.add_argument("--stream-reference", type=int, default=1,
                     help="1 times plain device copies for the copy-relative roofline fractions (0 skips them)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -579,6 +635,9 @@ def main():
         torch.cuda.empty_cache()
     if args.theta_steps > 0:
         out["theta_grid_products"] = theta_leg(args.theta_steps)
+        torch.cuda.empty_cache()
+    if args.pic_steps > 0:
+        out["pic"] = pic_leg(args.pic_steps)
         torch.cuda.empty_cache()
     if args.stream_reference:
         out["stream_reference"] = stream_reference()

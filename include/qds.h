@@ -100,7 +100,9 @@ typedef struct {
      * step ending at t^{n-1/2} (may be NULL: taken as zero) and pjx_next that
      * of the step ending at t^{n+1/2}; j_r and j_theta of the latter (pjr,
      * pjt, on integer columns) are averaged along x onto the source points
-     * x_{i+1/2} (Sec. 3.1, last paragraph).  Runs the staged kernels. */
+     * x_{i+1/2} (Sec. 3.1, last paragraph).  On the fused kernels the library
+ * forms these sums once per call into three planes of its own (allocated on
+ * first use), which the background march reads as its extra currents. */
     const void* pjx_prev;
     const void* pjx_next;
     const void* pjr;

@@ -39,7 +39,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     key[6] = double(p0.bx0.re); key[7] = double(p0.bx0.im); key[8] = double(p0.br1.re); key[9] = double(p0.br1.im);
     key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im);
     key[12] = double(c->trows[0]); key[13] = double(c->trows[1]); key[14] = double(c->trows[2]);
-    key[15] = double(p0.drive.on);
+    key[15] = double(p0.drive.on) + (p0.psrc[0] ? 2.0 : 0.0);
     if (!c->ktab_dev) {
         c->ktab_bytes = sizeof(KTab<double>);
         if (hipMalloc(&c->ktab_dev, c->ktab_bytes) != hipSuccess) {
@@ -228,6 +228,20 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
         }
     }
     p0.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
+    if (p0.pj[1]) {
+        // particle deposits: the background march reads them at the source
+        // points, formed once per call (they hold for every step of it)
+        const size_t pb = c->plane_elems * c->elem_bytes;
+        if (!c->psrc && hipMalloc(&c->psrc, 3 * pb) != hipSuccess) {
+            c->psrc = nullptr;
+            return fail(c, QDS_ENOMEM, "hipMalloc of the particle source planes failed%s");
+        }
+        for (int k = 0; k < 3; ++k)
+            p0.psrc[k] = reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->psrc) + size_t(k) * pb);
+        const hipError_t e = qds::particle_sources<T>(p0.pj[0], p0.pj[1], p0.pj[2], p0.pj[3], p0.g, p0.psrc[0],
+                                                      c->plane_elems, s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    }
     if (c->tune && n_steps >= kTrials) {
         // autotuner: timed ordinary steps, two passes over four tile heights per
         // kernel (candidates around each kernel's measured optimum)
@@ -277,7 +291,7 @@ qds_status run_steps(qds_ctx* c, qds_state* st, const qds_current* J, const qds_
                      hipStream_t s) {
     qds::StepPlan<T> p = make_plan<T>(c, J, ax);
     // particle currents run on the staged kernels
-    if (use_fused(c) && !(J && J->kind == QDS_J_PARTICLES)) return fused_steps<T>(c, st, p, n_steps, s);
+    if (use_fused(c)) return fused_steps<T>(c, st, p, n_steps, s);
     const bool window = c->g.x_bc == QDS_X_WINDOW;
     for (int64_t it = 0; it < n_steps; ++it) {
         int a = st->cur, b = 1 - st->cur;
@@ -838,6 +852,7 @@ qds_status qds_destroy(qds_handle h) {
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->drive_plane) (void)hipFree(h->drive_plane);
+    if (h->psrc) (void)hipFree(h->psrc);
     if (h->ktab_ev) {
         (void)hipEventSynchronize(h->ktab_ev);
         (void)hipEventDestroy(h->ktab_ev);

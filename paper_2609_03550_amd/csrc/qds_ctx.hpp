@@ -19,6 +19,7 @@ struct qds_ctx {
     int nplanes;
     void* scratch;           // axion-current planes (3) and S_a, library owned
     void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0 (allocated on first use)
+    void* psrc;              // particle currents at the source points, 3 planes (allocated on first use)
     int path;                // QDS_PATH_*
     int theta;               // QDS_PRODUCTS_THETA: theta-grid products (staged path)
     int rows;                // the last QDS_OPT_ROWS value (also copied into trows)
@@ -161,6 +162,7 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
     p.pj[1] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_next)) : nullptr;
     p.pj[2] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjr)) : nullptr;
     p.pj[3] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjt)) : nullptr;
+    p.psrc[0] = p.psrc[1] = p.psrc[2] = nullptr;   // set where the fused kernels take them
     return p;
 }
 
@@ -205,6 +207,13 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     if (p0.drive.on) {
         a.s0.jxa = p0.jdrv;
         a.s0.jxa_m0 = 1;
+    }
+    if (p0.psrc[0]) {
+        // particle currents at the source points, every mode
+        a.s0.jxa = p0.psrc[0];
+        a.s0.jra = p0.psrc[1];
+        a.s0.jta = p0.psrc[2];
+        a.s0.jxa_m0 = 0;
     }
     a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
     a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];

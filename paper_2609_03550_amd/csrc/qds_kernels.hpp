@@ -103,6 +103,7 @@ struct StepPlan {
     cx<T> bx0, br1, bt1;
     Drive drive;
     const cx<T>* pj[4];         // particle currents of set 0 (StageArgs::pjx0 ..), or null
+    cx<T>* psrc[3];             // the same at the source points (fused kernels), or null
     int64_t n, w;
 
     SetPtr<T> set(cx<T>* const* P, int s) const {
@@ -207,6 +208,14 @@ __device__ __forceinline__ int batch_find(const BatchList& L, int b) {
 }
 
 template <typename T> hipError_t staged_step(const StepPlan<T>& p, hipStream_t s);
+// Particle deposits (Sec. 3.1) brought to the source points where the
+// background set takes its currents: j_x^n = (j_x^{n-1/2} + j_x^{n+1/2})/2 at
+// x_{i+1/2} (pjx0 may be null), and j_r, j_theta of the step ending at
+// t^{n+1/2} averaged from x_i, x_{i+1} to x_{i+1/2}; written to the three
+// planes of out (the layout of a state plane).
+template <typename T>
+hipError_t particle_sources(const cx<T>* pjx0, const cx<T>* pjx1, const cx<T>* pjr, const cx<T>* pjt, const Geo& g,
+                            cx<T>* out, size_t plane_elems, hipStream_t s);
 // The prescribed drive's j_x^(0) of step n (window offset w) into the mode-0
 // rows of out (one plane of row pitch g.ld), read by the background set of the
 // fused kernels as its extra j_x.

@@ -502,6 +502,41 @@ __global__ void __launch_bounds__(256) k_axion_current(AxionArgs<T> a) {
 
 
 // ---------------------------------------------------------------------------
+// particle currents at the source points (read by the fused background march
+// as its extra currents; the staged stages form the same sums in place)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_particle_sources(const cx<T>* __restrict__ pjx0, const cx<T>* __restrict__ pjx1,
+                                                          const cx<T>* __restrict__ pjr, const cx<T>* __restrict__ pjt,
+                                                          Geo g, cx<T>* __restrict__ out, size_t plane) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;                // 0..nr
+    const int m = blockIdx.z;
+    if (i >= g.nx) return;
+    const size_t e = g.at(m, row, i);
+    cx<T> jx = zero<T>();
+    if (pjx0) jx = jx + T(0.5) * ld(pjx0 + e);
+    jx = jx + T(0.5) * ld(pjx1 + e);
+    const cx<T> jr = row < g.nr ? T(0.5) * (ldx(pjr, g, m, row, i) + ldx(pjr, g, m, row, i + 1)) : zero<T>();
+    const cx<T> jt = T(0.5) * (ldx(pjt, g, m, row, i) + ldx(pjt, g, m, row, i + 1));
+    st(out + e, jx);
+    st(out + plane + e, jr);
+    st(out + 2 * plane + e, jt);
+}
+
+template <typename T>
+hipError_t particle_sources(const cx<T>* pjx0, const cx<T>* pjx1, const cx<T>* pjr, const cx<T>* pjt, const Geo& g,
+                            cx<T>* out, size_t plane_elems, hipStream_t s) {
+    hipLaunchKernelGGL((k_particle_sources<T>), dim3((g.nx + 255) / 256, g.nr + 1, g.M), dim3(256), 0, s, pjx0, pjx1,
+                       pjr, pjt, g, out, plane_elems);
+    return hipGetLastError();
+}
+template hipError_t particle_sources<double>(const cx<double>*, const cx<double>*, const cx<double>*, const cx<double>*,
+                                             const Geo&, cx<double>*, size_t, hipStream_t);
+template hipError_t particle_sources<float>(const cx<float>*, const cx<float>*, const cx<float>*, const cx<float>*,
+                                            const Geo&, cx<float>*, size_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // moving window: copy every plane shifted left by one column, zero the last
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -113,19 +113,22 @@ def test_particles_outside_the_grid_are_skipped_and_counted():
     assert not np.array_equal(P.cpu().numpy()[:, 8:], pos[:, 8:])
 
 
-@pytest.mark.parametrize("M,dtype", [(2, "f64"), (3, "f64"), (3, "f32")])
-def test_coupled_pic_steps_match_the_oracle(M, dtype):
+@pytest.mark.parametrize("M,dtype,path", [(2, "f64", 0), (3, "f64", 0), (3, "f32", 0), (3, "f64", 1), (2, "f32", 1)])
+def test_coupled_pic_steps_match_the_oracle(M, dtype, path):
     """Eight coupled steps (particle step in the fields, then the field step
-    with the deposited current, QDS_J_PARTICLES on the staged kernels) of a
-    laser pulse and 300 electrons near it: fields and particles against the
-    oracle's coupled loop."""
+    with the deposited current, QDS_J_PARTICLES) of a laser pulse and 300
+    electrons near it, on the fused kernels (path 0: the deposits brought to
+    the source points once per step, two strips, chunks of 5 rows) and on the
+    staged ones (path 1): fields and particles against the oracle's coupled
+    loop."""
     from oracle import qds as Q
     from paper_2609_03550_amd import qds
     import parity_tools as PT
     nx, nr = 96, 12
     p = I.Pulse("y", 0.3, 1.0, 3 * I.LAMBDA, 12 * H, 0.55 * nx * H)
     wl = I.Workload("pic_coupled", nx, nr, M, 0, pulses=(p,))
-    s = qds.Solver(wl, dtype=dtype)
+    s = qds.Solver(wl, dtype=dtype, path=path, rows=5 if path == 0 else None)
+    assert s.fused == (path == 0)
     s.load_pulses()
     rng = np.random.default_rng(31)
     n = 300
