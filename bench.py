@@ -315,7 +315,7 @@ def theta_leg(steps=20):
     return out
 
 
-def pic_leg(steps, ppc=2, dtype="f64"):
+def pic_leg(steps, ppc=2, dtype="f64", sort=True):
     """The coupled PIC loop (Sec. 3.1) in place of the prescribed ring drive:
     the laser of the moving-window workload (4096 x 256 x 3 modes, a0 = 2,
     w0 = 10 lambda, 30 fs) in a cold electron slab of n_e = 1e17 cm^-3 over
@@ -341,6 +341,10 @@ def pic_leg(steps, ppc=2, dtype="f64"):
     r = r_max * np.sqrt(rng.uniform(0, 1, n))
     th = rng.uniform(-np.pi, np.pi, n)
     pos = torch.from_numpy(np.stack([x, r * np.cos(th), r * np.sin(th)])).to(s.device).contiguous()
+    if sort:
+        # by (x, r) cell, as PIC codes keep their particles
+        key = torch.floor(pos[0] / wl.h) * (nr + 1) + torch.floor(torch.sqrt(pos[1] ** 2 + pos[2] ** 2) / wl.dr)
+        pos = pos[:, torch.argsort(key)].contiguous()
     u = torch.zeros_like(pos)
     ne = 1e17 / I.NC_CM3                       # density in units of the critical density
     charge = -ne * (x_hi - x_lo) * np.pi * r_max ** 2 / n
@@ -363,7 +367,8 @@ def pic_leg(steps, ppc=2, dtype="f64"):
     t_part = e0.elapsed_time(e1) / steps
     fused = s.fused
     s.close()
-    return {"workload": wl.name, "dtype": dtype, "particles": n, "steps": steps, "path": "fused" if fused else "staged",
+    return {"workload": wl.name, "dtype": dtype, "particles": n, "sorted_by_cell": sort, "steps": steps,
+            "path": "fused" if fused else "staged",
             "coupled_ms_per_step": t_all, "particle_ms_per_step": t_part, "field_ms_per_step": t_all - t_part,
             "particle_pushes_per_s": n / (t_part / 1e3), "field_cell_mode_updates_per_s": wl.cell_modes / ((t_all - t_part) / 1e3),
             "skipped_particles": skipped}
