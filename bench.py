@@ -149,11 +149,12 @@ def batched_leg(step_scale, graph_steps, count=64):
     count (500..3000) times ``step_scale``, so that instances finish at
     different steps and the set of running instances changes along the run:
     the batch (one launch per kernel class per step over every running
-    instance, ``graph_steps`` steps per HIP graph, tiles from the batch's
-    autotuner) against the same schedule launched without graphs and against
-    each instance advanced alone with qds_step (each with the tiles its own
-    autotuner chose).  Graphs are captured on an untimed first pass of the
-    schedule and replayed on the timed one."""
+    instance, tiles from the batch's autotuner) with the whole uneven schedule
+    captured as one HIP graph and launched once (``graph_steps`` -1; otherwise
+    that many steps per graph), against the same schedule launched without
+    graphs and against each instance advanced alone with qds_step (each with
+    the tiles its own autotuner chose).  The graph is captured on an untimed
+    first pass of the schedule and replayed on the timed one."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
@@ -483,7 +484,8 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=0.04,
                     help="factor on the 64 instances' seeded step counts (500..3000) for the batched "
                          "comparison (0 skips it)")
-    ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--graph-steps", type=int, default=-1,
+                    help="steps per HIP graph of the batched leg (-1: the whole uneven schedule as one graph)")
     ap.add_argument("--theta-steps", type=int, default=20,
                     help="steps of the theta-grid vs direct product comparison at 6 and 8 modes (0 skips it)")
     ap.add_argument("--f32-steps", type=int, default=100,

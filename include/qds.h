@@ -385,12 +385,19 @@ qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch*
  * QDS_J_NONE, is accepted); axion[count]: per-instance axion parameters (may
  * be NULL when no instance has the axion).  graph_steps >= 1 captures up to
  * that many steps per HIP graph (graphs are kept for replay while the set of
- * running instances is unchanged); 0 launches the kernels directly.  With
+ * running instances is unchanged); 0 launches the kernels directly; -1
+ * captures the whole uneven schedule of the call (every instance's steps,
+ * the running set shrinking as instances finish) as one HIP graph and
+ * launches it once (kept for replay while the tables, the tiles and the step
+ * counts are the same).  With
  * tune != 0 and no tiles chosen yet, the autotuner times the first steps of
  * the run (two passes over the candidate tilings, 8 steps; only when every
  * running instance has that many steps left): each trial is an ordinary step
  * of the run, and the tiling does not change any result.  Asynchronous on
- * ``stream``; graphs of the previous call are released after waiting for it. */
+ * ``stream``.  Graphs stay with the batch across calls and are replayed
+ * whenever a call repeats a running set (or, with -1, a whole schedule) with
+ * the same tiles: the argument table they read is rewritten in place, after
+ * the previous call has finished, when the states or the physics change. */
 qds_status qds_batch_run(qds_batch b, qds_state* states, const qds_current* J, const qds_axion* axion,
                          const int64_t* n_steps, int32_t graph_steps, int32_t tune, void* stream);
 
@@ -401,9 +408,9 @@ qds_status qds_batch_get_tiles(qds_batch b, int32_t* tiles, int32_t* tuned);
 qds_status qds_batch_set_tiles(qds_batch b, const int32_t* tiles);
 
 /* Launch counters since the batch was created (int64[4]): graph launches,
- * graphs instantiated, kernel launches issued outside graphs (graph_steps 0
- * and the autotuner's trial steps are not counted), and kernel launches
- * carried by the launched graphs. */
+ * graphs instantiated, kernel launches issued outside graphs (graph_steps 0;
+ * the autotuner's trial steps are not counted), and kernel launches carried
+ * by the launched graphs. */
 qds_status qds_batch_stats(qds_batch b, int64_t* stats);
 
 const char* qds_batch_last_error(qds_batch b);

@@ -53,6 +53,9 @@ struct qds_batch_ctx {
     size_t args_cap = 0;
     std::vector<unsigned char> host_args;
     std::vector<Plan*> plans;           // plans and graphs, kept while the tables are unchanged
+    // graphs of whole uneven schedules (graph_steps < 0), keyed by the parity
+    // of the first step, the tiles and every instance's remaining steps
+    std::map<std::vector<int64_t>, std::pair<hipGraph_t, hipGraphExec_t>> whole;
     hipEvent_t done = nullptr;
     bool pending = false;
     // counters since creation: graph launches, graphs instantiated, kernel
@@ -82,6 +85,11 @@ void release(qds_batch_ctx* b) {
         delete p;
     }
     b->plans.clear();
+    for (auto& kv : b->whole) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    b->whole.clear();
 }
 
 int chunks(int nr, int rows) { return (nr + 1 + rows - 1) / rows; }
@@ -221,7 +229,16 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
     }
     hipError_t e;
     if (!(b->args && host == b->host_args)) {
-        release(b);
+        // the captured graphs and the launch lists hold only the table's device
+        // address, so new contents (states whose current buffer flipped, other
+        // physics) are uploaded in place once the previous run has finished;
+        // only a larger table, which moves, releases them
+        if (bytes > b->args_cap) {
+            release(b);
+        } else if (b->pending) {
+            (void)hipEventSynchronize(b->done);
+            b->pending = false;
+        }
         b->host_args.swap(host);
         if (bytes > b->args_cap) {
             if (b->args) (void)hipFree(b->args);
@@ -310,8 +327,63 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
         }
     }
+    if (graph_steps < 0) {
+        // the whole uneven schedule from step t as one graph: the plan of every
+        // segment (running set unchanged) first, its lists uploaded on s, then
+        // one capture of all the steps, replayed while the tables, the tiles and
+        // the step counts are the same
+        std::vector<int64_t> key;
+        key.push_back(t & 1);
+        key.insert(key.end(), b->tiles, b->tiles + QDS_NTILES);
+        for (size_t k = 0; k < N; ++k) key.push_back(std::max<int64_t>(n_steps[k] - t, 0));
+        std::vector<std::pair<Plan*, int64_t>> segs;
+        int64_t launches = 0;
+        for (int64_t tt = t;;) {
+            std::vector<int> act = running(tt);
+            if (act.empty()) break;
+            int64_t rem = INT64_MAX;
+            for (int k : act) rem = std::min(rem, n_steps[k] - tt);
+            Plan* P = find_plan(act);
+            if (!P && (st = build_plan(b, act, s, &P)) != QDS_OK) return st;
+            segs.emplace_back(P, rem);
+            launches += rem * int64_t(P->launches.size());
+            tt += rem;
+        }
+        if (!segs.empty()) {
+            auto it = b->whole.find(key);
+            if (it == b->whole.end()) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t x = nullptr;
+                e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+                if (e != hipSuccess) return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(e));
+                hipError_t le = hipSuccess;
+                int64_t tt = t;
+                for (const auto& sg : segs) {
+                    for (int64_t u = 0; u < sg.second && le == hipSuccess; ++u)
+                        le = launch_step<T>(b, *sg.first, int((tt + u) & 1), b->cap, nullptr);
+                    tt += sg.second;
+                }
+                e = hipStreamEndCapture(b->cap, &g);
+                if (le != hipSuccess || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(le != hipSuccess ? le : e));
+                }
+                e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    return bfail(b, QDS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+                }
+                it = b->whole.emplace(key, std::make_pair(g, x)).first;
+                b->stats[1] += 1;
+            }
+            e = hipGraphLaunch(it->second.second, s);
+            if (e != hipSuccess) return bfail(b, QDS_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+            b->stats[0] += 1;
+            b->stats[3] += launches;
+        }
+    }
     // the run proper, in segments over which the running set is unchanged
-    for (;;) {
+    for (; graph_steps >= 0;) {
         std::vector<int> act = running(t);
         if (act.empty()) break;
         int64_t rem = INT64_MAX;
@@ -409,7 +481,7 @@ qds_status qds_batch_run(qds_batch b, qds_state* states, const qds_current* J, c
                          const int64_t* n_steps, int32_t graph_steps, int32_t tune, void* stream) {
     if (!b) return bfail(nullptr, QDS_EINVAL, "null batch%s");
     if (!states || !n_steps) return bfail(b, QDS_EINVAL, "null states or step counts%s");
-    if (graph_steps < 0 || graph_steps > 100000) return bfail(b, QDS_EINVAL, "graph_steps must be 0..100000%s");
+    if (graph_steps < -1 || graph_steps > 100000) return bfail(b, QDS_EINVAL, "graph_steps must be -1..100000%s");
     for (size_t k = 0; k < b->inst.size(); ++k) {
         qds_ctx* c = b->inst[k];
         if (check_state(c, &states[k]) != QDS_OK) return bfail(b, QDS_ESTATE, "instance state: %s", c->err);

@@ -511,7 +511,7 @@ TILE_A1, TILE_CUR1, TILE_EM0, TILE_EM1 = 0, 4, 8, 9
 class Batch:
     """Many independent solvers advanced together by qds_batch_run: one launch
     per kernel class per step over all running instances, ``graph_steps``
-    steps per captured HIP graph."""
+    steps per captured HIP graph (-1: the whole uneven schedule as one graph)."""
 
     def __init__(self, solvers):
         self.solvers = list(solvers)

@@ -84,17 +84,30 @@ def test_mixed_content_batch_equals_one_at_a_time():
             P.compare_states(s.fields(), P.oracle_run(s.wl, n), *TOL["f64"])
 
 
-@pytest.mark.parametrize("graph_steps", [0, 1, 5])
+@pytest.mark.parametrize("graph_steps", [0, 1, 5, -1])
 def test_graph_length_does_not_change_results(graph_steps):
+    """Graphs of 1 or 5 steps, direct launches, and the whole uneven schedule
+    (instances of 9, 0, 4, 13, 6 steps) as one graph give bit-identical states;
+    the whole-schedule graph is one launch per run, captured once and replayed
+    on an equal second run."""
     from paper_2609_03550_amd import qds
     wls = _small(5, 12)
     steps = [9, 0, 4, 13, 6]
     ref = _solvers(wls, "f64")
     bs = _twins(ref)
     qds.Batch(ref).run(steps, graph_steps=16)
-    qds.Batch(bs).run(steps, graph_steps=graph_steps)
+    b = qds.Batch(bs)
+    b.run(steps, graph_steps=graph_steps)
     _identical(bs, ref)
     assert bs[1].n == 0
+    if graph_steps == -1:
+        s0 = b.stats()
+        assert s0[0] == 1 and s0[1] == 1 and s0[2] == 0
+        qds.Batch(ref).run(steps, graph_steps=16)
+        b.run(steps, graph_steps=-1)
+        _identical(bs, ref)
+        s1 = b.stats()
+        assert s1[0] == 2 and s1[1] == 1 and s1[3] == 2 * s0[3]
 
 
 @pytest.mark.parametrize("rows", [1, 3, 32])
