@@ -271,3 +271,26 @@ def test_adjoint_from_random_full_state():
     go = {k: (v.grad if v.grad is not None else torch.zeros_like(v)) for k, v in leaves.items()}
     assert L > 0 and abs(L / float(Lo.detach()) - 1) < 1e-11
     _compare_grad(lam, go, 1e-9)
+
+
+def test_adjoint_recomputes_through_kernel_ax():
+    """The backward's recomputation of each segment runs through the same
+    launch sequence as qds_step: with QDS_OPT_KERNEL_AX the forward segments
+    run kernel AX, and the loss, the scale sensitivities and lambda^0 agree
+    with the split kernels' to rounding, and with autograd through the oracle."""
+    from paper_2609_03550_amd import qds
+    wl = _full(190, 16, 3)
+    out = []
+    for kax in (0, 1):
+        s = qds.Solver(wl, dtype="f64")
+        s.set_option(qds.OPT_KERNEL_AX, kax)
+        s.load_pulses()
+        L, lam, dlds = s.backward(24, 5, 1, 1)
+        out.append((L, s.buffer_fields(lam), dlds))
+    assert abs(out[1][0] / out[0][0] - 1) < 1e-13
+    for q in range(2):
+        assert abs(out[1][2][q] / out[0][2][q] - 1) < 1e-12
+    P.compare_states(out[1][1], out[0][1], 1e-12, 1e-9)
+    Lo, go = _oracle_grad(wl, 24, 1, 1)
+    assert abs(out[1][0] / Lo - 1) < 1e-11
+    _compare_grad(out[1][1], go, 1e-9)

@@ -44,12 +44,23 @@ def _oracle_marks(wl, dtype=None):
     return out
 
 
-def test_single_precision_over_2000_steps():
+@pytest.fixture(scope="module")
+def oracle_marks():
+    """The plain and the storage-rounded oracle runs, shared by both kernel
+    arrangements."""
+    wl = _wl()
+    return _oracle_marks(wl), _oracle_marks(wl, "f32")
+
+
+@pytest.mark.parametrize("kernel_ax", [0, 1])
+def test_single_precision_over_2000_steps(oracle_marks, kernel_ax):
+    """The split kernels (kernel A, the axion kernel, kernel B) and kernel AX
+    (the background set, the axion and its current in one march) alike."""
     from paper_2609_03550_amd import qds
     wl = _wl()
-    ref = _oracle_marks(wl)
-    emu = _oracle_marks(wl, "f32")
+    ref, emu = oracle_marks
     s = qds.Solver(wl, dtype="f32")
+    s.set_option(qds.OPT_KERNEL_AX, kernel_ax)
     s.load_pulses()
     done = 0
     for n in MARKS:
