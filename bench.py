@@ -40,8 +40,15 @@ def plane_accesses(wl, kernel, split=True):
     the axion once and writes j_a (27 planes), and kernel 2 does not run.
     Electromagnetic-only: kernel 0 reads and writes the 6 (or 9) planes, and
     with a prescribed drive reads its j_x^(0) plane for mode 0 (1/M of a plane
-    per cell-mode; the drive kernel that writes it is not counted)."""
+    per cell-mode; the drive kernel that writes it is not counted).
+    Kernel 3 is the two-step march, per launch (two steps): the regenerated
+    set (or the set of an electromagnetic-only run) read and written once and,
+    with the regenerated set, the axion current of both steps read."""
     em = 6 + (3 if wl.wp2 else 0)
+    if kernel == 3:
+        # the two-step march (one launch per two steps): the set read and
+        # written once, the axion current of both steps read
+        return 2 * em + (6 if wl.arem else 0)
     if not wl.axion:
         if kernel != 0:
             return 0
@@ -59,6 +66,20 @@ def plane_accesses(wl, kernel, split=True):
 KERNEL_NAMES = {0: "kernel A (background set, axion source)", 1: "kernel B (regenerated set)",
                 2: "axion kernel (axion advance, axion current)"}
 KERNEL_NAME_AX = "kernel AX (background set, axion source, axion advance, axion current)"
+KERNEL_NAME_PAIR = {True: "two-step march of the regenerated set (two steps per launch)",
+                    False: "two-step march of the electromagnetic set (two steps per launch)"}
+# untimed steps of the library's autotuner: 8 trials, each a pair of steps
+# where steps run in pairs
+TUNE_STEPS = 16
+
+
+def pairs_active(wl, fused, pair=1, kernel_ax=0, overlap=0):
+    """Whether qds_step runs this workload in pairs of steps (QDS_OPT_PAIR):
+    the fused kernels without the moving window or a drive, with the
+    regenerated set on the split kernels, or without the axion."""
+    if not (pair and fused) or wl.x_bc == "window" or wl.drive is not None or overlap:
+        return False
+    return (wl.arem and not kernel_ax) or not wl.axion
 
 
 def workload(name):
@@ -72,7 +93,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current"}
+KERNEL_KEYS = {0: "kernel_a", 1: "kernel_b", 2: "axion_current", 3: "kernel_b2"}
 
 
 def _code_only(text):
@@ -124,13 +145,13 @@ def adjoint_ratio(dtype, steps, ckpt):
     f = qds.Solver(wl, dtype=dtype)
     f.load_pulses()
     f.set_option(qds.OPT_TUNE, 1)
-    f.step(10)                      # the forward's autotuner, then warm
+    f.step(TUNE_STEPS + 2)          # the forward's autotuner, then warm
     s.set_option(qds.OPT_TUNE, 1)
     # the caller-owned checkpoint pool and lambda buffer are allocated once,
     # as a caller repeating the gradient would keep them
     pool = torch.empty(s.backward_pool_bytes(steps, ckpt), dtype=torch.uint8, device=s.device)
     lam = torch.empty(s.nbytes, dtype=torch.uint8, device=s.device)
-    s.backward(20, 10, pool=pool, out=lam)    # tunes on its checkpoint pass; warms the adjoint
+    s.backward(40, 20, pool=pool, out=lam)    # tunes on its checkpoint pass; warms the adjoint
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     f.step(steps)
@@ -153,8 +174,10 @@ def batched_leg(step_scale, graph_steps, count=64):
     captured as one HIP graph and launched once (``graph_steps`` -1; otherwise
     that many steps per graph), against the same schedule launched without
     graphs and against each instance advanced alone with qds_step (each with
-    the tiles its own autotuner chose).  The graph is captured on an untimed
-    first pass of the schedule and replayed on the timed one."""
+    the tiles its own autotuner chose): in pairs of steps (the library's
+    default), and one step at a time (the kernels the batch launches).  The
+    graph is captured on an untimed first pass of the schedule and replayed
+    on the timed one."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
@@ -183,13 +206,24 @@ def batched_leg(step_scale, graph_steps, count=64):
     s2 = b.stats()
     for s in bs:
         s.set_option(qds.OPT_TUNE, 1)      # each instance's own autotuner, untimed
-        s.step(8)
+        s.step(TUNE_STEPS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s, n in zip(bs, steps):
         s.step(n)
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
+    # one at a time and one step at a time: the kernels the batch launches
+    for s in bs:
+        s.set_option(qds.OPT_PAIR, 0)
+        s.set_option(qds.OPT_TUNE, 1)
+        s.step(TUNE_STEPS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, n in zip(bs, steps):
+        s.step(n)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
     tiles, tuned = b.tiles()
     b.close()
     for s in bs:
@@ -201,6 +235,8 @@ def batched_leg(step_scale, graph_steps, count=64):
             "graph_launches_per_run": s1[0] - s0[0], "kernel_launches_per_run": kernel_launches_direct,
             "batched_updates_per_s": updates / t_batch, "batched_no_graph_updates_per_s": updates / t_direct,
             "one_at_a_time_updates_per_s": updates / t_solo, "speedup": t_solo / t_batch,
+            "one_at_a_time_single_steps_updates_per_s": updates / t_single,
+            "speedup_vs_single_steps": t_single / t_batch,
             "graph_gain_s": t_direct - t_batch,
             "launch_overhead_us_per_kernel": (t_direct - t_batch) / max(kernel_launches_direct, 1) * 1e6}
 
@@ -214,7 +250,7 @@ def f32_leg(wl, steps):
     s = qds.Solver(wl, dtype="f32")
     s.load_pulses()
     s.set_option(qds.OPT_TUNE, 1)
-    s.step(8)
+    s.step(TUNE_STEPS)
     s.step(10)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -234,17 +270,19 @@ def f32_leg(wl, steps):
 
 
 def kernel_variants_leg(wl, dtype, steps):
-    """The main workload on its three launch arrangements: the split kernels
-    (kernel A, the marched axion kernel, kernel B; the default) in one
-    stream, the same with kernel A of step k+1 on a second stream beside
-    kernel B of step k (QDS_OPT_OVERLAP), and the one-pass kernel AX then
-    kernel B (QDS_OPT_KERNEL_AX).
-    Each solver picks its tiles with its own autotuner on 8 untimed steps,
-    then runs 10 untimed and ``steps`` timed steps; the three run twice in
+    """The main workload on its launch arrangements: the split kernels in
+    pairs of steps (kernel A, the marched axion kernel, twice, then the
+    two-step march of the regenerated set; the default), the split kernels
+    one step at a time (kernel A, the marched axion kernel, kernel B), the
+    same with kernel A of step k+1 on a second stream beside kernel B of
+    step k (QDS_OPT_OVERLAP), and the one-pass kernel AX then kernel B
+    (QDS_OPT_KERNEL_AX).
+    Each solver picks its tiles with its own autotuner on TUNE_STEPS untimed steps,
+    then runs 10 untimed and ``steps`` timed steps; the four run twice in
     rotating order and the faster run of each is kept."""
     import torch
     from paper_2609_03550_amd import qds
-    names = ("split", "split_overlap", "ax")
+    names = ("split_pairs", "split", "split_overlap", "ax")
     res = {n: [] for n in names}
     tiles = {}
     for rep in range(2):
@@ -253,8 +291,9 @@ def kernel_variants_leg(wl, dtype, steps):
             s.load_pulses()
             s.set_option(qds.OPT_KERNEL_AX, 1 if name == "ax" else 0)
             s.set_option(qds.OPT_OVERLAP, 1 if name == "split_overlap" else 0)
+            s.set_option(qds.OPT_PAIR, 1 if name == "split_pairs" else 0)
             s.set_option(qds.OPT_TUNE, 1)
-            s.step(8)
+            s.step(TUNE_STEPS)
             s.step(10)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -271,6 +310,7 @@ def kernel_variants_leg(wl, dtype, steps):
         out[n + "_tiles"] = tiles[n]
     out["ax_over_split"] = out["ax_ms_per_step"] / out["split_ms_per_step"]
     out["overlap_over_split"] = out["split_overlap_ms_per_step"] / out["split_ms_per_step"]
+    out["pairs_over_split"] = out["split_pairs_ms_per_step"] / out["split_ms_per_step"]
     return out
 
 
@@ -281,7 +321,7 @@ def theta_leg(steps=20):
     wavefront per mode, autotuned tiles): 6 and 8 modes of the full physics on
     a 2048 x 64 grid with dr = 8 dx (what the radial stability bound allows
     for 8 modes), FP64, ``steps`` timed steps after 3 untimed (and the
-    autotuner's 8 on the fused kernels)."""
+    autotuner's TUNE_STEPS on the fused kernels)."""
     import torch
     from paper_2609_03550_amd import inputs as I
     from paper_2609_03550_amd import qds
@@ -300,7 +340,7 @@ def theta_leg(steps=20):
             s.load_pulses()
             if path == qds.PATH_FUSED:
                 s.set_option(qds.OPT_TUNE, 1)
-                s.step(8)
+                s.step(TUNE_STEPS)
             s.step(3)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -476,7 +516,8 @@ def main():
     ap.add_argument("--path", type=int, default=0, help="0 auto (fused), 1 staged, 2 fused")
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--tiles", default=None,
-                    help="tile heights of kernel A, the axion current and kernel B (a,c,b) instead of the autotuner")
+                    help="tile heights of kernel A, the axion current, kernel B and the two-step march "
+                         "(a,c,b[,p]) instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the forward + adjoint timing (0 skips it)")
@@ -493,6 +534,9 @@ def main():
     ap.add_argument("--kernel-ax", type=int, default=0,
                     help="1 runs the one-pass kernel AX instead of kernel A and the marched axion kernel "
                          "(QDS_OPT_KERNEL_AX)")
+    ap.add_argument("--pair", type=int, default=1,
+                    help="1 (default) runs steps in pairs with the two-step march of one set where it applies "
+                         "(QDS_OPT_PAIR); 0 one step at a time")
     ap.add_argument("--overlap", type=int, default=0,
                     help="1 runs kernel A of the next step beside the regenerated set (QDS_OPT_OVERLAP)")
     ap.add_argument("--variant-steps", type=int, default=100,
@@ -520,14 +564,17 @@ def main():
     s.load_pulses()
     s.set_option(qds.OPT_KERNEL_AX, args.kernel_ax)
     s.set_option(qds.OPT_OVERLAP, args.overlap)
+    s.set_option(qds.OPT_PAIR, args.pair)
+    paired = pairs_active(wl, s.fused, args.pair, args.kernel_ax, args.overlap)
     if args.tiles:
-        for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B), args.tiles.split(",")):
+        for opt, v in zip((qds.OPT_ROWS_A, qds.OPT_ROWS_CUR, qds.OPT_ROWS_B, qds.OPT_ROWS_PAIR),
+                          args.tiles.split(",")):
             s.set_option(opt, int(v))
     elif args.rows is None:
-        # tile heights chosen by the library's autotuner on 8 untimed steps of
+        # tile heights chosen by the library's autotuner on TUNE_STEPS untimed steps of
         # the run, before the warm-up steps
         s.set_option(qds.OPT_TUNE, 1)
-        s.step(8)
+        s.step(TUNE_STEPS)
         torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     if args.copy_calibration:
@@ -566,23 +613,28 @@ def main():
     cells = wl.cell_modes
     value = cells * args.steps / (total_ms / 1e3)
     eb = 16 if args.dtype == "f64" else 8
-    run_tiles = dict(zip(("kernel_a", "axion_current", "kernel_b"), s.tiles()[0]))
+    run_tiles = dict(zip(("kernel_a", "axion_current", "kernel_b", "kernel_b2"), s.tiles()[0]))
     kernels = {}
     for q in range(3):
         if not kn[q]:
             continue
         avg = kms[q] / kn[q]
+        # the timing slot of a set's two-step march is that of the set
+        kind = 3 if paired and q == (1 if wl.arem else 0) else q
         name = KERNEL_NAMES[q] if (s.fused and wl.axion) else ("electromagnetic set" if s.fused else
                                                                  "staged step (all stage kernels)")
         if s.fused and wl.arem and args.kernel_ax and q == 0:
             name = KERNEL_NAME_AX
-        alg = (plane_accesses(wl, q, not args.kernel_ax) if s.fused
+        if kind == 3:
+            name = KERNEL_NAME_PAIR[bool(wl.arem)]
+        alg = (plane_accesses(wl, kind, not args.kernel_ax) if s.fused
                else sum(plane_accesses(wl, k, True) for k in range(3))) * eb * cells
-        kernels[KERNEL_KEYS[q]] = {"name": name, "avg_launch_ms": avg, "launches": kn[q],
-                                   "plane_passes": alg / eb / cells, "algorithmic_bytes_per_launch": alg,
-                                   "achieved_gbps": alg / (avg / 1e3) / 1e9,
-                                   "hbm_bytes_per_launch": measured_traffic(wl, args.dtype, q, run_tiles)
-                                   if s.fused else None}
+        kernels[KERNEL_KEYS[kind]] = {"name": name, "avg_launch_ms": avg, "launches": kn[q],
+                                      "steps_per_launch": 2 if kind == 3 else 1,
+                                      "plane_passes": alg / eb / cells, "algorithmic_bytes_per_launch": alg,
+                                      "achieved_gbps": alg / (avg / 1e3) / 1e9,
+                                      "hbm_bytes_per_launch": measured_traffic(wl, args.dtype, kind, run_tiles)
+                                      if s.fused else None}
     # the whole step against the one-read-one-write byte model: every state
     # plane read once and written once per step
     nplanes = (21 if wl.arem else 12) if wl.axion else (9 if wl.wp2 else 6)
@@ -609,7 +661,10 @@ def main():
                    "physics": "QDS Maxwell + Klein-Gordon axion + regenerated fields + cold plasma"
                    if wl.arem else ("QDS Maxwell + prescribed current, moving window" if wl.drive else "QDS Maxwell"),
                    "path": "fused" if s.fused else "staged", "overlap": bool(args.overlap),
-                   "kernels": ("AX, B" if args.kernel_ax else "A, axion, B") if (s.fused and wl.arem) else None,
+                   "kernels": ("AX, B" if args.kernel_ax else ("A, axion, A, axion, two-step B" if paired
+                                                               else "A, axion, B"))
+                   if (s.fused and wl.arem) else None,
+                   "pairs_of_steps": paired,
                    "parallelism": "single GPU"},
         # the dominant unit is the whole step (its kernels run back to back):
         # algorithmic bytes = every state plane read once and written once

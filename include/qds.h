@@ -183,9 +183,10 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 which runs kernel AX),
  *                 QDS_PATH_STAGED (one kernel per stage), QDS_PATH_FUSED
  *  QDS_OPT_ROWS   radial rows per workgroup chunk of every fused kernel (1..4096)
- *  QDS_OPT_ROWS_A, QDS_OPT_ROWS_CUR, QDS_OPT_ROWS_B
+ *  QDS_OPT_ROWS_A, QDS_OPT_ROWS_CUR, QDS_OPT_ROWS_B, QDS_OPT_ROWS_PAIR
  *                 the same for one kernel (background set, axion current,
- *                 regenerated set), e.g. to replay heights the tuner chose
+ *                 regenerated set, two-step march), e.g. to replay heights
+ *                 the tuner chose
  *  QDS_OPT_TUNE   1: the next qds_step of at least 8 steps on the fused path
  *                 times its first 8 steps (two passes over four tile heights
  *                 per kernel: 8, 16, 24, 32 for the background set with the
@@ -193,7 +194,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 background set alone, 4, 6, 8,
  *                 16 for the axion current, 16, 32, 52, 64 for the regenerated
  *                 set; HIP events around every launch) and keeps the fastest
- *                 height for each kernel; the trial steps are ordinary
+ *                 height for each kernel (with QDS_OPT_PAIR in effect: its
+ *                 first 8 pairs, the two-step march in place of kernel B);
+ *                 the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream
  *                 once, after the trials.
  *  QDS_OPT_PRODUCTS QDS_PRODUCTS_DIRECT (default): the mode products of the
@@ -222,6 +225,26 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 re-reads the background set to advance the axion and form
  *                 its current (measured faster on MI355X: the one-pass march
  *                 holds both windows, which halves its occupancy).
+ *  QDS_OPT_PAIR   1: qds_step advances steps two at a time where the
+ *                 two-step march applies (fused kernels, no moving window, no
+ *                 prescribed drive; with the regenerated set on kernel A and
+ *                 the marched axion kernel, or the background set alone
+ *                 without the axion): one launch marches one set through two
+ *                 steps, the first step's rows handed to the second through
+ *                 LDS, so the set's planes are read and written once per two
+ *                 steps (temporal blocking of the Maxwell update of Sec. 2.1;
+ *                 the results equal those of single steps bit for bit).  With
+ *                 the regenerated set, kernel A and the axion kernel of the
+ *                 first step write to a state-sized buffer of the handle
+ *                 (allocated on first use, with 3 planes for the second
+ *                 step's axion current), those of the second step into the
+ *                 caller's other buffer.  Each pair flips fields->cur once and
+ *                 adds 2 to fields->step; an odd last step is a single step.
+ *                 Tile height QDS_OPT_ROWS_PAIR (default: two chunks; tuner
+ *                 candidates 16 and the heights that cut the nr + 1 rows into
+ *                 5, 3 and 2 chunks); the timing slot of the march is that of
+ *                 the set it advances, one launch per two steps.  1 is the
+ *                 default; 0: single steps.
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
@@ -229,7 +252,7 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
 enum {
     QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
     QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8, QDS_OPT_OVERLAP = 9,
-    QDS_OPT_KERNEL_AX = 10
+    QDS_OPT_KERNEL_AX = 10, QDS_OPT_PAIR = 11, QDS_OPT_ROWS_PAIR = 12
 };
 enum { QDS_PRODUCTS_DIRECT = 0, QDS_PRODUCTS_THETA = 1 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };
@@ -244,8 +267,8 @@ qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches);
 
 /* Tile heights (radial rows per workgroup) of the fused kernels in use:
  * rows[0] kernel A (or the background set without the axion), rows[1] the
- * axion current, rows[2] the regenerated set; *tuned = 1 once the autotuner
- * (QDS_OPT_TUNE) has chosen them. */
+ * axion current, rows[2] the regenerated set, rows[3] the two-step march;
+ * *tuned = 1 once the autotuner (QDS_OPT_TUNE) has chosen them. */
 qds_status qds_get_tiles(qds_handle h, int32_t* rows, int32_t* tuned);
 
 /* 1 if qds_step runs the fused kernels for this handle. */

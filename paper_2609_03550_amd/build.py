@@ -16,6 +16,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused within a source expression only: a step computes the
+    # same bits whichever kernel it is inlined into (the one-step and two-step
+    # marches, the kernel that advances the axion)
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-result",
 ]

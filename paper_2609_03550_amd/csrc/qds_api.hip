@@ -24,6 +24,19 @@ const int kCandAX[4] = {16, 24, 32, 48};
 const int kCandCur[4] = {4, 6, 8, 16};
 const int kCandB[4] = {16, 32, 52, 64};
 const int kCandEm[4] = {8, 16, 26, 52};
+// The two-step march runs fastest when all its workgroups are resident at
+// once (measured on MI355X: 129 rows, two chunks, for FP64 at 8192 x 256 x 3,
+// 86 rows, three chunks, for FP32): 16 rows and the heights that cut the
+// nr + 1 rows into 5, 3 and 2 chunks.
+void cand_pair(const qds_ctx* c, int* out) {
+    const int R = c->g.nr + 1;
+    const int parts[4] = {0, 5, 3, 2};
+    out[0] = 16;
+    for (int q = 1; q < 4; ++q) {
+        const int h = (R + parts[q] - 1) / parts[q];
+        out[q] = h < 4 ? 4 : h;
+    }
+}
 constexpr int kTrials = 8;
 
 // Makes the device argument table current for the state buffers of st
@@ -31,7 +44,7 @@ constexpr int kTrials = 8;
 template <typename T>
 qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0, hipStream_t s, KTab<T>** dev) {
     // the table depends on the two buffers, the physics and the tile height only
-    double key[16];
+    double key[18];
     memset(key, 0, sizeof(key));
     memcpy(&key[0], &st->buf[0], sizeof(void*));
     memcpy(&key[1], &st->buf[1], sizeof(void*));
@@ -40,6 +53,8 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     key[10] = double(p0.bt1.re); key[11] = double(p0.bt1.im);
     key[12] = double(c->trows[0]); key[13] = double(c->trows[1]); key[14] = double(c->trows[2]);
     key[15] = double(p0.drive.on) + (p0.psrc[0] ? 2.0 : 0.0);
+    memcpy(&key[16], &c->pairbuf, sizeof(void*));
+    key[17] = double(c->trows[3]);
     if (!c->ktab_dev) {
         c->ktab_bytes = sizeof(KTab<double>);
         if (hipMalloc(&c->ktab_dev, c->ktab_bytes) != hipSuccess) {
@@ -61,6 +76,15 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     for (int q = 0; q < 2; ++q) {
         t.fa[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
         t.xa[q] = axion_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
+        if (c->pairbuf) {
+            // the second step of a pair writes its axion current to the second j_a planes
+            qds::StepPlan<T> p2 = p0;
+            for (int k = 0; k < 3; ++k) p2.ja[k] = p0.ja2[k];
+            t.fp[q][0] = fused_args<T>(c, p0, st->buf[q], c->pairbuf);
+            t.xp[q][0] = axion_args<T>(c, p0, st->buf[q], c->pairbuf);
+            t.fp[q][1] = fused_args<T>(c, p2, c->pairbuf, st->buf[1 - q]);
+            t.xp[q][1] = axion_args<T>(c, p2, c->pairbuf, st->buf[1 - q]);
+        }
     }
     const int strips = qds::fused_strips(c->g.nx);
     auto chunks = [&](int rows) { return (c->g.nr + 1 + rows - 1) / rows; };
@@ -68,6 +92,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     t.firstA[1] = strips * chunks(c->trows[0]);
     t.firstC[1] = qds::current_strips(c->g.nx) * chunks(c->trows[1]);
     t.firstB[1] = strips * chunks(c->trows[2]) * c->M;
+    t.firstB2[1] = qds::pair_strips(c->g.nx) * chunks(c->trows[3]) * c->M;
     // the staging copy may still be read by the previous upload
     if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
         return fail(c, QDS_EHIP, "argument table upload failed%s");
@@ -91,20 +116,21 @@ struct TabView {
     const int* firstA;
     const int* firstC;
     const int* firstB;
-    int nA, nC, nB;
+    const int* firstB2;
+    int nA, nC, nB, nB2;
 };
 
 template <typename T>
 TabView<T> ktab_view(KTab<T>* K, const KTab<T>& host, int q) {
-    return TabView<T>{K->fa + q, K->xa + q, K->idx, K->firstA, K->firstC, K->firstB,
-                      host.firstA[1], host.firstC[1], host.firstB[1]};
+    return TabView<T>{K->fa + q, K->xa + q, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2,
+                      host.firstA[1], host.firstC[1], host.firstB[1], host.firstB2[1]};
 }
 
 // The three launches of one fused step through an argument-table entry:
 // kernel A (or the background set alone), the axion kernel and the
 // regenerated set, each on stream s and bracketed by the event pair e when
 // given (or by a timing pair when timing is on).
-enum { kLaunchA = 0, kLaunchX = 1, kLaunchB = 2 };
+enum { kLaunchA = 0, kLaunchX = 1, kLaunchB = 2, kLaunchB2 = 3 };
 
 template <typename T>
 qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, int which, hipStream_t s,
@@ -117,8 +143,10 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
         L.rows = rows;
         return L;
     };
-    // timing slots: 0 kernel A, 1 the regenerated set, 2 the axion kernel
-    const int slot = which == kLaunchA ? 0 : (which == kLaunchX ? 2 : 1);
+    // timing slots: 0 kernel A (or the background set alone, also its
+    // two-step march), 1 the regenerated set (also its two-step march), 2 the
+    // axion kernel
+    const int slot = which == kLaunchA ? 0 : (which == kLaunchX ? 2 : (which == kLaunchB2 && !p0.arem ? 0 : 1));
     hipEvent_t* ev = e ? e : (c->timing ? timing_pair(c, slot) : nullptr);
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t err = hipSuccess;
@@ -135,6 +163,8 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
         }
     } else if (which == kLaunchX) {
         err = qds::batch_current<T>(v.xa, list(v.firstC, c->trows[1]), c->M, v.nC, s);
+    } else if (which == kLaunchB2) {
+        err = qds::batch_em2<T>(v.fa, list(v.firstB2, c->trows[3]), p0.arem ? 1 : 0, v.nB2, s);
     } else {
         err = qds::batch_em<T>(v.fa, list(v.firstB, c->trows[2]), 1, v.nB, s);
     }
@@ -168,6 +198,36 @@ qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTa
     st->cur = 1 - st->cur;
     if (c->g.x_bc == QDS_X_WINDOW) st->window += 1;
     st->step += 1;
+    return QDS_OK;
+}
+
+// Two steps from buffer q to buffer 1 - q.  With the regenerated set: kernel
+// A and the axion kernel of the first step write the background set and the
+// axion to the pair buffer (the axion current to the first j_a planes), those
+// of the second step from there to buffer 1 - q (the axion current to the
+// second j_a planes), then the two-step march takes the regenerated set from
+// buffer q to buffer 1 - q with both currents.  Without it the two-step march
+// of the background set is the only launch.  The event pairs ev[0..1] (first
+// kernel A), ev[2..3] (first axion kernel) and ev[4..5] (the two-step march)
+// bracket those launches when ev is given.
+template <typename T>
+qds_status pair_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab<T>* K, const KTab<T>& host,
+                     hipStream_t s, hipEvent_t* ev) {
+    const int q = st->cur;
+    const TabView<T> v = ktab_view<T>(K, host, q);
+    qds_status r;
+    if (p0.arem) {
+        TabView<T> va = v, vb = v;
+        va.fa = &K->fp[q][0]; va.xa = &K->xp[q][0];
+        vb.fa = &K->fp[q][1]; vb.xa = &K->xp[q][1];
+        if ((r = table_launch_one<T>(c, p0, va, kLaunchA, s, ev)) != QDS_OK) return r;
+        if ((r = table_launch_one<T>(c, p0, va, kLaunchX, s, ev ? ev + 2 : nullptr)) != QDS_OK) return r;
+        if ((r = table_launch_one<T>(c, p0, vb, kLaunchA, s, nullptr)) != QDS_OK) return r;
+        if ((r = table_launch_one<T>(c, p0, vb, kLaunchX, s, nullptr)) != QDS_OK) return r;
+    }
+    if ((r = table_launch_one<T>(c, p0, v, kLaunchB2, s, ev ? ev + 4 : nullptr)) != QDS_OK) return r;
+    st->cur = 1 - st->cur;
+    st->step += 2;
     return QDS_OK;
 }
 
@@ -242,45 +302,74 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
                                                       c->plane_elems, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     }
-    if (c->tune && n_steps >= kTrials) {
-        // autotuner: timed ordinary steps, two passes over four tile heights per
-        // kernel (candidates around each kernel's measured optimum)
-        const int* cand[3] = {fuse_ax(c, p0) ? kCandAX : (p0.axion ? kCandA : kCandEm), kCandCur, kCandB};
+    const bool pairs = pair_ok(c, p0) && n_steps >= 2;
+    if (pairs && p0.arem && !c->pairbuf) {
+        // the background set and the axion between the two steps of a pair,
+        // then the second step's axion current
+        const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+        if (hipMalloc(&c->pairbuf, sbytes + 3 * c->plane_elems * c->elem_bytes) != hipSuccess) {
+            c->pairbuf = nullptr;
+            return fail(c, QDS_ENOMEM, "hipMalloc of the pair buffer failed%s");
+        }
+    }
+    if (c->pairbuf) {
+        // (the plan was made before the buffer existed on the first call)
+        const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+        for (int k = 0; k < 3; ++k)
+            p0.ja2[k] = reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->pairbuf) + sbytes +
+                                                      size_t(k) * c->plane_elems * c->elem_bytes);
+    }
+    const int per = pairs ? 2 : 1;     // steps per trial
+    if (c->tune && n_steps >= per * kTrials) {
+        // autotuner: timed ordinary steps (or pairs of steps), two passes over
+        // four tile heights per kernel (candidates around each kernel's
+        // measured optimum).  Slots: 0 kernel A / the background set, 1 the
+        // axion kernel, 2 kernel B or the two-step march.
+        int candB2[4];
+        cand_pair(c, candB2);
+        const int* cand[3] = {fuse_ax(c, p0) ? kCandAX : (p0.axion ? kCandA : kCandEm), kCandCur,
+                              pairs ? candB2 : kCandB};
+        int* const tr[3] = {&c->trows[0], &c->trows[1], pairs ? &c->trows[3] : &c->trows[2]};
+        const bool run[3] = {!(pairs && !p0.arem), p0.arem && !fuse_ax(c, p0), p0.arem || pairs};
         std::vector<hipEvent_t> ev(6 * kTrials);
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return fail(c, QDS_EHIP, "event creation failed%s");
         for (int t = 0; t < kTrials; ++t) {
-            for (int k = 0; k < 3; ++k) c->trows[k] = cand[k][t % 4];
+            for (int k = 0; k < 3; ++k)
+                if (run[k]) *tr[k] = cand[k][t % 4];
             if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
             const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
-            if ((r = table_step<T>(c, st, p0, K, host, s, ev.data() + 6 * t)) != QDS_OK) return r;
+            r = pairs ? pair_step<T>(c, st, p0, K, host, s, ev.data() + 6 * t)
+                      : table_step<T>(c, st, p0, K, host, s, ev.data() + 6 * t);
+            if (r != QDS_OK) return r;
         }
         if (hipStreamSynchronize(s) != hipSuccess) return fail(c, QDS_EHIP, "tuning steps failed%s");
         float best[3] = {3.4e38f, 3.4e38f, 3.4e38f};
-        int pick[3] = {16, 16, 16};
+        int pick[3] = {*tr[0], *tr[1], *tr[2]};
         for (int t = 0; t < kTrials; ++t)
             for (int k = 0; k < 3; ++k) {
-                if (k > 0 && !p0.arem) continue;
-                if (k == 1 && fuse_ax(c, p0)) continue;      // no separate axion kernel
+                if (!run[k]) continue;
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[6 * t + 2 * k], ev[6 * t + 2 * k + 1]) != hipSuccess) {
                     (void)hipGetLastError();   // do not leave the error for the next launch check
                     continue;
                 }
-                const int slot = k == 0 ? 0 : (k == 1 ? 1 : 2);
-                if (ms < best[slot]) { best[slot] = ms; pick[slot] = cand[slot][t % 4]; }
+                if (ms < best[k]) { best[k] = ms; pick[k] = cand[k][t % 4]; }
             }
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
-        for (int k = 0; k < 3; ++k) c->trows[k] = pick[k];
+        for (int k = 0; k < 3; ++k) *tr[k] = pick[k];
         c->tune = 0;
         c->tuned = 1;
-        done = kTrials;
+        done = per * kTrials;
     }
     if ((r = sync_ktab<T>(c, st, p0, s, &K)) != QDS_OK) return r;
     const KTab<T> host = *static_cast<const KTab<T>*>(c->ktab_pin);
     if (c->overlap && p0.arem && march_axion(c, p0) && !fuse_ax(c, p0) && !p0.drive.on && c->g.x_bc != QDS_X_WINDOW &&
         n_steps - done >= 2)
         return overlapped_steps<T>(c, st, p0, K, host, n_steps - done, s);
+    if (pairs)
+        for (; n_steps - done >= 2; done += 2)
+            if ((r = pair_step<T>(c, st, p0, K, host, s, nullptr)) != QDS_OK) return r;
     for (int64_t it = done; it < n_steps; ++it)
         if ((r = table_step<T>(c, st, p0, K, host, s, nullptr)) != QDS_OK) return r;
     return QDS_OK;
@@ -513,8 +602,8 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
         for (int64_t k = 0; k < n1 - n0; ++k) {
             if (tab) {
                 // fused kernels through the segment's argument table
-                const TabView<T> v{tab + k, xtab + k, K->idx, K->firstA, K->firstC, K->firstB,
-                                   khost.firstA[1], khost.firstC[1], khost.firstB[1]};
+                const TabView<T> v{tab + k, xtab + k, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2,
+                                   khost.firstA[1], khost.firstC[1], khost.firstB[1], khost.firstB2[1]};
                 qds_status st = table_launch<T>(c, p, v, s, nullptr);
                 if (st != QDS_OK) return st;
                 continue;
@@ -615,6 +704,8 @@ qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, q
     c->path = QDS_PATH_AUTO;
     c->rows = 16;
     c->trows[0] = c->trows[1] = c->trows[2] = 16;
+    c->trows[3] = (g.nr + 2) / 2;   // two chunks
+    c->pair = 1;
     if (g.content & QDS_HAS_AREM) {
         // j_a,x, j_a,r, j_a,theta at the source points and the axion source S_a
         hipError_t e = hipMalloc(&c->scratch, 4 * c->plane_elems * c->elem_bytes);
@@ -710,7 +801,7 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
         case QDS_OPT_ROWS:
             if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");
             h->rows = int(value);
-            h->trows[0] = h->trows[1] = h->trows[2] = int(value);
+            h->trows[0] = h->trows[1] = h->trows[2] = h->trows[3] = int(value);
             return QDS_OK;
         case QDS_OPT_ROWS_A:
         case QDS_OPT_ROWS_CUR:
@@ -727,6 +818,14 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
             return QDS_OK;
         case QDS_OPT_KERNEL_AX:
             h->kernel_ax = value ? 1 : 0;
+            return QDS_OK;
+        case QDS_OPT_PAIR:
+            h->pair = value ? 1 : 0;
+            return QDS_OK;
+        case QDS_OPT_ROWS_PAIR:
+            if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");
+            h->trows[3] = int(value);
+            h->tuned = 0;
             return QDS_OK;
         case QDS_OPT_PRODUCTS:
             if (value != QDS_PRODUCTS_DIRECT && value != QDS_PRODUCTS_THETA)
@@ -760,7 +859,7 @@ qds_status qds_get_timing(qds_handle h, double* ms, int64_t* launches) {
 
 qds_status qds_get_tiles(qds_handle h, int32_t* rows, int32_t* tuned) {
     if (!h || !rows) return fail(h, QDS_EINVAL, "null argument%s");
-    for (int k = 0; k < 3; ++k) rows[k] = h->trows[k];
+    for (int k = 0; k < 4; ++k) rows[k] = h->trows[k];
     if (tuned) *tuned = h->tuned;
     return QDS_OK;
 }
@@ -853,6 +952,7 @@ qds_status qds_destroy(qds_handle h) {
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->drive_plane) (void)hipFree(h->drive_plane);
     if (h->psrc) (void)hipFree(h->psrc);
+    if (h->pairbuf) (void)hipFree(h->pairbuf);
     if (h->ktab_ev) {
         (void)hipEventSynchronize(h->ktab_ev);
         (void)hipEventDestroy(h->ktab_ev);

@@ -20,15 +20,19 @@ struct qds_ctx {
     void* scratch;           // axion-current planes (3) and S_a, library owned
     void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0 (allocated on first use)
     void* psrc;              // particle currents at the source points, 3 planes (allocated on first use)
+    void* pairbuf;           // pairs of steps with the regenerated set: a state-sized buffer for the
+                             // background set and axion between the two steps, then j_a of the
+                             // second step (3 planes); allocated on first use
     int path;                // QDS_PATH_*
     int theta;               // QDS_PRODUCTS_THETA: theta-grid products (staged path)
     int rows;                // the last QDS_OPT_ROWS value (also copied into trows)
-    int trows[3];            // tile heights of the table-driven kernels: A, current, B
+    int trows[4];            // tile heights of the table-driven kernels: A, current, B, two-step march
     int tune;                // autotune the tile heights on the next long enough qds_step
     int tuned;
     int timing;              // record per-kernel HIP events in qds_step
     int overlap;             // kernel A of step k+1 on a second stream beside kernel B of step k
     int kernel_ax;           // 1: one-pass kernel AX instead of kernel A and the marched axion kernel
+    int pair;                // 1: advance steps in pairs with the two-step march of one set where it applies
     hipStream_t side;        // that stream (created on first use, default priority)
     hipEvent_t ev_x, ev_a;   // its ordering events
     // timing events, recorded without synchronising and resolved by
@@ -43,7 +47,7 @@ struct qds_ctx {
     size_t ktab_bytes;
     hipEvent_t ktab_ev;
     bool ktab_valid;
-    double ktab_key[16];     // buffers and physics the uploaded table was built for
+    double ktab_key[18];     // buffers and physics the uploaded table was built for
     char err[256];
 };
 
@@ -123,6 +127,7 @@ qds::SetP<T> fused_set(qds::cx<T>* const* A, qds::cx<T>* const* B, int s) {
     p.otrp = B[b + 0]; p.otrm = B[b + 1]; p.ottp = B[b + 2]; p.ottm = B[b + 3];
     p.oex = B[b + 4]; p.obx = B[b + 5]; p.ojx = B[b + 6]; p.ojr = B[b + 7]; p.ojt = B[b + 8];
     p.jxa = p.jra = p.jta = nullptr;
+    p.jxb = p.jrb = p.jtb = nullptr;
     p.jxa_m0 = 0;
     return p;
 }
@@ -156,6 +161,12 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
                            : nullptr;
     for (int k = 0; k < 3; ++k) p.ja[k] = sc[k];
     p.sa = sc[3];
+    // j_a of the second step of a pair: the 3 planes after the pair buffer's state
+    const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+    for (int k = 0; k < 3; ++k)
+        p.ja2[k] = c->pairbuf ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->pairbuf) + sbytes +
+                                                              size_t(k) * c->plane_elems * c->elem_bytes)
+                              : nullptr;
     p.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
     const bool part = J && J->kind == QDS_J_PARTICLES;
     p.pj[0] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_prev)) : nullptr;
@@ -204,6 +215,7 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     a.s0 = fused_set<T>(A, B, 0);
     a.s1 = fused_set<T>(A, B, 1);
     a.s1.jxa = a.jax; a.s1.jra = a.jar; a.s1.jta = a.jat;
+    a.s1.jxb = p0.ja2[0]; a.s1.jrb = p0.ja2[1]; a.s1.jtb = p0.ja2[2];
     if (p0.drive.on) {
         a.s0.jxa = p0.jdrv;
         a.s0.jxa_m0 = 1;
@@ -215,9 +227,25 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
         a.s0.jta = p0.psrc[2];
         a.s0.jxa_m0 = 0;
     }
+    // a pair of steps of the background set alone (no drive) reads the same
+    // extra currents in both steps
+    if (!p0.drive.on) {
+        a.s0.jxb = a.s0.jxa; a.s0.jrb = a.s0.jra; a.s0.jtb = a.s0.jta;
+    }
     a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
     a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
     return a;
+}
+
+// Whether qds_step advances steps in pairs, with the two-step march of one
+// set: the regenerated set (kernel A and the marched axion kernel for the
+// background set and the axion, no prescribed drive), or the background set
+// alone (no axion, no drive).  Not with the moving window.
+template <typename T>
+bool pair_ok(const qds_ctx* c, const qds::StepPlan<T>& p0) {
+    if (!c->pair || c->g.x_bc == QDS_X_WINDOW || p0.drive.on) return false;
+    if (p0.arem) return march_axion(c, p0) && !fuse_ax(c, p0);
+    return !p0.axion;
 }
 
 // Axion-current arguments of the same step.
@@ -247,8 +275,14 @@ template <typename T>
 struct KTab {
     qds::FusedArgs<T> fa[2];
     qds::AxionArgs<T> xa[2];
+    // a pair of steps from buffer q: [q][0] the background set and the axion
+    // from buffer q into the pair buffer (j_a into the first j_a planes),
+    // [q][1] from the pair buffer into buffer 1 - q (j_a into the second);
+    // the two-step march of the regenerated set uses fa[q]
+    qds::FusedArgs<T> fp[2][2];
+    qds::AxionArgs<T> xp[2][2];
     int idx[2];
-    int firstA[2], firstC[2], firstB[2];
+    int firstA[2], firstC[2], firstB[2], firstB2[2];
 };
 
 }  // namespace qdsi

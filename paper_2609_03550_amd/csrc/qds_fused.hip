@@ -253,25 +253,110 @@ __device__ __forceinline__ EmB<T> em_bvals(const Ctx<T>& c, const EmWin<T>& W) {
     return B;
 }
 
+// Where a march writes the new state.  IO_GLOBAL: the owner lanes store the
+// rows [r0, r1) of their columns to the output planes.  IO_RING (the first
+// step of the two-step march): every lane puts the values of its own column,
+// for the rows [r0, r1), into the workgroup's LDS ring, from which the second
+// step reads them in place of the state planes.  IO_FROM_RING (that second
+// step): global stores as IO_GLOBAL, and the old plasma j_theta that the
+// exterior ghost reads comes from the ring.
+enum { IO_GLOBAL = 0, IO_RING = 1, IO_FROM_RING = 2 };
+
+// The LDS ring of the two-step march: the 9 planes of one set (T_r^+-,
+// T_theta^+-, E_x, B_x, j_x, j_r, j_theta) for 4 consecutive rows (row k in
+// slot k mod 4) of the 64 lanes of a strip, lane-contiguous.
+enum { RG_TRP = 0, RG_TRM, RG_TTP, RG_TTM, RG_EX, RG_BX, RG_JX, RG_JR, RG_JT, RG_N };
+constexpr int RING_ROWS = 4;
+template <typename T>
+__device__ __forceinline__ cx<T>* rg(cx<T>* ring, int plane, int row, int lane) {
+    return ring + (plane * RING_ROWS + (row & (RING_ROWS - 1))) * WAVE + lane;
+}
+
 // total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra (the axion
 // current, or the prescribed drive)
-template <typename T>
+template <typename T, int IO = IO_GLOBAL>
 __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int row, cx<T> ex0, bool write,
-                                      cx<T> jx_old, cx<T> jxa) {
+                                      cx<T> jx_old, cx<T> jxa, cx<T>* ring = nullptr) {
     cx<T> v = zero<T>();
     if (!c.live) {
         // the dead last cell: its plasma current still advances (it enters no field)
-        if (c.plasma && write && c.owner && c.o.col(c.i) >= 0)
-            sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jx_old + c.wp2h * ex0);
+        if constexpr (IO == IO_RING) {
+            if (c.plasma && write) *rg(ring, RG_JX, row, c.lane) = jx_old + c.wp2h * ex0;
+        } else {
+            if (c.plasma && write && c.owner && c.o.col(c.i) >= 0)
+                sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jx_old + c.wp2h * ex0);
+        }
         return v;
     }
     if (c.plasma) {
         cx<T> jn = jx_old + c.wp2h * ex0;
-        if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jn);
+        if constexpr (IO == IO_RING) {
+            if (write) *rg(ring, RG_JX, row, c.lane) = jn;
+        } else {
+            if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jn);
+        }
         v = jn;
     }
     if (s.jxa) v = v + jxa;
     return v;
+}
+
+// Row k of the first step's results, from the ring, for the second step of
+// the two-step march (the values em_fetch reads from the state planes), with
+// the second step's extra j_x of row k, loaded a row ahead (em_xa).
+template <typename T>
+__device__ __forceinline__ EmPf<T> em_fetch_ring(const Ctx<T>& c, cx<T>* ring, int k, cx<T> jxa) {
+    const int l = c.lane;
+    EmPf<T> p;
+    p.rpa = p.rpb = p.rma = p.rmb = p.tpa = p.tpb = p.tma = p.tmb = zero<T>();
+    p.ex0 = p.bx0 = p.jx = p.jxa = zero<T>();
+    if (k < 0) return p;
+    if (k < c.g.nr) {
+        p.rpa = *rg(ring, RG_TRP, k, l);
+        p.rma = *rg(ring, RG_TRM, k, l);
+    } else if (k == c.g.nr) {
+        const cx<T> a = *rg(ring, RG_TRP, k, l);   // the exterior ghost B_theta
+        p.rpa = a; p.rma = -a;
+    }
+    if (k <= c.g.nr) {
+        p.tpa = *rg(ring, RG_TTP, k, l);
+        p.tma = *rg(ring, RG_TTM, k, l);
+        p.ex0 = *rg(ring, RG_EX, k, l);
+        p.bx0 = *rg(ring, RG_BX, k, l);
+        if (c.plasma) p.jx = *rg(ring, RG_JX, k, l);
+        p.jxa = jxa;
+    }
+    return p;
+}
+template <typename T>
+__device__ __forceinline__ EmRowX<T> em_fetch_x_ring(const Ctx<T>& c, cx<T>* ring, int j, const EmRowX<T>& ext) {
+    EmRowX<T> x;
+    x.jr = x.jt = x.jra = x.jta = zero<T>();
+    if (j < 0) return x;
+    if (c.plasma) {
+        if (j < c.g.nr) x.jr = *rg(ring, RG_JR, j, c.lane);
+        x.jt = *rg(ring, RG_JT, j, c.lane);
+    }
+    x.jra = ext.jra;
+    x.jta = ext.jta;
+    return x;
+}
+// The extra currents that the march reads from their planes (not from the
+// ring): j_x of row k, and j_r, j_theta of row j (zero where em_fetch and
+// em_fetch_x read none).
+template <typename T>
+__device__ __forceinline__ cx<T> em_xa(const Ctx<T>& c, const SetP<T>& s, int k) {
+    if (k < 0 || k > c.g.nr || !s.jxa || !c.live || (s.jxa_m0 && c.m != 0)) return zero<T>();
+    return c.x.L(s.jxa, c.m, k);
+}
+template <typename T>
+__device__ __forceinline__ EmRowX<T> em_xrt(const Ctx<T>& c, const SetP<T>& s, int j) {
+    EmRowX<T> x;
+    x.jr = x.jt = x.jra = x.jta = zero<T>();
+    if (j < 0) return x;
+    if (s.jra && j < c.g.nr) x.jra = c.x.L(s.jra, c.m, j);
+    if (s.jta && j <= c.g.nr) x.jta = c.x.L(s.jta, c.m, j);
+    return x;
 }
 
 // E_x^{n+1/2} at J = j+1 from the window (Eqs. Ex_update, Gammax_explicit, axis_Ex)
@@ -312,22 +397,29 @@ __device__ __forceinline__ cx<T> em_bx_new(const Ctx<T>& c, const EmWin<T>& W, c
 // plasma j_theta at (x_{i+1/2}, r_j, t^{n+1/2}) from the window slot s and the
 // old plasma j_theta at columns i (jti) and i+1 (jti1), writing the new plasma
 // j_theta at the integer column i
-template <typename T>
+template <typename T, int IO = IO_GLOBAL>
 __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, const EmB<T>& B,
-                                           int row, int slot, bool write, cx<T> jti, cx<T> jti1) {
+                                           int row, int slot, bool write, cx<T> jti, cx<T> jti1,
+                                           cx<T>* ring = nullptr) {
     cx<T> ja = jti + c.wp2h * (T(0.5) * (W.tpa[slot] + W.tma[slot]));
     cx<T> jb = jti1 + c.wp2h * (T(0.5) * (B.tpb[slot] + B.tmb[slot]));
     if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
-    if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
+    if constexpr (IO == IO_RING) {
+        if (write) *rg(ring, RG_JT, row, c.lane) = ja;
+    } else {
+        if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
+    }
     if (c.x.i1 < 0) jb = zero<T>();
     return T(0.5) * (ja + jb);
 }
 
 // one march step of the electromagnetic set: outputs E_x(J=j+1), B_x(K=j)
 // (and the exterior ghost at j = nr-1), T_r(K=j), T_theta(J=j)
-template <typename T>
+template <typename T, int IO = IO_GLOBAL>
 __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, const EmB<T>& B, int j,
-                                        int r0, int r1, const RowInv<T>& ri, const EmRowX<T>& X) {
+                                        int r0, int r1, const RowInv<T>& ri, const EmRowX<T>& X,
+                                        cx<T>* ring = nullptr) {
+    constexpr bool RING = IO == IO_RING;
     const Geo& g = c.g;
     const int m = c.m;
     const T h = c.h;
@@ -335,9 +427,13 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     const bool wI = c.owner && ocI >= 0;
     // ---- E_x^{n+1/2} at J = j+1
     if (j + 1 <= g.nr) {
-        W.jx_n1 = em_jx(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa);
+        W.jx_n1 = em_jx<T, IO>(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa, ring);
         W.ex1[2] = em_ex_new(c, W, B, j + 1, W.jx_n1, ri.irJ1);
-        if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
+        if constexpr (RING) {
+            if (j + 1 >= r0 && j + 1 < r1) *rg(ring, RG_EX, j + 1, c.lane) = W.ex1[2];
+        } else {
+            if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
+        }
         if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
     }
     if (j < 0) return;
@@ -345,7 +441,11 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     // ---- B_x^{n+1/2} at K = j
     if (j < g.nr) {
         W.bx1[1] = em_bx_new(c, W, B, ri.irK);
-        if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
+        if constexpr (RING) {
+            if (own_row) *rg(ring, RG_BX, j, c.lane) = W.bx1[1];
+        } else {
+            if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
+        }
     }
     // ---- exterior ghost B_x^{n+1/2} at r_{nr+1/2} (Eq. em_r_open_bx)
     if (j == g.nr - 1) {
@@ -359,13 +459,28 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
             cx<T> ra = T(0.25) * ((W.rpa[0] + W.rma[0]) + (B.rpb[0] + B.rmb[0]));
             rx = rx - (T(0.5) * ri.irJ1) * (ea + imul(T(m), ra));
             cx<T> jt = zero<T>();
-            if (c.plasma) jt = em_jt_avg(c, s, W, B, N, 1, false, c.x.L(s.jt, m, N), c.x.R(s.jt, m, N));
+            if (c.plasma) {
+                cx<T> jti, jti1;
+                if constexpr (IO == IO_FROM_RING) {
+                    // the first step's j_theta at row nr, columns i and i+1
+                    jti = *rg(ring, RG_JT, N, c.lane);
+                    jti1 = c.x.i1 >= 0 ? *rg(ring, RG_JT, N, min(c.lane + 1, WAVE - 1)) : zero<T>();
+                } else {
+                    jti = c.x.L(s.jt, m, N);
+                    jti1 = c.x.R(s.jt, m, N);
+                }
+                jt = em_jt_avg(c, s, W, B, N, 1, false, jti, jti1);
+            }
             if (s.jta) jt = jt + c.x.L(s.jta, m, N);
             rx = rx - T(0.5) * jt;
             gh = W.bx0[0] + kap * (W.bx0[1] - W.bx1[1]) + cR * rx;
         }
         W.bx1g = gh;
-        if (r1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
+        if constexpr (RING) {
+            if (r1 == g.nr + 1) *rg(ring, RG_BX, g.nr, c.lane) = gh;
+        } else {
+            if (r1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
+        }
     }
     // ---- T_r transport on K = j
     if (j < g.nr) {
@@ -374,7 +489,11 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         const cx<T> jr1 = c.plasma ? c.x.Rn(X.jr) : zero<T>();   // uniform control flow here
         if (c.plasma) {
             jra = X.jr + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
-            if (own_row && wI) sto(s.ojr, eoff<T>(g, m, j, ocI), jra);
+            if constexpr (RING) {
+                if (own_row) *rg(ring, RG_JR, j, c.lane) = jra;
+            } else {
+                if (own_row && wI) sto(s.ojr, eoff<T>(g, m, j, ocI), jra);
+            }
         }
         if (c.live) {
             cx<T> jr = zero<T>();
@@ -395,7 +514,13 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         cx<T> from_right = shfl_dn1(W.n_rma);
         W.n_rpa = (c.i == 0 && !g.per) ? zero<T>() : from_left;
         W.n_rmb = (c.x.i1 >= 0) ? from_right : zero<T>();
-        if (own_row) {
+        if constexpr (RING) {
+            // the lane's own column: T_r^+ came from the left neighbour
+            if (own_row) {
+                *rg(ring, RG_TRP, j, c.lane) = W.n_rpa;
+                *rg(ring, RG_TRM, j, c.lane) = W.n_rma;
+            }
+        } else if (own_row) {
             if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_rpb);
             if (wI) sto(s.otrm, eoff<T>(g, m, j, ocI), W.n_rma);
             if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
@@ -406,7 +531,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         const bool zrow = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
         cx<T> jt = zero<T>();
         const cx<T> jt1 = c.plasma ? c.x.Rn(X.jt) : zero<T>();   // uniform control flow here
-        if (c.plasma) jt = em_jt_avg(c, s, W, B, j, 0, own_row, X.jt, jt1);
+        if (c.plasma) jt = em_jt_avg<T, IO>(c, s, W, B, j, 0, own_row, X.jt, jt1, ring);
         if (s.jta && c.live) jt = jt + X.jta;
         cx<T> sp = zero<T>(), sm = zero<T>();
         if (c.live && !zrow) {
@@ -433,7 +558,12 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         cx<T> from_left = shfl_up1(W.n_tmb);
         W.n_tpb = (c.x.i1 >= 0) ? from_right : zero<T>();
         W.n_tma = (c.i == 0 && !g.per) ? zero<T>() : from_left;
-        if (own_row) {
+        if constexpr (RING) {
+            if (own_row) {
+                *rg(ring, RG_TTP, j, c.lane) = W.n_tpa;
+                *rg(ring, RG_TTM, j, c.lane) = W.n_tma;
+            }
+        } else if (own_row) {
             if (wI) sto(s.ottp, eoff<T>(g, m, j, ocI), W.n_tpa);
             if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_tmb);
             if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
@@ -442,9 +572,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
 }
 
 // exterior ghost B_theta at r_{nr+1/2} (Eq. em_r_open_bt), at j = nr - 1 after em_step
-template <typename T>
+template <typename T, int IO = IO_GLOBAL>
 __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, const EmWin<T>& W, const EmB<T>& B,
-                                             int r1) {
+                                             int r1, cx<T>* ring = nullptr) {
     const Geo& g = c.g;
     const int m = c.m, N = g.nr;
     const T dr = c.dr;
@@ -466,10 +596,15 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
         cx<T> rt = -T(0.5) * dxer - (T(1) / (T(2) * rN)) * (T(0.5) * (I0 + G0) + imul(T(m), br)) + T(0.5) * jxi;
         out = I0 + kap * (G0 - I1) + cR * rt;
     }
-    const int oc = c.o.col(c.i);
-    if (c.owner && oc >= 0 && r1 == g.nr + 1) {
-        sto(s.otrp, eoff<T>(g, m, N, oc), out);
-        sto(s.otrm, eoff<T>(g, m, N, oc), zero<T>());
+    if constexpr (IO == IO_RING) {
+        // the second step reads the ghost row through T_r^+ alone
+        if (r1 == g.nr + 1) *rg(ring, RG_TRP, N, c.lane) = out;
+    } else {
+        const int oc = c.o.col(c.i);
+        if (c.owner && oc >= 0 && r1 == g.nr + 1) {
+            sto(s.otrp, eoff<T>(g, m, N, oc), out);
+            sto(s.otrm, eoff<T>(g, m, N, oc), zero<T>());
+        }
     }
 }
 
@@ -486,18 +621,21 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
 // Per-lane context of a marching wave of mode m over one strip: column of
 // the lane (halo lanes wrap with periodic x; otherwise they are clamped, and
 // their results only reach owned lanes through terms the x boundary zeroes),
-// ownership and the step's constants.
-template <typename T>
+// ownership and the step's constants.  A strip owns OWNC columns after LH
+// left-halo lanes (the one-step marches: 61 after 1; the two-step march,
+// whose second step needs the first step's results one lane further out on
+// each side: 58 after 2).
+template <typename T, int OWNC = OWN, int LH = 1>
 __device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int m, int lane) {
     const Geo& g = a.g;
     Ctx<T> c;
     c.g = g;
     c.m = m;
     c.lane = lane;
-    const int raw = strip * OWN - 1 + lane;
+    const int raw = strip * OWNC - LH + lane;
     const bool inrange = raw >= 0 && raw < g.nx;
     c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
-    c.owner = inrange && lane >= 1 && lane <= OWN;
+    c.owner = inrange && lane >= LH && lane < LH + OWNC;
     c.live = g.per || c.i < g.nx - 1;
     c.x.nr1 = g.nr + 1;
     c.x.ld = g.ld;
@@ -1009,6 +1147,96 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
 }
 
 // ---------------------------------------------------------------------------
+// two steps of one set in one pass (temporal blocking): a workgroup of two
+// waves over one (strip, chunk, mode).  Wave 0 marches the first step as the
+// one-step march does, over the rows [p0, p1) that the second step reads, and
+// puts its results in an LDS ring of 4 rows instead of the state planes; wave
+// 1 marches the second step two rows behind, reading the first step's results
+// from the ring (and the second step's extra current from its plane), and
+// stores the rows [r0, r1) of its 58 owned columns.  One barrier per row: at
+// tick t wave 0 writes rows t and t+1, wave 1 reads rows t-2 and t-1, and the
+// barrier ends the tick, so every value wave 1 reads was written a tick before
+// and no slot is rewritten while it is read.  The set's planes are read and
+// written once per two steps; the arithmetic of each step is that of
+// em_step, in the same order, so the result equals two one-step marches.
+// ---------------------------------------------------------------------------
+template <typename T, int WHICH>
+__device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int chunk, int m, int rows) {
+    const Geo g = a.g;
+    // 0: first step, 1: second step (wave-uniform, so each wave takes one
+    // loop on a scalar branch and meets exactly that loop's barriers)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
+    const Ctx<T> c = make_ctx<T, kPairOwn, 2>(a, strip, m, lane);
+    const SetP<T>& s = WHICH ? a.s1 : a.s0;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cx<T>* const ring = reinterpret_cast<cx<T>*>(smem_raw);
+    // the second step's iterations, as in em_body
+    const int jsc = max(r0 - (r1 == g.nr + 1 ? 2 : 1), -1);
+    const int jec = r1 == g.nr + 1 ? g.nr : r1 - 1;
+    // the first step owns the rows the second reads, [p0, p1)
+    const int p0 = max(jsc, 0);
+    const int p1 = min(jec + 2, g.nr + 1);
+    const int jsp = max(p0 - (p1 == g.nr + 1 ? 2 : 1), -1);
+    const int jep = p1 == g.nr + 1 ? g.nr : p1 - 1;
+    EmWin<T> W;
+    for (int q = 0; q < 2; ++q) {
+        W.rpa[q] = W.rma[q] = zero<T>();
+        W.tpa[q] = W.tma[q] = zero<T>();
+        W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
+    }
+    W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
+    W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
+    W.pjx = W.pjxa = zero<T>();
+    // both loops run the ticks jsp .. jec + 2, one barrier each
+    if (wave == 0) {
+        if (jsp >= 0) em_take(c, W, em_fetch(c, s, jsp), jsp, g.nr);
+        EmPf<T> pf = em_fetch(c, s, jsp + 1);
+        for (int t = jsp; t <= jec + 2; ++t) {
+            if (t <= jep) {
+                em_rotate(W);
+                em_take(c, W, pf, t + 1, g.nr);
+                if (t < jep) pf = em_fetch(c, s, t + 2);
+                const EmRowX<T> X = em_fetch_x(c, s, t);
+                const EmB<T> B = em_bvals(c, W);
+                em_step<T, IO_RING>(c, s, W, B, t, p0, p1, row_inv(c, t), X, ring);
+                if (t == g.nr - 1) em_ghost_bth<T, IO_RING>(c, s, W, B, p1, ring);
+            }
+            __syncthreads();
+        }
+    } else {
+        // the second step's extra currents are those of the following step
+        SetP<T> s2 = s;
+        s2.jxa = s.jxb; s2.jra = s.jrb; s2.jta = s.jtb;
+        // its loads from the current planes run one iteration ahead: j_x of
+        // row j+1 and j_r, j_theta of row j are in flight since iteration j-1
+        cx<T> xa_pre = em_xa(c, s2, jsc);
+        cx<T> xa_nxt = em_xa(c, s2, jsc + 1);
+        EmRowX<T> xrt = em_xrt(c, s2, jsc);
+        for (int t = jsp; t <= jec + 2; ++t) {
+            const int j = t - 2;
+            if (j == jsc - 1) {
+                if (jsc >= 0) em_take(c, W, em_fetch_ring(c, ring, jsc, xa_pre), jsc, g.nr);
+            } else if (j >= jsc && j <= jec) {
+                em_rotate(W);
+                em_take(c, W, em_fetch_ring(c, ring, j + 1, xa_nxt), j + 1, g.nr);
+                const EmRowX<T> X = em_fetch_x_ring(c, ring, j, xrt);
+                if (j < jec) {
+                    xa_nxt = em_xa(c, s2, j + 2);
+                    xrt = em_xrt(c, s2, j + 1);
+                }
+                const EmB<T> B = em_bvals(c, W);
+                em_step<T, IO_FROM_RING>(c, s2, W, B, j, r0, r1, row_inv(c, j), X, ring);
+                if (j == g.nr - 1) em_ghost_bth<T, IO_FROM_RING>(c, s2, W, B, r1, ring);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batched launches: block -> (instance, tile) through the launch's list; the
 // instance's arguments are read from a device table
 // ---------------------------------------------------------------------------
@@ -1059,6 +1287,18 @@ __global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restric
     const int m = local % a.g.M;                 // the modes of one tile run side by side
     const int t = local / a.g.M;
     em_body<T, WHICH>(a, t / chunks, t % chunks, m, L.rows);
+}
+
+template <typename T, int WHICH>
+__global__ void __launch_bounds__(2 * WAVE) k_batch_em2(const FusedArgs<T>* __restrict__ args, BatchList L) {
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = batch_find(L, b);
+    const FusedArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
+    const int m = local % a.g.M;                 // the modes of one tile run side by side
+    const int t = local / a.g.M;
+    em2_body<T, WHICH>(a, t / chunks, t % chunks, m, L.rows);
 }
 
 }  // namespace fused
@@ -1137,12 +1377,25 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = size_t(fused::RG_N) * fused::RING_ROWS * fused::WAVE * sizeof(cx<T>);
+    if (which)
+        hipLaunchKernelGGL((fused::k_batch_em2<T, 1>), dim3(blocks), dim3(2 * fused::WAVE), lds, s, args, L);
+    else
+        hipLaunchKernelGGL((fused::k_batch_em2<T, 0>), dim3(blocks), dim3(2 * fused::WAVE), lds, s, args, L);
+    return hipGetLastError();
+}
+
 template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_ax<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_ax<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_em2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_em2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);
 template hipError_t drive_plane<float>(const Drive&, const Geo&, cx<float>*, int64_t, int64_t, hipStream_t);
 

@@ -95,6 +95,7 @@ struct StepPlan {
     cx<T>* A[21];
     cx<T>* B[21];
     cx<T>* ja[3];
+    cx<T>* ja2[3];              // j_a of the second step of a pair of steps (null until used)
     cx<T>* sa;                  // scratch S_a plane (regenerated set only)
     cx<T>* jdrv;                // drive plane (j_x^(0) of mode 0; null until first used)
     int plasma, axion, arem;
@@ -154,6 +155,9 @@ struct SetP {
     cx<T>* otrp; cx<T>* otrm; cx<T>* ottp; cx<T>* ottm;
     cx<T>* oex; cx<T>* obx; cx<T>* ojx; cx<T>* ojr; cx<T>* ojt;
     const cx<T>* jxa; const cx<T>* jra; const cx<T>* jta;
+    // the extra currents of the following step, read by the second step of
+    // the two-step march (the axion current of that step; null when absent)
+    const cx<T>* jxb; const cx<T>* jrb; const cx<T>* jtb;
     int jxa_m0;   // jxa holds mode 0 only (the prescribed drive); other modes add nothing
 };
 
@@ -177,6 +181,10 @@ struct FusedArgs {
 // left halo, lanes 62 and 63 the right halo (lane 63 only lends its column).
 constexpr int kFusedOwn = 61;
 __host__ __device__ inline int fused_strips(int nx) { return (nx + kFusedOwn - 1) / kFusedOwn; }
+// The two-step march of one set: its second step needs the first step's
+// results on lanes k-1 .. k+2, so a strip owns 58 columns (lanes 2-59).
+constexpr int kPairOwn = 58;
+__host__ __device__ inline int pair_strips(int nx) { return (nx + kPairOwn - 1) / kPairOwn; }
 
 // One launch of a batched kernel: the instances it covers (indices into the
 // argument tables), the first block of each (n + 1 entries, first[0] = 0, the
@@ -228,6 +236,12 @@ template <typename T>
 hipError_t batch_a(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, bool axt, hipStream_t s);
 template <typename T>
 hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
+// Two steps of one set in one pass (set 1 with the axion currents s1.jxa/jra/jta
+// of the first step and s1.jxb/jrb/jtb of the second; set 0 without an axion):
+// reads the set from the A planes and writes it, two steps on, to the B planes.
+// Tiles of pair_strips(nx) strips x rows-high chunks x modes, 128 threads each.
+template <typename T>
+hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
 // Kernel AX: the background set, the axion source, the axion advance and the
 // axion current in one launch (every instance of the list has sa set).
 template <typename T>

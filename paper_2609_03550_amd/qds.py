@@ -33,6 +33,7 @@ OPT_ROWS_A, OPT_ROWS_CUR, OPT_ROWS_B = 5, 6, 7       # one kernel's tile height
 OPT_PRODUCTS = 8
 OPT_OVERLAP = 9
 OPT_KERNEL_AX = 10
+OPT_PAIR, OPT_ROWS_PAIR = 11, 12                     # two steps per launch of the set's march
 PRODUCTS_DIRECT, PRODUCTS_THETA = 0, 1
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 
@@ -215,9 +216,9 @@ class Solver:
         return bool(lib().qds_uses_fused(self.h))
 
     def tiles(self):
-        """Tile heights (rows per workgroup) of kernel A, the axion current and
-        kernel B, and whether the autotuner chose them."""
-        t = (ctypes.c_int32 * 3)()
+        """Tile heights (rows per workgroup) of kernel A, the axion current,
+        kernel B and the two-step march, and whether the autotuner chose them."""
+        t = (ctypes.c_int32 * 4)()
         tuned = ctypes.c_int32()
         _check(lib().qds_get_tiles(self.h, t, ctypes.byref(tuned)), self.h)
         return list(t), bool(tuned.value)

@@ -1,0 +1,134 @@
+"""The two-step march (QDS_OPT_PAIR): one launch advances a set through two
+steps, the first step's rows handed to the second through an LDS ring.  Each
+step's arithmetic is the one-step march's, so a paired run must equal single
+steps bit for bit: the regenerated set with the axion (kernel A and the axion
+kernel writing the pair buffer in between), and the background set alone, at
+tile heights from one row up (the two-row lag, the ghost chunk, ragged last
+chunks), odd step counts (a single step after the pairs), 58-column strips
+over widths that leave ragged strips, periodic and open x, conducting and open
+outer walls; and against the oracle per field."""
+import pytest
+import torch
+
+from paper_2609_03550_amd import inputs as I
+import parity_tools as P
+from test_gpu_parity import _full, _random_reachable_state
+
+
+def _random_state_no_plasma(wl, seed):
+    """As _random_reachable_state, for a set without the plasma: its state
+    has no current planes, so the oracle's (which it would keep as fixed
+    sources) start at zero."""
+    from oracle import qds as Q
+    g, ph = Q.grid_physics(wl)
+    st = Q.init_state(wl)
+    gen = torch.Generator().manual_seed(seed)
+    for k, v in st.items():
+        if isinstance(v, torch.Tensor) and v.is_complex():
+            st[k] = torch.zeros_like(v) if k[0] == "j" else torch.randn(v.shape, dtype=torch.complex128, generator=gen)
+    return Q.step(st, g, ph), g, ph
+
+pytestmark = pytest.mark.gpu
+H = I.H
+
+
+def _em(nx, nr, M, **kw):
+    p = I.Pulse("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 0.4 * nx * H)
+    return I.Workload("em", nx, nr, M, 0, wp2=0.02, pulses=(p,)).with_(**kw)
+
+
+def _run(wl, dtype, st, nsteps, pair, rows, tune=False):
+    from paper_2609_03550_amd import qds
+    s = qds.Solver(wl, dtype=dtype)
+    s.set_option(qds.OPT_PAIR, pair)
+    s.set_option(qds.OPT_ROWS, rows)
+    if tune:
+        s.set_option(qds.OPT_TUNE, 1)
+    s.load_fields(st)
+    assert s.fused
+    s.step(nsteps)
+    torch.cuda.synchronize()
+    return s
+
+
+def _equal(a, b):
+    fa, fb = a.fields(), b.fields()
+    assert (a.n, a.window) == (b.n, b.window)
+    bad = {}
+    for k in fa:
+        if not torch.equal(fa[k], fb[k]):
+            d = (fa[k] - fb[k]).abs().max().item()
+            bad[k] = (d, fa[k].abs().max().item())
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows,nx", [
+    ("f64", 3, "open", "open", 1, 190), ("f64", 3, "open", "open", 2, 190), ("f64", 3, "open", "open", 5, 190),
+    ("f64", 3, "periodic", "pec", 3, 175), ("f64", 3, "open", "pec", 24, 117), ("f64", 1, "open", "open", 4, 59),
+    ("f64", 2, "periodic", "open", 7, 58), ("f64", 4, "open", "open", 6, 240), ("f64", 6, "open", "open", 5, 131),
+    ("f32", 3, "open", "open", 4, 190), ("f32", 2, "open", "pec", 1, 100), ("f32", 4, "periodic", "pec", 9, 121)])
+def test_pair_with_regenerated_set_equals_single_steps(dtype, M, x_bc, r_bc, rows, nx):
+    from oracle import qds as Q
+    kw = dict(x_bc=x_bc, r_bc=r_bc)
+    if M > 4:
+        kw["dr"] = M * H
+    wl = _full(nx, 23, M, **kw)
+    st, g, ph = _random_reachable_state(wl, 70 + rows + M)
+    a = _run(wl, dtype, st, 7, 1, rows)
+    b = _run(wl, dtype, st, 7, 0, rows)
+    _equal(a, b)
+    if dtype == "f64" and M == 3:
+        ref = Q.run(st, g, ph, 7)
+        P.compare_states(a.fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
+
+
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows,nx,wp2", [
+    ("f64", 3, "open", "open", 1, 190, 0.02), ("f64", 3, "open", "open", 3, 190, 0.0),
+    ("f64", 3, "periodic", "pec", 4, 175, 0.02), ("f64", 2, "open", "pec", 26, 117, 0.0),
+    ("f64", 1, "periodic", "open", 2, 61, 0.02), ("f64", 8, "open", "pec", 5, 131, 0.02),
+    ("f32", 3, "open", "open", 6, 190, 0.02), ("f32", 4, "periodic", "open", 2, 130, 0.0)])
+def test_pair_background_set_alone_equals_single_steps(dtype, M, x_bc, r_bc, rows, nx, wp2):
+    """With and without the cold plasma (whose currents the ring carries)."""
+    from oracle import qds as Q
+    kw = dict(x_bc=x_bc, r_bc=r_bc, wp2=wp2)
+    if M > 4:
+        kw["dr"] = M * H
+    wl = _em(nx, 19, M, **kw)
+    st, g, ph = (_random_reachable_state if wp2 else _random_state_no_plasma)(wl, 90 + rows + M)
+    a = _run(wl, dtype, st, 9, 1, rows)
+    b = _run(wl, dtype, st, 9, 0, rows)
+    _equal(a, b)
+    if dtype == "f64":
+        ref = Q.run(st, g, ph, 9)
+        P.compare_states(a.fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
+
+
+@pytest.mark.parametrize("arem", [True, False])
+def test_pair_autotuner_trials_change_nothing(arem):
+    """The tuner times its first 8 pairs over four heights of each kernel
+    (the two-step march in place of kernel B): 21 tuned paired steps equal
+    21 single steps at fixed heights."""
+    wl = _full(190, 23, 3) if arem else _em(190, 23, 3)
+    st, _, _ = _random_reachable_state(wl, 5)
+    a = _run(wl, "f64", st, 21, 1, 8, tune=True)
+    assert a.tiles()[1]
+    b = _run(wl, "f64", st, 21, 0, 8)
+    _equal(a, b)
+
+
+def test_pair_calls_in_a_row_and_uneven_counts():
+    """Calls of 1, 2, 3, 4 and 6 steps in a row (the pair buffer allocated on
+    the first call that pairs, the table rebuilt for it) equal one call of 16
+    single steps; the state's buffer index follows the pairs."""
+    from paper_2609_03550_amd import qds
+    wl = _full(150, 21, 3)
+    st, _, _ = _random_reachable_state(wl, 11)
+    a = qds.Solver(wl, dtype="f64")
+    a.set_option(qds.OPT_PAIR, 1)
+    a.set_option(qds.OPT_ROWS, 6)
+    a.load_fields(st)
+    for n in (1, 2, 3, 4, 6):
+        a.step(n)
+    torch.cuda.synchronize()
+    b = _run(wl, "f64", st, 16, 0, 6)
+    _equal(a, b)

@@ -165,23 +165,33 @@ def test_fused_matches_staged_on_a_long_run():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_autotuned_tiles_change_no_result(dtype):
-    """qds_step with the autotuner on: its 8 trial steps (four tile heights,
-    twice) and the chosen tiles give bit-identical states to the default
-    tiling, and the chosen heights are candidates."""
+@pytest.mark.parametrize("pair", [0, 1])
+def test_autotuned_tiles_change_no_result(dtype, pair):
+    """qds_step with the autotuner on: its 8 trials (four tile heights, twice;
+    single steps, or pairs of steps with the two-step march of the
+    regenerated set in place of kernel B) and the chosen tiles give
+    bit-identical states to the default tiling, and the chosen heights are
+    candidates (for the two-step march: 16 rows and the heights that cut the
+    21 rows into 5, 3 and 2 chunks)."""
     from paper_2609_03550_amd import qds
     wl = _full(70, 20, 3)
     a = qds.Solver(wl, dtype=dtype)
     a.load_pulses()
     b = qds.Solver(wl, dtype=dtype)
     b.load_pulses()
+    for s in (a, b):
+        s.set_option(qds.OPT_PAIR, pair)
     b.set_option(qds.OPT_TUNE, 1)
-    a.step(12)
-    b.step(12)
+    a.step(18)
+    b.step(18)
     torch.cuda.synchronize()
     rows, tuned = b.tiles()
-    assert tuned and rows[0] in (8, 16, 24, 32) and rows[1] in (4, 6, 8, 16) and rows[2] in (16, 32, 52, 64)
-    assert a.tiles() == ([16, 16, 16], False)
+    assert tuned and rows[0] in (8, 16, 24, 32) and rows[1] in (4, 6, 8, 16)
+    if pair:
+        assert rows[2] == 16 and rows[3] in (16, 5, 7, 11)
+    else:
+        assert rows[2] in (16, 32, 52, 64) and rows[3] == 11
+    assert a.tiles() == ([16, 16, 16, 11], False)
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
@@ -232,18 +242,19 @@ def test_overlapped_steps_change_no_result(dtype, M, x_bc, r_bc):
 
 
 def test_per_kernel_tile_heights_change_no_result():
-    """QDS_OPT_ROWS_A / _CUR / _B set one kernel's tile height each (used to
-    replay the autotuner's choice): uneven heights that leave ragged last
-    chunks give bit-identical states; out-of-range heights are rejected."""
+    """QDS_OPT_ROWS_A / _CUR / _B / _PAIR set one kernel's tile height each
+    (used to replay the autotuner's choice): uneven heights that leave ragged
+    last chunks give bit-identical states (9 steps: four pairs, then a single
+    step with kernel B); out-of-range heights are rejected."""
     from paper_2609_03550_amd import qds
     wl = _full(131, 21, 3)
     a = qds.Solver(wl, dtype="f64")
     a.load_pulses()
     b = qds.Solver(wl, dtype="f64")
     b.load_pulses()
-    for opt, v in ((qds.OPT_ROWS_A, 5), (qds.OPT_ROWS_CUR, 3), (qds.OPT_ROWS_B, 13)):
+    for opt, v in ((qds.OPT_ROWS_A, 5), (qds.OPT_ROWS_CUR, 3), (qds.OPT_ROWS_B, 13), (qds.OPT_ROWS_PAIR, 7)):
         b.set_option(opt, v)
-    assert b.tiles() == ([5, 3, 13], False)
+    assert b.tiles() == ([5, 3, 13, 7], False)
     a.step(9)
     b.step(9)
     torch.cuda.synchronize()
@@ -251,7 +262,9 @@ def test_per_kernel_tile_heights_change_no_result():
     for bad in (0, 4097):
         with pytest.raises(qds.QDSError):
             b.set_option(qds.OPT_ROWS_CUR, bad)
-    assert b.tiles() == ([5, 3, 13], False)
+        with pytest.raises(qds.QDSError):
+            b.set_option(qds.OPT_ROWS_PAIR, bad)
+    assert b.tiles() == ([5, 3, 13, 7], False)
 
 
 @pytest.mark.parametrize("dtype,x_bc,r_bc,arem,M", [("f64", "open", "open", True, 3), ("f64", "periodic", "pec", True, 3),
