@@ -190,7 +190,7 @@ def batched_leg(step_scale, graph_steps, count=64):
         bs.append(s)
     updates = sum(wl.cell_modes * n for wl, n in zip(wls, steps))
     b = qds.Batch(bs)
-    b.run(8, graph_steps=graph_steps, tune=True)       # the autotuner's trial steps
+    b.run(TUNE_STEPS, graph_steps=graph_steps, tune=True)   # the autotuner's trial steps (pairs)
     b.run(steps, graph_steps=graph_steps)              # capture pass
     torch.cuda.synchronize()
     s0 = b.stats()

@@ -383,8 +383,13 @@ qds_status qds_destroy(qds_handle h);
  * launch per kernel class covering the tiles of all instances still running
  * (kernel A per mode count, the axion current per mode count, the
  * regenerated set), and up to graph_steps such steps are captured in one HIP
- * graph and launched as one.  The per-step update of each instance is
- * exactly that of qds_step on the fused kernels (Sec. 2 scheme per instance).
+ * graph and launched as one.  When every instance has the regenerated set or
+ * no axion at all (and QDS_OPT_PAIR is on for every handle), the steps run in
+ * pairs as under qds_step: kernel A and the axion current twice (through each
+ * handle's pair buffer), then the two-step march of each set, one launch per
+ * class; an odd last step of a segment is a single step.  The update of each
+ * instance is exactly that of qds_step on the fused kernels (Sec. 2 scheme
+ * per instance), bit for bit.
  * --------------------------------------------------------------------------- */
 typedef struct qds_batch_ctx* qds_batch;
 
@@ -394,7 +399,9 @@ enum {
     QDS_TILE_CUR1 = 4,      /* axion current, 1..4 modes: slots 4..7 (rows per workgroup) */
     QDS_TILE_EM0 = 8,       /* background set without the axion */
     QDS_TILE_EM1 = 9,       /* regenerated set (kernel B) */
-    QDS_NTILES = 10
+    QDS_TILE_PAIR0 = 10,    /* two-step march of the background set without the axion */
+    QDS_TILE_PAIR1 = 11,    /* two-step march of the regenerated set */
+    QDS_NTILES = 12
 };
 
 /* Groups ``count`` handles (1..4096, all distinct, one dtype, each able to
@@ -414,9 +421,10 @@ qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch*
  * launches it once (kept for replay while the tables, the tiles and the step
  * counts are the same).  With
  * tune != 0 and no tiles chosen yet, the autotuner times the first steps of
- * the run (two passes over the candidate tilings, 8 steps; only when every
- * running instance has that many steps left): each trial is an ordinary step
- * of the run, and the tiling does not change any result.  Asynchronous on
+ * the run (two passes over the candidate tilings, 8 steps, or 8 pairs of
+ * steps when the batch runs in pairs; only when every running instance has
+ * that many steps left): each trial is an ordinary step (or pair) of the run,
+ * and the tiling does not change any result.  Asynchronous on
  * ``stream``.  Graphs stay with the batch across calls and are replayed
  * whenever a call repeats a running set (or, with -1, a whole schedule) with
  * the same tiles: the argument table they read is rewritten in place, after

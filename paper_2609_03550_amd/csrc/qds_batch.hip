@@ -1,7 +1,8 @@
 // Batched forward over many independent instances (qds_batch_* of
-// include/qds.h): per step, one launch per kernel class covering the tiles of
-// every running instance, several steps captured in one HIP graph, and an
-// autotuner that picks each class's tile height from timed steps of the run.
+// include/qds.h): per step (or pair of steps), one launch per kernel class
+// covering the tiles of every running instance, several steps captured in one
+// HIP graph, and an autotuner that picks each class's tile height from timed
+// steps of the run.
 #include <string.h>
 
 #include <algorithm>
@@ -26,10 +27,13 @@ struct Launch {
 };
 
 // Launch sequence of one set of running instances, with its device lists and
-// the graphs captured for it: key (steps, parity of the first step).
+// the graphs captured for it: key (steps, parity of the buffers at the first
+// step).  With pairs, the lists also hold the two-step marches (slots
+// QDS_TILE_PAIR0/1), which only pair units launch.
 struct Plan {
     std::vector<int> active;
     std::vector<int> tiles;
+    bool pairs = false;
     std::vector<int> host;
     void* dev = nullptr;
     std::vector<Launch> launches;
@@ -39,6 +43,7 @@ struct Plan {
 const int kCandA[4] = {8, 16, 24, 32};       // kernel A
 const int kCandCur[4] = {4, 6, 8, 16};       // axion current
 const int kCandEm[4] = {8, 16, 32, 52};      // the electromagnetic sets alone (kernel B)
+const int kCandPair[4] = {16, 32, 52, 86};   // the two-step marches
 constexpr int kTunePasses = 2;
 
 }  // namespace
@@ -48,6 +53,7 @@ struct qds_batch_ctx {
     int dtype = QDS_F64;
     int tiles[QDS_NTILES];
     int tuned = 0;
+    int pairs = 0;                      // this run advances in pairs of steps
     hipStream_t cap = nullptr;          // capture stream (never executes work)
     void* args = nullptr;               // per-run argument tables
     size_t args_cap = 0;
@@ -100,6 +106,7 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
     if (!P) return bfail(b, QDS_ENOMEM, "out of host memory%s");
     P->active = active;
     P->tiles.assign(b->tiles, b->tiles + QDS_NTILES);
+    P->pairs = b->pairs != 0;
     struct Pending { int slot, M; bool axt; std::vector<int> idx, first; };
     std::vector<Pending> pend;
     auto add = [&](int slot, int M, auto pick, auto blocks_of, bool axt = true) {
@@ -137,6 +144,13 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
         const int rows = b->tiles[QDS_TILE_EM1];
         add(QDS_TILE_EM1, 0, has_arem,
             [&](const qds_ctx* c) { return qds::fused_strips(c->g.nx) * chunks(c->g.nr, rows) * c->M; });
+    }
+    if (b->pairs) {
+        const int r0 = b->tiles[QDS_TILE_PAIR0], r1 = b->tiles[QDS_TILE_PAIR1];
+        add(QDS_TILE_PAIR0, 0, [&](const qds_ctx* c) { return !has_ax(c); },
+            [&](const qds_ctx* c) { return qds::pair_strips(c->g.nx) * chunks(c->g.nr, r0) * c->M; });
+        add(QDS_TILE_PAIR1, 0, has_arem,
+            [&](const qds_ctx* c) { return qds::pair_strips(c->g.nx) * chunks(c->g.nr, r1) * c->M; });
     }
     size_t total = 0;
     for (const Pending& q : pend) {
@@ -183,15 +197,56 @@ qds_status build_plan(qds_batch_ctx* b, const std::vector<int>& active, hipStrea
     return QDS_OK;
 }
 
+// Argument tables of a run (device, one allocation): fa[2][N] and xa[2][N]
+// for single steps from buffer (cur + parity) % 2; with pairs then fp[2][2][N]
+// and xp[2][2][N], the pair's first half (into the pair buffer) and second
+// half (from it) for each parity.
+template <typename T>
+const qds::FusedArgs<T>* tab_fa(const qds_batch_ctx* b, int parity) {
+    return static_cast<const qds::FusedArgs<T>*>(b->args) + size_t(parity) * b->inst.size();
+}
+template <typename T>
+const qds::AxionArgs<T>* tab_xa(const qds_batch_ctx* b, int parity) {
+    const size_t N = b->inst.size();
+    return reinterpret_cast<const qds::AxionArgs<T>*>(static_cast<const char*>(b->args) +
+                                                      2 * N * sizeof(qds::FusedArgs<T>)) +
+           size_t(parity) * N;
+}
+template <typename T>
+const qds::FusedArgs<T>* tab_fp(const qds_batch_ctx* b, int parity, int half) {
+    const size_t N = b->inst.size();
+    return reinterpret_cast<const qds::FusedArgs<T>*>(static_cast<const char*>(b->args) +
+                                                      2 * N * (sizeof(qds::FusedArgs<T>) + sizeof(qds::AxionArgs<T>))) +
+           size_t(2 * parity + half) * N;
+}
+template <typename T>
+const qds::AxionArgs<T>* tab_xp(const qds_batch_ctx* b, int parity, int half) {
+    const size_t N = b->inst.size();
+    return reinterpret_cast<const qds::AxionArgs<T>*>(static_cast<const char*>(b->args) +
+                                                      6 * N * sizeof(qds::FusedArgs<T>) +
+                                                      2 * N * sizeof(qds::AxionArgs<T>)) +
+           size_t(2 * parity + half) * N;
+}
+
+// Kernel launches of one single step and of one pair of steps of a plan.
+size_t step_launches(const Plan& P) {
+    size_t n = 0;
+    for (const Launch& l : P.launches) n += l.slot < QDS_TILE_PAIR0;
+    return n;
+}
+size_t pair_launches(const Plan& P) {
+    size_t n = 0;
+    for (const Launch& l : P.launches) n += l.slot < QDS_TILE_EM0 ? 2 : (l.slot >= QDS_TILE_PAIR0 ? 1 : 0);
+    return n;
+}
+
 template <typename T>
 hipError_t launch_step(const qds_batch_ctx* b, const Plan& P, int parity, hipStream_t s, hipEvent_t* ev) {
-    const size_t N = b->inst.size();
-    const auto* fa = static_cast<const qds::FusedArgs<T>*>(b->args) + size_t(parity) * N;
-    const auto* xa = reinterpret_cast<const qds::AxionArgs<T>*>(static_cast<const char*>(b->args) +
-                                                                 2 * N * sizeof(qds::FusedArgs<T>)) +
-                     size_t(parity) * N;
-    for (size_t q = 0; q < P.launches.size(); ++q) {
-        const Launch& l = P.launches[q];
+    const auto* fa = tab_fa<T>(b, parity);
+    const auto* xa = tab_xa<T>(b, parity);
+    size_t q = 0;
+    for (const Launch& l : P.launches) {
+        if (l.slot >= QDS_TILE_PAIR0) continue;
         hipError_t e;
         if (ev && (e = hipEventRecord(ev[2 * q], s)) != hipSuccess) return e;
         if (l.slot < QDS_TILE_CUR1) e = qds::batch_a<T>(fa, l.L, l.M, l.blocks, l.axt, s);
@@ -199,25 +254,102 @@ hipError_t launch_step(const qds_batch_ctx* b, const Plan& P, int parity, hipStr
         else e = qds::batch_em<T>(fa, l.L, l.slot == QDS_TILE_EM1 ? 1 : 0, l.blocks, s);
         if (e != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[2 * q + 1], s)) != hipSuccess) return e;
+        ++q;
     }
     return hipSuccess;
+}
+
+// One pair of steps from buffer (cur + parity) % 2: kernel A and the axion
+// current of the first step into each instance's pair buffer, those of the
+// second step out of it, then the two-step marches (launch order: the kernel-A
+// and axion-current classes twice, then the marches; event pairs ev[2q],
+// ev[2q + 1] in that order).
+template <typename T>
+hipError_t launch_pair(const qds_batch_ctx* b, const Plan& P, int parity, hipStream_t s, hipEvent_t* ev) {
+    size_t q = 0;
+    auto rec = [&](int k) { return ev ? hipEventRecord(ev[2 * q + k], s) : hipSuccess; };
+    for (int half = 0; half < 2; ++half) {
+        const auto* fp = tab_fp<T>(b, parity, half);
+        const auto* xp = tab_xp<T>(b, parity, half);
+        for (const Launch& l : P.launches) {
+            if (l.slot >= QDS_TILE_EM0) continue;
+            hipError_t e;
+            if ((e = rec(0)) != hipSuccess) return e;
+            e = l.slot < QDS_TILE_CUR1 ? qds::batch_a<T>(fp, l.L, l.M, l.blocks, false, s)
+                                       : qds::batch_current<T>(xp, l.L, l.M, l.blocks, s);
+            if (e != hipSuccess) return e;
+            if ((e = rec(1)) != hipSuccess) return e;
+            ++q;
+        }
+    }
+    const auto* fa = tab_fa<T>(b, parity);
+    for (const Launch& l : P.launches) {
+        if (l.slot < QDS_TILE_PAIR0) continue;
+        hipError_t e;
+        if ((e = rec(0)) != hipSuccess) return e;
+        if ((e = qds::batch_em2<T>(fa, l.L, l.slot == QDS_TILE_PAIR1 ? 1 : 0, l.blocks, s)) != hipSuccess) return e;
+        if ((e = rec(1)) != hipSuccess) return e;
+        ++q;
+    }
+    return hipSuccess;
+}
+
+// The steps of a segment of ``steps`` steps whose first step reads buffer
+// parity ``f`` % 2: pairs while two steps remain (with pairs), then single
+// steps; returns the buffer flips, adds the kernel launches to *n.
+template <typename T>
+hipError_t launch_steps(const qds_batch_ctx* b, const Plan& P, int64_t steps, int64_t f, hipStream_t s,
+                        int64_t* flips, int64_t* n) {
+    int64_t u = 0, k = 0;
+    hipError_t e = hipSuccess;
+    if (b->pairs)
+        for (; u + 2 <= steps && e == hipSuccess; u += 2, ++k) {
+            e = launch_pair<T>(b, P, int((f + k) & 1), s, nullptr);
+            *n += int64_t(pair_launches(P));
+        }
+    for (; u < steps && e == hipSuccess; ++u, ++k) {
+        e = launch_step<T>(b, P, int((f + k) & 1), s, nullptr);
+        *n += int64_t(step_launches(P));
+    }
+    *flips = k;
+    return e;
 }
 
 template <typename T>
 qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, const qds_axion* ax,
                     const int64_t* n_steps, int graph_steps, int tune, hipStream_t s) {
     const size_t N = b->inst.size();
+    // pairs of steps when every instance can take them (the regenerated set
+    // on kernel A and the marched axion current, or no axion at all)
+    b->pairs = 1;
+    for (const qds_ctx* c : b->inst)
+        if (!c->pair || (has(c, QDS_P_PHI) && !has(c, QDS_P_SET1))) b->pairs = 0;
+    if (b->pairs)
+        for (qds_ctx* c : b->inst) {
+            if (!has(c, QDS_P_SET1) || c->pairbuf) continue;
+            // the instance's pair buffer, as qds_step allocates it
+            const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
+            if (hipMalloc(&c->pairbuf, sbytes + 3 * c->plane_elems * c->elem_bytes) != hipSuccess) {
+                c->pairbuf = nullptr;
+                return bfail(b, QDS_ENOMEM, "hipMalloc of a pair buffer failed%s");
+            }
+        }
     // argument tables: parity q reads buf[(cur + q) % 2] and writes the other;
     // the step and window counters are not used by the batched kernels (no
     // drive, no window) and are left at zero so that equal states reuse them
     const size_t fbytes = 2 * N * sizeof(qds::FusedArgs<T>);
-    const size_t bytes = fbytes + 2 * N * sizeof(qds::AxionArgs<T>);
+    const size_t sbytes = fbytes + 2 * N * sizeof(qds::AxionArgs<T>);
+    const size_t bytes = sbytes + (b->pairs ? 2 * sbytes : 0);
     std::vector<unsigned char> host(bytes, 0);
     auto* fa = reinterpret_cast<qds::FusedArgs<T>*>(host.data());
     auto* xa = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + fbytes);
+    auto* fp = reinterpret_cast<qds::FusedArgs<T>*>(host.data() + sbytes);
+    auto* xp = reinterpret_cast<qds::AxionArgs<T>*>(host.data() + sbytes + 2 * fbytes);
     for (size_t k = 0; k < N; ++k) {
         const qds_ctx* c = b->inst[k];
         const qds::StepPlan<T> p0 = make_plan<T>(c, J ? &J[k] : nullptr, ax ? &ax[k] : nullptr);
+        qds::StepPlan<T> p2 = p0;   // the second step of a pair: its axion current to the second j_a planes
+        for (int q = 0; q < 3; ++q) p2.ja[q] = p0.ja2[q];
         for (int q = 0; q < 2; ++q) {
             void* A = states[k].buf[(states[k].cur + q) & 1];
             void* B = states[k].buf[(states[k].cur + q + 1) & 1];
@@ -225,6 +357,17 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             qds::AxionArgs<T> x = axion_args<T>(c, p0, A, B);
             memcpy(&fa[q * N + k], &f, sizeof(f));
             memcpy(&xa[q * N + k], &x, sizeof(x));
+            if (!b->pairs) continue;
+            // instances without the axion only launch the march (from fa)
+            void* S = c->pairbuf ? c->pairbuf : B;
+            f = fused_args<T>(c, p0, A, S);
+            x = axion_args<T>(c, p0, A, S);
+            memcpy(&fp[(2 * q) * N + k], &f, sizeof(f));
+            memcpy(&xp[(2 * q) * N + k], &x, sizeof(x));
+            f = fused_args<T>(c, p2, S, B);
+            x = axion_args<T>(c, p2, S, B);
+            memcpy(&fp[(2 * q + 1) * N + k], &f, sizeof(f));
+            memcpy(&xp[(2 * q + 1) * N + k], &x, sizeof(x));
         }
     }
     hipError_t e;
@@ -261,18 +404,29 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             if (n_steps[k] > t) a.push_back(int(k));
         return a;
     };
-    int64_t t = 0;
+    // t: steps done; f: buffer flips done (a pair flips the buffers once);
+    // flips[k]: those of instance k (the parity of its state's buffer index)
+    int64_t t = 0, f = 0;
+    std::vector<int64_t> flips(N, 0);
+    auto advance = [&](const std::vector<int>& act, int64_t steps, int64_t nf) {
+        for (int k : act) flips[size_t(k)] += nf;
+        t += steps;
+        f += nf;
+    };
+    const int per = b->pairs ? 2 : 1;     // steps per trial of the tuner
     qds_status st;
     auto find_plan = [&](const std::vector<int>& act) -> Plan* {
         for (Plan* p : b->plans)
-            if (p->active == act && std::equal(p->tiles.begin(), p->tiles.end(), b->tiles)) return p;
+            if (p->active == act && p->pairs == (b->pairs != 0) &&
+                std::equal(p->tiles.begin(), p->tiles.end(), b->tiles))
+                return p;
         return nullptr;
     };
-    // autotuner: timed trial steps of the run, each candidate tiling twice
+    // autotuner: timed trial steps (or pairs) of the run, each candidate tiling twice
     if (tune && !b->tuned) {
         std::vector<int> act = running(0);
         bool enough = !act.empty();
-        for (int k : act) enough = enough && n_steps[k] >= 4 * kTunePasses;
+        for (int k : act) enough = enough && n_steps[k] >= 4 * kTunePasses * per;
         if (enough) {
             std::vector<hipEvent_t> evs;
             std::vector<Plan*> trial;
@@ -281,22 +435,26 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = kCandA[cand];
                     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = kCandCur[cand];
                     b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = kCandEm[cand];
+                    b->tiles[QDS_TILE_PAIR0] = b->tiles[QDS_TILE_PAIR1] = kCandPair[cand];
                     Plan* P;
                     if ((st = build_plan(b, act, s, &P)) != QDS_OK) return st;
                     trial.push_back(P);
                     const size_t base = evs.size();
-                    for (size_t q = 0; q < 2 * P->launches.size(); ++q) {
+                    const size_t nl = b->pairs ? pair_launches(*P) : step_launches(*P);
+                    for (size_t q = 0; q < 2 * nl; ++q) {
                         hipEvent_t ev;
                         if (hipEventCreate(&ev) != hipSuccess) return bfail(b, QDS_EHIP, "event creation failed%s");
                         evs.push_back(ev);
                     }
-                    e = launch_step<T>(b, *P, int(t & 1), s, evs.data() + base);
+                    e = b->pairs ? launch_pair<T>(b, *P, int(f & 1), s, evs.data() + base)
+                                 : launch_step<T>(b, *P, int(f & 1), s, evs.data() + base);
                     if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-                    ++t;
+                    advance(act, per, 1);
                 }
             }
             if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, QDS_EHIP, "tuning run failed%s");
-            // per trial, the summed time of the launches of each slot
+            // per trial, the summed time of the launches of each slot (in the
+            // order launch_step or launch_pair issued them)
             float best[QDS_NTILES];
             int pick[QDS_NTILES];
             for (int q = 0; q < QDS_NTILES; ++q) { best[q] = 3.4e38f; pick[q] = -1; }
@@ -306,22 +464,35 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 float sum[QDS_NTILES];
                 bool seen[QDS_NTILES];
                 for (int q = 0; q < QDS_NTILES; ++q) { sum[q] = 0.f; seen[q] = false; }
-                for (const Launch& l : trial[tr]->launches) {
+                std::vector<int> order;
+                if (b->pairs) {
+                    for (int half = 0; half < 2; ++half)
+                        for (const Launch& l : trial[tr]->launches)
+                            if (l.slot < QDS_TILE_EM0) order.push_back(l.slot);
+                    for (const Launch& l : trial[tr]->launches)
+                        if (l.slot >= QDS_TILE_PAIR0) order.push_back(l.slot);
+                } else {
+                    for (const Launch& l : trial[tr]->launches)
+                        if (l.slot < QDS_TILE_PAIR0) order.push_back(l.slot);
+                }
+                for (int slot : order) {
                     float ms = 0.f;
                     if (hipEventElapsedTime(&ms, evs[ei], evs[ei + 1]) != hipSuccess) {
                         ms = 3.4e38f;
                         (void)hipGetLastError();   // not left for the next launch check
                     }
                     ei += 2;
-                    sum[l.slot] += ms;
-                    seen[l.slot] = true;
+                    sum[slot] += ms;
+                    seen[slot] = true;
                 }
                 for (int q = 0; q < QDS_NTILES; ++q)
                     if (seen[q] && sum[q] < best[q]) { best[q] = sum[q]; pick[q] = cand; }
             }
             for (int q = 0; q < QDS_NTILES; ++q) {
                 const int cand = pick[q] < 0 ? 2 : pick[q];
-                b->tiles[q] = q < QDS_TILE_CUR1 ? kCandA[cand] : (q < QDS_TILE_EM0 ? kCandCur[cand] : kCandEm[cand]);
+                b->tiles[q] = q < QDS_TILE_CUR1 ? kCandA[cand]
+                                                : (q < QDS_TILE_EM0 ? kCandCur[cand]
+                                                                    : (q < QDS_TILE_PAIR0 ? kCandEm[cand] : kCandPair[cand]));
             }
             b->tuned = 1;
             for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
@@ -333,11 +504,11 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         // one capture of all the steps, replayed while the tables, the tiles and
         // the step counts are the same
         std::vector<int64_t> key;
-        key.push_back(t & 1);
+        key.push_back(f & 1);
+        key.push_back(b->pairs);
         key.insert(key.end(), b->tiles, b->tiles + QDS_NTILES);
         for (size_t k = 0; k < N; ++k) key.push_back(std::max<int64_t>(n_steps[k] - t, 0));
         std::vector<std::pair<Plan*, int64_t>> segs;
-        int64_t launches = 0;
         for (int64_t tt = t;;) {
             std::vector<int> act = running(tt);
             if (act.empty()) break;
@@ -346,23 +517,33 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
             Plan* P = find_plan(act);
             if (!P && (st = build_plan(b, act, s, &P)) != QDS_OK) return st;
             segs.emplace_back(P, rem);
-            launches += rem * int64_t(P->launches.size());
             tt += rem;
         }
         if (!segs.empty()) {
             auto it = b->whole.find(key);
-            if (it == b->whole.end()) {
-                hipGraph_t g = nullptr;
-                hipGraphExec_t x = nullptr;
-                e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
-                if (e != hipSuccess) return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(e));
-                hipError_t le = hipSuccess;
-                int64_t tt = t;
-                for (const auto& sg : segs) {
-                    for (int64_t u = 0; u < sg.second && le == hipSuccess; ++u)
-                        le = launch_step<T>(b, *sg.first, int((tt + u) & 1), b->cap, nullptr);
-                    tt += sg.second;
+            int64_t launches = 0, ff = f;
+            hipError_t le = hipSuccess;
+            const bool capture = it == b->whole.end();
+            hipGraph_t g = nullptr;
+            hipGraphExec_t x = nullptr;
+            if (capture && (e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess)
+                return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(e));
+            for (const auto& sg : segs) {
+                // (the launches are only recorded when capturing; the flips and
+                // launch counts of a replay are the same)
+                int64_t nf = 0;
+                if (capture) {
+                    if (le == hipSuccess) le = launch_steps<T>(b, *sg.first, sg.second, ff, b->cap, &nf, &launches);
+                } else {
+                    nf = b->pairs ? sg.second / 2 + sg.second % 2 : sg.second;
+                    launches += b->pairs ? (sg.second / 2) * int64_t(pair_launches(*sg.first)) +
+                                               (sg.second % 2) * int64_t(step_launches(*sg.first))
+                                         : sg.second * int64_t(step_launches(*sg.first));
                 }
+                for (int k : sg.first->active) flips[size_t(k)] += nf;
+                ff += nf;
+            }
+            if (capture) {
                 e = hipStreamEndCapture(b->cap, &g);
                 if (le != hipSuccess || e != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -391,25 +572,24 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         Plan* P = find_plan(act);
         if (!P && (st = build_plan(b, act, s, &P)) != QDS_OK) return st;
         if (graph_steps <= 0) {
-            for (int64_t u = 0; u < rem; ++u) {
-                e = launch_step<T>(b, *P, int((t + u) & 1), s, nullptr);
-                if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
-            }
-            b->stats[2] += rem * int64_t(P->launches.size());
-            t += rem;
+            int64_t nf = 0, nl = 0;
+            e = launch_steps<T>(b, *P, rem, f, s, &nf, &nl);
+            if (e != hipSuccess) return bfail(b, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+            b->stats[2] += nl;
+            advance(act, rem, nf);
             continue;
         }
         while (rem > 0) {
             const int seg = int(std::min<int64_t>(rem, graph_steps));
-            const std::pair<int, int> key(seg, int(t & 1));
+            const std::pair<int, int> key(seg, int(f & 1));
             auto it = P->graphs.find(key);
+            int64_t nf = 0, nl = 0;
             if (it == P->graphs.end()) {
                 hipGraph_t g = nullptr;
                 hipGraphExec_t x = nullptr;
                 e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
                 if (e != hipSuccess) return bfail(b, QDS_EHIP, "capture failed: %s", hipGetErrorString(e));
-                hipError_t le = hipSuccess;
-                for (int u = 0; u < seg && le == hipSuccess; ++u) le = launch_step<T>(b, *P, int((t + u) & 1), b->cap, nullptr);
+                const hipError_t le = launch_steps<T>(b, *P, seg, f, b->cap, &nf, &nl);
                 e = hipStreamEndCapture(b->cap, &g);
                 if (le != hipSuccess || e != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -422,17 +602,21 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
                 }
                 it = P->graphs.emplace(key, std::make_pair(g, x)).first;
                 b->stats[1] += 1;
+            } else {
+                nf = b->pairs ? seg / 2 + seg % 2 : seg;
+                nl = b->pairs ? int64_t(seg / 2) * int64_t(pair_launches(*P)) + int64_t(seg % 2) * int64_t(step_launches(*P))
+                              : int64_t(seg) * int64_t(step_launches(*P));
             }
             e = hipGraphLaunch(it->second.second, s);
             if (e != hipSuccess) return bfail(b, QDS_EHIP, "graph launch failed: %s", hipGetErrorString(e));
             b->stats[0] += 1;
-            b->stats[3] += int64_t(seg) * int64_t(P->launches.size());
-            t += seg;
+            b->stats[3] += nl;
+            advance(act, seg, nf);
             rem -= seg;
         }
     }
     for (size_t k = 0; k < N; ++k) {
-        states[k].cur ^= int(n_steps[k] & 1);
+        states[k].cur ^= int(flips[k] & 1);
         states[k].step += n_steps[k];
     }
     if (hipEventRecord(b->done, s) != hipSuccess) return bfail(b, QDS_EHIP, "event record failed%s");
@@ -466,6 +650,7 @@ qds_status qds_batch_create(const qds_handle* handles, int32_t count, qds_batch*
     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_A1 + q] = 16;
     for (int q = 0; q < 4; ++q) b->tiles[QDS_TILE_CUR1 + q] = 16;
     b->tiles[QDS_TILE_EM0] = b->tiles[QDS_TILE_EM1] = 16;
+    b->tiles[QDS_TILE_PAIR0] = b->tiles[QDS_TILE_PAIR1] = 32;
     b->err[0] = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {

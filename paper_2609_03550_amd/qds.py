@@ -505,8 +505,8 @@ class Solver:
             pass
 
 
-NTILES = 10
-TILE_A1, TILE_CUR1, TILE_EM0, TILE_EM1 = 0, 4, 8, 9
+NTILES = 12
+TILE_A1, TILE_CUR1, TILE_EM0, TILE_EM1, TILE_PAIR0, TILE_PAIR1 = 0, 4, 8, 9, 10, 11
 
 
 class Batch:

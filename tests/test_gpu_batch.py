@@ -84,6 +84,40 @@ def test_mixed_content_batch_equals_one_at_a_time():
             P.compare_states(s.fields(), P.oracle_run(s.wl, n), *TOL["f64"])
 
 
+@pytest.mark.parametrize("graph_steps", [0, 3, -1])
+def test_paired_batch_with_electromagnetic_instances(graph_steps):
+    """Every instance takes pairs of steps: instances with the regenerated set
+    (kernel A and the axion current twice, then the regenerated set's
+    two-step march) and two without the axion (the two-step march of the
+    background set alone); uneven counts, so segments of odd length end in a
+    single step.  Bit-identical to the same batch one step at a time and to
+    each instance alone, with fewer kernel launches."""
+    from paper_2609_03550_amd import qds
+    wls = _small(6, 19)
+    wls[2] = wls[2].with_(axion=False, arem=False)
+    wls[5] = wls[5].with_(axion=False, arem=False)
+    steps = [11, 6, 9, 0, 14, 7]
+    ref = _solvers(wls, "f64")
+    single = _twins(ref)
+    paired = _twins(ref)
+    for s in single:
+        s.set_option(qds.OPT_PAIR, 0)
+    bs = qds.Batch(single)
+    bs.run(steps, graph_steps=graph_steps)
+    bp = qds.Batch(paired)
+    bp.run(steps, graph_steps=graph_steps)
+    for s, n in zip(ref, steps):
+        s.step(n)
+    _identical(paired, ref)
+    _identical(single, ref)
+    assert [s.state.cur for s in paired] != [s.state.cur for s in single]   # pairs flip once
+
+    def launches(b):
+        st = b.stats()
+        return st[2] + st[3]
+    assert launches(bp) < launches(bs)
+
+
 @pytest.mark.parametrize("graph_steps", [0, 1, 5, -1])
 def test_graph_length_does_not_change_results(graph_steps):
     """Graphs of 1 or 5 steps, direct launches, and the whole uneven schedule
@@ -128,16 +162,18 @@ def test_autotuner_picks_candidates_and_keeps_results():
     wls = _small(5, 14)
     ref = _solvers(wls, "f32")
     bs = _twins(ref)
-    qds.Batch(ref).run(12, graph_steps=4)
+    qds.Batch(ref).run(18, graph_steps=4)
     b = qds.Batch(bs)
     assert b.tiles()[1] is False
-    b.run(12, graph_steps=4, tune=True)
+    b.run(18, graph_steps=4, tune=True)      # 8 trial pairs, then one more pair
     tiles, tuned = b.tiles()
     assert tuned
-    # kernel A (slots 0-3), axion current (4-7), electromagnetic sets alone (8, 9)
+    # kernel A (slots 0-3), axion current (4-7), electromagnetic sets alone
+    # (8, 9; not run by pairs), the two-step marches (10, 11)
     assert all(t in (8, 16, 24, 32) for t in tiles[:4])
     assert all(t in (4, 6, 8, 16) for t in tiles[4:8])
-    assert all(t in (8, 16, 32, 52) for t in tiles[8:])
+    assert all(t in (8, 16, 32, 52) for t in tiles[8:10])
+    assert all(t in (16, 32, 52, 86) for t in tiles[10:])
     _identical(bs, ref)
     # a second run reuses the chosen tiles
     b.run(3, graph_steps=2, tune=True)
