@@ -14,6 +14,9 @@ from paper_2609_03550_amd import inputs as I
 import parity_tools as P
 from test_gpu_parity import _full, _random_reachable_state
 
+pytestmark = pytest.mark.gpu
+H = I.H
+
 
 def _random_state_no_plasma(wl, seed):
     """As _random_reachable_state, for a set without the plasma: its state
@@ -27,9 +30,6 @@ def _random_state_no_plasma(wl, seed):
         if isinstance(v, torch.Tensor) and v.is_complex():
             st[k] = torch.zeros_like(v) if k[0] == "j" else torch.randn(v.shape, dtype=torch.complex128, generator=gen)
     return Q.step(st, g, ph), g, ph
-
-pytestmark = pytest.mark.gpu
-H = I.H
 
 
 def _em(nx, nr, M, **kw):
