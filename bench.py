@@ -47,8 +47,9 @@ def plane_accesses(wl, kernel, split=True):
     em = 6 + (3 if wl.wp2 else 0)
     if kernel == 3:
         # the two-step march (one launch per two steps): the set read and
-        # written once, the axion current of both steps read
-        return 2 * em + (6 if wl.arem else 0)
+        # written once, the axion current (or the drive's mode-0 plane) of
+        # both steps read
+        return 2 * em + (6 if wl.arem else 0) + (2.0 / wl.nmodes if wl.drive is not None else 0.0)
     if not wl.axion:
         if kernel != 0:
             return 0
@@ -75,11 +76,13 @@ TUNE_STEPS = 16
 
 def pairs_active(wl, fused, pair=1, kernel_ax=0, overlap=0):
     """Whether qds_step runs this workload in pairs of steps (QDS_OPT_PAIR):
-    the fused kernels without the moving window or a drive, with the
-    regenerated set on the split kernels, or without the axion."""
-    if not (pair and fused) or wl.x_bc == "window" or wl.drive is not None or overlap:
+    on the fused kernels, with the regenerated set on the split kernels (no
+    moving window, no drive), or without the axion (with or without both)."""
+    if not (pair and fused) or overlap:
         return False
-    return (wl.arem and not kernel_ax) or not wl.axion
+    if wl.axion:
+        return bool(wl.arem) and not kernel_ax and wl.x_bc != "window" and wl.drive is None
+    return True
 
 
 def workload(name):

@@ -226,10 +226,12 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 its current (measured faster on MI355X: the one-pass march
  *                 holds both windows, which halves its occupancy).
  *  QDS_OPT_PAIR   1: qds_step advances steps two at a time where the
- *                 two-step march applies (fused kernels, no moving window, no
- *                 prescribed drive; with the regenerated set on kernel A and
- *                 the marched axion kernel, or the background set alone
- *                 without the axion): one launch marches one set through two
+ *                 two-step march applies (fused kernels; with the regenerated
+ *                 set on kernel A and the marched axion kernel, without the
+ *                 moving window or a prescribed drive; or the background set
+ *                 alone without the axion, also with the moving window and
+ *                 the drive, whose plane is then filled for both steps): one
+ *                 launch marches one set through two
  *                 steps, the first step's rows handed to the second through
  *                 LDS, so the set's planes are read and written once per two
  *                 steps (temporal blocking of the Maxwell update of Sec. 2.1;
@@ -241,8 +243,8 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 caller's other buffer.  Each pair flips fields->cur once and
  *                 adds 2 to fields->step; an odd last step is a single step.
  *                 Tile height QDS_OPT_ROWS_PAIR (default: two chunks; tuner
- *                 candidates 16 and the heights that cut the nr + 1 rows into
- *                 5, 3 and 2 chunks); the timing slot of the march is that of
+ *                 candidates 20 and the heights that cut the nr + 1 rows into
+ *                 4, 3 and 2 chunks); the timing slot of the march is that of
  *                 the set it advances, one launch per two steps.  1 is the
  *                 default; 0: single steps.
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP

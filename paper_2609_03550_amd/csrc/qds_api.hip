@@ -24,14 +24,14 @@ const int kCandAX[4] = {16, 24, 32, 48};
 const int kCandCur[4] = {4, 6, 8, 16};
 const int kCandB[4] = {16, 32, 52, 64};
 const int kCandEm[4] = {8, 16, 26, 52};
-// The two-step march runs fastest when all its workgroups are resident at
-// once (measured on MI355X: 129 rows, two chunks, for FP64 at 8192 x 256 x 3,
-// 86 rows, three chunks, for FP32): 16 rows and the heights that cut the
-// nr + 1 rows into 5, 3 and 2 chunks.
+// Tile heights of the two-step march (measured on MI355X): at 8192 x 256 x 3
+// it is fastest with every workgroup resident at once (129 rows, two chunks,
+// in FP64; 86 rows, three chunks, in FP32), at 4096 x 256 x 3 with about 20
+// rows: 20 rows and the heights that cut the nr + 1 rows into 4, 3 and 2 chunks.
 void cand_pair(const qds_ctx* c, int* out) {
     const int R = c->g.nr + 1;
-    const int parts[4] = {0, 5, 3, 2};
-    out[0] = 16;
+    const int parts[4] = {0, 4, 3, 2};
+    out[0] = 20;
     for (int q = 1; q < 4; ++q) {
         const int h = (R + parts[q] - 1) / parts[q];
         out[q] = h < 4 ? 4 : h;
@@ -92,7 +92,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     t.firstA[1] = strips * chunks(c->trows[0]);
     t.firstC[1] = qds::current_strips(c->g.nx) * chunks(c->trows[1]);
     t.firstB[1] = strips * chunks(c->trows[2]) * c->M;
-    t.firstB2[1] = qds::pair_strips(c->g.nx) * chunks(c->trows[3]) * c->M;
+    t.firstB2[1] = qds::pair_strips(c->g.nx, c->g.x_bc == QDS_X_WINDOW ? 1 : 0) * chunks(c->trows[3]) * c->M;
     // the staging copy may still be read by the previous upload
     if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
         return fail(c, QDS_EHIP, "argument table upload failed%s");
@@ -215,7 +215,15 @@ qds_status pair_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab
                      hipStream_t s, hipEvent_t* ev) {
     const int q = st->cur;
     const TabView<T> v = ktab_view<T>(K, host, q);
+    const bool window = c->g.x_bc == QDS_X_WINDOW;
     qds_status r;
+    if (p0.drive.on) {
+        // j_x^(0) of both steps (the second one column on with the window)
+        hipError_t e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, st->step, st->window, s);
+        if (e == hipSuccess)
+            e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv2, st->step + 1, st->window + (window ? 1 : 0), s);
+        if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
+    }
     if (p0.arem) {
         TabView<T> va = v, vb = v;
         va.fa = &K->fp[q][0]; va.xa = &K->xp[q][0];
@@ -228,6 +236,7 @@ qds_status pair_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab
     if ((r = table_launch_one<T>(c, p0, v, kLaunchB2, s, ev ? ev + 4 : nullptr)) != QDS_OK) return r;
     st->cur = 1 - st->cur;
     st->step += 2;
+    if (window) st->window += 2;
     return QDS_OK;
 }
 
@@ -281,13 +290,17 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
     int64_t done = 0;
     qds::StepPlan<T> p0 = p1;
     if (p0.drive.on && !c->drive_plane) {
-        // the drive plane (mode 0 of one plane), allocated on first use
-        if (hipMalloc(&c->drive_plane, size_t(c->g.nr + 1) * size_t(c->ld) * c->elem_bytes) != hipSuccess) {
+        // the drive planes (mode 0 of one plane, for the two steps of a pair),
+        // allocated on first use
+        if (hipMalloc(&c->drive_plane, 2 * size_t(c->g.nr + 1) * size_t(c->ld) * c->elem_bytes) != hipSuccess) {
             c->drive_plane = nullptr;
             return fail(c, QDS_ENOMEM, "hipMalloc of the drive plane failed%s");
         }
     }
     p0.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
+    p0.jdrv2 = c->drive_plane ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->drive_plane) +
+                                                             size_t(c->g.nr + 1) * size_t(c->ld) * c->elem_bytes)
+                              : nullptr;
     if (p0.pj[1]) {
         // particle deposits: the background march reads them at the source
         // points, formed once per call (they hold for every step of it)

@@ -18,7 +18,7 @@ struct qds_ctx {
     int slot[QDS_NPLANES];   // plane -> position in the buffer, -1 if absent
     int nplanes;
     void* scratch;           // axion-current planes (3) and S_a, library owned
-    void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0 (allocated on first use)
+    void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0, for two steps (allocated on first use)
     void* psrc;              // particle currents at the source points, 3 planes (allocated on first use)
     void* pairbuf;           // pairs of steps with the regenerated set: a state-sized buffer for the
                              // background set and axion between the two steps, then j_a of the
@@ -168,6 +168,9 @@ qds::StepPlan<T> make_plan(const qds_ctx* c, const qds_current* J, const qds_axi
                                                               size_t(k) * c->plane_elems * c->elem_bytes)
                               : nullptr;
     p.jdrv = static_cast<qds::cx<T>*>(c->drive_plane);
+    p.jdrv2 = c->drive_plane ? reinterpret_cast<qds::cx<T>*>(static_cast<char*>(c->drive_plane) +
+                                                            size_t(c->g.nr + 1) * size_t(c->ld) * c->elem_bytes)
+                             : nullptr;
     const bool part = J && J->kind == QDS_J_PARTICLES;
     p.pj[0] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_prev)) : nullptr;
     p.pj[1] = part ? static_cast<qds::cx<T>*>(const_cast<void*>(J->pjx_next)) : nullptr;
@@ -231,6 +234,8 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
     // extra currents in both steps
     if (!p0.drive.on) {
         a.s0.jxb = a.s0.jxa; a.s0.jrb = a.s0.jra; a.s0.jtb = a.s0.jta;
+    } else {
+        a.s0.jxb = p0.jdrv2;   // j_x^(0) of the pair's second step
     }
     a.phi = A[QDS_P_PHI]; a.tap = A[QDS_P_TAP]; a.tam = A[QDS_P_TAM];
     a.ophi = B[QDS_P_PHI]; a.otap = B[QDS_P_TAP]; a.otam = B[QDS_P_TAM];
@@ -239,12 +244,13 @@ qds::FusedArgs<T> fused_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void*
 
 // Whether qds_step advances steps in pairs, with the two-step march of one
 // set: the regenerated set (kernel A and the marched axion kernel for the
-// background set and the axion, no prescribed drive), or the background set
-// alone (no axion, no drive).  Not with the moving window.
+// background set and the axion; no prescribed drive, no moving window), or
+// the background set alone (no axion; with or without the prescribed drive
+// and the moving window).
 template <typename T>
 bool pair_ok(const qds_ctx* c, const qds::StepPlan<T>& p0) {
-    if (!c->pair || c->g.x_bc == QDS_X_WINDOW || p0.drive.on) return false;
-    if (p0.arem) return march_axion(c, p0) && !fuse_ax(c, p0);
+    if (!c->pair) return false;
+    if (p0.arem) return march_axion(c, p0) && !fuse_ax(c, p0) && !p0.drive.on;
     return !p0.axion;
 }
 

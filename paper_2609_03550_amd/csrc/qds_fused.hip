@@ -154,6 +154,10 @@ struct Ctx {
     T inv_2h;            // 1/(2 h)
     T wp2h;
     int plasma;
+    // the first step of the two-step march with the moving window: this
+    // lane's column is the one the window brings in, so what it puts in the
+    // ring is the zero-filled state
+    bool rzero;
 };
 
 // reciprocal radii of one march step: 1/r_{j+1}, 1/r_{j+1/2}, 1/r_j (0 on the axis)
@@ -271,6 +275,11 @@ template <typename T>
 __device__ __forceinline__ cx<T>* rg(cx<T>* ring, int plane, int row, int lane) {
     return ring + (plane * RING_ROWS + (row & (RING_ROWS - 1))) * WAVE + lane;
 }
+// one value of the lane's own column into the ring
+template <typename T>
+__device__ __forceinline__ void rput(const Ctx<T>& c, cx<T>* ring, int plane, int row, cx<T> v) {
+    *rg(ring, plane, row, c.lane) = c.rzero ? zero<T>() : v;
+}
 
 // total j_x at (x_{i+1/2}, r_row, t^n): plasma j_x^n + extra (the axion
 // current, or the prescribed drive)
@@ -281,7 +290,7 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
     if (!c.live) {
         // the dead last cell: its plasma current still advances (it enters no field)
         if constexpr (IO == IO_RING) {
-            if (c.plasma && write) *rg(ring, RG_JX, row, c.lane) = jx_old + c.wp2h * ex0;
+            if (c.plasma && write) rput(c, ring, RG_JX, row, jx_old + c.wp2h * ex0);
         } else {
             if (c.plasma && write && c.owner && c.o.col(c.i) >= 0)
                 sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jx_old + c.wp2h * ex0);
@@ -291,7 +300,7 @@ __device__ __forceinline__ cx<T> em_jx(const Ctx<T>& c, const SetP<T>& s, int ro
     if (c.plasma) {
         cx<T> jn = jx_old + c.wp2h * ex0;
         if constexpr (IO == IO_RING) {
-            if (write) *rg(ring, RG_JX, row, c.lane) = jn;
+            if (write) rput(c, ring, RG_JX, row, jn);
         } else {
             if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojx, eoff<T>(c.g, c.m, row, c.o.col(c.i)), jn);
         }
@@ -405,7 +414,7 @@ __device__ __forceinline__ cx<T> em_jt_avg(const Ctx<T>& c, const SetP<T>& s, co
     cx<T> jb = jti1 + c.wp2h * (T(0.5) * (B.tpb[slot] + B.tmb[slot]));
     if (!c.g.open_r && row == c.g.nr) ja = jb = zero<T>();
     if constexpr (IO == IO_RING) {
-        if (write) *rg(ring, RG_JT, row, c.lane) = ja;
+        if (write) rput(c, ring, RG_JT, row, ja);
     } else {
         if (write && c.owner && c.o.col(c.i) >= 0) sto(s.ojt, eoff<T>(c.g, c.m, row, c.o.col(c.i)), ja);
     }
@@ -430,7 +439,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         W.jx_n1 = em_jx<T, IO>(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa, ring);
         W.ex1[2] = em_ex_new(c, W, B, j + 1, W.jx_n1, ri.irJ1);
         if constexpr (RING) {
-            if (j + 1 >= r0 && j + 1 < r1) *rg(ring, RG_EX, j + 1, c.lane) = W.ex1[2];
+            if (j + 1 >= r0 && j + 1 < r1) rput(c, ring, RG_EX, j + 1, W.ex1[2]);
         } else {
             if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
         }
@@ -442,7 +451,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
     if (j < g.nr) {
         W.bx1[1] = em_bx_new(c, W, B, ri.irK);
         if constexpr (RING) {
-            if (own_row) *rg(ring, RG_BX, j, c.lane) = W.bx1[1];
+            if (own_row) rput(c, ring, RG_BX, j, W.bx1[1]);
         } else {
             if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
         }
@@ -477,7 +486,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         }
         W.bx1g = gh;
         if constexpr (RING) {
-            if (r1 == g.nr + 1) *rg(ring, RG_BX, g.nr, c.lane) = gh;
+            if (r1 == g.nr + 1) rput(c, ring, RG_BX, g.nr, gh);
         } else {
             if (r1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
         }
@@ -490,7 +499,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         if (c.plasma) {
             jra = X.jr + c.wp2h * (T(0.5) * (W.rpa[0] + W.rma[0]));
             if constexpr (RING) {
-                if (own_row) *rg(ring, RG_JR, j, c.lane) = jra;
+                if (own_row) rput(c, ring, RG_JR, j, jra);
             } else {
                 if (own_row && wI) sto(s.ojr, eoff<T>(g, m, j, ocI), jra);
             }
@@ -517,8 +526,8 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         if constexpr (RING) {
             // the lane's own column: T_r^+ came from the left neighbour
             if (own_row) {
-                *rg(ring, RG_TRP, j, c.lane) = W.n_rpa;
-                *rg(ring, RG_TRM, j, c.lane) = W.n_rma;
+                rput(c, ring, RG_TRP, j, W.n_rpa);
+                rput(c, ring, RG_TRM, j, W.n_rma);
             }
         } else if (own_row) {
             if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_rpb);
@@ -560,8 +569,8 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         W.n_tma = (c.i == 0 && !g.per) ? zero<T>() : from_left;
         if constexpr (RING) {
             if (own_row) {
-                *rg(ring, RG_TTP, j, c.lane) = W.n_tpa;
-                *rg(ring, RG_TTM, j, c.lane) = W.n_tma;
+                rput(c, ring, RG_TTP, j, W.n_tpa);
+                rput(c, ring, RG_TTM, j, W.n_tma);
             }
         } else if (own_row) {
             if (wI) sto(s.ottp, eoff<T>(g, m, j, ocI), W.n_tpa);
@@ -598,7 +607,7 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
     }
     if constexpr (IO == IO_RING) {
         // the second step reads the ghost row through T_r^+ alone
-        if (r1 == g.nr + 1) *rg(ring, RG_TRP, N, c.lane) = out;
+        if (r1 == g.nr + 1) rput(c, ring, RG_TRP, N, out);
     } else {
         const int oc = c.o.col(c.i);
         if (c.owner && oc >= 0 && r1 == g.nr + 1) {
@@ -624,15 +633,18 @@ __device__ __forceinline__ void em_rotate(EmWin<T>& W) {
 // ownership and the step's constants.  A strip owns OWNC columns after LH
 // left-halo lanes (the one-step marches: 61 after 1; the two-step march,
 // whose second step needs the first step's results one lane further out on
-// each side: 58 after 2).
+// each side: 58 after 2).  xshift moves the strip's columns left (the second
+// step of the two-step march with the moving window works in the frame the
+// first step's shift made).
 template <typename T, int OWNC = OWN, int LH = 1>
-__device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int m, int lane) {
+__device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int m, int lane, int xshift = 0) {
     const Geo& g = a.g;
     Ctx<T> c;
     c.g = g;
     c.m = m;
     c.lane = lane;
-    const int raw = strip * OWNC - LH + lane;
+    c.rzero = false;
+    const int raw = strip * OWNC - LH - xshift + lane;
     const bool inrange = raw >= 0 && raw < g.nx;
     c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
     c.owner = inrange && lane >= LH && lane < LH + OWNC;
@@ -1169,7 +1181,12 @@ __device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int c
     const int lane = threadIdx.x % WAVE;
     const int r0 = chunk * rows;
     const int r1 = min(g.nr + 1, r0 + rows);
-    const Ctx<T> c = make_ctx<T, kPairOwn, 2>(a, strip, m, lane);
+    // with the moving window the first step's result of lane k lands one
+    // column to the left, so the second step's strip starts one column
+    // further left and lane k still reads ring slot k; the first step's lanes
+    // on column nx put the zero-filled column the window brings in
+    Ctx<T> c = make_ctx<T, kPairOwn, 2>(a, strip, m, lane, wave == 1 ? a.window : 0);
+    if (wave == 0 && a.window) c.rzero = strip * kPairOwn - 2 + lane >= g.nx;
     const SetP<T>& s = WHICH ? a.s1 : a.s0;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     cx<T>* const ring = reinterpret_cast<cx<T>*>(smem_raw);
@@ -1232,6 +1249,16 @@ __device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int c
                 if (j == g.nr - 1) em_ghost_bth<T, IO_FROM_RING>(c, s2, W, B, r1, ring);
             }
             __syncthreads();
+        }
+        // moving window: the owner of the last cell zero-fills the last column
+        // of the new state, as the one-step march does
+        if (a.window && c.owner && c.i == g.nx - 1) {
+            for (int row = r0; row < r1; ++row) {
+                const uint32_t e = eoff<T>(g, m, row, g.nx - 1);
+                sto(s.otrp, e, zero<T>()); sto(s.otrm, e, zero<T>()); sto(s.ottp, e, zero<T>()); sto(s.ottm, e, zero<T>());
+                sto(s.oex, e, zero<T>()); sto(s.obx, e, zero<T>());
+                if (c.plasma) { sto(s.ojx, e, zero<T>()); sto(s.ojr, e, zero<T>()); sto(s.ojt, e, zero<T>()); }
+            }
         }
     }
 }

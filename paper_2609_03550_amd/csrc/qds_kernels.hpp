@@ -98,6 +98,7 @@ struct StepPlan {
     cx<T>* ja2[3];              // j_a of the second step of a pair of steps (null until used)
     cx<T>* sa;                  // scratch S_a plane (regenerated set only)
     cx<T>* jdrv;                // drive plane (j_x^(0) of mode 0; null until first used)
+    cx<T>* jdrv2;               // the drive plane of the second step of a pair
     int plasma, axion, arem;
     int theta;                  // staged path: theta-grid products instead of the direct convolution
     double wp2, ma2, s_phi, s_j;
@@ -185,6 +186,9 @@ __host__ __device__ inline int fused_strips(int nx) { return (nx + kFusedOwn - 1
 // results on lanes k-1 .. k+2, so a strip owns 58 columns (lanes 2-59).
 constexpr int kPairOwn = 58;
 __host__ __device__ inline int pair_strips(int nx) { return (nx + kPairOwn - 1) / kPairOwn; }
+// With the moving window the second step's strips start one column further
+// left, so one more column must be covered.
+__host__ __device__ inline int pair_strips(int nx, int window) { return pair_strips(nx + window); }
 
 // One launch of a batched kernel: the instances it covers (indices into the
 // argument tables), the first block of each (n + 1 entries, first[0] = 0, the

@@ -132,3 +132,49 @@ def test_pair_calls_in_a_row_and_uneven_counts():
     torch.cuda.synchronize()
     b = _run(wl, "f64", st, 16, 0, 6)
     _equal(a, b)
+
+
+def _window_wl(nx, wp2, noise):
+    d = I.Drive(amp=50.0, x0=60 * H, v=0.999, sx=10 * H, r0=0.0, sr=4 * I.DR, noise=noise, seed=3)
+    return I.Workload("pair_window", nx, 17, 3, 0, x_bc="window", wp2=wp2,
+                      pulses=(I.Pulse("y", 0.5, 1.0, 3 * I.LAMBDA, 20 * H, 50 * H),), drive=d)
+
+
+@pytest.mark.parametrize("dtype,nx,wp2,noise,rows,random", [
+    ("f64", 200, 0.01, 1e-3, 5, False), ("f64", 116, 0.0, 0.0, 3, False), ("f64", 117, 0.01, 1e-3, 1, True),
+    ("f64", 232, 0.01, 1e-3, 26, True), ("f32", 175, 0.01, 1e-3, 7, False), ("f32", 174, 0.0, 1e-3, 2, True)])
+def test_pair_moving_window_with_drive_equals_single_steps(dtype, nx, wp2, noise, rows, random):
+    """The moving window with the prescribed drive, in pairs: the second
+    step's strips start one column left (its lane k reads the first step's
+    result of lane k), the first step puts the column the window brings in
+    into the ring as zeros, and the drive is evaluated for both steps (the
+    second one column on).  Widths at and beside multiples of the 58-column
+    strip (the second step covers one more column), with and without the
+    plasma: 9 steps equal single steps bit for bit, counters included, and
+    the oracle in FP64."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = _window_wl(nx, wp2, noise)
+    out = []
+    for pair in (1, 0):
+        s = qds.Solver(wl, dtype=dtype)
+        s.set_option(qds.OPT_PAIR, pair)
+        s.set_option(qds.OPT_ROWS, rows)
+        if random:
+            st, g, ph = (_random_reachable_state if wp2 else _random_state_no_plasma)(wl, 50 + nx)
+            s.load_fields(st)
+        else:
+            s.load_pulses()
+        assert s.fused
+        w0 = s.window
+        s.step(9)
+        torch.cuda.synchronize()
+        assert s.window == w0 + 9
+        out.append(s)
+    _equal(out[0], out[1])
+    if dtype == "f64":
+        if random:
+            ref = Q.run(st, g, ph, 9)
+        else:
+            ref = P.oracle_run(wl, 9)
+        P.compare_states(out[0].fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)

@@ -171,8 +171,8 @@ def test_autotuned_tiles_change_no_result(dtype, pair):
     single steps, or pairs of steps with the two-step march of the
     regenerated set in place of kernel B) and the chosen tiles give
     bit-identical states to the default tiling, and the chosen heights are
-    candidates (for the two-step march: 16 rows and the heights that cut the
-    21 rows into 5, 3 and 2 chunks)."""
+    candidates (for the two-step march: 20 rows and the heights that cut the
+    21 rows into 4, 3 and 2 chunks)."""
     from paper_2609_03550_amd import qds
     wl = _full(70, 20, 3)
     a = qds.Solver(wl, dtype=dtype)
@@ -188,30 +188,36 @@ def test_autotuned_tiles_change_no_result(dtype, pair):
     rows, tuned = b.tiles()
     assert tuned and rows[0] in (8, 16, 24, 32) and rows[1] in (4, 6, 8, 16)
     if pair:
-        assert rows[2] == 16 and rows[3] in (16, 5, 7, 11)
+        assert rows[2] == 16 and rows[3] in (20, 6, 7, 11)
     else:
         assert rows[2] in (16, 32, 52, 64) and rows[3] == 11
     assert a.tiles() == ([16, 16, 16, 11], False)
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
-def test_autotuned_tiles_with_a_drive_change_no_result():
+@pytest.mark.parametrize("pair", [0, 1])
+def test_autotuned_tiles_with_a_drive_change_no_result(pair):
     """With a prescribed drive (moving window, no axion; the drive plane is
-    filled before every step) the autotuner's choice for the background set
-    is one of the candidates of the background set alone and the states are
-    bit-identical to the default tiling."""
+    filled before every step, both planes before every pair) the autotuner's
+    choice is one of the candidates of the background set alone (single
+    steps) or of the two-step march (pairs: 20 rows and the heights that cut
+    the 21 rows into 4, 3 and 2 chunks), and the states are bit-identical to
+    the default tiling."""
     from paper_2609_03550_amd import qds
     wl = I.driven_window(nx=200, nr=20, steps=0)
     d = wl.drive
     wl = wl.with_(drive=d.__class__(d.amp * 1e4, 90 * H, d.v, 10 * H, 0.0, 4 * DR, d.noise, d.seed))
     a = _solver(wl, "f64")
     b = _solver(wl, "f64")
+    for s in (a, b):
+        s.set_option(qds.OPT_PAIR, pair)
     b.set_option(qds.OPT_TUNE, 1)
-    a.step(12)
-    b.step(12)
+    a.step(18)
+    b.step(18)
     torch.cuda.synchronize()
     rows, tuned = b.tiles()
-    assert tuned and rows[0] in (8, 16, 26, 52)
+    assert tuned
+    assert rows[3] in (20, 6, 7, 11) if pair else rows[0] in (8, 16, 26, 52)
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
