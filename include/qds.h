@@ -151,7 +151,11 @@ qds_status qds_radial_mu_max(int32_t nr, double dr, int32_t modes, int32_t r_bc,
  * exactly then).  qds_step fails with QDS_ECFL when the axion is advanced
  * and dt^2 (mu_kg + m_a^2) > 4.  Allocates
  * the library's own scratch in device memory: with the regenerated set, four
- * planes (the three axion-current components and the axion source S_a). */
+ * planes (the three axion-current components and the axion source S_a).
+ * Later allocations of the handle, on first use: the pair buffer
+ * (qds_state_bytes plus three planes, QDS_OPT_PAIR with the regenerated set),
+ * two mode-0 drive planes (a prescribed drive on the fused kernels), three
+ * particle-current planes (QDS_J_PARTICLES on the fused kernels). */
 qds_status qds_init(const qds_grid* grid, int32_t modes, double dx, double dt, qds_handle* out);
 
 /* Bytes of one state buffer, the row pitch in elements, and the byte offset
@@ -211,7 +215,8 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 stream of the handle beside kernel B of step k (they share
  *                 no plane); events order it after the axion kernel of step
  *                 k, and every launch is joined back into the caller's
- *                 stream before qds_step returns.  0: one stream.
+ *                 stream before qds_step returns; steps are then single (it
+ *                 takes precedence over QDS_OPT_PAIR).  0: one stream.
  *  QDS_OPT_KERNEL_AX 1: with the regenerated set on the fused kernels (up
  *                 to 4 modes; always with the moving window), one launch
  *                 (kernel AX) advances the
