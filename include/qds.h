@@ -252,6 +252,16 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 4, 3 and 2 chunks); the timing slot of the march is that of
  *                 the set it advances, one launch per two steps.  1 is the
  *                 default; 0: single steps.
+ *  QDS_OPT_PAIR_A 1: in pairs with the regenerated set (up to 4 modes, its
+ *                 LDS within 160 KiB: 3 modes in FP64, 4 in FP32), the
+ *                 background set is advanced by its own two-step march with
+ *                 the axion source of both steps (2 x modes waves per tile,
+ *                 the first step's field planes and the second S_a to the
+ *                 pair buffer) in place of kernel A twice; tile height
+ *                 QDS_OPT_ROWS_A (tuner candidates 16, 24, 32, 43).  The
+ *                 results equal single steps bit for bit.  0 (default): kernel
+ *                 A twice (measured faster on MI355X: the march's 2 x modes
+ *                 waves in lockstep, one workgroup per CU in FP64).
  *  QDS_OPT_TIMING 1: qds_step brackets each kernel launch with a pair of HIP
  *                 events recorded on the caller's stream (no synchronisation;
  *                 the library keeps one pair per launch until reset); any
@@ -259,7 +269,7 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
 enum {
     QDS_OPT_PATH = 1, QDS_OPT_ROWS = 2, QDS_OPT_TIMING = 3, QDS_OPT_TUNE = 4,
     QDS_OPT_ROWS_A = 5, QDS_OPT_ROWS_CUR = 6, QDS_OPT_ROWS_B = 7, QDS_OPT_PRODUCTS = 8, QDS_OPT_OVERLAP = 9,
-    QDS_OPT_KERNEL_AX = 10, QDS_OPT_PAIR = 11, QDS_OPT_ROWS_PAIR = 12
+    QDS_OPT_KERNEL_AX = 10, QDS_OPT_PAIR = 11, QDS_OPT_ROWS_PAIR = 12, QDS_OPT_PAIR_A = 13
 };
 enum { QDS_PRODUCTS_DIRECT = 0, QDS_PRODUCTS_THETA = 1 };
 enum { QDS_PATH_AUTO = 0, QDS_PATH_STAGED = 1, QDS_PATH_FUSED = 2 };

@@ -24,6 +24,7 @@ const int kCandAX[4] = {16, 24, 32, 48};
 const int kCandCur[4] = {4, 6, 8, 16};
 const int kCandB[4] = {16, 32, 52, 64};
 const int kCandEm[4] = {8, 16, 26, 52};
+const int kCandA2[4] = {16, 24, 32, 43};
 // Tile heights of the two-step march (measured on MI355X): at 8192 x 256 x 3
 // it is fastest with every workgroup resident at once (129 rows, two chunks,
 // in FP64; 86 rows, three chunks, in FP32), at 4096 x 256 x 3 with about 20
@@ -84,6 +85,19 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
             t.xp[q][0] = axion_args<T>(c, p0, st->buf[q], c->pairbuf);
             t.fp[q][1] = fused_args<T>(c, p2, c->pairbuf, st->buf[1 - q]);
             t.xp[q][1] = axion_args<T>(c, p2, c->pairbuf, st->buf[1 - q]);
+            // the background set's two-step march: the first step's field
+            // planes into the pair buffer, the second S_a after its j_a planes
+            qds::cx<T>* P[QDS_NPLANES];
+            plane_table<T>(c, c->pairbuf, P);
+            qds::cx<T>* sa2 = p0.ja2[2] + c->plane_elems;
+            t.fa2[q] = fused_args<T>(c, p0, st->buf[q], st->buf[1 - q]);
+            t.fa2[q].mtrp = P[QDS_P_TRP]; t.fa2[q].mtrm = P[QDS_P_TRM];
+            t.fa2[q].mttp = P[QDS_P_TTP]; t.fa2[q].mttm = P[QDS_P_TTM];
+            t.fa2[q].mex = P[QDS_P_EX]; t.fa2[q].mbx = P[QDS_P_BX];
+            t.fa2[q].sa2 = sa2;
+            qds::StepPlan<T> p3 = p2;
+            p3.sa = sa2;
+            t.xp2[q] = axion_args<T>(c, p3, c->pairbuf, st->buf[1 - q]);
         }
     }
     const int strips = qds::fused_strips(c->g.nx);
@@ -93,6 +107,7 @@ qds_status sync_ktab(qds_ctx* c, const qds_state* st, const qds::StepPlan<T>& p0
     t.firstC[1] = qds::current_strips(c->g.nx) * chunks(c->trows[1]);
     t.firstB[1] = strips * chunks(c->trows[2]) * c->M;
     t.firstB2[1] = qds::pair_strips(c->g.nx, c->g.x_bc == QDS_X_WINDOW ? 1 : 0) * chunks(c->trows[3]) * c->M;
+    t.firstA2[1] = qds::pair_strips(c->g.nx) * chunks(c->trows[0]);
     // the staging copy may still be read by the previous upload
     if (c->ktab_valid && hipEventSynchronize(c->ktab_ev) != hipSuccess)
         return fail(c, QDS_EHIP, "argument table upload failed%s");
@@ -117,20 +132,21 @@ struct TabView {
     const int* firstC;
     const int* firstB;
     const int* firstB2;
-    int nA, nC, nB, nB2;
+    const int* firstA2;
+    int nA, nC, nB, nB2, nA2;
 };
 
 template <typename T>
 TabView<T> ktab_view(KTab<T>* K, const KTab<T>& host, int q) {
-    return TabView<T>{K->fa + q, K->xa + q, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2,
-                      host.firstA[1], host.firstC[1], host.firstB[1], host.firstB2[1]};
+    return TabView<T>{K->fa + q, K->xa + q, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2, K->firstA2,
+                      host.firstA[1], host.firstC[1], host.firstB[1], host.firstB2[1], host.firstA2[1]};
 }
 
 // The three launches of one fused step through an argument-table entry:
 // kernel A (or the background set alone), the axion kernel and the
 // regenerated set, each on stream s and bracketed by the event pair e when
 // given (or by a timing pair when timing is on).
-enum { kLaunchA = 0, kLaunchX = 1, kLaunchB = 2, kLaunchB2 = 3 };
+enum { kLaunchA = 0, kLaunchX = 1, kLaunchB = 2, kLaunchB2 = 3, kLaunchA2 = 4 };
 
 template <typename T>
 qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabView<T>& v, int which, hipStream_t s,
@@ -146,7 +162,9 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
     // timing slots: 0 kernel A (or the background set alone, also its
     // two-step march), 1 the regenerated set (also its two-step march), 2 the
     // axion kernel
-    const int slot = which == kLaunchA ? 0 : (which == kLaunchX ? 2 : (which == kLaunchB2 && !p0.arem ? 0 : 1));
+    const int slot = (which == kLaunchA || which == kLaunchA2)
+                         ? 0
+                         : (which == kLaunchX ? 2 : (which == kLaunchB2 && !p0.arem ? 0 : 1));
     hipEvent_t* ev = e ? e : (c->timing ? timing_pair(c, slot) : nullptr);
     if (ev && hipEventRecord(ev[0], s) != hipSuccess) return fail(c, QDS_EHIP, "event record failed%s");
     hipError_t err = hipSuccess;
@@ -165,6 +183,8 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
         err = qds::batch_current<T>(v.xa, list(v.firstC, c->trows[1]), c->M, v.nC, s);
     } else if (which == kLaunchB2) {
         err = qds::batch_em2<T>(v.fa, list(v.firstB2, c->trows[3]), p0.arem ? 1 : 0, v.nB2, s);
+    } else if (which == kLaunchA2) {
+        err = qds::batch_a2<T>(v.fa, list(v.firstA2, c->trows[0]), c->M, v.nA2, s);
     } else {
         err = qds::batch_em<T>(v.fa, list(v.firstB, c->trows[2]), 1, v.nB, s);
     }
@@ -224,7 +244,15 @@ qds_status pair_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab
             e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv2, st->step + 1, st->window + (window ? 1 : 0), s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     }
-    if (p0.arem) {
+    if (p0.arem && pair_a2(c, p0)) {
+        // the background set's two-step march, then the axion kernel of each step
+        TabView<T> va = v, vb = v;
+        va.fa = &K->fa2[q]; va.xa = &K->xp[q][0];
+        vb.xa = &K->xp2[q];
+        if ((r = table_launch_one<T>(c, p0, va, kLaunchA2, s, ev)) != QDS_OK) return r;
+        if ((r = table_launch_one<T>(c, p0, va, kLaunchX, s, ev ? ev + 2 : nullptr)) != QDS_OK) return r;
+        if ((r = table_launch_one<T>(c, p0, vb, kLaunchX, s, nullptr)) != QDS_OK) return r;
+    } else if (p0.arem) {
         TabView<T> va = v, vb = v;
         va.fa = &K->fp[q][0]; va.xa = &K->xp[q][0];
         vb.fa = &K->fp[q][1]; vb.xa = &K->xp[q][1];
@@ -318,9 +346,8 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
     const bool pairs = pair_ok(c, p0) && n_steps >= 2;
     if (pairs && p0.arem && !c->pairbuf) {
         // the background set and the axion between the two steps of a pair,
-        // then the second step's axion current
-        const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
-        if (hipMalloc(&c->pairbuf, sbytes + 3 * c->plane_elems * c->elem_bytes) != hipSuccess) {
+        // then the second step's axion current and axion source
+        if (hipMalloc(&c->pairbuf, pairbuf_bytes(c)) != hipSuccess) {
             c->pairbuf = nullptr;
             return fail(c, QDS_ENOMEM, "hipMalloc of the pair buffer failed%s");
         }
@@ -340,8 +367,9 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
         // axion kernel, 2 kernel B or the two-step march.
         int candB2[4];
         cand_pair(c, candB2);
-        const int* cand[3] = {fuse_ax(c, p0) ? kCandAX : (p0.axion ? kCandA : kCandEm), kCandCur,
-                              pairs ? candB2 : kCandB};
+        const int* cand[3] = {fuse_ax(c, p0) ? kCandAX
+                                             : (pairs && pair_a2(c, p0) ? kCandA2 : (p0.axion ? kCandA : kCandEm)),
+                              kCandCur, pairs ? candB2 : kCandB};
         int* const tr[3] = {&c->trows[0], &c->trows[1], pairs ? &c->trows[3] : &c->trows[2]};
         const bool run[3] = {!(pairs && !p0.arem), p0.arem && !fuse_ax(c, p0), p0.arem || pairs};
         std::vector<hipEvent_t> ev(6 * kTrials);
@@ -615,8 +643,9 @@ qds_status backward_impl(qds_ctx* c, const qds_state* u0, const qds_current* J, 
         for (int64_t k = 0; k < n1 - n0; ++k) {
             if (tab) {
                 // fused kernels through the segment's argument table
-                const TabView<T> v{tab + k, xtab + k, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2,
-                                   khost.firstA[1], khost.firstC[1], khost.firstB[1], khost.firstB2[1]};
+                const TabView<T> v{tab + k, xtab + k, K->idx, K->firstA, K->firstC, K->firstB, K->firstB2, K->firstA2,
+                                   khost.firstA[1], khost.firstC[1], khost.firstB[1], khost.firstB2[1],
+                                   khost.firstA2[1]};
                 qds_status st = table_launch<T>(c, p, v, s, nullptr);
                 if (st != QDS_OK) return st;
                 continue;
@@ -834,6 +863,9 @@ qds_status qds_set_option(qds_handle h, int32_t key, int64_t value) {
             return QDS_OK;
         case QDS_OPT_PAIR:
             h->pair = value ? 1 : 0;
+            return QDS_OK;
+        case QDS_OPT_PAIR_A:
+            h->pair_a = value ? 1 : 0;
             return QDS_OK;
         case QDS_OPT_ROWS_PAIR:
             if (value < 1 || value > 4096) return fail(h, QDS_EINVAL, "rows must be 1..4096%s");

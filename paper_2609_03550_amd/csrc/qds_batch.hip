@@ -328,8 +328,7 @@ qds_status run_impl(qds_batch_ctx* b, qds_state* states, const qds_current* J, c
         for (qds_ctx* c : b->inst) {
             if (!has(c, QDS_P_SET1) || c->pairbuf) continue;
             // the instance's pair buffer, as qds_step allocates it
-            const size_t sbytes = size_t(c->nplanes) * c->plane_elems * c->elem_bytes;
-            if (hipMalloc(&c->pairbuf, sbytes + 3 * c->plane_elems * c->elem_bytes) != hipSuccess) {
+            if (hipMalloc(&c->pairbuf, pairbuf_bytes(c)) != hipSuccess) {
                 c->pairbuf = nullptr;
                 return bfail(b, QDS_ENOMEM, "hipMalloc of a pair buffer failed%s");
             }

@@ -21,8 +21,8 @@ struct qds_ctx {
     void* drive_plane;       // j_x^(0) of the prescribed drive, mode 0, for two steps (allocated on first use)
     void* psrc;              // particle currents at the source points, 3 planes (allocated on first use)
     void* pairbuf;           // pairs of steps with the regenerated set: a state-sized buffer for the
-                             // background set and axion between the two steps, then j_a of the
-                             // second step (3 planes); allocated on first use
+                             // background set and axion between the two steps, then j_a (3 planes)
+                             // and S_a (1 plane) of the second step; allocated on first use
     int path;                // QDS_PATH_*
     int theta;               // QDS_PRODUCTS_THETA: theta-grid products (staged path)
     int rows;                // the last QDS_OPT_ROWS value (also copied into trows)
@@ -33,6 +33,7 @@ struct qds_ctx {
     int overlap;             // kernel A of step k+1 on a second stream beside kernel B of step k
     int kernel_ax;           // 1: one-pass kernel AX instead of kernel A and the marched axion kernel
     int pair;                // 1: advance steps in pairs with the two-step march of one set where it applies
+    int pair_a;              // 1: in pairs, the background set too by its two-step march with the axion source
     hipStream_t side;        // that stream (created on first use, default priority)
     hipEvent_t ev_x, ev_a;   // its ordering events
     // timing events, recorded without synchronising and resolved by
@@ -77,6 +78,12 @@ inline qds_status fail(qds_ctx* c, qds_status s, const char* fmt, const char* de
 }
 
 inline bool has(const qds_ctx* c, int plane) { return c->slot[plane] >= 0; }
+
+// Bytes of the pair buffer: a state, then j_a (3 planes) and S_a (1 plane) of
+// a pair's second step.
+inline size_t pairbuf_bytes(const qds_ctx* c) {
+    return (size_t(c->nplanes) + 4) * c->plane_elems * c->elem_bytes;
+}
 
 template <typename T>
 void plane_table(const qds_ctx* c, void* base, qds::cx<T>** out) {
@@ -254,6 +261,15 @@ bool pair_ok(const qds_ctx* c, const qds::StepPlan<T>& p0) {
     return !p0.axion;
 }
 
+// Whether a pair of steps also advances the background set by its two-step
+// march with the axion source (in place of kernel A twice): QDS_OPT_PAIR_A,
+// the regenerated set in pairs, up to 4 modes, and its LDS within a CU.
+template <typename T>
+bool pair_a2(const qds_ctx* c, const qds::StepPlan<T>& p0) {
+    return c->pair_a && pair_ok(c, p0) && p0.arem && c->M <= 4 &&
+           qds::a2_lds_bytes(c->M, c->elem_bytes / 2) <= 160 * 1024;
+}
+
 // Axion-current arguments of the same step.
 template <typename T>
 qds::AxionArgs<T> axion_args(const qds_ctx* c, const qds::StepPlan<T>& p0, void* bufA, void* bufB) {
@@ -287,8 +303,13 @@ struct KTab {
     // the two-step march of the regenerated set uses fa[q]
     qds::FusedArgs<T> fp[2][2];
     qds::AxionArgs<T> xp[2][2];
+    // with the background set's two-step march: its arguments (buffer q to
+    // buffer 1 - q, the first step's field planes and the second S_a in the
+    // pair buffer) and those of the second axion kernel (reading that S_a)
+    qds::FusedArgs<T> fa2[2];
+    qds::AxionArgs<T> xp2[2];
     int idx[2];
-    int firstA[2], firstC[2], firstB[2], firstB2[2];
+    int firstA[2], firstC[2], firstB[2], firstB2[2], firstA2[2];
 };
 
 }  // namespace qdsi

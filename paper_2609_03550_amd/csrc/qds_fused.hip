@@ -158,6 +158,7 @@ struct Ctx {
     // lane's column is the one the window brings in, so what it puts in the
     // ring is the zero-filled state
     bool rzero;
+    int gr0, gr1;    // IO_RING_G: rows whose field values also go to the output planes
 };
 
 // reciprocal radii of one march step: 1/r_{j+1}, 1/r_{j+1/2}, 1/r_j (0 on the axis)
@@ -264,7 +265,11 @@ __device__ __forceinline__ EmB<T> em_bvals(const Ctx<T>& c, const EmWin<T>& W) {
 // step reads them in place of the state planes.  IO_FROM_RING (that second
 // step): global stores as IO_GLOBAL, and the old plasma j_theta that the
 // exterior ghost reads comes from the ring.
-enum { IO_GLOBAL = 0, IO_RING = 1, IO_FROM_RING = 2 };
+// IO_RING_G (the first step of the background set's two-step march with the
+// axion source): the ring as IO_RING and, for the rows [c.gr0, c.gr1), the
+// field planes (T^+-, E_x, B_x: what the axion kernel reads) to the output
+// planes as IO_GLOBAL; the currents go to the ring only.
+enum { IO_GLOBAL = 0, IO_RING = 1, IO_FROM_RING = 2, IO_RING_G = 3 };
 
 // The LDS ring of the two-step march: the 9 planes of one set (T_r^+-,
 // T_theta^+-, E_x, B_x, j_x, j_r, j_theta) for 4 consecutive rows (row k in
@@ -428,32 +433,40 @@ template <typename T, int IO = IO_GLOBAL>
 __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin<T>& W, const EmB<T>& B, int j,
                                         int r0, int r1, const RowInv<T>& ri, const EmRowX<T>& X,
                                         cx<T>* ring = nullptr) {
-    constexpr bool RING = IO == IO_RING;
+    constexpr bool RING = IO == IO_RING || IO == IO_RING_G;   // results to the ring
+    constexpr bool GLOB = IO != IO_RING;                        // field values to the output planes
+    constexpr int IOJ = IO == IO_RING_G ? IO_RING : IO;         // where the currents go
     const Geo& g = c.g;
     const int m = c.m;
     const T h = c.h;
     const int ocI = c.o.col(c.i);     // output column of integer column i
     const bool wI = c.owner && ocI >= 0;
+    // rows stored to the output planes
+    const int gr0 = IO == IO_RING_G ? c.gr0 : r0;
+    const int gr1 = IO == IO_RING_G ? c.gr1 : r1;
     // ---- E_x^{n+1/2} at J = j+1
     if (j + 1 <= g.nr) {
-        W.jx_n1 = em_jx<T, IO>(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa, ring);
+        W.jx_n1 = em_jx<T, IOJ>(c, s, j + 1, W.ex0[1], j + 1 >= r0 && j + 1 < r1, W.pjx, W.pjxa, ring);
         W.ex1[2] = em_ex_new(c, W, B, j + 1, W.jx_n1, ri.irJ1);
         if constexpr (RING) {
             if (j + 1 >= r0 && j + 1 < r1) rput(c, ring, RG_EX, j + 1, W.ex1[2]);
-        } else {
-            if (j + 1 >= r0 && j + 1 < r1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
+        }
+        if constexpr (GLOB) {
+            if (j + 1 >= gr0 && j + 1 < gr1 && wI) sto(s.oex, eoff<T>(g, m, j + 1, ocI), W.ex1[2]);
         }
         if (j + 1 == g.nr) W.jx_nr = W.jx_n1;
     }
     if (j < 0) return;
     const bool own_row = j >= r0 && j < r1;
+    const bool g_own = j >= gr0 && j < gr1;
     // ---- B_x^{n+1/2} at K = j
     if (j < g.nr) {
         W.bx1[1] = em_bx_new(c, W, B, ri.irK);
         if constexpr (RING) {
             if (own_row) rput(c, ring, RG_BX, j, W.bx1[1]);
-        } else {
-            if (own_row && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
+        }
+        if constexpr (GLOB) {
+            if (g_own && wI) sto(s.obx, eoff<T>(g, m, j, ocI), W.bx1[1]);
         }
     }
     // ---- exterior ghost B_x^{n+1/2} at r_{nr+1/2} (Eq. em_r_open_bx)
@@ -487,8 +500,9 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         W.bx1g = gh;
         if constexpr (RING) {
             if (r1 == g.nr + 1) rput(c, ring, RG_BX, g.nr, gh);
-        } else {
-            if (r1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
+        }
+        if constexpr (GLOB) {
+            if (gr1 == g.nr + 1 && wI) sto(s.obx, eoff<T>(g, m, g.nr, ocI), gh);
         }
     }
     // ---- T_r transport on K = j
@@ -529,7 +543,8 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
                 rput(c, ring, RG_TRP, j, W.n_rpa);
                 rput(c, ring, RG_TRM, j, W.n_rma);
             }
-        } else if (own_row) {
+        }
+        if (GLOB && g_own) {
             if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_rpb);
             if (wI) sto(s.otrm, eoff<T>(g, m, j, ocI), W.n_rma);
             if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.otrp, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
@@ -540,7 +555,7 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
         const bool zrow = (!g.open_r && j == g.nr) || (j == 0 && m != 1);
         cx<T> jt = zero<T>();
         const cx<T> jt1 = c.plasma ? c.x.Rn(X.jt) : zero<T>();   // uniform control flow here
-        if (c.plasma) jt = em_jt_avg<T, IO>(c, s, W, B, j, 0, own_row, X.jt, jt1, ring);
+        if (c.plasma) jt = em_jt_avg<T, IOJ>(c, s, W, B, j, 0, own_row, X.jt, jt1, ring);
         if (s.jta && c.live) jt = jt + X.jta;
         cx<T> sp = zero<T>(), sm = zero<T>();
         if (c.live && !zrow) {
@@ -572,7 +587,8 @@ __device__ __forceinline__ void em_step(const Ctx<T>& c, const SetP<T>& s, EmWin
                 rput(c, ring, RG_TTP, j, W.n_tpa);
                 rput(c, ring, RG_TTM, j, W.n_tma);
             }
-        } else if (own_row) {
+        }
+        if (GLOB && g_own) {
             if (wI) sto(s.ottp, eoff<T>(g, m, j, ocI), W.n_tpa);
             if (c.owner && c.x.ir >= 0 && c.o.col(c.x.ir) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(c.x.ir)), W.n_tmb);
             if (c.owner && c.i == 0 && !g.per && c.o.col(0) >= 0) sto(s.ottm, eoff<T>(g, m, j, c.o.col(0)), zero<T>());
@@ -605,12 +621,14 @@ __device__ __forceinline__ void em_ghost_bth(const Ctx<T>& c, const SetP<T>& s, 
         cx<T> rt = -T(0.5) * dxer - (T(1) / (T(2) * rN)) * (T(0.5) * (I0 + G0) + imul(T(m), br)) + T(0.5) * jxi;
         out = I0 + kap * (G0 - I1) + cR * rt;
     }
-    if constexpr (IO == IO_RING) {
+    if constexpr (IO == IO_RING || IO == IO_RING_G) {
         // the second step reads the ghost row through T_r^+ alone
         if (r1 == g.nr + 1) rput(c, ring, RG_TRP, N, out);
-    } else {
+    }
+    if constexpr (IO != IO_RING) {
         const int oc = c.o.col(c.i);
-        if (c.owner && oc >= 0 && r1 == g.nr + 1) {
+        const int gr1 = IO == IO_RING_G ? c.gr1 : r1;
+        if (c.owner && oc >= 0 && gr1 == g.nr + 1) {
             sto(s.otrp, eoff<T>(g, m, N, oc), out);
             sto(s.otrm, eoff<T>(g, m, N, oc), zero<T>());
         }
@@ -644,6 +662,7 @@ __device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int
     c.m = m;
     c.lane = lane;
     c.rzero = false;
+    c.gr0 = c.gr1 = 0;
     const int raw = strip * OWNC - LH - xshift + lane;
     const bool inrange = raw >= 0 && raw < g.nx;
     c.i = g.per ? ((raw % g.nx) + g.nx) % g.nx : (raw < 0 ? 0 : (raw >= g.nx ? g.nx - 1 : raw));
@@ -671,6 +690,36 @@ __device__ __forceinline__ Ctx<T> make_ctx(const FusedArgs<T>& a, int strip, int
 // LDS exchange slots per lane: the 6 factors of the axion source (two such
 // buffers, alternating by row)
 constexpr int NS = 6;
+
+// The factors of the axion source at K = j (Eqs. source_mode_zero,
+// source_mode_m) of mode m from the window after em_step on row j: E_x and
+// B_x at t^n, and the transport-variable form of the transverse part,
+//   C{E_r, B_r} + C{E_th, B_th}
+//     = 1/2 C{T_r^+ + b_th, T_th^+ + b_r} - 1/2 C{T_r^- - b_th, T_th^- - b_r}
+// (exact; no cancellation between two large products for co-propagating
+// waves); ex1_j is E_x^{n+1/2}(J = j), taken before em_step moved it on.
+// The source is sum C_m{f0, f1} + C_m{f2, f3} + C_m{f4, f5}.
+template <typename T>
+__device__ __forceinline__ void sa_factors(const FusedArgs<T>& a, int m, const EmWin<T>& W, const EmB<T>& B,
+                                           cx<T> ex1_j, cx<T>* f) {
+    cx<T> bx_n = T(0.5) * (W.bx0[0] + W.bx1[1]);
+    cx<T> exn0 = T(0.5) * (W.ex0[0] + ex1_j);
+    cx<T> exn1 = T(0.5) * (W.ex0[1] + W.ex1[2]);
+    cx<T> fEx = T(0.5) * (exn0 + exn1);
+    cx<T> fBx = bx_n;
+    cx<T> fPp = T(0.25) * (W.rpa[0] + B.rpb[0]);
+    cx<T> fPm = T(-0.25) * (W.rma[0] + B.rmb[0]);
+    cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (B.tpb[0] + B.tpb[1]));
+    cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (B.tmb[0] + B.tmb[1]));
+    if (m == 0) fBx = fBx + a.bx0;
+    if (m == 1) {
+        fPp = fPp + T(0.5) * a.bt1;
+        fPm = fPm + T(0.5) * a.bt1;
+        fQp = fQp + a.br1;
+        fQm = fQm - a.br1;
+    }
+    f[0] = fEx; f[1] = fBx; f[2] = fPp; f[3] = fQp; f[4] = fPm; f[5] = fQm;
+}
 
 // ---------------------------------------------------------------------------
 // kernel A: background set + axion
@@ -759,26 +808,10 @@ __device__ __forceinline__ void fused_a_body(const FusedArgs<T>& a, int strip, i
         cx<T> Sa = zero<T>();
         cx<T> ga = zero<T>();
         if (j < g.nr) {
-            cx<T> bx_n = T(0.5) * (W.bx0[0] + W.bx1[1]);
-            cx<T> exn0 = T(0.5) * (W.ex0[0] + ex1_j);
-            cx<T> exn1 = T(0.5) * (W.ex0[1] + W.ex1[2]);
-            cx<T> fEx = T(0.5) * (exn0 + exn1);
-            cx<T> fBx = bx_n;
-            // transverse part from the transport variables: C{E_r, B_r} + C{E_th, B_th}
-            // = 1/2 C{T_r^+ + b_th, T_th^+ + b_r} - 1/2 C{T_r^- - b_th, T_th^- - b_r}
-            // (exact; no cancellation between two large products for co-propagating waves)
-            cx<T> fPp = T(0.25) * (W.rpa[0] + B.rpb[0]);
-            cx<T> fPm = T(-0.25) * (W.rma[0] + B.rmb[0]);
-            cx<T> fQp = T(0.25) * ((W.tpa[0] + W.tpa[1]) + (B.tpb[0] + B.tpb[1]));
-            cx<T> fQm = T(0.25) * ((W.tma[0] + W.tma[1]) + (B.tmb[0] + B.tmb[1]));
-            if (m == 0) fBx = fBx + a.bx0;
-            if (m == 1) {
-                fPp = fPp + T(0.5) * a.bt1;
-                fPm = fPm + T(0.5) * a.bt1;
-                fQp = fQp + a.br1;
-                fQm = fQm - a.br1;
-            }
-            put(smS, 0, fEx); put(smS, 1, fBx); put(smS, 2, fPp); put(smS, 3, fQp); put(smS, 4, fPm); put(smS, 5, fQm);
+            cx<T> f[NS];
+            sa_factors(a, m, W, B, ex1_j, f);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) put(smS, q, f[q]);
         }
         __syncthreads();
         if (j < g.nr) {
@@ -1264,6 +1297,130 @@ __device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int c
 }
 
 // ---------------------------------------------------------------------------
+// two steps of the background set with the axion source of each (temporal
+// blocking of kernel A): a workgroup of 2M waves over one (strip, chunk).
+// Waves 0..M-1 run the first step of modes 0..M-1 as kernel A does, putting
+// their rows into a per-mode LDS ring and their field values (T^+-, E_x, B_x,
+// which the axion kernel reads) into the intermediate planes; waves M..2M-1
+// run the second step two rows behind from the ring, into the output planes.
+// Each group forms S_a of its step through its own exchange area.  Two
+// barriers per row: after the rows' ring writes and factors, and after the
+// convolutions, so a factor slot is rewritten only once every wave of its
+// group has read it; the ring keeps the lag and slot rules of em2_body.
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__device__ __forceinline__ void fused_a2_body(const FusedArgs<T>& a, int strip, int chunk, int rows) {
+    const Geo g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int grp = wave / M;        // 0: first step, 1: second step (wave-uniform)
+    const int m = wave - grp * M;
+    const int lane = threadIdx.x % WAVE;
+    const int r0 = chunk * rows;
+    const int r1 = min(g.nr + 1, r0 + rows);
+    Ctx<T> c = make_ctx<T, kPairOwn, 2>(a, strip, m, lane);
+    c.gr0 = r0;
+    c.gr1 = r1;
+    const SetP<T>& s = a.s0;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    cx<T>* const base = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* const ring = base + m * (RG_N * RING_ROWS * WAVE);
+    cx<T>* const xch = base + M * (RG_N * RING_ROWS * WAVE);   // [2 groups][NS][M][WAVE]
+    auto put = [&](int f, cx<T> v) { xch[((grp * NS + f) * M + m) * WAVE + lane] = v; };
+    auto gS = [&](int f, int k) { return xch[((grp * NS + f) * M + k) * WAVE + lane]; };
+    // the rows of the two steps, as in em2_body
+    const int jsc = max(r0 - (r1 == g.nr + 1 ? 2 : 1), -1);
+    const int jec = r1 == g.nr + 1 ? g.nr : r1 - 1;
+    const int p0 = max(jsc, 0);
+    const int p1 = min(jec + 2, g.nr + 1);
+    const int jsp = max(p0 - (p1 == g.nr + 1 ? 2 : 1), -1);
+    const int jep = p1 == g.nr + 1 ? g.nr : p1 - 1;
+    EmWin<T> W;
+    for (int q = 0; q < 2; ++q) {
+        W.rpa[q] = W.rma[q] = zero<T>();
+        W.tpa[q] = W.tma[q] = zero<T>();
+        W.ex0[q] = W.bx0[q] = W.bx1[q] = zero<T>();
+    }
+    W.ex1[0] = W.ex1[1] = W.ex1[2] = zero<T>();
+    W.bx1g = W.jx_n1 = W.jx_nr = zero<T>();
+    W.pjx = W.pjxa = zero<T>();
+    // S_a of row k from the factors the group put: stored for the rows
+    // [r0, r1) (unshifted columns, as kernel A)
+    auto sa_store = [&](int k, cx<T>* out) {
+        cx<T> Sa = zero<T>();
+        conv_pair<T, M>(gS, 0, 1, m, Sa, T(1));
+        conv_pair<T, M>(gS, 2, 3, m, Sa, T(1));
+        conv_pair<T, M>(gS, 4, 5, m, Sa, T(1));
+        if (!c.live) Sa = zero<T>();
+        if (k >= r0 && k < r1 && c.owner) sto(out, eoff<T>(g, m, k, c.i), Sa);
+    };
+    if (grp == 0) {
+        // the first step's field planes go to the intermediate planes
+        SetP<T> sp = s;
+        sp.otrp = a.mtrp; sp.otrm = a.mtrm; sp.ottp = a.mttp; sp.ottm = a.mttm; sp.oex = a.mex; sp.obx = a.mbx;
+        if (jsp >= 0) em_take(c, W, em_fetch(c, s, jsp), jsp, g.nr);
+        EmPf<T> pf = em_fetch(c, s, jsp + 1);
+        for (int t = jsp; t <= jec + 2; ++t) {
+            bool sa_row = false;
+            if (t <= jep) {
+                em_rotate(W);
+                em_take(c, W, pf, t + 1, g.nr);
+                if (t < jep) pf = em_fetch(c, s, t + 2);
+                const EmRowX<T> X = em_fetch_x(c, s, t);
+                const EmB<T> B = em_bvals(c, W);
+                const cx<T> ex1_t = W.ex1[1];
+                em_step<T, IO_RING_G>(c, sp, W, B, t, p0, p1, row_inv(c, t), X, ring);
+                if (t == g.nr - 1) em_ghost_bth<T, IO_RING_G>(c, sp, W, B, p1, ring);
+                if (t >= 0 && t < g.nr) {
+                    cx<T> f[NS];
+                    sa_factors(a, m, W, B, ex1_t, f);
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) put(q, f[q]);
+                    sa_row = true;
+                }
+            }
+            __syncthreads();
+            if (sa_row) sa_store(t, a.sa);
+            __syncthreads();
+        }
+    } else {
+        SetP<T> s2 = s;    // the second step's extra currents
+        s2.jxa = s.jxb; s2.jra = s.jrb; s2.jta = s.jtb;
+        cx<T> xa_pre = em_xa(c, s2, jsc);
+        cx<T> xa_nxt = em_xa(c, s2, jsc + 1);
+        EmRowX<T> xrt = em_xrt(c, s2, jsc);
+        for (int t = jsp; t <= jec + 2; ++t) {
+            const int j = t - 2;
+            bool sa_row = false;
+            if (j == jsc - 1) {
+                if (jsc >= 0) em_take(c, W, em_fetch_ring(c, ring, jsc, xa_pre), jsc, g.nr);
+            } else if (j >= jsc && j <= jec) {
+                em_rotate(W);
+                em_take(c, W, em_fetch_ring(c, ring, j + 1, xa_nxt), j + 1, g.nr);
+                const EmRowX<T> X = em_fetch_x_ring(c, ring, j, xrt);
+                if (j < jec) {
+                    xa_nxt = em_xa(c, s2, j + 2);
+                    xrt = em_xrt(c, s2, j + 1);
+                }
+                const EmB<T> B = em_bvals(c, W);
+                const cx<T> ex1_j = W.ex1[1];
+                em_step<T, IO_FROM_RING>(c, s2, W, B, j, r0, r1, row_inv(c, j), X, ring);
+                if (j == g.nr - 1) em_ghost_bth<T, IO_FROM_RING>(c, s2, W, B, r1, ring);
+                if (j >= 0 && j < g.nr) {
+                    cx<T> f[NS];
+                    sa_factors(a, m, W, B, ex1_j, f);
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) put(q, f[q]);
+                    sa_row = true;
+                }
+            }
+            __syncthreads();
+            if (sa_row) sa_store(j, a.sa2);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batched launches: block -> (instance, tile) through the launch's list; the
 // instance's arguments are read from a device table
 // ---------------------------------------------------------------------------
@@ -1314,6 +1471,16 @@ __global__ void __launch_bounds__(WAVE) k_batch_em(const FusedArgs<T>* __restric
     const int m = local % a.g.M;                 // the modes of one tile run side by side
     const int t = local / a.g.M;
     em_body<T, WHICH>(a, t / chunks, t % chunks, m, L.rows);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(2 * WAVE * M) k_batch_a2(const FusedArgs<T>* __restrict__ args, BatchList L) {
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = batch_find(L, b);
+    const FusedArgs<T>& a = args[L.idx[k]];
+    const int local = b - L.first[k];
+    const int strips = pair_strips(a.g.nx);   // strips fastest, as kernel A
+    fused_a2_body<T, M>(a, local % strips, local / strips, L.rows);
 }
 
 template <typename T, int WHICH>
@@ -1415,6 +1582,29 @@ hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, in
     return hipGetLastError();
 }
 
+size_t a2_lds_bytes(int M, size_t elem_bytes) {
+    return size_t(M) * (size_t(fused::RG_N) * fused::RING_ROWS + 2 * fused::NS) * fused::WAVE * 2 * elem_bytes;
+}
+
+template <typename T>
+hipError_t batch_a2(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = a2_lds_bytes(M, sizeof(T));
+    switch (M) {
+#define QDS_BA2(MM)                                                                                       \
+    case MM: {                                                                                            \
+        static const hipError_t attr = allow_lds(reinterpret_cast<const void*>(&fused::k_batch_a2<T, MM>), lds); \
+        if (attr != hipSuccess) return attr;                                                              \
+        hipLaunchKernelGGL((fused::k_batch_a2<T, MM>), dim3(blocks), dim3(2 * fused::WAVE * MM), lds, s, args, L); \
+        break;                                                                                            \
+    }
+        QDS_BA2(1) QDS_BA2(2) QDS_BA2(3) QDS_BA2(4)
+#undef QDS_BA2
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template hipError_t batch_a<double>(const FusedArgs<double>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_a<float>(const FusedArgs<float>*, const BatchList&, int, int, bool, hipStream_t);
 template hipError_t batch_ax<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
@@ -1423,6 +1613,8 @@ template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&,
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_a2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
+template hipError_t batch_a2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);
 template hipError_t drive_plane<float>(const Drive&, const Geo&, cx<float>*, int64_t, int64_t, hipStream_t);
 

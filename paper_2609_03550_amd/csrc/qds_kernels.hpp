@@ -172,6 +172,11 @@ struct FusedArgs {
     // non-null: kernel A writes the axion source S_a here (unshifted columns,
     // no moving window) and leaves T_a and phi to the axion-current march
     cx<T>* sa;
+    // the background set's two-step march with the axion source: the first
+    // step's field planes (T^+-, E_x, B_x, what the axion kernel reads) and
+    // the second step's S_a
+    cx<T>* mtrp; cx<T>* mtrm; cx<T>* mttp; cx<T>* mttm; cx<T>* mex; cx<T>* mbx;
+    cx<T>* sa2;
     int plasma, axion;
     double wp2, ma2, s_phi, s_j;
     cx<T> bx0, br1, bt1;
@@ -246,6 +251,14 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
 // Tiles of pair_strips(nx) strips x rows-high chunks x modes, 128 threads each.
 template <typename T>
 hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
+// Two steps of the background set with the axion source of each (2M waves per
+// tile of pair_strips(nx) strips x rows-high chunks): reads s0's A planes,
+// writes the first step's field planes to mtrp..mbx and its S_a to sa, the
+// second step's state to s0's B planes and its S_a to sa2.  LDS: M x 48 KiB
+// in FP64, M x 24 KiB in FP32 (a2_lds_bytes), at most 160 KiB.
+template <typename T>
+hipError_t batch_a2(const FusedArgs<T>* args, const BatchList& L, int M, int blocks, hipStream_t s);
+size_t a2_lds_bytes(int M, size_t elem_bytes);
 // Kernel AX: the background set, the axion source, the axion advance and the
 // axion current in one launch (every instance of the list has sa set).
 template <typename T>

@@ -34,6 +34,7 @@ OPT_PRODUCTS = 8
 OPT_OVERLAP = 9
 OPT_KERNEL_AX = 10
 OPT_PAIR, OPT_ROWS_PAIR = 11, 12                     # two steps per launch of the set's march
+OPT_PAIR_A = 13                                      # in pairs, the background set's two-step march too
 PRODUCTS_DIRECT, PRODUCTS_THETA = 0, 1
 PATH_AUTO, PATH_STAGED, PATH_FUSED = 0, 1, 2
 

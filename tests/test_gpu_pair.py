@@ -178,3 +178,35 @@ def test_pair_moving_window_with_drive_equals_single_steps(dtype, nx, wp2, noise
         else:
             ref = P.oracle_run(wl, 9)
         P.compare_states(out[0].fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
+
+
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows,nx", [
+    ("f64", 3, "open", "open", 1, 190), ("f64", 3, "open", "open", 5, 190), ("f64", 3, "periodic", "pec", 3, 175),
+    ("f64", 3, "open", "pec", 24, 117), ("f64", 1, "open", "open", 4, 59), ("f64", 2, "periodic", "open", 7, 58),
+    ("f64", 4, "open", "open", 6, 130), ("f32", 3, "open", "open", 4, 190), ("f32", 4, "periodic", "pec", 9, 121),
+    ("f32", 2, "open", "pec", 2, 100)])
+def test_pair_with_background_set_march_equals_single_steps(dtype, M, x_bc, r_bc, rows, nx):
+    """QDS_OPT_PAIR_A: the background set's two-step march with the axion
+    source of both steps (2M waves per tile, each group forming S_a through
+    its own exchange area), the first step's field planes to the pair buffer
+    for the axion kernel.  7 steps from random reachable states equal single
+    steps bit for bit (FP64 with 4 modes does not fit its LDS and pairs with
+    kernel A instead); the oracle per field in FP64."""
+    from oracle import qds as Q
+    from paper_2609_03550_amd import qds
+    wl = _full(nx, 23, M, x_bc=x_bc, r_bc=r_bc)
+    st, g, ph = _random_reachable_state(wl, 30 + rows + M)
+    out = []
+    for pair, pa in ((1, 1), (0, 0)):
+        s = qds.Solver(wl, dtype=dtype)
+        s.set_option(qds.OPT_PAIR, pair)
+        s.set_option(qds.OPT_PAIR_A, pa)
+        s.set_option(qds.OPT_ROWS, rows)
+        s.load_fields(st)
+        s.step(7)
+        torch.cuda.synchronize()
+        out.append(s)
+    _equal(out[0], out[1])
+    if dtype == "f64" and M == 3:
+        ref = Q.run(st, g, ph, 7)
+        P.compare_states(out[0].fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
