@@ -36,6 +36,21 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def test_binding_constants_match_the_header():
+    """Every option key, tile slot and the tile count the Python binding
+    passes equal the header's enum values."""
+    from paper_2609_03550_amd import qds
+    txt = open(HEADER).read()
+    enum = {k: int(v) for k, v in re.findall(r"\b(QDS_(?:OPT|TILE)_\w+|QDS_NTILES)\s*=\s*(\d+)", txt)}
+    names = [k for k in dir(qds) if k.startswith(("OPT_", "TILE_")) or k == "NTILES"]
+    assert len(names) >= 20
+    for k in names:
+        assert "QDS_" + k in enum, k
+        assert getattr(qds, k) == enum["QDS_" + k], k
+    for k in enum:
+        assert hasattr(qds, k[4:]), k
+
+
 def test_init_rejects_bad_arguments(lib):
     from paper_2609_03550_amd import qds
     h = ctypes.c_void_p()
