@@ -244,6 +244,39 @@ def batched_leg(step_scale, graph_steps, count=64):
             "launch_overhead_us_per_kernel": (t_direct - t_batch) / max(kernel_launches_direct, 1) * 1e6}
 
 
+def window_leg(steps):
+    """The moving-window workload with the prescribed ring drive (4096 x 256 x
+    3 modes, electromagnetic only, steps in pairs) in FP64 and FP32: autotuned
+    tiles, 10 warm-up steps, ``steps`` timed; the whole step against its
+    one-read-one-write byte model (the 9 planes of the set with the plasma)."""
+    import torch
+    from paper_2609_03550_amd import qds
+    wl = workload("window")
+    out = {"workload": wl.name, "steps": steps}
+    for dt in ("f64", "f32"):
+        s = qds.Solver(wl, dtype=dt)
+        s.load_pulses()
+        s.set_option(qds.OPT_TUNE, 1)
+        s.step(TUNE_STEPS)
+        s.step(10)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        eb = 16 if dt == "f64" else 8
+        nplanes = 9 if wl.wp2 else 6
+        out[dt] = {"ms_per_step": ms, "value": wl.cell_modes / (ms / 1e3),
+                   "roofline_frac": 2 * nplanes * eb * wl.cell_modes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                   "pairs_of_steps": pairs_active(wl, s.fused), "tiles": s.tiles()[0]}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def f32_leg(wl, steps):
     """The same workload in single precision: autotuned tiles, 10 warm-up
     steps, then ``steps`` timed steps; the whole step against its
@@ -532,6 +565,8 @@ def main():
                     help="steps per HIP graph of the batched leg (-1: the whole uneven schedule as one graph)")
     ap.add_argument("--theta-steps", type=int, default=20,
                     help="steps of the theta-grid vs direct product comparison at 6 and 8 modes (0 skips it)")
+    ap.add_argument("--window-steps", type=int, default=100,
+                    help="steps of the moving-window workload with the drive, FP64 and FP32 (0 skips it)")
     ap.add_argument("--f32-steps", type=int, default=100,
                     help="steps of the single-precision figure of the same workload (0 skips it)")
     ap.add_argument("--kernel-ax", type=int, default=0,
@@ -689,6 +724,10 @@ def main():
         out["fwd_adj_over_fwd"] = adj["ratio"]
         out["adjoint"] = adj
         torch.cuda.empty_cache()
+        if args.dtype == "f64":
+            # the configuration's single-precision variant
+            out["adjoint_f32"] = adjoint_ratio("f32", args.adjoint_steps, args.ckpt_every)
+            torch.cuda.empty_cache()
     if args.batched_scale > 0:
         out["batched"] = batched_leg(args.batched_scale, args.graph_steps)
         torch.cuda.empty_cache()
@@ -697,6 +736,9 @@ def main():
         torch.cuda.empty_cache()
     if args.variant_steps > 0 and wl.arem and s_fused:
         out["kernel_variants"] = kernel_variants_leg(wl, args.dtype, args.variant_steps)
+        torch.cuda.empty_cache()
+    if args.window_steps > 0 and args.workload == "axion":
+        out["window"] = window_leg(args.window_steps)
         torch.cuda.empty_cache()
     if args.theta_steps > 0:
         out["theta_grid_products"] = theta_leg(args.theta_steps)
