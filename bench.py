@@ -709,6 +709,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "whole step (" + " + ".join(k["name"] for k in kernels.values()) + ")",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "traffic_over_model": traffic / step_bytes if traffic else None,
+                     # the measured fraction: HBM bytes (rocprofv3 counters) per step / step time / 8 TB/s
+                     "measured_frac": traffic / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBPS if traffic else None,
                      "bytes_per_step": step_bytes, "bytes_per_cell_mode": 2 * nplanes * eb,
                      "step_ms": ms_per_step, "kernel_sum_ms": kernel_sum_ms,
                      "breakdown_pass_step_ms": breakdown_ms},
