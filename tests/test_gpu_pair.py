@@ -7,6 +7,8 @@ tile heights from one row up (the two-row lag, the ghost chunk, ragged last
 chunks), odd step counts (a single step after the pairs), 58-column strips
 over widths that leave ragged strips, periodic and open x, conducting and open
 outer walls; and against the oracle per field."""
+import ctypes
+
 import pytest
 import torch
 
@@ -210,3 +212,38 @@ def test_pair_with_background_set_march_equals_single_steps(dtype, M, x_bc, r_bc
     if dtype == "f64" and M == 3:
         ref = Q.run(st, g, ph, 7)
         P.compare_states(out[0].fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
+
+
+@pytest.mark.parametrize("arem", [True, False])
+def test_pair_with_particle_currents_equals_single_steps(arem):
+    """Deposited particle currents (QDS_J_PARTICLES, the same deposit for every
+    step of the call) over one call of 5 steps: in pairs (the fused sources
+    formed once per call, read by both steps of a pair) equal to single steps
+    bit for bit, and to the staged kernels (which form the sums themselves) to
+    rounding, with and without the regenerated set."""
+    from paper_2609_03550_amd import qds
+    wl = _full(150, 21, 3) if arem else _em(150, 21, 3)
+    st, _, _ = _random_reachable_state(wl, 17)
+    gen = torch.Generator().manual_seed(5)
+    planes = None
+    out = []
+    for pair, path in ((1, qds.PATH_AUTO), (0, qds.PATH_AUTO), (0, qds.PATH_STAGED)):
+        s = qds.Solver(wl, dtype="f64", path=path)
+        s.set_option(qds.OPT_PAIR, pair)
+        s.set_option(qds.OPT_ROWS, 6)
+        s.load_fields(st)
+        if planes is None:
+            planes = [p.copy_(torch.randn(p.shape, dtype=p.dtype, generator=gen).to(p.device))
+                      for p in s.current_planes() + s.current_planes()[:1]]
+        J = qds.Current()
+        ctypes.memmove(ctypes.byref(J), ctypes.byref(s.cur), ctypes.sizeof(qds.Current))
+        J.kind = qds.J_PARTICLES
+        J.pjx_prev = planes[3].data_ptr()
+        J.pjx_next, J.pjr, J.pjt = planes[0].data_ptr(), planes[1].data_ptr(), planes[2].data_ptr()
+        qds._check(qds.lib().qds_step(s.h, ctypes.byref(s.state), ctypes.byref(J), ctypes.byref(s.ax), 5,
+                                      qds._stream_ptr()), s.h)
+        torch.cuda.synchronize()
+        out.append(s)
+    assert out[0].fused and not out[2].fused
+    _equal(out[0], out[1])
+    P.compare_states(out[0].fields(), out[2].fields(), 1e-13, 1e-15)
