@@ -20,6 +20,14 @@
 // per step into a plane of its own (k_drive_plane) that the background set
 // reads as an extra j_x of mode 0.  They compute exactly the quantities of
 // the staged kernels.
+//
+// Temporal blocking: the two-step march (em2_body) advances one set through
+// two steps in one pass, its first step's rows handed to a second wave
+// through an LDS ring, so the set's planes are read and written once per two
+// steps (the regenerated set in pairs of steps, or the background set of an
+// electromagnetic-only run, also with the moving window and the drive).
+// fused_a2_body does the same for the background set with the axion source of
+// both steps (2M waves per workgroup; an option, measured slower).
 #include "qds_current_rows.hpp"
 
 namespace qds {
