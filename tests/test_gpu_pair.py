@@ -247,3 +247,37 @@ def test_pair_with_particle_currents_equals_single_steps(arem):
     assert out[0].fused and not out[2].fused
     _equal(out[0], out[1])
     P.compare_states(out[0].fields(), out[2].fields(), 1e-13, 1e-15)
+
+
+@pytest.mark.parametrize("nx,nr,M,kind", [(8, 4, 1, "full"), (8, 4, 3, "full"), (9, 5, 2, "full"), (8, 4, 3, "em"),
+                                          (12, 4, 2, "window"), (8, 6, 3, "full_a2")])
+def test_pair_on_the_smallest_grids(nx, nr, M, kind):
+    """The smallest grids the library accepts (nx >= 8, nr >= 4): a single
+    strip with most lanes beyond the grid, chunks shorter than the two-row
+    lag, the exterior ghost row in the first chunk; pairs equal single steps
+    bit for bit over 7 steps."""
+    from paper_2609_03550_amd import qds
+    dr = M * H if M > 1 else I.DR
+    if kind.startswith("full"):
+        wl = _full(nx, nr, M, dr=dr)
+    elif kind == "em":
+        wl = _em(nx, nr, M, dr=dr)
+    else:
+        d = I.Drive(amp=50.0, x0=4 * H, v=0.999, sx=2 * H, r0=0.0, sr=dr, noise=1e-3, seed=3)
+        wl = I.Workload("pair_tiny_window", nx, nr, M, 0, x_bc="window", wp2=0.01, dr=dr,
+                        pulses=(I.Pulse("y", 0.5, 1.0, 3 * I.LAMBDA, 2 * H, 4 * H),), drive=d)
+    st, _, _ = _random_reachable_state(wl, 3 + nx + nr)
+    out = []
+    for pair in (1, 0):
+        for rows in (1, 3):
+            s = qds.Solver(wl, dtype="f64")
+            s.set_option(qds.OPT_PAIR, pair)
+            s.set_option(qds.OPT_PAIR_A, 1 if kind == "full_a2" else 0)
+            s.set_option(qds.OPT_ROWS, rows)
+            s.load_fields(st)
+            assert s.fused
+            s.step(7)
+            torch.cuda.synchronize()
+            out.append(s)
+    for s in out[1:]:
+        _equal(out[0], s)
