@@ -248,8 +248,10 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 caller's other buffer.  Each pair flips fields->cur once and
  *                 adds 2 to fields->step; an odd last step is a single step.
  *                 Tile height QDS_OPT_ROWS_PAIR (default: two chunks; tuner
- *                 candidates 20 and the heights that cut the nr + 1 rows into
- *                 4, 3 and 2 chunks); the timing slot of the march is that of
+ *                 candidates 20 and the heights at which the launch's
+ *                 workgroups just fill one, two, three, ... rounds of the
+ *                 workgroups the GPU holds at once, the three smallest
+ *                 distinct chunk counts; the timing slot of the march is that of
  *                 the set it advances, one launch per two steps.  1 is the
  *                 default; 0: single steps.
  *  QDS_OPT_PAIR_A 1: in pairs with the regenerated set (up to 4 modes, its

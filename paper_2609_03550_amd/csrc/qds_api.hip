@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -25,18 +26,39 @@ const int kCandCur[4] = {4, 6, 8, 16};
 const int kCandB[4] = {16, 32, 52, 64};
 const int kCandEm[4] = {8, 16, 26, 52};
 const int kCandA2[4] = {16, 24, 32, 43};
-// Tile heights of the two-step march (measured on MI355X): at 8192 x 256 x 3
-// it is fastest with every workgroup resident at once (129 rows, two chunks,
-// in FP64; 86 rows, three chunks, in FP32), at 4096 x 256 x 3 with about 20
-// rows: 20 rows and the heights that cut the nr + 1 rows into 4, 3 and 2 chunks.
-void cand_pair(const qds_ctx* c, int* out) {
+// Tile heights of the two-step march.  Its workgroups march their chunks in
+// lockstep rounds, and it runs fastest where a launch's workgroups (strips x
+// chunks x modes) just fit in a whole number of rounds of what the GPU holds
+// at once (measured on MI355X: at 8192 x 256 x 3 all resident at once, 129
+// rows in FP64 and 86 in FP32; at 4096 x 256 x 3 in FP32 37 rows, one round,
+// 10% faster than 20 rows, two rounds less a few).  Candidates: the heights of
+// the three smallest distinct chunk counts that fill 1, 2, 3, ... rounds, and
+// 20 rows; without an occupancy figure from the runtime, the heights that cut
+// the nr + 1 rows into 2, 4 and 3 chunks.
+template <typename T>
+void cand_pair(const qds_ctx* c, int which, int* out) {
     const int R = c->g.nr + 1;
-    const int parts[4] = {0, 4, 3, 2};
-    out[0] = 20;
-    for (int q = 1; q < 4; ++q) {
-        const int h = (R + parts[q] - 1) / parts[q];
+    const int per = qds::pair_strips(c->g.nx, c->g.x_bc == QDS_X_WINDOW ? 1 : 0) * c->M;   // workgroups per chunk row
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        cus = 0;
+    }
+    const int64_t slots = int64_t(qds::em2_blocks_per_cu<T>(which)) * cus;
+    int chunks[3] = {2, 4, 3};
+    if (slots > 0) {
+        int n = 0, last = 0;
+        for (int64_t k = 1; n < 3 && k <= 64; ++k) {
+            const int64_t q = std::min<int64_t>(k * slots / per, R);
+            if (q >= 1 && q != last) chunks[n++] = last = int(q);
+        }
+        for (; n < 3; ++n) chunks[n] = last > 0 ? last : 2;
+    }
+    for (int q = 0; q < 3; ++q) {
+        const int h = (R + chunks[q] - 1) / chunks[q];
         out[q] = h < 4 ? 4 : h;
     }
+    out[3] = 20;
 }
 constexpr int kTrials = 8;
 
@@ -366,7 +388,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
         // measured optimum).  Slots: 0 kernel A / the background set, 1 the
         // axion kernel, 2 kernel B or the two-step march.
         int candB2[4];
-        cand_pair(c, candB2);
+        if (pairs) cand_pair<T>(c, p0.arem ? 1 : 0, candB2);
         const int* cand[3] = {fuse_ax(c, p0) ? kCandAX
                                              : (pairs && pair_a2(c, p0) ? kCandA2 : (p0.axion ? kCandA : kCandEm)),
                               kCandCur, pairs ? candB2 : kCandB};

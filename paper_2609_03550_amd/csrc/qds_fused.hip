@@ -1590,6 +1590,19 @@ hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, in
     return hipGetLastError();
 }
 
+template <typename T>
+int em2_blocks_per_cu(int which) {
+    const size_t lds = size_t(fused::RG_N) * fused::RING_ROWS * fused::WAVE * sizeof(cx<T>);
+    int n = 0;
+    const hipError_t e = which ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused::k_batch_em2<T, 1>, 2 * fused::WAVE, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused::k_batch_em2<T, 0>, 2 * fused::WAVE, lds);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
 size_t a2_lds_bytes(int M, size_t elem_bytes) {
     return size_t(M) * (size_t(fused::RG_N) * fused::RING_ROWS + 2 * fused::NS) * fused::WAVE * 2 * elem_bytes;
 }
@@ -1621,6 +1634,8 @@ template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&,
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
+template int em2_blocks_per_cu<double>(int);
+template int em2_blocks_per_cu<float>(int);
 template hipError_t batch_a2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_a2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);

@@ -171,8 +171,8 @@ def test_autotuned_tiles_change_no_result(dtype, pair):
     single steps, or pairs of steps with the two-step march of the
     regenerated set in place of kernel B) and the chosen tiles give
     bit-identical states to the default tiling, and the chosen heights are
-    candidates (for the two-step march: 20 rows and the heights that cut the
-    21 rows into 4, 3 and 2 chunks)."""
+    candidates (for the two-step march, whose candidates follow the GPU's
+    occupancy: 20 rows or a height that tiles the 21 rows)."""
     from paper_2609_03550_amd import qds
     wl = _full(70, 20, 3)
     a = qds.Solver(wl, dtype=dtype)
@@ -188,7 +188,7 @@ def test_autotuned_tiles_change_no_result(dtype, pair):
     rows, tuned = b.tiles()
     assert tuned and rows[0] in (8, 16, 24, 32) and rows[1] in (4, 6, 8, 16)
     if pair:
-        assert rows[2] == 16 and rows[3] in (20, 6, 7, 11)
+        assert rows[2] == 16 and 4 <= rows[3] <= 21
     else:
         assert rows[2] in (16, 32, 52, 64) and rows[3] == 11
     assert a.tiles() == ([16, 16, 16, 11], False)
@@ -200,9 +200,8 @@ def test_autotuned_tiles_with_a_drive_change_no_result(pair):
     """With a prescribed drive (moving window, no axion; the drive plane is
     filled before every step, both planes before every pair) the autotuner's
     choice is one of the candidates of the background set alone (single
-    steps) or of the two-step march (pairs: 20 rows and the heights that cut
-    the 21 rows into 4, 3 and 2 chunks), and the states are bit-identical to
-    the default tiling."""
+    steps) or of the two-step march (pairs: 20 rows or a height that tiles
+    the 21 rows), and the states are bit-identical to the default tiling."""
     from paper_2609_03550_amd import qds
     wl = I.driven_window(nx=200, nr=20, steps=0)
     d = wl.drive
@@ -217,7 +216,7 @@ def test_autotuned_tiles_with_a_drive_change_no_result(pair):
     torch.cuda.synchronize()
     rows, tuned = b.tiles()
     assert tuned
-    assert rows[3] in (20, 6, 7, 11) if pair else rows[0] in (8, 16, 26, 52)
+    assert 4 <= rows[3] <= 21 if pair else rows[0] in (8, 16, 26, 52)
     assert torch.equal(a.bufs[a.state.cur], b.bufs[b.state.cur])
 
 
