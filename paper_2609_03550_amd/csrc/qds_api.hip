@@ -36,7 +36,7 @@ const int kCandA2[4] = {16, 24, 32, 43};
 // 20 rows; without an occupancy figure from the runtime, the heights that cut
 // the nr + 1 rows into 2, 4 and 3 chunks.
 template <typename T>
-void cand_pair(const qds_ctx* c, int which, int* out) {
+void cand_pair(const qds_ctx* c, int which, bool plasma, int* out) {
     const int R = c->g.nr + 1;
     const int per = qds::pair_strips(c->g.nx, c->g.x_bc == QDS_X_WINDOW ? 1 : 0) * c->M;   // workgroups per chunk row
     int dev = 0, cus = 0;
@@ -44,7 +44,7 @@ void cand_pair(const qds_ctx* c, int which, int* out) {
         (void)hipGetLastError();
         cus = 0;
     }
-    const int64_t slots = int64_t(qds::em2_blocks_per_cu<T>(which)) * cus;
+    const int64_t slots = int64_t(qds::em2_blocks_per_cu<T>(which, plasma)) * cus;
     int chunks[3] = {2, 4, 3};
     if (slots > 0) {
         int n = 0, last = 0;
@@ -204,7 +204,7 @@ qds_status table_launch_one(qds_ctx* c, const qds::StepPlan<T>& p0, const TabVie
     } else if (which == kLaunchX) {
         err = qds::batch_current<T>(v.xa, list(v.firstC, c->trows[1]), c->M, v.nC, s);
     } else if (which == kLaunchB2) {
-        err = qds::batch_em2<T>(v.fa, list(v.firstB2, c->trows[3]), p0.arem ? 1 : 0, v.nB2, s);
+        err = qds::batch_em2<T>(v.fa, list(v.firstB2, c->trows[3]), p0.arem ? 1 : 0, p0.plasma != 0, v.nB2, s);
     } else if (which == kLaunchA2) {
         err = qds::batch_a2<T>(v.fa, list(v.firstA2, c->trows[0]), c->M, v.nA2, s);
     } else {
@@ -388,7 +388,7 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
         // measured optimum).  Slots: 0 kernel A / the background set, 1 the
         // axion kernel, 2 kernel B or the two-step march.
         int candB2[4];
-        if (pairs) cand_pair<T>(c, p0.arem ? 1 : 0, candB2);
+        if (pairs) cand_pair<T>(c, p0.arem ? 1 : 0, p0.plasma != 0, candB2);
         const int* cand[3] = {fuse_ax(c, p0) ? kCandAX
                                              : (pairs && pair_a2(c, p0) ? kCandA2 : (p0.axion ? kCandA : kCandEm)),
                               kCandCur, pairs ? candB2 : kCandB};

@@ -287,7 +287,7 @@ hipError_t launch_pair(const qds_batch_ctx* b, const Plan& P, int parity, hipStr
         if (l.slot < QDS_TILE_PAIR0) continue;
         hipError_t e;
         if ((e = rec(0)) != hipSuccess) return e;
-        if ((e = qds::batch_em2<T>(fa, l.L, l.slot == QDS_TILE_PAIR1 ? 1 : 0, l.blocks, s)) != hipSuccess) return e;
+        if ((e = qds::batch_em2<T>(fa, l.L, l.slot == QDS_TILE_PAIR1 ? 1 : 0, true, l.blocks, s)) != hipSuccess) return e;
         if ((e = rec(1)) != hipSuccess) return e;
         ++q;
     }

@@ -1213,7 +1213,10 @@ __device__ __forceinline__ void em_body(const FusedArgs<T>& a, int strip, int ch
 // written once per two steps; the arithmetic of each step is that of
 // em_step, in the same order, so the result equals two one-step marches.
 // ---------------------------------------------------------------------------
-template <typename T, int WHICH>
+// PL = 0: the set carries no plasma currents (a.plasma is 0), which the
+// compiler then drops (in FP32 126 VGPRs instead of 140: four waves per SIMD
+// instead of three).
+template <typename T, int WHICH, int PL>
 __device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int chunk, int m, int rows) {
     const Geo g = a.g;
     // 0: first step, 1: second step (wave-uniform, so each wave takes one
@@ -1227,6 +1230,7 @@ __device__ __forceinline__ void em2_body(const FusedArgs<T>& a, int strip, int c
     // further left and lane k still reads ring slot k; the first step's lanes
     // on column nx put the zero-filled column the window brings in
     Ctx<T> c = make_ctx<T, kPairOwn, 2>(a, strip, m, lane, wave == 1 ? a.window : 0);
+    if (!PL) c.plasma = 0;
     if (wave == 0 && a.window) c.rzero = strip * kPairOwn - 2 + lane >= g.nx;
     const SetP<T>& s = WHICH ? a.s1 : a.s0;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -1491,7 +1495,7 @@ __global__ void __launch_bounds__(2 * WAVE * M) k_batch_a2(const FusedArgs<T>* _
     fused_a2_body<T, M>(a, local % strips, local / strips, L.rows);
 }
 
-template <typename T, int WHICH>
+template <typename T, int WHICH, int PL>
 __global__ void __launch_bounds__(2 * WAVE) k_batch_em2(const FusedArgs<T>* __restrict__ args, BatchList L) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int k = batch_find(L, b);
@@ -1500,7 +1504,7 @@ __global__ void __launch_bounds__(2 * WAVE) k_batch_em2(const FusedArgs<T>* __re
     const int chunks = (a.g.nr + 1 + L.rows - 1) / L.rows;
     const int m = local % a.g.M;                 // the modes of one tile run side by side
     const int t = local / a.g.M;
-    em2_body<T, WHICH>(a, t / chunks, t % chunks, m, L.rows);
+    em2_body<T, WHICH, PL>(a, t / chunks, t % chunks, m, L.rows);
 }
 
 }  // namespace fused
@@ -1579,23 +1583,26 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
     return hipGetLastError();
 }
 
+// the instantiation of the two-step march for (which, plasma)
 template <typename T>
-hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s) {
+static auto em2_kernel(int which, bool plasma) {
+    return which ? (plasma ? fused::k_batch_em2<T, 1, 1> : fused::k_batch_em2<T, 1, 0>)
+                 : (plasma ? fused::k_batch_em2<T, 0, 1> : fused::k_batch_em2<T, 0, 0>);
+}
+
+template <typename T>
+hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, bool plasma, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     const size_t lds = size_t(fused::RG_N) * fused::RING_ROWS * fused::WAVE * sizeof(cx<T>);
-    if (which)
-        hipLaunchKernelGGL((fused::k_batch_em2<T, 1>), dim3(blocks), dim3(2 * fused::WAVE), lds, s, args, L);
-    else
-        hipLaunchKernelGGL((fused::k_batch_em2<T, 0>), dim3(blocks), dim3(2 * fused::WAVE), lds, s, args, L);
+    hipLaunchKernelGGL(em2_kernel<T>(which, plasma), dim3(blocks), dim3(2 * fused::WAVE), lds, s, args, L);
     return hipGetLastError();
 }
 
 template <typename T>
-int em2_blocks_per_cu(int which) {
+int em2_blocks_per_cu(int which, bool plasma) {
     const size_t lds = size_t(fused::RG_N) * fused::RING_ROWS * fused::WAVE * sizeof(cx<T>);
     int n = 0;
-    const hipError_t e = which ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused::k_batch_em2<T, 1>, 2 * fused::WAVE, lds)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused::k_batch_em2<T, 0>, 2 * fused::WAVE, lds);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, em2_kernel<T>(which, plasma), 2 * fused::WAVE, lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -1632,10 +1639,10 @@ template hipError_t batch_ax<double>(const FusedArgs<double>*, const BatchList&,
 template hipError_t batch_ax<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_em<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
-template hipError_t batch_em2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
-template hipError_t batch_em2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
-template int em2_blocks_per_cu<double>(int);
-template int em2_blocks_per_cu<float>(int);
+template hipError_t batch_em2<double>(const FusedArgs<double>*, const BatchList&, int, bool, int, hipStream_t);
+template hipError_t batch_em2<float>(const FusedArgs<float>*, const BatchList&, int, bool, int, hipStream_t);
+template int em2_blocks_per_cu<double>(int, bool);
+template int em2_blocks_per_cu<float>(int, bool);
 template hipError_t batch_a2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_a2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
 template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);

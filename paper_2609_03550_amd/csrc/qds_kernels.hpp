@@ -249,13 +249,15 @@ hipError_t batch_em(const FusedArgs<T>* args, const BatchList& L, int which, int
 // of the first step and s1.jxb/jrb/jtb of the second; set 0 without an axion):
 // reads the set from the A planes and writes it, two steps on, to the B planes.
 // Tiles of pair_strips(nx) strips x rows-high chunks x modes, 128 threads each.
+// plasma false: no instance of the list carries plasma currents (a leaner
+// instantiation).
 template <typename T>
-hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, int blocks, hipStream_t s);
-// Workgroups of the two-step march (which: set 1 or set 0) that one CU holds
-// at once, as the runtime computes it from the kernel's registers and ring; 0
-// if it cannot tell.
+hipError_t batch_em2(const FusedArgs<T>* args, const BatchList& L, int which, bool plasma, int blocks, hipStream_t s);
+// Workgroups of that launch of the two-step march that one CU holds at once,
+// as the runtime computes it from the kernel's registers and ring; 0 if it
+// cannot tell.
 template <typename T>
-int em2_blocks_per_cu(int which);
+int em2_blocks_per_cu(int which, bool plasma);
 // Two steps of the background set with the axion source of each (2M waves per
 // tile of pair_strips(nx) strips x rows-high chunks): reads s0's A planes,
 // writes the first step's field planes to mtrp..mbx and its S_a to sa, the

@@ -84,6 +84,24 @@ def test_pair_with_regenerated_set_equals_single_steps(dtype, M, x_bc, r_bc, row
         P.compare_states(a.fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
 
 
+@pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows,nx", [
+    ("f64", 3, "open", "open", 2, 190), ("f64", 2, "periodic", "pec", 5, 121), ("f32", 3, "open", "open", 4, 190),
+    ("f32", 1, "open", "pec", 3, 64)])
+def test_pair_with_regenerated_set_without_plasma_equals_single_steps(dtype, M, x_bc, r_bc, rows, nx):
+    """The axion physics without the cold plasma: the march's instantiation
+    without plasma currents (fewer registers) equals single steps bit for
+    bit, and the oracle per field."""
+    from oracle import qds as Q
+    wl = _full(nx, 23, M, x_bc=x_bc, r_bc=r_bc, wp2=0.0)
+    st, g, ph = _random_state_no_plasma(wl, 110 + rows + M)
+    a = _run(wl, dtype, st, 7, 1, rows)
+    b = _run(wl, dtype, st, 7, 0, rows)
+    _equal(a, b)
+    if dtype == "f64":
+        ref = Q.run(st, g, ph, 7)
+        P.compare_states(a.fields(), ref, 1e-12, 1e-14, set_floor=P.SET_FLOOR, phys=True)
+
+
 @pytest.mark.parametrize("dtype,M,x_bc,r_bc,rows,nx,wp2", [
     ("f64", 3, "open", "open", 1, 190, 0.02), ("f64", 3, "open", "open", 3, 190, 0.0),
     ("f64", 3, "periodic", "pec", 4, 175, 0.02), ("f64", 2, "open", "pec", 26, 117, 0.0),
