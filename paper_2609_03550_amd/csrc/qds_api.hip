@@ -232,7 +232,7 @@ qds_status table_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTa
                       hipStream_t s, hipEvent_t* ev) {
     if (p0.drive.on) {
         // this step's j_x^(0), read by the background set as its extra j_x
-        const hipError_t e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, st->step, st->window, s);
+        const hipError_t e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, nullptr, st->step, st->window, 0, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     }
     const qds_status r = table_launch<T>(c, p0, ktab_view<T>(K, host, st->cur), s, ev);
@@ -261,9 +261,8 @@ qds_status pair_step(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p0, KTab
     qds_status r;
     if (p0.drive.on) {
         // j_x^(0) of both steps (the second one column on with the window)
-        hipError_t e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, st->step, st->window, s);
-        if (e == hipSuccess)
-            e = qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv2, st->step + 1, st->window + (window ? 1 : 0), s);
+        const hipError_t e =
+            qds::drive_plane<T>(p0.drive, p0.g, p0.jdrv, p0.jdrv2, st->step, st->window, window ? 1 : 0, s);
         if (e != hipSuccess) return fail(c, QDS_EHIP, "launch failed: %s", hipGetErrorString(e));
     }
     if (p0.arem && pair_a2(c, p0)) {

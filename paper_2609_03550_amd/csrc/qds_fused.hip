@@ -86,25 +86,43 @@ __device__ __forceinline__ cx<T> shfl_dn1(cx<T> v) {
     return cx<T>{__shfl_down(v.re, 1, WAVE), __shfl_down(v.im, 1, WAVE)};
 }
 
-// Prescribed j_x^(0) of step n at (x_{i+1/2}, r_j, t^n), lab column i + w,
-// into the mode-0 rows of out (row pitch g.ld): one thread per point, so the
-// marching kernels, which read it as an extra current, carry none of its
-// exponentials and normal variates in their registers.
+// Prescribed j_x^(0) of step n + z at (x_{i+1/2}, r_j, t^{n+z}), lab column
+// i + w + z dw, into the mode-0 rows of plane z of a launch (row pitch g.ld;
+// z = blockIdx.z, one or two planes: a pair of steps fills both in one launch).
+// A thread holds one column over kDriveRows rows: the x Gaussian is evaluated
+// once per thread and the r Gaussian once per row of the workgroup, so a point
+// costs its normal variate only (the same expressions as one evaluation per
+// point, hence the same bits).  The marching kernels read it as an extra
+// current and carry none of its exponentials and variates in their registers.
+constexpr int kDriveRows = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_drive_plane(Drive d, Geo g, cx<T>* out, int64_t n, int64_t w) {
+__global__ void __launch_bounds__(256) k_drive_plane(Drive d, Geo g, cx<T>* out0, cx<T>* out1, int64_t n, int64_t w,
+                                                     int64_t dw) {
+    const int z = blockIdx.z;
+    const int64_t nz = n + z, wz = w + z * dw;
+    cx<T>* const out = z ? out1 : out0;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= g.nx || j > g.nr) return;
-    const double x = (double(i) + 0.5 + double(w)) * g.h;
-    const double t = double(n) * g.h;
-    const double r = double(j) * g.dr;
+    const int j0 = blockIdx.y * kDriveRows;
+    const int j1 = min(g.nr + 1, j0 + kDriveRows);
+    __shared__ double grs[kDriveRows];
+    if (threadIdx.x < kDriveRows) {
+        const double r = double(j0 + int(threadIdx.x)) * g.dr;
+        const double ar = r - d.r0;
+        grs[threadIdx.x] = exp(-ar * ar / (2.0 * d.sr * d.sr));
+    }
+    __syncthreads();
+    if (i >= g.nx) return;
+    const double x = (double(i) + 0.5 + double(wz)) * g.h;
+    const double t = double(nz) * g.h;
     const double ax = x - d.x0 - d.v * t;
-    const double ar = r - d.r0;
     const double gx = exp(-ax * ax / (2.0 * d.sx * d.sx));
-    const double gr = exp(-ar * ar / (2.0 * d.sr * d.sr));
-    const uint64_t c = (uint64_t(n) << 32) | (uint64_t(int64_t(i) + w) << 12) | uint64_t(j);
-    const double v = d.amp * gr * gx * (1.0 + d.noise * normal_ctr(d.seed, c));
-    st(out + size_t(j) * size_t(g.ld) + size_t(i), cx<T>{T(v), T(0)});
+    for (int j = j0; j < j1; ++j) {
+        const double gr = grs[j - j0];
+        const uint64_t c = (uint64_t(nz) << 32) | (uint64_t(int64_t(i) + wz) << 12) | uint64_t(j);
+        const double v = d.amp * gr * gx * (1.0 + d.noise * normal_ctr(d.seed, c));
+        st(out + size_t(j) * size_t(g.ld) + size_t(i), cx<T>{T(v), T(0)});
+    }
 }
 
 // Output addressing: with the moving window every write lands one column to
@@ -1510,8 +1528,11 @@ __global__ void __launch_bounds__(2 * WAVE) k_batch_em2(const FusedArgs<T>* __re
 }  // namespace fused
 
 template <typename T>
-hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, int64_t n, int64_t w, hipStream_t s) {
-    hipLaunchKernelGGL((fused::k_drive_plane<T>), dim3((g.nx + 255) / 256, g.nr + 1), dim3(256), 0, s, d, g, out, n, w);
+hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, cx<T>* out2, int64_t n, int64_t w, int64_t dw,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((fused::k_drive_plane<T>),
+                       dim3((g.nx + 255) / 256, (g.nr + fused::kDriveRows) / fused::kDriveRows, out2 ? 2 : 1), dim3(256), 0,
+                       s, d, g, out, out2, n, w, dw);
     return hipGetLastError();
 }
 
@@ -1645,7 +1666,9 @@ template int em2_blocks_per_cu<double>(int, bool);
 template int em2_blocks_per_cu<float>(int, bool);
 template hipError_t batch_a2<double>(const FusedArgs<double>*, const BatchList&, int, int, hipStream_t);
 template hipError_t batch_a2<float>(const FusedArgs<float>*, const BatchList&, int, int, hipStream_t);
-template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, int64_t, int64_t, hipStream_t);
-template hipError_t drive_plane<float>(const Drive&, const Geo&, cx<float>*, int64_t, int64_t, hipStream_t);
+template hipError_t drive_plane<double>(const Drive&, const Geo&, cx<double>*, cx<double>*, int64_t, int64_t, int64_t,
+                                        hipStream_t);
+template hipError_t drive_plane<float>(const Drive&, const Geo&, cx<float>*, cx<float>*, int64_t, int64_t, int64_t,
+                                       hipStream_t);
 
 }  // namespace qds

@@ -235,9 +235,11 @@ hipError_t particle_sources(const cx<T>* pjx0, const cx<T>* pjx1, const cx<T>* p
                             cx<T>* out, size_t plane_elems, hipStream_t s);
 // The prescribed drive's j_x^(0) of step n (window offset w) into the mode-0
 // rows of out (one plane of row pitch g.ld), read by the background set of the
-// fused kernels as its extra j_x.
+// fused kernels as its extra j_x; with out2, in the same launch, that of step
+// n + 1 (window offset w + dw) into out2.
 template <typename T>
-hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, int64_t n, int64_t w, hipStream_t s);
+hipError_t drive_plane(const Drive& d, const Geo& g, cx<T>* out, cx<T>* out2, int64_t n, int64_t w, int64_t dw,
+                       hipStream_t s);
 // Batched launches over many instances (argument tables in device memory).
 // axt: kernel A advances the axion (every instance of the list has sa null);
 // otherwise every instance has sa set and the axion current advances it.
