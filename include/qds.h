@@ -197,8 +197,10 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 axion, 16, 24, 32, 48 for kernel AX, 8, 16, 26, 52 for the
  *                 background set alone, 4, 6, 8,
  *                 16 for the axion current, 16, 32, 52, 64 for the regenerated
- *                 set; HIP events around every launch) and keeps the fastest
- *                 height for each kernel (with QDS_OPT_PAIR in effect: its
+ *                 set; HIP events around every launch) and keeps, for the
+ *                 marches of the sets, the tallest height whose fastest trial
+ *                 is within 2% of the fastest of all, for the axion current
+ *                 the fastest (with QDS_OPT_PAIR in effect: its
  *                 first 8 pairs, the two-step march in place of kernel B);
  *                 the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream

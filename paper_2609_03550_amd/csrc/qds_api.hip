@@ -406,8 +406,14 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
             if (r != QDS_OK) return r;
         }
         if (hipStreamSynchronize(s) != hipSuccess) return fail(c, QDS_EHIP, "tuning steps failed%s");
-        float best[3] = {3.4e38f, 3.4e38f, 3.4e38f};
-        int pick[3] = {*tr[0], *tr[1], *tr[2]};
+        // fastest trial of each candidate; for the bandwidth-bound marches of
+        // the sets (slots 0 and 2), among the candidates within the trials'
+        // noise (2%) of the fastest, the tallest, whose chunks re-read the
+        // fewest halo rows; for the axion kernel, whose time is set by its
+        // workgroups in flight rather than its bytes, the fastest
+        float best[3][4];
+        for (int k = 0; k < 3; ++k)
+            for (int q = 0; q < 4; ++q) best[k][q] = 3.4e38f;
         for (int t = 0; t < kTrials; ++t)
             for (int k = 0; k < 3; ++k) {
                 if (!run[k]) continue;
@@ -416,10 +422,20 @@ qds_status fused_steps(qds_ctx* c, qds_state* st, const qds::StepPlan<T>& p1, in
                     (void)hipGetLastError();   // do not leave the error for the next launch check
                     continue;
                 }
-                if (ms < best[k]) { best[k] = ms; pick[k] = cand[k][t % 4]; }
+                best[k][t % 4] = std::min(best[k][t % 4], ms);
             }
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
-        for (int k = 0; k < 3; ++k) *tr[k] = pick[k];
+        for (int k = 0; k < 3; ++k) {
+            if (!run[k]) continue;
+            float fastest = 3.4e38f;
+            for (int q = 0; q < 4; ++q) fastest = std::min(fastest, best[k][q]);
+            if (!(fastest < 3.4e38f)) continue;   // no trial timed: keep the last height
+            const float tol = k == 1 ? 1.0f : 1.02f;
+            int pick = 0;
+            for (int q = 0; q < 4; ++q)
+                if (best[k][q] <= tol * fastest && (pick == 0 || cand[k][q] > pick)) pick = cand[k][q];
+            *tr[k] = pick;
+        }
         c->tune = 0;
         c->tuned = 1;
         done = per * kTrials;
