@@ -419,8 +419,11 @@ def pic_leg(steps, ppc=2, dtype="f64", sort=True):
     th = rng.uniform(-np.pi, np.pi, n)
     pos = torch.from_numpy(np.stack([x, r * np.cos(th), r * np.sin(th)])).to(s.device).contiguous()
     if sort:
-        # by (x, r) cell, as PIC codes keep their particles
-        key = torch.floor(pos[0] / wl.h) * (nr + 1) + torch.floor(torch.sqrt(pos[1] ** 2 + pos[2] ** 2) / wl.dr)
+        # by cell, as PIC codes keep their particles, rows of x-consecutive
+        # cells (the planes' contiguous direction): a wave's 64 particles then
+        # sit on a few consecutive columns of one row, so each of its gather
+        # loads touches a few cache lines (with r fastest, one line per row)
+        key = torch.floor(torch.sqrt(pos[1] ** 2 + pos[2] ** 2) / wl.dr) * nx + torch.floor(pos[0] / wl.h)
         pos = pos[:, torch.argsort(key)].contiguous()
     u = torch.zeros_like(pos)
     ne = 1e17 / I.NC_CM3                       # density in units of the critical density

@@ -188,16 +188,18 @@ def test_tiled_and_direct_deposits_agree(dtype):
     """A workgroup whose particles' deposit windows fit one LDS tile (sorted
     by cell) accumulates there and adds each tile value to the planes once;
     one whose particles spread over the grid (unsorted) adds every value
-    directly.  The same 6000 particles in both orders deposit the same
-    currents to rounding, and leave with the same positions."""
+    directly.  The same 6000 particles unsorted, sorted by cell with r
+    fastest and sorted with x fastest deposit the same currents to rounding,
+    and leave with the same positions."""
     from paper_2609_03550_amd import qds
     s, _, _, pos, u, Q = _setup(3, dtype, nx=256, nr=40, n=6000, near_axis=200)
     dev = s.device
     h, dr = s.wl.h, s.wl.dr
-    key = np.floor(pos[0] / h) * (s.wl.nr + 1) + np.floor(np.sqrt(pos[1] ** 2 + pos[2] ** 2) / dr)
-    order = np.argsort(key, kind="stable")
+    ix, ir = np.floor(pos[0] / h), np.floor(np.sqrt(pos[1] ** 2 + pos[2] ** 2) / dr)
+    by_r = np.argsort(ix * (s.wl.nr + 1) + ir, kind="stable")
+    by_x = np.argsort(ir * s.wl.nx + ix, kind="stable")
     out = []
-    for idx in (np.arange(pos.shape[1]), order):
+    for idx in (np.arange(pos.shape[1]), by_r, by_x):
         P = torch.from_numpy(pos[:, idx].copy()).to(dev)
         U = torch.from_numpy(u[:, idx].copy()).to(dev)
         Qd = torch.from_numpy(Q[idx].copy()).to(dev)
@@ -208,6 +210,7 @@ def test_tiled_and_direct_deposits_agree(dtype):
         inv[idx] = np.arange(idx.size)
         out.append(([pl.cpu().to(torch.complex128).numpy() for pl in planes], P.cpu().numpy()[:, inv]))
     tol = 1e-13 if dtype == "f64" else 1e-5
-    for a, b in zip(out[0][0], out[1][0]):
-        assert _rel(a, b) < tol
-    assert np.array_equal(out[0][1], out[1][1])
+    for k in (1, 2):
+        for a, b in zip(out[0][0], out[k][0]):
+            assert _rel(a, b) < tol
+        assert np.array_equal(out[0][1], out[k][1])
