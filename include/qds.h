@@ -392,7 +392,12 @@ typedef struct {
  * A particle whose old or new position leaves 2 <= x/dx <= nx - 3,
  * r/dr <= nr - 2 is left unchanged, deposits nothing and is counted in
  * *skipped_dev (a device counter, may be NULL).  Open x boundaries only
- * (QDS_EUNSUPPORTED otherwise).  Asynchronous on ``stream``. */
+ * (QDS_EUNSUPPORTED otherwise).  Asynchronous on ``stream``.
+ * Any particle order gives the same result to rounding; the step is fastest
+ * with the particles sorted by cell in rows of x-consecutive cells (the
+ * planes' contiguous direction): each workgroup of 256 then gathers from a
+ * few cache lines per load and deposits into an LDS tile, adding each tile
+ * value to the planes once. */
 qds_status qds_particles_step(qds_handle h, const qds_state* fields, int32_t extrapolate, qds_particles* particles,
                               void* jx, void* jr, void* jt, unsigned long long* skipped_dev, void* stream);
 
