@@ -419,11 +419,18 @@ def pic_leg(steps, ppc=2, dtype="f64", sort=True):
     th = rng.uniform(-np.pi, np.pi, n)
     pos = torch.from_numpy(np.stack([x, r * np.cos(th), r * np.sin(th)])).to(s.device).contiguous()
     if sort:
-        # by cell, as PIC codes keep their particles, rows of x-consecutive
-        # cells (the planes' contiguous direction): a wave's 64 particles then
-        # sit on a few consecutive columns of one row, so each of its gather
-        # loads touches a few cache lines (with r fastest, one line per row)
-        key = torch.floor(torch.sqrt(pos[1] ** 2 + pos[2] ** 2) / wl.dr) * nx + torch.floor(pos[0] / wl.h)
+        # by cell, as PIC codes keep their particles: tiles of 8 rows x 16
+        # columns (a workgroup's 256 particles at two per cell), x fastest
+        # within a tile (the planes' contiguous direction).  A wave's 64
+        # particles then sit on 16 consecutive columns of two rows, so each
+        # of its gather loads touches a few cache lines (sorted with r fastest,
+        # one line per row), and a workgroup's deposit box is 19 x 11 cells
+        # (in rows of 128 cells, 131 x 5: about twice the tile values to add)
+        tr, tc = 8, 16
+        ix = torch.floor(pos[0] / wl.h)
+        ir = torch.floor(torch.sqrt(pos[1] ** 2 + pos[2] ** 2) / wl.dr)
+        tile = torch.div(ir, tr, rounding_mode="floor") * ((nx + tc - 1) // tc) + torch.div(ix, tc, rounding_mode="floor")
+        key = tile * (tr * tc) + torch.remainder(ir, tr) * tc + torch.remainder(ix, tc)
         pos = pos[:, torch.argsort(key)].contiguous()
     u = torch.zeros_like(pos)
     ne = 1e17 / I.NC_CM3                       # density in units of the critical density

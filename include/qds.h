@@ -394,10 +394,11 @@ typedef struct {
  * *skipped_dev (a device counter, may be NULL).  Open x boundaries only
  * (QDS_EUNSUPPORTED otherwise).  Asynchronous on ``stream``.
  * Any particle order gives the same result to rounding; the step is fastest
- * with the particles sorted by cell in rows of x-consecutive cells (the
- * planes' contiguous direction): each workgroup of 256 then gathers from a
- * few cache lines per load and deposits into an LDS tile, adding each tile
- * value to the planes once. */
+ * with the particles sorted by cell in small 2D tiles, x fastest within a
+ * tile (the planes' contiguous direction), e.g. 8 rows x 16 columns at two
+ * particles per cell: each wave then gathers from a few cache lines per load,
+ * and each workgroup of 256 deposits into an LDS tile over a compact box,
+ * adding each tile value to the planes once. */
 qds_status qds_particles_step(qds_handle h, const qds_state* fields, int32_t extrapolate, qds_particles* particles,
                               void* jx, void* jr, void* jt, unsigned long long* skipped_dev, void* stream);
 

@@ -189,8 +189,8 @@ def test_tiled_and_direct_deposits_agree(dtype):
     by cell) accumulates there and adds each tile value to the planes once;
     one whose particles spread over the grid (unsorted) adds every value
     directly.  The same 6000 particles unsorted, sorted by cell with r
-    fastest and sorted with x fastest deposit the same currents to rounding,
-    and leave with the same positions."""
+    fastest, with x fastest and in tiles of 8 rows x 16 columns deposit the
+    same currents to rounding, and leave with the same positions."""
     from paper_2609_03550_amd import qds
     s, _, _, pos, u, Q = _setup(3, dtype, nx=256, nr=40, n=6000, near_axis=200)
     dev = s.device
@@ -198,8 +198,10 @@ def test_tiled_and_direct_deposits_agree(dtype):
     ix, ir = np.floor(pos[0] / h), np.floor(np.sqrt(pos[1] ** 2 + pos[2] ** 2) / dr)
     by_r = np.argsort(ix * (s.wl.nr + 1) + ir, kind="stable")
     by_x = np.argsort(ir * s.wl.nx + ix, kind="stable")
+    tile = (ir // 8) * ((s.wl.nx + 15) // 16) + ix // 16
+    by_tile = np.argsort(tile * 128 + (ir % 8) * 16 + ix % 16, kind="stable")
     out = []
-    for idx in (np.arange(pos.shape[1]), by_r, by_x):
+    for idx in (np.arange(pos.shape[1]), by_r, by_x, by_tile):
         P = torch.from_numpy(pos[:, idx].copy()).to(dev)
         U = torch.from_numpy(u[:, idx].copy()).to(dev)
         Qd = torch.from_numpy(Q[idx].copy()).to(dev)
@@ -210,7 +212,7 @@ def test_tiled_and_direct_deposits_agree(dtype):
         inv[idx] = np.arange(idx.size)
         out.append(([pl.cpu().to(torch.complex128).numpy() for pl in planes], P.cpu().numpy()[:, inv]))
     tol = 1e-13 if dtype == "f64" else 1e-5
-    for k in (1, 2):
+    for k in (1, 2, 3):
         for a, b in zip(out[0][0], out[k][0]):
             assert _rel(a, b) < tol
         assert np.array_equal(out[0][1], out[k][1])
