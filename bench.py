@@ -72,6 +72,8 @@ KERNEL_NAME_PAIR = {True: "two-step march of the regenerated set (two steps per 
 # untimed steps of the library's autotuner: 8 trials, each a pair of steps
 # where steps run in pairs
 TUNE_STEPS = 16
+# untimed steps before the autotuner's trials of the headline solver
+TUNE_WARM = 20
 
 
 def pairs_active(wl, fused, pair=1, kernel_ax=0, overlap=0):
@@ -620,7 +622,9 @@ def main():
             s.set_option(opt, int(v))
     elif args.rows is None:
         # tile heights chosen by the library's autotuner on TUNE_STEPS untimed steps of
-        # the run, before the warm-up steps
+        # the run, before the warm-up steps; its trials follow TUNE_WARM untimed steps
+        # at the default heights, so that they are not timed on a GPU still idle
+        s.step(TUNE_WARM)
         s.set_option(qds.OPT_TUNE, 1)
         s.step(TUNE_STEPS)
         torch.cuda.synchronize()
