@@ -204,7 +204,9 @@ qds_status qds_step(qds_handle h, qds_state* fields, const qds_current* J, const
  *                 first 8 pairs, the two-step march in place of kernel B);
  *                 the trial steps are ordinary
  *                 steps (the tiling changes no result).  Waits for the stream
- *                 once, after the trials.
+ *                 once, after the trials.  Trials timed on a GPU that has
+ *                 just been idle can mislead (its clocks still ramping): run
+ *                 a few steps first.
  *  QDS_OPT_PRODUCTS QDS_PRODUCTS_DIRECT (default): the mode products of the
  *                 axion source and current by the direct convolution C_m
  *                 (Eq. mode_convolution); QDS_PRODUCTS_THETA: by a transform
