@@ -30,8 +30,8 @@ const int kCandA2[4] = {16, 24, 32, 43};
 // lockstep rounds, and it runs fastest where a launch's workgroups (strips x
 // chunks x modes) just fit in a whole number of rounds of what the GPU holds
 // at once (measured on MI355X: at 8192 x 256 x 3 all resident at once, 129
-// rows in FP64 and 86 in FP32; at 4096 x 256 x 3 in FP32 37 rows, one round,
-// 10% faster than 20 rows, two rounds less a few).  Candidates: the heights of
+// rows in FP64 and 86 in FP32; on the 4096 x 256 x 3 window workload 29 rows,
+// just under two rounds, in both).  Candidates: the heights of
 // the three smallest distinct chunk counts that fill 1, 2, 3, ... rounds, and
 // 20 rows; without an occupancy figure from the runtime, the heights that cut
 // the nr + 1 rows into 2, 4 and 3 chunks.
