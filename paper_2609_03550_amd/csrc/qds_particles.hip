@@ -99,12 +99,15 @@ __device__ __forceinline__ void moments(double phi, cx<double>* E) {
 template <typename T>
 constexpr int kTileCells = 49152 / (3 * int(sizeof(cx<T>)));
 
-// Two waves per SIMD, with some of the deposit's values spilled to scratch:
-// measured faster than one wave without spills (FP32 1.00 against 1.17 ms,
-// FP64 1.10 against 1.13 ms on 983,040 particles at 4096 x 256 x 3), and than
-// separate push and deposit kernels (the deposit alone holds the registers).
+// The deposit's outer loops stay rolled: 202 VGPRs in FP64, two waves per
+// SIMD without spills (fully unrolled, the kernel held 256 VGPRs and ~50
+// AGPRs, one wave per SIMD, or spilled ~100 registers at two).  On 983,040
+// particles at 4096 x 256 x 3 sorted in 8 x 16 tiles: 0.66 ms in FP64 against
+// 0.85 unrolled (three waves, spilling 48 registers: 0.95), 0.70 in FP32 at
+// three waves (33 spilled) against 0.72 at two and 0.81 unrolled.
 template <typename T, int M>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_particle_step(PartArgs<T> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
+k_particle_step(PartArgs<T> a) {
     const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const Geo& g = a.g;
     const double h = g.h, dr = g.dr, dt = g.h;
@@ -284,7 +287,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             const cx<double> C = m == 0 ? cx<double>{1.0, 0.0} : cx<double>{2.0 * cc, 2.0 * sc};
             for (int k = 0; k < 3; ++k) Ek[k] = C * Ek[k];
             // j_x: cumulative over the columns of each row (face x_{i+1/2})
-#pragma unroll
+#pragma unroll 1
             for (int v = 0; v < 4; ++v) {
                 cx<double> acc{0.0, 0.0};
 #pragma unroll
@@ -295,7 +298,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                 }
             }
             // j_r: cumulative outward over the rows of each column (face r_{j+1/2})
-#pragma unroll
+#pragma unroll 1
             for (int u = 0; u < 4; ++u) {
                 cx<double> flux{0.0, 0.0};
 #pragma unroll
@@ -306,7 +309,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                 }
             }
             // j_theta at (x_i, r_j)
-#pragma unroll
+#pragma unroll 1
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
