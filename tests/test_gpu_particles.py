@@ -216,3 +216,50 @@ def test_tiled_and_direct_deposits_agree(dtype):
         for a, b in zip(out[0][0], out[k][0]):
             assert _rel(a, b) < tol
         assert np.array_equal(out[0][1], out[k][1])
+
+
+def test_full_size_particle_step_sampled_against_the_oracle():
+    """The benchmarked particle step at its full size and launch layout: the
+    4096 x 256 x 3 laser grid, 983,040 electrons in the slab, sorted by cell in
+    8 x 16 tiles (so every workgroup gathers and deposits through the LDS
+    tile), one step in FP64.  Positions and momenta of a seeded sample of 64
+    particles equal the oracle's push of those particles in the same fields
+    (the deposit of so many particles is checked by the pair and continuity
+    tests on smaller grids)."""
+    from paper_2609_03550_amd import qds
+    base = I.driven_window(4096, 256, 4000)
+    wl = base.with_(name="pic_4096x256x3", x_bc="open", drive=None)
+    s = qds.Solver(wl, dtype="f64")
+    s.load_pulses()
+    s.step(40)                       # the pulse moves on: nonzero fields over the slab's edge
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    nx, nr = wl.nx, wl.nr
+    x_lo, x_hi, r_max = 0.25 * nx * wl.h, 0.75 * nx * wl.h, 240 * wl.dr
+    n = int(2 * (0.5 * nx) * 240)
+    x = rng.uniform(x_lo, x_hi, n)
+    r = r_max * np.sqrt(rng.uniform(0, 1, n))
+    th = rng.uniform(-np.pi, np.pi, n)
+    ix, ir = np.floor(x / wl.h), np.floor(r / wl.dr)
+    key = ((ir // 8) * (nx // 16) + ix // 16) * 128 + (ir % 8) * 16 + ix % 16
+    order = np.argsort(key, kind="stable")
+    pos = np.stack([x, r * np.cos(th), r * np.sin(th)])[:, order].copy()
+    u = np.zeros_like(pos)
+    u[0] = 0.05
+    charge = -(1e17 / I.NC_CM3) * (x_hi - x_lo) * np.pi * r_max ** 2 / n
+    f = s.fields()
+    fields = {"Ex": f["Ex0"].numpy(), "Bx": f["Bx0"].numpy(),
+              "Er": (0.5 * (f["Trp0"] + f["Trm0"])).numpy(), "Bt": (0.5 * (f["Trp0"] - f["Trm0"])).numpy(),
+              "Et": (0.5 * (f["Ttp0"] + f["Ttm0"])).numpy(), "Br": (0.5 * (f["Ttp0"] - f["Ttm0"])).numpy()}
+    P = torch.from_numpy(pos).to(s.device)
+    U = torch.from_numpy(u).to(s.device)
+    _, skipped = s.particles_step(P, U, -1.0, charge, clear=True)
+    torch.cuda.synchronize()
+    assert int(skipped.item()) == 0
+    pick = np.random.default_rng(5).choice(n, 64, replace=False)
+    npos, nu, _ = OP.particle_step(fields, None, pos[:, pick].T.copy(), u[:, pick].T.copy(),
+                                   np.full(64, charge), -1.0, wl.h, wl.dr, wl.h)
+    gpos, gu = P.cpu().numpy()[:, pick].T, U.cpu().numpy()[:, pick].T
+    assert np.abs(gu - u[:, pick].T).max() > 1e-6     # the fields moved the sampled momenta
+    assert np.abs(gpos - npos).max() <= 1e-12 * np.abs(npos).max()
+    assert np.abs(gu - nu).max() <= 1e-11 * np.abs(nu).max()
