@@ -226,7 +226,7 @@ def test_autograd_function_gradients():
     gq, ph = Q.grid_physics(wl)
     st = Q.run(Q.init_state(wl), gq, ph, 8)
     L_hat = float(T.loss_energy(st, gq, 1, 1))
-    assert abs(float(L) / (1e-12 * L_hat) - 1) < 1e-12
+    assert abs(float(L.detach()) / (1e-12 * L_hat) - 1) < 1e-12
     assert abs(float(gc.grad) / (4 * float(L) / 1e-3) - 1) < 1e-12
     hstep = 1e-6
     for q in (0, 2, 5):
