@@ -227,7 +227,7 @@ def test_autograd_function_gradients():
     st = Q.run(Q.init_state(wl), gq, ph, 8)
     L_hat = float(T.loss_energy(st, gq, 1, 1))
     assert abs(float(L.detach()) / (1e-12 * L_hat) - 1) < 1e-12
-    assert abs(float(gc.grad) / (4 * float(L) / 1e-3) - 1) < 1e-12
+    assert abs(float(gc.grad) / (4 * float(L.detach()) / 1e-3) - 1) < 1e-12
     hstep = 1e-6
     for q in (0, 2, 5):
         vals = []
@@ -238,7 +238,7 @@ def test_autograd_function_gradients():
             w2 = wl.with_(pulses=(p2, wl.pulses[1]))
             vals.append(float(T.loss_energy(Q.run(Q.init_state(w2), gq, ph, 8), gq, 1, 1)))
         fd = 1e-12 * (vals[0] - vals[1]) / (2 * hstep)
-        assert abs(float(c.grad[q]) - fd) <= 1e-5 * abs(fd) + 1e-12 * float(L), (q, float(c.grad[q]), fd)
+        assert abs(float(c.grad[q]) - fd) <= 1e-5 * abs(fd) + 1e-12 * float(L.detach()), (q, float(c.grad[q]), fd)
 
 
 def test_adjoint_from_random_full_state():
